@@ -1,0 +1,71 @@
+"""Model constants of the oracle (Table 1 of the paper) and the readings taken
+where the paper is silent, ambiguous or garbled.
+
+Test infrastructure only.  The HIP library carries its own transcription of
+the same table; a CPU test compares the two field by field.
+"""
+from dataclasses import dataclass, field, replace
+
+MIN_PER_DAY = 1440.0
+
+
+@dataclass(frozen=True)
+class Params:
+    # lattice and coupled step ------------------------------------------------
+    h_um: float = 20.0          # voxel edge (the paper's 2-D lattice uses 10 um)
+    dt_min: float = 30.0        # Table 1 "time interval of cell cycle update"
+    # oxygen, Eq. (oxygen), Table 1 -----------------------------------------
+    D_K: float = 1.05e5         # um^2/min
+    r_k: float = 1.88e4         # supply rate per unit perfusion weight, 1/min
+    K0: float = 20.0            # blood oxygen, mmHg
+    phi_K: float = 900.0        # consumption rate per occupied voxel
+    K1: float = 2.5             # half-maximal consumption, mmHg
+    # chemotherapies, Eq. (chemo), Table 1 ------------------------------------
+    D_G: float = 9.6e3          # um^2/min
+    psi_G: float = 1.0e-2       # decay, 1/min
+    kappa_G: float = 0.1        # vessel transfer per unit perfusion weight, 1/min
+    # plasma elimination: drug 1 cyclophosphamide cl_3/u, drug 2 fluorouracil
+    # in its linear regime v_max/k_m (Table 1)
+    k_pk: tuple = (3.93e3 / 2430e3, 1.75 / 27.0)
+    G_ref: tuple = (1.0, 1.0)   # normalisation of the kill probability
+    b_int: tuple = (1, 1)       # Table 1 "FEC dose-response shape" alpha = 1
+    # intracellular module, Eqs. (odep53), (odevegf), (cellcycle), Table 1 ----
+    k1: float = 4.0e-4
+    k1p: float = 1.0e-2
+    K_p53: float = 1.0e-2
+    k2: float = 2.0e-3
+    k2p: float = 1.0e-2
+    k2pp: float = -2.0e-4
+    J5: float = 4.0e-2
+    K_V: float = 1.0e-2
+    K_phi: float = 1.4
+    T_cycle: float = 3.74 * MIN_PER_DAY
+    ode_substeps: int = 30      # V_c sub-steps of 1 min (the paper's VODE max step)
+
+    @property
+    def a_K(self):
+        """Face coupling D_K/h^2 of the oxygen Laplacian, 1/min."""
+        return self.D_K / (self.h_um * self.h_um)
+
+    @property
+    def a_G(self):
+        """Face coupling D_G/h^2 of the drug Laplacian, 1/min."""
+        return self.D_G / (self.h_um * self.h_um)
+
+    def with_(self, **kw):
+        return replace(self, **kw)
+
+
+DEFAULT = Params()
+
+# Philox stream identifiers (third counter word)
+STREAM_INIT = 0
+STREAM_KILL = 1
+
+# cell codes of the cellular module
+EMPTY, CANCER, STROMA = 0, 1, 2
+
+# CA proposal codes: 0..25 = Moore direction, then these
+CODE_NOSPACE = 26
+CODE_KILL = 27
+CODE_NONE = 255

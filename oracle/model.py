@@ -1,0 +1,133 @@
+"""Algorithm 1 of the paper: initialisation and the coupled time step.
+
+Test infrastructure only.
+
+State at t^n = n dt:  L (uint8 cell map), K, G1, G2, P, Vc, phi (float64),
+with the static perfusion map w (0 = no vessel, > 0 = perfusion weight).
+
+One coupled step n -> n+1 (loop body of Algorithm 1, with the implicit Euler
+step dt of the cell-cycle update):
+
+1. plasma concentrations G_{i,0}(t^{n+1}) (intravascular module, closed form);
+2. oxygen, Eq. (oxygen) with s_K = 1, linearised as the paper does: the
+   uptake phi_K K/(K1 + K) becomes phi_K K^{n+1}/(K1 + K^n):
+       (1/dt + r_k w + phi_K chi_c/(K1 + K^n)) K^{n+1} - a_K Lap K^{n+1}
+           = K^n/dt + r_k w K0,
+   chi_c = [L != 0] the cell indicator (Eq. delta_function with one unit
+   delta per occupied voxel), w the vessel indicator weighted by perfusion;
+3. each drug, Eq. (chemo):
+       (1/dt + psi_G + kappa_G w) G^{n+1} - a_G Lap G^{n+1}
+           = G^n/dt + kappa_G w G_{i,0}(t^{n+1});
+4. intracellular ODEs with K^{n+1} frozen;
+5. cellular automaton on the state after 4.
+
+Initialisation (Algorithm 1 before the loop): K^0 solves Eq. (oxygen) with
+s_K = 0 (Picard iteration on the uptake coefficient from K = K0 until the
+max-norm relative change is below ``picard_tol``); P, V_c are the ODE steady
+states at K^0 on occupied voxels; phi_0 ~ U(0, 1) for cancer cells from
+Philox stream INIT at counter (gid, 0, 0, 0); G = 0.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import ca, lattice, ode, philox, pk
+from .constants import CANCER, STREAM_INIT
+
+
+@dataclass
+class Schedule:
+    """Dose times (min) and amounts (multiples of G_ref) per drug."""
+    times: tuple = ((), ())
+    amts: tuple = ((), ())
+
+
+@dataclass
+class State:
+    L: np.ndarray
+    K: np.ndarray
+    G1: np.ndarray
+    G2: np.ndarray
+    P: np.ndarray
+    Vc: np.ndarray
+    phi: np.ndarray
+    step: int = 0
+
+    def copy(self):
+        return State(self.L.copy(), self.K.copy(), self.G1.copy(), self.G2.copy(),
+                     self.P.copy(), self.Vc.copy(), self.phi.copy(), self.step)
+
+
+def plasma_pair(t, sched, p):
+    return tuple(pk.plasma(t, sched.times[i], sched.amts[i], p.k_pk[i], p.G_ref[i])
+                 for i in range(2))
+
+
+def o2_system(L, w, K_old, p):
+    chi = (L != 0).astype(np.float64)
+    c = 1.0 / p.dt_min + p.r_k * w + p.phi_K * chi / (p.K1 + K_old)
+    b = K_old / p.dt_min + p.r_k * w * p.K0
+    return c, b
+
+
+def drug_system(w, G_old, g0, p):
+    c = 1.0 / p.dt_min + p.psi_G + p.kappa_G * w
+    b = G_old / p.dt_min + p.kappa_G * w * g0
+    return c, b
+
+
+def steady_o2_system(L, w, K_iter, p):
+    chi = (L != 0).astype(np.float64)
+    c = p.r_k * w + p.phi_K * chi / (p.K1 + K_iter)
+    b = p.r_k * w * p.K0
+    return c, b
+
+
+def steady_oxygen(L, w, p, picard_tol=1e-13, maxit=200, method="lu"):
+    K = np.full(L.shape, p.K0)
+    for it in range(maxit):
+        c, b = steady_o2_system(L, w, K, p)
+        Kn = lattice.solve(c, p.a_K, b, x0=K, method=method)
+        change = np.max(np.abs(Kn - K)) / np.max(np.abs(Kn))
+        K = Kn
+        if change < picard_tol:
+            return K, it + 1
+    raise RuntimeError("steady oxygen Picard iteration did not converge")
+
+
+def init_state(L, w, seed, p, method="lu"):
+    L = L.astype(np.uint8)
+    K, _ = steady_oxygen(L, w, p, method=method)
+    occ = L != 0
+    P = np.zeros(L.shape)
+    Vc = np.zeros(L.shape)
+    P[occ] = ode.steady_p53(K[occ], p)
+    Vc[occ] = ode.steady_vegf(K[occ], P[occ], p)
+    phi = np.zeros(L.shape)
+    gids = np.flatnonzero(L == CANCER)
+    o0, _, _, _ = philox.block_vec(gids.astype(np.uint64), 0, STREAM_INIT, 0, (seed, 0))
+    phi.ravel()[gids] = philox.to_unit_vec(o0)
+    z = np.zeros(L.shape)
+    return State(L, K, z.copy(), z.copy(), P, Vc, phi, 0)
+
+
+def solve_fields(s, w, sched, p, method="lu"):
+    """Steps 1-3: returns (K^{n+1}, G1^{n+1}, G2^{n+1})."""
+    t1 = (s.step + 1) * p.dt_min
+    g0 = plasma_pair(t1, sched, p)
+    c, b = o2_system(s.L, w, s.K, p)
+    K = lattice.solve(c, p.a_K, b, x0=s.K, method=method)
+    c, b = drug_system(w, s.G1, g0[0], p)
+    G1 = lattice.solve(c, p.a_G, b, x0=s.G1, method=method)
+    c, b = drug_system(w, s.G2, g0[1], p)
+    G2 = lattice.solve(c, p.a_G, b, x0=s.G2, method=method)
+    return K, G1, G2
+
+
+def step(s, w, sched, seed, p, method="lu"):
+    """One coupled step; returns (new state, CA event counts)."""
+    K, G1, G2 = solve_fields(s, w, sched, p, method)
+    P, Vc, phi = ode.ode_step(s.L, K, s.P, s.Vc, s.phi, p)
+    Ln, phin, Pn, Vn, ev, _, _ = ca.ca_update(s.L, w, K, G1, G2, phi, P, Vc,
+                                              s.step, seed, p)
+    return State(Ln, K, G1, G2, Pn, Vn, phin, s.step + 1), ev
