@@ -1,0 +1,188 @@
+/*
+ * hca.h - C ABI of the MI355X (gfx950) coupled time step of the stochastic
+ * hybrid cellular automaton (HCA) of Lai et al., "A scalable solver for a
+ * stochastic, hybrid cellular automaton model of personalized breast cancer
+ * therapy".
+ *
+ * The library advances, for one or many independent replicates, the state
+ *   L   uint8 cell map (0 empty, 1 cancer, 2 stroma)      (cellular module)
+ *   K   oxygen pressure, mmHg                              (Eq. oxygen)
+ *   G1  drug 1 (cyclophosphamide-like) concentration       (Eq. chemo)
+ *   G2  drug 2 (fluorouracil-like, linear regime)          (Eq. chemo)
+ *   P   intracellular p53                                  (Eq. odep53)
+ *   Vc  intracellular VEGF                                 (Eq. odevegf)
+ *   phi cell-cycle clock                                   (Eq. cellcycle)
+ * on a cubic voxel lattice with a static perfusion map w (0 = no vessel), by
+ * the coupled step of Algorithm 1: implicit-Euler reaction-diffusion solves of
+ * oxygen and both drugs, the intracellular ODEs, then the cellular automaton.
+ *
+ * Layout: every per-voxel array is x-fastest, gid = x + nx*(y + ny*z),
+ * FP64 for fields and uint8 for the cell map.  All replicates live in one
+ * device allocation per field, concatenated in replicate order.
+ *
+ * Errors: every call returns an hca_status; nothing is thrown across the ABI.
+ * A failed hca_step / hca_run_phases marks the context failed: further steps
+ * return HCA_E_INVALID, while hca_fields, hca_stats, hca_last_error and
+ * hca_destroy still work.  Contexts are independent and not thread-safe; one
+ * context issues all its work on one HIP stream.
+ */
+#ifndef HCA_H
+#define HCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HCA_ABI_VERSION 1
+#define HCA_MAX_DOSES 64          /* per drug and replicate */
+
+typedef enum hca_status {
+  HCA_OK = 0,
+  HCA_E_INVALID = -1,    /* bad argument, bad input data, or failed context   */
+  HCA_E_NOMEM = -2,      /* device or host allocation failed                  */
+  HCA_E_DEVICE = -3,     /* a HIP runtime call failed                         */
+  HCA_E_NOCONV = -4,     /* a linear solve hit cg_maxit above cg_rtol         */
+  HCA_E_NONFINITE = -5,  /* a field became NaN or Inf                         */
+  HCA_E_SINGULAR = -6,   /* steady oxygen has no vessel source                */
+  HCA_E_RANGE = -7       /* replicate index or buffer size out of range       */
+} hca_status;
+
+typedef enum hca_field {
+  HCA_F_O2 = 0, HCA_F_DRUG1 = 1, HCA_F_DRUG2 = 2, HCA_F_CELL = 3 /* uint8 */,
+  HCA_F_P53 = 4, HCA_F_VEGF_IC = 5, HCA_F_PHI = 6, HCA_F_VESSEL_W = 7 /* read-only */
+} hca_field;
+
+/* Phases of one coupled step n -> n+1 (loop body of Algorithm 1). */
+enum {
+  HCA_PH_O2 = 1u << 0,      /* plasma kinetics + oxygen solve                 */
+  HCA_PH_DRUGS = 1u << 1,   /* plasma kinetics + both drug solves             */
+  HCA_PH_ODE = 1u << 2,     /* intracellular ODEs with the current K          */
+  HCA_PH_CA = 1u << 3,      /* cellular automaton propose/resolve/finalize    */
+  HCA_PH_STATS = 1u << 4,   /* counts and non-finite check                    */
+  HCA_PH_ADVANCE = 1u << 5, /* n := n + 1 at the end                          */
+  HCA_PH_ALL = 63u
+};
+
+/* Model constants (Table 1) and numerical settings.  Fill with
+ * hca_default_params() and override as needed. */
+typedef struct hca_params {
+  double h_um;         /* voxel edge, um (20)                                   */
+  double dt_min;       /* coupled step, min (Table 1 cell-cycle update, 30)     */
+  /* oxygen, Eq. (oxygen) */
+  double D_K;          /* diffusion, um^2/min                                   */
+  double r_k;          /* vessel supply per unit perfusion weight, 1/min        */
+  double K0;           /* blood oxygen, mmHg                                    */
+  double phi_K;        /* uptake rate per occupied voxel, mmHg/min              */
+  double K1;           /* half-maximal uptake, mmHg                             */
+  /* drugs, Eq. (chemo) */
+  double D_G;          /* diffusion, um^2/min                                   */
+  double psi_G;        /* decay, 1/min                                          */
+  double kappa_G;      /* vessel transfer per unit perfusion weight, 1/min      */
+  double k_pk[2];      /* plasma elimination rates, 1/min                       */
+  double G_ref[2];     /* kill-probability normalisation of each drug           */
+  int32_t b_int[2];    /* dose-response shape b of I(x; 1, b), integer >= 1     */
+  /* intracellular module, Eqs. (odep53), (odevegf), (cellcycle) */
+  double k1, k1p, K_p53, k2, k2p, k2pp, J5, K_V, K_phi, T_cycle;
+  int32_t ode_substeps;    /* RK4 sub-steps of V_c per coupled step (30)        */
+  /* linear solver */
+  int32_t precond;         /* 0 = Jacobi, 1 = geometric multigrid V-cycle       */
+  double cg_rtol;          /* stop when ||r||_2 <= cg_rtol ||b||_2              */
+  int32_t cg_maxit;        /* per solve                                          */
+  int32_t mg_smooth;       /* Jacobi sweeps before and after the coarse grid     */
+  int32_t mg_coarse_max;   /* levels with at most this many voxels are solved
+                              in one workgroup                                   */
+  /* initialisation */
+  double init_rtol;        /* steady oxygen: Picard until the nonlinear residual
+                              is below init_rtol ||b||                          */
+  int32_t init_maxit;      /* Picard iterations                                  */
+  int32_t profile;         /* 1 = time kernels with HIP events (hca_kernel_time) */
+} hca_params;
+
+/* One replicate's inputs.  hca_init deep-copies every array; the caller keeps
+ * ownership.  Host pointers. */
+typedef struct hca_replicate {
+  int32_t nx, ny, nz;          /* lattice, each >= 1 (nz = 1: the paper's 2-D) */
+  uint64_t seed;               /* Philox key word 0                            */
+  const uint8_t* cell;         /* nx*ny*nz codes in {0,1,2}                    */
+  const double* vessel_w;      /* nx*ny*nz, finite, >= 0; no cell where w > 0  */
+  int32_t n_doses[2];          /* doses per drug, <= HCA_MAX_DOSES             */
+  const double* dose_t_min[2]; /* dose times (min), ascending                  */
+  const double* dose_amt[2];   /* dose amounts, multiples of G_ref             */
+} hca_replicate;
+
+typedef struct hca_stats_s {
+  int64_t step;                /* index n of the current state                 */
+  int64_t n_cancer, n_stroma, n_empty, n_vessel;
+  /* cellular-automaton events of the last step */
+  int64_t committed, divisions, kills, nospace, lost;
+  /* cumulative since init */
+  int64_t total_divisions, total_kills;
+  /* last solve per field (O2, drug 1, drug 2) */
+  int32_t cg_iters[3];
+  double cg_relres[3];
+  int32_t nonfinite;           /* 1 if a NaN/Inf was seen by the last stats pass */
+  int32_t init_picard_iters;
+} hca_stats_t;
+
+typedef struct hca_ctx hca_ctx;
+
+/* Table 1 of the paper plus the readings of its silent passages. */
+hca_status hca_default_params(hca_params* out);
+
+/* Algorithm 1 initialisation for n_reps replicates: uploads the inputs, solves
+ * Eq. (oxygen) with s_K = 0 by Picard iteration, sets P and V_c to the ODE
+ * steady states at that oxygen on occupied voxels, draws phi ~ U(0,1) for
+ * cancer cells (Philox counter (gid, 0, 0, 0), key (seed, 0)) and sets both
+ * drugs to 0.  `stream` is a hipStream_t (NULL: the library creates one).
+ * On success *out owns all device memory of the context. */
+hca_status hca_init(hca_ctx** out, const hca_params* p, const hca_replicate* reps,
+                    int n_reps, void* stream);
+
+/* n_steps full coupled steps (all phases, advancing n each time).  Returns
+ * after enqueuing and synchronising the context's stream. */
+hca_status hca_step(hca_ctx* c, int n_steps);
+
+/* The selected phases of the step n -> n+1, in Algorithm 1 order
+ * (O2, drugs, ODE, CA, stats); n advances only with HCA_PH_ADVANCE. */
+hca_status hca_run_phases(hca_ctx* c, unsigned mask);
+
+/* Copy replicate `rep`'s field into dst (host or device).  dst_bytes must be
+ * >= nx*ny*nz*elem (elem 1 for HCA_F_CELL, else 8): else HCA_E_RANGE. */
+hca_status hca_fields(hca_ctx* c, int rep, hca_field f, void* dst, size_t dst_bytes,
+                      int dst_is_device);
+
+/* Overwrite replicate `rep`'s state field (checkpoint restore, tests).  The
+ * vessel map is read-only.  A cell map with codes outside {0,1,2} or cells on
+ * vessel voxels gives HCA_E_INVALID and leaves the state unchanged. */
+hca_status hca_set_field(hca_ctx* c, int rep, hca_field f, const void* src,
+                         size_t src_bytes, int src_is_device);
+
+/* Set the step index n of the current state (resume from a checkpoint). */
+hca_status hca_set_step(hca_ctx* c, int64_t step);
+
+hca_status hca_stats(hca_ctx* c, int rep, hca_stats_t* out);
+
+/* With params.profile = 1: accumulated device time (ms) and launch count of
+ * kernel class `kernel` (see hca_kernel_name) since the last reset. */
+hca_status hca_kernel_time(hca_ctx* c, int kernel, double* ms, int64_t* launches,
+                           double* bytes_per_launch);
+const char* hca_kernel_name(int kernel);
+int hca_num_kernels(void);
+hca_status hca_reset_kernel_time(hca_ctx* c);
+
+/* Block the host until all work of the context has finished. */
+hca_status hca_synchronize(hca_ctx* c);
+
+/* Human-readable reason of the context's last failure ("" if none). */
+const char* hca_last_error(const hca_ctx* c);
+
+/* Frees every resource of the context (NULL is allowed). */
+void hca_destroy(hca_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HCA_H */

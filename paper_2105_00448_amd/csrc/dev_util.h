@@ -1,0 +1,121 @@
+// Device helpers: fixed-order workgroup reductions, the per-replicate
+// "last workgroup finishes the reduction" handshake, work-item decoding and
+// the Philox4x64-10 block function.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hca_internal.h"
+
+namespace hca {
+
+// Sum over a 256-thread workgroup in a fixed order (wavefront butterfly, then
+// the four wavefront sums in index order).  Every thread returns the total.
+__device__ inline double block_sum(double v, double* lds4) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds4[wave] = v;
+  __syncthreads();
+  double t = ((lds4[0] + lds4[1]) + lds4[2]) + lds4[3];
+  __syncthreads();
+  return t;
+}
+
+__device__ inline unsigned long long block_sum_u64(unsigned long long v,
+                                                   unsigned long long* lds4) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds4[wave] = v;
+  __syncthreads();
+  unsigned long long t = lds4[0] + lds4[1] + lds4[2] + lds4[3];
+  __syncthreads();
+  return t;
+}
+
+__device__ inline double block_max(double v, double* lds4) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds4[wave] = v;
+  __syncthreads();
+  double t = fmax(fmax(lds4[0], lds4[1]), fmax(lds4[2], lds4[3]));
+  __syncthreads();
+  return t;
+}
+
+// Publish this workgroup's partial sums and report whether it is the last
+// workgroup of its replicate to do so.  The last one may then read every
+// partial of the replicate (reads go through acquire_load below).
+__device__ inline bool publish_and_check_last(double* slot, const double* vals, int nvals,
+                                              unsigned* counter, int nblocks) {
+  __shared__ int am_last;
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < nvals; ++k)
+      __hip_atomic_store(slot + k, vals[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __atomic_thread_fence(__ATOMIC_RELEASE);   // (agent scope by default on device)
+    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+    am_last = (prev == (unsigned)(nblocks - 1));
+    if (am_last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  return am_last != 0;
+}
+
+__device__ inline double acquire_load(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum of nvals-strided partials [0, nb) of component k, fixed order:
+// thread t sums t, t+256, ... then block_sum.
+__device__ inline double reduce_partials(const double* base, int nb, int nvals, int k,
+                                         double* lds4) {
+  double s = 0.0;
+  for (int j = threadIdx.x; j < nb; j += kBlock) s += acquire_load(base + (size_t)j * nvals + k);
+  return block_sum(s, lds4);
+}
+
+// ---- Philox4x64-10 (Salmon et al., SC'11) ----------------------------------
+struct U64x4 {
+  uint64_t v[4];
+};
+
+__device__ inline U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                      uint64_t k0, uint64_t k1) {
+  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
+    const uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  U64x4 o;
+  o.v[0] = c0;
+  o.v[1] = c1;
+  o.v[2] = c2;
+  o.v[3] = c3;
+  return o;
+}
+
+__device__ inline double unit53(uint64_t o) { return (double)(o >> 11) * 0x1.0p-53; }
+
+// Moore neighbour d (0..25, ascending gid order) offsets.
+__device__ inline void moore_offset(int d, int& dx, int& dy, int& dz) {
+  const int e = d < 13 ? d : d + 1;   // skip the centre (13)
+  dz = e / 9 - 1;
+  dy = (e / 3) % 3 - 1;
+  dx = e % 3 - 1;
+}
+
+__device__ inline int moore_opposite(int d) { return 25 - d; }
+
+}  // namespace hca

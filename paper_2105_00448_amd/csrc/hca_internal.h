@@ -1,0 +1,141 @@
+// Internal declarations shared by the HIP translation units of libhca.
+// Device-side parameter block, replicate / work tables and the launchers
+// each kernel file exports to the runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hca.h"
+
+namespace hca {
+
+constexpr int kBlock = 256;        // threads per workgroup for every kernel
+constexpr int kFlatChunk = 1024;   // voxels per flat work item (4 per thread)
+constexpr int kMaxFlatBlocksPerRep = 2048;
+
+// CA proposal codes: 0..25 Moore direction (ascending gid order), then:
+constexpr uint8_t kCodeNoSpace = 26;
+constexpr uint8_t kCodeKill = 27;
+constexpr uint8_t kCodeNone = 255;
+
+constexpr uint64_t kStreamInit = 0;
+constexpr uint64_t kStreamKill = 1;
+
+// Model constants as the kernels use them.
+struct DevParams {
+  double dt, inv_dt;
+  double aK, aG;              // D/h^2 of oxygen and drugs
+  double r_k, K0, phi_K, K1;
+  double psi_G, kappa_G;
+  double k_pk[2], G_ref[2];
+  int b_int[2];
+  double k1, k1p, K_p53, k2, k2p, k2pp, J5, K_V, K_phi, T_cycle;
+  int nsub;
+};
+
+// One replicate on the device.
+struct RepDev {
+  int nx, ny, nz, pad0;
+  long long off;              // first voxel in the concatenated arrays
+  long long n;                // nx*ny*nz
+  unsigned long long seed;
+  int flat_b0, flat_nb;       // range in the flat block table
+  int tile_b0, tile_nb;       // range in the stencil tile table
+  int ndose[2];
+  int dose_off;               // into the dose arrays (2*HCA_MAX_DOSES per rep)
+  int tx;                     // stencil tile width (tile = tx x (kBlock/tx) columns)
+};
+
+// Work item of the flat kernels: replicate and first chunk index.
+struct FlatBlk {
+  int rep, first;
+};
+
+// Work item of the stencil kernels: a TX x TY column tile over [z0, z1).
+struct Tile {
+  int rep;
+  short x0, y0;
+  short z0, z1;
+  int pad;
+};
+
+// Per-replicate scalars of one conjugate-gradient solve.
+struct SolveScal {
+  double bb;        // ||b||^2
+  double rr;        // ||r||^2
+  double rz;        // r.z of the current direction
+  double rzo;       // r_new . z_old (flexible CG)
+  double rzn;       // r_new . z_new
+  double pq;        // p.Ap
+  double alpha, beta;
+  double rr0;       // ||r_0||^2 of this solve
+  int it, done, conv, first;
+};
+
+// Per-replicate event counters (integers: order-independent sums).
+struct Counters {
+  unsigned long long committed, kills, divisions, nospace, lost;
+  unsigned long long n_cancer, n_stroma, n_empty, n_vessel;
+  unsigned long long nonfinite;
+  unsigned long long total_divisions, total_kills;
+  unsigned long long pad[4];
+};
+
+struct Work {
+  int nreps;
+  const RepDev* reps;
+  const FlatBlk* flat;
+  int nflat;
+  const Tile* tiles;
+  int ntiles;
+};
+
+// ---- launchers (defined in the .hip files) --------------------------------
+// setup / init / plasma kinetics (k_setup.hip)
+void launch_plasma(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
+                   const double* dose_t, const double* dose_a, double* g0);
+void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
+                     const double* vw, const double* K, double* c, double* b, int steady);
+void launch_setup_drug(hipStream_t s, const Work& w, const DevParams& p, int drug,
+                       const double* vw, const double* G, const double* g0, double* c, double* b);
+void launch_init_cells(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
+                       const double* K, double* P, double* Vc, double* phi);
+
+// solver (k_solver.hip)
+struct SolverBufs {
+  double *r, *z, *p0, *p1, *q;
+  double* partial;            // per work item
+  unsigned* counter;          // per replicate
+  SolveScal* ss;              // per replicate
+  int* ndone;                 // replicates finished
+};
+void launch_cg_start(hipStream_t s, const Work& w, double a, double rtol, int maxit,
+                     const double* c, const double* b, const double* x, const SolverBufs& sb);
+// One iteration is launch_cg_apply then launch_cg_update with the same
+// parity (the direction p alternates between p0 and p1).
+void launch_cg_apply(hipStream_t s, const Work& w, double a, const double* c,
+                     const SolverBufs& sb, int parity);
+void launch_cg_update(hipStream_t s, const Work& w, double a, double rtol, int maxit,
+                      const double* c, double* x, const SolverBufs& sb, int parity);
+
+// ODE (k_ode.hip)
+void launch_ode(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
+                const double* K, double* P, double* Vc, double* phi);
+
+// CA and stats (k_ca.hip)
+void launch_ca_propose(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
+                       const uint8_t* L, const double* vw, const double* K, const double* G1,
+                       const double* G2, const double* phi, uint8_t* code);
+void launch_ca_resolve(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
+                       const double* phi, const uint8_t* code, uint8_t* win);
+void launch_ca_finalize(hipStream_t s, const Work& w, uint8_t* L, double* phi, double* P,
+                        double* Vc, const uint8_t* code, const uint8_t* win, Counters* cnt);
+void launch_stats(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
+                  const double* const* fields, int nfields, Counters* cnt);
+void launch_zero_counters(hipStream_t s, Counters* cnt, int nreps, int events_only);
+void launch_advance(hipStream_t s, long long* d_step);
+void launch_validate_cells(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
+                           int rep, unsigned long long* bad);
+
+}  // namespace hca

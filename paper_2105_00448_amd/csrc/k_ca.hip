@@ -1,0 +1,306 @@
+// Stochastic cellular automaton of the cellular module, as three gather-only
+// passes over the lattice (no atomics on the state, no scatter), so the
+// result cannot depend on thread scheduling or tiling:
+//
+// propose   a cancer cell with phi >= 1 is committed.  One Philox4x64-10 block
+//           (key (seed, 0), counter (gid, n+1, KILL, 0)) gives one uniform per
+//           drug; drug i kills with probability I(x_i; 1, b_i) = 1 - (1-x_i)^b_i,
+//           x_i = clip(G_i / G_ref_i, 0, 1), the power by repeated products.
+//           A surviving cell proposes the empty non-vessel Moore neighbour of
+//           highest oxygen (first strict maximum in ascending gid order), else
+//           NOSPACE.
+// resolve   every empty non-vessel voxel picks, among the neighbours proposing
+//           it, the one with the largest phi (Algorithm 2's priority), equal phi
+//           -> lowest gid.
+// finalize  each voxel applies its own outcome from the codes of the previous
+//           passes: killed -> emptied and zeroed; won -> phi = P = Vc = 0;
+//           lost or NOSPACE -> phi = 0; daughter site -> cancer with zero state.
+//
+// Every decision reads the pre-update state (asynchronous rule of the CA
+// numerical treatment).  This file is compiled without floating-point
+// contraction; decisions use only correctly rounded +, -, *, / and compares.
+#include "dev_util.h"
+
+namespace hca {
+
+struct VoxelCoord {
+  int x, y, z;
+};
+
+__device__ inline VoxelCoord coord_of(long long li, const RepDev& rp) {
+  VoxelCoord v;
+  v.x = (int)(li % rp.nx);
+  const long long t = li / rp.nx;
+  v.y = (int)(t % rp.ny);
+  v.z = (int)(t / rp.ny);
+  return v;
+}
+
+__device__ inline bool neighbour(const RepDev& rp, const VoxelCoord& v, int d, long long& nli) {
+  int dx, dy, dz;
+  moore_offset(d, dx, dy, dz);
+  const int x = v.x + dx, y = v.y + dy, z = v.z + dz;
+  if (x < 0 || y < 0 || z < 0 || x >= rp.nx || y >= rp.ny || z >= rp.nz) return false;
+  nli = x + (long long)rp.nx * (y + (long long)rp.ny * z);
+  return true;
+}
+
+template <typename F>
+__device__ inline void for_each_voxel_ca(const Work& w, F f) {
+  const FlatBlk fb = w.flat[blockIdx.x];
+  const RepDev rp = w.reps[fb.rep];
+  const long long nchunks = (rp.n + kFlatChunk - 1) / kFlatChunk;
+  for (long long ch = fb.first; ch < nchunks; ch += rp.flat_nb) {
+    const long long base = ch * kFlatChunk;
+#pragma unroll
+    for (int k = 0; k < kFlatChunk / kBlock; ++k) {
+      const long long li = base + k * kBlock + threadIdx.x;
+      if (li < rp.n) f(fb.rep, rp, li);
+    }
+  }
+}
+
+__device__ inline double kill_probability(double G, double Gref, int b) {
+  double x = G / Gref;
+  x = x < 0.0 ? 0.0 : x;
+  x = x > 1.0 ? 1.0 : x;
+  const double y = 1.0 - x;
+  double pw = y;
+  for (int k = 1; k < b; ++k) pw = pw * y;
+  return 1.0 - pw;
+}
+
+__global__ void __launch_bounds__(kBlock) k_ca_propose(Work w, DevParams p,
+                                                       const long long* d_step,
+                                                       const uint8_t* __restrict__ L,
+                                                       const double* __restrict__ vw,
+                                                       const double* __restrict__ K,
+                                                       const double* __restrict__ G1,
+                                                       const double* __restrict__ G2,
+                                                       const double* __restrict__ phi,
+                                                       uint8_t* __restrict__ code) {
+  const long long step = d_step[0];
+  for_each_voxel_ca(w, [&](int, const RepDev& rp, long long li) {
+    const long long i = rp.off + li;
+    uint8_t cd = kCodeNone;
+    if (L[i] == 1 && phi[i] >= 1.0) {
+      const U64x4 o = philox4x64_10((uint64_t)li, (uint64_t)(step + 1), kStreamKill, 0ull,
+                                    rp.seed, 0ull);
+      const double u0 = unit53(o.v[0]), u1 = unit53(o.v[1]);
+      const double p1 = kill_probability(G1[i], p.G_ref[0], p.b_int[0]);
+      const double p2 = kill_probability(G2[i], p.G_ref[1], p.b_int[1]);
+      if (u0 < p1 || u1 < p2) {
+        cd = kCodeKill;
+      } else {
+        const VoxelCoord v = coord_of(li, rp);
+        double best = -INFINITY;
+        cd = kCodeNoSpace;
+        for (int d = 0; d < 26; ++d) {
+          long long nli;
+          if (!neighbour(rp, v, d, nli)) continue;
+          const long long j = rp.off + nli;
+          if (L[j] != 0 || vw[j] != 0.0) continue;
+          const double kj = K[j];
+          if (kj > best) {
+            best = kj;
+            cd = (uint8_t)d;
+          }
+        }
+      }
+    }
+    code[i] = cd;
+  });
+}
+
+__global__ void __launch_bounds__(kBlock) k_ca_resolve(Work w, const uint8_t* __restrict__ L,
+                                                       const double* __restrict__ vw,
+                                                       const double* __restrict__ phi,
+                                                       const uint8_t* __restrict__ code,
+                                                       uint8_t* __restrict__ win) {
+  for_each_voxel_ca(w, [&](int, const RepDev& rp, long long li) {
+    const long long i = rp.off + li;
+    uint8_t wn = kCodeNone;
+    if (L[i] == 0 && vw[i] == 0.0) {
+      const VoxelCoord v = coord_of(li, rp);
+      double best = -INFINITY;
+      for (int d = 0; d < 26; ++d) {   // ascending parent gid: strict > keeps the lowest
+        long long nli;
+        if (!neighbour(rp, v, d, nli)) continue;
+        const long long j = rp.off + nli;
+        if (code[j] != (uint8_t)moore_opposite(d)) continue;
+        const double ph = phi[j];
+        if (ph > best) {
+          best = ph;
+          wn = (uint8_t)d;
+        }
+      }
+    }
+    win[i] = wn;
+  });
+}
+
+__global__ void __launch_bounds__(kBlock) k_ca_finalize(Work w, uint8_t* __restrict__ L,
+                                                        double* __restrict__ phi,
+                                                        double* __restrict__ P,
+                                                        double* __restrict__ Vc,
+                                                        const uint8_t* __restrict__ code,
+                                                        const uint8_t* __restrict__ win,
+                                                        Counters* cnt) {
+  __shared__ unsigned long long lds4[4];
+  unsigned long long n_com = 0, n_kill = 0, n_div = 0, n_nosp = 0, n_lost = 0;
+  for_each_voxel_ca(w, [&](int, const RepDev& rp, long long li) {
+    const long long i = rp.off + li;
+    const uint8_t cd = code[i];
+    const uint8_t wn = win[i];
+    if (cd != kCodeNone) {
+      ++n_com;
+      if (cd == kCodeKill) {
+        ++n_kill;
+        L[i] = 0;
+        phi[i] = 0.0;
+        P[i] = 0.0;
+        Vc[i] = 0.0;
+      } else if (cd == kCodeNoSpace) {
+        ++n_nosp;
+        phi[i] = 0.0;
+      } else {
+        const VoxelCoord v = coord_of(li, rp);
+        long long nli = 0;
+        neighbour(rp, v, cd, nli);
+        if (win[rp.off + nli] == (uint8_t)moore_opposite(cd)) {
+          ++n_div;
+          phi[i] = 0.0;
+          P[i] = 0.0;
+          Vc[i] = 0.0;
+        } else {
+          ++n_lost;
+          phi[i] = 0.0;
+        }
+      }
+    }
+    if (wn != kCodeNone) {
+      L[i] = 1;
+      phi[i] = 0.0;
+      P[i] = 0.0;
+      Vc[i] = 0.0;
+    }
+  });
+  const int rep = w.flat[blockIdx.x].rep;
+  const unsigned long long a = block_sum_u64(n_com, lds4);
+  const unsigned long long b = block_sum_u64(n_kill, lds4);
+  const unsigned long long c = block_sum_u64(n_div, lds4);
+  const unsigned long long d = block_sum_u64(n_nosp, lds4);
+  const unsigned long long e = block_sum_u64(n_lost, lds4);
+  if (threadIdx.x == 0) {
+    Counters* cr = cnt + rep;
+    if (a) atomicAdd(&cr->committed, a);
+    if (b) atomicAdd(&cr->kills, b);
+    if (c) atomicAdd(&cr->divisions, c);
+    if (c) atomicAdd(&cr->total_divisions, c);
+    if (b) atomicAdd(&cr->total_kills, b);
+    if (d) atomicAdd(&cr->nospace, d);
+    if (e) atomicAdd(&cr->lost, e);
+  }
+}
+
+// Cell-type counts and a non-finite scan of the listed fields.
+__global__ void __launch_bounds__(kBlock) k_stats(Work w, const uint8_t* __restrict__ L,
+                                                  const double* __restrict__ vw,
+                                                  const double* const* fields, int nfields,
+                                                  Counters* cnt) {
+  __shared__ unsigned long long lds4[4];
+  unsigned long long nc = 0, ns = 0, ne = 0, nv = 0, bad = 0;
+  for_each_voxel_ca(w, [&](int, const RepDev& rp, long long li) {
+    const long long i = rp.off + li;
+    const uint8_t l = L[i];
+    nc += l == 1;
+    ns += l == 2;
+    ne += l == 0;
+    nv += vw[i] != 0.0;
+    for (int f = 0; f < nfields; ++f) bad += !isfinite(fields[f][i]);
+  });
+  const int rep = w.flat[blockIdx.x].rep;
+  const unsigned long long a = block_sum_u64(nc, lds4);
+  const unsigned long long b = block_sum_u64(ns, lds4);
+  const unsigned long long c = block_sum_u64(ne, lds4);
+  const unsigned long long d = block_sum_u64(nv, lds4);
+  const unsigned long long e = block_sum_u64(bad, lds4);
+  if (threadIdx.x == 0) {
+    Counters* cr = cnt + rep;
+    if (a) atomicAdd(&cr->n_cancer, a);
+    if (b) atomicAdd(&cr->n_stroma, b);
+    if (c) atomicAdd(&cr->n_empty, c);
+    if (d) atomicAdd(&cr->n_vessel, d);
+    if (e) atomicAdd(&cr->nonfinite, e);
+  }
+}
+
+// Zero the event counters (events_only) or the state counters.  A kernel,
+// not a memset, so the sequence stays safe to capture in a graph.
+__global__ void k_zero_counters(Counters* cnt, int nreps, int events_only) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nreps) return;
+  Counters& c = cnt[r];
+  if (events_only) {
+    c.committed = c.kills = c.divisions = c.nospace = c.lost = 0;
+  } else {
+    c.n_cancer = c.n_stroma = c.n_empty = c.n_vessel = c.nonfinite = 0;
+  }
+}
+
+__global__ void k_advance(long long* d_step) { d_step[0] += 1; }
+
+// Counts cell codes outside {0,1,2} and cells on vessel voxels of replicate rep.
+__global__ void __launch_bounds__(kBlock) k_validate_cells(Work w, const uint8_t* __restrict__ L,
+                                                           const double* __restrict__ vw, int rep,
+                                                           unsigned long long* bad) {
+  const FlatBlk fb = w.flat[blockIdx.x];
+  if (fb.rep != rep) return;
+  unsigned long long nb = 0;
+  for_each_voxel_ca(w, [&](int, const RepDev& rp, long long li) {
+    const long long i = rp.off + li;
+    const uint8_t l = L[i];
+    nb += (l > 2) || (l != 0 && vw[i] != 0.0);
+  });
+  for (int o = 32; o > 0; o >>= 1) nb += __shfl_xor(nb, o, 64);
+  if ((threadIdx.x & 63) == 0 && nb) atomicAdd(bad, nb);
+}
+
+void launch_ca_propose(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
+                       const uint8_t* L, const double* vw, const double* K, const double* G1,
+                       const double* G2, const double* phi, uint8_t* code) {
+  hipLaunchKernelGGL(k_ca_propose, dim3(w.nflat), dim3(kBlock), 0, s, w, p, d_step, L, vw, K, G1,
+                     G2, phi, code);
+}
+
+void launch_ca_resolve(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
+                       const double* phi, const uint8_t* code, uint8_t* win) {
+  hipLaunchKernelGGL(k_ca_resolve, dim3(w.nflat), dim3(kBlock), 0, s, w, L, vw, phi, code, win);
+}
+
+void launch_ca_finalize(hipStream_t s, const Work& w, uint8_t* L, double* phi, double* P,
+                        double* Vc, const uint8_t* code, const uint8_t* win, Counters* cnt) {
+  hipLaunchKernelGGL(k_ca_finalize, dim3(w.nflat), dim3(kBlock), 0, s, w, L, phi, P, Vc, code, win,
+                     cnt);
+}
+
+void launch_stats(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
+                  const double* const* fields, int nfields, Counters* cnt) {
+  hipLaunchKernelGGL(k_stats, dim3(w.nflat), dim3(kBlock), 0, s, w, L, vw, fields, nfields, cnt);
+}
+
+void launch_zero_counters(hipStream_t s, Counters* cnt, int nreps, int events_only) {
+  hipLaunchKernelGGL(k_zero_counters, dim3((nreps + 63) / 64), dim3(64), 0, s, cnt, nreps,
+                     events_only);
+}
+
+void launch_advance(hipStream_t s, long long* d_step) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, d_step);
+}
+
+void launch_validate_cells(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
+                           int rep, unsigned long long* bad) {
+  hipLaunchKernelGGL(k_validate_cells, dim3(w.nflat), dim3(kBlock), 0, s, w, L, vw, rep, bad);
+}
+
+}  // namespace hca

@@ -1,0 +1,139 @@
+// Plasma kinetics, coefficient / right-hand-side setup of the implicit-Euler
+// systems, and the cell-state initialisation of Algorithm 1.
+//
+// Every implicit-Euler update of Eqs. (oxygen) and (chemo) on the voxel
+// lattice is   c_i u_i - a (Lap u)_i = b_i   with a = D/h^2 and the
+// zero-flux 7-point Laplacian; these kernels produce c and b per voxel.
+#include "dev_util.h"
+
+namespace hca {
+
+// G_{i,0}(t^{n+1}) of both drugs for every replicate: a_m G_ref e^{-k (t - t_m)}
+// for the latest bolus t_m <= t (reset at each dose), 0 before the first dose.
+// One-compartment linear elimination (Eq. intrachemo3; the fluorouracil model
+// in its linear regime).
+__global__ void k_plasma(int nreps, const RepDev* reps, DevParams p, const long long* d_step,
+                         const double* dose_t, const double* dose_a, double* g0) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nreps) return;
+  const double t = (double)(d_step[0] + 1) * p.dt;
+  const RepDev rp = reps[r];
+  for (int i = 0; i < 2; ++i) {
+    double g = 0.0;
+    double tm = -1.0;
+    for (int k = 0; k < rp.ndose[i]; ++k) {
+      const double td = dose_t[rp.dose_off + i * HCA_MAX_DOSES + k];
+      if (td <= t && td >= tm) {
+        tm = td;
+        g = dose_a[rp.dose_off + i * HCA_MAX_DOSES + k] * p.G_ref[i];
+      }
+    }
+    if (tm >= 0.0) g = g * exp(-p.k_pk[i] * (t - tm));
+    g0[2 * r + i] = g;
+  }
+}
+
+template <typename F>
+__device__ inline void for_each_voxel(const Work& w, F f) {
+  const FlatBlk fb = w.flat[blockIdx.x];
+  const RepDev rp = w.reps[fb.rep];
+  const long long nchunks = (rp.n + kFlatChunk - 1) / kFlatChunk;
+  for (long long ch = fb.first; ch < nchunks; ch += rp.flat_nb) {
+    const long long base = ch * kFlatChunk;
+#pragma unroll
+    for (int k = 0; k < kFlatChunk / kBlock; ++k) {
+      const long long i = base + k * kBlock + threadIdx.x;
+      if (i < rp.n) f(fb.rep, rp, rp.off + i);
+    }
+  }
+}
+
+// Oxygen, Eq. (oxygen) linearised as in the paper: the uptake
+// phi_K K/(K1 + K) becomes phi_K K^{n+1}/(K1 + K^n).  chi = [L != 0] marks the
+// cell delta functions, w weights the vessel sources.
+//   step:   c = 1/dt + r_k w + phi_K chi/(K1 + K^n),   b = K^n/dt + r_k w K0
+//   steady: c =        r_k w + phi_K chi/(K1 + K),     b =        r_k w K0
+__global__ void __launch_bounds__(kBlock) k_setup_o2(Work w, DevParams p, const uint8_t* L,
+                                                     const double* vw, const double* K,
+                                                     double* c, double* b, int steady) {
+  for_each_voxel(w, [&](int, const RepDev&, long long g) {
+    const double k = K[g];
+    const double wv = vw[g];
+    const double chi = L[g] != 0 ? 1.0 : 0.0;
+    const double up = p.phi_K * chi / (p.K1 + k);
+    if (steady) {
+      c[g] = p.r_k * wv + up;
+      b[g] = p.r_k * wv * p.K0;
+    } else {
+      c[g] = p.inv_dt + p.r_k * wv + up;
+      b[g] = k * p.inv_dt + p.r_k * wv * p.K0;
+    }
+  });
+}
+
+// Drug i, Eq. (chemo): c = 1/dt + psi_G + kappa_G w,  b = G^n/dt + kappa_G w G_{i,0}.
+__global__ void __launch_bounds__(kBlock) k_setup_drug(Work w, DevParams p, int drug,
+                                                       const double* vw, const double* G,
+                                                       const double* g0, double* c, double* b) {
+  for_each_voxel(w, [&](int rep, const RepDev&, long long g) {
+    const double wv = vw[g];
+    const double gp = g0[2 * rep + drug];
+    c[g] = p.inv_dt + p.psi_G + p.kappa_G * wv;
+    b[g] = G[g] * p.inv_dt + p.kappa_G * wv * gp;
+  });
+}
+
+// Algorithm 1 initialisation of the cell state at the initial oxygen K^0:
+// P, V_c at the steady states of Eqs. (odep53), (odevegf) on occupied voxels,
+// phi ~ U(0,1) for cancer cells (Philox counter (gid, 0, INIT, 0), key (seed, 0)).
+__global__ void __launch_bounds__(kBlock) k_init_cells(Work w, DevParams p, const uint8_t* L,
+                                                       const double* K, double* P, double* Vc,
+                                                       double* phi) {
+  for_each_voxel(w, [&](int, const RepDev& rp, long long g) {
+    const uint8_t l = L[g];
+    double pv = 0.0, vv = 0.0, ph = 0.0;
+    if (l != 0) {
+      const double k = K[g];
+      const double lam = p.k1p * k / (p.K_p53 + k);
+      pv = p.k1 / lam;
+      const double mu = p.k2p * k / (p.K_V + k);
+      const double beta = p.k2 + p.k2pp * pv - mu * p.J5;
+      const double disc = sqrt(beta * beta + 4.0 * mu * p.k2 * p.J5);
+      // positive root of mu V^2 - beta V - k2 J5 = 0, in the cancellation-free form
+      vv = beta >= 0.0 ? (beta + disc) / (2.0 * mu) : (2.0 * p.k2 * p.J5) / (disc - beta);
+    }
+    if (l == 1) {
+      const uint64_t gid = (uint64_t)(g - rp.off);
+      const U64x4 o = philox4x64_10(gid, 0ull, kStreamInit, 0ull, rp.seed, 0ull);
+      ph = unit53(o.v[0]);
+    }
+    P[g] = pv;
+    Vc[g] = vv;
+    phi[g] = ph;
+  });
+}
+
+void launch_plasma(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
+                   const double* dose_t, const double* dose_a, double* g0) {
+  const int nb = (w.nreps + 63) / 64;
+  hipLaunchKernelGGL(k_plasma, dim3(nb), dim3(64), 0, s, w.nreps, w.reps, p, d_step, dose_t,
+                     dose_a, g0);
+}
+
+void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
+                     const double* vw, const double* K, double* c, double* b, int steady) {
+  hipLaunchKernelGGL(k_setup_o2, dim3(w.nflat), dim3(kBlock), 0, s, w, p, L, vw, K, c, b, steady);
+}
+
+void launch_setup_drug(hipStream_t s, const Work& w, const DevParams& p, int drug,
+                       const double* vw, const double* G, const double* g0, double* c,
+                       double* b) {
+  hipLaunchKernelGGL(k_setup_drug, dim3(w.nflat), dim3(kBlock), 0, s, w, p, drug, vw, G, g0, c, b);
+}
+
+void launch_init_cells(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
+                       const double* K, double* P, double* Vc, double* phi) {
+  hipLaunchKernelGGL(k_init_cells, dim3(w.nflat), dim3(kBlock), 0, s, w, p, L, K, P, Vc, phi);
+}
+
+}  // namespace hca

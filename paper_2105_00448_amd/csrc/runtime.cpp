@@ -1,0 +1,854 @@
+// Host runtime of libhca: context, device memory, replicate / work tables,
+// the per-step phase sequence of Algorithm 1, the CG driver and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hca.h"
+#include "hca_internal.h"
+
+using namespace hca;
+
+namespace {
+
+enum KernelClass {
+  KC_PLASMA = 0, KC_SETUP_O2, KC_SETUP_DRUG, KC_CG_START, KC_CG_APPLY, KC_CG_UPDATE, KC_ODE,
+  KC_CA_PROPOSE, KC_CA_RESOLVE, KC_CA_FINALIZE, KC_STATS, KC_COUNT
+};
+
+const char* kKernelNames[KC_COUNT] = {
+    "k_plasma", "k_setup_o2", "k_setup_drug", "k_cg_start", "k_cg_apply", "k_cg_update",
+    "k_ode", "k_ca_propose", "k_ca_resolve", "k_ca_finalize", "k_stats"};
+
+// Compulsory (algorithmic) HBM bytes per voxel of each kernel class.
+const double kBytesPerVoxel[KC_COUNT] = {
+    0.0,          // plasma: per replicate only
+    33.0,         // setup_o2: read L, w, K; write c, b
+    32.0,         // setup_drug: read w, G; write c, b
+    40.0,         // cg_start: read x, c, b; write r, z
+    40.0,         // cg_apply: read z, p_old, c; write p_new, q
+    72.0,         // cg_update: read x, p, r, q, z, c; write x, r, z
+    57.0,         // ode: read L, K, P, Vc, phi; write P, Vc, phi
+    10.0,         // ca_propose: read L, phi; write code
+    11.0,         // ca_resolve: read L, w, code; write win
+    2.0,          // ca_finalize: read code, win (writes only where cells change)
+    57.0};        // stats: read L, w and six fields
+
+struct RepHost {
+  int nx, ny, nz;
+  long long off, n;
+  uint64_t seed;
+  int nvessel;
+};
+
+struct ProfEntry {
+  int kc;
+  hipEvent_t a, b;
+  int iter;      // CG iteration index within the solve, -1 otherwise
+  double bytes;
+};
+
+}  // namespace
+
+struct hca_ctx {
+  hca_params prm;
+  DevParams dp;
+  int nreps = 0;
+  std::vector<RepHost> reps;
+  long long ntot = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+
+  uint8_t *L = nullptr, *code = nullptr, *win = nullptr;
+  double *w = nullptr, *K = nullptr, *G1 = nullptr, *G2 = nullptr, *P = nullptr, *Vc = nullptr,
+         *phi = nullptr, *c = nullptr, *b = nullptr;
+  SolverBufs sb{};
+  double *dose_t = nullptr, *dose_a = nullptr, *g0 = nullptr;
+  long long* d_step = nullptr;
+  RepDev* d_reps = nullptr;
+  FlatBlk* d_flat = nullptr;
+  Tile* d_tiles = nullptr;
+  Counters* d_cnt = nullptr;
+  const double** d_fields = nullptr;
+  unsigned long long* d_bad = nullptr;
+  Work work{};
+
+  SolveScal* h_ss = nullptr;     // pinned
+  Counters* h_cnt = nullptr;     // pinned
+  long long step = 0;
+  int last_it[3] = {0, 0, 0};
+  std::vector<SolveScal> last_ss[3];
+  int picard_iters = 0;
+
+  bool failed = false;
+  std::string err;
+
+  // profiling
+  std::vector<ProfEntry> pending;
+  std::vector<hipEvent_t> free_events;
+  double prof_ms[KC_COUNT] = {0};
+  long long prof_n[KC_COUNT] = {0};
+  double prof_bytes[KC_COUNT] = {0};
+};
+
+namespace {
+
+hca_status fail(hca_ctx* c, hca_status st, const std::string& msg) {
+  if (c) {
+    c->err = msg;
+    if (st != HCA_E_RANGE) c->failed = true;
+  }
+  return st;
+}
+
+#define HIPCHK(ctx, expr)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(ctx, HCA_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  return hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+}
+
+hipEvent_t take_event(hca_ctx* c) {
+  if (!c->free_events.empty()) {
+    hipEvent_t e = c->free_events.back();
+    c->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct ProfScope {
+  hca_ctx* c;
+  int kc;
+  int iter;
+  double bytes;
+  hipEvent_t a = nullptr;
+  ProfScope(hca_ctx* c_, int kc_, double bytes_, int iter_ = -1)
+      : c(c_), kc(kc_), iter(iter_), bytes(bytes_) {
+    if (c->prm.profile) {
+      a = take_event(c);
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~ProfScope() {
+    if (!c->prm.profile || !a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, c->stream);
+    c->pending.push_back(ProfEntry{kc, a, b, iter, bytes});
+  }
+};
+
+// Accumulate every pending timing; CG launches at iteration >= real_iters
+// found their replicates already finished and are dropped.
+void prof_flush(hca_ctx* c, int real_iters) {
+  if (c->pending.empty()) return;
+  (void)hipEventSynchronize(c->pending.back().b);
+  for (const ProfEntry& e : c->pending) {
+    const bool noop = e.iter >= 0 && e.iter >= real_iters;
+    if (!noop) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+        c->prof_ms[e.kc] += ms;
+        c->prof_n[e.kc] += 1;
+        c->prof_bytes[e.kc] += e.bytes;
+      }
+    }
+    c->free_events.push_back(e.a);
+    c->free_events.push_back(e.b);
+  }
+  c->pending.clear();
+}
+
+double bytes_all(const hca_ctx* c, int kc) { return kBytesPerVoxel[kc] * (double)c->ntot; }
+
+DevParams make_dev_params(const hca_params& p) {
+  DevParams d{};
+  d.dt = p.dt_min;
+  d.inv_dt = 1.0 / p.dt_min;
+  d.aK = p.D_K / (p.h_um * p.h_um);
+  d.aG = p.D_G / (p.h_um * p.h_um);
+  d.r_k = p.r_k;
+  d.K0 = p.K0;
+  d.phi_K = p.phi_K;
+  d.K1 = p.K1;
+  d.psi_G = p.psi_G;
+  d.kappa_G = p.kappa_G;
+  for (int i = 0; i < 2; ++i) {
+    d.k_pk[i] = p.k_pk[i];
+    d.G_ref[i] = p.G_ref[i];
+    d.b_int[i] = p.b_int[i];
+  }
+  d.k1 = p.k1;
+  d.k1p = p.k1p;
+  d.K_p53 = p.K_p53;
+  d.k2 = p.k2;
+  d.k2p = p.k2p;
+  d.k2pp = p.k2pp;
+  d.J5 = p.J5;
+  d.K_V = p.K_V;
+  d.K_phi = p.K_phi;
+  d.T_cycle = p.T_cycle;
+  d.nsub = p.ode_substeps;
+  return d;
+}
+
+int pick_tx(int nx) {
+  if (nx > 32) return 64;
+  if (nx > 16) return 32;
+  return 16;
+}
+
+// Conjugate-gradient solve of (diag(c) - a Lap) x = b for every replicate.
+// Launches iterations in batches sized from the previous solve of the same
+// field and polls the per-replicate scalars between batches.
+hca_status solve(hca_ctx* c, int field, double a, double rtol, int maxit, double* x,
+                 int* real_iters_out) {
+  {
+    ProfScope ps(c, KC_CG_START, bytes_all(c, KC_CG_START));
+    launch_cg_start(c->stream, c->work, a, rtol, maxit, c->c, c->b, x, c->sb);
+  }
+  int launched = 0;
+  int batch = std::max(1, c->last_it[field] - 1);
+  int real = 0;
+  for (;;) {
+    batch = std::min(batch, maxit - launched);
+    for (int k = 0; k < batch; ++k, ++launched) {
+      {
+        ProfScope ps(c, KC_CG_APPLY, bytes_all(c, KC_CG_APPLY), launched);
+        launch_cg_apply(c->stream, c->work, a, c->c, c->sb, launched & 1);
+      }
+      {
+        ProfScope ps(c, KC_CG_UPDATE, bytes_all(c, KC_CG_UPDATE), launched);
+        launch_cg_update(c->stream, c->work, a, rtol, maxit, c->c, x, c->sb, launched & 1);
+      }
+    }
+    HIPCHK(c, hipMemcpyAsync(c->h_ss, c->sb.ss, sizeof(SolveScal) * c->nreps,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    bool all = true;
+    real = 0;
+    for (int r = 0; r < c->nreps; ++r) {
+      all = all && c->h_ss[r].done;
+      real = std::max(real, c->h_ss[r].it);
+    }
+    if (all || launched >= maxit) break;
+    batch = 2;
+  }
+  prof_flush(c, real);
+  c->last_ss[field].assign(c->h_ss, c->h_ss + c->nreps);
+  c->last_it[field] = real;
+  if (real_iters_out) *real_iters_out = real;
+  for (int r = 0; r < c->nreps; ++r)
+    if (!c->h_ss[r].conv) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "field %d replicate %d: CG stopped at %d iterations, rel. res %.3e",
+               field, r, c->h_ss[r].it,
+               c->h_ss[r].bb > 0 ? std::sqrt(c->h_ss[r].rr / c->h_ss[r].bb) : 0.0);
+      return fail(c, HCA_E_NOCONV, buf);
+    }
+  return HCA_OK;
+}
+
+hca_status run_phases(hca_ctx* c, unsigned mask) {
+  const Work& wk = c->work;
+  hipStream_t s = c->stream;
+  if (mask & (HCA_PH_O2 | HCA_PH_DRUGS)) {
+    ProfScope ps(c, KC_PLASMA, 0.0);
+    launch_plasma(s, wk, c->dp, c->d_step, c->dose_t, c->dose_a, c->g0);
+  }
+  if (mask & HCA_PH_O2) {
+    {
+      ProfScope ps(c, KC_SETUP_O2, bytes_all(c, KC_SETUP_O2));
+      launch_setup_o2(s, wk, c->dp, c->L, c->w, c->K, c->c, c->b, 0);
+    }
+    hca_status st = solve(c, 0, c->dp.aK, c->prm.cg_rtol, c->prm.cg_maxit, c->K, nullptr);
+    if (st != HCA_OK) return st;
+  }
+  if (mask & HCA_PH_DRUGS) {
+    double* G[2] = {c->G1, c->G2};
+    for (int i = 0; i < 2; ++i) {
+      {
+        ProfScope ps(c, KC_SETUP_DRUG, bytes_all(c, KC_SETUP_DRUG));
+        launch_setup_drug(s, wk, c->dp, i, c->w, G[i], c->g0, c->c, c->b);
+      }
+      hca_status st = solve(c, 1 + i, c->dp.aG, c->prm.cg_rtol, c->prm.cg_maxit, G[i], nullptr);
+      if (st != HCA_OK) return st;
+    }
+  }
+  if (mask & HCA_PH_ODE) {
+    ProfScope ps(c, KC_ODE, bytes_all(c, KC_ODE));
+    launch_ode(s, wk, c->dp, c->L, c->K, c->P, c->Vc, c->phi);
+  }
+  if (mask & HCA_PH_CA) {
+    launch_zero_counters(s, c->d_cnt, c->nreps, 1);
+    {
+      ProfScope ps(c, KC_CA_PROPOSE, bytes_all(c, KC_CA_PROPOSE));
+      launch_ca_propose(s, wk, c->dp, c->d_step, c->L, c->w, c->K, c->G1, c->G2, c->phi, c->code);
+    }
+    {
+      ProfScope ps(c, KC_CA_RESOLVE, bytes_all(c, KC_CA_RESOLVE));
+      launch_ca_resolve(s, wk, c->L, c->w, c->phi, c->code, c->win);
+    }
+    {
+      ProfScope ps(c, KC_CA_FINALIZE, bytes_all(c, KC_CA_FINALIZE));
+      launch_ca_finalize(s, wk, c->L, c->phi, c->P, c->Vc, c->code, c->win, c->d_cnt);
+    }
+  }
+  if (mask & HCA_PH_STATS) {
+    launch_zero_counters(s, c->d_cnt, c->nreps, 0);
+    ProfScope ps(c, KC_STATS, bytes_all(c, KC_STATS));
+    launch_stats(s, wk, c->L, c->w, c->d_fields, 6, c->d_cnt);
+  }
+  if (mask & HCA_PH_ADVANCE) {
+    launch_advance(s, c->d_step);
+    c->step += 1;
+  }
+  HIPCHK(c, hipGetLastError());
+  return HCA_OK;
+}
+
+hca_status check_after(hca_ctx* c) {
+  HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(Counters) * c->nreps, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_flush(c, 0);
+  for (int r = 0; r < c->nreps; ++r)
+    if (c->h_cnt[r].nonfinite) {
+      char buf[96];
+      snprintf(buf, sizeof buf, "replicate %d: %llu non-finite field values", r,
+               (unsigned long long)c->h_cnt[r].nonfinite);
+      return fail(c, HCA_E_NONFINITE, buf);
+    }
+  return HCA_OK;
+}
+
+hca_status validate_reps(const hca_replicate* reps, int n, std::string& msg, int& singular) {
+  singular = -1;
+  for (int r = 0; r < n; ++r) {
+    const hca_replicate& R = reps[r];
+    char buf[160];
+    if (R.nx < 1 || R.ny < 1 || R.nz < 1 || R.nx > 32767 || R.ny > 32767 || R.nz > 32767) {
+      snprintf(buf, sizeof buf, "replicate %d: lattice %dx%dx%d out of range", r, R.nx, R.ny, R.nz);
+      msg = buf;
+      return HCA_E_INVALID;
+    }
+    if (!R.cell || !R.vessel_w) {
+      snprintf(buf, sizeof buf, "replicate %d: null cell or vessel map", r);
+      msg = buf;
+      return HCA_E_INVALID;
+    }
+    const long long nv = (long long)R.nx * R.ny * R.nz;
+    int nves = 0;
+    for (long long i = 0; i < nv; ++i) {
+      const double wv = R.vessel_w[i];
+      const uint8_t l = R.cell[i];
+      if (!(std::isfinite(wv) && wv >= 0.0) || l > 2 || (l != 0 && wv != 0.0)) {
+        snprintf(buf, sizeof buf,
+                 "replicate %d voxel %lld: cell %d, w %g (codes 0..2, finite w >= 0, no cell "
+                 "on a vessel)",
+                 r, i, (int)l, wv);
+        msg = buf;
+        return HCA_E_INVALID;
+      }
+      nves += wv > 0.0;
+    }
+    if (nves == 0 && singular < 0) singular = r;
+    for (int d = 0; d < 2; ++d) {
+      if (R.n_doses[d] < 0 || R.n_doses[d] > HCA_MAX_DOSES ||
+          (R.n_doses[d] > 0 && (!R.dose_t_min[d] || !R.dose_amt[d]))) {
+        snprintf(buf, sizeof buf, "replicate %d drug %d: bad dose list", r, d);
+        msg = buf;
+        return HCA_E_INVALID;
+      }
+      for (int k = 0; k < R.n_doses[d]; ++k) {
+        if (!std::isfinite(R.dose_t_min[d][k]) || !std::isfinite(R.dose_amt[d][k]) ||
+            R.dose_t_min[d][k] < 0.0 || R.dose_amt[d][k] < 0.0 ||
+            (k > 0 && R.dose_t_min[d][k] < R.dose_t_min[d][k - 1])) {
+          snprintf(buf, sizeof buf, "replicate %d drug %d: dose %d not finite, negative or unsorted",
+                   r, d, k);
+          msg = buf;
+          return HCA_E_INVALID;
+        }
+      }
+    }
+  }
+  return HCA_OK;
+}
+
+hca_status validate_params(const hca_params* p, std::string& msg) {
+  const double pos[] = {p->h_um, p->dt_min, p->D_K, p->D_G, p->K1, p->G_ref[0], p->G_ref[1],
+                        p->K_p53, p->J5, p->K_V, p->K_phi, p->T_cycle, p->cg_rtol, p->init_rtol};
+  for (double v : pos)
+    if (!(std::isfinite(v) && v > 0.0)) {
+      msg = "parameter must be finite and > 0";
+      return HCA_E_INVALID;
+    }
+  const double nonneg[] = {p->r_k, p->K0, p->phi_K, p->psi_G, p->kappa_G, p->k_pk[0], p->k_pk[1],
+                           p->k1, p->k1p, p->k2, p->k2p};
+  for (double v : nonneg)
+    if (!(std::isfinite(v) && v >= 0.0)) {
+      msg = "parameter must be finite and >= 0";
+      return HCA_E_INVALID;
+    }
+  if (!std::isfinite(p->k2pp) || p->b_int[0] < 1 || p->b_int[1] < 1 || p->b_int[0] > 64 ||
+      p->b_int[1] > 64 || p->ode_substeps < 1 || p->cg_maxit < 1 || p->init_maxit < 1 ||
+      (p->precond != 0 && p->precond != 1)) {
+    msg = "integer parameter out of range";
+    return HCA_E_INVALID;
+  }
+  return HCA_OK;
+}
+
+hca_status build_tables(hca_ctx* c) {
+  std::vector<RepDev> rd(c->nreps);
+  std::vector<FlatBlk> flat;
+  std::vector<Tile> tiles;
+  const int tz = 16;
+  for (int r = 0; r < c->nreps; ++r) {
+    const RepHost& R = c->reps[r];
+    // tile shape per replicate, so a replicate's arithmetic (and rounding) is
+    // the same alone or in a batch
+    const int tx = pick_tx(R.nx);
+    const int ty = kBlock / tx;
+    RepDev& d = rd[r];
+    memset(&d, 0, sizeof d);
+    d.nx = R.nx;
+    d.ny = R.ny;
+    d.nz = R.nz;
+    d.off = R.off;
+    d.n = R.n;
+    d.seed = R.seed;
+    const long long chunks = (R.n + kFlatChunk - 1) / kFlatChunk;
+    d.flat_nb = (int)std::min<long long>(chunks, kMaxFlatBlocksPerRep);
+    d.flat_b0 = (int)flat.size();
+    for (int k = 0; k < d.flat_nb; ++k) flat.push_back(FlatBlk{r, k});
+    d.tile_b0 = (int)tiles.size();
+    for (int z0 = 0; z0 < R.nz; z0 += tz)
+      for (int y0 = 0; y0 < R.ny; y0 += ty)
+        for (int x0 = 0; x0 < R.nx; x0 += tx) {
+          Tile t{};
+          t.rep = r;
+          t.x0 = (short)x0;
+          t.y0 = (short)y0;
+          t.z0 = (short)z0;
+          t.z1 = (short)std::min(R.nz, z0 + tz);
+          tiles.push_back(t);
+        }
+    d.tile_nb = (int)tiles.size() - d.tile_b0;
+    d.dose_off = r * 2 * HCA_MAX_DOSES;
+    d.tx = tx;
+  }
+  c->work.nreps = c->nreps;
+  c->work.nflat = (int)flat.size();
+  c->work.ntiles = (int)tiles.size();
+  HIPCHK(c, dalloc(&c->d_reps, rd.size()));
+  HIPCHK(c, dalloc(&c->d_flat, flat.size()));
+  HIPCHK(c, dalloc(&c->d_tiles, tiles.size()));
+  HIPCHK(c, hipMemcpy(c->d_reps, rd.data(), rd.size() * sizeof(RepDev), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_flat, flat.data(), flat.size() * sizeof(FlatBlk), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  c->work.reps = c->d_reps;
+  c->work.flat = c->d_flat;
+  c->work.tiles = c->d_tiles;
+  return HCA_OK;
+}
+
+hca_status alloc_all(hca_ctx* c) {
+  const size_t n = (size_t)c->ntot;
+  HIPCHK(c, dalloc(&c->L, n));
+  HIPCHK(c, dalloc(&c->code, n));
+  HIPCHK(c, dalloc(&c->win, n));
+  double** f64[] = {&c->w, &c->K, &c->G1, &c->G2, &c->P, &c->Vc, &c->phi, &c->c, &c->b,
+                    &c->sb.r, &c->sb.z, &c->sb.p0, &c->sb.p1, &c->sb.q};
+  for (double** p : f64) {
+    hipError_t e = dalloc(p, n);
+    if (e == hipErrorOutOfMemory) return fail(c, HCA_E_NOMEM, "device memory exhausted");
+    HIPCHK(c, e);
+  }
+  const size_t nwork = (size_t)std::max(c->work.ntiles, c->work.nflat);
+  HIPCHK(c, dalloc(&c->sb.partial, 3 * nwork));
+  HIPCHK(c, dalloc(&c->sb.counter, c->nreps));
+  HIPCHK(c, hipMemset(c->sb.counter, 0, sizeof(unsigned) * c->nreps));
+  HIPCHK(c, dalloc(&c->sb.ss, c->nreps));
+  HIPCHK(c, hipMemset(c->sb.ss, 0, sizeof(SolveScal) * c->nreps));
+  HIPCHK(c, dalloc(&c->sb.ndone, 1));
+  HIPCHK(c, dalloc(&c->dose_t, (size_t)c->nreps * 2 * HCA_MAX_DOSES));
+  HIPCHK(c, dalloc(&c->dose_a, (size_t)c->nreps * 2 * HCA_MAX_DOSES));
+  HIPCHK(c, dalloc(&c->g0, (size_t)c->nreps * 2));
+  HIPCHK(c, dalloc(&c->d_step, 1));
+  HIPCHK(c, dalloc(&c->d_cnt, c->nreps));
+  HIPCHK(c, hipMemset(c->d_cnt, 0, sizeof(Counters) * c->nreps));
+  HIPCHK(c, dalloc(&c->d_fields, 6));
+  HIPCHK(c, dalloc(&c->d_bad, 1));
+  const double* fl[6] = {c->K, c->G1, c->G2, c->P, c->Vc, c->phi};
+  HIPCHK(c, hipMemcpy(c->d_fields, fl, sizeof fl, hipMemcpyHostToDevice));
+  HIPCHK(c, hipHostMalloc((void**)&c->h_ss, sizeof(SolveScal) * c->nreps, hipHostMallocDefault));
+  HIPCHK(c, hipHostMalloc((void**)&c->h_cnt, sizeof(Counters) * c->nreps, hipHostMallocDefault));
+  return HCA_OK;
+}
+
+// Algorithm 1, steady oxygen: Picard on the uptake coefficient, each iterate
+// one CG solve; stops when the nonlinear residual of the current iterate
+// (the solve's initial residual) is below init_rtol ||b||.
+hca_status steady_oxygen(hca_ctx* c) {
+  const Work& wk = c->work;
+  // K^(0) = K0
+  std::vector<double> k0((size_t)c->ntot, c->prm.K0);
+  HIPCHK(c, hipMemcpyAsync(c->K, k0.data(), k0.size() * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream));
+  for (int m = 0; m < c->prm.init_maxit; ++m) {
+    launch_setup_o2(c->stream, wk, c->dp, c->L, c->w, c->K, c->c, c->b, 1);
+    launch_cg_start(c->stream, wk, c->dp.aK, c->prm.init_rtol, c->prm.cg_maxit, c->c, c->b, c->K,
+                    c->sb);
+    HIPCHK(c, hipMemcpyAsync(c->h_ss, c->sb.ss, sizeof(SolveScal) * c->nreps,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    bool all = true;
+    for (int r = 0; r < c->nreps; ++r) all = all && c->h_ss[r].conv;
+    if (all) {
+      c->picard_iters = m;
+      return HCA_OK;
+    }
+    hca_status st = solve(c, 0, c->dp.aK, c->prm.cg_rtol, c->prm.cg_maxit, c->K, nullptr);
+    if (st != HCA_OK) return st;
+  }
+  return fail(c, HCA_E_NOCONV, "steady oxygen Picard iteration did not converge");
+}
+
+void free_all(hca_ctx* c) {
+  void* bufs[] = {c->L, c->code, c->win, c->w, c->K, c->G1, c->G2, c->P, c->Vc, c->phi, c->c,
+                  c->b, c->sb.r, c->sb.z, c->sb.p0, c->sb.p1, c->sb.q, c->sb.partial,
+                  c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->d_step,
+                  c->d_reps, c->d_flat, c->d_tiles, c->d_cnt, (void*)c->d_fields, c->d_bad};
+  for (void* p : bufs)
+    if (p) (void)hipFree(p);
+  if (c->h_ss) (void)hipHostFree(c->h_ss);
+  if (c->h_cnt) (void)hipHostFree(c->h_cnt);
+  for (auto& e : c->pending) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  for (auto e : c->free_events) (void)hipEventDestroy(e);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+}
+
+void* field_ptr(hca_ctx* c, hca_field f, size_t& elem) {
+  elem = 8;
+  switch (f) {
+    case HCA_F_O2: return c->K;
+    case HCA_F_DRUG1: return c->G1;
+    case HCA_F_DRUG2: return c->G2;
+    case HCA_F_CELL: elem = 1; return c->L;
+    case HCA_F_P53: return c->P;
+    case HCA_F_VEGF_IC: return c->Vc;
+    case HCA_F_PHI: return c->phi;
+    case HCA_F_VESSEL_W: return c->w;
+  }
+  return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+hca_status hca_default_params(hca_params* out) {
+  if (!out) return HCA_E_INVALID;
+  memset(out, 0, sizeof *out);
+  out->h_um = 20.0;
+  out->dt_min = 30.0;
+  out->D_K = 1.05e5;
+  out->r_k = 1.88e4;
+  out->K0 = 20.0;
+  out->phi_K = 900.0;
+  out->K1 = 2.5;
+  out->D_G = 9.6e3;
+  out->psi_G = 1.0e-2;
+  out->kappa_G = 0.1;
+  out->k_pk[0] = 3.93e3 / 2430e3;   // cyclophosphamide cl_3 / u
+  out->k_pk[1] = 1.75 / 27.0;       // fluorouracil v_max / k_m (linear regime)
+  out->G_ref[0] = 1.0;
+  out->G_ref[1] = 1.0;
+  out->b_int[0] = 1;
+  out->b_int[1] = 1;
+  out->k1 = 4.0e-4;
+  out->k1p = 1.0e-2;
+  out->K_p53 = 1.0e-2;
+  out->k2 = 2.0e-3;
+  out->k2p = 1.0e-2;
+  out->k2pp = -2.0e-4;
+  out->J5 = 4.0e-2;
+  out->K_V = 1.0e-2;
+  out->K_phi = 1.4;
+  out->T_cycle = 3.74 * 1440.0;
+  out->ode_substeps = 30;
+  out->precond = 0;
+  out->cg_rtol = 1.0e-10;
+  out->cg_maxit = 2000;
+  out->mg_smooth = 2;
+  out->mg_coarse_max = 4096;
+  out->init_rtol = 1.0e-10;
+  out->init_maxit = 200;
+  out->profile = 0;
+  return HCA_OK;
+}
+
+hca_status hca_init(hca_ctx** out, const hca_params* p, const hca_replicate* reps, int n_reps,
+                    void* stream) {
+  if (!out || !p || !reps || n_reps < 1) return HCA_E_INVALID;
+  *out = nullptr;
+  std::string msg;
+  hca_status st = validate_params(p, msg);
+  if (st != HCA_OK) return st;
+  int singular = -1;
+  st = validate_reps(reps, n_reps, msg, singular);
+  if (st != HCA_OK) {
+    fprintf(stderr, "hca_init: %s\n", msg.c_str());
+    return st;
+  }
+  if (singular >= 0) {
+    fprintf(stderr, "hca_init: replicate %d has no vessel: steady oxygen is zero\n", singular);
+    return HCA_E_SINGULAR;
+  }
+  hca_ctx* c = new (std::nothrow) hca_ctx();
+  if (!c) return HCA_E_NOMEM;
+  c->prm = *p;
+  c->dp = make_dev_params(*p);
+  c->nreps = n_reps;
+  long long off = 0;
+  for (int r = 0; r < n_reps; ++r) {
+    RepHost R{};
+    R.nx = reps[r].nx;
+    R.ny = reps[r].ny;
+    R.nz = reps[r].nz;
+    R.n = (long long)R.nx * R.ny * R.nz;
+    R.off = off;
+    R.seed = reps[r].seed;
+    off += R.n;
+    c->reps.push_back(R);
+  }
+  c->ntot = off;
+  auto bail = [&](hca_status s) {
+    if (c) {
+      if (!c->err.empty()) fprintf(stderr, "hca_init: %s\n", c->err.c_str());
+      free_all(c);
+      delete c;
+    }
+    return s;
+  };
+  if (hipGetDevice(&c->device) != hipSuccess) return bail(HCA_E_DEVICE);
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(HCA_E_DEVICE);
+    c->own_stream = true;
+  }
+  if ((st = build_tables(c)) != HCA_OK) return bail(st);
+  if ((st = alloc_all(c)) != HCA_OK) return bail(st);
+  // upload inputs and dose tables
+  std::vector<double> dt((size_t)n_reps * 2 * HCA_MAX_DOSES, 0.0), da(dt.size(), 0.0);
+  std::vector<RepDev> rd(n_reps);
+  if (hipMemcpy(rd.data(), c->d_reps, sizeof(RepDev) * n_reps, hipMemcpyDeviceToHost) != hipSuccess)
+    return bail(HCA_E_DEVICE);
+  for (int r = 0; r < n_reps; ++r) {
+    const RepHost& R = c->reps[r];
+    if (hipMemcpy(c->L + R.off, reps[r].cell, (size_t)R.n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->w + R.off, reps[r].vessel_w, (size_t)R.n * 8, hipMemcpyHostToDevice) !=
+            hipSuccess)
+      return bail(HCA_E_DEVICE);
+    for (int d = 0; d < 2; ++d) {
+      rd[r].ndose[d] = reps[r].n_doses[d];
+      for (int k = 0; k < reps[r].n_doses[d]; ++k) {
+        dt[(size_t)r * 2 * HCA_MAX_DOSES + d * HCA_MAX_DOSES + k] = reps[r].dose_t_min[d][k];
+        da[(size_t)r * 2 * HCA_MAX_DOSES + d * HCA_MAX_DOSES + k] = reps[r].dose_amt[d][k];
+      }
+    }
+  }
+  if (hipMemcpy(c->d_reps, rd.data(), sizeof(RepDev) * n_reps, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(c->dose_t, dt.data(), dt.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->dose_a, da.data(), da.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+    return bail(HCA_E_DEVICE);
+  long long zero = 0;
+  if (hipMemcpy(c->d_step, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess)
+    return bail(HCA_E_DEVICE);
+  if ((st = steady_oxygen(c)) != HCA_OK) return bail(st);
+  launch_init_cells(c->stream, c->work, c->dp, c->L, c->K, c->P, c->Vc, c->phi);
+  if (hipMemsetAsync(c->G1, 0, (size_t)c->ntot * 8, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->G2, 0, (size_t)c->ntot * 8, c->stream) != hipSuccess)
+    return bail(HCA_E_DEVICE);
+  launch_zero_counters(c->stream, c->d_cnt, n_reps, 1);
+  launch_zero_counters(c->stream, c->d_cnt, n_reps, 0);
+  launch_stats(c->stream, c->work, c->L, c->w, c->d_fields, 6, c->d_cnt);
+  if (hipGetLastError() != hipSuccess) return bail(HCA_E_DEVICE);
+  if ((st = check_after(c)) != HCA_OK) return bail(st);
+  for (int f = 0; f < 3; ++f) c->last_it[f] = 0;
+  for (int k = 0; k < KC_COUNT; ++k) c->prof_ms[k] = c->prof_n[k] = c->prof_bytes[k] = 0;
+  *out = c;
+  return HCA_OK;
+}
+
+hca_status hca_run_phases(hca_ctx* c, unsigned mask) {
+  if (!c) return HCA_E_INVALID;
+  if (c->failed) return HCA_E_INVALID;
+  hca_status st = run_phases(c, mask);
+  if (st != HCA_OK) return st;
+  return check_after(c);
+}
+
+hca_status hca_step(hca_ctx* c, int n_steps) {
+  if (!c || n_steps < 0) return HCA_E_INVALID;
+  if (c->failed) return HCA_E_INVALID;
+  for (int k = 0; k < n_steps; ++k) {
+    hca_status st = run_phases(c, HCA_PH_ALL);
+    if (st != HCA_OK) return st;
+  }
+  return check_after(c);
+}
+
+hca_status hca_fields(hca_ctx* c, int rep, hca_field f, void* dst, size_t dst_bytes,
+                      int dst_is_device) {
+  if (!c || !dst) return HCA_E_INVALID;
+  if (rep < 0 || rep >= c->nreps) return fail(c, HCA_E_RANGE, "replicate index out of range");
+  size_t elem = 0;
+  char* src = (char*)field_ptr(c, f, elem);
+  if (!src) return HCA_E_INVALID;
+  const RepHost& R = c->reps[rep];
+  const size_t bytes = (size_t)R.n * elem;
+  if (dst_bytes < bytes) return fail(c, HCA_E_RANGE, "destination buffer too small");
+  HIPCHK(c, hipMemcpyAsync(dst, src + (size_t)R.off * elem, bytes,
+                           dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return HCA_OK;
+}
+
+hca_status hca_set_field(hca_ctx* c, int rep, hca_field f, const void* src, size_t src_bytes,
+                         int src_is_device) {
+  if (!c || !src) return HCA_E_INVALID;
+  if (rep < 0 || rep >= c->nreps) return fail(c, HCA_E_RANGE, "replicate index out of range");
+  if (f == HCA_F_VESSEL_W) return HCA_E_INVALID;
+  size_t elem = 0;
+  char* dst = (char*)field_ptr(c, f, elem);
+  if (!dst) return HCA_E_INVALID;
+  const RepHost& R = c->reps[rep];
+  const size_t bytes = (size_t)R.n * elem;
+  if (src_bytes < bytes) return fail(c, HCA_E_RANGE, "source buffer too small");
+  const hipMemcpyKind kind = src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (f == HCA_F_CELL) {
+    // stage in the proposal buffer (rewritten by every CA pass) and validate
+    HIPCHK(c, hipMemcpyAsync(c->code + R.off, src, bytes, kind, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_bad, 0, sizeof(unsigned long long), c->stream));
+    launch_validate_cells(c->stream, c->work, c->code, c->w, rep, c->d_bad);
+    unsigned long long bad = 0;
+    HIPCHK(c, hipMemcpyAsync(&bad, c->d_bad, sizeof bad, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (bad) {
+      c->err = "cell map has codes outside {0,1,2} or cells on vessel voxels";
+      return HCA_E_INVALID;
+    }
+    HIPCHK(c, hipMemcpyAsync(dst + R.off, c->code + R.off, bytes, hipMemcpyDeviceToDevice,
+                             c->stream));
+  } else {
+    HIPCHK(c, hipMemcpyAsync(dst + (size_t)R.off * elem, src, bytes, kind, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return HCA_OK;
+}
+
+hca_status hca_set_step(hca_ctx* c, int64_t step) {
+  if (!c || step < 0) return HCA_E_INVALID;
+  long long s = step;
+  HIPCHK(c, hipMemcpyAsync(c->d_step, &s, sizeof s, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->step = step;
+  return HCA_OK;
+}
+
+hca_status hca_stats(hca_ctx* c, int rep, hca_stats_t* out) {
+  if (!c || !out) return HCA_E_INVALID;
+  if (rep < 0 || rep >= c->nreps) return fail(c, HCA_E_RANGE, "replicate index out of range");
+  HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(Counters) * c->nreps, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const Counters& k = c->h_cnt[rep];
+  memset(out, 0, sizeof *out);
+  out->step = c->step;
+  out->n_cancer = (int64_t)k.n_cancer;
+  out->n_stroma = (int64_t)k.n_stroma;
+  out->n_empty = (int64_t)k.n_empty;
+  out->n_vessel = (int64_t)k.n_vessel;
+  out->committed = (int64_t)k.committed;
+  out->divisions = (int64_t)k.divisions;
+  out->kills = (int64_t)k.kills;
+  out->nospace = (int64_t)k.nospace;
+  out->lost = (int64_t)k.lost;
+  out->total_divisions = (int64_t)k.total_divisions;
+  out->total_kills = (int64_t)k.total_kills;
+  for (int f = 0; f < 3; ++f) {
+    if ((int)c->last_ss[f].size() > rep) {
+      const SolveScal& s = c->last_ss[f][rep];
+      out->cg_iters[f] = s.it;
+      out->cg_relres[f] = s.bb > 0 ? std::sqrt(s.rr / s.bb) : 0.0;
+    }
+  }
+  out->nonfinite = k.nonfinite ? 1 : 0;
+  out->init_picard_iters = c->picard_iters;
+  return HCA_OK;
+}
+
+int hca_num_kernels(void) { return KC_COUNT; }
+
+const char* hca_kernel_name(int kernel) {
+  if (kernel < 0 || kernel >= KC_COUNT) return "";
+  return kKernelNames[kernel];
+}
+
+hca_status hca_kernel_time(hca_ctx* c, int kernel, double* ms, int64_t* launches,
+                           double* bytes_per_launch) {
+  if (!c || kernel < 0 || kernel >= KC_COUNT) return HCA_E_INVALID;
+  prof_flush(c, 1 << 30);
+  if (ms) *ms = c->prof_ms[kernel];
+  if (launches) *launches = c->prof_n[kernel];
+  if (bytes_per_launch)
+    *bytes_per_launch = c->prof_n[kernel] ? c->prof_bytes[kernel] / (double)c->prof_n[kernel] : 0.0;
+  return HCA_OK;
+}
+
+hca_status hca_reset_kernel_time(hca_ctx* c) {
+  if (!c) return HCA_E_INVALID;
+  prof_flush(c, 1 << 30);
+  for (int k = 0; k < KC_COUNT; ++k) c->prof_ms[k] = c->prof_n[k] = c->prof_bytes[k] = 0;
+  return HCA_OK;
+}
+
+hca_status hca_synchronize(hca_ctx* c) {
+  if (!c) return HCA_E_INVALID;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return HCA_OK;
+}
+
+const char* hca_last_error(const hca_ctx* c) { return c ? c->err.c_str() : ""; }
+
+void hca_destroy(hca_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+}
+
+}  // extern "C"

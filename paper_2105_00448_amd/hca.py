@@ -1,0 +1,257 @@
+"""ctypes binding of libhca (include/hca.h): argument marshalling only.
+
+Every computation runs in the HIP library.  If libhca.so is missing or
+cannot be loaded this module raises; there is no fallback path.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhca.so")
+_lib = None
+
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_NOCONV, E_NONFINITE, E_SINGULAR, E_RANGE = 0, -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {0: "HCA_OK", -1: "HCA_E_INVALID", -2: "HCA_E_NOMEM", -3: "HCA_E_DEVICE",
+                -4: "HCA_E_NOCONV", -5: "HCA_E_NONFINITE", -6: "HCA_E_SINGULAR", -7: "HCA_E_RANGE"}
+
+F_O2, F_DRUG1, F_DRUG2, F_CELL, F_P53, F_VEGF_IC, F_PHI, F_VESSEL_W = range(8)
+FIELDS = {"K": F_O2, "G1": F_DRUG1, "G2": F_DRUG2, "L": F_CELL, "P": F_P53, "Vc": F_VEGF_IC,
+          "phi": F_PHI, "w": F_VESSEL_W}
+
+PH_O2, PH_DRUGS, PH_ODE, PH_CA, PH_STATS, PH_ADVANCE = 1, 2, 4, 8, 16, 32
+PH_ALL = 63
+MAX_DOSES = 64
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("h_um", C.c_double), ("dt_min", C.c_double),
+        ("D_K", C.c_double), ("r_k", C.c_double), ("K0", C.c_double), ("phi_K", C.c_double),
+        ("K1", C.c_double),
+        ("D_G", C.c_double), ("psi_G", C.c_double), ("kappa_G", C.c_double),
+        ("k_pk", C.c_double * 2), ("G_ref", C.c_double * 2), ("b_int", C.c_int32 * 2),
+        ("k1", C.c_double), ("k1p", C.c_double), ("K_p53", C.c_double), ("k2", C.c_double),
+        ("k2p", C.c_double), ("k2pp", C.c_double), ("J5", C.c_double), ("K_V", C.c_double),
+        ("K_phi", C.c_double), ("T_cycle", C.c_double),
+        ("ode_substeps", C.c_int32),
+        ("precond", C.c_int32), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
+        ("mg_smooth", C.c_int32), ("mg_coarse_max", C.c_int32),
+        ("init_rtol", C.c_double), ("init_maxit", C.c_int32), ("profile", C.c_int32),
+    ]
+
+
+class Replicate(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("seed", C.c_uint64),
+        ("cell", C.POINTER(C.c_uint8)), ("vessel_w", C.POINTER(C.c_double)),
+        ("n_doses", C.c_int32 * 2),
+        ("dose_t_min", C.POINTER(C.c_double) * 2), ("dose_amt", C.POINTER(C.c_double) * 2),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64), ("n_cancer", C.c_int64), ("n_stroma", C.c_int64),
+        ("n_empty", C.c_int64), ("n_vessel", C.c_int64),
+        ("committed", C.c_int64), ("divisions", C.c_int64), ("kills", C.c_int64),
+        ("nospace", C.c_int64), ("lost", C.c_int64),
+        ("total_divisions", C.c_int64), ("total_kills", C.c_int64),
+        ("cg_iters", C.c_int32 * 3), ("cg_relres", C.c_double * 3),
+        ("nonfinite", C.c_int32), ("init_picard_iters", C.c_int32),
+    ]
+
+    def as_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if hasattr(v, "__len__") else v
+        return d
+
+
+def lib():
+    """Load libhca.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is not built: run `python -m paper_2105_00448_amd.build`")
+    L = C.CDLL(_LIB_PATH)
+    P = C.POINTER
+    vp = C.c_void_p
+    sigs = {
+        "hca_default_params": (C.c_int, [P(Params)]),
+        "hca_init": (C.c_int, [P(vp), P(Params), P(Replicate), C.c_int, vp]),
+        "hca_step": (C.c_int, [vp, C.c_int]),
+        "hca_run_phases": (C.c_int, [vp, C.c_uint]),
+        "hca_fields": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_size_t, C.c_int]),
+        "hca_set_field": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_size_t, C.c_int]),
+        "hca_set_step": (C.c_int, [vp, C.c_int64]),
+        "hca_stats": (C.c_int, [vp, C.c_int, P(Stats)]),
+        "hca_kernel_time": (C.c_int, [vp, C.c_int, P(C.c_double), P(C.c_int64), P(C.c_double)]),
+        "hca_kernel_name": (C.c_char_p, [C.c_int]),
+        "hca_num_kernels": (C.c_int, []),
+        "hca_reset_kernel_time": (C.c_int, [vp]),
+        "hca_synchronize": (C.c_int, [vp]),
+        "hca_last_error": (C.c_char_p, [vp]),
+        "hca_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+class HcaError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+
+
+def default_params(**overrides):
+    p = Params()
+    st = lib().hca_default_params(C.byref(p))
+    if st != OK:
+        raise HcaError(st, "hca_default_params")
+    for k, v in overrides.items():
+        if isinstance(v, (tuple, list)):
+            arr = getattr(p, k)
+            for i, x in enumerate(v):
+                arr[i] = x
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Simulation:
+    """One context: a batch of replicates stepped together.
+
+    ``replicates``: list of (cell uint8 (nz,ny,nx), w float64 (nz,ny,nx), seed,
+    (dose_times, dose_amts) per drug as a pair of sequences).
+    """
+
+    def __init__(self, replicates, params=None, stream=None):
+        self._lib = lib()
+        self.params = params if params is not None else default_params()
+        self.shapes = []
+        keep = []
+        reps = (Replicate * len(replicates))()
+        for r, (cell, w, seed, sched) in enumerate(replicates):
+            cell = np.ascontiguousarray(cell, dtype=np.uint8)
+            w = np.ascontiguousarray(w, dtype=np.float64)
+            if cell.shape != w.shape or cell.ndim != 3:
+                raise ValueError("cell and w must be (nz, ny, nx) arrays of one shape")
+            nz, ny, nx = cell.shape
+            self.shapes.append(cell.shape)
+            R = reps[r]
+            R.nx, R.ny, R.nz, R.seed = nx, ny, nz, int(seed)
+            R.cell = cell.ctypes.data_as(C.POINTER(C.c_uint8))
+            R.vessel_w = _dptr(w)
+            keep += [cell, w]
+            times, amts = sched
+            for d in range(2):
+                t = np.ascontiguousarray(times[d], dtype=np.float64)
+                a = np.ascontiguousarray(amts[d], dtype=np.float64)
+                R.n_doses[d] = len(t)
+                R.dose_t_min[d] = _dptr(t)
+                R.dose_amt[d] = _dptr(a)
+                keep += [t, a]
+        h = C.c_void_p()
+        st = self._lib.hca_init(C.byref(h), C.byref(self.params), reps, len(replicates),
+                                C.c_void_p(stream) if stream else None)
+        if st != OK:
+            raise HcaError(st, "hca_init failed (details on stderr)")
+        self._h = h
+
+    # -- stepping --------------------------------------------------------
+    def _check(self, st, what):
+        if st != OK:
+            raise HcaError(st, f"{what}: {self._lib.hca_last_error(self._h).decode()}")
+
+    def step(self, n=1):
+        self._check(self._lib.hca_step(self._h, n), "hca_step")
+
+    def run_phases(self, mask):
+        self._check(self._lib.hca_run_phases(self._h, mask), "hca_run_phases")
+
+    def set_step(self, n):
+        self._check(self._lib.hca_set_step(self._h, n), "hca_set_step")
+
+    # -- state -----------------------------------------------------------
+    def _check_rep(self, rep, f):
+        if not 0 <= rep < len(self.shapes):
+            # let the library report the range error
+            dummy = np.empty(1, dtype=np.uint8)
+            self._check(self._lib.hca_fields(self._h, rep, f, dummy.ctypes.data, 0, 0),
+                        "hca_fields")
+
+    def field(self, name, rep=0):
+        f = FIELDS[name]
+        self._check_rep(rep, f)
+        shape = self.shapes[rep]
+        out = np.empty(shape, dtype=np.uint8 if f == F_CELL else np.float64)
+        self._check(self._lib.hca_fields(self._h, rep, f, out.ctypes.data, out.nbytes, 0),
+                    "hca_fields")
+        return out
+
+    def field_to_device(self, name, tensor, rep=0):
+        """Copy into a caller-owned torch device tensor (device-to-device)."""
+        f = FIELDS[name]
+        self._check(self._lib.hca_fields(self._h, rep, f, tensor.data_ptr(),
+                                         tensor.numel() * tensor.element_size(), 1), "hca_fields")
+        return tensor
+
+    def set_field(self, name, arr, rep=0):
+        f = FIELDS[name]
+        a = np.ascontiguousarray(arr, dtype=np.uint8 if f == F_CELL else np.float64)
+        self._check(self._lib.hca_set_field(self._h, rep, f, a.ctypes.data, a.nbytes, 0),
+                    "hca_set_field")
+
+    def stats(self, rep=0):
+        s = Stats()
+        self._check(self._lib.hca_stats(self._h, rep, C.byref(s)), "hca_stats")
+        return s.as_dict()
+
+    def kernel_times(self):
+        out = {}
+        for k in range(self._lib.hca_num_kernels()):
+            ms, n, b = C.c_double(), C.c_int64(), C.c_double()
+            self._check(self._lib.hca_kernel_time(self._h, k, C.byref(ms), C.byref(n), C.byref(b)),
+                        "hca_kernel_time")
+            out[self._lib.hca_kernel_name(k).decode()] = dict(ms=ms.value, launches=n.value,
+                                                              bytes_per_launch=b.value)
+        return out
+
+    def reset_kernel_times(self):
+        self._check(self._lib.hca_reset_kernel_time(self._h), "hca_reset_kernel_time")
+
+    def synchronize(self):
+        self._check(self._lib.hca_synchronize(self._h), "hca_synchronize")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hca_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def schedule_tuple(sched):
+    """(times, amts) pair from a synth.DoseSchedule-like object."""
+    return (tuple(tuple(t) for t in sched.times), tuple(tuple(a) for a in sched.amts))

@@ -1,0 +1,124 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol that
+include/hca.h declares, carries the same Table 1 constants as the oracle, and
+rejects invalid inputs before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.constants import DEFAULT as ORACLE
+from paper_2105_00448_amd import hca
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(hca_\w+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(hca._LIB_PATH)
+    names = declared_symbols()
+    assert "hca_init" in names and "hca_step" in names and "hca_fields" in names
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_default_params_match_the_oracle_transcription_of_table1():
+    p = hca.default_params()
+    for name in ["h_um", "dt_min", "D_K", "r_k", "K0", "phi_K", "K1", "D_G", "psi_G", "kappa_G",
+                 "k1", "k1p", "K_p53", "k2", "k2p", "k2pp", "J5", "K_V", "K_phi", "T_cycle",
+                 "ode_substeps"]:
+        assert getattr(p, name) == getattr(ORACLE, name), name
+    assert list(p.k_pk) == list(ORACLE.k_pk)
+    assert list(p.G_ref) == list(ORACLE.G_ref)
+    assert list(p.b_int) == list(ORACLE.b_int)
+
+
+def tiny(shape=(3, 4, 5)):
+    cell = np.zeros(shape, dtype=np.uint8)
+    w = np.zeros(shape)
+    w[0, 0, 0] = 1.0
+    cell[1, 1, 1] = 1
+    return cell, w
+
+
+def init_status(reps, params=None):
+    lib = hca.lib()
+    params = params or hca.default_params()
+    arr = (hca.Replicate * len(reps))()
+    keep = []
+    for i, (cell, w, doses) in enumerate(reps):
+        R = arr[i]
+        R.nz, R.ny, R.nx = cell.shape
+        R.seed = 1
+        R.cell = cell.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        R.vessel_w = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        for d in range(2):
+            t = np.asarray(doses[d][0], dtype=np.float64)
+            a = np.asarray(doses[d][1], dtype=np.float64)
+            keep += [t, a]
+            R.n_doses[d] = len(t)
+            R.dose_t_min[d] = t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            R.dose_amt[d] = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    h = ctypes.c_void_p()
+    st = lib.hca_init(ctypes.byref(h), ctypes.byref(params), arr, len(reps), None)
+    assert not h.value
+    return st
+
+
+NODOSE = (((), ()), ((), ()))
+
+
+def test_rejects_cell_on_vessel():
+    cell, w = tiny()
+    cell[0, 0, 0] = 2
+    assert init_status([(cell, w, NODOSE)]) == hca.E_INVALID
+
+
+def test_rejects_bad_cell_code_and_bad_weight():
+    cell, w = tiny()
+    cell[2, 2, 2] = 3
+    assert init_status([(cell, w, NODOSE)]) == hca.E_INVALID
+    cell, w = tiny()
+    w[2, 3, 4] = np.nan
+    assert init_status([(cell, w, NODOSE)]) == hca.E_INVALID
+    cell, w = tiny()
+    w[2, 3, 4] = -1.0
+    assert init_status([(cell, w, NODOSE)]) == hca.E_INVALID
+
+
+def test_rejects_unsorted_or_negative_doses():
+    cell, w = tiny()
+    doses = (((30.0, 0.0), (1.0, 1.0)), ((), ()))
+    assert init_status([(cell, w, doses)]) == hca.E_INVALID
+    doses = (((0.0,), (-1.0,)), ((), ()))
+    assert init_status([(cell, w, doses)]) == hca.E_INVALID
+
+
+def test_no_vessel_is_singular():
+    cell, w = tiny()
+    w[:] = 0.0
+    assert init_status([(cell, w, NODOSE)]) == hca.E_SINGULAR
+
+
+def test_rejects_bad_params_and_arguments():
+    cell, w = tiny()
+    p = hca.default_params(cg_rtol=-1.0)
+    assert init_status([(cell, w, NODOSE)], p) == hca.E_INVALID
+    p = hca.default_params(b_int=(0, 1))
+    assert init_status([(cell, w, NODOSE)], p) == hca.E_INVALID
+    p = hca.default_params(precond=7)
+    assert init_status([(cell, w, NODOSE)], p) == hca.E_INVALID
+    lib = hca.lib()
+    assert lib.hca_init(None, None, None, 0, None) == hca.E_INVALID
+    assert lib.hca_step(None, 1) == hca.E_INVALID
+    lib.hca_destroy(None)

@@ -1,0 +1,254 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Fields: max-norm relative error <= 1e-10 (FP64 solves taken to a relative
+residual of 1e-13 here, so the solver error stays far below the bar).
+Cellular automaton and everything integer: bit-exact on shared inputs.
+"""
+import numpy as np
+import pytest
+
+from oracle import ca as oca
+from oracle import model as om
+from oracle import ode as oode
+from oracle.constants import DEFAULT as OP
+from paper_2105_00448_amd import hca, synth
+
+pytestmark = pytest.mark.gpu
+
+FIELD_TOL = 1e-10
+
+
+def parity_params(**kw):
+    base = dict(cg_rtol=1e-15, init_rtol=1e-15, cg_maxit=20000, init_maxit=400)
+    base.update(kw)
+    return hca.default_params(**base)
+
+
+def relerr(a, b):
+    scale = np.abs(b).max()
+    return np.abs(a - b).max() / (scale if scale > 0 else 1.0)
+
+
+def oracle_sched(sched):
+    return om.Schedule(times=sched.times, amts=sched.amts)
+
+
+def make_sim(tissues_scheds, **kw):
+    reps = [(t.cell, t.w, t.seed, (s.times, s.amts)) for t, s in tissues_scheds]
+    return hca.Simulation(reps, parity_params(**kw))
+
+
+def push_state(sim, s, rep=0):
+    for name in ("L", "K", "G1", "G2", "P", "Vc", "phi"):
+        sim.set_field(name, getattr(s, name), rep)
+    sim.set_step(s.step)
+
+
+@pytest.fixture(scope="module")
+def case32():
+    print("\n[case32] 32^3, 8 Gaussians, seed 1", flush=True)
+    tis = synth.make_tissue(32, 8, seed=1)
+    sched = synth.bolus_schedule([0])
+    s0 = om.init_state(tis.cell, tis.w, tis.seed, OP)
+    return tis, sched, s0
+
+
+def test_init_matches_oracle(case32):
+    tis, sched, s0 = case32
+    with make_sim([(tis, sched)]) as sim:
+        assert np.array_equal(sim.field("L"), s0.L)
+        assert relerr(sim.field("K"), s0.K) <= FIELD_TOL
+        assert relerr(sim.field("P"), s0.P) <= FIELD_TOL
+        assert relerr(sim.field("Vc"), s0.Vc) <= FIELD_TOL
+        assert np.array_equal(sim.field("phi"), s0.phi)      # Philox uniforms, exact
+        assert not sim.field("G1").any() and not sim.field("G2").any()
+        st = sim.stats()
+        assert st["n_cancer"] == np.count_nonzero(s0.L == 1)
+        assert st["n_vessel"] == np.count_nonzero(tis.w > 0)
+
+
+def test_solves_match_oracle_exact_solution(case32):
+    tis, sched, s0 = case32
+    osched = oracle_sched(sched)
+    # a state with drug already in the tissue: two oracle steps from init
+    s = s0
+    for _ in range(2):
+        s, _ = om.step(s, tis.w, osched, tis.seed, OP)
+    with make_sim([(tis, sched)]) as sim:
+        push_state(sim, s)
+        sim.run_phases(hca.PH_O2 | hca.PH_DRUGS)
+        K, G1, G2 = om.solve_fields(s, tis.w, osched, OP)
+        assert relerr(sim.field("K"), K) <= FIELD_TOL
+        assert relerr(sim.field("G1"), G1) <= FIELD_TOL
+        assert relerr(sim.field("G2"), G2) <= FIELD_TOL
+        it = sim.stats()["cg_iters"]
+        assert all(i > 0 for i in it)
+
+
+def test_ode_matches_oracle(case32):
+    tis, sched, s0 = case32
+    rng = np.random.default_rng(2)
+    s = s0.copy()
+    s.K = s0.K * (0.5 + rng.random(s0.K.shape))        # off the steady state
+    s.Vc = s0.Vc * (0.5 + rng.random(s0.K.shape))
+    s.Vc[s.L == 0] = 0.0
+    with make_sim([(tis, sched)]) as sim:
+        push_state(sim, s)
+        sim.run_phases(hca.PH_ODE)
+        P, Vc, phi = oode.ode_step(s.L, s.K, s.P, s.Vc, s.phi, OP)
+        assert relerr(sim.field("P"), P) <= FIELD_TOL
+        assert relerr(sim.field("Vc"), Vc) <= FIELD_TOL
+        assert np.array_equal(sim.field("phi"), phi)    # same rounding, no contraction
+
+
+def random_ca_state(tis, rng):
+    shape = tis.cell.shape
+    L = tis.cell.copy()
+    K = 5.0 + 15.0 * rng.random(shape)
+    K[rng.random(shape) < 0.3] = 12.5                # exact ties
+    G1 = rng.random(shape) * 0.4
+    G2 = rng.random(shape) * 0.2
+    phi = np.where(L == 1, rng.choice([0.3, 0.99, 1.0, 1.2, 1.2, 1.7], size=shape), 0.0)
+    P = np.where(L != 0, rng.random(shape), 0.0)
+    Vc = np.where(L != 0, rng.random(shape), 0.0)
+    return om.State(L, K, G1, G2, P, Vc, phi, step=int(rng.integers(0, 1000)))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_ca_bit_exact_on_shared_fields(case32, seed):
+    tis, sched, _ = case32
+    rng = np.random.default_rng(10 + seed)
+    s = random_ca_state(tis, rng)
+    with make_sim([(tis, sched)]) as sim:
+        push_state(sim, s)
+        sim.run_phases(hca.PH_CA | hca.PH_STATS)
+        Ln, phin, Pn, Vn, ev, _, _ = oca.ca_update(s.L, tis.w, s.K, s.G1, s.G2, s.phi, s.P, s.Vc,
+                                                   s.step, tis.seed, OP)
+        assert np.array_equal(sim.field("L"), Ln)
+        assert np.array_equal(sim.field("phi"), phin)
+        assert np.array_equal(sim.field("P"), Pn)
+        assert np.array_equal(sim.field("Vc"), Vn)
+        st = sim.stats()
+        for k in ("committed", "kills", "divisions", "nospace", "lost"):
+            assert st[k] == ev[k], k
+        assert ev["divisions"] > 10 and ev["lost"] > 0 and ev["kills"] > 10
+
+
+def test_trajectory_20_steps_resynchronised(case32):
+    """Config-1 trajectory: each step's solves and ODE vs the oracle at the
+    field tolerance, the CA bit-exact on the shared fields; the GPU restarts
+    every step from the oracle's state."""
+    tis, sched, s0 = case32
+    osched = oracle_sched(sched)
+    s = s0
+    total_div = total_kill = 0
+    with make_sim([(tis, sched)]) as sim:
+        for n in range(20):
+            push_state(sim, s)
+            sim.run_phases(hca.PH_O2 | hca.PH_DRUGS)
+            K, G1, G2 = om.solve_fields(s, tis.w, osched, OP)
+            for name, ref in (("K", K), ("G1", G1), ("G2", G2)):
+                assert relerr(sim.field(name), ref) <= FIELD_TOL, (n, name)
+            # shared fields for the cell update
+            sim.set_field("K", K)
+            sim.set_field("G1", G1)
+            sim.set_field("G2", G2)
+            sim.run_phases(hca.PH_ODE | hca.PH_CA | hca.PH_STATS | hca.PH_ADVANCE)
+            P, Vc, phi = oode.ode_step(s.L, K, s.P, s.Vc, s.phi, OP)
+            Ln, phin, Pn, Vn, ev, _, _ = oca.ca_update(s.L, tis.w, K, G1, G2, phi, P, Vc, s.step,
+                                                       tis.seed, OP)
+            assert np.array_equal(sim.field("L"), Ln), n
+            assert np.array_equal(sim.field("phi"), phin), n
+            assert relerr(sim.field("P"), Pn) <= FIELD_TOL
+            assert relerr(sim.field("Vc"), Vn) <= FIELD_TOL
+            st = sim.stats()
+            assert st["step"] == n + 1
+            assert (st["divisions"], st["kills"]) == (ev["divisions"], ev["kills"])
+            total_div += ev["divisions"]
+            total_kill += ev["kills"]
+            s = om.State(Ln, K, G1, G2, Pn, Vn, phin, s.step + 1)
+    assert total_div > 0 and total_kill > 0
+
+
+@pytest.mark.parametrize("shape", [(9, 23, 17), (1, 40, 33), (70, 5, 5), (2, 2, 130)])
+def test_ragged_lattices(shape):
+    print(f"\n[ragged] shape {shape}", flush=True)
+    tis = synth.make_tissue(shape, 4, seed=sum(shape))
+    if not (tis.w > 0).any():
+        tis.w.ravel()[0] = 1.0
+        tis.cell.ravel()[0] = 0
+    sched = synth.bolus_schedule([0, 2])
+    osched = oracle_sched(sched)
+    s = om.init_state(tis.cell, tis.w, tis.seed, OP)
+    with make_sim([(tis, sched)]) as sim:
+        assert relerr(sim.field("K"), s.K) <= FIELD_TOL
+        for n in range(4):
+            push_state(sim, s)
+            sim.run_phases(hca.PH_ALL)
+            s2, ev = om.step(s, tis.w, osched, tis.seed, OP)
+            for name in ("K", "G1", "G2", "P", "Vc"):
+                assert relerr(sim.field(name), getattr(s2, name)) <= FIELD_TOL, (n, name)
+            # CA on the oracle's fields: bit-exact
+            push_state(sim, s)
+            K, G1, G2 = om.solve_fields(s, tis.w, osched, OP)
+            P, Vc, phi = oode.ode_step(s.L, K, s.P, s.Vc, s.phi, OP)
+            for name, v in (("K", K), ("G1", G1), ("G2", G2), ("P", P), ("Vc", Vc), ("phi", phi)):
+                sim.set_field(name, v)
+            sim.run_phases(hca.PH_CA)
+            assert np.array_equal(sim.field("L"), s2.L)
+            assert np.array_equal(sim.field("phi"), s2.phi)
+            s = s2
+
+
+def test_batched_replicates_equal_single_runs():
+    specs = [((20, 24, 28), 11, [0]), ((17, 17, 17), 12, [1]), ((8, 40, 31), 13, [])]
+    cases = []
+    for shape, seed, days in specs:
+        t = synth.make_tissue(shape, 4, seed=seed)
+        cases.append((t, synth.bolus_schedule(days)))
+    with make_sim(cases, cg_rtol=1e-10, init_rtol=1e-10) as batch:
+        batch.step(4)
+        for r, case in enumerate(cases):
+            with make_sim([case], cg_rtol=1e-10, init_rtol=1e-10) as single:
+                single.step(4)
+                for name in ("L", "K", "G1", "G2", "P", "Vc", "phi"):
+                    assert np.array_equal(batch.field(name, r), single.field(name)), (r, name)
+                assert batch.stats(r)["total_divisions"] == single.stats()["total_divisions"]
+
+
+def test_runs_are_deterministic(case32):
+    tis, sched, _ = case32
+    out = []
+    for _ in range(2):
+        with make_sim([(tis, sched)], cg_rtol=1e-10, init_rtol=1e-10) as sim:
+            sim.step(3)
+            out.append([sim.field(n) for n in ("L", "K", "G1", "phi", "Vc")])
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
+def test_error_paths_on_device(case32):
+    tis, sched, _ = case32
+    with make_sim([(tis, sched)], cg_rtol=1e-10, init_rtol=1e-10) as sim:
+        bad = tis.cell.copy()
+        bad[tis.w > 0] = 1
+        with pytest.raises(hca.HcaError) as e:
+            sim.set_field("L", bad)
+        assert e.value.status == hca.E_INVALID
+        with pytest.raises(hca.HcaError) as e:
+            sim.field("K", rep=3)
+        assert e.value.status == hca.E_RANGE
+        sim.step(1)                 # context still usable
+        K = sim.field("K")
+        K[5, 5, 5] = np.nan
+        sim.set_field("K", K)
+        with pytest.raises(hca.HcaError) as e:
+            sim.step(1)
+        assert e.value.status in (hca.E_NONFINITE, hca.E_NOCONV)
+        with pytest.raises(hca.HcaError) as e:
+            sim.step(1)             # failed context refuses further steps
+        assert e.value.status == hca.E_INVALID
+        assert sim.field("L").shape == tis.cell.shape   # but still reads
+    with pytest.raises(hca.HcaError) as e:
+        make_sim([(tis, sched)], cg_rtol=1e-12, cg_maxit=2, init_rtol=1e-10)
+    assert e.value.status == hca.E_NOCONV
