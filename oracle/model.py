@@ -83,7 +83,7 @@ def steady_o2_system(L, w, K_iter, p):
     return c, b
 
 
-def steady_oxygen(L, w, p, picard_tol=1e-13, maxit=200, method="lu"):
+def steady_oxygen(L, w, p, picard_tol=1e-13, maxit=200, method="cg"):
     K = np.full(L.shape, p.K0)
     for it in range(maxit):
         c, b = steady_o2_system(L, w, K, p)
@@ -95,7 +95,7 @@ def steady_oxygen(L, w, p, picard_tol=1e-13, maxit=200, method="lu"):
     raise RuntimeError("steady oxygen Picard iteration did not converge")
 
 
-def init_state(L, w, seed, p, method="lu"):
+def init_state(L, w, seed, p, method="cg"):
     L = L.astype(np.uint8)
     K, _ = steady_oxygen(L, w, p, method=method)
     occ = L != 0
@@ -111,7 +111,7 @@ def init_state(L, w, seed, p, method="lu"):
     return State(L, K, z.copy(), z.copy(), P, Vc, phi, 0)
 
 
-def solve_fields(s, w, sched, p, method="lu"):
+def solve_fields(s, w, sched, p, method="cg"):
     """Steps 1-3: returns (K^{n+1}, G1^{n+1}, G2^{n+1})."""
     t1 = (s.step + 1) * p.dt_min
     g0 = plasma_pair(t1, sched, p)
@@ -124,7 +124,7 @@ def solve_fields(s, w, sched, p, method="lu"):
     return K, G1, G2
 
 
-def step(s, w, sched, seed, p, method="lu"):
+def step(s, w, sched, seed, p, method="cg"):
     """One coupled step; returns (new state, CA event counts)."""
     K, G1, G2 = solve_fields(s, w, sched, p, method)
     P, Vc, phi = ode.ode_step(s.L, K, s.P, s.Vc, s.phi, p)
