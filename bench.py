@@ -98,7 +98,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="plain128")
-    ap.add_argument("--precond", type=int, default=0)
+    ap.add_argument("--precond", type=int, default=1, help="0 Jacobi, 1 multigrid")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     args = ap.parse_args()

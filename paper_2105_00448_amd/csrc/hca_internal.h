@@ -105,6 +105,8 @@ void launch_init_cells(hipStream_t s, const Work& w, const DevParams& p, const u
 // solver (k_solver.hip)
 struct SolverBufs {
   double *r, *z, *p0, *p1, *q;
+  double* dinv;               // 1/diag(A), written by the start kernel (Jacobi)
+  int jacobi;                 // 1: Jacobi preconditioner inside the update kernel
   double* partial;            // per work item
   unsigned* counter;          // per replicate
   SolveScal* ss;              // per replicate
@@ -118,6 +120,64 @@ void launch_cg_apply(hipStream_t s, const Work& w, double a, const double* c,
                      const SolverBufs& sb, int parity);
 void launch_cg_update(hipStream_t s, const Work& w, double a, double rtol, int maxit,
                       const double* c, double* x, const SolverBufs& sb, int parity);
+
+// ---- geometric multigrid (k_mg.hip) ---------------------------------------
+constexpr int kMaxLevels = 16;
+constexpr int kCoarseThreads = 1024;
+constexpr int kCoarseMaxCellsPerThread = 8;
+
+// One replicate at one multigrid level.  Level k cell I covers fine cells
+// [I 2^k, min((I+1) 2^k, n0)) per axis; dims n_k = ceil(n_{k-1} / 2).
+struct MgRep {
+  int nx, ny, nz;
+  int k;
+  int n0x, n0y, n0z;
+  int active;               // 1: level smoothed by the global kernels (k < kc)
+  long long off;            // first cell of this replicate in the level arrays
+  int tile_b0, tile_nb;     // smoothing tiles (active levels)
+  int rtile_b0, rtile_nb;   // tiles of the cells this level receives by restriction
+  int tx, pad;
+};
+
+struct MgLevel {
+  const MgRep* reps;        // [nreps]
+  const Tile* tiles;        // smoothing tiles, reps with k < kc
+  int ntiles;
+  const Tile* rtiles;       // restriction-target tiles, reps with 1 <= k <= kc
+  int nrtiles;
+  float *c, *dinv, *r, *u, *ualt;
+};
+
+// The levels kc.. of one replicate, solved by one workgroup in LDS.
+struct MgCoarseRep {
+  int nlev;                 // LDS levels (kc .. kc+nlev-1), the last has one cell
+  int kc;
+  int n0[3];
+  int dims[kMaxLevels][3];
+  int lds_off[kMaxLevels];  // float offset of each level's (u, r, dinv) block
+  long long off_kc;         // replicate offset in the level-kc arrays
+};
+
+struct MgBufs {
+  MgLevel lev[kMaxLevels];
+  int nlev_glob;            // max over replicates of kc
+  const MgCoarseRep* coarse;
+  int coarse_lds_bytes;
+  float omega;
+  float** lev_c;            // device arrays of the per-level pointers
+  float** lev_r;
+  float** lev_u;
+};
+
+void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, double a, const double* c);
+// One V-cycle on the residual sb.r, result in sb.z; finishes the flexible-CG
+// scalars (r.z, beta) with the same last-workgroup reduction as the CG kernels.
+// `hook(ctx, segment, begin)` brackets the launches of each segment (for
+// kernel timing); segments: see MgSegment.
+enum MgSegment { MG_PRE0 = 0, MG_RESTRICT0, MG_DOWN, MG_COARSE, MG_UP, MG_POST1_0, MG_POST2_0 };
+typedef void (*MgHook)(void* ctx, int segment, int begin);
+void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, double a,
+                      const SolverBufs& sb, MgHook hook, void* hook_ctx);
 
 // ODE (k_ode.hip)
 void launch_ode(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,

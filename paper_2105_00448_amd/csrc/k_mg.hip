@@ -1,0 +1,543 @@
+// Geometric multigrid V-cycle, FP32, used as the preconditioner of the FP64
+// flexible CG for the implicit-Euler systems of Eqs. (oxygen) and (chemo).
+// (The paper preconditions the same SPD systems with algebraic multigrid.)
+//
+// Hierarchy: voxel-centred 2:1 coarsening per axis, n_{k+1} = ceil(n_k / 2); a
+// level-k cell I covers the fine cells [I 2^k, min((I+1) 2^k, n0)) per axis
+// (ragged at odd edges).  The level-k operator is
+//     (A_k u)_I = c_I u_I + sum_faces g_IJ (u_I - u_J),
+// c_I the sum of the fine reaction coefficients over the cell, and g_IJ the
+// finite-volume coupling of the two aggregates: D/h^2 times the shared face
+// area over the centre distance, both in fine-voxel units,
+//     g = a * area / ((e_I + e_J) / 2),   e = extents along the face normal.
+// Restriction sums fine residuals over the aggregate, prolongation is
+// piecewise constant; smoothing is weighted Jacobi (two sweeps before and two
+// after the coarse-grid correction).  Levels above `mg_coarse_max` cells run
+// as multi-workgroup kernels; the remaining levels of each replicate are one
+// workgroup working in LDS down to a single cell (solved exactly).
+//
+// Fused kernels per global level k:
+//   pre      u1 = w Dinv r (first sweep from zero, formed on the fly at the
+//            neighbours), u2 = (1-w) u1 + w Dinv (r + sum g u1_J)
+//   restrict r_{k+1}(I) = sum over children of (r - A u2)
+//   post1    u3 = u2 + P e_{k+1} (formed on the fly), u4 = Jacobi(u3)
+//   post2    u5 = Jacobi(u4); at level 0 u5 is the CG's z, and the same kernel
+//            reduces r.z and finishes beta of the flexible CG.
+#include "dev_util.h"
+
+namespace hca {
+
+template <bool UNI>
+struct Geo {
+  int nx, ny, nz, k, n0x, n0y, n0z;
+  float a;
+
+  __device__ inline int ext(int I, int n0) const {
+    if (UNI) return 1;
+    const int lo = I << k;
+    const int hi = min((I + 1) << k, n0);
+    return hi - lo;
+  }
+  // couplings of the faces (x,y,z)-(x+1,y,z), (x,y,z)-(x,y+1,z), (x,y,z)-(x,y,z+1)
+  __device__ inline float gx(int x, int y, int z) const {
+    if (UNI) return a;
+    return 2.f * a * (float)(ext(y, n0y) * ext(z, n0z)) / (float)(ext(x, n0x) + ext(x + 1, n0x));
+  }
+  __device__ inline float gy(int x, int y, int z) const {
+    if (UNI) return a;
+    return 2.f * a * (float)(ext(x, n0x) * ext(z, n0z)) / (float)(ext(y, n0y) + ext(y + 1, n0y));
+  }
+  __device__ inline float gz(int x, int y, int z) const {
+    if (UNI) return a;
+    return 2.f * a * (float)(ext(x, n0x) * ext(y, n0y)) / (float)(ext(z, n0z) + ext(z + 1, n0z));
+  }
+  // sum of the couplings of the existing faces of (x,y,z)
+  __device__ inline float gsum(int x, int y, int z) const {
+    float s = 0.f;
+    if (x > 0) s += gx(x - 1, y, z);
+    if (x + 1 < nx) s += gx(x, y, z);
+    if (y > 0) s += gy(x, y - 1, z);
+    if (y + 1 < ny) s += gy(x, y, z);
+    if (z > 0) s += gz(x, y, z - 1);
+    if (z + 1 < nz) s += gz(x, y, z);
+    return s;
+  }
+};
+
+template <bool UNI>
+__device__ inline Geo<UNI> geo_of(const MgRep& m, float a) {
+  Geo<UNI> g;
+  g.nx = m.nx;
+  g.ny = m.ny;
+  g.nz = m.nz;
+  g.k = m.k;
+  g.n0x = m.n0x;
+  g.n0y = m.n0y;
+  g.n0z = m.n0z;
+  g.a = a;
+  return g;
+}
+
+// sum_J g_IJ V(J) over the existing neighbours of (x, y, z); V(x,y,z,idx)
+// with idx the level-array index; z-neighbours come from the caller.
+template <bool UNI, typename VF>
+__device__ inline float nb_sum_xy(const Geo<UNI>& G, int x, int y, int z, long long i, VF V) {
+  float s = 0.f;
+  if (x > 0) s += G.gx(x - 1, y, z) * V(x - 1, y, z, i - 1);
+  if (x + 1 < G.nx) s += G.gx(x, y, z) * V(x + 1, y, z, i + 1);
+  if (y > 0) s += G.gy(x, y - 1, z) * V(x, y - 1, z, i - G.nx);
+  if (y + 1 < G.ny) s += G.gy(x, y, z) * V(x, y + 1, z, i + G.nx);
+  return s;
+}
+
+// March one (x, y) column over [z0, z1): f(z, i, v_i, sum_J g_IJ v_J).
+template <bool UNI, typename VF, typename F>
+__device__ inline void mg_column(const Geo<UNI>& G, int x, int y, int z0, int z1, long long base,
+                                 VF V, F f) {
+  const long long plane = (long long)G.nx * G.ny;
+  long long i = base + x + (long long)G.nx * (y + (long long)G.ny * z0);
+  float vm = z0 > 0 ? V(x, y, z0 - 1, i - plane) : 0.f;
+  float vc = V(x, y, z0, i);
+  for (int z = z0; z < z1; ++z) {
+    const bool zr = z + 1 < G.nz;
+    const float vp = zr ? V(x, y, z + 1, i + plane) : 0.f;
+    float s = nb_sum_xy(G, x, y, z, i, V);
+    if (z > 0) s += G.gz(x, y, z - 1) * vm;
+    if (zr) s += G.gz(x, y, z) * vp;
+    f(z, i, vc, s);
+    vm = vc;
+    vc = vp;
+    i += plane;
+  }
+}
+
+struct TileXY {
+  int rep, x, y, z0, z1;
+  bool valid;
+};
+
+__device__ inline TileXY tile_xy(const Tile* tiles, const MgRep* reps) {
+  const Tile t = tiles[blockIdx.x];
+  const MgRep& m = reps[t.rep];
+  TileXY c;
+  c.rep = t.rep;
+  c.x = t.x0 + (int)(threadIdx.x % m.tx);
+  c.y = t.y0 + (int)(threadIdx.x / m.tx);
+  c.z0 = t.z0;
+  c.z1 = t.z1;
+  c.valid = c.x < m.nx && c.y < m.ny;
+  return c;
+}
+
+// ---- setup per solve -------------------------------------------------------
+
+// Level 0: Dinv = 1 / (c + a deg).
+__global__ void __launch_bounds__(kBlock) k_mg_prep0(MgLevel L0, float a,
+                                                     const double* __restrict__ c) {
+  const TileXY t = tile_xy(L0.tiles, L0.reps);
+  if (!t.valid) return;
+  const MgRep m = L0.reps[t.rep];
+  const Geo<true> G = geo_of<true>(m, a);
+  long long i = m.off + t.x + (long long)m.nx * (t.y + (long long)m.ny * t.z0);
+  const long long plane = (long long)m.nx * m.ny;
+  for (int z = t.z0; z < t.z1; ++z, i += plane)
+    L0.dinv[i] = (float)(1.0 / (c[i] + (double)G.gsum(t.x, t.y, z)));
+}
+
+// Level k+1 from level k: c_{k+1} = sum of the children's c, Dinv_{k+1}.
+template <bool FROM0>
+__global__ void __launch_bounds__(kBlock) k_mg_coarsen(MgLevel Lf, MgLevel Lc, float a,
+                                                       const double* __restrict__ c0) {
+  const TileXY t = tile_xy(Lc.rtiles, Lc.reps);
+  if (!t.valid) return;
+  const MgRep mc = Lc.reps[t.rep];
+  const MgRep mf = Lf.reps[t.rep];
+  const Geo<false> G = geo_of<false>(mc, a);
+  for (int Z = t.z0; Z < t.z1; ++Z) {
+    float s = 0.f;
+    for (int dz = 0; dz < 2; ++dz) {
+      const int z = 2 * Z + dz;
+      if (z >= mf.nz) break;
+      for (int dy = 0; dy < 2; ++dy) {
+        const int y = 2 * t.y + dy;
+        if (y >= mf.ny) break;
+        for (int dx = 0; dx < 2; ++dx) {
+          const int x = 2 * t.x + dx;
+          if (x >= mf.nx) break;
+          const long long j = mf.off + x + (long long)mf.nx * (y + (long long)mf.ny * z);
+          s += FROM0 ? (float)c0[j] : Lf.c[j];
+        }
+      }
+    }
+    const long long I = mc.off + t.x + (long long)mc.nx * (t.y + (long long)mc.ny * Z);
+    Lc.c[I] = s;
+    Lc.dinv[I] = 1.f / (s + G.gsum(t.x, t.y, Z));
+  }
+}
+
+// ---- V-cycle, global levels ------------------------------------------------
+
+template <bool L0, typename RT>
+__global__ void __launch_bounds__(kBlock) k_mg_pre(MgLevel Lk, float a, float omega,
+                                                   const RT* __restrict__ r, const SolveScal* ss) {
+  const TileXY t = tile_xy(Lk.tiles, Lk.reps);
+  if (ss[t.rep].done || !t.valid) return;
+  const MgRep m = Lk.reps[t.rep];
+  const Geo<L0> G = geo_of<L0>(m, a);
+  const float* __restrict__ dinv = Lk.dinv;
+  float* __restrict__ u = Lk.u;
+  auto U1 = [&](int, int, int, long long j) { return omega * dinv[j] * (float)r[j]; };
+  mg_column(G, t.x, t.y, t.z0, t.z1, m.off, U1, [&](int, long long i, float u1, float s) {
+    u[i] = (1.f - omega) * u1 + omega * dinv[i] * ((float)r[i] + s);
+  });
+}
+
+// residual of level k at (x, y, z): r - A u = r - u/Dinv + sum g u_J
+template <bool UNI, typename RT>
+__device__ inline float level_residual(const Geo<UNI>& G, long long off, int x, int y, int z,
+                                       const RT* __restrict__ r, const float* __restrict__ dinv,
+                                       const float* __restrict__ u) {
+  const long long plane = (long long)G.nx * G.ny;
+  const long long i = off + x + (long long)G.nx * (y + (long long)G.ny * z);
+  auto V = [&](int, int, int, long long j) { return u[j]; };
+  float s = nb_sum_xy(G, x, y, z, i, V);
+  if (z > 0) s += G.gz(x, y, z - 1) * u[i - plane];
+  if (z + 1 < G.nz) s += G.gz(x, y, z) * u[i + plane];
+  return (float)r[i] - u[i] / dinv[i] + s;
+}
+
+template <bool L0, typename RT>
+__global__ void __launch_bounds__(kBlock) k_mg_restrict(MgLevel Lf, MgLevel Lc, float a,
+                                                        const RT* __restrict__ r,
+                                                        const SolveScal* ss) {
+  const TileXY t = tile_xy(Lc.rtiles, Lc.reps);
+  if (ss[t.rep].done || !t.valid) return;
+  const MgRep mc = Lc.reps[t.rep];
+  const MgRep mf = Lf.reps[t.rep];
+  const Geo<L0> G = geo_of<L0>(mf, a);
+  for (int Z = t.z0; Z < t.z1; ++Z) {
+    float s = 0.f;
+    for (int dz = 0; dz < 2; ++dz) {
+      const int z = 2 * Z + dz;
+      if (z >= mf.nz) break;
+      for (int dy = 0; dy < 2; ++dy) {
+        const int y = 2 * t.y + dy;
+        if (y >= mf.ny) break;
+        for (int dx = 0; dx < 2; ++dx) {
+          const int x = 2 * t.x + dx;
+          if (x >= mf.nx) break;
+          s += level_residual(G, mf.off, x, y, z, r, Lf.dinv, Lf.u);
+        }
+      }
+    }
+    Lc.r[mc.off + t.x + (long long)mc.nx * (t.y + (long long)mc.ny * Z)] = s;
+  }
+}
+
+template <bool L0, typename RT>
+__global__ void __launch_bounds__(kBlock) k_mg_post1(MgLevel Lk, MgLevel Lc, float a, float omega,
+                                                     const RT* __restrict__ r, const SolveScal* ss) {
+  const TileXY t = tile_xy(Lk.tiles, Lk.reps);
+  if (ss[t.rep].done || !t.valid) return;
+  const MgRep m = Lk.reps[t.rep];
+  const MgRep mc = Lc.reps[t.rep];
+  const Geo<L0> G = geo_of<L0>(m, a);
+  const float* __restrict__ dinv = Lk.dinv;
+  const float* __restrict__ u = Lk.u;
+  const float* __restrict__ e = Lc.u;
+  float* __restrict__ out = Lk.ualt;
+  auto U3 = [&](int x, int y, int z, long long j) {
+    return u[j] + e[mc.off + (x >> 1) + (long long)mc.nx * ((y >> 1) + (long long)mc.ny * (z >> 1))];
+  };
+  mg_column(G, t.x, t.y, t.z0, t.z1, m.off, U3, [&](int, long long i, float u3, float s) {
+    out[i] = (1.f - omega) * u3 + omega * dinv[i] * ((float)r[i] + s);
+  });
+}
+
+template <bool L0, typename RT>
+__global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float a, float omega,
+                                                     const RT* __restrict__ r, SolverBufs sb) {
+  __shared__ double lds4[4];
+  const TileXY t = tile_xy(Lk.tiles, Lk.reps);
+  if (sb.ss[t.rep].done) return;
+  const MgRep m = Lk.reps[t.rep];
+  const Geo<L0> G = geo_of<L0>(m, a);
+  const float* __restrict__ dinv = Lk.dinv;
+  const float* __restrict__ u = Lk.ualt;
+  double rz = 0.0;
+  if (t.valid) {
+    auto U4 = [&](int, int, int, long long j) { return u[j]; };
+    mg_column(G, t.x, t.y, t.z0, t.z1, m.off, U4, [&](int, long long i, float u4, float s) {
+      const float u5 = (1.f - omega) * u4 + omega * dinv[i] * ((float)r[i] + s);
+      if (L0) {
+        sb.z[i] = (double)u5;
+        rz += (double)r[i] * (double)u5;
+      } else {
+        Lk.u[i] = u5;
+      }
+    });
+  }
+  if (!L0) return;
+  // level 0: r.z and the flexible-CG beta of this replicate
+  double v = block_sum(rz, lds4);
+  if (publish_and_check_last(sb.partial + (size_t)blockIdx.x * 3, &v, 1, sb.counter + t.rep,
+                             m.tile_nb)) {
+    const double trz = reduce_partials(sb.partial + (size_t)m.tile_b0 * 3, m.tile_nb, 3, 0, lds4);
+    if (threadIdx.x == 0) {
+      SolveScal& s = sb.ss[t.rep];
+      s.rzn = trz;
+      if (s.first) {
+        s.beta = 0.0;
+      } else {
+        s.beta = (trz - s.rzo) / s.rz;
+      }
+      s.rz = trz;
+    }
+  }
+}
+
+// ---- coarse levels: one workgroup per replicate, in LDS -----------------------
+
+struct CoarseLevel {
+  Geo<false> G;
+  int n;
+  float *u, *r, *dinv;
+};
+
+__device__ inline CoarseLevel coarse_level(const MgCoarseRep& cr, float* lds, int j, float a) {
+  CoarseLevel L;
+  L.G.nx = cr.dims[j][0];
+  L.G.ny = cr.dims[j][1];
+  L.G.nz = cr.dims[j][2];
+  L.G.k = cr.kc + j;
+  L.G.n0x = cr.n0[0];
+  L.G.n0y = cr.n0[1];
+  L.G.n0z = cr.n0[2];
+  L.G.a = a;
+  L.n = L.G.nx * L.G.ny * L.G.nz;
+  L.u = lds + cr.lds_off[j];
+  L.r = L.u + L.n;
+  L.dinv = L.r + L.n;
+  return L;
+}
+
+__device__ inline void coords(int t, int nx, int ny, int& x, int& y, int& z) {
+  x = t % nx;
+  const int q = t / nx;
+  y = q % ny;
+  z = q / ny;
+}
+
+__device__ inline float lds_nbsum(const CoarseLevel& L, const float* v, int t, int x, int y, int z) {
+  const Geo<false>& G = L.G;
+  const int plane = G.nx * G.ny;
+  float s = 0.f;
+  if (x > 0) s += G.gx(x - 1, y, z) * v[t - 1];
+  if (x + 1 < G.nx) s += G.gx(x, y, z) * v[t + 1];
+  if (y > 0) s += G.gy(x, y - 1, z) * v[t - G.nx];
+  if (y + 1 < G.ny) s += G.gy(x, y, z) * v[t + G.nx];
+  if (z > 0) s += G.gz(x, y, z - 1) * v[t - plane];
+  if (z + 1 < G.nz) s += G.gz(x, y, z) * v[t + plane];
+  return s;
+}
+
+__device__ inline void lds_jacobi(const CoarseLevel& L, float omega) {
+  float nv[kCoarseMaxCellsPerThread];
+#pragma unroll
+  for (int m = 0; m < kCoarseMaxCellsPerThread; ++m) {
+    const int t = threadIdx.x + m * kCoarseThreads;
+    if (t < L.n) {
+      int x, y, z;
+      coords(t, L.G.nx, L.G.ny, x, y, z);
+      nv[m] = (1.f - omega) * L.u[t] + omega * L.dinv[t] * (L.r[t] + lds_nbsum(L, L.u, t, x, y, z));
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < kCoarseMaxCellsPerThread; ++m) {
+    const int t = threadIdx.x + m * kCoarseThreads;
+    if (t < L.n) L.u[t] = nv[m];
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep* coarse, float a,
+                                                              float omega, const float* const* lev_c,
+                                                              const float* const* lev_r,
+                                                              float* const* lev_u,
+                                                              const SolveScal* ss) {
+  extern __shared__ float lds[];
+  const int rep = blockIdx.x;
+  if (ss[rep].done) return;
+  const MgCoarseRep& cr = coarse[rep];
+  const int J = cr.nlev;
+  // load level kc: r, and c (into the u slot)
+  {
+    const CoarseLevel L = coarse_level(cr, lds, 0, a);
+    const float* gc = lev_c[cr.kc] + cr.off_kc;
+    const float* gr = lev_r[cr.kc] + cr.off_kc;
+    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) {
+      L.u[t] = gc[t];
+      L.r[t] = gr[t];
+    }
+  }
+  __syncthreads();
+  // coarser c by summation, then Dinv on every level
+  for (int j = 1; j < J; ++j) {
+    const CoarseLevel F = coarse_level(cr, lds, j - 1, a);
+    const CoarseLevel C = coarse_level(cr, lds, j, a);
+    for (int t = threadIdx.x; t < C.n; t += kCoarseThreads) {
+      int X, Y, Z;
+      coords(t, C.G.nx, C.G.ny, X, Y, Z);
+      float s = 0.f;
+      for (int dz = 0; dz < 2 && 2 * Z + dz < F.G.nz; ++dz)
+        for (int dy = 0; dy < 2 && 2 * Y + dy < F.G.ny; ++dy)
+          for (int dx = 0; dx < 2 && 2 * X + dx < F.G.nx; ++dx)
+            s += F.u[(2 * X + dx) + F.G.nx * ((2 * Y + dy) + F.G.ny * (2 * Z + dz))];
+      C.u[t] = s;
+    }
+    __syncthreads();
+  }
+  for (int j = 0; j < J; ++j) {
+    const CoarseLevel L = coarse_level(cr, lds, j, a);
+    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) {
+      int x, y, z;
+      coords(t, L.G.nx, L.G.ny, x, y, z);
+      L.dinv[t] = 1.f / (L.u[t] + L.G.gsum(x, y, z));
+    }
+  }
+  __syncthreads();
+  // down
+  for (int j = 0; j + 1 < J; ++j) {
+    const CoarseLevel L = coarse_level(cr, lds, j, a);
+    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) L.u[t] = omega * L.dinv[t] * L.r[t];
+    __syncthreads();
+    lds_jacobi(L, omega);
+    const CoarseLevel C = coarse_level(cr, lds, j + 1, a);
+    for (int t = threadIdx.x; t < C.n; t += kCoarseThreads) {
+      int X, Y, Z;
+      coords(t, C.G.nx, C.G.ny, X, Y, Z);
+      float s = 0.f;
+      for (int dz = 0; dz < 2 && 2 * Z + dz < L.G.nz; ++dz)
+        for (int dy = 0; dy < 2 && 2 * Y + dy < L.G.ny; ++dy)
+          for (int dx = 0; dx < 2 && 2 * X + dx < L.G.nx; ++dx) {
+            const int x = 2 * X + dx, y = 2 * Y + dy, z = 2 * Z + dz;
+            const int f = x + L.G.nx * (y + L.G.ny * z);
+            s += L.r[f] - L.u[f] / L.dinv[f] + lds_nbsum(L, L.u, f, x, y, z);
+          }
+      C.r[t] = s;
+    }
+    __syncthreads();
+  }
+  // coarsest: one cell and no faces, so u = r / c exactly; larger: sweeps
+  {
+    const CoarseLevel L = coarse_level(cr, lds, J - 1, a);
+    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) L.u[t] = L.dinv[t] * L.r[t];
+    __syncthreads();
+    if (L.n > 1)
+      for (int it = 0; it < 30; ++it) lds_jacobi(L, omega);
+  }
+  // up
+  for (int j = J - 2; j >= 0; --j) {
+    const CoarseLevel L = coarse_level(cr, lds, j, a);
+    const CoarseLevel C = coarse_level(cr, lds, j + 1, a);
+    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) {
+      int x, y, z;
+      coords(t, L.G.nx, L.G.ny, x, y, z);
+      L.u[t] += C.u[(x >> 1) + C.G.nx * ((y >> 1) + C.G.ny * (z >> 1))];
+    }
+    __syncthreads();
+    lds_jacobi(L, omega);
+    lds_jacobi(L, omega);
+  }
+  {
+    const CoarseLevel L = coarse_level(cr, lds, 0, a);
+    float* gu = lev_u[cr.kc] + cr.off_kc;
+    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) gu[t] = L.u[t];
+  }
+}
+
+// ---- launchers -------------------------------------------------------------
+
+void launch_mg_prepare(hipStream_t s, const Work&, const MgBufs& mg, double a, const double* c) {
+  const float af = (float)a;
+  if (mg.lev[0].ntiles)
+    hipLaunchKernelGGL(k_mg_prep0, dim3(mg.lev[0].ntiles), dim3(kBlock), 0, s, mg.lev[0], af, c);
+  for (int k = 0; k < mg.nlev_glob; ++k) {
+    const MgLevel& Lc = mg.lev[k + 1];
+    if (!Lc.nrtiles) continue;
+    if (k == 0)
+      hipLaunchKernelGGL(k_mg_coarsen<true>, dim3(Lc.nrtiles), dim3(kBlock), 0, s, mg.lev[k], Lc, af,
+                         c);
+    else
+      hipLaunchKernelGGL(k_mg_coarsen<false>, dim3(Lc.nrtiles), dim3(kBlock), 0, s, mg.lev[k], Lc,
+                         af, c);
+  }
+}
+
+void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, double a,
+                      const SolverBufs& sb, MgHook hook, void* hctx) {
+  const float af = (float)a;
+  const float om = mg.omega;
+  const SolveScal* ss = sb.ss;
+  auto H = [&](int seg, int begin) {
+    if (hook) hook(hctx, seg, begin);
+  };
+  {
+    const MgLevel& L = mg.lev[0];
+    const MgLevel& C = mg.lev[1];
+    H(MG_PRE0, 1);
+    hipLaunchKernelGGL((k_mg_pre<true, double>), dim3(L.ntiles), dim3(kBlock), 0, s, L, af, om,
+                       (const double*)sb.r, ss);
+    H(MG_PRE0, 0);
+    H(MG_RESTRICT0, 1);
+    hipLaunchKernelGGL((k_mg_restrict<true, double>), dim3(C.nrtiles), dim3(kBlock), 0, s, L, C, af,
+                       (const double*)sb.r, ss);
+    H(MG_RESTRICT0, 0);
+  }
+  if (mg.nlev_glob > 1) {
+    H(MG_DOWN, 1);
+    for (int k = 1; k < mg.nlev_glob; ++k) {
+      const MgLevel& L = mg.lev[k];
+      const MgLevel& C = mg.lev[k + 1];
+      if (!L.ntiles) continue;
+      hipLaunchKernelGGL((k_mg_pre<false, float>), dim3(L.ntiles), dim3(kBlock), 0, s, L, af, om,
+                         (const float*)L.r, ss);
+      hipLaunchKernelGGL((k_mg_restrict<false, float>), dim3(C.nrtiles), dim3(kBlock), 0, s, L, C,
+                         af, (const float*)L.r, ss);
+    }
+    H(MG_DOWN, 0);
+  }
+  H(MG_COARSE, 1);
+  hipLaunchKernelGGL(k_mg_coarse, dim3(w.nreps), dim3(kCoarseThreads), mg.coarse_lds_bytes, s,
+                     mg.coarse, af, om, (const float* const*)mg.lev_c, (const float* const*)mg.lev_r,
+                     (float* const*)mg.lev_u, ss);
+  H(MG_COARSE, 0);
+  if (mg.nlev_glob > 1) {
+    H(MG_UP, 1);
+    for (int k = mg.nlev_glob - 1; k >= 1; --k) {
+      const MgLevel& L = mg.lev[k];
+      const MgLevel& C = mg.lev[k + 1];
+      if (!L.ntiles) continue;
+      hipLaunchKernelGGL((k_mg_post1<false, float>), dim3(L.ntiles), dim3(kBlock), 0, s, L, C, af,
+                         om, (const float*)L.r, ss);
+      hipLaunchKernelGGL((k_mg_post2<false, float>), dim3(L.ntiles), dim3(kBlock), 0, s, L, af, om,
+                         (const float*)L.r, sb);
+    }
+    H(MG_UP, 0);
+  }
+  {
+    const MgLevel& L = mg.lev[0];
+    const MgLevel& C = mg.lev[1];
+    H(MG_POST1_0, 1);
+    hipLaunchKernelGGL((k_mg_post1<true, double>), dim3(L.ntiles), dim3(kBlock), 0, s, L, C, af, om,
+                       (const double*)sb.r, ss);
+    H(MG_POST1_0, 0);
+    H(MG_POST2_0, 1);
+    hipLaunchKernelGGL((k_mg_post2<true, double>), dim3(L.ntiles), dim3(kBlock), 0, s, L, af, om,
+                       (const double*)sb.r, sb);
+    H(MG_POST2_0, 0);
+  }
+}
+
+}  // namespace hca

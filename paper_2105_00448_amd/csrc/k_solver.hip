@@ -94,12 +94,16 @@ __global__ void __launch_bounds__(kBlock) k_cg_start(Work w, double a, double rt
                    [&](long long i, int deg, double, double Ax) {
                      const double bi = b[i];
                      const double r = bi - Ax;
-                     const double zz = r / (c[i] + a * deg);
                      sb.r[i] = r;
-                     sb.z[i] = zz;
                      bb += bi * bi;
                      rr += r * r;
-                     rz += r * zz;
+                     if (sb.jacobi) {
+                       const double di = 1.0 / (c[i] + a * deg);
+                       const double zz = r * di;
+                       sb.dinv[i] = di;
+                       sb.z[i] = zz;
+                       rz += r * zz;
+                     }
                    });
   }
   double v[3];
@@ -171,10 +175,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, double a,
   }
 }
 
-// x += alpha p, r -= alpha q, Jacobi z' = r / diag(A); convergence check;
-// beta = (r.z' - r.z_old) / r.z.
-__global__ void __launch_bounds__(kBlock) k_cg_update(Work w, double a, double rtol, int maxit,
-                                                      const double* __restrict__ c,
+// x += alpha p, r -= alpha q; convergence check.  Jacobi mode also forms
+// z' = r / diag(A) and beta = (r.z' - r.z_old) / r.z; multigrid mode leaves z'
+// and beta to the V-cycle and only records r.z_old.
+__global__ void __launch_bounds__(kBlock) k_cg_update(Work w, double rtol, int maxit,
                                                       double* __restrict__ x,
                                                       const double* __restrict__ p,
                                                       const double* __restrict__ q,
@@ -185,30 +189,27 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(Work w, double a, double r
   if (ssr->done) return;
   const RepDev rp = w.reps[fb.rep];
   const double alpha = ssr->alpha;
+  const bool jac = sb.jacobi != 0;
   double rr = 0.0, rzo = 0.0, rzn = 0.0;
   const long long nchunks = (rp.n + kFlatChunk - 1) / kFlatChunk;
-  const long long plane = (long long)rp.nx * rp.ny;
   for (long long ch = fb.first; ch < nchunks; ch += rp.flat_nb) {
-    const long long base = ch * kFlatChunk;
+    const long long base = rp.off + ch * kFlatChunk;
+    const long long lim = rp.off + rp.n;
 #pragma unroll
     for (int k = 0; k < kFlatChunk / kBlock; ++k) {
-      const long long li = base + k * kBlock + threadIdx.x;
-      if (li < rp.n) {
-        const long long i = rp.off + li;
-        const int xx = (int)(li % rp.nx);
-        const int yy = (int)((li / rp.nx) % rp.ny);
-        const int zz = (int)(li / plane);
-        const int deg = (xx > 0) + (xx + 1 < rp.nx) + (yy > 0) + (yy + 1 < rp.ny) + (zz > 0) +
-                        (zz + 1 < rp.nz);
+      const long long i = base + k * kBlock + threadIdx.x;
+      if (i < lim) {
         x[i] += alpha * p[i];
         const double r = sb.r[i] - alpha * q[i];
         sb.r[i] = r;
         const double zold = sb.z[i];
-        const double znew = r / (c[i] + a * deg);
-        sb.z[i] = znew;
         rr += r * r;
         rzo += r * zold;
-        rzn += r * znew;
+        if (jac) {
+          const double znew = r * sb.dinv[i];
+          sb.z[i] = znew;
+          rzn += r * znew;
+        }
       }
     }
   }
@@ -226,11 +227,13 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(Work w, double a, double r
       SolveScal& s = sb.ss[fb.rep];
       s.rr = trr;
       s.rzo = trzo;
-      s.rzn = trzn;
       s.it += 1;
       s.first = 0;
-      s.beta = (trzn - trzo) / s.rz;
-      s.rz = trzn;
+      if (jac) {
+        s.rzn = trzn;
+        s.beta = (trzn - trzo) / s.rz;
+        s.rz = trzn;
+      }
       const bool conv = trr <= rtol * rtol * s.bb;
       s.conv = conv ? 1 : 0;
       if (conv || s.it >= maxit || !isfinite(trr)) {
@@ -257,10 +260,10 @@ void launch_cg_apply(hipStream_t s, const Work& w, double a, const double* c,
                      sb.q, sb);
 }
 
-void launch_cg_update(hipStream_t s, const Work& w, double a, double rtol, int maxit,
-                      const double* c, double* x, const SolverBufs& sb, int parity) {
+void launch_cg_update(hipStream_t s, const Work& w, double, double rtol, int maxit,
+                      const double*, double* x, const SolverBufs& sb, int parity) {
   const double* pnew = parity ? sb.p0 : sb.p1;
-  hipLaunchKernelGGL(k_cg_update, dim3(w.nflat), dim3(kBlock), 0, s, w, a, rtol, maxit, c, x, pnew,
+  hipLaunchKernelGGL(k_cg_update, dim3(w.nflat), dim3(kBlock), 0, s, w, rtol, maxit, x, pnew,
                      (const double*)sb.q, sb);
 }
 

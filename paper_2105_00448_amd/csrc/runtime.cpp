@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -18,26 +19,39 @@ namespace {
 
 enum KernelClass {
   KC_PLASMA = 0, KC_SETUP_O2, KC_SETUP_DRUG, KC_CG_START, KC_CG_APPLY, KC_CG_UPDATE, KC_ODE,
-  KC_CA_PROPOSE, KC_CA_RESOLVE, KC_CA_FINALIZE, KC_STATS, KC_COUNT
+  KC_CA_PROPOSE, KC_CA_RESOLVE, KC_CA_FINALIZE, KC_STATS,
+  KC_MG_PREP, KC_MG_PRE0, KC_MG_RESTRICT0, KC_MG_LEVELS, KC_MG_COARSE, KC_MG_POST1_0,
+  KC_MG_POST2_0, KC_COUNT
 };
 
 const char* kKernelNames[KC_COUNT] = {
     "k_plasma", "k_setup_o2", "k_setup_drug", "k_cg_start", "k_cg_apply", "k_cg_update",
-    "k_ode", "k_ca_propose", "k_ca_resolve", "k_ca_finalize", "k_stats"};
+    "k_ode", "k_ca_propose", "k_ca_resolve", "k_ca_finalize", "k_stats",
+    "k_mg_prep0+k_mg_coarsen", "k_mg_pre<L0>", "k_mg_restrict<L0>", "mg levels >= 1 (global)",
+    "k_mg_coarse", "k_mg_post1<L0>", "k_mg_post2<L0>"};
 
-// Compulsory (algorithmic) HBM bytes per voxel of each kernel class.
+// Compulsory (algorithmic) HBM bytes per fine voxel of each kernel class
+// (0: not priced, launch- or latency-bound).
 const double kBytesPerVoxel[KC_COUNT] = {
     0.0,          // plasma: per replicate only
     33.0,         // setup_o2: read L, w, K; write c, b
     32.0,         // setup_drug: read w, G; write c, b
-    40.0,         // cg_start: read x, c, b; write r, z
+    40.0,         // cg_start: read x, c, b; write r, (Jacobi: dinv, z)
     40.0,         // cg_apply: read z, p_old, c; write p_new, q
-    72.0,         // cg_update: read x, p, r, q, z, c; write x, r, z
+    72.0,         // cg_update, Jacobi: read x, p, r, q, z, dinv; write x, r, z
     57.0,         // ode: read L, K, P, Vc, phi; write P, Vc, phi
     10.0,         // ca_propose: read L, phi; write code
     11.0,         // ca_resolve: read L, w, code; write win
     2.0,          // ca_finalize: read code, win (writes only where cells change)
-    57.0};        // stats: read L, w and six fields
+    57.0,         // stats: read L, w and six fields
+    21.0,         // mg prepare: read c (8); write dinv0 (4); level 1: read c, write c1, dinv1
+    16.0,         // mg pre L0: read r (8), dinv (4); write u (4)
+    16.5,         // mg restrict L0: read u, r, dinv; write r1 (1/8 of 4)
+    0.0,          // coarser global levels
+    0.0,          // coarse workgroup levels
+    20.5,         // mg post1 L0: read u, e (1/8), r, dinv; write ualt
+    24.0};        // mg post2 L0: read ualt, r, dinv; write z (8)
+constexpr double kBytesUpdateMg = 56.0;   // cg_update, multigrid: read x, p, r, q, z; write x, r
 
 struct RepHost {
   int nx, ny, nz;
@@ -69,6 +83,9 @@ struct hca_ctx {
   double *w = nullptr, *K = nullptr, *G1 = nullptr, *G2 = nullptr, *P = nullptr, *Vc = nullptr,
          *phi = nullptr, *c = nullptr, *b = nullptr;
   SolverBufs sb{};
+  bool use_mg = false;
+  MgBufs mg{};
+  std::vector<void*> mg_mem;
   double *dose_t = nullptr, *dose_a = nullptr, *g0 = nullptr;
   long long* d_step = nullptr;
   RepDev* d_reps = nullptr;
@@ -173,7 +190,53 @@ void prof_flush(hca_ctx* c, int real_iters) {
   c->pending.clear();
 }
 
-double bytes_all(const hca_ctx* c, int kc) { return kBytesPerVoxel[kc] * (double)c->ntot; }
+double bytes_all(const hca_ctx* c, int kc) {
+  if (kc == KC_CG_UPDATE && c->use_mg) return kBytesUpdateMg * (double)c->ntot;
+  return kBytesPerVoxel[kc] * (double)c->ntot;
+}
+
+// Event pairs around the V-cycle's launch segments (profile mode).
+struct MgProf {
+  hca_ctx* c;
+  hipEvent_t start[8];
+  int iter;
+};
+
+int mg_segment_class(int seg) {
+  switch (seg) {
+    case MG_PRE0: return KC_MG_PRE0;
+    case MG_RESTRICT0: return KC_MG_RESTRICT0;
+    case MG_COARSE: return KC_MG_COARSE;
+    case MG_POST1_0: return KC_MG_POST1_0;
+    case MG_POST2_0: return KC_MG_POST2_0;
+    default: return KC_MG_LEVELS;
+  }
+}
+
+void mg_hook(void* p, int seg, int begin) {
+  MgProf* m = (MgProf*)p;
+  hca_ctx* c = m->c;
+  if (!c->prm.profile) return;
+  if (begin) {
+    m->start[seg] = take_event(c);
+    if (m->start[seg]) (void)hipEventRecord(m->start[seg], c->stream);
+    return;
+  }
+  if (!m->start[seg]) return;
+  hipEvent_t b = take_event(c);
+  if (!b) return;
+  (void)hipEventRecord(b, c->stream);
+  const int kc = mg_segment_class(seg);
+  c->pending.push_back(ProfEntry{kc, m->start[seg], b, m->iter, bytes_all(c, kc)});
+  m->start[seg] = nullptr;
+}
+
+void run_vcycle(hca_ctx* c, double a, int iter_tag) {
+  MgProf mp{};
+  mp.c = c;
+  mp.iter = iter_tag;
+  launch_mg_vcycle(c->stream, c->work, c->mg, a, c->sb, mg_hook, &mp);
+}
 
 DevParams make_dev_params(const hca_params& p) {
   DevParams d{};
@@ -217,10 +280,16 @@ int pick_tx(int nx) {
 // field and polls the per-replicate scalars between batches.
 hca_status solve(hca_ctx* c, int field, double a, double rtol, int maxit, double* x,
                  int* real_iters_out) {
+  if (c->use_mg) {
+    ProfScope ps(c, KC_MG_PREP, bytes_all(c, KC_MG_PREP));
+    launch_mg_prepare(c->stream, c->work, c->mg, a, c->c);
+  }
   {
     ProfScope ps(c, KC_CG_START, bytes_all(c, KC_CG_START));
     launch_cg_start(c->stream, c->work, a, rtol, maxit, c->c, c->b, x, c->sb);
   }
+  // the preconditioned start residual (no-op if the start already converged)
+  if (c->use_mg) run_vcycle(c, a, 0);
   int launched = 0;
   int batch = std::max(1, c->last_it[field] - 1);
   int real = 0;
@@ -235,6 +304,8 @@ hca_status solve(hca_ctx* c, int field, double a, double rtol, int maxit, double
         ProfScope ps(c, KC_CG_UPDATE, bytes_all(c, KC_CG_UPDATE), launched);
         launch_cg_update(c->stream, c->work, a, rtol, maxit, c->c, x, c->sb, launched & 1);
       }
+      // z = M r for the next direction; real only if this iteration did not converge
+      if (c->use_mg) run_vcycle(c, a, launched + 1);
     }
     HIPCHK(c, hipMemcpyAsync(c->h_ss, c->sb.ss, sizeof(SolveScal) * c->nreps,
                              hipMemcpyDeviceToHost, c->stream));
@@ -413,17 +484,44 @@ hca_status validate_params(const hca_params* p, std::string& msg) {
   return HCA_OK;
 }
 
+// z-extent of a column tile: enough tiles to fill the chip (about `target`
+// for this replicate), at most 16 planes per tile.
+int pick_tz(int nx, int ny, int nz, int tx, double target) {
+  const int ty = kBlock / tx;
+  const double nxy = (double)((nx + tx - 1) / tx) * (double)((ny + ty - 1) / ty);
+  const int tz = (int)std::floor(nz * nxy / std::max(1.0, target));
+  return std::max(1, std::min(16, tz));
+}
+
+void add_tiles(std::vector<Tile>& v, int rep, int nx, int ny, int nz, int tx, int tz) {
+  const int ty = kBlock / tx;
+  for (int z0 = 0; z0 < nz; z0 += tz)
+    for (int y0 = 0; y0 < ny; y0 += ty)
+      for (int x0 = 0; x0 < nx; x0 += tx) {
+        Tile t{};
+        t.rep = rep;
+        t.x0 = (short)x0;
+        t.y0 = (short)y0;
+        t.z0 = (short)z0;
+        t.z1 = (short)std::min(nz, z0 + tz);
+        v.push_back(t);
+      }
+}
+
+constexpr double kTileTarget = 1024.0;   // column tiles per launch on a lone replicate
+
 hca_status build_tables(hca_ctx* c) {
   std::vector<RepDev> rd(c->nreps);
   std::vector<FlatBlk> flat;
   std::vector<Tile> tiles;
-  const int tz = 16;
   for (int r = 0; r < c->nreps; ++r) {
     const RepHost& R = c->reps[r];
-    // tile shape per replicate, so a replicate's arithmetic (and rounding) is
-    // the same alone or in a batch
+    // tile shape per replicate (from its own size only), so a replicate's
+    // arithmetic and rounding are the same alone or in a batch
     const int tx = pick_tx(R.nx);
     const int ty = kBlock / tx;
+    const int tz = pick_tz(R.nx, R.ny, R.nz, tx, kTileTarget);
+    (void)ty;
     RepDev& d = rd[r];
     memset(&d, 0, sizeof d);
     d.nx = R.nx;
@@ -437,17 +535,7 @@ hca_status build_tables(hca_ctx* c) {
     d.flat_b0 = (int)flat.size();
     for (int k = 0; k < d.flat_nb; ++k) flat.push_back(FlatBlk{r, k});
     d.tile_b0 = (int)tiles.size();
-    for (int z0 = 0; z0 < R.nz; z0 += tz)
-      for (int y0 = 0; y0 < R.ny; y0 += ty)
-        for (int x0 = 0; x0 < R.nx; x0 += tx) {
-          Tile t{};
-          t.rep = r;
-          t.x0 = (short)x0;
-          t.y0 = (short)y0;
-          t.z0 = (short)z0;
-          t.z1 = (short)std::min(R.nz, z0 + tz);
-          tiles.push_back(t);
-        }
+    add_tiles(tiles, r, R.nx, R.ny, R.nz, tx, tz);
     d.tile_nb = (int)tiles.size() - d.tile_b0;
     d.dose_off = r * 2 * HCA_MAX_DOSES;
     d.tx = tx;
@@ -498,6 +586,161 @@ hca_status alloc_all(hca_ctx* c) {
   HIPCHK(c, hipMemcpy(c->d_fields, fl, sizeof fl, hipMemcpyHostToDevice));
   HIPCHK(c, hipHostMalloc((void**)&c->h_ss, sizeof(SolveScal) * c->nreps, hipHostMallocDefault));
   HIPCHK(c, hipHostMalloc((void**)&c->h_cnt, sizeof(Counters) * c->nreps, hipHostMallocDefault));
+  c->sb.jacobi = c->use_mg ? 0 : 1;
+  if (!c->use_mg) HIPCHK(c, dalloc(&c->sb.dinv, n));
+  return HCA_OK;
+}
+
+template <typename T>
+hca_status mg_alloc(hca_ctx* c, T** p, size_t count) {
+  hipError_t e = dalloc(p, count);
+  if (e == hipErrorOutOfMemory) return fail(c, HCA_E_NOMEM, "device memory exhausted (multigrid)");
+  HIPCHK(c, e);
+  c->mg_mem.push_back((void*)*p);
+  return HCA_OK;
+}
+
+template <typename T>
+hca_status mg_upload(hca_ctx* c, T** p, const std::vector<T>& v) {
+  hca_status st = mg_alloc(c, p, v.size());
+  if (st != HCA_OK) return st;
+  if (!v.empty()) HIPCHK(c, hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return HCA_OK;
+}
+
+// Multigrid hierarchy of every replicate: level dims (ceil halving down to one
+// cell, at least two levels), the first level handed to the one-workgroup
+// coarse solve (kc: <= mg_coarse_max cells and its LDS block fits in 64 KiB),
+// level arrays, per-level work tables and the coarse-solve descriptors.
+hca_status build_mg(hca_ctx* c) {
+  const int R = c->nreps;
+  constexpr size_t kLdsCap = 65536;
+  std::vector<std::vector<std::array<int, 3>>> dims(R);
+  std::vector<int> kc(R, 1);
+  int nglob = 1;
+  for (int r = 0; r < R; ++r) {
+    auto& d = dims[r];
+    d.push_back({c->reps[r].nx, c->reps[r].ny, c->reps[r].nz});
+    auto cells = [](const std::array<int, 3>& a) { return (long long)a[0] * a[1] * a[2]; };
+    while (cells(d.back()) > 1 || d.size() < 2) {
+      const auto& b = d.back();
+      d.push_back({(b[0] + 1) / 2, (b[1] + 1) / 2, (b[2] + 1) / 2});
+      if ((int)d.size() > kMaxLevels) return fail(c, HCA_E_INVALID, "lattice too large for multigrid");
+    }
+    for (int k = 1; k < (int)d.size(); ++k) {
+      size_t lds = 0;
+      for (int j = k; j < (int)d.size(); ++j) lds += 3 * sizeof(float) * (size_t)cells(d[j]);
+      const long long n = cells(d[k]);
+      if (n <= c->prm.mg_coarse_max && n <= (long long)kCoarseThreads * kCoarseMaxCellsPerThread &&
+          lds <= kLdsCap) {
+        kc[r] = k;
+        break;
+      }
+    }
+    nglob = std::max(nglob, kc[r]);
+  }
+  MgBufs& mg = c->mg;
+  mg.nlev_glob = nglob;
+  mg.omega = 0.8f;
+  // level 0 shares the CG's tiles and replicate offsets
+  std::vector<float*> pc(kMaxLevels, nullptr), pr(kMaxLevels, nullptr), pu(kMaxLevels, nullptr);
+  std::vector<RepDev> rd(R);
+  HIPCHK(c, hipMemcpy(rd.data(), c->d_reps, sizeof(RepDev) * R, hipMemcpyDeviceToHost));
+  for (int k = 0; k <= nglob; ++k) {
+    std::vector<MgRep> mr(R);
+    std::vector<Tile> tiles, rtiles;
+    long long off = 0;
+    for (int r = 0; r < R; ++r) {
+      MgRep& m = mr[r];
+      memset(&m, 0, sizeof m);
+      m.k = k;
+      m.n0x = dims[r][0][0];
+      m.n0y = dims[r][0][1];
+      m.n0z = dims[r][0][2];
+      if (k >= (int)dims[r].size() || k > kc[r]) continue;
+      m.nx = dims[r][k][0];
+      m.ny = dims[r][k][1];
+      m.nz = dims[r][k][2];
+      m.active = k < kc[r];
+      m.tx = k == 0 ? rd[r].tx : pick_tx(m.nx);
+      if (k == 0) {
+        m.off = c->reps[r].off;
+        m.tile_b0 = rd[r].tile_b0;
+        m.tile_nb = rd[r].tile_nb;
+        continue;
+      }
+      m.off = off;
+      off += (long long)m.nx * m.ny * m.nz;
+      const int tz = pick_tz(m.nx, m.ny, m.nz, m.tx, kTileTarget);
+      if (m.active) {
+        m.tile_b0 = (int)tiles.size();
+        add_tiles(tiles, r, m.nx, m.ny, m.nz, m.tx, tz);
+        m.tile_nb = (int)tiles.size() - m.tile_b0;
+      }
+      m.rtile_b0 = (int)rtiles.size();
+      add_tiles(rtiles, r, m.nx, m.ny, m.nz, m.tx, tz);
+      m.rtile_nb = (int)rtiles.size() - m.rtile_b0;
+    }
+    MgLevel& L = mg.lev[k];
+    MgRep* d_mr = nullptr;
+    hca_status st = mg_upload(c, &d_mr, mr);
+    if (st != HCA_OK) return st;
+    L.reps = d_mr;
+    if (k == 0) {
+      L.tiles = c->d_tiles;
+      L.ntiles = c->work.ntiles;
+      const size_t n = (size_t)c->ntot;
+      if ((st = mg_alloc(c, &L.dinv, n)) != HCA_OK || (st = mg_alloc(c, &L.u, n)) != HCA_OK ||
+          (st = mg_alloc(c, &L.ualt, n)) != HCA_OK)
+        return st;
+    } else {
+      Tile* dt = nullptr;
+      Tile* drt = nullptr;
+      if ((st = mg_upload(c, &dt, tiles)) != HCA_OK || (st = mg_upload(c, &drt, rtiles)) != HCA_OK)
+        return st;
+      L.tiles = dt;
+      L.ntiles = (int)tiles.size();
+      L.rtiles = drt;
+      L.nrtiles = (int)rtiles.size();
+      const size_t n = (size_t)std::max<long long>(off, 1);
+      if ((st = mg_alloc(c, &L.c, n)) != HCA_OK || (st = mg_alloc(c, &L.dinv, n)) != HCA_OK ||
+          (st = mg_alloc(c, &L.r, n)) != HCA_OK || (st = mg_alloc(c, &L.u, n)) != HCA_OK ||
+          (st = mg_alloc(c, &L.ualt, n)) != HCA_OK)
+        return st;
+      pc[k] = L.c;
+      pr[k] = L.r;
+      pu[k] = L.u;
+    }
+  }
+  // coarse-solve descriptors
+  std::vector<MgCoarseRep> cr(R);
+  size_t lds_max = 0;
+  for (int r = 0; r < R; ++r) {
+    MgCoarseRep& d = cr[r];
+    memset(&d, 0, sizeof d);
+    d.kc = kc[r];
+    d.nlev = (int)dims[r].size() - kc[r];
+    for (int i = 0; i < 3; ++i) d.n0[i] = dims[r][0][i];
+    int o = 0;
+    for (int j = 0; j < d.nlev; ++j) {
+      for (int i = 0; i < 3; ++i) d.dims[j][i] = dims[r][kc[r] + j][i];
+      d.lds_off[j] = o;
+      o += 3 * d.dims[j][0] * d.dims[j][1] * d.dims[j][2];
+    }
+    lds_max = std::max(lds_max, (size_t)o * sizeof(float));
+    std::vector<MgRep> mr(R);
+    HIPCHK(c, hipMemcpy(mr.data(), mg.lev[kc[r]].reps, sizeof(MgRep) * R, hipMemcpyDeviceToHost));
+    d.off_kc = mr[r].off;
+  }
+  MgCoarseRep* dcr = nullptr;
+  hca_status st = mg_upload(c, &dcr, cr);
+  if (st != HCA_OK) return st;
+  mg.coarse = dcr;
+  mg.coarse_lds_bytes = (int)lds_max;
+  std::vector<float*> vc(pc), vr(pr), vu(pu);
+  if ((st = mg_upload(c, &mg.lev_c, vc)) != HCA_OK || (st = mg_upload(c, &mg.lev_r, vr)) != HCA_OK ||
+      (st = mg_upload(c, &mg.lev_u, vu)) != HCA_OK)
+    return st;
   return HCA_OK;
 }
 
@@ -533,9 +776,13 @@ void free_all(hca_ctx* c) {
   void* bufs[] = {c->L, c->code, c->win, c->w, c->K, c->G1, c->G2, c->P, c->Vc, c->phi, c->c,
                   c->b, c->sb.r, c->sb.z, c->sb.p0, c->sb.p1, c->sb.q, c->sb.partial,
                   c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->d_step,
-                  c->d_reps, c->d_flat, c->d_tiles, c->d_cnt, (void*)c->d_fields, c->d_bad};
+                  c->d_reps, c->d_flat, c->d_tiles, c->d_cnt, (void*)c->d_fields, c->d_bad,
+                  c->sb.dinv};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
+  for (void* p : c->mg_mem)
+    if (p) (void)hipFree(p);
+  c->mg_mem.clear();
   if (c->h_ss) (void)hipHostFree(c->h_ss);
   if (c->h_cnt) (void)hipHostFree(c->h_cnt);
   for (auto& e : c->pending) {
@@ -595,7 +842,7 @@ hca_status hca_default_params(hca_params* out) {
   out->K_phi = 1.4;
   out->T_cycle = 3.74 * 1440.0;
   out->ode_substeps = 30;
-  out->precond = 0;
+  out->precond = 1;
   out->cg_rtol = 1.0e-10;
   out->cg_maxit = 2000;
   out->mg_smooth = 2;
@@ -628,6 +875,7 @@ hca_status hca_init(hca_ctx** out, const hca_params* p, const hca_replicate* rep
   c->prm = *p;
   c->dp = make_dev_params(*p);
   c->nreps = n_reps;
+  c->use_mg = p->precond == 1;
   long long off = 0;
   for (int r = 0; r < n_reps; ++r) {
     RepHost R{};
@@ -659,6 +907,7 @@ hca_status hca_init(hca_ctx** out, const hca_params* p, const hca_replicate* rep
   }
   if ((st = build_tables(c)) != HCA_OK) return bail(st);
   if ((st = alloc_all(c)) != HCA_OK) return bail(st);
+  if (c->use_mg && (st = build_mg(c)) != HCA_OK) return bail(st);
   // upload inputs and dose tables
   std::vector<double> dt((size_t)n_reps * 2 * HCA_MAX_DOSES, 0.0), da(dt.size(), 0.0);
   std::vector<RepDev> rd(n_reps);

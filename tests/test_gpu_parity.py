@@ -67,14 +67,18 @@ def test_init_matches_oracle(case32):
         assert st["n_vessel"] == np.count_nonzero(tis.w > 0)
 
 
-def test_solves_match_oracle_exact_solution(case32):
+PRECONDS = pytest.mark.parametrize("precond", [0, 1], ids=["jacobi", "multigrid"])
+
+
+@PRECONDS
+def test_solves_match_oracle_exact_solution(case32, precond):
     tis, sched, s0 = case32
     osched = oracle_sched(sched)
     # a state with drug already in the tissue: two oracle steps from init
     s = s0
     for _ in range(2):
         s, _ = om.step(s, tis.w, osched, tis.seed, OP)
-    with make_sim([(tis, sched)]) as sim:
+    with make_sim([(tis, sched)], precond=precond) as sim:
         push_state(sim, s)
         sim.run_phases(hca.PH_O2 | hca.PH_DRUGS)
         K, G1, G2 = om.solve_fields(s, tis.w, osched, OP)
@@ -134,15 +138,16 @@ def test_ca_bit_exact_on_shared_fields(case32, seed):
         assert ev["divisions"] > 10 and ev["lost"] > 0 and ev["kills"] > 10
 
 
-def test_trajectory_20_steps_resynchronised(case32):
-    """Config-1 trajectory: each step's solves and ODE vs the oracle at the
+@PRECONDS
+def test_trajectory_20_steps_resynchronised(case32, precond):
+    """32^3 trajectory: each step's solves and ODE vs the oracle at the
     field tolerance, the CA bit-exact on the shared fields; the GPU restarts
     every step from the oracle's state."""
     tis, sched, s0 = case32
     osched = oracle_sched(sched)
     s = s0
     total_div = total_kill = 0
-    with make_sim([(tis, sched)]) as sim:
+    with make_sim([(tis, sched)], precond=precond) as sim:
         for n in range(20):
             push_state(sim, s)
             sim.run_phases(hca.PH_O2 | hca.PH_DRUGS)
@@ -170,9 +175,11 @@ def test_trajectory_20_steps_resynchronised(case32):
     assert total_div > 0 and total_kill > 0
 
 
-@pytest.mark.parametrize("shape", [(9, 23, 17), (1, 40, 33), (70, 5, 5), (2, 2, 130)])
-def test_ragged_lattices(shape):
-    print(f"\n[ragged] shape {shape}", flush=True)
+@PRECONDS
+@pytest.mark.parametrize("shape", [(9, 23, 17), (1, 40, 33), (70, 5, 5), (2, 2, 130), (1, 1, 1),
+                                   (3, 1, 2)])
+def test_ragged_lattices(shape, precond):
+    print(f"\n[ragged] shape {shape} precond {precond}", flush=True)
     tis = synth.make_tissue(shape, 4, seed=sum(shape))
     if not (tis.w > 0).any():
         tis.w.ravel()[0] = 1.0
@@ -180,7 +187,7 @@ def test_ragged_lattices(shape):
     sched = synth.bolus_schedule([0, 2])
     osched = oracle_sched(sched)
     s = om.init_state(tis.cell, tis.w, tis.seed, OP)
-    with make_sim([(tis, sched)]) as sim:
+    with make_sim([(tis, sched)], precond=precond) as sim:
         assert relerr(sim.field("K"), s.K) <= FIELD_TOL
         for n in range(4):
             push_state(sim, s)
@@ -200,16 +207,19 @@ def test_ragged_lattices(shape):
             s = s2
 
 
-def test_batched_replicates_equal_single_runs():
-    specs = [((20, 24, 28), 11, [0]), ((17, 17, 17), 12, [1]), ((8, 40, 31), 13, [])]
+@PRECONDS
+def test_batched_replicates_equal_single_runs(precond):
+    specs = [((20, 24, 28), 11, [0]), ((17, 17, 17), 12, [1]), ((8, 40, 31), 13, []),
+             ((1, 33, 35), 14, [0])]
     cases = []
     for shape, seed, days in specs:
         t = synth.make_tissue(shape, 4, seed=seed)
         cases.append((t, synth.bolus_schedule(days)))
-    with make_sim(cases, cg_rtol=1e-10, init_rtol=1e-10) as batch:
+    kw = dict(cg_rtol=1e-10, init_rtol=1e-10, precond=precond)
+    with make_sim(cases, **kw) as batch:
         batch.step(4)
         for r, case in enumerate(cases):
-            with make_sim([case], cg_rtol=1e-10, init_rtol=1e-10) as single:
+            with make_sim([case], **kw) as single:
                 single.step(4)
                 for name in ("L", "K", "G1", "G2", "P", "Vc", "phi"):
                     assert np.array_equal(batch.field(name, r), single.field(name)), (r, name)
