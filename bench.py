@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="plain128")
     ap.add_argument("--precond", type=int, default=1, help="0 Jacobi, 1 multigrid")
+    ap.add_argument("--mg-coarse-max", type=int, default=None,
+                    help="levels with at most this many cells go to the one-workgroup solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     args = ap.parse_args()
@@ -117,18 +119,21 @@ def main():
 
     print(f"[bench] generating workload {args.workload}", file=sys.stderr, flush=True)
     reps, cfg, cfg_steps = make_workload(args.workload)
+    solver_kw = {"precond": args.precond}
+    if args.mg_coarse_max is not None:
+        solver_kw["mg_coarse_max"] = args.mg_coarse_max
     steps = args.steps if args.steps is not None else cfg_steps
     nvox = sum(r[0].size for r in reps)
 
     # warm-up on a throwaway context (code loading, clocks), then the timed
     # run from step 0 of the workload
     if args.warmup > 0:
-        p = hca.default_params(precond=args.precond)
+        p = hca.default_params(**solver_kw)
         with hca.Simulation(reps, p, stream=stream) as sim:
             sim.step(args.warmup)
         print(f"[bench] warm-up {args.warmup} steps done", file=sys.stderr, flush=True)
 
-    p = hca.default_params(precond=args.precond, profile=0 if args.no_profile else 1)
+    p = hca.default_params(profile=0 if args.no_profile else 1, **solver_kw)
     t_init = time.perf_counter()
     sim = hca.Simulation(reps, p, stream=stream)
     t_init = time.perf_counter() - t_init
@@ -160,7 +165,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": dict(cfg, precond="jacobi" if args.precond == 0 else "multigrid"),
+        "config": dict(cfg, precond="jacobi" if args.precond == 0 else "multigrid",
+                       mg_coarse_max=p.mg_coarse_max),
     }
     if not args.no_profile:
         real = {k: v for k, v in kt.items() if v["launches"] > 0 and v["bytes_per_launch"] > 0}

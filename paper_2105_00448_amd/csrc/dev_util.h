@@ -43,36 +43,15 @@ __device__ inline double block_max(double v, double* lds4) {
   return t;
 }
 
-// Publish this workgroup's partial sums and report whether it is the last
-// workgroup of its replicate to do so.  The last one may then read every
-// partial of the replicate (reads go through acquire_load below).
-__device__ inline bool publish_and_check_last(double* slot, const double* vals, int nvals,
-                                              unsigned* counter, int nblocks) {
-  __shared__ int am_last;
+// A workgroup's three partial sums, stored at its work-item slot (3 doubles);
+// a later reduce kernel (one workgroup per replicate) sums the slots of a
+// replicate in a fixed order.  The kernel boundary orders the two.
+__device__ inline void store_partials(double* slot, double a, double b, double c) {
   if (threadIdx.x == 0) {
-    for (int k = 0; k < nvals; ++k)
-      __hip_atomic_store(slot + k, vals[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __atomic_thread_fence(__ATOMIC_RELEASE);   // (agent scope by default on device)
-    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-    am_last = (prev == (unsigned)(nblocks - 1));
-    if (am_last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    slot[0] = a;
+    slot[1] = b;
+    slot[2] = c;
   }
-  __syncthreads();
-  return am_last != 0;
-}
-
-__device__ inline double acquire_load(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Sum of nvals-strided partials [0, nb) of component k, fixed order:
-// thread t sums t, t+256, ... then block_sum.
-__device__ inline double reduce_partials(const double* base, int nb, int nvals, int k,
-                                         double* lds4) {
-  double s = 0.0;
-  for (int j = threadIdx.x; j < nb; j += kBlock) s += acquire_load(base + (size_t)j * nvals + k);
-  return block_sum(s, lds4);
 }
 
 // ---- Philox4x64-10 (Salmon et al., SC'11) ----------------------------------

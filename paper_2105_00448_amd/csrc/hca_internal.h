@@ -34,7 +34,9 @@ struct DevParams {
   int nsub;
 };
 
-// One replicate on the device.
+// One replicate on the device, or (in the solver's tables) one linear system:
+// system s = field * nreps + rep, field 0 oxygen, 1 and 2 the drugs, its
+// unknowns at [off, off + n) of the 3 x total-voxel solver arrays.
 struct RepDev {
   int nx, ny, nz, pad0;
   long long off;              // first voxel in the concatenated arrays
@@ -45,6 +47,7 @@ struct RepDev {
   int ndose[2];
   int dose_off;               // into the dose arrays (2*HCA_MAX_DOSES per rep)
   int tx;                     // stencil tile width (tile = tx x (kBlock/tx) columns)
+  double a;                   // systems: face coupling D/h^2 of the field
 };
 
 // Work item of the flat kernels: replicate and first chunk index.
@@ -99,6 +102,11 @@ void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uin
                      const double* vw, const double* K, double* c, double* b, int steady);
 void launch_setup_drug(hipStream_t s, const Work& w, const DevParams& p, int drug,
                        const double* vw, const double* G, const double* g0, double* c, double* b);
+// All three systems of a coupled step at once: F = [K | G1 | G2] (3 x ntot),
+// c and b of the same layout.
+void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
+                       const uint8_t* L, const double* vw, const double* F, const double* g0,
+                       double* c, double* b);
 void launch_init_cells(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
                        const double* K, double* P, double* Vc, double* phi);
 
@@ -112,14 +120,22 @@ struct SolverBufs {
   SolveScal* ss;              // per replicate
   int* ndone;                 // replicates finished
 };
-void launch_cg_start(hipStream_t s, const Work& w, double a, double rtol, int maxit,
-                     const double* c, const double* b, const double* x, const SolverBufs& sb);
+// Systems whose field (s / nrep) is not in field_mask are marked finished.
+void launch_cg_start(hipStream_t s, const Work& w, double rtol, int maxit, const double* c,
+                     const double* b, const double* x, const SolverBufs& sb, unsigned field_mask,
+                     int nrep);
+// Reduce kernels (one workgroup per replicate) that follow the kernels
+// producing partial sums: start (b.b, r.r, r.z), apply (p.q), update
+// (r.r, r.z_old, r.z'), and the preconditioner's r.z'.
+enum ReduceKind { RED_START = 0, RED_APPLY = 1, RED_UPDATE = 2, RED_RZ = 3 };
+void launch_cg_reduce(hipStream_t s, const Work& w, const SolverBufs& sb, int kind, double rtol,
+                      int maxit, unsigned field_mask = 7u, int nrep = 1);
 // One iteration is launch_cg_apply then launch_cg_update with the same
 // parity (the direction p alternates between p0 and p1).
-void launch_cg_apply(hipStream_t s, const Work& w, double a, const double* c,
+void launch_cg_apply(hipStream_t s, const Work& w, const double* c,
                      const SolverBufs& sb, int parity);
-void launch_cg_update(hipStream_t s, const Work& w, double a, double rtol, int maxit,
-                      const double* c, double* x, const SolverBufs& sb, int parity);
+void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, double* x,
+                      const SolverBufs& sb, int parity);
 
 // ---- geometric multigrid (k_mg.hip) ---------------------------------------
 constexpr int kMaxLevels = 16;
@@ -136,7 +152,8 @@ struct MgRep {
   long long off;            // first cell of this replicate in the level arrays
   int tile_b0, tile_nb;     // smoothing tiles (active levels)
   int rtile_b0, rtile_nb;   // tiles of the cells this level receives by restriction
-  int tx, pad;
+  int tx;
+  float a;                  // face coupling D/h^2 of the system's field
 };
 
 struct MgLevel {
@@ -156,6 +173,7 @@ struct MgCoarseRep {
   int dims[kMaxLevels][3];
   int lds_off[kMaxLevels];  // float offset of each level's (u, r, dinv) block
   long long off_kc;         // replicate offset in the level-kc arrays
+  float a;
 };
 
 struct MgBufs {
@@ -169,15 +187,15 @@ struct MgBufs {
   float** lev_u;
 };
 
-void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, double a, const double* c);
+void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, const double* c);
 // One V-cycle on the residual sb.r, result in sb.z; finishes the flexible-CG
-// scalars (r.z, beta) with the same last-workgroup reduction as the CG kernels.
+// scalars (r.z, beta) with a RED_RZ reduce.
 // `hook(ctx, segment, begin)` brackets the launches of each segment (for
 // kernel timing); segments: see MgSegment.
 enum MgSegment { MG_PRE0 = 0, MG_RESTRICT0, MG_DOWN, MG_COARSE, MG_UP, MG_POST1_0, MG_POST2_0 };
 typedef void (*MgHook)(void* ctx, int segment, int begin);
-void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, double a,
-                      const SolverBufs& sb, MgHook hook, void* hook_ctx);
+void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const SolverBufs& sb,
+                      MgHook hook, void* hook_ctx);
 
 // ODE (k_ode.hip)
 void launch_ode(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,

@@ -65,7 +65,8 @@ struct Geo {
 };
 
 template <bool UNI>
-__device__ inline Geo<UNI> geo_of(const MgRep& m, float a) {
+__device__ inline Geo<UNI> geo_of(const MgRep& m) {
+  const float a = m.a;
   Geo<UNI> g;
   g.nx = m.nx;
   g.ny = m.ny;
@@ -132,12 +133,11 @@ __device__ inline TileXY tile_xy(const Tile* tiles, const MgRep* reps) {
 // ---- setup per solve -------------------------------------------------------
 
 // Level 0: Dinv = 1 / (c + a deg).
-__global__ void __launch_bounds__(kBlock) k_mg_prep0(MgLevel L0, float a,
-                                                     const double* __restrict__ c) {
+__global__ void __launch_bounds__(kBlock) k_mg_prep0(MgLevel L0, const double* __restrict__ c) {
   const TileXY t = tile_xy(L0.tiles, L0.reps);
   if (!t.valid) return;
   const MgRep m = L0.reps[t.rep];
-  const Geo<true> G = geo_of<true>(m, a);
+  const Geo<true> G = geo_of<true>(m);
   long long i = m.off + t.x + (long long)m.nx * (t.y + (long long)m.ny * t.z0);
   const long long plane = (long long)m.nx * m.ny;
   for (int z = t.z0; z < t.z1; ++z, i += plane)
@@ -146,13 +146,13 @@ __global__ void __launch_bounds__(kBlock) k_mg_prep0(MgLevel L0, float a,
 
 // Level k+1 from level k: c_{k+1} = sum of the children's c, Dinv_{k+1}.
 template <bool FROM0>
-__global__ void __launch_bounds__(kBlock) k_mg_coarsen(MgLevel Lf, MgLevel Lc, float a,
+__global__ void __launch_bounds__(kBlock) k_mg_coarsen(MgLevel Lf, MgLevel Lc,
                                                        const double* __restrict__ c0) {
   const TileXY t = tile_xy(Lc.rtiles, Lc.reps);
   if (!t.valid) return;
   const MgRep mc = Lc.reps[t.rep];
   const MgRep mf = Lf.reps[t.rep];
-  const Geo<false> G = geo_of<false>(mc, a);
+  const Geo<false> G = geo_of<false>(mc);
   for (int Z = t.z0; Z < t.z1; ++Z) {
     float s = 0.f;
     for (int dz = 0; dz < 2; ++dz) {
@@ -178,12 +178,12 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarsen(MgLevel Lf, MgLevel Lc, f
 // ---- V-cycle, global levels ------------------------------------------------
 
 template <bool L0, typename RT>
-__global__ void __launch_bounds__(kBlock) k_mg_pre(MgLevel Lk, float a, float omega,
+__global__ void __launch_bounds__(kBlock) k_mg_pre(MgLevel Lk, float omega,
                                                    const RT* __restrict__ r, const SolveScal* ss) {
   const TileXY t = tile_xy(Lk.tiles, Lk.reps);
   if (ss[t.rep].done || !t.valid) return;
   const MgRep m = Lk.reps[t.rep];
-  const Geo<L0> G = geo_of<L0>(m, a);
+  const Geo<L0> G = geo_of<L0>(m);
   const float* __restrict__ dinv = Lk.dinv;
   float* __restrict__ u = Lk.u;
   auto U1 = [&](int, int, int, long long j) { return omega * dinv[j] * (float)r[j]; };
@@ -207,14 +207,14 @@ __device__ inline float level_residual(const Geo<UNI>& G, long long off, int x, 
 }
 
 template <bool L0, typename RT>
-__global__ void __launch_bounds__(kBlock) k_mg_restrict(MgLevel Lf, MgLevel Lc, float a,
+__global__ void __launch_bounds__(kBlock) k_mg_restrict(MgLevel Lf, MgLevel Lc,
                                                         const RT* __restrict__ r,
                                                         const SolveScal* ss) {
   const TileXY t = tile_xy(Lc.rtiles, Lc.reps);
   if (ss[t.rep].done || !t.valid) return;
   const MgRep mc = Lc.reps[t.rep];
   const MgRep mf = Lf.reps[t.rep];
-  const Geo<L0> G = geo_of<L0>(mf, a);
+  const Geo<L0> G = geo_of<L0>(mf);
   for (int Z = t.z0; Z < t.z1; ++Z) {
     float s = 0.f;
     for (int dz = 0; dz < 2; ++dz) {
@@ -235,13 +235,13 @@ __global__ void __launch_bounds__(kBlock) k_mg_restrict(MgLevel Lf, MgLevel Lc, 
 }
 
 template <bool L0, typename RT>
-__global__ void __launch_bounds__(kBlock) k_mg_post1(MgLevel Lk, MgLevel Lc, float a, float omega,
+__global__ void __launch_bounds__(kBlock) k_mg_post1(MgLevel Lk, MgLevel Lc, float omega,
                                                      const RT* __restrict__ r, const SolveScal* ss) {
   const TileXY t = tile_xy(Lk.tiles, Lk.reps);
   if (ss[t.rep].done || !t.valid) return;
   const MgRep m = Lk.reps[t.rep];
   const MgRep mc = Lc.reps[t.rep];
-  const Geo<L0> G = geo_of<L0>(m, a);
+  const Geo<L0> G = geo_of<L0>(m);
   const float* __restrict__ dinv = Lk.dinv;
   const float* __restrict__ u = Lk.u;
   const float* __restrict__ e = Lc.u;
@@ -255,13 +255,13 @@ __global__ void __launch_bounds__(kBlock) k_mg_post1(MgLevel Lk, MgLevel Lc, flo
 }
 
 template <bool L0, typename RT>
-__global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float a, float omega,
+__global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float omega,
                                                      const RT* __restrict__ r, SolverBufs sb) {
   __shared__ double lds4[4];
   const TileXY t = tile_xy(Lk.tiles, Lk.reps);
   if (sb.ss[t.rep].done) return;
   const MgRep m = Lk.reps[t.rep];
-  const Geo<L0> G = geo_of<L0>(m, a);
+  const Geo<L0> G = geo_of<L0>(m);
   const float* __restrict__ dinv = Lk.dinv;
   const float* __restrict__ u = Lk.ualt;
   double rz = 0.0;
@@ -278,22 +278,9 @@ __global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float a, float 
     });
   }
   if (!L0) return;
-  // level 0: r.z and the flexible-CG beta of this replicate
-  double v = block_sum(rz, lds4);
-  if (publish_and_check_last(sb.partial + (size_t)blockIdx.x * 3, &v, 1, sb.counter + t.rep,
-                             m.tile_nb)) {
-    const double trz = reduce_partials(sb.partial + (size_t)m.tile_b0 * 3, m.tile_nb, 3, 0, lds4);
-    if (threadIdx.x == 0) {
-      SolveScal& s = sb.ss[t.rep];
-      s.rzn = trz;
-      if (s.first) {
-        s.beta = 0.0;
-      } else {
-        s.beta = (trz - s.rzo) / s.rz;
-      }
-      s.rz = trz;
-    }
-  }
+  // level 0: partial r.z of this workgroup (finished by the RED_RZ reduce)
+  rz = block_sum(rz, lds4);
+  store_partials(sb.partial + (size_t)blockIdx.x * 3, rz, 0.0, 0.0);
 }
 
 // ---- coarse levels: one workgroup per replicate, in LDS -----------------------
@@ -361,7 +348,7 @@ __device__ inline void lds_jacobi(const CoarseLevel& L, float omega) {
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep* coarse, float a,
+__global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep* coarse,
                                                               float omega, const float* const* lev_c,
                                                               const float* const* lev_r,
                                                               float* const* lev_u,
@@ -370,6 +357,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep*
   const int rep = blockIdx.x;
   if (ss[rep].done) return;
   const MgCoarseRep& cr = coarse[rep];
+  const float a = cr.a;
   const int J = cr.nlev;
   // load level kc: r, and c (into the u slot)
   {
@@ -459,25 +447,21 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep*
 
 // ---- launchers -------------------------------------------------------------
 
-void launch_mg_prepare(hipStream_t s, const Work&, const MgBufs& mg, double a, const double* c) {
-  const float af = (float)a;
+void launch_mg_prepare(hipStream_t s, const Work&, const MgBufs& mg, const double* c) {
   if (mg.lev[0].ntiles)
-    hipLaunchKernelGGL(k_mg_prep0, dim3(mg.lev[0].ntiles), dim3(kBlock), 0, s, mg.lev[0], af, c);
+    hipLaunchKernelGGL(k_mg_prep0, dim3(mg.lev[0].ntiles), dim3(kBlock), 0, s, mg.lev[0], c);
   for (int k = 0; k < mg.nlev_glob; ++k) {
     const MgLevel& Lc = mg.lev[k + 1];
     if (!Lc.nrtiles) continue;
     if (k == 0)
-      hipLaunchKernelGGL(k_mg_coarsen<true>, dim3(Lc.nrtiles), dim3(kBlock), 0, s, mg.lev[k], Lc, af,
-                         c);
+      hipLaunchKernelGGL(k_mg_coarsen<true>, dim3(Lc.nrtiles), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
     else
-      hipLaunchKernelGGL(k_mg_coarsen<false>, dim3(Lc.nrtiles), dim3(kBlock), 0, s, mg.lev[k], Lc,
-                         af, c);
+      hipLaunchKernelGGL(k_mg_coarsen<false>, dim3(Lc.nrtiles), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
   }
 }
 
-void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, double a,
-                      const SolverBufs& sb, MgHook hook, void* hctx) {
-  const float af = (float)a;
+void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const SolverBufs& sb,
+                      MgHook hook, void* hctx) {
   const float om = mg.omega;
   const SolveScal* ss = sb.ss;
   auto H = [&](int seg, int begin) {
@@ -487,11 +471,11 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, double a,
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_PRE0, 1);
-    hipLaunchKernelGGL((k_mg_pre<true, double>), dim3(L.ntiles), dim3(kBlock), 0, s, L, af, om,
+    hipLaunchKernelGGL((k_mg_pre<true, double>), dim3(L.ntiles), dim3(kBlock), 0, s, L, om,
                        (const double*)sb.r, ss);
     H(MG_PRE0, 0);
     H(MG_RESTRICT0, 1);
-    hipLaunchKernelGGL((k_mg_restrict<true, double>), dim3(C.nrtiles), dim3(kBlock), 0, s, L, C, af,
+    hipLaunchKernelGGL((k_mg_restrict<true, double>), dim3(C.nrtiles), dim3(kBlock), 0, s, L, C,
                        (const double*)sb.r, ss);
     H(MG_RESTRICT0, 0);
   }
@@ -501,16 +485,16 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, double a,
       const MgLevel& L = mg.lev[k];
       const MgLevel& C = mg.lev[k + 1];
       if (!L.ntiles) continue;
-      hipLaunchKernelGGL((k_mg_pre<false, float>), dim3(L.ntiles), dim3(kBlock), 0, s, L, af, om,
+      hipLaunchKernelGGL((k_mg_pre<false, float>), dim3(L.ntiles), dim3(kBlock), 0, s, L, om,
                          (const float*)L.r, ss);
       hipLaunchKernelGGL((k_mg_restrict<false, float>), dim3(C.nrtiles), dim3(kBlock), 0, s, L, C,
-                         af, (const float*)L.r, ss);
+                         (const float*)L.r, ss);
     }
     H(MG_DOWN, 0);
   }
   H(MG_COARSE, 1);
   hipLaunchKernelGGL(k_mg_coarse, dim3(w.nreps), dim3(kCoarseThreads), mg.coarse_lds_bytes, s,
-                     mg.coarse, af, om, (const float* const*)mg.lev_c, (const float* const*)mg.lev_r,
+                     mg.coarse, om, (const float* const*)mg.lev_c, (const float* const*)mg.lev_r,
                      (float* const*)mg.lev_u, ss);
   H(MG_COARSE, 0);
   if (mg.nlev_glob > 1) {
@@ -519,9 +503,9 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, double a,
       const MgLevel& L = mg.lev[k];
       const MgLevel& C = mg.lev[k + 1];
       if (!L.ntiles) continue;
-      hipLaunchKernelGGL((k_mg_post1<false, float>), dim3(L.ntiles), dim3(kBlock), 0, s, L, C, af,
-                         om, (const float*)L.r, ss);
-      hipLaunchKernelGGL((k_mg_post2<false, float>), dim3(L.ntiles), dim3(kBlock), 0, s, L, af, om,
+      hipLaunchKernelGGL((k_mg_post1<false, float>), dim3(L.ntiles), dim3(kBlock), 0, s, L, C, om,
+                         (const float*)L.r, ss);
+      hipLaunchKernelGGL((k_mg_post2<false, float>), dim3(L.ntiles), dim3(kBlock), 0, s, L, om,
                          (const float*)L.r, sb);
     }
     H(MG_UP, 0);
@@ -530,13 +514,14 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, double a,
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_POST1_0, 1);
-    hipLaunchKernelGGL((k_mg_post1<true, double>), dim3(L.ntiles), dim3(kBlock), 0, s, L, C, af, om,
+    hipLaunchKernelGGL((k_mg_post1<true, double>), dim3(L.ntiles), dim3(kBlock), 0, s, L, C, om,
                        (const double*)sb.r, ss);
     H(MG_POST1_0, 0);
     H(MG_POST2_0, 1);
-    hipLaunchKernelGGL((k_mg_post2<true, double>), dim3(L.ntiles), dim3(kBlock), 0, s, L, af, om,
+    hipLaunchKernelGGL((k_mg_post2<true, double>), dim3(L.ntiles), dim3(kBlock), 0, s, L, om,
                        (const double*)sb.r, sb);
     H(MG_POST2_0, 0);
+    launch_cg_reduce(s, w, sb, RED_RZ, 0.0, 0);
   }
 }
 

@@ -83,6 +83,30 @@ __global__ void __launch_bounds__(kBlock) k_setup_drug(Work w, DevParams p, int 
   });
 }
 
+// The three systems of one coupled step (oxygen and both drugs, see above)
+// in one pass; F = [K | G1 | G2], c and b in the same 3 x ntot layout.
+__global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long long ntot,
+                                                       const uint8_t* __restrict__ L,
+                                                       const double* __restrict__ vw,
+                                                       const double* __restrict__ F,
+                                                       const double* __restrict__ g0,
+                                                       double* __restrict__ c,
+                                                       double* __restrict__ b) {
+  for_each_voxel(w, [&](int rep, const RepDev&, long long g) {
+    const double wv = vw[g];
+    const double k = F[g];
+    const double chi = L[g] != 0 ? 1.0 : 0.0;
+    c[g] = p.inv_dt + p.r_k * wv + p.phi_K * chi / (p.K1 + k);
+    b[g] = k * p.inv_dt + p.r_k * wv * p.K0;
+    const double cg = p.inv_dt + p.psi_G + p.kappa_G * wv;
+    for (int i = 0; i < 2; ++i) {
+      const long long j = g + (i + 1) * ntot;
+      c[j] = cg;
+      b[j] = F[j] * p.inv_dt + p.kappa_G * wv * g0[2 * rep + i];
+    }
+  });
+}
+
 // Algorithm 1 initialisation of the cell state at the initial oxygen K^0:
 // P, V_c at the steady states of Eqs. (odep53), (odevegf) on occupied voxels,
 // phi ~ U(0,1) for cancer cells (Philox counter (gid, 0, INIT, 0), key (seed, 0)).
@@ -129,6 +153,13 @@ void launch_setup_drug(hipStream_t s, const Work& w, const DevParams& p, int dru
                        const double* vw, const double* G, const double* g0, double* c,
                        double* b) {
   hipLaunchKernelGGL(k_setup_drug, dim3(w.nflat), dim3(kBlock), 0, s, w, p, drug, vw, G, g0, c, b);
+}
+
+void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
+                       const uint8_t* L, const double* vw, const double* F, const double* g0,
+                       double* c, double* b) {
+  hipLaunchKernelGGL(k_setup_step, dim3(w.nflat), dim3(kBlock), 0, s, w, p, ntot, L, vw, F, g0, c,
+                     b);
 }
 
 void launch_init_cells(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,

@@ -6,9 +6,10 @@
 // Lap the 7-point Laplacian with zero-flux faces (a missing neighbour is
 // dropped), A a symmetric M-matrix.  The paper solves the same SPD systems
 // with CG (chemotherapy, linearised oxygen).  Here every replicate of the
-// batch runs its own CG in the same launches: per-replicate dot products are
-// reduced in a fixed order by the last workgroup of the replicate, and a
-// finished replicate's workgroups return at once.
+// batch runs its own CG in the same launches: each workgroup stores its
+// partial dot products, and a one-workgroup-per-replicate reduce kernel sums
+// them in a fixed order and advances the replicate's scalars.  A finished
+// replicate's workgroups return at once.
 //
 // Iteration (flexible CG, Polak-Ribiere beta, so a varying preconditioner is
 // allowed):
@@ -30,6 +31,7 @@ struct TileCoord {
   bool valid;
   int nx, ny, nz;
   long long off;
+  double a;
 };
 
 __device__ inline TileCoord tile_coord(const Work& w) {
@@ -45,16 +47,18 @@ __device__ inline TileCoord tile_coord(const Work& w) {
   tc.ny = rp.ny;
   tc.nz = rp.nz;
   tc.off = rp.off;
+  tc.a = rp.a;
   tc.valid = tc.x < rp.nx && tc.y < rp.ny;
   return tc;
 }
 
-// Marches one column (x, y) over [z0, z1) and calls f(i, z, u_c, Au, deg)
+// Marches one column (x, y) over [z0, z1) and calls f(i, deg, u_i, (A u)_i)
 // where u = U(j) is the operand (possibly formed on the fly) and
-// Au = (c_i + a deg) u_i - a sum_nb u_j.
+// (A u)_i = (c_i + a deg) u_i - a sum_nb u_j.
 template <typename UF, typename F>
-__device__ inline void stencil_column(const TileCoord& tc, const double* __restrict__ c, double a,
-                                      UF U, F f) {
+__device__ inline void stencil_column(const TileCoord& tc, const double* __restrict__ c, UF U,
+                                      F f) {
+  const double a = tc.a;
   const long long plane = (long long)tc.nx * tc.ny;
   long long i = tc.off + tc.x + (long long)tc.nx * (tc.y + (long long)tc.ny * tc.z0);
   double um = tc.z0 > 0 ? U(i - plane) : 0.0;
@@ -80,17 +84,17 @@ __device__ inline void stencil_column(const TileCoord& tc, const double* __restr
   }
 }
 
-// r = b - A x; Jacobi z = r / diag(A); p is set by the first iteration.
-__global__ void __launch_bounds__(kBlock) k_cg_start(Work w, double a, double rtol,
-                                                     const double* __restrict__ c,
+// r = b - A x; Jacobi mode also Dinv = 1/diag(A), z = Dinv r.
+__global__ void __launch_bounds__(kBlock) k_cg_start(Work w, const double* __restrict__ c,
                                                      const double* __restrict__ b,
                                                      const double* __restrict__ x,
                                                      SolverBufs sb) {
   __shared__ double lds4[4];
   const TileCoord tc = tile_coord(w);
+  const double a = tc.a;
   double bb = 0.0, rr = 0.0, rz = 0.0;
   if (tc.valid) {
-    stencil_column(tc, c, a, [&](long long j) { return x[j]; },
+    stencil_column(tc, c, [&](long long j) { return x[j]; },
                    [&](long long i, int deg, double, double Ax) {
                      const double bi = b[i];
                      const double r = bi - Ax;
@@ -106,43 +110,14 @@ __global__ void __launch_bounds__(kBlock) k_cg_start(Work w, double a, double rt
                      }
                    });
   }
-  double v[3];
-  v[0] = block_sum(bb, lds4);
-  v[1] = block_sum(rr, lds4);
-  v[2] = block_sum(rz, lds4);
-  const RepDev rp = w.reps[tc.rep];
-  if (publish_and_check_last(sb.partial + (size_t)blockIdx.x * 3, v, 3, sb.counter + tc.rep,
-                             rp.tile_nb)) {
-    const double* base = sb.partial + (size_t)rp.tile_b0 * 3;
-    const double tbb = reduce_partials(base, rp.tile_nb, 3, 0, lds4);
-    const double trr = reduce_partials(base, rp.tile_nb, 3, 1, lds4);
-    const double trz = reduce_partials(base, rp.tile_nb, 3, 2, lds4);
-    if (threadIdx.x == 0) {
-      SolveScal& s = sb.ss[tc.rep];
-      s.bb = tbb;
-      s.rr = trr;
-      s.rr0 = trr;
-      s.rz = trz;
-      s.rzn = trz;
-      s.rzo = 0.0;
-      s.beta = 0.0;
-      s.alpha = 0.0;
-      s.pq = 0.0;
-      s.it = 0;
-      s.first = 1;
-      const bool conv = trr <= rtol * rtol * tbb;
-      const bool bad = !isfinite(trr) || !isfinite(tbb);   // give up at once
-      s.conv = conv ? 1 : 0;
-      s.done = (conv || bad) ? 1 : 0;
-      if (s.done) atomicAdd(sb.ndone, 1);
-    }
-  }
+  bb = block_sum(bb, lds4);
+  rr = block_sum(rr, lds4);
+  rz = block_sum(rz, lds4);
+  store_partials(sb.partial + (size_t)blockIdx.x * 3, bb, rr, rz);
 }
 
-// p_new = z + beta p_old (p_new = z on the first iteration), q = A p_new,
-// alpha = r.z / p.q.
-__global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, double a,
-                                                     const double* __restrict__ c,
+// p_new = z + beta p_old (p_new = z on the first iteration), q = A p_new.
+__global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, const double* __restrict__ c,
                                                      const double* __restrict__ z,
                                                      const double* __restrict__ pold,
                                                      double* __restrict__ pnew,
@@ -156,30 +131,18 @@ __global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, double a,
   double pq = 0.0;
   if (tc.valid) {
     auto U = [&](long long j) { return first ? z[j] : z[j] + beta * pold[j]; };
-    stencil_column(tc, c, a, U, [&](long long i, int, double pc, double Ap) {
+    stencil_column(tc, c, U, [&](long long i, int, double pc, double Ap) {
       pnew[i] = pc;
       q[i] = Ap;
       pq += pc * Ap;
     });
   }
-  double v = block_sum(pq, lds4);
-  const RepDev rp = w.reps[tc.rep];
-  if (publish_and_check_last(sb.partial + (size_t)blockIdx.x * 3, &v, 1, sb.counter + tc.rep,
-                             rp.tile_nb)) {
-    const double tpq = reduce_partials(sb.partial + (size_t)rp.tile_b0 * 3, rp.tile_nb, 3, 0, lds4);
-    if (threadIdx.x == 0) {
-      SolveScal& s = sb.ss[tc.rep];
-      s.pq = tpq;
-      s.alpha = s.rz / tpq;
-    }
-  }
+  pq = block_sum(pq, lds4);
+  store_partials(sb.partial + (size_t)blockIdx.x * 3, pq, 0.0, 0.0);
 }
 
-// x += alpha p, r -= alpha q; convergence check.  Jacobi mode also forms
-// z' = r / diag(A) and beta = (r.z' - r.z_old) / r.z; multigrid mode leaves z'
-// and beta to the V-cycle and only records r.z_old.
-__global__ void __launch_bounds__(kBlock) k_cg_update(Work w, double rtol, int maxit,
-                                                      double* __restrict__ x,
+// x += alpha p, r -= alpha q; partials of r.r, r.z_old and (Jacobi) r.z'.
+__global__ void __launch_bounds__(kBlock) k_cg_update(Work w, double* __restrict__ x,
                                                       const double* __restrict__ p,
                                                       const double* __restrict__ q,
                                                       SolverBufs sb) {
@@ -213,58 +176,133 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(Work w, double rtol, int m
       }
     }
   }
-  double v[3];
-  v[0] = block_sum(rr, lds4);
-  v[1] = block_sum(rzo, lds4);
-  v[2] = block_sum(rzn, lds4);
-  if (publish_and_check_last(sb.partial + (size_t)blockIdx.x * 3, v, 3, sb.counter + fb.rep,
-                             rp.flat_nb)) {
-    const double* base = sb.partial + (size_t)rp.flat_b0 * 3;
-    const double trr = reduce_partials(base, rp.flat_nb, 3, 0, lds4);
-    const double trzo = reduce_partials(base, rp.flat_nb, 3, 1, lds4);
-    const double trzn = reduce_partials(base, rp.flat_nb, 3, 2, lds4);
+  rr = block_sum(rr, lds4);
+  rzo = block_sum(rzo, lds4);
+  rzn = block_sum(rzn, lds4);
+  store_partials(sb.partial + (size_t)blockIdx.x * 3, rr, rzo, rzn);
+}
+
+// Fixed-order sum of component k of the partials [b0, b0 + nb).
+__device__ inline double sum_partials(const double* partial, int b0, int nb, int k, double* lds4) {
+  double s = 0.0;
+  for (int j = threadIdx.x; j < nb; j += kBlock) s += partial[(size_t)(b0 + j) * 3 + k];
+  return block_sum(s, lds4);
+}
+
+// One workgroup per replicate: finish the reduction of the preceding kernel
+// and advance the replicate's CG scalars.
+template <int KIND>
+__global__ void __launch_bounds__(kBlock) k_cg_reduce(Work w, SolverBufs sb, double rtol, int maxit,
+                                                      unsigned fmask, int nrep) {
+  __shared__ double lds4[4];
+  const int rep = blockIdx.x;
+  SolveScal& s = sb.ss[rep];
+  if (KIND != RED_START && s.done) return;
+  if (KIND == RED_START && !((fmask >> (rep / nrep)) & 1u)) {   // field not requested
     if (threadIdx.x == 0) {
-      SolveScal& s = sb.ss[fb.rep];
-      s.rr = trr;
-      s.rzo = trzo;
-      s.it += 1;
-      s.first = 0;
-      if (jac) {
-        s.rzn = trzn;
-        s.beta = (trzn - trzo) / s.rz;
-        s.rz = trzn;
-      }
-      const bool conv = trr <= rtol * rtol * s.bb;
-      s.conv = conv ? 1 : 0;
-      if (conv || s.it >= maxit || !isfinite(trr)) {
-        s.done = 1;
-        atomicAdd(sb.ndone, 1);
-      }
+      s.it = 0;
+      s.rr = s.bb = 0.0;
+      s.conv = 1;
+      s.done = 1;
+      atomicAdd(sb.ndone, 1);
     }
+    return;
+  }
+  const RepDev rp = w.reps[rep];
+  const bool tiles = KIND != RED_UPDATE;
+  const int b0 = tiles ? rp.tile_b0 : rp.flat_b0;
+  const int nb = tiles ? rp.tile_nb : rp.flat_nb;
+  const double t0 = sum_partials(sb.partial, b0, nb, 0, lds4);
+  const double t1 = (KIND == RED_START || KIND == RED_UPDATE) ? sum_partials(sb.partial, b0, nb, 1, lds4) : 0.0;
+  const double t2 = (KIND == RED_START || KIND == RED_UPDATE) ? sum_partials(sb.partial, b0, nb, 2, lds4) : 0.0;
+  if (threadIdx.x != 0) return;
+  if (KIND == RED_START) {
+    s.bb = t0;
+    s.rr = t1;
+    s.rr0 = t1;
+    s.rz = t2;
+    s.rzn = t2;
+    s.rzo = 0.0;
+    s.beta = 0.0;
+    s.alpha = 0.0;
+    s.pq = 0.0;
+    s.it = 0;
+    s.first = 1;
+    const bool conv = t1 <= rtol * rtol * t0;
+    const bool bad = !isfinite(t1) || !isfinite(t0);   // give up at once
+    s.conv = conv ? 1 : 0;
+    s.done = (conv || bad) ? 1 : 0;
+    if (s.done) atomicAdd(sb.ndone, 1);
+  } else if (KIND == RED_APPLY) {
+    s.pq = t0;
+    s.alpha = s.rz / t0;
+  } else if (KIND == RED_UPDATE) {
+    s.rr = t0;
+    s.rzo = t1;
+    s.it += 1;
+    s.first = 0;
+    if (sb.jacobi) {
+      s.rzn = t2;
+      s.beta = (t2 - t1) / s.rz;
+      s.rz = t2;
+    }
+    const bool conv = t0 <= rtol * rtol * s.bb;
+    s.conv = conv ? 1 : 0;
+    if (conv || s.it >= maxit || !isfinite(t0)) {
+      s.done = 1;
+      atomicAdd(sb.ndone, 1);
+    }
+  } else {   // RED_RZ: r.z' of the preconditioner, beta of the flexible CG
+    s.rzn = t0;
+    s.beta = s.first ? 0.0 : (t0 - s.rzo) / s.rz;
+    s.rz = t0;
   }
 }
 
 __global__ void k_zero_int(int* p) { *p = 0; }
 
-void launch_cg_start(hipStream_t s, const Work& w, double a, double rtol, int,
-                     const double* c, const double* b, const double* x, const SolverBufs& sb) {
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, sb.ndone);
-  hipLaunchKernelGGL(k_cg_start, dim3(w.ntiles), dim3(kBlock), 0, s, w, a, rtol, c, b, x, sb);
+void launch_cg_reduce(hipStream_t s, const Work& w, const SolverBufs& sb, int kind, double rtol,
+                      int maxit, unsigned fm, int nrep) {
+  const dim3 g(w.nreps), b(kBlock);
+  switch (kind) {
+    case RED_START:
+      hipLaunchKernelGGL(k_cg_reduce<RED_START>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
+      break;
+    case RED_APPLY:
+      hipLaunchKernelGGL(k_cg_reduce<RED_APPLY>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
+      break;
+    case RED_UPDATE:
+      hipLaunchKernelGGL(k_cg_reduce<RED_UPDATE>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
+      break;
+    default:
+      hipLaunchKernelGGL(k_cg_reduce<RED_RZ>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
+      break;
+  }
 }
 
-void launch_cg_apply(hipStream_t s, const Work& w, double a, const double* c,
-                     const SolverBufs& sb, int parity) {
+void launch_cg_start(hipStream_t s, const Work& w, double rtol, int maxit, const double* c,
+                     const double* b, const double* x, const SolverBufs& sb, unsigned field_mask,
+                     int nrep) {
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, sb.ndone);
+  hipLaunchKernelGGL(k_cg_start, dim3(w.ntiles), dim3(kBlock), 0, s, w, c, b, x, sb);
+  launch_cg_reduce(s, w, sb, RED_START, rtol, maxit, field_mask, nrep);
+}
+
+void launch_cg_apply(hipStream_t s, const Work& w, const double* c, const SolverBufs& sb,
+                     int parity) {
   const double* pold = parity ? sb.p1 : sb.p0;
   double* pnew = parity ? sb.p0 : sb.p1;
-  hipLaunchKernelGGL(k_cg_apply, dim3(w.ntiles), dim3(kBlock), 0, s, w, a, c, sb.z, pold, pnew,
-                     sb.q, sb);
+  hipLaunchKernelGGL(k_cg_apply, dim3(w.ntiles), dim3(kBlock), 0, s, w, c, sb.z, pold, pnew, sb.q,
+                     sb);
+  launch_cg_reduce(s, w, sb, RED_APPLY, 0.0, 0);
 }
 
-void launch_cg_update(hipStream_t s, const Work& w, double, double rtol, int maxit,
-                      const double*, double* x, const SolverBufs& sb, int parity) {
+void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, double* x,
+                      const SolverBufs& sb, int parity) {
   const double* pnew = parity ? sb.p0 : sb.p1;
-  hipLaunchKernelGGL(k_cg_update, dim3(w.nflat), dim3(kBlock), 0, s, w, rtol, maxit, x, pnew,
+  hipLaunchKernelGGL(k_cg_update, dim3(w.nflat), dim3(kBlock), 0, s, w, x, pnew,
                      (const double*)sb.q, sb);
+  launch_cg_reduce(s, w, sb, RED_UPDATE, rtol, maxit);
 }
 
 }  // namespace hca

@@ -1,5 +1,12 @@
-// Host runtime of libhca: context, device memory, replicate / work tables,
-// the per-step phase sequence of Algorithm 1, the CG driver and the C ABI.
+// Host runtime of libhca: context, device memory, replicate / system work
+// tables, the per-step phase sequence of Algorithm 1, the CG driver and the
+// C ABI.
+//
+// The three implicit-Euler solves of a step (oxygen and two drugs) are
+// independent given the state at t^n, so they run as one batch of 3 x nreps
+// linear systems (system s = field * nreps + rep) through the same launches;
+// the fields live in one allocation [K | G1 | G2] and the solver arrays have
+// the same 3 x total-voxel layout.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,24 +25,23 @@ using namespace hca;
 namespace {
 
 enum KernelClass {
-  KC_PLASMA = 0, KC_SETUP_O2, KC_SETUP_DRUG, KC_CG_START, KC_CG_APPLY, KC_CG_UPDATE, KC_ODE,
+  KC_PLASMA = 0, KC_SETUP, KC_CG_START, KC_CG_APPLY, KC_CG_UPDATE, KC_ODE,
   KC_CA_PROPOSE, KC_CA_RESOLVE, KC_CA_FINALIZE, KC_STATS,
   KC_MG_PREP, KC_MG_PRE0, KC_MG_RESTRICT0, KC_MG_LEVELS, KC_MG_COARSE, KC_MG_POST1_0,
   KC_MG_POST2_0, KC_COUNT
 };
 
 const char* kKernelNames[KC_COUNT] = {
-    "k_plasma", "k_setup_o2", "k_setup_drug", "k_cg_start", "k_cg_apply", "k_cg_update",
+    "k_plasma", "k_setup_step", "k_cg_start", "k_cg_apply", "k_cg_update",
     "k_ode", "k_ca_propose", "k_ca_resolve", "k_ca_finalize", "k_stats",
     "k_mg_prep0+k_mg_coarsen", "k_mg_pre<L0>", "k_mg_restrict<L0>", "mg levels >= 1 (global)",
     "k_mg_coarse", "k_mg_post1<L0>", "k_mg_post2<L0>"};
 
-// Compulsory (algorithmic) HBM bytes per fine voxel of each kernel class
-// (0: not priced, launch- or latency-bound).
+// Compulsory (algorithmic) HBM bytes per voxel of each kernel class; solver
+// classes per voxel of each active system (0: not priced, latency-bound).
 const double kBytesPerVoxel[KC_COUNT] = {
     0.0,          // plasma: per replicate only
-    33.0,         // setup_o2: read L, w, K; write c, b
-    32.0,         // setup_drug: read w, G; write c, b
+    81.0,         // setup_step: read L, w, K, G1, G2; write c, b of three systems
     40.0,         // cg_start: read x, c, b; write r, (Jacobi: dinv, z)
     40.0,         // cg_apply: read z, p_old, c; write p_new, q
     72.0,         // cg_update, Jacobi: read x, p, r, q, z, dinv; write x, r, z
@@ -53,18 +59,20 @@ const double kBytesPerVoxel[KC_COUNT] = {
     24.0};        // mg post2 L0: read ualt, r, dinv; write z (8)
 constexpr double kBytesUpdateMg = 56.0;   // cg_update, multigrid: read x, p, r, q, z; write x, r
 
+constexpr int kTagState = -2;   // launches over every voxel of every replicate
+constexpr int kTagAll = -1;     // solver launches over every system
+
 struct RepHost {
   int nx, ny, nz;
   long long off, n;
   uint64_t seed;
-  int nvessel;
 };
 
 struct ProfEntry {
   int kc;
   hipEvent_t a, b;
-  int iter;      // CG iteration index within the solve, -1 otherwise
-  double bytes;
+  int tag;       // CG iteration index of the launch, kTagAll or kTagState
+  double bpv;    // bytes per active voxel
 };
 
 }  // namespace
@@ -79,28 +87,39 @@ struct hca_ctx {
   bool own_stream = false;
   int device = 0;
 
+  // state
   uint8_t *L = nullptr, *code = nullptr, *win = nullptr;
-  double *w = nullptr, *K = nullptr, *G1 = nullptr, *G2 = nullptr, *P = nullptr, *Vc = nullptr,
-         *phi = nullptr, *c = nullptr, *b = nullptr;
+  double *w = nullptr, *P = nullptr, *Vc = nullptr, *phi = nullptr;
+  double* F = nullptr;                          // [K | G1 | G2]
+  double *K = nullptr, *G1 = nullptr, *G2 = nullptr;
+  // solver, 3 x ntot
+  double *c = nullptr, *b = nullptr;
   SolverBufs sb{};
   bool use_mg = false;
-  MgBufs mg{};
+  MgBufs mg3{}, mg1{};                          // all systems / oxygen systems only
   std::vector<void*> mg_mem;
   double *dose_t = nullptr, *dose_a = nullptr, *g0 = nullptr;
   long long* d_step = nullptr;
+  // replicate tables (state kernels)
   RepDev* d_reps = nullptr;
   FlatBlk* d_flat = nullptr;
   Tile* d_tiles = nullptr;
+  Work work{};
+  // system tables (solver kernels); sys1 is the oxygen prefix of sys3
+  RepDev* d_sys = nullptr;
+  FlatBlk* d_sflat = nullptr;
+  Tile* d_stiles = nullptr;
+  Work sys3{}, sys1{};
+  std::vector<long long> sys_n;
   Counters* d_cnt = nullptr;
   const double** d_fields = nullptr;
   unsigned long long* d_bad = nullptr;
-  Work work{};
 
-  SolveScal* h_ss = nullptr;     // pinned
+  SolveScal* h_ss = nullptr;     // pinned, 3 x nreps
   Counters* h_cnt = nullptr;     // pinned
   long long step = 0;
-  int last_it[3] = {0, 0, 0};
-  std::vector<SolveScal> last_ss[3];
+  int last_it[2] = {0, 0};       // iterations of the last step solve / init solve
+  std::vector<SolveScal> last_ss;
   int picard_iters = 0;
 
   bool failed = false;
@@ -136,6 +155,8 @@ hipError_t dalloc(T** p, size_t count) {
   return hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
 }
 
+// ---- kernel timing (params.profile) ----------------------------------------
+
 hipEvent_t take_event(hca_ctx* c) {
   if (!c->free_events.empty()) {
     hipEvent_t e = c->free_events.back();
@@ -147,14 +168,17 @@ hipEvent_t take_event(hca_ctx* c) {
   return e;
 }
 
+double bpv_of(const hca_ctx* c, int kc) {
+  if (kc == KC_CG_UPDATE && c->use_mg) return kBytesUpdateMg;
+  return kBytesPerVoxel[kc];
+}
+
 struct ProfScope {
   hca_ctx* c;
   int kc;
-  int iter;
-  double bytes;
+  int tag;
   hipEvent_t a = nullptr;
-  ProfScope(hca_ctx* c_, int kc_, double bytes_, int iter_ = -1)
-      : c(c_), kc(kc_), iter(iter_), bytes(bytes_) {
+  ProfScope(hca_ctx* c_, int kc_, int tag_) : c(c_), kc(kc_), tag(tag_) {
     if (c->prm.profile) {
       a = take_event(c);
       if (a) (void)hipEventRecord(a, c->stream);
@@ -165,23 +189,29 @@ struct ProfScope {
     hipEvent_t b = take_event(c);
     if (!b) return;
     (void)hipEventRecord(b, c->stream);
-    c->pending.push_back(ProfEntry{kc, a, b, iter, bytes});
+    c->pending.push_back(ProfEntry{kc, a, b, tag, bpv_of(c, kc)});
   }
 };
 
-// Accumulate every pending timing; CG launches at iteration >= real_iters
-// found their replicates already finished and are dropped.
-void prof_flush(hca_ctx* c, int real_iters) {
+// Accumulate the pending timings.  A solver launch with tag t does work for
+// the systems still iterating (iterations > t); launches that found every
+// system finished are dropped, the others are priced on the active voxels.
+void prof_flush(hca_ctx* c, const SolveScal* ss, int nsys) {
   if (c->pending.empty()) return;
   (void)hipEventSynchronize(c->pending.back().b);
   for (const ProfEntry& e : c->pending) {
-    const bool noop = e.iter >= 0 && e.iter >= real_iters;
-    if (!noop) {
+    double vox = (double)c->ntot;
+    if (e.tag >= kTagAll && ss) {
+      vox = 0.0;
+      for (int s = 0; s < nsys; ++s)
+        if (e.tag == kTagAll || ss[s].it > e.tag) vox += (double)c->sys_n[s];
+    }
+    if (vox > 0.0) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
         c->prof_ms[e.kc] += ms;
         c->prof_n[e.kc] += 1;
-        c->prof_bytes[e.kc] += e.bytes;
+        c->prof_bytes[e.kc] += e.bpv * vox;
       }
     }
     c->free_events.push_back(e.a);
@@ -190,16 +220,11 @@ void prof_flush(hca_ctx* c, int real_iters) {
   c->pending.clear();
 }
 
-double bytes_all(const hca_ctx* c, int kc) {
-  if (kc == KC_CG_UPDATE && c->use_mg) return kBytesUpdateMg * (double)c->ntot;
-  return kBytesPerVoxel[kc] * (double)c->ntot;
-}
-
-// Event pairs around the V-cycle's launch segments (profile mode).
+// Event pairs around the V-cycle's launch segments.
 struct MgProf {
   hca_ctx* c;
   hipEvent_t start[8];
-  int iter;
+  int tag;
 };
 
 int mg_segment_class(int seg) {
@@ -227,15 +252,15 @@ void mg_hook(void* p, int seg, int begin) {
   if (!b) return;
   (void)hipEventRecord(b, c->stream);
   const int kc = mg_segment_class(seg);
-  c->pending.push_back(ProfEntry{kc, m->start[seg], b, m->iter, bytes_all(c, kc)});
+  c->pending.push_back(ProfEntry{kc, m->start[seg], b, m->tag, bpv_of(c, kc)});
   m->start[seg] = nullptr;
 }
 
-void run_vcycle(hca_ctx* c, double a, int iter_tag) {
+void run_vcycle(hca_ctx* c, const Work& W, const MgBufs& mg, int tag) {
   MgProf mp{};
   mp.c = c;
-  mp.iter = iter_tag;
-  launch_mg_vcycle(c->stream, c->work, c->mg, a, c->sb, mg_hook, &mp);
+  mp.tag = tag;
+  launch_mg_vcycle(c->stream, W, mg, c->sb, mg_hook, &mp);
 }
 
 DevParams make_dev_params(const hca_params& p) {
@@ -275,60 +300,63 @@ int pick_tx(int nx) {
   return 16;
 }
 
-// Conjugate-gradient solve of (diag(c) - a Lap) x = b for every replicate.
-// Launches iterations in batches sized from the previous solve of the same
-// field and polls the per-replicate scalars between batches.
-hca_status solve(hca_ctx* c, int field, double a, double rtol, int maxit, double* x,
-                 int* real_iters_out) {
+// ---- the solver driver -------------------------------------------------------
+
+// Flexible CG on the systems of W (all systems: sys3, oxygen only: sys1) for
+// (diag(c) - a Lap) x = b, x = the field array F.  Systems of fields outside
+// `fmask` are marked finished at the start.  Iterations are launched in
+// batches sized from the previous solve of the same kind, with a poll of the
+// per-system scalars between batches.
+hca_status solve(hca_ctx* c, const Work& W, const MgBufs& mg, unsigned fmask, double rtol,
+                 int maxit, int kind) {
+  const int nsys = W.nreps;
   if (c->use_mg) {
-    ProfScope ps(c, KC_MG_PREP, bytes_all(c, KC_MG_PREP));
-    launch_mg_prepare(c->stream, c->work, c->mg, a, c->c);
+    ProfScope ps(c, KC_MG_PREP, kTagAll);
+    launch_mg_prepare(c->stream, W, mg, c->c);
   }
   {
-    ProfScope ps(c, KC_CG_START, bytes_all(c, KC_CG_START));
-    launch_cg_start(c->stream, c->work, a, rtol, maxit, c->c, c->b, x, c->sb);
+    ProfScope ps(c, KC_CG_START, kTagAll);
+    launch_cg_start(c->stream, W, rtol, maxit, c->c, c->b, c->F, c->sb, fmask, c->nreps);
   }
-  // the preconditioned start residual (no-op if the start already converged)
-  if (c->use_mg) run_vcycle(c, a, 0);
+  if (c->use_mg) run_vcycle(c, W, mg, 0);   // z of the start residual
   int launched = 0;
-  int batch = std::max(1, c->last_it[field] - 1);
+  int batch = std::max(1, c->last_it[kind] - 1);
   int real = 0;
   for (;;) {
     batch = std::min(batch, maxit - launched);
     for (int k = 0; k < batch; ++k, ++launched) {
       {
-        ProfScope ps(c, KC_CG_APPLY, bytes_all(c, KC_CG_APPLY), launched);
-        launch_cg_apply(c->stream, c->work, a, c->c, c->sb, launched & 1);
+        ProfScope ps(c, KC_CG_APPLY, launched);
+        launch_cg_apply(c->stream, W, c->c, c->sb, launched & 1);
       }
       {
-        ProfScope ps(c, KC_CG_UPDATE, bytes_all(c, KC_CG_UPDATE), launched);
-        launch_cg_update(c->stream, c->work, a, rtol, maxit, c->c, x, c->sb, launched & 1);
+        ProfScope ps(c, KC_CG_UPDATE, launched);
+        launch_cg_update(c->stream, W, rtol, maxit, c->F, c->sb, launched & 1);
       }
-      // z = M r for the next direction; real only if this iteration did not converge
-      if (c->use_mg) run_vcycle(c, a, launched + 1);
+      // z = M r for the next direction (work only where this iteration did not converge)
+      if (c->use_mg) run_vcycle(c, W, mg, launched + 1);
     }
-    HIPCHK(c, hipMemcpyAsync(c->h_ss, c->sb.ss, sizeof(SolveScal) * c->nreps,
-                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->h_ss, c->sb.ss, sizeof(SolveScal) * nsys, hipMemcpyDeviceToHost,
+                             c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     bool all = true;
     real = 0;
-    for (int r = 0; r < c->nreps; ++r) {
-      all = all && c->h_ss[r].done;
-      real = std::max(real, c->h_ss[r].it);
+    for (int s = 0; s < nsys; ++s) {
+      all = all && c->h_ss[s].done;
+      real = std::max(real, c->h_ss[s].it);
     }
     if (all || launched >= maxit) break;
     batch = 2;
   }
-  prof_flush(c, real);
-  c->last_ss[field].assign(c->h_ss, c->h_ss + c->nreps);
-  c->last_it[field] = real;
-  if (real_iters_out) *real_iters_out = real;
-  for (int r = 0; r < c->nreps; ++r)
-    if (!c->h_ss[r].conv) {
+  prof_flush(c, c->h_ss, nsys);
+  c->last_it[kind] = real;
+  if (kind == 0) c->last_ss.assign(c->h_ss, c->h_ss + nsys);
+  for (int s = 0; s < nsys; ++s)
+    if (!c->h_ss[s].conv) {
       char buf[160];
       snprintf(buf, sizeof buf, "field %d replicate %d: CG stopped at %d iterations, rel. res %.3e",
-               field, r, c->h_ss[r].it,
-               c->h_ss[r].bb > 0 ? std::sqrt(c->h_ss[r].rr / c->h_ss[r].bb) : 0.0);
+               s / c->nreps, s % c->nreps, c->h_ss[s].it,
+               c->h_ss[s].bb > 0 ? std::sqrt(c->h_ss[s].rr / c->h_ss[s].bb) : 0.0);
       return fail(c, HCA_E_NOCONV, buf);
     }
   return HCA_OK;
@@ -337,51 +365,41 @@ hca_status solve(hca_ctx* c, int field, double a, double rtol, int maxit, double
 hca_status run_phases(hca_ctx* c, unsigned mask) {
   const Work& wk = c->work;
   hipStream_t s = c->stream;
-  if (mask & (HCA_PH_O2 | HCA_PH_DRUGS)) {
-    ProfScope ps(c, KC_PLASMA, 0.0);
-    launch_plasma(s, wk, c->dp, c->d_step, c->dose_t, c->dose_a, c->g0);
-  }
-  if (mask & HCA_PH_O2) {
+  const unsigned fmask = ((mask & HCA_PH_O2) ? 1u : 0u) | ((mask & HCA_PH_DRUGS) ? 6u : 0u);
+  if (fmask) {
     {
-      ProfScope ps(c, KC_SETUP_O2, bytes_all(c, KC_SETUP_O2));
-      launch_setup_o2(s, wk, c->dp, c->L, c->w, c->K, c->c, c->b, 0);
+      ProfScope ps(c, KC_PLASMA, kTagState);
+      launch_plasma(s, wk, c->dp, c->d_step, c->dose_t, c->dose_a, c->g0);
     }
-    hca_status st = solve(c, 0, c->dp.aK, c->prm.cg_rtol, c->prm.cg_maxit, c->K, nullptr);
+    {
+      ProfScope ps(c, KC_SETUP, kTagState);
+      launch_setup_step(s, wk, c->dp, c->ntot, c->L, c->w, c->F, c->g0, c->c, c->b);
+    }
+    hca_status st = solve(c, c->sys3, c->mg3, fmask, c->prm.cg_rtol, c->prm.cg_maxit, 0);
     if (st != HCA_OK) return st;
   }
-  if (mask & HCA_PH_DRUGS) {
-    double* G[2] = {c->G1, c->G2};
-    for (int i = 0; i < 2; ++i) {
-      {
-        ProfScope ps(c, KC_SETUP_DRUG, bytes_all(c, KC_SETUP_DRUG));
-        launch_setup_drug(s, wk, c->dp, i, c->w, G[i], c->g0, c->c, c->b);
-      }
-      hca_status st = solve(c, 1 + i, c->dp.aG, c->prm.cg_rtol, c->prm.cg_maxit, G[i], nullptr);
-      if (st != HCA_OK) return st;
-    }
-  }
   if (mask & HCA_PH_ODE) {
-    ProfScope ps(c, KC_ODE, bytes_all(c, KC_ODE));
+    ProfScope ps(c, KC_ODE, kTagState);
     launch_ode(s, wk, c->dp, c->L, c->K, c->P, c->Vc, c->phi);
   }
   if (mask & HCA_PH_CA) {
     launch_zero_counters(s, c->d_cnt, c->nreps, 1);
     {
-      ProfScope ps(c, KC_CA_PROPOSE, bytes_all(c, KC_CA_PROPOSE));
+      ProfScope ps(c, KC_CA_PROPOSE, kTagState);
       launch_ca_propose(s, wk, c->dp, c->d_step, c->L, c->w, c->K, c->G1, c->G2, c->phi, c->code);
     }
     {
-      ProfScope ps(c, KC_CA_RESOLVE, bytes_all(c, KC_CA_RESOLVE));
+      ProfScope ps(c, KC_CA_RESOLVE, kTagState);
       launch_ca_resolve(s, wk, c->L, c->w, c->phi, c->code, c->win);
     }
     {
-      ProfScope ps(c, KC_CA_FINALIZE, bytes_all(c, KC_CA_FINALIZE));
+      ProfScope ps(c, KC_CA_FINALIZE, kTagState);
       launch_ca_finalize(s, wk, c->L, c->phi, c->P, c->Vc, c->code, c->win, c->d_cnt);
     }
   }
   if (mask & HCA_PH_STATS) {
     launch_zero_counters(s, c->d_cnt, c->nreps, 0);
-    ProfScope ps(c, KC_STATS, bytes_all(c, KC_STATS));
+    ProfScope ps(c, KC_STATS, kTagState);
     launch_stats(s, wk, c->L, c->w, c->d_fields, 6, c->d_cnt);
   }
   if (mask & HCA_PH_ADVANCE) {
@@ -396,7 +414,7 @@ hca_status check_after(hca_ctx* c) {
   HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(Counters) * c->nreps, hipMemcpyDeviceToHost,
                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  prof_flush(c, 0);
+  prof_flush(c, nullptr, 0);
   for (int r = 0; r < c->nreps; ++r)
     if (c->h_cnt[r].nonfinite) {
       char buf[96];
@@ -406,6 +424,8 @@ hca_status check_after(hca_ctx* c) {
     }
   return HCA_OK;
 }
+
+// ---- validation ----------------------------------------------------------------
 
 hca_status validate_reps(const hca_replicate* reps, int n, std::string& msg, int& singular) {
   singular = -1;
@@ -423,7 +443,7 @@ hca_status validate_reps(const hca_replicate* reps, int n, std::string& msg, int
       return HCA_E_INVALID;
     }
     const long long nv = (long long)R.nx * R.ny * R.nz;
-    int nves = 0;
+    long long nves = 0;
     for (long long i = 0; i < nv; ++i) {
       const double wv = R.vessel_w[i];
       const uint8_t l = R.cell[i];
@@ -477,15 +497,17 @@ hca_status validate_params(const hca_params* p, std::string& msg) {
     }
   if (!std::isfinite(p->k2pp) || p->b_int[0] < 1 || p->b_int[1] < 1 || p->b_int[0] > 64 ||
       p->b_int[1] > 64 || p->ode_substeps < 1 || p->cg_maxit < 1 || p->init_maxit < 1 ||
-      (p->precond != 0 && p->precond != 1)) {
+      (p->precond != 0 && p->precond != 1) || p->mg_coarse_max < 1) {
     msg = "integer parameter out of range";
     return HCA_E_INVALID;
   }
   return HCA_OK;
 }
 
-// z-extent of a column tile: enough tiles to fill the chip (about `target`
-// for this replicate), at most 16 planes per tile.
+// ---- work tables -------------------------------------------------------------
+
+// z-extent of a column tile: about `target` tiles per lattice (enough to fill
+// the chip for a lone lattice), at most 16 planes per tile.
 int pick_tz(int nx, int ny, int nz, int tx, double target) {
   const int ty = kBlock / tx;
   const double nxy = (double)((nx + tx - 1) / tx) * (double)((ny + ty - 1) / ty);
@@ -508,71 +530,132 @@ void add_tiles(std::vector<Tile>& v, int rep, int nx, int ny, int nz, int tx, in
       }
 }
 
-constexpr double kTileTarget = 1024.0;   // column tiles per launch on a lone replicate
+constexpr double kTileTarget = 1024.0;
 
-hca_status build_tables(hca_ctx* c) {
-  std::vector<RepDev> rd(c->nreps);
-  std::vector<FlatBlk> flat;
-  std::vector<Tile> tiles;
-  for (int r = 0; r < c->nreps; ++r) {
-    const RepHost& R = c->reps[r];
-    // tile shape per replicate (from its own size only), so a replicate's
-    // arithmetic and rounding are the same alone or in a batch
-    const int tx = pick_tx(R.nx);
-    const int ty = kBlock / tx;
-    const int tz = pick_tz(R.nx, R.ny, R.nz, tx, kTileTarget);
-    (void)ty;
-    RepDev& d = rd[r];
-    memset(&d, 0, sizeof d);
-    d.nx = R.nx;
-    d.ny = R.ny;
-    d.nz = R.nz;
-    d.off = R.off;
-    d.n = R.n;
-    d.seed = R.seed;
-    const long long chunks = (R.n + kFlatChunk - 1) / kFlatChunk;
-    d.flat_nb = (int)std::min<long long>(chunks, kMaxFlatBlocksPerRep);
-    d.flat_b0 = (int)flat.size();
-    for (int k = 0; k < d.flat_nb; ++k) flat.push_back(FlatBlk{r, k});
-    d.tile_b0 = (int)tiles.size();
-    add_tiles(tiles, r, R.nx, R.ny, R.nz, tx, tz);
-    d.tile_nb = (int)tiles.size() - d.tile_b0;
-    d.dose_off = r * 2 * HCA_MAX_DOSES;
-    d.tx = tx;
+template <typename T>
+hca_status upload(hca_ctx* c, T** p, const std::vector<T>& v) {
+  HIPCHK(c, dalloc(p, v.size()));
+  if (!v.empty()) HIPCHK(c, hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return HCA_OK;
+}
+
+// Table entry of one lattice (a replicate, or one field's system of it).
+// Tile shape and flat blocking come from the lattice's own size only, so a
+// lattice's arithmetic and rounding are the same alone or in a batch.
+RepDev lattice_entry(const RepHost& R, long long off, int idx, std::vector<FlatBlk>& flat,
+                     std::vector<Tile>& tiles) {
+  RepDev d;
+  memset(&d, 0, sizeof d);
+  d.nx = R.nx;
+  d.ny = R.ny;
+  d.nz = R.nz;
+  d.off = off;
+  d.n = R.n;
+  d.seed = R.seed;
+  const long long chunks = (R.n + kFlatChunk - 1) / kFlatChunk;
+  d.flat_nb = (int)std::min<long long>(chunks, kMaxFlatBlocksPerRep);
+  d.flat_b0 = (int)flat.size();
+  for (int k = 0; k < d.flat_nb; ++k) flat.push_back(FlatBlk{idx, k});
+  d.tx = pick_tx(R.nx);
+  const int tz = pick_tz(R.nx, R.ny, R.nz, d.tx, kTileTarget);
+  d.tile_b0 = (int)tiles.size();
+  add_tiles(tiles, idx, R.nx, R.ny, R.nz, d.tx, tz);
+  d.tile_nb = (int)tiles.size() - d.tile_b0;
+  return d;
+}
+
+hca_status build_tables(hca_ctx* c, const hca_replicate* in) {
+  const int R = c->nreps;
+  {
+    std::vector<RepDev> rd;
+    std::vector<FlatBlk> flat;
+    std::vector<Tile> tiles;
+    for (int r = 0; r < R; ++r) {
+      RepDev d = lattice_entry(c->reps[r], c->reps[r].off, r, flat, tiles);
+      d.dose_off = r * 2 * HCA_MAX_DOSES;
+      d.ndose[0] = in[r].n_doses[0];
+      d.ndose[1] = in[r].n_doses[1];
+      rd.push_back(d);
+    }
+    hca_status st;
+    if ((st = upload(c, &c->d_reps, rd)) != HCA_OK || (st = upload(c, &c->d_flat, flat)) != HCA_OK ||
+        (st = upload(c, &c->d_tiles, tiles)) != HCA_OK)
+      return st;
+    c->work.nreps = R;
+    c->work.reps = c->d_reps;
+    c->work.flat = c->d_flat;
+    c->work.nflat = (int)flat.size();
+    c->work.tiles = c->d_tiles;
+    c->work.ntiles = (int)tiles.size();
   }
-  c->work.nreps = c->nreps;
-  c->work.nflat = (int)flat.size();
-  c->work.ntiles = (int)tiles.size();
-  HIPCHK(c, dalloc(&c->d_reps, rd.size()));
-  HIPCHK(c, dalloc(&c->d_flat, flat.size()));
-  HIPCHK(c, dalloc(&c->d_tiles, tiles.size()));
-  HIPCHK(c, hipMemcpy(c->d_reps, rd.data(), rd.size() * sizeof(RepDev), hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->d_flat, flat.data(), flat.size() * sizeof(FlatBlk), hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
-  c->work.reps = c->d_reps;
-  c->work.flat = c->d_flat;
-  c->work.tiles = c->d_tiles;
+  {
+    std::vector<RepDev> sd;
+    std::vector<FlatBlk> flat;
+    std::vector<Tile> tiles;
+    int nflat1 = 0, ntiles1 = 0;
+    c->sys_n.clear();
+    for (int f = 0; f < 3; ++f) {
+      for (int r = 0; r < R; ++r) {
+        RepDev d = lattice_entry(c->reps[r], (long long)f * c->ntot + c->reps[r].off, f * R + r,
+                                 flat, tiles);
+        d.a = f == 0 ? c->dp.aK : c->dp.aG;
+        sd.push_back(d);
+        c->sys_n.push_back(c->reps[r].n);
+      }
+      if (f == 0) {
+        nflat1 = (int)flat.size();
+        ntiles1 = (int)tiles.size();
+      }
+    }
+    hca_status st;
+    if ((st = upload(c, &c->d_sys, sd)) != HCA_OK || (st = upload(c, &c->d_sflat, flat)) != HCA_OK ||
+        (st = upload(c, &c->d_stiles, tiles)) != HCA_OK)
+      return st;
+    c->sys3.nreps = 3 * R;
+    c->sys3.reps = c->d_sys;
+    c->sys3.flat = c->d_sflat;
+    c->sys3.nflat = (int)flat.size();
+    c->sys3.tiles = c->d_stiles;
+    c->sys3.ntiles = (int)tiles.size();
+    c->sys1 = c->sys3;
+    c->sys1.nreps = R;
+    c->sys1.nflat = nflat1;
+    c->sys1.ntiles = ntiles1;
+  }
   return HCA_OK;
 }
 
 hca_status alloc_all(hca_ctx* c) {
   const size_t n = (size_t)c->ntot;
+  const size_t n3 = 3 * n;
+  const int nsys = 3 * c->nreps;
+  auto big = [&](double** p, size_t count) -> hca_status {
+    hipError_t e = dalloc(p, count);
+    if (e == hipErrorOutOfMemory) return fail(c, HCA_E_NOMEM, "device memory exhausted");
+    HIPCHK(c, e);
+    return HCA_OK;
+  };
   HIPCHK(c, dalloc(&c->L, n));
   HIPCHK(c, dalloc(&c->code, n));
   HIPCHK(c, dalloc(&c->win, n));
-  double** f64[] = {&c->w, &c->K, &c->G1, &c->G2, &c->P, &c->Vc, &c->phi, &c->c, &c->b,
-                    &c->sb.r, &c->sb.z, &c->sb.p0, &c->sb.p1, &c->sb.q};
-  for (double** p : f64) {
-    hipError_t e = dalloc(p, n);
-    if (e == hipErrorOutOfMemory) return fail(c, HCA_E_NOMEM, "device memory exhausted");
-    HIPCHK(c, e);
-  }
-  const size_t nwork = (size_t)std::max(c->work.ntiles, c->work.nflat);
+  hca_status st;
+  double** f1[] = {&c->w, &c->P, &c->Vc, &c->phi};
+  for (double** p : f1)
+    if ((st = big(p, n)) != HCA_OK) return st;
+  double** f3[] = {&c->F, &c->c, &c->b, &c->sb.r, &c->sb.z, &c->sb.p0, &c->sb.p1, &c->sb.q};
+  for (double** p : f3)
+    if ((st = big(p, n3)) != HCA_OK) return st;
+  c->K = c->F;
+  c->G1 = c->F + n;
+  c->G2 = c->F + 2 * n;
+  c->sb.jacobi = c->use_mg ? 0 : 1;
+  if (!c->use_mg && (st = big(&c->sb.dinv, n3)) != HCA_OK) return st;
+  const size_t nwork = (size_t)std::max(c->sys3.ntiles, c->sys3.nflat);
   HIPCHK(c, dalloc(&c->sb.partial, 3 * nwork));
-  HIPCHK(c, dalloc(&c->sb.counter, c->nreps));
-  HIPCHK(c, hipMemset(c->sb.counter, 0, sizeof(unsigned) * c->nreps));
-  HIPCHK(c, dalloc(&c->sb.ss, c->nreps));
-  HIPCHK(c, hipMemset(c->sb.ss, 0, sizeof(SolveScal) * c->nreps));
+  HIPCHK(c, dalloc(&c->sb.counter, nsys));
+  HIPCHK(c, hipMemset(c->sb.counter, 0, sizeof(unsigned) * nsys));
+  HIPCHK(c, dalloc(&c->sb.ss, nsys));
+  HIPCHK(c, hipMemset(c->sb.ss, 0, sizeof(SolveScal) * nsys));
   HIPCHK(c, dalloc(&c->sb.ndone, 1));
   HIPCHK(c, dalloc(&c->dose_t, (size_t)c->nreps * 2 * HCA_MAX_DOSES));
   HIPCHK(c, dalloc(&c->dose_a, (size_t)c->nreps * 2 * HCA_MAX_DOSES));
@@ -584,12 +667,12 @@ hca_status alloc_all(hca_ctx* c) {
   HIPCHK(c, dalloc(&c->d_bad, 1));
   const double* fl[6] = {c->K, c->G1, c->G2, c->P, c->Vc, c->phi};
   HIPCHK(c, hipMemcpy(c->d_fields, fl, sizeof fl, hipMemcpyHostToDevice));
-  HIPCHK(c, hipHostMalloc((void**)&c->h_ss, sizeof(SolveScal) * c->nreps, hipHostMallocDefault));
+  HIPCHK(c, hipHostMalloc((void**)&c->h_ss, sizeof(SolveScal) * nsys, hipHostMallocDefault));
   HIPCHK(c, hipHostMalloc((void**)&c->h_cnt, sizeof(Counters) * c->nreps, hipHostMallocDefault));
-  c->sb.jacobi = c->use_mg ? 0 : 1;
-  if (!c->use_mg) HIPCHK(c, dalloc(&c->sb.dinv, n));
   return HCA_OK;
 }
+
+// ---- multigrid hierarchy -------------------------------------------------------
 
 template <typename T>
 hca_status mg_alloc(hca_ctx* c, T** p, size_t count) {
@@ -608,22 +691,23 @@ hca_status mg_upload(hca_ctx* c, T** p, const std::vector<T>& v) {
   return HCA_OK;
 }
 
-// Multigrid hierarchy of every replicate: level dims (ceil halving down to one
-// cell, at least two levels), the first level handed to the one-workgroup
-// coarse solve (kc: <= mg_coarse_max cells and its LDS block fits in 64 KiB),
-// level arrays, per-level work tables and the coarse-solve descriptors.
+// Hierarchy of every system (field-major, like the solver tables): level
+// dims by ceil halving down to one cell (at least two levels); kc, the first
+// level handed to the one-workgroup coarse solve (<= mg_coarse_max cells and
+// its LDS block within 64 KiB); level arrays, per-level tiles, coarse-solve
+// descriptors.  mg1 is the oxygen prefix (the first nreps systems) of mg3.
 hca_status build_mg(hca_ctx* c) {
   const int R = c->nreps;
+  const int S = 3 * R;
   constexpr size_t kLdsCap = 65536;
+  auto cells = [](const std::array<int, 3>& a) { return (long long)a[0] * a[1] * a[2]; };
   std::vector<std::vector<std::array<int, 3>>> dims(R);
-  std::vector<int> kc(R, 1);
-  int nglob = 1;
+  std::vector<int> kcr(R, 1);
   for (int r = 0; r < R; ++r) {
     auto& d = dims[r];
     d.push_back({c->reps[r].nx, c->reps[r].ny, c->reps[r].nz});
-    auto cells = [](const std::array<int, 3>& a) { return (long long)a[0] * a[1] * a[2]; };
     while (cells(d.back()) > 1 || d.size() < 2) {
-      const auto& b = d.back();
+      const auto b = d.back();
       d.push_back({(b[0] + 1) / 2, (b[1] + 1) / 2, (b[2] + 1) / 2});
       if ((int)d.size() > kMaxLevels) return fail(c, HCA_E_INVALID, "lattice too large for multigrid");
     }
@@ -633,53 +717,65 @@ hca_status build_mg(hca_ctx* c) {
       const long long n = cells(d[k]);
       if (n <= c->prm.mg_coarse_max && n <= (long long)kCoarseThreads * kCoarseMaxCellsPerThread &&
           lds <= kLdsCap) {
-        kc[r] = k;
+        kcr[r] = k;
         break;
       }
     }
-    nglob = std::max(nglob, kc[r]);
   }
-  MgBufs& mg = c->mg;
+  int nglob = 1;
+  for (int r = 0; r < R; ++r) nglob = std::max(nglob, kcr[r]);
+  std::vector<RepDev> sd(S);
+  HIPCHK(c, hipMemcpy(sd.data(), c->d_sys, sizeof(RepDev) * S, hipMemcpyDeviceToHost));
+  MgBufs& mg = c->mg3;
   mg.nlev_glob = nglob;
   mg.omega = 0.8f;
-  // level 0 shares the CG's tiles and replicate offsets
+  c->mg1 = mg;
   std::vector<float*> pc(kMaxLevels, nullptr), pr(kMaxLevels, nullptr), pu(kMaxLevels, nullptr);
-  std::vector<RepDev> rd(R);
-  HIPCHK(c, hipMemcpy(rd.data(), c->d_reps, sizeof(RepDev) * R, hipMemcpyDeviceToHost));
+  std::vector<std::vector<MgRep>> mreps(nglob + 1);
   for (int k = 0; k <= nglob; ++k) {
-    std::vector<MgRep> mr(R);
+    std::vector<MgRep>& mr = mreps[k];
+    mr.resize(S);
     std::vector<Tile> tiles, rtiles;
+    int ntiles1 = 0, nrtiles1 = 0;
     long long off = 0;
-    for (int r = 0; r < R; ++r) {
-      MgRep& m = mr[r];
+    for (int s = 0; s < S; ++s) {
+      const int r = s % R;
+      MgRep& m = mr[s];
       memset(&m, 0, sizeof m);
       m.k = k;
       m.n0x = dims[r][0][0];
       m.n0y = dims[r][0][1];
       m.n0z = dims[r][0][2];
-      if (k >= (int)dims[r].size() || k > kc[r]) continue;
-      m.nx = dims[r][k][0];
-      m.ny = dims[r][k][1];
-      m.nz = dims[r][k][2];
-      m.active = k < kc[r];
-      m.tx = k == 0 ? rd[r].tx : pick_tx(m.nx);
-      if (k == 0) {
-        m.off = c->reps[r].off;
-        m.tile_b0 = rd[r].tile_b0;
-        m.tile_nb = rd[r].tile_nb;
-        continue;
+      m.a = (float)sd[s].a;
+      if (k < (int)dims[r].size() && k <= kcr[r]) {
+        m.nx = dims[r][k][0];
+        m.ny = dims[r][k][1];
+        m.nz = dims[r][k][2];
+        m.active = k < kcr[r];
+        if (k == 0) {
+          m.tx = sd[s].tx;
+          m.off = sd[s].off;
+          m.tile_b0 = sd[s].tile_b0;
+          m.tile_nb = sd[s].tile_nb;
+        } else {
+          m.tx = pick_tx(m.nx);
+          m.off = off;
+          off += (long long)m.nx * m.ny * m.nz;
+          const int tz = pick_tz(m.nx, m.ny, m.nz, m.tx, kTileTarget);
+          if (m.active) {
+            m.tile_b0 = (int)tiles.size();
+            add_tiles(tiles, s, m.nx, m.ny, m.nz, m.tx, tz);
+            m.tile_nb = (int)tiles.size() - m.tile_b0;
+          }
+          m.rtile_b0 = (int)rtiles.size();
+          add_tiles(rtiles, s, m.nx, m.ny, m.nz, m.tx, tz);
+          m.rtile_nb = (int)rtiles.size() - m.rtile_b0;
+        }
       }
-      m.off = off;
-      off += (long long)m.nx * m.ny * m.nz;
-      const int tz = pick_tz(m.nx, m.ny, m.nz, m.tx, kTileTarget);
-      if (m.active) {
-        m.tile_b0 = (int)tiles.size();
-        add_tiles(tiles, r, m.nx, m.ny, m.nz, m.tx, tz);
-        m.tile_nb = (int)tiles.size() - m.tile_b0;
+      if (s == R - 1) {
+        ntiles1 = (int)tiles.size();
+        nrtiles1 = (int)rtiles.size();
       }
-      m.rtile_b0 = (int)rtiles.size();
-      add_tiles(rtiles, r, m.nx, m.ny, m.nz, m.tx, tz);
-      m.rtile_nb = (int)rtiles.size() - m.rtile_b0;
     }
     MgLevel& L = mg.lev[k];
     MgRep* d_mr = nullptr;
@@ -687,9 +783,10 @@ hca_status build_mg(hca_ctx* c) {
     if (st != HCA_OK) return st;
     L.reps = d_mr;
     if (k == 0) {
-      L.tiles = c->d_tiles;
-      L.ntiles = c->work.ntiles;
-      const size_t n = (size_t)c->ntot;
+      L.tiles = c->d_stiles;
+      L.ntiles = c->sys3.ntiles;
+      ntiles1 = c->sys1.ntiles;
+      const size_t n = 3 * (size_t)c->ntot;
       if ((st = mg_alloc(c, &L.dinv, n)) != HCA_OK || (st = mg_alloc(c, &L.u, n)) != HCA_OK ||
           (st = mg_alloc(c, &L.ualt, n)) != HCA_OK)
         return st;
@@ -711,52 +808,62 @@ hca_status build_mg(hca_ctx* c) {
       pr[k] = L.r;
       pu[k] = L.u;
     }
+    c->mg1.lev[k] = L;
+    c->mg1.lev[k].ntiles = ntiles1;
+    c->mg1.lev[k].nrtiles = k == 0 ? 0 : nrtiles1;
   }
+  int nglob1 = 1;
+  for (int r = 0; r < R; ++r) nglob1 = std::max(nglob1, kcr[r]);
+  c->mg1.nlev_glob = nglob1;
   // coarse-solve descriptors
-  std::vector<MgCoarseRep> cr(R);
+  std::vector<MgCoarseRep> cr(S);
   size_t lds_max = 0;
-  for (int r = 0; r < R; ++r) {
-    MgCoarseRep& d = cr[r];
+  for (int s = 0; s < S; ++s) {
+    const int r = s % R;
+    MgCoarseRep& d = cr[s];
     memset(&d, 0, sizeof d);
-    d.kc = kc[r];
-    d.nlev = (int)dims[r].size() - kc[r];
+    d.kc = kcr[r];
+    d.nlev = (int)dims[r].size() - kcr[r];
+    d.a = (float)sd[s].a;
     for (int i = 0; i < 3; ++i) d.n0[i] = dims[r][0][i];
     int o = 0;
     for (int j = 0; j < d.nlev; ++j) {
-      for (int i = 0; i < 3; ++i) d.dims[j][i] = dims[r][kc[r] + j][i];
+      for (int i = 0; i < 3; ++i) d.dims[j][i] = dims[r][kcr[r] + j][i];
       d.lds_off[j] = o;
       o += 3 * d.dims[j][0] * d.dims[j][1] * d.dims[j][2];
     }
     lds_max = std::max(lds_max, (size_t)o * sizeof(float));
-    std::vector<MgRep> mr(R);
-    HIPCHK(c, hipMemcpy(mr.data(), mg.lev[kc[r]].reps, sizeof(MgRep) * R, hipMemcpyDeviceToHost));
-    d.off_kc = mr[r].off;
+    d.off_kc = mreps[kcr[r]][s].off;
   }
   MgCoarseRep* dcr = nullptr;
   hca_status st = mg_upload(c, &dcr, cr);
   if (st != HCA_OK) return st;
   mg.coarse = dcr;
   mg.coarse_lds_bytes = (int)lds_max;
-  std::vector<float*> vc(pc), vr(pr), vu(pu);
-  if ((st = mg_upload(c, &mg.lev_c, vc)) != HCA_OK || (st = mg_upload(c, &mg.lev_r, vr)) != HCA_OK ||
-      (st = mg_upload(c, &mg.lev_u, vu)) != HCA_OK)
+  if ((st = mg_upload(c, &mg.lev_c, pc)) != HCA_OK || (st = mg_upload(c, &mg.lev_r, pr)) != HCA_OK ||
+      (st = mg_upload(c, &mg.lev_u, pu)) != HCA_OK)
     return st;
+  c->mg1.coarse = mg.coarse;
+  c->mg1.coarse_lds_bytes = mg.coarse_lds_bytes;
+  c->mg1.lev_c = mg.lev_c;
+  c->mg1.lev_r = mg.lev_r;
+  c->mg1.lev_u = mg.lev_u;
   return HCA_OK;
 }
 
 // Algorithm 1, steady oxygen: Picard on the uptake coefficient, each iterate
-// one CG solve; stops when the nonlinear residual of the current iterate
-// (the solve's initial residual) is below init_rtol ||b||.
+// one CG solve of the oxygen systems; stops when the nonlinear residual of the
+// current iterate (the solve's initial residual) is below init_rtol ||b||.
 hca_status steady_oxygen(hca_ctx* c) {
   const Work& wk = c->work;
-  // K^(0) = K0
   std::vector<double> k0((size_t)c->ntot, c->prm.K0);
   HIPCHK(c, hipMemcpyAsync(c->K, k0.data(), k0.size() * sizeof(double), hipMemcpyHostToDevice,
                            c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   for (int m = 0; m < c->prm.init_maxit; ++m) {
     launch_setup_o2(c->stream, wk, c->dp, c->L, c->w, c->K, c->c, c->b, 1);
-    launch_cg_start(c->stream, wk, c->dp.aK, c->prm.init_rtol, c->prm.cg_maxit, c->c, c->b, c->K,
-                    c->sb);
+    launch_cg_start(c->stream, c->sys1, c->prm.init_rtol, c->prm.cg_maxit, c->c, c->b, c->F,
+                    c->sb, 1u, c->nreps);
     HIPCHK(c, hipMemcpyAsync(c->h_ss, c->sb.ss, sizeof(SolveScal) * c->nreps,
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -766,18 +873,18 @@ hca_status steady_oxygen(hca_ctx* c) {
       c->picard_iters = m;
       return HCA_OK;
     }
-    hca_status st = solve(c, 0, c->dp.aK, c->prm.cg_rtol, c->prm.cg_maxit, c->K, nullptr);
+    hca_status st = solve(c, c->sys1, c->mg1, 1u, c->prm.cg_rtol, c->prm.cg_maxit, 1);
     if (st != HCA_OK) return st;
   }
   return fail(c, HCA_E_NOCONV, "steady oxygen Picard iteration did not converge");
 }
 
 void free_all(hca_ctx* c) {
-  void* bufs[] = {c->L, c->code, c->win, c->w, c->K, c->G1, c->G2, c->P, c->Vc, c->phi, c->c,
-                  c->b, c->sb.r, c->sb.z, c->sb.p0, c->sb.p1, c->sb.q, c->sb.partial,
+  void* bufs[] = {c->L, c->code, c->win, c->w, c->P, c->Vc, c->phi, c->F, c->c, c->b,
+                  c->sb.r, c->sb.z, c->sb.p0, c->sb.p1, c->sb.q, c->sb.dinv, c->sb.partial,
                   c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->d_step,
-                  c->d_reps, c->d_flat, c->d_tiles, c->d_cnt, (void*)c->d_fields, c->d_bad,
-                  c->sb.dinv};
+                  c->d_reps, c->d_flat, c->d_tiles, c->d_sys, c->d_sflat, c->d_stiles, c->d_cnt,
+                  (void*)c->d_fields, c->d_bad};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   for (void* p : c->mg_mem)
@@ -846,7 +953,7 @@ hca_status hca_default_params(hca_params* out) {
   out->cg_rtol = 1.0e-10;
   out->cg_maxit = 2000;
   out->mg_smooth = 2;
-  out->mg_coarse_max = 4096;
+  out->mg_coarse_max = 512;
   out->init_rtol = 1.0e-10;
   out->init_maxit = 200;
   out->profile = 0;
@@ -890,11 +997,9 @@ hca_status hca_init(hca_ctx** out, const hca_params* p, const hca_replicate* rep
   }
   c->ntot = off;
   auto bail = [&](hca_status s) {
-    if (c) {
-      if (!c->err.empty()) fprintf(stderr, "hca_init: %s\n", c->err.c_str());
-      free_all(c);
-      delete c;
-    }
+    if (!c->err.empty()) fprintf(stderr, "hca_init: %s\n", c->err.c_str());
+    free_all(c);
+    delete c;
     return s;
   };
   if (hipGetDevice(&c->device) != hipSuccess) return bail(HCA_E_DEVICE);
@@ -905,31 +1010,24 @@ hca_status hca_init(hca_ctx** out, const hca_params* p, const hca_replicate* rep
       return bail(HCA_E_DEVICE);
     c->own_stream = true;
   }
-  if ((st = build_tables(c)) != HCA_OK) return bail(st);
+  if ((st = build_tables(c, reps)) != HCA_OK) return bail(st);
   if ((st = alloc_all(c)) != HCA_OK) return bail(st);
   if (c->use_mg && (st = build_mg(c)) != HCA_OK) return bail(st);
   // upload inputs and dose tables
   std::vector<double> dt((size_t)n_reps * 2 * HCA_MAX_DOSES, 0.0), da(dt.size(), 0.0);
-  std::vector<RepDev> rd(n_reps);
-  if (hipMemcpy(rd.data(), c->d_reps, sizeof(RepDev) * n_reps, hipMemcpyDeviceToHost) != hipSuccess)
-    return bail(HCA_E_DEVICE);
   for (int r = 0; r < n_reps; ++r) {
     const RepHost& R = c->reps[r];
     if (hipMemcpy(c->L + R.off, reps[r].cell, (size_t)R.n, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->w + R.off, reps[r].vessel_w, (size_t)R.n * 8, hipMemcpyHostToDevice) !=
             hipSuccess)
       return bail(HCA_E_DEVICE);
-    for (int d = 0; d < 2; ++d) {
-      rd[r].ndose[d] = reps[r].n_doses[d];
+    for (int d = 0; d < 2; ++d)
       for (int k = 0; k < reps[r].n_doses[d]; ++k) {
         dt[(size_t)r * 2 * HCA_MAX_DOSES + d * HCA_MAX_DOSES + k] = reps[r].dose_t_min[d][k];
         da[(size_t)r * 2 * HCA_MAX_DOSES + d * HCA_MAX_DOSES + k] = reps[r].dose_amt[d][k];
       }
-    }
   }
-  if (hipMemcpy(c->d_reps, rd.data(), sizeof(RepDev) * n_reps, hipMemcpyHostToDevice) !=
-          hipSuccess ||
-      hipMemcpy(c->dose_t, dt.data(), dt.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+  if (hipMemcpy(c->dose_t, dt.data(), dt.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->dose_a, da.data(), da.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
     return bail(HCA_E_DEVICE);
   long long zero = 0;
@@ -937,15 +1035,14 @@ hca_status hca_init(hca_ctx** out, const hca_params* p, const hca_replicate* rep
     return bail(HCA_E_DEVICE);
   if ((st = steady_oxygen(c)) != HCA_OK) return bail(st);
   launch_init_cells(c->stream, c->work, c->dp, c->L, c->K, c->P, c->Vc, c->phi);
-  if (hipMemsetAsync(c->G1, 0, (size_t)c->ntot * 8, c->stream) != hipSuccess ||
-      hipMemsetAsync(c->G2, 0, (size_t)c->ntot * 8, c->stream) != hipSuccess)
+  if (hipMemsetAsync(c->G1, 0, (size_t)c->ntot * 16, c->stream) != hipSuccess)   // G1 and G2
     return bail(HCA_E_DEVICE);
   launch_zero_counters(c->stream, c->d_cnt, n_reps, 1);
   launch_zero_counters(c->stream, c->d_cnt, n_reps, 0);
   launch_stats(c->stream, c->work, c->L, c->w, c->d_fields, 6, c->d_cnt);
   if (hipGetLastError() != hipSuccess) return bail(HCA_E_DEVICE);
   if ((st = check_after(c)) != HCA_OK) return bail(st);
-  for (int f = 0; f < 3; ++f) c->last_it[f] = 0;
+  c->last_it[0] = 0;
   for (int k = 0; k < KC_COUNT; ++k) c->prof_ms[k] = c->prof_n[k] = c->prof_bytes[k] = 0;
   *out = c;
   return HCA_OK;
@@ -1048,9 +1145,9 @@ hca_status hca_stats(hca_ctx* c, int rep, hca_stats_t* out) {
   out->lost = (int64_t)k.lost;
   out->total_divisions = (int64_t)k.total_divisions;
   out->total_kills = (int64_t)k.total_kills;
-  for (int f = 0; f < 3; ++f) {
-    if ((int)c->last_ss[f].size() > rep) {
-      const SolveScal& s = c->last_ss[f][rep];
+  if ((int)c->last_ss.size() == 3 * c->nreps) {
+    for (int f = 0; f < 3; ++f) {
+      const SolveScal& s = c->last_ss[f * c->nreps + rep];
       out->cg_iters[f] = s.it;
       out->cg_relres[f] = s.bb > 0 ? std::sqrt(s.rr / s.bb) : 0.0;
     }
@@ -1070,7 +1167,7 @@ const char* hca_kernel_name(int kernel) {
 hca_status hca_kernel_time(hca_ctx* c, int kernel, double* ms, int64_t* launches,
                            double* bytes_per_launch) {
   if (!c || kernel < 0 || kernel >= KC_COUNT) return HCA_E_INVALID;
-  prof_flush(c, 1 << 30);
+  prof_flush(c, nullptr, 0);
   if (ms) *ms = c->prof_ms[kernel];
   if (launches) *launches = c->prof_n[kernel];
   if (bytes_per_launch)
@@ -1080,7 +1177,7 @@ hca_status hca_kernel_time(hca_ctx* c, int kernel, double* ms, int64_t* launches
 
 hca_status hca_reset_kernel_time(hca_ctx* c) {
   if (!c) return HCA_E_INVALID;
-  prof_flush(c, 1 << 30);
+  prof_flush(c, nullptr, 0);
   for (int k = 0; k < KC_COUNT; ++k) c->prof_ms[k] = c->prof_n[k] = c->prof_bytes[k] = 0;
   return HCA_OK;
 }
