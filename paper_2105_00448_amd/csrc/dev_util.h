@@ -43,6 +43,17 @@ __device__ inline double block_max(double v, double* lds4) {
   return t;
 }
 
+// Persistent launches: G workgroups cover T work items in contiguous chunks.
+// Workgroups are dealt to the 8 XCDs round-robin, so logical block
+// lb = (b % 8) * (G / 8) + b / 8 gives each XCD one contiguous run of chunks
+// (neighbouring tiles, shared halos in that XCD's L2).
+__device__ inline void work_range(int T, int& begin, int& end) {
+  const int G = gridDim.x, b = blockIdx.x;
+  const int lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  begin = (int)((long long)lb * T / G);
+  end = (int)((long long)(lb + 1) * T / G);
+}
+
 // A workgroup's three partial sums, stored at its work-item slot (3 doubles);
 // a later reduce kernel (one workgroup per replicate) sums the slots of a
 // replicate in a fixed order.  The kernel boundary orders the two.

@@ -50,9 +50,10 @@ struct RepDev {
   double a;                   // systems: face coupling D/h^2 of the field
 };
 
-// Work item of the flat kernels: replicate and first chunk index.
+// Work item of the flat kernels: voxels [begin, end) of one lattice.
 struct FlatBlk {
-  int rep, first;
+  int rep, pad;
+  long long begin, end;
 };
 
 // Work item of the stencil kernels: a TX x TY column tile over [z0, z1).
@@ -92,7 +93,25 @@ struct Work {
   int nflat;
   const Tile* tiles;
   int ntiles;
+  int max_blocks;             // persistent grid size (multiple of 8)
 };
+
+// Launch shape of the work-item kernels (process-wide, set once from the
+// tuning knobs): with xcd_remap the grid is a multiple of 8 and work_range
+// deals each XCD one contiguous run of work items; otherwise the grid is not
+// a multiple of 8 and workgroup b takes run b.
+extern int g_xcd_remap;
+
+// Grid of a launch over n work items, at most max_blocks workgroups.
+inline int grid_for(int n, int max_blocks) {
+  int g = n < max_blocks ? n : max_blocks;
+  if (g < 1) g = 1;
+  if (g_xcd_remap)
+    g = (g + 7) / 8 * 8;
+  else if (g % 8 == 0)
+    g += 1;
+  return g;
+}
 
 // ---- launchers (defined in the .hip files) --------------------------------
 // setup / init / plasma kinetics (k_setup.hip)

@@ -45,19 +45,23 @@ __device__ inline bool neighbour(const RepDev& rp, const VoxelCoord& v, int d, l
   return true;
 }
 
+// f(rep, replicate, local voxel index) over this workgroup's work items;
+// end_item(rep) after each item (per-replicate counter flushes).
+template <typename F, typename E>
+__device__ inline void for_each_voxel_ca(const Work& w, F f, E end_item) {
+  int b0, b1;
+  work_range(w.nflat, b0, b1);
+  for (int it = b0; it < b1; ++it) {
+    const FlatBlk fb = w.flat[it];
+    const RepDev rp = w.reps[fb.rep];
+    for (long long li = fb.begin + threadIdx.x; li < fb.end; li += kBlock) f(fb.rep, rp, li);
+    end_item(fb.rep);
+  }
+}
+
 template <typename F>
 __device__ inline void for_each_voxel_ca(const Work& w, F f) {
-  const FlatBlk fb = w.flat[blockIdx.x];
-  const RepDev rp = w.reps[fb.rep];
-  const long long nchunks = (rp.n + kFlatChunk - 1) / kFlatChunk;
-  for (long long ch = fb.first; ch < nchunks; ch += rp.flat_nb) {
-    const long long base = ch * kFlatChunk;
-#pragma unroll
-    for (int k = 0; k < kFlatChunk / kBlock; ++k) {
-      const long long li = base + k * kBlock + threadIdx.x;
-      if (li < rp.n) f(fb.rep, rp, li);
-    }
-  }
+  for_each_voxel_ca(w, f, [](int) {});
 }
 
 __device__ inline double kill_probability(double G, double Gref, int b) {
@@ -184,23 +188,24 @@ __global__ void __launch_bounds__(kBlock) k_ca_finalize(Work w, uint8_t* __restr
       P[i] = 0.0;
       Vc[i] = 0.0;
     }
+  }, [&](int rep) {
+    const unsigned long long a = block_sum_u64(n_com, lds4);
+    const unsigned long long b = block_sum_u64(n_kill, lds4);
+    const unsigned long long c = block_sum_u64(n_div, lds4);
+    const unsigned long long d = block_sum_u64(n_nosp, lds4);
+    const unsigned long long e = block_sum_u64(n_lost, lds4);
+    if (threadIdx.x == 0) {
+      Counters* cr = cnt + rep;
+      if (a) atomicAdd(&cr->committed, a);
+      if (b) atomicAdd(&cr->kills, b);
+      if (c) atomicAdd(&cr->divisions, c);
+      if (c) atomicAdd(&cr->total_divisions, c);
+      if (b) atomicAdd(&cr->total_kills, b);
+      if (d) atomicAdd(&cr->nospace, d);
+      if (e) atomicAdd(&cr->lost, e);
+    }
+    n_com = n_kill = n_div = n_nosp = n_lost = 0;
   });
-  const int rep = w.flat[blockIdx.x].rep;
-  const unsigned long long a = block_sum_u64(n_com, lds4);
-  const unsigned long long b = block_sum_u64(n_kill, lds4);
-  const unsigned long long c = block_sum_u64(n_div, lds4);
-  const unsigned long long d = block_sum_u64(n_nosp, lds4);
-  const unsigned long long e = block_sum_u64(n_lost, lds4);
-  if (threadIdx.x == 0) {
-    Counters* cr = cnt + rep;
-    if (a) atomicAdd(&cr->committed, a);
-    if (b) atomicAdd(&cr->kills, b);
-    if (c) atomicAdd(&cr->divisions, c);
-    if (c) atomicAdd(&cr->total_divisions, c);
-    if (b) atomicAdd(&cr->total_kills, b);
-    if (d) atomicAdd(&cr->nospace, d);
-    if (e) atomicAdd(&cr->lost, e);
-  }
 }
 
 // Cell-type counts and a non-finite scan of the listed fields.
@@ -218,21 +223,22 @@ __global__ void __launch_bounds__(kBlock) k_stats(Work w, const uint8_t* __restr
     ne += l == 0;
     nv += vw[i] != 0.0;
     for (int f = 0; f < nfields; ++f) bad += !isfinite(fields[f][i]);
+  }, [&](int rep) {
+    const unsigned long long a = block_sum_u64(nc, lds4);
+    const unsigned long long b = block_sum_u64(ns, lds4);
+    const unsigned long long c = block_sum_u64(ne, lds4);
+    const unsigned long long d = block_sum_u64(nv, lds4);
+    const unsigned long long e = block_sum_u64(bad, lds4);
+    if (threadIdx.x == 0) {
+      Counters* cr = cnt + rep;
+      if (a) atomicAdd(&cr->n_cancer, a);
+      if (b) atomicAdd(&cr->n_stroma, b);
+      if (c) atomicAdd(&cr->n_empty, c);
+      if (d) atomicAdd(&cr->n_vessel, d);
+      if (e) atomicAdd(&cr->nonfinite, e);
+    }
+    nc = ns = ne = nv = bad = 0;
   });
-  const int rep = w.flat[blockIdx.x].rep;
-  const unsigned long long a = block_sum_u64(nc, lds4);
-  const unsigned long long b = block_sum_u64(ns, lds4);
-  const unsigned long long c = block_sum_u64(ne, lds4);
-  const unsigned long long d = block_sum_u64(nv, lds4);
-  const unsigned long long e = block_sum_u64(bad, lds4);
-  if (threadIdx.x == 0) {
-    Counters* cr = cnt + rep;
-    if (a) atomicAdd(&cr->n_cancer, a);
-    if (b) atomicAdd(&cr->n_stroma, b);
-    if (c) atomicAdd(&cr->n_empty, c);
-    if (d) atomicAdd(&cr->n_vessel, d);
-    if (e) atomicAdd(&cr->nonfinite, e);
-  }
 }
 
 // Zero the event counters (events_only) or the state counters.  A kernel,
@@ -254,10 +260,9 @@ __global__ void k_advance(long long* d_step) { d_step[0] += 1; }
 __global__ void __launch_bounds__(kBlock) k_validate_cells(Work w, const uint8_t* __restrict__ L,
                                                            const double* __restrict__ vw, int rep,
                                                            unsigned long long* bad) {
-  const FlatBlk fb = w.flat[blockIdx.x];
-  if (fb.rep != rep) return;
   unsigned long long nb = 0;
-  for_each_voxel_ca(w, [&](int, const RepDev& rp, long long li) {
+  for_each_voxel_ca(w, [&](int r, const RepDev& rp, long long li) {
+    if (r != rep) return;
     const long long i = rp.off + li;
     const uint8_t l = L[i];
     nb += (l > 2) || (l != 0 && vw[i] != 0.0);
@@ -269,24 +274,24 @@ __global__ void __launch_bounds__(kBlock) k_validate_cells(Work w, const uint8_t
 void launch_ca_propose(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
                        const uint8_t* L, const double* vw, const double* K, const double* G1,
                        const double* G2, const double* phi, uint8_t* code) {
-  hipLaunchKernelGGL(k_ca_propose, dim3(w.nflat), dim3(kBlock), 0, s, w, p, d_step, L, vw, K, G1,
+  hipLaunchKernelGGL(k_ca_propose, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, d_step, L, vw, K, G1,
                      G2, phi, code);
 }
 
 void launch_ca_resolve(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
                        const double* phi, const uint8_t* code, uint8_t* win) {
-  hipLaunchKernelGGL(k_ca_resolve, dim3(w.nflat), dim3(kBlock), 0, s, w, L, vw, phi, code, win);
+  hipLaunchKernelGGL(k_ca_resolve, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, vw, phi, code, win);
 }
 
 void launch_ca_finalize(hipStream_t s, const Work& w, uint8_t* L, double* phi, double* P,
                         double* Vc, const uint8_t* code, const uint8_t* win, Counters* cnt) {
-  hipLaunchKernelGGL(k_ca_finalize, dim3(w.nflat), dim3(kBlock), 0, s, w, L, phi, P, Vc, code, win,
+  hipLaunchKernelGGL(k_ca_finalize, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, phi, P, Vc, code, win,
                      cnt);
 }
 
 void launch_stats(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
                   const double* const* fields, int nfields, Counters* cnt) {
-  hipLaunchKernelGGL(k_stats, dim3(w.nflat), dim3(kBlock), 0, s, w, L, vw, fields, nfields, cnt);
+  hipLaunchKernelGGL(k_stats, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, vw, fields, nfields, cnt);
 }
 
 void launch_zero_counters(hipStream_t s, Counters* cnt, int nreps, int events_only) {
@@ -300,7 +305,7 @@ void launch_advance(hipStream_t s, long long* d_step) {
 
 void launch_validate_cells(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
                            int rep, unsigned long long* bad) {
-  hipLaunchKernelGGL(k_validate_cells, dim3(w.nflat), dim3(kBlock), 0, s, w, L, vw, rep, bad);
+  hipLaunchKernelGGL(k_validate_cells, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, vw, rep, bad);
 }
 
 }  // namespace hca

@@ -117,8 +117,8 @@ struct TileXY {
   bool valid;
 };
 
-__device__ inline TileXY tile_xy(const Tile* tiles, const MgRep* reps) {
-  const Tile t = tiles[blockIdx.x];
+__device__ inline TileXY tile_xy(const Tile* tiles, const MgRep* reps, int ti) {
+  const Tile t = tiles[ti];
   const MgRep& m = reps[t.rep];
   TileXY c;
   c.rep = t.rep;
@@ -130,48 +130,58 @@ __device__ inline TileXY tile_xy(const Tile* tiles, const MgRep* reps) {
   return c;
 }
 
+// Every kernel below loops over its workgroup's contiguous run of tiles.
+#define FOR_MY_TILES(ntiles)   \
+  int tile_b_, tile_e_;        \
+  work_range((ntiles), tile_b_, tile_e_); \
+  for (int ti = tile_b_; ti < tile_e_; ++ti)
+
 // ---- setup per solve -------------------------------------------------------
 
 // Level 0: Dinv = 1 / (c + a deg).
 __global__ void __launch_bounds__(kBlock) k_mg_prep0(MgLevel L0, const double* __restrict__ c) {
-  const TileXY t = tile_xy(L0.tiles, L0.reps);
-  if (!t.valid) return;
-  const MgRep m = L0.reps[t.rep];
-  const Geo<true> G = geo_of<true>(m);
-  long long i = m.off + t.x + (long long)m.nx * (t.y + (long long)m.ny * t.z0);
-  const long long plane = (long long)m.nx * m.ny;
-  for (int z = t.z0; z < t.z1; ++z, i += plane)
-    L0.dinv[i] = (float)(1.0 / (c[i] + (double)G.gsum(t.x, t.y, z)));
+  FOR_MY_TILES(L0.ntiles) {
+    const TileXY t = tile_xy(L0.tiles, L0.reps, ti);
+    if (!t.valid) continue;
+    const MgRep m = L0.reps[t.rep];
+    const Geo<true> G = geo_of<true>(m);
+    long long i = m.off + t.x + (long long)m.nx * (t.y + (long long)m.ny * t.z0);
+    const long long plane = (long long)m.nx * m.ny;
+    for (int z = t.z0; z < t.z1; ++z, i += plane)
+      L0.dinv[i] = (float)(1.0 / (c[i] + (double)G.gsum(t.x, t.y, z)));
+  }
 }
 
 // Level k+1 from level k: c_{k+1} = sum of the children's c, Dinv_{k+1}.
 template <bool FROM0>
 __global__ void __launch_bounds__(kBlock) k_mg_coarsen(MgLevel Lf, MgLevel Lc,
                                                        const double* __restrict__ c0) {
-  const TileXY t = tile_xy(Lc.rtiles, Lc.reps);
-  if (!t.valid) return;
-  const MgRep mc = Lc.reps[t.rep];
-  const MgRep mf = Lf.reps[t.rep];
-  const Geo<false> G = geo_of<false>(mc);
-  for (int Z = t.z0; Z < t.z1; ++Z) {
-    float s = 0.f;
-    for (int dz = 0; dz < 2; ++dz) {
-      const int z = 2 * Z + dz;
-      if (z >= mf.nz) break;
-      for (int dy = 0; dy < 2; ++dy) {
-        const int y = 2 * t.y + dy;
-        if (y >= mf.ny) break;
-        for (int dx = 0; dx < 2; ++dx) {
-          const int x = 2 * t.x + dx;
-          if (x >= mf.nx) break;
-          const long long j = mf.off + x + (long long)mf.nx * (y + (long long)mf.ny * z);
-          s += FROM0 ? (float)c0[j] : Lf.c[j];
+  FOR_MY_TILES(Lc.nrtiles) {
+    const TileXY t = tile_xy(Lc.rtiles, Lc.reps, ti);
+    if (!t.valid) continue;
+    const MgRep mc = Lc.reps[t.rep];
+    const MgRep mf = Lf.reps[t.rep];
+    const Geo<false> G = geo_of<false>(mc);
+    for (int Z = t.z0; Z < t.z1; ++Z) {
+      float s = 0.f;
+      for (int dz = 0; dz < 2; ++dz) {
+        const int z = 2 * Z + dz;
+        if (z >= mf.nz) break;
+        for (int dy = 0; dy < 2; ++dy) {
+          const int y = 2 * t.y + dy;
+          if (y >= mf.ny) break;
+          for (int dx = 0; dx < 2; ++dx) {
+            const int x = 2 * t.x + dx;
+            if (x >= mf.nx) break;
+            const long long j = mf.off + x + (long long)mf.nx * (y + (long long)mf.ny * z);
+            s += FROM0 ? (float)c0[j] : Lf.c[j];
+          }
         }
       }
+      const long long I = mc.off + t.x + (long long)mc.nx * (t.y + (long long)mc.ny * Z);
+      Lc.c[I] = s;
+      Lc.dinv[I] = 1.f / (s + G.gsum(t.x, t.y, Z));
     }
-    const long long I = mc.off + t.x + (long long)mc.nx * (t.y + (long long)mc.ny * Z);
-    Lc.c[I] = s;
-    Lc.dinv[I] = 1.f / (s + G.gsum(t.x, t.y, Z));
   }
 }
 
@@ -180,16 +190,18 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarsen(MgLevel Lf, MgLevel Lc,
 template <bool L0, typename RT>
 __global__ void __launch_bounds__(kBlock) k_mg_pre(MgLevel Lk, float omega,
                                                    const RT* __restrict__ r, const SolveScal* ss) {
-  const TileXY t = tile_xy(Lk.tiles, Lk.reps);
-  if (ss[t.rep].done || !t.valid) return;
-  const MgRep m = Lk.reps[t.rep];
-  const Geo<L0> G = geo_of<L0>(m);
   const float* __restrict__ dinv = Lk.dinv;
   float* __restrict__ u = Lk.u;
-  auto U1 = [&](int, int, int, long long j) { return omega * dinv[j] * (float)r[j]; };
-  mg_column(G, t.x, t.y, t.z0, t.z1, m.off, U1, [&](int, long long i, float u1, float s) {
-    u[i] = (1.f - omega) * u1 + omega * dinv[i] * ((float)r[i] + s);
-  });
+  FOR_MY_TILES(Lk.ntiles) {
+    const TileXY t = tile_xy(Lk.tiles, Lk.reps, ti);
+    if (ss[t.rep].done || !t.valid) continue;
+    const MgRep m = Lk.reps[t.rep];
+    const Geo<L0> G = geo_of<L0>(m);
+    auto U1 = [&](int, int, int, long long j) { return omega * dinv[j] * (float)r[j]; };
+    mg_column(G, t.x, t.y, t.z0, t.z1, m.off, U1, [&](int, long long i, float u1, float s) {
+      u[i] = (1.f - omega) * u1 + omega * dinv[i] * ((float)r[i] + s);
+    });
+  }
 }
 
 // residual of level k at (x, y, z): r - A u = r - u/Dinv + sum g u_J
@@ -210,77 +222,84 @@ template <bool L0, typename RT>
 __global__ void __launch_bounds__(kBlock) k_mg_restrict(MgLevel Lf, MgLevel Lc,
                                                         const RT* __restrict__ r,
                                                         const SolveScal* ss) {
-  const TileXY t = tile_xy(Lc.rtiles, Lc.reps);
-  if (ss[t.rep].done || !t.valid) return;
-  const MgRep mc = Lc.reps[t.rep];
-  const MgRep mf = Lf.reps[t.rep];
-  const Geo<L0> G = geo_of<L0>(mf);
-  for (int Z = t.z0; Z < t.z1; ++Z) {
-    float s = 0.f;
-    for (int dz = 0; dz < 2; ++dz) {
-      const int z = 2 * Z + dz;
-      if (z >= mf.nz) break;
-      for (int dy = 0; dy < 2; ++dy) {
-        const int y = 2 * t.y + dy;
-        if (y >= mf.ny) break;
-        for (int dx = 0; dx < 2; ++dx) {
-          const int x = 2 * t.x + dx;
-          if (x >= mf.nx) break;
-          s += level_residual(G, mf.off, x, y, z, r, Lf.dinv, Lf.u);
+  FOR_MY_TILES(Lc.nrtiles) {
+    const TileXY t = tile_xy(Lc.rtiles, Lc.reps, ti);
+    if (ss[t.rep].done || !t.valid) continue;
+    const MgRep mc = Lc.reps[t.rep];
+    const MgRep mf = Lf.reps[t.rep];
+    const Geo<L0> G = geo_of<L0>(mf);
+    for (int Z = t.z0; Z < t.z1; ++Z) {
+      float s = 0.f;
+      for (int dz = 0; dz < 2; ++dz) {
+        const int z = 2 * Z + dz;
+        if (z >= mf.nz) break;
+        for (int dy = 0; dy < 2; ++dy) {
+          const int y = 2 * t.y + dy;
+          if (y >= mf.ny) break;
+          for (int dx = 0; dx < 2; ++dx) {
+            const int x = 2 * t.x + dx;
+            if (x >= mf.nx) break;
+            s += level_residual(G, mf.off, x, y, z, r, Lf.dinv, Lf.u);
+          }
         }
       }
+      Lc.r[mc.off + t.x + (long long)mc.nx * (t.y + (long long)mc.ny * Z)] = s;
     }
-    Lc.r[mc.off + t.x + (long long)mc.nx * (t.y + (long long)mc.ny * Z)] = s;
   }
 }
 
 template <bool L0, typename RT>
 __global__ void __launch_bounds__(kBlock) k_mg_post1(MgLevel Lk, MgLevel Lc, float omega,
                                                      const RT* __restrict__ r, const SolveScal* ss) {
-  const TileXY t = tile_xy(Lk.tiles, Lk.reps);
-  if (ss[t.rep].done || !t.valid) return;
-  const MgRep m = Lk.reps[t.rep];
-  const MgRep mc = Lc.reps[t.rep];
-  const Geo<L0> G = geo_of<L0>(m);
   const float* __restrict__ dinv = Lk.dinv;
   const float* __restrict__ u = Lk.u;
   const float* __restrict__ e = Lc.u;
   float* __restrict__ out = Lk.ualt;
-  auto U3 = [&](int x, int y, int z, long long j) {
-    return u[j] + e[mc.off + (x >> 1) + (long long)mc.nx * ((y >> 1) + (long long)mc.ny * (z >> 1))];
-  };
-  mg_column(G, t.x, t.y, t.z0, t.z1, m.off, U3, [&](int, long long i, float u3, float s) {
-    out[i] = (1.f - omega) * u3 + omega * dinv[i] * ((float)r[i] + s);
-  });
+  FOR_MY_TILES(Lk.ntiles) {
+    const TileXY t = tile_xy(Lk.tiles, Lk.reps, ti);
+    if (ss[t.rep].done || !t.valid) continue;
+    const MgRep m = Lk.reps[t.rep];
+    const MgRep mc = Lc.reps[t.rep];
+    const Geo<L0> G = geo_of<L0>(m);
+    auto U3 = [&](int x, int y, int z, long long j) {
+      return u[j] + e[mc.off + (x >> 1) + (long long)mc.nx * ((y >> 1) + (long long)mc.ny * (z >> 1))];
+    };
+    mg_column(G, t.x, t.y, t.z0, t.z1, m.off, U3, [&](int, long long i, float u3, float s) {
+      out[i] = (1.f - omega) * u3 + omega * dinv[i] * ((float)r[i] + s);
+    });
+  }
 }
 
 template <bool L0, typename RT>
 __global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float omega,
                                                      const RT* __restrict__ r, SolverBufs sb) {
   __shared__ double lds4[4];
-  const TileXY t = tile_xy(Lk.tiles, Lk.reps);
-  if (sb.ss[t.rep].done) return;
-  const MgRep m = Lk.reps[t.rep];
-  const Geo<L0> G = geo_of<L0>(m);
   const float* __restrict__ dinv = Lk.dinv;
   const float* __restrict__ u = Lk.ualt;
-  double rz = 0.0;
-  if (t.valid) {
-    auto U4 = [&](int, int, int, long long j) { return u[j]; };
-    mg_column(G, t.x, t.y, t.z0, t.z1, m.off, U4, [&](int, long long i, float u4, float s) {
-      const float u5 = (1.f - omega) * u4 + omega * dinv[i] * ((float)r[i] + s);
-      if (L0) {
-        sb.z[i] = (double)u5;
-        rz += (double)r[i] * (double)u5;
-      } else {
-        Lk.u[i] = u5;
-      }
-    });
+  FOR_MY_TILES(Lk.ntiles) {
+    const TileXY t = tile_xy(Lk.tiles, Lk.reps, ti);
+    if (sb.ss[t.rep].done) continue;
+    const MgRep m = Lk.reps[t.rep];
+    const Geo<L0> G = geo_of<L0>(m);
+    double rz = 0.0;
+    if (t.valid) {
+      auto U4 = [&](int, int, int, long long j) { return u[j]; };
+      mg_column(G, t.x, t.y, t.z0, t.z1, m.off, U4, [&](int, long long i, float u4, float s) {
+        const float u5 = (1.f - omega) * u4 + omega * dinv[i] * ((float)r[i] + s);
+        if (L0) {
+          sb.z[i] = (double)u5;
+          rz += (double)r[i] * (double)u5;
+        } else {
+          Lk.u[i] = u5;
+        }
+      });
+    }
+    if (L0) {
+      // level 0: partial r.z of this tile (finished by the RED_RZ reduce)
+      rz = block_sum(rz, lds4);
+      store_partials(sb.partial + (size_t)ti * 3, rz, 0.0, 0.0);
+    }
   }
-  if (!L0) return;
-  // level 0: partial r.z of this workgroup (finished by the RED_RZ reduce)
-  rz = block_sum(rz, lds4);
-  store_partials(sb.partial + (size_t)blockIdx.x * 3, rz, 0.0, 0.0);
 }
 
 // ---- coarse levels: one workgroup per replicate, in LDS -----------------------
@@ -447,16 +466,16 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep*
 
 // ---- launchers -------------------------------------------------------------
 
-void launch_mg_prepare(hipStream_t s, const Work&, const MgBufs& mg, const double* c) {
+void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, const double* c) {
   if (mg.lev[0].ntiles)
-    hipLaunchKernelGGL(k_mg_prep0, dim3(mg.lev[0].ntiles), dim3(kBlock), 0, s, mg.lev[0], c);
+    hipLaunchKernelGGL(k_mg_prep0, dim3(grid_for(mg.lev[0].ntiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[0], c);
   for (int k = 0; k < mg.nlev_glob; ++k) {
     const MgLevel& Lc = mg.lev[k + 1];
     if (!Lc.nrtiles) continue;
     if (k == 0)
-      hipLaunchKernelGGL(k_mg_coarsen<true>, dim3(Lc.nrtiles), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
+      hipLaunchKernelGGL(k_mg_coarsen<true>, dim3(grid_for(Lc.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
     else
-      hipLaunchKernelGGL(k_mg_coarsen<false>, dim3(Lc.nrtiles), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
+      hipLaunchKernelGGL(k_mg_coarsen<false>, dim3(grid_for(Lc.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
   }
 }
 
@@ -471,11 +490,11 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_PRE0, 1);
-    hipLaunchKernelGGL((k_mg_pre<true, double>), dim3(L.ntiles), dim3(kBlock), 0, s, L, om,
+    hipLaunchKernelGGL((k_mg_pre<true, double>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
                        (const double*)sb.r, ss);
     H(MG_PRE0, 0);
     H(MG_RESTRICT0, 1);
-    hipLaunchKernelGGL((k_mg_restrict<true, double>), dim3(C.nrtiles), dim3(kBlock), 0, s, L, C,
+    hipLaunchKernelGGL((k_mg_restrict<true, double>), dim3(grid_for(C.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
                        (const double*)sb.r, ss);
     H(MG_RESTRICT0, 0);
   }
@@ -485,9 +504,9 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
       const MgLevel& L = mg.lev[k];
       const MgLevel& C = mg.lev[k + 1];
       if (!L.ntiles) continue;
-      hipLaunchKernelGGL((k_mg_pre<false, float>), dim3(L.ntiles), dim3(kBlock), 0, s, L, om,
+      hipLaunchKernelGGL((k_mg_pre<false, float>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
                          (const float*)L.r, ss);
-      hipLaunchKernelGGL((k_mg_restrict<false, float>), dim3(C.nrtiles), dim3(kBlock), 0, s, L, C,
+      hipLaunchKernelGGL((k_mg_restrict<false, float>), dim3(grid_for(C.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
                          (const float*)L.r, ss);
     }
     H(MG_DOWN, 0);
@@ -503,9 +522,9 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
       const MgLevel& L = mg.lev[k];
       const MgLevel& C = mg.lev[k + 1];
       if (!L.ntiles) continue;
-      hipLaunchKernelGGL((k_mg_post1<false, float>), dim3(L.ntiles), dim3(kBlock), 0, s, L, C, om,
+      hipLaunchKernelGGL((k_mg_post1<false, float>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, om,
                          (const float*)L.r, ss);
-      hipLaunchKernelGGL((k_mg_post2<false, float>), dim3(L.ntiles), dim3(kBlock), 0, s, L, om,
+      hipLaunchKernelGGL((k_mg_post2<false, float>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
                          (const float*)L.r, sb);
     }
     H(MG_UP, 0);
@@ -514,11 +533,11 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_POST1_0, 1);
-    hipLaunchKernelGGL((k_mg_post1<true, double>), dim3(L.ntiles), dim3(kBlock), 0, s, L, C, om,
+    hipLaunchKernelGGL((k_mg_post1<true, double>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, om,
                        (const double*)sb.r, ss);
     H(MG_POST1_0, 0);
     H(MG_POST2_0, 1);
-    hipLaunchKernelGGL((k_mg_post2<true, double>), dim3(L.ntiles), dim3(kBlock), 0, s, L, om,
+    hipLaunchKernelGGL((k_mg_post2<true, double>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
                        (const double*)sb.r, sb);
     H(MG_POST2_0, 0);
     launch_cg_reduce(s, w, sb, RED_RZ, 0.0, 0);

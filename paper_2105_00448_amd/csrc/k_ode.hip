@@ -37,16 +37,14 @@ __global__ void __launch_bounds__(kBlock) k_ode(Work w, DevParams p, const uint8
                                                 double* __restrict__ P,
                                                 double* __restrict__ Vc,
                                                 double* __restrict__ phi) {
-  const FlatBlk fb = w.flat[blockIdx.x];
-  const RepDev rp = w.reps[fb.rep];
-  const long long nchunks = (rp.n + kFlatChunk - 1) / kFlatChunk;
   const double h = p.dt / p.nsub;
-  for (long long ch = fb.first; ch < nchunks; ch += rp.flat_nb) {
-    const long long base = ch * kFlatChunk;
-    for (int k = 0; k < kFlatChunk / kBlock; ++k) {
-      const long long li = base + k * kBlock + threadIdx.x;
-      if (li >= rp.n) continue;
-      const long long i = rp.off + li;
+  int b0, b1;
+  work_range(w.nflat, b0, b1);
+  for (int it = b0; it < b1; ++it) {
+    const FlatBlk fb = w.flat[it];
+    const long long off = w.reps[fb.rep].off;
+    for (long long li = fb.begin + threadIdx.x; li < fb.end; li += kBlock) {
+      const long long i = off + li;
       const uint8_t l = L[i];
       if (l == 0) continue;
       const double kk = K[i];
@@ -88,7 +86,7 @@ __global__ void __launch_bounds__(kBlock) k_ode(Work w, DevParams p, const uint8
 
 void launch_ode(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
                 const double* K, double* P, double* Vc, double* phi) {
-  hipLaunchKernelGGL(k_ode, dim3(w.nflat), dim3(kBlock), 0, s, w, p, L, K, P, Vc, phi);
+  hipLaunchKernelGGL(k_ode, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, K, P, Vc, phi);
 }
 
 }  // namespace hca

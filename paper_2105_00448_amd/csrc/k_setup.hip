@@ -35,16 +35,12 @@ __global__ void k_plasma(int nreps, const RepDev* reps, DevParams p, const long 
 
 template <typename F>
 __device__ inline void for_each_voxel(const Work& w, F f) {
-  const FlatBlk fb = w.flat[blockIdx.x];
-  const RepDev rp = w.reps[fb.rep];
-  const long long nchunks = (rp.n + kFlatChunk - 1) / kFlatChunk;
-  for (long long ch = fb.first; ch < nchunks; ch += rp.flat_nb) {
-    const long long base = ch * kFlatChunk;
-#pragma unroll
-    for (int k = 0; k < kFlatChunk / kBlock; ++k) {
-      const long long i = base + k * kBlock + threadIdx.x;
-      if (i < rp.n) f(fb.rep, rp, rp.off + i);
-    }
+  int b0, b1;
+  work_range(w.nflat, b0, b1);
+  for (int it = b0; it < b1; ++it) {
+    const FlatBlk fb = w.flat[it];
+    const RepDev rp = w.reps[fb.rep];
+    for (long long i = fb.begin + threadIdx.x; i < fb.end; i += kBlock) f(fb.rep, rp, rp.off + i);
   }
 }
 
@@ -146,25 +142,25 @@ void launch_plasma(hipStream_t s, const Work& w, const DevParams& p, const long 
 
 void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
                      const double* vw, const double* K, double* c, double* b, int steady) {
-  hipLaunchKernelGGL(k_setup_o2, dim3(w.nflat), dim3(kBlock), 0, s, w, p, L, vw, K, c, b, steady);
+  hipLaunchKernelGGL(k_setup_o2, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, vw, K, c, b, steady);
 }
 
 void launch_setup_drug(hipStream_t s, const Work& w, const DevParams& p, int drug,
                        const double* vw, const double* G, const double* g0, double* c,
                        double* b) {
-  hipLaunchKernelGGL(k_setup_drug, dim3(w.nflat), dim3(kBlock), 0, s, w, p, drug, vw, G, g0, c, b);
+  hipLaunchKernelGGL(k_setup_drug, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, drug, vw, G, g0, c, b);
 }
 
 void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
                        const uint8_t* L, const double* vw, const double* F, const double* g0,
                        double* c, double* b) {
-  hipLaunchKernelGGL(k_setup_step, dim3(w.nflat), dim3(kBlock), 0, s, w, p, ntot, L, vw, F, g0, c,
+  hipLaunchKernelGGL(k_setup_step, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot, L, vw, F, g0, c,
                      b);
 }
 
 void launch_init_cells(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
                        const double* K, double* P, double* Vc, double* phi) {
-  hipLaunchKernelGGL(k_init_cells, dim3(w.nflat), dim3(kBlock), 0, s, w, p, L, K, P, Vc, phi);
+  hipLaunchKernelGGL(k_init_cells, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, K, P, Vc, phi);
 }
 
 }  // namespace hca

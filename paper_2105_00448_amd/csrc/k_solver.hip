@@ -34,8 +34,8 @@ struct TileCoord {
   double a;
 };
 
-__device__ inline TileCoord tile_coord(const Work& w) {
-  const Tile t = w.tiles[blockIdx.x];
+__device__ inline TileCoord tile_coord(const Work& w, int ti) {
+  const Tile t = w.tiles[ti];
   const RepDev rp = w.reps[t.rep];
   TileCoord tc;
   tc.rep = t.rep;
@@ -90,30 +90,34 @@ __global__ void __launch_bounds__(kBlock) k_cg_start(Work w, const double* __res
                                                      const double* __restrict__ x,
                                                      SolverBufs sb) {
   __shared__ double lds4[4];
-  const TileCoord tc = tile_coord(w);
-  const double a = tc.a;
-  double bb = 0.0, rr = 0.0, rz = 0.0;
-  if (tc.valid) {
-    stencil_column(tc, c, [&](long long j) { return x[j]; },
-                   [&](long long i, int deg, double, double Ax) {
-                     const double bi = b[i];
-                     const double r = bi - Ax;
-                     sb.r[i] = r;
-                     bb += bi * bi;
-                     rr += r * r;
-                     if (sb.jacobi) {
-                       const double di = 1.0 / (c[i] + a * deg);
-                       const double zz = r * di;
-                       sb.dinv[i] = di;
-                       sb.z[i] = zz;
-                       rz += r * zz;
-                     }
-                   });
+  int t0, t1;
+  work_range(w.ntiles, t0, t1);
+  for (int ti = t0; ti < t1; ++ti) {
+    const TileCoord tc = tile_coord(w, ti);
+    const double a = tc.a;
+    double bb = 0.0, rr = 0.0, rz = 0.0;
+    if (tc.valid) {
+      stencil_column(tc, c, [&](long long j) { return x[j]; },
+                     [&](long long i, int deg, double, double Ax) {
+                       const double bi = b[i];
+                       const double r = bi - Ax;
+                       sb.r[i] = r;
+                       bb += bi * bi;
+                       rr += r * r;
+                       if (sb.jacobi) {
+                         const double di = 1.0 / (c[i] + a * deg);
+                         const double zz = r * di;
+                         sb.dinv[i] = di;
+                         sb.z[i] = zz;
+                         rz += r * zz;
+                       }
+                     });
+    }
+    bb = block_sum(bb, lds4);
+    rr = block_sum(rr, lds4);
+    rz = block_sum(rz, lds4);
+    store_partials(sb.partial + (size_t)ti * 3, bb, rr, rz);
   }
-  bb = block_sum(bb, lds4);
-  rr = block_sum(rr, lds4);
-  rz = block_sum(rz, lds4);
-  store_partials(sb.partial + (size_t)blockIdx.x * 3, bb, rr, rz);
 }
 
 // p_new = z + beta p_old (p_new = z on the first iteration), q = A p_new.
@@ -123,22 +127,26 @@ __global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, const double* __res
                                                      double* __restrict__ pnew,
                                                      double* __restrict__ q, SolverBufs sb) {
   __shared__ double lds4[4];
-  const TileCoord tc = tile_coord(w);
-  const SolveScal* ssr = sb.ss + tc.rep;
-  if (ssr->done) return;
-  const double beta = ssr->beta;
-  const bool first = ssr->first != 0;
-  double pq = 0.0;
-  if (tc.valid) {
-    auto U = [&](long long j) { return first ? z[j] : z[j] + beta * pold[j]; };
-    stencil_column(tc, c, U, [&](long long i, int, double pc, double Ap) {
-      pnew[i] = pc;
-      q[i] = Ap;
-      pq += pc * Ap;
-    });
+  int t0, t1;
+  work_range(w.ntiles, t0, t1);
+  for (int ti = t0; ti < t1; ++ti) {
+    const TileCoord tc = tile_coord(w, ti);
+    const SolveScal* ssr = sb.ss + tc.rep;
+    if (ssr->done) continue;
+    const double beta = ssr->beta;
+    const bool first = ssr->first != 0;
+    double pq = 0.0;
+    if (tc.valid) {
+      auto U = [&](long long j) { return first ? z[j] : z[j] + beta * pold[j]; };
+      stencil_column(tc, c, U, [&](long long i, int, double pc, double Ap) {
+        pnew[i] = pc;
+        q[i] = Ap;
+        pq += pc * Ap;
+      });
+    }
+    pq = block_sum(pq, lds4);
+    store_partials(sb.partial + (size_t)ti * 3, pq, 0.0, 0.0);
   }
-  pq = block_sum(pq, lds4);
-  store_partials(sb.partial + (size_t)blockIdx.x * 3, pq, 0.0, 0.0);
 }
 
 // x += alpha p, r -= alpha q; partials of r.r, r.z_old and (Jacobi) r.z'.
@@ -147,39 +155,34 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(Work w, double* __restrict
                                                       const double* __restrict__ q,
                                                       SolverBufs sb) {
   __shared__ double lds4[4];
-  const FlatBlk fb = w.flat[blockIdx.x];
-  const SolveScal* ssr = sb.ss + fb.rep;
-  if (ssr->done) return;
-  const RepDev rp = w.reps[fb.rep];
-  const double alpha = ssr->alpha;
   const bool jac = sb.jacobi != 0;
-  double rr = 0.0, rzo = 0.0, rzn = 0.0;
-  const long long nchunks = (rp.n + kFlatChunk - 1) / kFlatChunk;
-  for (long long ch = fb.first; ch < nchunks; ch += rp.flat_nb) {
-    const long long base = rp.off + ch * kFlatChunk;
-    const long long lim = rp.off + rp.n;
-#pragma unroll
-    for (int k = 0; k < kFlatChunk / kBlock; ++k) {
-      const long long i = base + k * kBlock + threadIdx.x;
-      if (i < lim) {
-        x[i] += alpha * p[i];
-        const double r = sb.r[i] - alpha * q[i];
-        sb.r[i] = r;
-        const double zold = sb.z[i];
-        rr += r * r;
-        rzo += r * zold;
-        if (jac) {
-          const double znew = r * sb.dinv[i];
-          sb.z[i] = znew;
-          rzn += r * znew;
-        }
+  int b0, b1;
+  work_range(w.nflat, b0, b1);
+  for (int it = b0; it < b1; ++it) {
+    const FlatBlk fb = w.flat[it];
+    const SolveScal* ssr = sb.ss + fb.rep;
+    if (ssr->done) continue;
+    const long long off = w.reps[fb.rep].off;
+    const double alpha = ssr->alpha;
+    double rr = 0.0, rzo = 0.0, rzn = 0.0;
+    for (long long i = off + fb.begin + threadIdx.x; i < off + fb.end; i += kBlock) {
+      x[i] += alpha * p[i];
+      const double r = sb.r[i] - alpha * q[i];
+      sb.r[i] = r;
+      const double zold = sb.z[i];
+      rr += r * r;
+      rzo += r * zold;
+      if (jac) {
+        const double znew = r * sb.dinv[i];
+        sb.z[i] = znew;
+        rzn += r * znew;
       }
     }
+    rr = block_sum(rr, lds4);
+    rzo = block_sum(rzo, lds4);
+    rzn = block_sum(rzn, lds4);
+    store_partials(sb.partial + (size_t)it * 3, rr, rzo, rzn);
   }
-  rr = block_sum(rr, lds4);
-  rzo = block_sum(rzo, lds4);
-  rzn = block_sum(rzn, lds4);
-  store_partials(sb.partial + (size_t)blockIdx.x * 3, rr, rzo, rzn);
 }
 
 // Fixed-order sum of component k of the partials [b0, b0 + nb).
@@ -284,7 +287,7 @@ void launch_cg_start(hipStream_t s, const Work& w, double rtol, int maxit, const
                      const double* b, const double* x, const SolverBufs& sb, unsigned field_mask,
                      int nrep) {
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, sb.ndone);
-  hipLaunchKernelGGL(k_cg_start, dim3(w.ntiles), dim3(kBlock), 0, s, w, c, b, x, sb);
+  hipLaunchKernelGGL(k_cg_start, dim3(grid_for(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c, b, x, sb);
   launch_cg_reduce(s, w, sb, RED_START, rtol, maxit, field_mask, nrep);
 }
 
@@ -292,7 +295,7 @@ void launch_cg_apply(hipStream_t s, const Work& w, const double* c, const Solver
                      int parity) {
   const double* pold = parity ? sb.p1 : sb.p0;
   double* pnew = parity ? sb.p0 : sb.p1;
-  hipLaunchKernelGGL(k_cg_apply, dim3(w.ntiles), dim3(kBlock), 0, s, w, c, sb.z, pold, pnew, sb.q,
+  hipLaunchKernelGGL(k_cg_apply, dim3(grid_for(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c, sb.z, pold, pnew, sb.q,
                      sb);
   launch_cg_reduce(s, w, sb, RED_APPLY, 0.0, 0);
 }
@@ -300,7 +303,7 @@ void launch_cg_apply(hipStream_t s, const Work& w, const double* c, const Solver
 void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, double* x,
                       const SolverBufs& sb, int parity) {
   const double* pnew = parity ? sb.p0 : sb.p1;
-  hipLaunchKernelGGL(k_cg_update, dim3(w.nflat), dim3(kBlock), 0, s, w, x, pnew,
+  hipLaunchKernelGGL(k_cg_update, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, x, pnew,
                      (const double*)sb.q, sb);
   launch_cg_reduce(s, w, sb, RED_UPDATE, rtol, maxit);
 }

@@ -13,6 +13,7 @@
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -21,6 +22,10 @@
 #include "hca_internal.h"
 
 using namespace hca;
+
+namespace hca {
+int g_xcd_remap = 0;   // measured slower on the 128^3 workload (HCA_XCD_REMAP=1 to enable)
+}
 
 namespace {
 
@@ -555,7 +560,13 @@ RepDev lattice_entry(const RepHost& R, long long off, int idx, std::vector<FlatB
   const long long chunks = (R.n + kFlatChunk - 1) / kFlatChunk;
   d.flat_nb = (int)std::min<long long>(chunks, kMaxFlatBlocksPerRep);
   d.flat_b0 = (int)flat.size();
-  for (int k = 0; k < d.flat_nb; ++k) flat.push_back(FlatBlk{idx, k});
+  for (int k = 0; k < d.flat_nb; ++k) {
+    FlatBlk fb{};
+    fb.rep = idx;
+    fb.begin = R.n * k / d.flat_nb;
+    fb.end = R.n * (k + 1) / d.flat_nb;
+    flat.push_back(fb);
+  }
   d.tx = pick_tx(R.nx);
   const int tz = pick_tz(R.nx, R.ny, R.nz, d.tx, kTileTarget);
   d.tile_b0 = (int)tiles.size();
@@ -566,6 +577,14 @@ RepDev lattice_entry(const RepHost& R, long long off, int idx, std::vector<FlatB
 
 hca_status build_tables(hca_ctx* c, const hca_replicate* in) {
   const int R = c->nreps;
+  // work-item kernels: one item per workgroup unless HCA_MAX_BLOCKS caps the
+  // grid (then each workgroup loops over a contiguous run of items)
+  int max_blocks = 1 << 30;
+  if (const char* e = getenv("HCA_MAX_BLOCKS")) {
+    const int v = atoi(e);
+    if (v > 0) max_blocks = v;
+  }
+  if (const char* e = getenv("HCA_XCD_REMAP")) g_xcd_remap = atoi(e) != 0;
   {
     std::vector<RepDev> rd;
     std::vector<FlatBlk> flat;
@@ -587,6 +606,7 @@ hca_status build_tables(hca_ctx* c, const hca_replicate* in) {
     c->work.nflat = (int)flat.size();
     c->work.tiles = c->d_tiles;
     c->work.ntiles = (int)tiles.size();
+    c->work.max_blocks = max_blocks;
   }
   {
     std::vector<RepDev> sd;
@@ -617,6 +637,7 @@ hca_status build_tables(hca_ctx* c, const hca_replicate* in) {
     c->sys3.nflat = (int)flat.size();
     c->sys3.tiles = c->d_stiles;
     c->sys3.ntiles = (int)tiles.size();
+    c->sys3.max_blocks = max_blocks;
     c->sys1 = c->sys3;
     c->sys1.nreps = R;
     c->sys1.nflat = nflat1;
