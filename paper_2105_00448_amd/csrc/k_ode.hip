@@ -1,43 +1,16 @@
-// Intracellular module: Eqs. (odep53), (odevegf), (cellcycle) per occupied
-// voxel over one coupled step dt, with oxygen frozen at K^{n+1}.
-//
-// * p53 is linear with constant coefficients while K is frozen, so it is
-//   advanced exactly (the paper's explicit form):
-//     lam = k1' K/(K_p53 + K),  P(t) = P0 e^{-lam t} + k1 t phi1(lam t),
-//     phi1(z) = (1 - e^{-z})/z = -expm1(-z)/z.
-// * V_c: classical RK4 with the fixed step h = dt/nsub (1 min, the paper's
-//   VODE maximum step), the exact P(t) at the stage times, advanced along the
-//   half-step grid by products and sums of positive terms.
-// * phi (cancer cells only): phi += dt K / (T (K_phi + K)), evaluated without
-//   contraction so it rounds exactly like the plain expression.
-//
-// FP64; the kernel is bound by the VALU (about 120 divides per voxel).
+// Intracellular module over one coupled step for every occupied voxel: the
+// plain integrator of ode_dev.h.  FP64; the kernel is bound by the VALU
+// (about 120 divides per voxel).
 #include "dev_util.h"
+#include "ode_dev.h"
 
 namespace hca {
-
-__device__ inline double cycle_increment(double dt, double K, double T, double Kphi) {
-#pragma clang fp contract(off)
-  const double num = dt * K;
-  const double den = T * (Kphi + K);
-  return num / den;
-}
-
-__device__ inline double add_nocontract(double a, double b) {
-#pragma clang fp contract(off)
-  return a + b;
-}
-
-__device__ inline double vegf_rhs(double V, double Pt, double mu, const DevParams& p) {
-  return p.k2 + p.k2pp * Pt * V / (p.J5 + V) - mu * V;
-}
 
 __global__ void __launch_bounds__(kBlock) k_ode(Work w, DevParams p, const uint8_t* __restrict__ L,
                                                 const double* __restrict__ K,
                                                 double* __restrict__ P,
                                                 double* __restrict__ Vc,
                                                 double* __restrict__ phi) {
-  const double h = p.dt / p.nsub;
   int b0, b1;
   work_range(w.nflat, b0, b1);
   for (int it = b0; it < b1; ++it) {
@@ -47,46 +20,19 @@ __global__ void __launch_bounds__(kBlock) k_ode(Work w, DevParams p, const uint8
       const long long i = off + li;
       const uint8_t l = L[i];
       if (l == 0) continue;
-      const double kk = K[i];
-      const double P0 = P[i];
-      const double lam = p.k1p * kk / (p.K_p53 + kk);
-      const double mu = p.k2p * kk / (p.K_V + kk);
-      // Along the half-step grid: E(t) = e^{-lam t} and
-      // Gi(t) = int_0^t e^{-lam s} ds = t phi1(lam t), so P(t) = P0 E + k1 Gi.
-      // Both advance by products and sums of positive terms (no cancellation):
-      //   E(t + h/2) = E eh,   Gi(t + h/2) = Gi + E gh,
-      //   eh = e^{-lam h/2},   gh = -expm1(-lam h/2)/lam  (h/2 when lam = 0).
-      const double zh = lam * 0.5 * h;
-      const double eh = exp(-zh);
-      const double gh = zh > 0.0 ? -expm1(-zh) / lam : 0.5 * h;
-      double E = 1.0, Gi = 0.0;
-      double V = Vc[i];
-      for (int s = 0; s < p.nsub; ++s) {
-        const double Pa = P0 * E + p.k1 * Gi;
-        const double Gm = Gi + E * gh;
-        const double Em = E * eh;
-        const double Pm = P0 * Em + p.k1 * Gm;
-        Gi = Gm + Em * gh;
-        E = Em * eh;
-        const double Pb = P0 * E + p.k1 * Gi;
-        const double s1 = vegf_rhs(V, Pa, mu, p);
-        const double s2 = vegf_rhs(V + 0.5 * h * s1, Pm, mu, p);
-        const double s3 = vegf_rhs(V + 0.5 * h * s2, Pm, mu, p);
-        const double s4 = vegf_rhs(V + h * s3, Pb, mu, p);
-        V = V + (h / 6.0) * (s1 + 2.0 * s2 + 2.0 * s3 + s4);
-      }
-      const double z = lam * p.dt;
-      const double ph1 = z > 0.0 ? -expm1(-z) / z : 1.0;
-      P[i] = P0 * exp(-z) + p.k1 * p.dt * ph1;
-      Vc[i] = V;
-      if (l == 1) phi[i] = add_nocontract(phi[i], cycle_increment(p.dt, kk, p.T_cycle, p.K_phi));
+      double pv = P[i], vv = Vc[i], ph = phi[i];
+      ode_voxel(p, l, K[i], pv, vv, ph);
+      P[i] = pv;
+      Vc[i] = vv;
+      if (l == 1) phi[i] = ph;
     }
   }
 }
 
 void launch_ode(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
                 const double* K, double* P, double* Vc, double* phi) {
-  hipLaunchKernelGGL(k_ode, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, K, P, Vc, phi);
+  hipLaunchKernelGGL(k_ode, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, K,
+                     P, Vc, phi);
 }
 
 }  // namespace hca
