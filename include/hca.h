@@ -125,9 +125,36 @@ typedef struct hca_stats_s {
   double cg_relres[3];
   int32_t nonfinite;           /* 1 if a NaN/Inf was seen by the last stats pass */
   int32_t init_picard_iters;
+  /* last ODE phase with a surrogate set: occupied voxels advanced by the
+   * network, and by the plain integrator (threshold margin or range) */
+  int64_t sur_voxels, sur_fallbacks;
 } hca_stats_t;
 
 typedef struct hca_ctx hca_ctx;
+
+/* ---- ODE surrogate --------------------------------------------------------
+ * A 6 -> 64 -> 64 -> 64 -> 3 perceptron with GELU (erf form) after each
+ * hidden layer that maps a voxel's (K, G1, G2, P, Vc, phi) before the
+ * intracellular substep to the substep's update (dP, dVc, dphi), dphi being
+ * the clock increment of a cancer cell (Eq. cellcycle).  It evaluates in
+ * bfloat16 on the matrix cores with FP32 accumulation. */
+#define HCA_MLP_NIN 6
+#define HCA_MLP_NHID 64
+#define HCA_MLP_NOUT 3
+#define HCA_MLP_NPARAM 8963
+
+typedef struct hca_mlp {
+  /* HCA_MLP_NPARAM FP32 values: W1 (64x6, row-major, row = output unit), b1,
+   * W2 (64x64), b2, W3 (64x64), b3, W4 (3x64), b4.  Host or device memory
+   * (theta_is_device); hca_set_surrogate copies it. */
+  const float* theta;
+  int32_t theta_is_device;
+  float in_mean[HCA_MLP_NIN], in_scale[HCA_MLP_NIN];     /* x_s = (x - mean) * scale */
+  float out_mean[HCA_MLP_NOUT], out_scale[HCA_MLP_NOUT]; /* y = y_s * scale + mean   */
+  float in_lo[HCA_MLP_NIN], in_hi[HCA_MLP_NIN];          /* training input range     */
+  int32_t box_check;   /* 1: voxels with inputs outside [in_lo, in_hi] use the
+                          plain integrator                                      */
+} hca_mlp;
 
 /* Table 1 of the paper plus the readings of its silent passages. */
 hca_status hca_default_params(hca_params* out);
@@ -172,6 +199,61 @@ hca_status hca_kernel_time(hca_ctx* c, int kernel, double* ms, int64_t* launches
 const char* hca_kernel_name(int kernel);
 int hca_num_kernels(void);
 hca_status hca_reset_kernel_time(hca_ctx* c);
+
+/* Replace the plain integrator of the ODE phase (Eqs. odep53, odevegf,
+ * cellcycle) by the surrogate network: every occupied voxel takes the
+ * network's update, except that a cancer cell whose updated phi would lie
+ * within `margin` of the division threshold phi = 1 (cellular module), and
+ * with box_check any voxel whose inputs leave the training range, is
+ * advanced by the plain integrator.  net = NULL restores the plain
+ * integrator.  Non-finite statistics, a zero scale or a negative margin give
+ * HCA_E_INVALID and leave the setting unchanged. */
+hca_status hca_set_surrogate(hca_ctx* c, const hca_mlp* net, double margin);
+
+/* One full coupled step with the plain integrator (whether or not a
+ * surrogate is set) that also records one training pair per occupied voxel of
+ * every replicate, replicate-major and in gid order within a replicate:
+ * X row = (K^{n+1}, G1^{n+1}, G2^{n+1}, P^n, Vc^n, phi^n) (FP32, 6 per row) and
+ * Y row = (P^{n+1} - P^n, Vc^{n+1} - Vc^n, cancer-clock increment) (3 per
+ * row).  X and Y are device buffers of cap_rows rows; more occupied voxels
+ * than cap_rows gives HCA_E_RANGE before any work.  *n_rows = rows written. */
+hca_status hca_harvest_step(hca_ctx* c, float* X, float* Y, int64_t cap_rows, int64_t* n_rows);
+
+/* ---- surrogate training -----------------------------------------------------
+ * A trainer holds a standardised copy of n_rows training pairs (X: n x 6,
+ * Y: n x 3, FP32 device arrays, row-major, the caller keeps them), the
+ * per-column statistics (mean and standard deviation over the set; a column
+ * with zero spread gets scale 1), the parameters, and the Adam moments
+ * (beta1 0.9, beta2 0.999, eps 1e-8).  Parameters start as
+ * U(-sqrt(3/fan_in), sqrt(3/fan_in)) weights from Philox key (seed, 0) and
+ * zero biases.  Loss: mean squared error over the batch and the three
+ * standardised outputs.  One trainer per stream; not thread-safe. */
+typedef struct hca_mlp_trainer hca_mlp_trainer;
+
+hca_status hca_mlp_trainer_create(hca_mlp_trainer** out, const float* X, const float* Y,
+                                  int64_t n_rows, uint64_t seed, void* stream);
+/* Overwrite the parameters (host or device, HCA_MLP_NPARAM) and reset Adam. */
+hca_status hca_mlp_trainer_set_params(hca_mlp_trainer* t, const float* theta, int is_device);
+hca_status hca_mlp_trainer_params(hca_mlp_trainer* t, float* theta, int is_device);
+/* The standardised training set (device buffers of n x 6 and n x 3). */
+hca_status hca_mlp_trainer_data(hca_mlp_trainer* t, float* Xs, float* Ys);
+/* Fill *out for hca_set_surrogate: statistics, range, theta = the trainer's
+ * device parameters (valid until the next update or destroy), box_check 0. */
+hca_status hca_mlp_trainer_export(hca_mlp_trainer* t, hca_mlp* out);
+/* Gradient (device, HCA_MLP_NPARAM) and loss (host) of the batch of rows
+ * idx[0..batch) (device int32, clamped to [0, n_rows)); batch a positive
+ * multiple of 64, at most 65536, else HCA_E_RANGE.  No update. */
+hca_status hca_mlp_gradient(hca_mlp_trainer* t, const int32_t* idx, int batch, float* grad,
+                            float* loss);
+/* n_steps Adam steps on minibatches drawn with replacement (Philox counter
+ * (j, step, 3, 0), key (seed, 0)); losses[k] (host, may be NULL) = loss of
+ * step k's batch before its update. */
+hca_status hca_mlp_train(hca_mlp_trainer* t, int n_steps, int batch, float lr, float* losses);
+/* Network outputs for n rows of X (device) into Y (device): raw = 1 takes
+ * and returns model values, raw = 0 standardised ones. */
+hca_status hca_mlp_eval(hca_mlp_trainer* t, const float* X, int64_t n, int raw, float* Y);
+const char* hca_mlp_trainer_last_error(const hca_mlp_trainer* t);
+void hca_mlp_trainer_destroy(hca_mlp_trainer* t);
 
 /* Block the host until all work of the context has finished. */
 hca_status hca_synchronize(hca_ctx* c);

@@ -31,7 +31,7 @@ COMMON = [
 EXTRA = {
     "k_ca.hip": ["-ffp-contract=off"],
 }
-SOURCES = ["runtime.cpp", "k_setup.hip", "k_solver.hip", "k_ode.hip", "k_ca.hip", "k_mg.hip",
+SOURCES = ["runtime.cpp", "mlp_runtime.cpp", "k_setup.hip", "k_solver.hip", "k_ode.hip", "k_ca.hip", "k_mg.hip",
            "k_mlp.hip"]
 
 

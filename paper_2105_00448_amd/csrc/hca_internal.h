@@ -83,7 +83,8 @@ struct Counters {
   unsigned long long n_cancer, n_stroma, n_empty, n_vessel;
   unsigned long long nonfinite;
   unsigned long long total_divisions, total_kills;
-  unsigned long long pad[4];
+  unsigned long long sur_voxels, sur_fallbacks;   // ODE phase with the surrogate
+  unsigned long long pad[2];
 };
 
 struct Work {
@@ -230,7 +231,8 @@ void launch_ca_finalize(hipStream_t s, const Work& w, uint8_t* L, double* phi, d
                         double* Vc, const uint8_t* code, const uint8_t* win, Counters* cnt);
 void launch_stats(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
                   const double* const* fields, int nfields, Counters* cnt);
-void launch_zero_counters(hipStream_t s, Counters* cnt, int nreps, int events_only);
+// what: 1 CA events, 0 census and non-finite count, 2 surrogate counts.
+void launch_zero_counters(hipStream_t s, Counters* cnt, int nreps, int what);
 void launch_advance(hipStream_t s, long long* d_step);
 void launch_validate_cells(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
                            int rep, unsigned long long* bad);

@@ -243,14 +243,16 @@ __global__ void __launch_bounds__(kBlock) k_stats(Work w, const uint8_t* __restr
 
 // Zero the event counters (events_only) or the state counters.  A kernel,
 // not a memset, so the sequence stays safe to capture in a graph.
-__global__ void k_zero_counters(Counters* cnt, int nreps, int events_only) {
+__global__ void k_zero_counters(Counters* cnt, int nreps, int what) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nreps) return;
   Counters& c = cnt[r];
-  if (events_only) {
+  if (what == 1) {
     c.committed = c.kills = c.divisions = c.nospace = c.lost = 0;
-  } else {
+  } else if (what == 0) {
     c.n_cancer = c.n_stroma = c.n_empty = c.n_vessel = c.nonfinite = 0;
+  } else {
+    c.sur_voxels = c.sur_fallbacks = 0;
   }
 }
 
@@ -294,9 +296,8 @@ void launch_stats(hipStream_t s, const Work& w, const uint8_t* L, const double* 
   hipLaunchKernelGGL(k_stats, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, vw, fields, nfields, cnt);
 }
 
-void launch_zero_counters(hipStream_t s, Counters* cnt, int nreps, int events_only) {
-  hipLaunchKernelGGL(k_zero_counters, dim3((nreps + 63) / 64), dim3(64), 0, s, cnt, nreps,
-                     events_only);
+void launch_zero_counters(hipStream_t s, Counters* cnt, int nreps, int what) {
+  hipLaunchKernelGGL(k_zero_counters, dim3((nreps + 63) / 64), dim3(64), 0, s, cnt, nreps, what);
 }
 
 void launch_advance(hipStream_t s, long long* d_step) {

@@ -20,6 +20,7 @@
 
 #include "hca.h"
 #include "hca_internal.h"
+#include "mlp_dev.h"
 
 using namespace hca;
 
@@ -33,14 +34,14 @@ enum KernelClass {
   KC_PLASMA = 0, KC_SETUP, KC_CG_START, KC_CG_APPLY, KC_CG_UPDATE, KC_ODE,
   KC_CA_PROPOSE, KC_CA_RESOLVE, KC_CA_FINALIZE, KC_STATS,
   KC_MG_PREP, KC_MG_PRE0, KC_MG_RESTRICT0, KC_MG_LEVELS, KC_MG_COARSE, KC_MG_POST1_0,
-  KC_MG_POST2_0, KC_COUNT
+  KC_MG_POST2_0, KC_MLP_APPLY, KC_COUNT
 };
 
 const char* kKernelNames[KC_COUNT] = {
     "k_plasma", "k_setup_step", "k_cg_start", "k_cg_apply", "k_cg_update",
     "k_ode", "k_ca_propose", "k_ca_resolve", "k_ca_finalize", "k_stats",
     "k_mg_prep0+k_mg_coarsen", "k_mg_pre<L0>", "k_mg_restrict<L0>", "mg levels >= 1 (global)",
-    "k_mg_coarse", "k_mg_post1<L0>", "k_mg_post2<L0>"};
+    "k_mg_coarse", "k_mg_post1<L0>", "k_mg_post2<L0>", "k_mlp_apply"};
 
 // Compulsory (algorithmic) HBM bytes per voxel of each kernel class; solver
 // classes per voxel of each active system (0: not priced, latency-bound).
@@ -61,7 +62,8 @@ const double kBytesPerVoxel[KC_COUNT] = {
     0.0,          // coarser global levels
     0.0,          // coarse workgroup levels
     20.5,         // mg post1 L0: read u, e (1/8), r, dinv; write ualt
-    24.0};        // mg post2 L0: read ualt, r, dinv; write z (8)
+    24.0,         // mg post2 L0: read ualt, r, dinv; write z (8)
+    73.0};        // mlp apply: read L, K, G1, G2, P, Vc, phi; write P, Vc, phi
 constexpr double kBytesUpdateMg = 56.0;   // cg_update, multigrid: read x, p, r, q, z; write x, r
 
 constexpr int kTagState = -2;   // launches over every voxel of every replicate
@@ -119,6 +121,14 @@ struct hca_ctx {
   Counters* d_cnt = nullptr;
   const double** d_fields = nullptr;
   unsigned long long* d_bad = nullptr;
+  // ODE surrogate (hca_set_surrogate) and training-pair harvest buffers
+  bool sur_on = false;
+  MlpDev net{};
+  float* d_theta = nullptr;
+  bf16x8* d_pack = nullptr;
+  double* before = nullptr;       // 3 x ntot
+  int* item_cnt = nullptr;        // per flat work item
+  long long* item_off = nullptr;  // nflat + 1
 
   SolveScal* h_ss = nullptr;     // pinned, 3 x nreps
   Counters* h_cnt = nullptr;     // pinned
@@ -384,8 +394,15 @@ hca_status run_phases(hca_ctx* c, unsigned mask) {
     if (st != HCA_OK) return st;
   }
   if (mask & HCA_PH_ODE) {
-    ProfScope ps(c, KC_ODE, kTagState);
-    launch_ode(s, wk, c->dp, c->L, c->K, c->P, c->Vc, c->phi);
+    if (c->sur_on) {
+      launch_zero_counters(s, c->d_cnt, c->nreps, 2);
+      ProfScope ps(c, KC_MLP_APPLY, kTagState);
+      launch_mlp_apply(s, wk, c->dp, c->net, c->L, c->K, c->G1, c->G2, c->P, c->Vc, c->phi,
+                       c->d_cnt);
+    } else {
+      ProfScope ps(c, KC_ODE, kTagState);
+      launch_ode(s, wk, c->dp, c->L, c->K, c->P, c->Vc, c->phi);
+    }
   }
   if (mask & HCA_PH_CA) {
     launch_zero_counters(s, c->d_cnt, c->nreps, 1);
@@ -905,7 +922,8 @@ void free_all(hca_ctx* c) {
                   c->sb.r, c->sb.z, c->sb.p0, c->sb.p1, c->sb.q, c->sb.dinv, c->sb.partial,
                   c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->d_step,
                   c->d_reps, c->d_flat, c->d_tiles, c->d_sys, c->d_sflat, c->d_stiles, c->d_cnt,
-                  (void*)c->d_fields, c->d_bad};
+                  (void*)c->d_fields, c->d_bad, c->d_theta, (void*)c->d_pack, c->before,
+                  c->item_cnt, c->item_off};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   for (void* p : c->mg_mem)
@@ -1175,6 +1193,8 @@ hca_status hca_stats(hca_ctx* c, int rep, hca_stats_t* out) {
   }
   out->nonfinite = k.nonfinite ? 1 : 0;
   out->init_picard_iters = c->picard_iters;
+  out->sur_voxels = (int64_t)k.sur_voxels;
+  out->sur_fallbacks = (int64_t)k.sur_fallbacks;
   return HCA_OK;
 }
 
@@ -1200,6 +1220,90 @@ hca_status hca_reset_kernel_time(hca_ctx* c) {
   if (!c) return HCA_E_INVALID;
   prof_flush(c, nullptr, 0);
   for (int k = 0; k < KC_COUNT; ++k) c->prof_ms[k] = c->prof_n[k] = c->prof_bytes[k] = 0;
+  return HCA_OK;
+}
+
+hca_status hca_set_surrogate(hca_ctx* c, const hca_mlp* net, double margin) {
+  if (!c) return HCA_E_INVALID;
+  if (!net) {
+    c->sur_on = false;
+    return HCA_OK;
+  }
+  auto reject = [&](const char* msg) {
+    c->err = msg;
+    return HCA_E_INVALID;
+  };
+  if (!net->theta || !std::isfinite(margin) || margin < 0.0)
+    return reject("surrogate: null parameters or bad margin");
+  for (int f = 0; f < HCA_MLP_NIN; ++f)
+    if (!std::isfinite(net->in_mean[f]) || !std::isfinite(net->in_scale[f]) ||
+        net->in_scale[f] == 0.f || std::isnan(net->in_lo[f]) || std::isnan(net->in_hi[f]))
+      return reject("surrogate: bad input statistics");
+  for (int o = 0; o < HCA_MLP_NOUT; ++o)
+    if (!std::isfinite(net->out_mean[o]) || !std::isfinite(net->out_scale[o]) ||
+        net->out_scale[o] == 0.f)
+      return reject("surrogate: bad output statistics");
+  if (!c->d_theta) {
+    HIPCHK(c, dalloc(&c->d_theta, kMlpNparam));
+    HIPCHK(c, dalloc(&c->d_pack, kPackAll));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d_theta, net->theta, sizeof(float) * kMlpNparam,
+                           net->theta_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           c->stream));
+  launch_mlp_pack(c->stream, c->d_theta, c->d_pack);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  MlpDev& d = c->net;
+  d.packed = c->d_pack;
+  d.theta = c->d_theta;
+  for (int f = 0; f < HCA_MLP_NIN; ++f) {
+    d.in_mean[f] = net->in_mean[f];
+    d.in_scale[f] = net->in_scale[f];
+    d.in_lo[f] = net->in_lo[f];
+    d.in_hi[f] = net->in_hi[f];
+  }
+  for (int o = 0; o < HCA_MLP_NOUT; ++o) {
+    d.out_mean[o] = net->out_mean[o];
+    d.out_scale[o] = net->out_scale[o];
+  }
+  d.box = net->box_check ? 1 : 0;
+  d.margin = margin;
+  c->sur_on = true;
+  return HCA_OK;
+}
+
+hca_status hca_harvest_step(hca_ctx* c, float* X, float* Y, int64_t cap_rows, int64_t* n_rows) {
+  if (!c || !X || !Y || !n_rows || cap_rows < 0) return HCA_E_INVALID;
+  if (c->failed) return HCA_E_INVALID;
+  *n_rows = 0;
+  const Work& wk = c->work;
+  hipStream_t s = c->stream;
+  if (!c->before) {
+    HIPCHK(c, dalloc(&c->before, 3 * (size_t)c->ntot));
+    HIPCHK(c, dalloc(&c->item_cnt, (size_t)wk.nflat));
+    HIPCHK(c, dalloc(&c->item_off, (size_t)wk.nflat + 1));
+  }
+  // rows = occupied voxels of the current map (the map changes only in the CA phase)
+  launch_mlp_count(s, wk, c->L, c->item_cnt);
+  launch_mlp_scan(s, wk.nflat, c->item_cnt, c->item_off);
+  long long total = 0;
+  HIPCHK(c, hipMemcpyAsync(&total, c->item_off + wk.nflat, sizeof total, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (total > cap_rows) return fail(c, HCA_E_RANGE, "harvest: more occupied voxels than cap_rows");
+  hca_status st = run_phases(c, HCA_PH_O2 | HCA_PH_DRUGS);
+  if (st != HCA_OK) return st;
+  launch_mlp_save_state(s, wk, c->P, c->Vc, c->phi, c->before);
+  {
+    ProfScope ps(c, KC_ODE, kTagState);
+    launch_ode(s, wk, c->dp, c->L, c->K, c->P, c->Vc, c->phi);
+  }
+  launch_mlp_harvest(s, wk, c->dp, c->L, c->K, c->G1, c->G2, c->P, c->Vc, c->before, c->item_off,
+                     X, Y);
+  st = run_phases(c, HCA_PH_CA | HCA_PH_STATS | HCA_PH_ADVANCE);
+  if (st != HCA_OK) return st;
+  st = check_after(c);
+  if (st != HCA_OK) return st;
+  *n_rows = total;
   return HCA_OK;
 }
 

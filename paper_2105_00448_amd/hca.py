@@ -59,6 +59,7 @@ class Stats(C.Structure):
         ("total_divisions", C.c_int64), ("total_kills", C.c_int64),
         ("cg_iters", C.c_int32 * 3), ("cg_relres", C.c_double * 3),
         ("nonfinite", C.c_int32), ("init_picard_iters", C.c_int32),
+        ("sur_voxels", C.c_int64), ("sur_fallbacks", C.c_int64),
     ]
 
     def as_dict(self):
@@ -67,6 +68,23 @@ class Stats(C.Structure):
             v = getattr(self, name)
             d[name] = list(v) if hasattr(v, "__len__") else v
         return d
+
+
+MLP_NIN, MLP_NHID, MLP_NOUT, MLP_NPARAM = 6, 64, 3, 8963
+
+
+class Mlp(C.Structure):
+    _fields_ = [
+        ("theta", C.c_void_p), ("theta_is_device", C.c_int32),
+        ("in_mean", C.c_float * MLP_NIN), ("in_scale", C.c_float * MLP_NIN),
+        ("out_mean", C.c_float * MLP_NOUT), ("out_scale", C.c_float * MLP_NOUT),
+        ("in_lo", C.c_float * MLP_NIN), ("in_hi", C.c_float * MLP_NIN),
+        ("box_check", C.c_int32),
+    ]
+
+    def stats(self):
+        return {k: np.array(getattr(self, k), dtype=np.float32)
+                for k in ("in_mean", "in_scale", "out_mean", "out_scale", "in_lo", "in_hi")}
 
 
 def lib():
@@ -95,6 +113,18 @@ def lib():
         "hca_synchronize": (C.c_int, [vp]),
         "hca_last_error": (C.c_char_p, [vp]),
         "hca_destroy": (None, [vp]),
+        "hca_set_surrogate": (C.c_int, [vp, P(Mlp), C.c_double]),
+        "hca_harvest_step": (C.c_int, [vp, vp, vp, C.c_int64, P(C.c_int64)]),
+        "hca_mlp_trainer_create": (C.c_int, [P(vp), vp, vp, C.c_int64, C.c_uint64, vp]),
+        "hca_mlp_trainer_set_params": (C.c_int, [vp, vp, C.c_int]),
+        "hca_mlp_trainer_params": (C.c_int, [vp, vp, C.c_int]),
+        "hca_mlp_trainer_data": (C.c_int, [vp, vp, vp]),
+        "hca_mlp_trainer_export": (C.c_int, [vp, P(Mlp)]),
+        "hca_mlp_gradient": (C.c_int, [vp, vp, C.c_int, vp, P(C.c_float)]),
+        "hca_mlp_train": (C.c_int, [vp, C.c_int, C.c_int, C.c_float, vp]),
+        "hca_mlp_eval": (C.c_int, [vp, vp, C.c_int64, C.c_int, vp]),
+        "hca_mlp_trainer_last_error": (C.c_char_p, [vp]),
+        "hca_mlp_trainer_destroy": (None, [vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)
@@ -234,6 +264,21 @@ class Simulation:
     def synchronize(self):
         self._check(self._lib.hca_synchronize(self._h), "hca_synchronize")
 
+    # -- surrogate ---------------------------------------------------------
+    def set_surrogate(self, net, margin=1e-3):
+        """net: an Mlp (e.g. Trainer.export()) or None for the plain integrator."""
+        self._check(self._lib.hca_set_surrogate(self._h, C.byref(net) if net is not None else None,
+                                                float(margin)), "hca_set_surrogate")
+
+    def harvest_step(self, X, Y):
+        """One coupled step that writes training rows into the device tensors
+        X (cap x 6) and Y (cap x 3), float32; returns the rows written."""
+        n = C.c_int64()
+        self._check(self._lib.hca_harvest_step(self._h, X.data_ptr(), Y.data_ptr(),
+                                               min(X.shape[0], Y.shape[0]), C.byref(n)),
+                    "hca_harvest_step")
+        return n.value
+
     def close(self):
         if getattr(self, "_h", None):
             self._lib.hca_destroy(self._h)
@@ -255,3 +300,71 @@ class Simulation:
 def schedule_tuple(sched):
     """(times, amts) pair from a synth.DoseSchedule-like object."""
     return (tuple(tuple(t) for t in sched.times), tuple(tuple(a) for a in sched.amts))
+
+
+class Trainer:
+    """hca_mlp_trainer: X (n x 6) and Y (n x 3) are float32 device tensors."""
+
+    def __init__(self, X, Y, seed=0, stream=None):
+        self._lib = lib()
+        if X.shape[0] != Y.shape[0] or X.shape[1:] != (MLP_NIN,) or Y.shape[1:] != (MLP_NOUT,):
+            raise ValueError("X must be (n, 6) and Y (n, 3)")
+        self.n = X.shape[0]
+        h = C.c_void_p()
+        st = self._lib.hca_mlp_trainer_create(C.byref(h), X.data_ptr(), Y.data_ptr(), self.n,
+                                              int(seed), C.c_void_p(stream) if stream else None)
+        if st != OK:
+            raise HcaError(st, "hca_mlp_trainer_create failed (details on stderr)")
+        self._h = h
+
+    def _check(self, st, what):
+        if st != OK:
+            raise HcaError(st, f"{what}: {self._lib.hca_mlp_trainer_last_error(self._h).decode()}")
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        if a.shape != (MLP_NPARAM,):
+            raise ValueError("theta must have HCA_MLP_NPARAM values")
+        self._check(self._lib.hca_mlp_trainer_set_params(self._h, a.ctypes.data, 0), "set_params")
+
+    def params(self):
+        a = np.empty(MLP_NPARAM, dtype=np.float32)
+        self._check(self._lib.hca_mlp_trainer_params(self._h, a.ctypes.data, 0), "params")
+        return a
+
+    def data(self, Xs, Ys):
+        self._check(self._lib.hca_mlp_trainer_data(self._h, Xs.data_ptr(), Ys.data_ptr()), "data")
+
+    def export(self):
+        m = Mlp()
+        self._check(self._lib.hca_mlp_trainer_export(self._h, C.byref(m)), "export")
+        return m
+
+    def gradient(self, idx, grad):
+        """idx: int32 device tensor (batch); grad: float32 device tensor (NPARAM)."""
+        loss = C.c_float()
+        self._check(self._lib.hca_mlp_gradient(self._h, idx.data_ptr(), idx.numel(),
+                                               grad.data_ptr(), C.byref(loss)), "gradient")
+        return loss.value
+
+    def train(self, steps, batch=1024, lr=1e-3):
+        out = np.empty(steps, dtype=np.float32)
+        self._check(self._lib.hca_mlp_train(self._h, steps, batch, float(lr), out.ctypes.data),
+                    "train")
+        return out
+
+    def eval(self, X, Y, raw=True):
+        self._check(self._lib.hca_mlp_eval(self._h, X.data_ptr(), X.shape[0], 1 if raw else 0,
+                                           Y.data_ptr()), "eval")
+        return Y
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hca_mlp_trainer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
