@@ -15,6 +15,16 @@ of the timed steps (inputs resident in HBM, init excluded).  ``roofline`` is
 the dominant kernel's algorithmic bytes per launch / its mean launch time from
 HIP events recorded on the library's stream during the timed steps.
 ``cpu_baseline`` times the FP64 CPU oracle on a bounded sample on one core.
+
+Two further legs (skip with --no-legs) report the other throughputs of the
+same metric beside the plain one:
+  surrogate  training pairs harvested from the plain integrator on 32^3
+             lattices (3 seeds x 20 steps), the network trained on the GPU,
+             then the 256^3 lattice (64 Gaussians, bolus at steps 0 and 50)
+             stepped plain and with the surrogate ODE phase (margin 1e-3), and
+             the per-step error and decision-flip rate of the surrogate against
+             the plain integrator on identical inputs;
+  batched    the batched64 ensemble.
 """
 import argparse
 import json
@@ -65,8 +75,9 @@ def cpu_model():
 
 
 def cpu_baseline(budget_s=20.0):
-    """The oracle as it stands (sparse-LU solves, NumPy ODE/CA) on one core,
-    timed on whole coupled steps of the 32^3 lattice of the same recipe."""
+    """The oracle as it stands (CG solves to rel. residual 1e-15, NumPy ODE and
+    CA) on one core, timed on whole coupled steps of the 32^3 lattice of the
+    same recipe."""
     from threadpoolctl import threadpool_limits
 
     from oracle import model as om
@@ -88,8 +99,156 @@ def cpu_baseline(budget_s=20.0):
     vox = tis.cell.size
     return {"value": vox * n / el, "unit": "voxel-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} coupled steps of a 32^3 lattice (same generator recipe), FP64 "
-                      f"sparse-LU solves, single thread, {el:.1f}s; host: {cpu_model()}, "
-                      f"{os.cpu_count()} logical CPUs"}
+                      f"diagonally scaled CG to rel. residual 1e-15, single thread, {el:.1f}s; "
+                      f"host: {cpu_model()}, {os.cpu_count()} logical CPUs"}
+
+
+def timed_run(reps, params, steps, stream, net=None, margin=1e-3):
+    """Steps `steps` coupled steps of a fresh context; returns wall time,
+    per-replicate stats and kernel times."""
+    import torch
+
+    from paper_2105_00448_amd import hca
+    sim = hca.Simulation(reps, params, stream=stream)
+    if net is not None:
+        sim.set_surrogate(net, margin)
+    sim.reset_kernel_times()
+    torch.cuda.synchronize()
+    sim.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = [sim.stats(r) for r in range(len(reps))]
+    kt = sim.kernel_times()
+    sim.close()
+    return el, st, kt
+
+
+def surrogate_leg(stream, steps, train_steps, margin=1e-3, err_steps=3, edge=256):
+    import torch
+
+    from paper_2105_00448_amd import hca, synth
+    dev = torch.device("cuda", 0)
+    log = lambda m: print(f"[bench:surrogate] {m}", file=sys.stderr, flush=True)
+    # training pairs from the plain integrator
+    t0 = time.perf_counter()
+    Xs, Ys = [], []
+    for seed in (1, 2, 3):
+        tis = synth.make_tissue(32, 8, seed=seed)
+        sched = synth.bolus_schedule([0])
+        with hca.Simulation([(tis.cell, tis.w, tis.seed, (sched.times, sched.amts))],
+                            hca.default_params(), stream=stream) as sim:
+            X = torch.empty((tis.cell.size, 6), device=dev)
+            Y = torch.empty((tis.cell.size, 3), device=dev)
+            for _ in range(20):
+                n = sim.harvest_step(X, Y)
+                Xs.append(X[:n].clone())
+                Ys.append(Y[:n].clone())
+    X, Y = torch.cat(Xs), torch.cat(Ys)
+    del Xs, Ys
+    t_harvest = time.perf_counter() - t0
+    log(f"{X.shape[0]} pairs in {t_harvest:.1f}s; training {train_steps} steps")
+    tr = hca.Trainer(X, Y, seed=1, stream=stream)
+    batch = 4096
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    l1 = tr.train(train_steps // 2, batch=batch, lr=2e-3)
+    l2 = tr.train(train_steps - train_steps // 2, batch=batch, lr=5e-4)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    losses = np.concatenate([l1, l2])
+    flop_per_sample = 3 * 2 * (6 * 64 + 2 * 64 * 64 + 64 * 3)   # forward + two backward products
+    net = tr.export()
+    # the large lattice, plain and with the surrogate
+    tis = synth.make_tissue(edge, 64, seed=4)
+    sched = synth.bolus_schedule([0, 50])
+    reps = [(tis.cell, tis.w, tis.seed, (sched.times, sched.amts))]
+    nvox = tis.cell.size
+    names = [hca.lib().hca_kernel_name(k).decode() for k in range(hca.lib().hca_num_kernels())]
+    log(f"{edge}^3 plain, {steps} steps")
+    el_p, st_p, kt_p = timed_run(reps, hca.default_params(profile=names.index("k_ode") + 2), steps,
+                                 stream)
+    log(f"{edge}^3 surrogate, {steps} steps")
+    el_s, st_s, kt_s = timed_run(reps, hca.default_params(profile=names.index("k_mlp_apply") + 2),
+                                 steps, stream, net, margin)
+    ode_p = kt_p["k_ode"]["ms"] / max(1, kt_p["k_ode"]["launches"])
+    ode_s = kt_s["k_mlp_apply"]["ms"] / max(1, kt_s["k_mlp_apply"]["launches"])
+    # error and decision flips on identical inputs
+    log(f"error at matched inputs, {err_steps} steps")
+    errs = []
+    with hca.Simulation(reps, hca.default_params(), stream=stream) as p, \
+            hca.Simulation(reps, hca.default_params(), stream=stream) as s:
+        s.set_surrogate(net, margin)
+        buf8 = torch.empty(nvox, dtype=torch.float64, device=dev)
+        buf1 = torch.empty(nvox, dtype=torch.uint8, device=dev)
+        for _ in range(err_steps):
+            p.run_phases(hca.PH_O2 | hca.PH_DRUGS)
+            for k in ("L", "K", "G1", "G2", "P", "Vc", "phi"):
+                b = buf1 if k == "L" else buf8
+                p.field_to_device(k, b)
+                s.set_field_from_device(k, b)
+            p.run_phases(hca.PH_ODE)
+            s.run_phases(hca.PH_ODE)
+            L = p.field_to_device("L", torch.empty(nvox, dtype=torch.uint8, device=dev))
+            occ, can = L != 0, L == 1
+            e = {}
+            for k in ("P", "Vc", "phi"):
+                a = s.field_to_device(k, torch.empty(nvox, dtype=torch.float64, device=dev))
+                b = p.field_to_device(k, torch.empty(nvox, dtype=torch.float64, device=dev))
+                m = can if k == "phi" else occ
+                e[k] = ((a[m] - b[m]).abs().max() / b[m].abs().max()).item()
+                if k == "phi":
+                    e["flips"] = int(((a[can] >= 1.0) != (b[can] >= 1.0)).sum().item())
+                    e["cancer"] = int(can.sum().item())
+            e["fallbacks"] = s.stats()["sur_fallbacks"]
+            e["occupied"] = int(occ.sum().item())
+            errs.append(e)
+            p.run_phases(hca.PH_CA | hca.PH_STATS | hca.PH_ADVANCE)
+    tr.close()
+    return {
+        "workload": f"surrogate ODE: {edge}^3 voxels, 64-Gaussian density, bolus at steps 0 and "
+                    f"50, {steps} steps; network 6-64-64-64-3 GELU(erf), BF16 MFMA / FP32 "
+                    f"accumulation; plain-integrator fallback within {margin} of phi = 1",
+        "value_plain": nvox * steps / el_p,
+        "value_surrogate": nvox * steps / el_s,
+        "unit": "voxel-steps/s",
+        "step_speedup": el_p / el_s,
+        "ms_per_step_plain": el_p / steps * 1e3,
+        "ms_per_step_surrogate": el_s / steps * 1e3,
+        "ode_phase_ms_plain": ode_p,
+        "ode_phase_ms_surrogate": ode_s,
+        "ode_phase_speedup": ode_p / ode_s if ode_s > 0 else None,
+        "fallback_frac_last_step": st_s[0]["sur_fallbacks"]
+        / max(1, st_s[0]["sur_fallbacks"] + st_s[0]["sur_voxels"]),
+        "n_cancer_end": {"plain": st_p[0]["n_cancer"], "surrogate": st_s[0]["n_cancer"]},
+        "error_matched_inputs": {
+            "steps": err_steps,
+            "P_max_rel": max(e["P"] for e in errs),
+            "Vc_max_rel": max(e["Vc"] for e in errs),
+            "phi_max_rel": max(e["phi"] for e in errs),
+            "flip_rate": sum(e["flips"] for e in errs) / max(1, sum(e["cancer"] for e in errs)),
+            "fallback_frac": sum(e["fallbacks"] for e in errs) / max(1, sum(e["occupied"] for e in errs)),
+        },
+        "training": {"pairs": int(X.shape[0]), "harvest_s": t_harvest, "steps": train_steps,
+                     "batch": batch, "seconds": t_train,
+                     "samples_per_s": train_steps * batch / t_train,
+                     "tflops": train_steps * batch * flop_per_sample / t_train / 1e12,
+                     "loss_first": float(losses[:10].mean()), "loss_last": float(losses[-50:].mean())},
+    }
+
+
+def batched_leg(stream, steps=None):
+    from paper_2105_00448_amd import hca
+    reps, cfg, cfg_steps = make_workload("batched64")
+    steps = steps or cfg_steps
+    nvox = sum(r[0].size for r in reps)
+    print(f"[bench:batched] {len(reps)} replicates, {nvox} voxels, {steps} steps",
+          file=sys.stderr, flush=True)
+    el, st, _ = timed_run(reps, hca.default_params(), steps, stream)
+    return {"workload": cfg["workload"], "value": nvox * steps / el, "unit": "voxel-steps/s",
+            "voxels": nvox, "steps": steps, "ms_per_step": el / steps * 1e3}
 
 
 def main():
@@ -103,6 +262,12 @@ def main():
                     help="levels with at most this many cells go to the one-workgroup solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-legs", action="store_true", help="plain workload only")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device three times (a kernel of known "
+                         "traffic for scaling hardware byte counters)")
+    ap.add_argument("--sur-steps", type=int, default=100)
+    ap.add_argument("--train-steps", type=int, default=4000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -117,6 +282,16 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
 
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"[bench] copy calibration: 3 x {args.copy_calibration} MiB", file=sys.stderr,
+              flush=True)
     print(f"[bench] generating workload {args.workload}", file=sys.stderr, flush=True)
     reps, cfg, cfg_steps = make_workload(args.workload)
     solver_kw = {"precond": args.precond}
@@ -125,15 +300,28 @@ def main():
     steps = args.steps if args.steps is not None else cfg_steps
     nvox = sum(r[0].size for r in reps)
 
-    # warm-up on a throwaway context (code loading, clocks), then the timed
-    # run from step 0 of the workload
+    # warm-up on a throwaway context (code loading, clocks), every kernel
+    # class timed to find the dominant one; then the timed run from step 0 of
+    # the workload with HIP events around that class only (events around every
+    # launch would add their own overhead to the timed steps)
+    names = [hca.lib().hca_kernel_name(k).decode() for k in range(hca.lib().hca_num_kernels())]
+    dom_class, warm_share = None, None
     if args.warmup > 0:
-        p = hca.default_params(**solver_kw)
+        p = hca.default_params(profile=0 if args.no_profile else 1, **solver_kw)
         with hca.Simulation(reps, p, stream=stream) as sim:
             sim.step(args.warmup)
+            kt_w = sim.kernel_times()
+        if not args.no_profile:
+            real = {k: v for k, v in kt_w.items() if v["launches"] > 0 and v["bytes_per_launch"] > 0}
+            dom_class = names.index(max(real, key=lambda k: real[k]["ms"]))
+            tot = sum(v["ms"] for v in kt_w.values())
+            warm_share = {k: round(v["ms"] / tot, 4) for k, v in kt_w.items() if v["ms"] > 0}
         print(f"[bench] warm-up {args.warmup} steps done", file=sys.stderr, flush=True)
+    if dom_class is None and not args.no_profile:
+        dom_class = names.index("k_cg_apply")
 
-    p = hca.default_params(profile=0 if args.no_profile else 1, **solver_kw)
+    prof = 0 if args.no_profile else dom_class + 2
+    p = hca.default_params(profile=prof, **solver_kw)
     t_init = time.perf_counter()
     sim = hca.Simulation(reps, p, stream=stream)
     t_init = time.perf_counter() - t_init
@@ -169,9 +357,8 @@ def main():
                        mg_coarse_max=p.mg_coarse_max),
     }
     if not args.no_profile:
-        real = {k: v for k, v in kt.items() if v["launches"] > 0 and v["bytes_per_launch"] > 0}
-        dom = max(real, key=lambda k: real[k]["ms"])
-        d = real[dom]
+        dom = names[dom_class]
+        d = kt[dom]
         mean_s = d["ms"] / d["launches"] * 1e-3
         achieved = d["bytes_per_launch"] / mean_s / 1e9
         rec["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved,
@@ -179,13 +366,16 @@ def main():
                            "traffic": None, "mean_launch_us": mean_s * 1e6,
                            "launches": d["launches"],
                            "bytes_per_launch": d["bytes_per_launch"]}
-        tot = sum(v["ms"] for v in kt.values())
-        rec["kernel_share"] = {k: round(v["ms"] / tot, 4) for k, v in kt.items() if v["ms"] > 0}
+        if warm_share:
+            rec["kernel_share_warmup"] = warm_share
     rec["solver"] = {"cg_iters_last_step": st[0]["cg_iters"],
                      "relres_last_step": st[0]["cg_relres"]}
     rec["cells"] = {"cancer": sum(s["n_cancer"] for s in st),
                     "divisions": sum(s["total_divisions"] for s in st),
                     "kills": sum(s["total_kills"] for s in st)}
+    if not args.no_legs:
+        rec["surrogate"] = surrogate_leg(stream, args.sur_steps, args.train_steps)
+        rec["batched"] = batched_leg(stream)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline()

@@ -98,7 +98,8 @@ typedef struct hca_params {
   double init_rtol;        /* steady oxygen: Picard until the nonlinear residual
                               is below init_rtol ||b||                          */
   int32_t init_maxit;      /* Picard iterations                                  */
-  int32_t profile;         /* 1 = time kernels with HIP events (hca_kernel_time) */
+  int32_t profile;         /* time kernels with HIP events (hca_kernel_time):
+                              0 off, 1 every kernel class, k + 2 class k only  */
 } hca_params;
 
 /* One replicate's inputs.  hca_init deep-copies every array; the caller keeps
@@ -192,7 +193,7 @@ hca_status hca_set_step(hca_ctx* c, int64_t step);
 
 hca_status hca_stats(hca_ctx* c, int rep, hca_stats_t* out);
 
-/* With params.profile = 1: accumulated device time (ms) and launch count of
+/* With params.profile set: accumulated device time (ms) and launch count of
  * kernel class `kernel` (see hca_kernel_name) since the last reset. */
 hca_status hca_kernel_time(hca_ctx* c, int kernel, double* ms, int64_t* launches,
                            double* bytes_per_launch);

@@ -91,23 +91,80 @@ __device__ inline float nb_sum_xy(const Geo<UNI>& G, int x, int y, int z, long l
   return s;
 }
 
-// March one (x, y) column over [z0, z1): f(z, i, v_i, sum_J g_IJ v_J).
+// LDS plane of one tile with a one-cell frame: (tx + 2) (256/tx + 2) values.
+constexpr int kPlaneMaxF = 400;
+
+// Marches a tile over [t.z0, t.z1) and calls f(z, i, v_i, sum_J g_IJ v_J)
+// for the tile's cells inside the level, v = V(x, y, z, index) possibly
+// formed on the fly.  Each plane of V with its x/y frame is formed once into
+// LDS (double buffered), so V is evaluated about once per cell instead of at
+// every neighbour; the neighbour terms are added in the order -x, +x, -y, +y,
+// -z, +z.  Called by the whole workgroup (it synchronises).
 template <bool UNI, typename VF, typename F>
-__device__ inline void mg_column(const Geo<UNI>& G, int x, int y, int z0, int z1, long long base,
-                                 VF V, F f) {
+__device__ inline void mg_plane(const Geo<UNI>& G, const Tile& t, int tx, long long base,
+                                float (*lds)[kPlaneMaxF], VF V, F f) {
+  const int ty = kBlock / tx;
+  const int lx = (int)(threadIdx.x % tx), ly = (int)(threadIdx.x / tx);
+  const int x = t.x0 + lx, y = t.y0 + ly;
+  const bool valid = x < G.nx && y < G.ny;
+  const int W = tx + 2;
+  const int o = (ly + 1) * W + lx + 1;
+  const int nframe = 2 * W + 2 * ty;
   const long long plane = (long long)G.nx * G.ny;
+  auto fill = [&](float* buf, int z) {
+    const long long pz = base + plane * z;
+    buf[o] = valid ? V(x, y, z, pz + x + (long long)G.nx * y) : 0.f;
+    for (int k = threadIdx.x; k < nframe; k += kBlock) {
+      int hx, hy;
+      if (k < W) {
+        hx = k;
+        hy = 0;
+      } else if (k < 2 * W) {
+        hx = k - W;
+        hy = ty + 1;
+      } else if (k < 2 * W + ty) {
+        hx = 0;
+        hy = 1 + k - 2 * W;
+      } else {
+        hx = W - 1;
+        hy = 1 + k - 2 * W - ty;
+      }
+      const int gx = t.x0 + hx - 1, gy = t.y0 + hy - 1;
+      const bool in = gx >= 0 && gx < G.nx && gy >= 0 && gy < G.ny;
+      buf[hy * W + hx] = in ? V(gx, gy, z, pz + gx + (long long)G.nx * gy) : 0.f;
+    }
+  };
+  const int z0 = t.z0, z1 = t.z1;
   long long i = base + x + (long long)G.nx * (y + (long long)G.ny * z0);
-  float vm = z0 > 0 ? V(x, y, z0 - 1, i - plane) : 0.f;
-  float vc = V(x, y, z0, i);
+  float* cur = lds[0];
+  float* nxt = lds[1];
+  __syncthreads();   // the previous tile's readers are done with both buffers
+  fill(cur, z0);
+  float vm = (valid && z0 > 0) ? V(x, y, z0 - 1, i - plane) : 0.f;
+  __syncthreads();
+  float vc = cur[o];
   for (int z = z0; z < z1; ++z) {
     const bool zr = z + 1 < G.nz;
-    const float vp = zr ? V(x, y, z + 1, i + plane) : 0.f;
-    float s = nb_sum_xy(G, x, y, z, i, V);
-    if (z > 0) s += G.gz(x, y, z - 1) * vm;
-    if (zr) s += G.gz(x, y, z) * vp;
-    f(z, i, vc, s);
+    if (zr) fill(nxt, z + 1);
+    float s = 0.f;
+    if (valid) {
+      if (x > 0) s += G.gx(x - 1, y, z) * cur[o - 1];
+      if (x + 1 < G.nx) s += G.gx(x, y, z) * cur[o + 1];
+      if (y > 0) s += G.gy(x, y - 1, z) * cur[o - W];
+      if (y + 1 < G.ny) s += G.gy(x, y, z) * cur[o + W];
+    }
+    __syncthreads();
+    const float vp = zr ? nxt[o] : 0.f;
+    if (valid) {
+      if (z > 0) s += G.gz(x, y, z - 1) * vm;
+      if (zr) s += G.gz(x, y, z) * vp;
+      f(z, i, vc, s);
+    }
     vm = vc;
     vc = vp;
+    float* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
     i += plane;
   }
 }
@@ -190,15 +247,16 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarsen(MgLevel Lf, MgLevel Lc,
 template <bool L0, typename RT>
 __global__ void __launch_bounds__(kBlock) k_mg_pre(MgLevel Lk, float omega,
                                                    const RT* __restrict__ r, const SolveScal* ss) {
+  __shared__ float lds[2][kPlaneMaxF];
   const float* __restrict__ dinv = Lk.dinv;
   float* __restrict__ u = Lk.u;
   FOR_MY_TILES(Lk.ntiles) {
-    const TileXY t = tile_xy(Lk.tiles, Lk.reps, ti);
-    if (ss[t.rep].done || !t.valid) continue;
+    const Tile t = Lk.tiles[ti];
+    if (ss[t.rep].done) continue;
     const MgRep m = Lk.reps[t.rep];
     const Geo<L0> G = geo_of<L0>(m);
     auto U1 = [&](int, int, int, long long j) { return omega * dinv[j] * (float)r[j]; };
-    mg_column(G, t.x, t.y, t.z0, t.z1, m.off, U1, [&](int, long long i, float u1, float s) {
+    mg_plane(G, t, m.tx, m.off, lds, U1, [&](int, long long i, float u1, float s) {
       u[i] = (1.f - omega) * u1 + omega * dinv[i] * ((float)r[i] + s);
     });
   }
@@ -251,20 +309,21 @@ __global__ void __launch_bounds__(kBlock) k_mg_restrict(MgLevel Lf, MgLevel Lc,
 template <bool L0, typename RT>
 __global__ void __launch_bounds__(kBlock) k_mg_post1(MgLevel Lk, MgLevel Lc, float omega,
                                                      const RT* __restrict__ r, const SolveScal* ss) {
+  __shared__ float lds[2][kPlaneMaxF];
   const float* __restrict__ dinv = Lk.dinv;
   const float* __restrict__ u = Lk.u;
   const float* __restrict__ e = Lc.u;
   float* __restrict__ out = Lk.ualt;
   FOR_MY_TILES(Lk.ntiles) {
-    const TileXY t = tile_xy(Lk.tiles, Lk.reps, ti);
-    if (ss[t.rep].done || !t.valid) continue;
+    const Tile t = Lk.tiles[ti];
+    if (ss[t.rep].done) continue;
     const MgRep m = Lk.reps[t.rep];
     const MgRep mc = Lc.reps[t.rep];
     const Geo<L0> G = geo_of<L0>(m);
     auto U3 = [&](int x, int y, int z, long long j) {
       return u[j] + e[mc.off + (x >> 1) + (long long)mc.nx * ((y >> 1) + (long long)mc.ny * (z >> 1))];
     };
-    mg_column(G, t.x, t.y, t.z0, t.z1, m.off, U3, [&](int, long long i, float u3, float s) {
+    mg_plane(G, t, m.tx, m.off, lds, U3, [&](int, long long i, float u3, float s) {
       out[i] = (1.f - omega) * u3 + omega * dinv[i] * ((float)r[i] + s);
     });
   }
@@ -274,17 +333,18 @@ template <bool L0, typename RT>
 __global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float omega,
                                                      const RT* __restrict__ r, SolverBufs sb) {
   __shared__ double lds4[4];
+  __shared__ float lds[2][kPlaneMaxF];
   const float* __restrict__ dinv = Lk.dinv;
   const float* __restrict__ u = Lk.ualt;
   FOR_MY_TILES(Lk.ntiles) {
-    const TileXY t = tile_xy(Lk.tiles, Lk.reps, ti);
+    const Tile t = Lk.tiles[ti];
     if (sb.ss[t.rep].done) continue;
     const MgRep m = Lk.reps[t.rep];
     const Geo<L0> G = geo_of<L0>(m);
     double rz = 0.0;
-    if (t.valid) {
+    {
       auto U4 = [&](int, int, int, long long j) { return u[j]; };
-      mg_column(G, t.x, t.y, t.z0, t.z1, m.off, U4, [&](int, long long i, float u4, float s) {
+      mg_plane(G, t, m.tx, m.off, lds, U4, [&](int, long long i, float u4, float s) {
         const float u5 = (1.f - omega) * u4 + omega * dinv[i] * ((float)r[i] + s);
         if (L0) {
           sb.z[i] = (double)u5;

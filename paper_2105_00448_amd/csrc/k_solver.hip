@@ -32,6 +32,7 @@ struct TileCoord {
   int nx, ny, nz;
   long long off;
   double a;
+  int x0, y0, tx, ty, lx, ly;   // tile origin and shape, thread position in it
 };
 
 __device__ inline TileCoord tile_coord(const Work& w, int ti) {
@@ -39,8 +40,14 @@ __device__ inline TileCoord tile_coord(const Work& w, int ti) {
   const RepDev rp = w.reps[t.rep];
   TileCoord tc;
   tc.rep = t.rep;
-  tc.x = t.x0 + (int)(threadIdx.x % rp.tx);
-  tc.y = t.y0 + (int)(threadIdx.x / rp.tx);
+  tc.tx = rp.tx;
+  tc.ty = kBlock / rp.tx;
+  tc.lx = (int)(threadIdx.x % rp.tx);
+  tc.ly = (int)(threadIdx.x / rp.tx);
+  tc.x0 = t.x0;
+  tc.y0 = t.y0;
+  tc.x = t.x0 + tc.lx;
+  tc.y = t.y0 + tc.ly;
   tc.z0 = t.z0;
   tc.z1 = t.z1;
   tc.nx = rp.nx;
@@ -52,34 +59,79 @@ __device__ inline TileCoord tile_coord(const Work& w, int ti) {
   return tc;
 }
 
-// Marches one column (x, y) over [z0, z1) and calls f(i, deg, u_i, (A u)_i)
-// where u = U(j) is the operand (possibly formed on the fly) and
-// (A u)_i = (c_i + a deg) u_i - a sum_nb u_j.
+// LDS plane of one tile with a one-cell frame: (tx + 2) (256/tx + 2) values,
+// at most 66 x 6 (tx = 64).
+constexpr int kPlaneMax = 400;
+
+// Marches the tile over [z0, z1) and calls f(i, deg, u_i, (A u)_i) for every
+// voxel of the tile inside the lattice, where u = U(j) is the operand
+// (possibly formed on the fly) and (A u)_i = (c_i + a deg) u_i - a sum_nb u_j.
+// Each plane of u, with its x/y frame, is formed once into LDS (double
+// buffered), so U is evaluated about once per voxel; outside the lattice the
+// frame holds 0, which adds nothing to the neighbour sum.  Called by the whole
+// workgroup (it synchronises).
 template <typename UF, typename F>
-__device__ inline void stencil_column(const TileCoord& tc, const double* __restrict__ c, UF U,
-                                      F f) {
+__device__ inline void plane_stencil(const TileCoord& tc, const double* __restrict__ c,
+                                     double (*lds)[kPlaneMax], UF U, F f) {
   const double a = tc.a;
+  const int W = tc.tx + 2;
+  const int o = (tc.ly + 1) * W + tc.lx + 1;
+  const int nframe = 2 * W + 2 * tc.ty;
   const long long plane = (long long)tc.nx * tc.ny;
-  long long i = tc.off + tc.x + (long long)tc.nx * (tc.y + (long long)tc.ny * tc.z0);
-  double um = tc.z0 > 0 ? U(i - plane) : 0.0;
-  double uc = U(i);
+  auto fill = [&](double* buf, int z) {
+    const long long pz = tc.off + plane * z;
+    buf[o] = tc.valid ? U(pz + tc.x + (long long)tc.nx * tc.y) : 0.0;
+    for (int k = threadIdx.x; k < nframe; k += kBlock) {
+      int hx, hy;
+      if (k < W) {
+        hx = k;
+        hy = 0;
+      } else if (k < 2 * W) {
+        hx = k - W;
+        hy = tc.ty + 1;
+      } else if (k < 2 * W + tc.ty) {
+        hx = 0;
+        hy = 1 + k - 2 * W;
+      } else {
+        hx = W - 1;
+        hy = 1 + k - 2 * W - tc.ty;
+      }
+      const int gx = tc.x0 + hx - 1, gy = tc.y0 + hy - 1;
+      const bool in = gx >= 0 && gx < tc.nx && gy >= 0 && gy < tc.ny;
+      buf[hy * W + hx] = in ? U(pz + gx + (long long)tc.nx * gy) : 0.0;
+    }
+  };
   const bool xl = tc.x > 0, xr = tc.x + 1 < tc.nx, yl = tc.y > 0, yr = tc.y + 1 < tc.ny;
   const int deg_xy = (int)xl + (int)xr + (int)yl + (int)yr;
+  long long i = tc.off + tc.x + (long long)tc.nx * (tc.y + (long long)tc.ny * tc.z0);
+  double* cur = lds[0];
+  double* nxt = lds[1];
+  __syncthreads();   // the previous tile's readers are done with both buffers
+  fill(cur, tc.z0);
+  double um = (tc.valid && tc.z0 > 0) ? U(i - plane) : 0.0;
+  __syncthreads();
+  double uc = cur[o];
   for (int z = tc.z0; z < tc.z1; ++z) {
     const bool zl = z > 0, zr = z + 1 < tc.nz;
-    const double up = zr ? U(i + plane) : 0.0;
-    double s = 0.0;
-    if (xl) s += U(i - 1);
-    if (xr) s += U(i + 1);
-    if (yl) s += U(i - tc.nx);
-    if (yr) s += U(i + tc.nx);
-    if (zl) s += um;
-    if (zr) s += up;
-    const int deg = deg_xy + (int)zl + (int)zr;
-    const double Au = (c[i] + a * deg) * uc - a * s;
-    f(i, deg, uc, Au);
+    if (zr) fill(nxt, z + 1);
+    double s = cur[o - 1];
+    s += cur[o + 1];
+    s += cur[o - W];
+    s += cur[o + W];
+    __syncthreads();
+    const double up = zr ? nxt[o] : 0.0;
+    s += um;
+    s += up;
+    if (tc.valid) {
+      const int deg = deg_xy + (int)zl + (int)zr;
+      const double Au = (c[i] + a * deg) * uc - a * s;
+      f(i, deg, uc, Au);
+    }
     um = uc;
     uc = up;
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
     i += plane;
   }
 }
@@ -90,14 +142,15 @@ __global__ void __launch_bounds__(kBlock) k_cg_start(Work w, const double* __res
                                                      const double* __restrict__ x,
                                                      SolverBufs sb) {
   __shared__ double lds4[4];
+  __shared__ double lds[2][kPlaneMax];
   int t0, t1;
   work_range(w.ntiles, t0, t1);
   for (int ti = t0; ti < t1; ++ti) {
     const TileCoord tc = tile_coord(w, ti);
     const double a = tc.a;
     double bb = 0.0, rr = 0.0, rz = 0.0;
-    if (tc.valid) {
-      stencil_column(tc, c, [&](long long j) { return x[j]; },
+    {
+      plane_stencil(tc, c, lds, [&](long long j) { return x[j]; },
                      [&](long long i, int deg, double, double Ax) {
                        const double bi = b[i];
                        const double r = bi - Ax;
@@ -127,6 +180,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, const double* __res
                                                      double* __restrict__ pnew,
                                                      double* __restrict__ q, SolverBufs sb) {
   __shared__ double lds4[4];
+  __shared__ double lds[2][kPlaneMax];
   int t0, t1;
   work_range(w.ntiles, t0, t1);
   for (int ti = t0; ti < t1; ++ti) {
@@ -136,9 +190,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, const double* __res
     const double beta = ssr->beta;
     const bool first = ssr->first != 0;
     double pq = 0.0;
-    if (tc.valid) {
+    {
       auto U = [&](long long j) { return first ? z[j] : z[j] + beta * pold[j]; };
-      stencil_column(tc, c, U, [&](long long i, int, double pc, double Ap) {
+      plane_stencil(tc, c, lds, U, [&](long long i, int, double pc, double Ap) {
         pnew[i] = pc;
         q[i] = Ap;
         pq += pc * Ap;

@@ -178,8 +178,10 @@ hipEvent_t take_event(hca_ctx* c) {
     c->free_events.pop_back();
     return e;
   }
+  // timing-only events: no system-scope fence (no cache writeback and
+  // invalidation between the kernels being timed)
   hipEvent_t e;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -188,19 +190,24 @@ double bpv_of(const hca_ctx* c, int kc) {
   return kBytesPerVoxel[kc];
 }
 
+// params.profile: 0 off, 1 every kernel class, k + 2 class k only.
+inline bool prof_on(const hca_ctx* c, int kc) {
+  return c->prm.profile == 1 || c->prm.profile == kc + 2;
+}
+
 struct ProfScope {
   hca_ctx* c;
   int kc;
   int tag;
   hipEvent_t a = nullptr;
   ProfScope(hca_ctx* c_, int kc_, int tag_) : c(c_), kc(kc_), tag(tag_) {
-    if (c->prm.profile) {
+    if (prof_on(c, kc)) {
       a = take_event(c);
       if (a) (void)hipEventRecord(a, c->stream);
     }
   }
   ~ProfScope() {
-    if (!c->prm.profile || !a) return;
+    if (!a) return;
     hipEvent_t b = take_event(c);
     if (!b) return;
     (void)hipEventRecord(b, c->stream);
@@ -256,7 +263,7 @@ int mg_segment_class(int seg) {
 void mg_hook(void* p, int seg, int begin) {
   MgProf* m = (MgProf*)p;
   hca_ctx* c = m->c;
-  if (!c->prm.profile) return;
+  if (!prof_on(c, mg_segment_class(seg))) return;
   if (begin) {
     m->start[seg] = take_event(c);
     if (m->start[seg]) (void)hipEventRecord(m->start[seg], c->stream);
@@ -519,7 +526,8 @@ hca_status validate_params(const hca_params* p, std::string& msg) {
     }
   if (!std::isfinite(p->k2pp) || p->b_int[0] < 1 || p->b_int[1] < 1 || p->b_int[0] > 64 ||
       p->b_int[1] > 64 || p->ode_substeps < 1 || p->cg_maxit < 1 || p->init_maxit < 1 ||
-      (p->precond != 0 && p->precond != 1) || p->mg_coarse_max < 1) {
+      (p->precond != 0 && p->precond != 1) || p->mg_coarse_max < 1 || p->profile < 0 ||
+      p->profile > KC_COUNT + 1) {
     msg = "integer parameter out of range";
     return HCA_E_INVALID;
   }
@@ -552,7 +560,8 @@ void add_tiles(std::vector<Tile>& v, int rep, int nx, int ny, int nz, int tx, in
       }
 }
 
-constexpr double kTileTarget = 1024.0;
+// Stencil tiles per lattice the z-chunking aims at (tuning knob HCA_TILE_TARGET).
+double g_tile_target = 1024.0;
 
 template <typename T>
 hca_status upload(hca_ctx* c, T** p, const std::vector<T>& v) {
@@ -585,7 +594,7 @@ RepDev lattice_entry(const RepHost& R, long long off, int idx, std::vector<FlatB
     flat.push_back(fb);
   }
   d.tx = pick_tx(R.nx);
-  const int tz = pick_tz(R.nx, R.ny, R.nz, d.tx, kTileTarget);
+  const int tz = pick_tz(R.nx, R.ny, R.nz, d.tx, g_tile_target);
   d.tile_b0 = (int)tiles.size();
   add_tiles(tiles, idx, R.nx, R.ny, R.nz, d.tx, tz);
   d.tile_nb = (int)tiles.size() - d.tile_b0;
@@ -602,6 +611,10 @@ hca_status build_tables(hca_ctx* c, const hca_replicate* in) {
     if (v > 0) max_blocks = v;
   }
   if (const char* e = getenv("HCA_XCD_REMAP")) g_xcd_remap = atoi(e) != 0;
+  if (const char* e = getenv("HCA_TILE_TARGET")) {
+    const double v = atof(e);
+    if (v >= 1.0) g_tile_target = v;
+  }
   {
     std::vector<RepDev> rd;
     std::vector<FlatBlk> flat;
@@ -799,7 +812,7 @@ hca_status build_mg(hca_ctx* c) {
           m.tx = pick_tx(m.nx);
           m.off = off;
           off += (long long)m.nx * m.ny * m.nz;
-          const int tz = pick_tz(m.nx, m.ny, m.nz, m.tx, kTileTarget);
+          const int tz = pick_tz(m.nx, m.ny, m.nz, m.tx, g_tile_target);
           if (m.active) {
             m.tile_b0 = (int)tiles.size();
             add_tiles(tiles, s, m.nx, m.ny, m.nz, m.tx, tz);

@@ -243,6 +243,13 @@ class Simulation:
         self._check(self._lib.hca_set_field(self._h, rep, f, a.ctypes.data, a.nbytes, 0),
                     "hca_set_field")
 
+    def set_field_from_device(self, name, tensor, rep=0):
+        """Overwrite a state field from a torch device tensor (device-to-device)."""
+        f = FIELDS[name]
+        self._check(self._lib.hca_set_field(self._h, rep, f, tensor.data_ptr(),
+                                            tensor.numel() * tensor.element_size(), 1),
+                    "hca_set_field")
+
     def stats(self, rep=0):
         s = Stats()
         self._check(self._lib.hca_stats(self._h, rep, C.byref(s)), "hca_stats")
