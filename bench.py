@@ -262,7 +262,10 @@ def main():
                     help="levels with at most this many cells go to the one-workgroup solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--graphs", type=int, default=1, help="1: replay captured CG iterations")
     ap.add_argument("--no-legs", action="store_true", help="plain workload only")
+    ap.add_argument("--legs", default="surrogate,batched",
+                    help="comma-separated further legs: surrogate, batched")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -294,7 +297,7 @@ def main():
               flush=True)
     print(f"[bench] generating workload {args.workload}", file=sys.stderr, flush=True)
     reps, cfg, cfg_steps = make_workload(args.workload)
-    solver_kw = {"precond": args.precond}
+    solver_kw = {"precond": args.precond, "graphs": args.graphs}
     if args.mg_coarse_max is not None:
         solver_kw["mg_coarse_max"] = args.mg_coarse_max
     steps = args.steps if args.steps is not None else cfg_steps
@@ -373,8 +376,10 @@ def main():
     rec["cells"] = {"cancer": sum(s["n_cancer"] for s in st),
                     "divisions": sum(s["total_divisions"] for s in st),
                     "kills": sum(s["total_kills"] for s in st)}
-    if not args.no_legs:
+    legs = [] if args.no_legs else [x for x in args.legs.split(",") if x]
+    if "surrogate" in legs:
         rec["surrogate"] = surrogate_leg(stream, args.sur_steps, args.train_steps)
+    if "batched" in legs:
         rec["batched"] = batched_leg(stream)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)

@@ -100,6 +100,8 @@ typedef struct hca_params {
   int32_t init_maxit;      /* Picard iterations                                  */
   int32_t profile;         /* time kernels with HIP events (hca_kernel_time):
                               0 off, 1 every kernel class, k + 2 class k only  */
+  int32_t graphs;          /* 1: replay captured HIP graphs of CG iterations
+                              (only while profile = 0); 0: direct launches     */
 } hca_params;
 
 /* One replicate's inputs.  hca_init deep-copies every array; the caller keeps

@@ -106,25 +106,59 @@ struct Pre {
   f32x16 z[3][2];   // hidden pre-activations (training)
 };
 
-// Accumulator initialised with the bias of each D row.
-__device__ inline f32x16 bias_acc(const float* __restrict__ b, int mt, int h) {
-  f32x16 acc;
+// Weight source: A operand of packed block `blk` (kPackL1/64 ...) for this
+// lane.  Bias source: accumulator of layer L (0..2), row tile mt, initialised
+// with the bias of each D row.
+struct GlobalNet {
+  const bf16x8* __restrict__ pk;
+  const float* __restrict__ th;
+  int lane;
+  __device__ inline bf16x8 A(int blk) const { return pk[blk * 64 + lane]; }
+  __device__ inline f32x16 bias(int L, int mt) const {
+    const float* b = th + (L == 0 ? kOb1 : L == 1 ? kOb2 : kOb3);
+    const int h = lane >> 5;
+    f32x16 acc;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) acc[j] = b[drow(mt, j, h)];
-  return acc;
-}
+    for (int j = 0; j < 16; ++j) acc[j] = b[drow(mt, j, h)];
+    return acc;
+  }
+  __device__ inline float b4(int o) const { return th[kOb4 + o]; }
+};
+
+// The forward operands held in registers for a wavefront's lifetime (88
+// VGPRs); hidden biases in LDS in D-row order, sb[((L*2 + mt)*2 + h)*16 + j].
+struct RegNet {
+  bf16x8 w[kPackFwd / 64];
+  const float* sb;   // LDS, 192 floats
+  float ob[kMlpOut];
+  int lane;
+  __device__ inline bf16x8 A(int blk) const { return w[blk]; }
+  __device__ inline f32x16 bias(int L, int mt) const {
+    const float4* q = reinterpret_cast<const float4*>(sb + ((L * 2 + mt) * 2 + (lane >> 5)) * 16);
+    f32x16 acc;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float4 v = q[k];
+      acc[4 * k + 0] = v.x;
+      acc[4 * k + 1] = v.y;
+      acc[4 * k + 2] = v.z;
+      acc[4 * k + 3] = v.w;
+    }
+    return acc;
+  }
+  __device__ inline float b4(int o) const { return ob[o]; }
+};
 
 // xin: layer-1 B operand (lanes of half 0 hold the 6 standardised inputs of
 // sample n = lane).  Returns the output accumulator including b4: outputs in
 // registers 0..2 of lanes 0..31.
-template <bool KEEP>
-__device__ inline f32x16 mlp_forward_tile(const bf16x8* __restrict__ pk, const float* __restrict__ th,
-                                          bf16x8 xin, int lane, Pre* pre, Hid* hs) {
+template <bool KEEP, typename NET>
+__device__ inline f32x16 mlp_forward_tile(const NET& net, bf16x8 xin, int lane, Pre* pre, Hid* hs) {
   const int h = lane >> 5;
   Hid H;
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt) {
-    f32x16 acc = mfma16(pk[kPackL1 + mt * 64 + lane], xin, bias_acc(th + kOb1, mt, h));
+    f32x16 acc = mfma16(net.A(kPackL1 / 64 + mt), xin, net.bias(0, mt));
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       float g, dg;
@@ -136,14 +170,13 @@ __device__ inline f32x16 mlp_forward_tile(const bf16x8* __restrict__ pk, const f
   if (KEEP) hs[0] = H;
 #pragma unroll
   for (int L = 1; L < 3; ++L) {
-    const int blk = L == 1 ? kPackL2 : kPackL3;
-    const float* bias = th + (L == 1 ? kOb2 : kOb3);
+    const int blk = (L == 1 ? kPackL2 : kPackL3) / 64;
     Hid Hn;
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
-      f32x16 acc = bias_acc(bias, mt, h);
+      f32x16 acc = net.bias(L, mt);
 #pragma unroll
-      for (int kb = 0; kb < 4; ++kb) acc = mfma16(pk[blk + (mt * 4 + kb) * 64 + lane], bop(H, kb), acc);
+      for (int kb = 0; kb < 4; ++kb) acc = mfma16(net.A(blk + mt * 4 + kb), bop(H, kb), acc);
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         float g, dg;
@@ -158,10 +191,10 @@ __device__ inline f32x16 mlp_forward_tile(const bf16x8* __restrict__ pk, const f
   f32x16 out = {};
   if (h == 0) {
 #pragma unroll
-    for (int o = 0; o < kMlpOut; ++o) out[o] = th[kOb4 + o];
+    for (int o = 0; o < kMlpOut; ++o) out[o] = net.b4(o);
   }
 #pragma unroll
-  for (int kb = 0; kb < 4; ++kb) out = mfma16(pk[kPackL4 + kb * 64 + lane], bop(H, kb), out);
+  for (int kb = 0; kb < 4; ++kb) out = mfma16(net.A(kPackL4 / 64 + kb), bop(H, kb), out);
   return out;
 }
 
@@ -174,14 +207,15 @@ __device__ inline bf16x8 input_operand(const float (&x)[kMlpIn], int h) {
 
 // Network outputs for the 64 samples of a wavefront, sample = lane:
 // tile 0 takes lanes 0..31, tile 1 lanes 32..63 (inputs moved down by 32).
-__device__ inline void forward64(const bf16x8* __restrict__ pk, const float* __restrict__ th,
-                                 const float (&x)[kMlpIn], int lane, float (&y)[kMlpOut]) {
+template <typename NET>
+__device__ inline void forward64(const NET& net, const float (&x)[kMlpIn], int lane,
+                                 float (&y)[kMlpOut]) {
   const int h = lane >> 5;
   float x1[kMlpIn];
 #pragma unroll
   for (int f = 0; f < kMlpIn; ++f) x1[f] = __shfl(x[f], (lane & 31) + 32, 64);
-  const f32x16 o0 = mlp_forward_tile<false>(pk, th, input_operand(x, h), lane, nullptr, nullptr);
-  const f32x16 o1 = mlp_forward_tile<false>(pk, th, input_operand(x1, h), lane, nullptr, nullptr);
+  const f32x16 o0 = mlp_forward_tile<false>(net, input_operand(x, h), lane, nullptr, nullptr);
+  const f32x16 o1 = mlp_forward_tile<false>(net, input_operand(x1, h), lane, nullptr, nullptr);
 #pragma unroll
   for (int o = 0; o < kMlpOut; ++o) {
     const float t1 = __shfl(o1[o], lane & 31, 64);
@@ -189,13 +223,27 @@ __device__ inline void forward64(const bf16x8* __restrict__ pk, const float* __r
   }
 }
 
+// Network outputs for one 32-sample tile: sample = lane & 31, inputs taken
+// from lanes 0..31, outputs valid in lanes 0..31.
+template <typename NET>
+__device__ inline void forward32(const NET& net, const float (&x)[kMlpIn], int lane,
+                                 float (&y)[kMlpOut]) {
+  const f32x16 o = mlp_forward_tile<false>(net, input_operand(x, lane >> 5), lane, nullptr, nullptr);
+#pragma unroll
+  for (int k = 0; k < kMlpOut; ++k) y[k] = o[k];
+}
+
 // ---- surrogate in the coupled step ---------------------------------------------
 
-// Each wavefront takes 64 voxels per pass.  Occupied voxels get
-// (P, Vc) += network update and, for cancer cells, phi += its update.  A
-// cancer cell whose predicted phi lands within `margin` of the division
-// threshold 1, or (box mode) any voxel whose inputs leave the training range,
-// is advanced by the plain integrator instead.
+// Per flat work item, in runs of at most kFlatChunk voxels:
+//  1. the item's occupied voxels are listed in LDS, in voxel order;
+//  2. each wavefront evaluates the network on 32 listed voxels at a time,
+//     weights in registers; a voxel takes (P, Vc) += update and, for a cancer
+//     cell, phi += update;
+//  3. a cancer cell whose predicted phi lands within `margin` of the division
+//     threshold 1, or (box mode) a voxel whose inputs leave the training
+//     range, is queued instead and, after the network pass, advanced by the
+//     plain integrator, the queue spread over all lanes.
 __global__ void __launch_bounds__(kBlock) k_mlp_apply(Work w, DevParams p, MlpDev net,
                                                       const uint8_t* __restrict__ L,
                                                       const double* __restrict__ K,
@@ -204,59 +252,108 @@ __global__ void __launch_bounds__(kBlock) k_mlp_apply(Work w, DevParams p, MlpDe
                                                       double* __restrict__ P, double* __restrict__ Vc,
                                                       double* __restrict__ phi, Counters* cnt) {
   __shared__ unsigned long long lds4[4];
+  __shared__ int list[kFlatChunk];
+  __shared__ int fb_list[kFlatChunk];
+  __shared__ int wcnt[4];
+  __shared__ int n_fb_s;
+  __shared__ __attribute__((aligned(16))) float sbias[192];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = threadIdx.x; k < 192; k += kBlock) {
+    const int j = k & 15, h = (k >> 4) & 1, mt = (k >> 5) & 1, Ly = k >> 6;
+    const int ob = Ly == 0 ? kOb1 : Ly == 1 ? kOb2 : kOb3;
+    sbias[k] = net.theta[ob + drow(mt, j, h)];
+  }
+  RegNet R;
+#pragma unroll
+  for (int b = 0; b < kPackFwd / 64; ++b) R.w[b] = net.packed[b * 64 + lane];
+#pragma unroll
+  for (int o = 0; o < kMlpOut; ++o) R.ob[o] = net.theta[kOb4 + o];
+  R.sb = sbias;
+  R.lane = lane;
   int b0, b1;
   work_range(w.nflat, b0, b1);
   for (int it = b0; it < b1; ++it) {
     const FlatBlk fb = w.flat[it];
-    const long long off = w.reps[fb.rep].off;
-    unsigned long long n_sur = 0, n_fb = 0;
-    for (long long v0 = fb.begin + 64 * wave; v0 < fb.end; v0 += kBlock) {
-      const long long li = v0 + lane;
-      const bool inr = li < fb.end;
-      const long long i = off + (inr ? li : fb.begin);
-      const uint8_t l = inr ? L[i] : 0;
-      double raw[kMlpIn] = {0, 0, 0, 0, 0, 0};
-      if (l != 0) {
-        raw[0] = K[i];
-        raw[1] = G1[i];
-        raw[2] = G2[i];
-        raw[3] = P[i];
-        raw[4] = Vc[i];
-        raw[5] = phi[i];
+    unsigned long long n_sur = 0, n_fbk = 0;
+    // the item in runs of at most kFlatChunk voxels (the LDS list size)
+    for (long long c0 = fb.begin; c0 < fb.end; c0 += kFlatChunk) {
+      const long long off = w.reps[fb.rep].off + c0;
+      const int len = (int)min((long long)kFlatChunk, fb.end - c0);
+      // 1. list the occupied voxels (index within the run), in order
+      if (threadIdx.x == 0) n_fb_s = 0;
+      int n = 0;
+      for (int base = 0; base < len; base += kBlock) {
+        const int li = base + (int)threadIdx.x;
+        const bool occ = li < len && L[off + li] != 0;
+        const unsigned long long bal = __ballot(occ);
+        const int rank = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) wcnt[wave] = __popcll(bal);
+        __syncthreads();
+        int woff = 0;
+        for (int k = 0; k < wave; ++k) woff += wcnt[k];
+        if (occ) list[n + woff + rank] = li;
+        n += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+        __syncthreads();
       }
-      float x[kMlpIn];
-      bool inbox = true;
+      // 2. network pass, 32 listed voxels per wavefront step (lanes 0..31)
+      for (int s0 = 32 * wave; s0 < n; s0 += 32 * (kBlock / 64)) {
+        const int si = s0 + (lane & 31);
+        const bool act = si < n && lane < 32;
+        const long long i = off + (act ? list[si] : 0);
+        double raw[kMlpIn] = {0, 0, 0, 0, 0, 0};
+        uint8_t l = 0;
+        if (act) {
+          l = L[i];
+          raw[0] = K[i];
+          raw[1] = G1[i];
+          raw[2] = G2[i];
+          raw[3] = P[i];
+          raw[4] = Vc[i];
+          raw[5] = phi[i];
+        }
+        float x[kMlpIn];
+        bool inbox = true;
 #pragma unroll
-      for (int f = 0; f < kMlpIn; ++f) {
-        const float r = (float)raw[f];
-        inbox = inbox && r >= net.in_lo[f] && r <= net.in_hi[f];
-        x[f] = l != 0 ? (r - net.in_mean[f]) * net.in_scale[f] : 0.0f;
+        for (int f = 0; f < kMlpIn; ++f) {
+          const float r = (float)raw[f];
+          inbox = inbox && r >= net.in_lo[f] && r <= net.in_hi[f];
+          x[f] = act ? (r - net.in_mean[f]) * net.in_scale[f] : 0.0f;
+        }
+        float y[kMlpOut];
+        forward32(R, x, lane, y);
+        if (!act) continue;
+        const double dphi = (double)(y[2] * net.out_scale[2] + net.out_mean[2]);
+        const bool fallback =
+            (net.box && !inbox) || (l == 1 && fabs(raw[5] + dphi - 1.0) < net.margin);
+        if (fallback) {
+          fb_list[atomicAdd(&n_fb_s, 1)] = si;
+        } else {
+          P[i] = raw[3] + (double)(y[0] * net.out_scale[0] + net.out_mean[0]);
+          Vc[i] = raw[4] + (double)(y[1] * net.out_scale[1] + net.out_mean[1]);
+          if (l == 1) phi[i] = raw[5] + dphi;
+          ++n_sur;
+        }
       }
-      float y[kMlpOut];
-      forward64(net.packed, net.theta, x, lane, y);
-      if (l == 0) continue;
-      double pv = raw[3], vv = raw[4], ph = raw[5];
-      const double dphi = (double)(y[2] * net.out_scale[2] + net.out_mean[2]);
-      const bool fallback = (net.box && !inbox) || (l == 1 && fabs(ph + dphi - 1.0) < net.margin);
-      if (fallback) {
-        ode_voxel(p, l, raw[0], pv, vv, ph);
-        ++n_fb;
-      } else {
-        pv += (double)(y[0] * net.out_scale[0] + net.out_mean[0]);
-        vv += (double)(y[1] * net.out_scale[1] + net.out_mean[1]);
-        if (l == 1) ph += dphi;
-        ++n_sur;
+      __syncthreads();
+      // 3. the queued voxels by the plain integrator (voxels are independent,
+      //    so the queue order does not matter)
+      const int nfb = n_fb_s;
+      for (int q = threadIdx.x; q < nfb; q += kBlock) {
+        const long long i = off + list[fb_list[q]];
+        const uint8_t l = L[i];
+        double pv = P[i], vv = Vc[i], ph = phi[i];
+        ode_voxel(p, l, K[i], pv, vv, ph);
+        P[i] = pv;
+        Vc[i] = vv;
+        if (l == 1) phi[i] = ph;
       }
-      P[i] = pv;
-      Vc[i] = vv;
-      if (l == 1) phi[i] = ph;
+      n_fbk += (unsigned long long)nfb;
+      __syncthreads();   // list, fb_list and n_fb_s are reused by the next run
     }
     const unsigned long long a = block_sum_u64(n_sur, lds4);
-    const unsigned long long b = block_sum_u64(n_fb, lds4);
     if (threadIdx.x == 0) {
       if (a) atomicAdd(&cnt[fb.rep].sur_voxels, a);
-      if (b) atomicAdd(&cnt[fb.rep].sur_fallbacks, b);
+      if (n_fbk) atomicAdd(&cnt[fb.rep].sur_fallbacks, n_fbk);
     }
   }
 }
@@ -547,7 +644,8 @@ __global__ void __launch_bounds__(128) k_mlp_grad(const bf16x8* __restrict__ pk,
   }
   Pre pre;
   Hid hs[3];
-  const f32x16 out = mlp_forward_tile<true>(pk, th, input_operand(x, h), lane, &pre, hs);
+  const GlobalNet gnet{pk, th, lane};
+  const f32x16 out = mlp_forward_tile<true>(gnet, input_operand(x, h), lane, &pre, hs);
 #pragma unroll
   for (int L = 0; L < 3; ++L) lds_store_tile(sH[L], hs[L], lane, col0);
   // dL/dy on the lanes of half 0 (sample n); loss = mean over batch and outputs
@@ -685,7 +783,8 @@ __global__ void __launch_bounds__(kBlock) k_mlp_eval(const bf16x8* __restrict__ 
     x[f] = raw ? (v - st[kStInMean + f]) * st[kStInScale + f] : v;
   }
   float y[kMlpOut];
-  forward64(pk, th, x, lane, y);
+  const GlobalNet gnet{pk, th, lane};
+  forward64(gnet, x, lane, y);
   if (r < n) {
 #pragma unroll
     for (int o = 0; o < kMlpOut; ++o)

@@ -92,6 +92,9 @@ struct hca_ctx {
   long long ntot = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t cap_stream = nullptr;              // capture only (never executes work)
+  hipGraphExec_t iter_graph[2] = {nullptr, nullptr};   // two CG iterations, per solve kind
+  bool graph_failed = false;
   int device = 0;
 
   // state
@@ -324,6 +327,36 @@ int pick_tx(int nx) {
 
 // ---- the solver driver -------------------------------------------------------
 
+// Captures two CG iterations (parities 0 and 1, with their V-cycles) of the
+// systems of W into a HIP graph on the capture-only stream.  On failure the
+// context falls back to direct launches for good.
+bool capture_iterations(hca_ctx* c, const Work& W, const MgBufs& mg, double rtol, int maxit,
+                        int kind) {
+  hipStream_t cs = c->cap_stream;
+  if (!cs) return false;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    c->graph_failed = true;
+    return false;
+  }
+  for (int par = 0; par < 2; ++par) {
+    launch_cg_apply(cs, W, c->c, c->sb, par);
+    launch_cg_update(cs, W, rtol, maxit, c->F, c->sb, par);
+    if (c->use_mg) launch_mg_vcycle(cs, W, mg, c->sb, nullptr, nullptr);
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(cs, &g);
+  hipGraphExec_t ex = nullptr;
+  if (e == hipSuccess && g) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipGetLastError();
+  if (e != hipSuccess || !ex) {
+    c->graph_failed = true;
+    return false;
+  }
+  c->iter_graph[kind] = ex;
+  return true;
+}
+
 // Flexible CG on the systems of W (all systems: sys3, oxygen only: sys1) for
 // (diag(c) - a Lap) x = b, x = the field array F.  Systems of fields outside
 // `fmask` are marked finished at the start.  Iterations are launched in
@@ -344,20 +377,35 @@ hca_status solve(hca_ctx* c, const Work& W, const MgBufs& mg, unsigned fmask, do
   int launched = 0;
   int batch = std::max(1, c->last_it[kind] - 1);
   int real = 0;
+  auto iteration = [&](int it) {
+    {
+      ProfScope ps(c, KC_CG_APPLY, it);
+      launch_cg_apply(c->stream, W, c->c, c->sb, it & 1);
+    }
+    {
+      ProfScope ps(c, KC_CG_UPDATE, it);
+      launch_cg_update(c->stream, W, rtol, maxit, c->F, c->sb, it & 1);
+    }
+    // z = M r for the next direction (work only where this iteration did not converge)
+    if (c->use_mg) run_vcycle(c, W, mg, it + 1);
+  };
+  // Replays of a captured pair of iterations (even, odd) when no kernel is
+  // being timed; finished systems make the extra launches no-ops.
+  const bool graphs = c->prm.graphs && c->prm.profile == 0 && !c->graph_failed &&
+                      (c->iter_graph[kind] || capture_iterations(c, W, mg, rtol, maxit, kind));
   for (;;) {
     batch = std::min(batch, maxit - launched);
-    for (int k = 0; k < batch; ++k, ++launched) {
-      {
-        ProfScope ps(c, KC_CG_APPLY, launched);
-        launch_cg_apply(c->stream, W, c->c, c->sb, launched & 1);
+    int k = 0;
+    if (graphs) {
+      if ((launched & 1) && k < batch) {
+        iteration(launched);
+        ++k;
+        ++launched;
       }
-      {
-        ProfScope ps(c, KC_CG_UPDATE, launched);
-        launch_cg_update(c->stream, W, rtol, maxit, c->F, c->sb, launched & 1);
-      }
-      // z = M r for the next direction (work only where this iteration did not converge)
-      if (c->use_mg) run_vcycle(c, W, mg, launched + 1);
+      for (; k + 2 <= batch; k += 2, launched += 2)
+        HIPCHK(c, hipGraphLaunch(c->iter_graph[kind], c->stream));
     }
+    for (; k < batch; ++k, ++launched) iteration(launched);
     HIPCHK(c, hipMemcpyAsync(c->h_ss, c->sb.ss, sizeof(SolveScal) * nsys, hipMemcpyDeviceToHost,
                              c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -527,7 +575,7 @@ hca_status validate_params(const hca_params* p, std::string& msg) {
   if (!std::isfinite(p->k2pp) || p->b_int[0] < 1 || p->b_int[1] < 1 || p->b_int[0] > 64 ||
       p->b_int[1] > 64 || p->ode_substeps < 1 || p->cg_maxit < 1 || p->init_maxit < 1 ||
       (p->precond != 0 && p->precond != 1) || p->mg_coarse_max < 1 || p->profile < 0 ||
-      p->profile > KC_COUNT + 1) {
+      p->profile > KC_COUNT + 1 || (p->graphs != 0 && p->graphs != 1)) {
     msg = "integer parameter out of range";
     return HCA_E_INVALID;
   }
@@ -949,6 +997,9 @@ void free_all(hca_ctx* c) {
     (void)hipEventDestroy(e.b);
   }
   for (auto e : c->free_events) (void)hipEventDestroy(e);
+  for (auto& g : c->iter_graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
 }
 
@@ -1009,6 +1060,7 @@ hca_status hca_default_params(hca_params* out) {
   out->init_rtol = 1.0e-10;
   out->init_maxit = 200;
   out->profile = 0;
+  out->graphs = 1;
   return HCA_OK;
 }
 
@@ -1062,6 +1114,8 @@ hca_status hca_init(hca_ctx** out, const hca_params* p, const hca_replicate* rep
       return bail(HCA_E_DEVICE);
     c->own_stream = true;
   }
+  if (p->graphs && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(HCA_E_DEVICE);
   if ((st = build_tables(c, reps)) != HCA_OK) return bail(st);
   if ((st = alloc_all(c)) != HCA_OK) return bail(st);
   if (c->use_mg && (st = build_mg(c)) != HCA_OK) return bail(st);

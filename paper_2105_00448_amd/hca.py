@@ -38,6 +38,7 @@ class Params(C.Structure):
         ("precond", C.c_int32), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
         ("mg_smooth", C.c_int32), ("mg_coarse_max", C.c_int32),
         ("init_rtol", C.c_double), ("init_maxit", C.c_int32), ("profile", C.c_int32),
+        ("graphs", C.c_int32),
     ]
 
 

@@ -237,6 +237,27 @@ def test_runs_are_deterministic(case32):
         assert np.array_equal(a, b)
 
 
+@PRECONDS
+def test_graph_replay_equals_direct_launches(case32, precond):
+    """CG iterations replayed from a captured HIP graph (many replays, with
+    eager start/setup/CA work and host polls between them) give bit-identical
+    fields to direct launches; also after a context's graph has been reused
+    across several solves of different lengths."""
+    tis, sched, _ = case32
+    out = []
+    for graphs in (0, 1):
+        with make_sim([(tis, sched)], cg_rtol=1e-10, init_rtol=1e-10, precond=precond,
+                      graphs=graphs) as sim:
+            fields = []
+            for _ in range(4):
+                sim.step(1)
+                fields.append([sim.field(n) for n in ("L", "K", "G1", "G2", "phi", "P", "Vc")])
+            out.append(fields)
+    for fa, fb in zip(*out):
+        for a, b in zip(fa, fb):
+            assert np.array_equal(a, b)
+
+
 def test_error_paths_on_device(case32):
     tis, sched, _ = case32
     with make_sim([(tis, sched)], cg_rtol=1e-10, init_rtol=1e-10) as sim:
