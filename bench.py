@@ -18,8 +18,8 @@ HIP events recorded on the library's stream during the timed steps.
 
 Two further legs (skip with --no-legs) report the other throughputs of the
 same metric beside the plain one:
-  surrogate  training pairs harvested from the plain integrator on 32^3
-             lattices (3 seeds x 20 steps), the network trained on the GPU,
+  surrogate  10^6 training pairs harvested from the plain integrator on 32^3
+             lattices (seeds 1..6, 20 steps each), the network trained on the GPU,
              then the 256^3 lattice (64 Gaussians, bolus at steps 0 and 50)
              stepped plain and with the surrogate ODE phase (margin 1e-3), and
              the per-step error and decision-flip rate of the surrogate against
@@ -74,33 +74,35 @@ def cpu_model():
     return platform.processor()
 
 
-def cpu_baseline(budget_s=20.0):
+def cpu_baseline(budget_s=12.0):
     """The oracle as it stands (CG solves to rel. residual 1e-15, NumPy ODE and
-    CA) on one core, timed on whole coupled steps of the 32^3 lattice of the
-    same recipe."""
+    CA) on one core: the small workload in full (32^3 lattice, 8-Gaussian
+    density, seed 1, bolus of both drugs at step 0, 20 coupled steps from
+    init), repeated until about `budget_s` seconds of stepping."""
     from threadpoolctl import threadpool_limits
 
     from oracle import model as om
     from oracle.constants import DEFAULT as OP
     from paper_2105_00448_amd import synth
     tis = synth.make_tissue(32, 8, seed=1)
-    sched = synth.bolus_schedule([0, 50])
+    sched = synth.bolus_schedule([0])
     osched = om.Schedule(times=sched.times, amts=sched.amts)
+    el, n, runs = 0.0, 0, 0
     with threadpool_limits(limits=1):
-        s = om.init_state(tis.cell, tis.w, tis.seed, OP)
-        t0 = time.perf_counter()
-        n = 0
-        while True:
-            s, _ = om.step(s, tis.w, osched, tis.seed, OP)
-            n += 1
-            el = time.perf_counter() - t0
-            if el > budget_s or n >= 50:
-                break
+        while el < budget_s:
+            s = om.init_state(tis.cell, tis.w, tis.seed, OP)
+            t0 = time.perf_counter()
+            for _ in range(20):
+                s, _ = om.step(s, tis.w, osched, tis.seed, OP)
+            el += time.perf_counter() - t0
+            n += 20
+            runs += 1
     vox = tis.cell.size
     return {"value": vox * n / el, "unit": "voxel-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} coupled steps of a 32^3 lattice (same generator recipe), FP64 "
-                      f"diagonally scaled CG to rel. residual 1e-15, single thread, {el:.1f}s; "
-                      f"host: {cpu_model()}, {os.cpu_count()} logical CPUs"}
+            "sample": f"the 32^3 workload (8-Gaussian density, seed 1, bolus at step 0) in full, "
+                      f"20 coupled steps from init, {runs} runs ({n} steps, {el:.1f}s of stepping, "
+                      f"init excluded); FP64 diagonally scaled CG to rel. residual 1e-15, single "
+                      f"thread; host: {cpu_model()}, {os.cpu_count()} logical CPUs"}
 
 
 def timed_run(reps, params, steps, stream, net=None, margin=1e-3):
@@ -126,7 +128,8 @@ def timed_run(reps, params, steps, stream, net=None, margin=1e-3):
     return el, st, kt
 
 
-def surrogate_leg(stream, steps, train_steps, margin=1e-3, err_steps=3, edge=256):
+def surrogate_leg(stream, steps, train_steps, margin=1e-3, err_steps=3, edge=256,
+                  n_pairs=1_000_000):
     import torch
 
     from paper_2105_00448_amd import hca, synth
@@ -135,7 +138,7 @@ def surrogate_leg(stream, steps, train_steps, margin=1e-3, err_steps=3, edge=256
     # training pairs from the plain integrator
     t0 = time.perf_counter()
     Xs, Ys = [], []
-    for seed in (1, 2, 3):
+    for seed in range(1, 7):
         tis = synth.make_tissue(32, 8, seed=seed)
         sched = synth.bolus_schedule([0])
         with hca.Simulation([(tis.cell, tis.w, tis.seed, (sched.times, sched.amts))],
@@ -146,7 +149,7 @@ def surrogate_leg(stream, steps, train_steps, margin=1e-3, err_steps=3, edge=256
                 n = sim.harvest_step(X, Y)
                 Xs.append(X[:n].clone())
                 Ys.append(Y[:n].clone())
-    X, Y = torch.cat(Xs), torch.cat(Ys)
+    X, Y = torch.cat(Xs)[:n_pairs].contiguous(), torch.cat(Ys)[:n_pairs].contiguous()
     del Xs, Ys
     t_harvest = time.perf_counter() - t0
     log(f"{X.shape[0]} pairs in {t_harvest:.1f}s; training {train_steps} steps")
@@ -263,6 +266,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--graphs", type=int, default=1, help="1: replay captured CG iterations")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed repeats from a fresh context; value = median")
     ap.add_argument("--no-legs", action="store_true", help="plain workload only")
     ap.add_argument("--legs", default="surrogate,batched",
                     help="comma-separated further legs: surrogate, batched")
@@ -325,22 +330,35 @@ def main():
 
     prof = 0 if args.no_profile else dom_class + 2
     p = hca.default_params(profile=prof, **solver_kw)
-    t_init = time.perf_counter()
-    sim = hca.Simulation(reps, p, stream=stream)
-    t_init = time.perf_counter() - t_init
-    print(f"[bench] init {t_init:.2f}s, timing {steps} steps", file=sys.stderr, flush=True)
-    sim.reset_kernel_times()
-    torch.cuda.synchronize()
-    sim.synchronize()
-    t0 = time.perf_counter()
-    sim.step(steps)
-    sim.synchronize()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    st = [sim.stats(r) for r in range(len(reps))]
-    kt = sim.kernel_times()
-    sim.close()
-    print(f"[bench] {steps} steps in {el:.3f}s", file=sys.stderr, flush=True)
+    times, kt = [], None
+    for rep_i in range(args.repeats):
+        t_init = time.perf_counter()
+        sim = hca.Simulation(reps, p, stream=stream)
+        t_init = time.perf_counter() - t_init
+        print(f"[bench] repeat {rep_i}: init {t_init:.2f}s, timing {steps} steps", file=sys.stderr,
+              flush=True)
+        sim.reset_kernel_times()
+        torch.cuda.synchronize()
+        sim.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.synchronize()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        st = [sim.stats(r) for r in range(len(reps))]
+        k1 = sim.kernel_times()
+        sim.close()
+        if kt is None:
+            kt = k1
+        else:
+            for k, v in k1.items():
+                kt[k]["ms"] += v["ms"]
+                kt[k]["bytes_per_launch"] = (
+                    (kt[k]["bytes_per_launch"] * kt[k]["launches"] + v["bytes_per_launch"] * v["launches"])
+                    / max(1, kt[k]["launches"] + v["launches"]))
+                kt[k]["launches"] += v["launches"]
+        print(f"[bench] {steps} steps in {times[-1]:.3f}s", file=sys.stderr, flush=True)
+    el = float(np.median(times))
 
     value = nvox * steps / el
     rec = {
@@ -351,6 +369,8 @@ def main():
         "steps": steps,
         "warmup": args.warmup,
         "ms_per_step": el / steps * 1e3,
+        "repeats": len(times),
+        "value_min_time": nvox * steps / min(times),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -1,6 +1,9 @@
 // Intracellular module over one coupled step for every occupied voxel: the
-// plain integrator of ode_dev.h.  FP64; the kernel is bound by the VALU
-// (about 120 divides per voxel).
+// plain integrator of ode_dev.h, FP64, bound by the vector ALU (about 120
+// divides per voxel).  Each workgroup first lists the occupied voxels of its
+// run of the lattice in LDS, so every lane of a wavefront integrates an
+// occupied voxel (empty voxels would otherwise idle half the lanes at the
+// typical occupancy of one half).
 #include "dev_util.h"
 #include "ode_dev.h"
 
@@ -11,20 +14,40 @@ __global__ void __launch_bounds__(kBlock) k_ode(Work w, DevParams p, const uint8
                                                 double* __restrict__ P,
                                                 double* __restrict__ Vc,
                                                 double* __restrict__ phi) {
+  __shared__ int list[kFlatChunk];
+  __shared__ int wcnt[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int b0, b1;
   work_range(w.nflat, b0, b1);
   for (int it = b0; it < b1; ++it) {
     const FlatBlk fb = w.flat[it];
-    const long long off = w.reps[fb.rep].off;
-    for (long long li = fb.begin + threadIdx.x; li < fb.end; li += kBlock) {
-      const long long i = off + li;
-      const uint8_t l = L[i];
-      if (l == 0) continue;
-      double pv = P[i], vv = Vc[i], ph = phi[i];
-      ode_voxel(p, l, K[i], pv, vv, ph);
-      P[i] = pv;
-      Vc[i] = vv;
-      if (l == 1) phi[i] = ph;
+    for (long long c0 = fb.begin; c0 < fb.end; c0 += kFlatChunk) {
+      const long long off = w.reps[fb.rep].off + c0;
+      const int len = (int)min((long long)kFlatChunk, fb.end - c0);
+      int n = 0;
+      for (int base = 0; base < len; base += kBlock) {
+        const int li = base + (int)threadIdx.x;
+        const bool occ = li < len && L[off + li] != 0;
+        const unsigned long long bal = __ballot(occ);
+        const int rank = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) wcnt[wave] = __popcll(bal);
+        __syncthreads();
+        int woff = 0;
+        for (int k = 0; k < wave; ++k) woff += wcnt[k];
+        if (occ) list[n + woff + rank] = li;
+        n += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+        __syncthreads();
+      }
+      for (int s = threadIdx.x; s < n; s += kBlock) {
+        const long long i = off + list[s];
+        const uint8_t l = L[i];
+        double pv = P[i], vv = Vc[i], ph = phi[i];
+        ode_voxel(p, l, K[i], pv, vv, ph);
+        P[i] = pv;
+        Vc[i] = vv;
+        if (l == 1) phi[i] = ph;
+      }
+      __syncthreads();   // the list is rewritten by the next run
     }
   }
 }

@@ -47,10 +47,19 @@ constexpr int kPackL3T = kPackL4T + 2 * 64;
 constexpr int kPackL2T = kPackL3T + 8 * 64;
 constexpr int kPackAll = kPackL2T + 8 * 64;
 
+// Normal CDF Phi on [-6, 6] at 64 points per unit (768 intervals): entry i
+// holds (Phi(z_i), Phi(z_{i+1}) - Phi(z_i)), z_i = -6 + i/64, the last slope
+// 0.  Forward passes evaluate GELU(z) = z Phi(z) by linear interpolation in
+// it (error <= 8e-6 in Phi, a few hundredths of a bfloat16 rounding step of
+// the activation); outside [-6, 6] Phi is held at its end values.
+constexpr int kGeluN = 768;
+constexpr float kGeluScale = 64.f, kGeluOrigin = 384.f;
+
 // Everything a kernel needs to evaluate the network on raw model values.
 struct MlpDev {
   const bf16x8* packed;       // kPackAll
   const float* theta;         // kMlpNparam (biases are read from here)
+  const float2* gelu_tab;     // kGeluN + 1
   float in_mean[kMlpIn], in_scale[kMlpIn];     // x_s = (x - mean) * scale
   float out_mean[kMlpOut], out_scale[kMlpOut]; // y = y_s * scale + mean
   float in_lo[kMlpIn], in_hi[kMlpIn];          // training box
@@ -60,6 +69,7 @@ struct MlpDev {
 
 // Launchers (k_mlp.hip).
 void launch_mlp_pack(hipStream_t s, const float* theta, bf16x8* packed);
+void launch_mlp_gelu_table(hipStream_t s, float2* tab);
 void launch_mlp_apply(hipStream_t s, const Work& w, const DevParams& p, const MlpDev& net,
                       const uint8_t* L, const double* K, const double* G1, const double* G2,
                       double* P, double* Vc, double* phi, Counters* cnt);
@@ -82,12 +92,13 @@ void launch_mlp_standardize(hipStream_t s, const float* X, const float* Y, long 
                             const float* stats, float* Xs, float* Ys);
 void launch_mlp_init(hipStream_t s, uint64_t seed, float* theta);
 void launch_mlp_sample(hipStream_t s, uint64_t seed, long long t, long long n, int batch, int* idx);
-void launch_mlp_grad(hipStream_t s, const bf16x8* pk, const float* th, const float* Xs,
-                     const float* Ys, const int* idx, int batch, long long nrows, float* partial);
+void launch_mlp_grad(hipStream_t s, const bf16x8* pk, const float* th, const float2* tab,
+                     const float* Xs, const float* Ys, const int* idx, int batch, long long nrows,
+                     float* partial);
 void launch_mlp_adam(hipStream_t s, float* th, float* m1, float* m2, const float* partial, int nwg,
                      int t, float lr, float b1, float b2, float eps, int update,
                      float* grad_out, float* loss_out, int batch);
-void launch_mlp_eval(hipStream_t s, const bf16x8* pk, const float* th, const float* stats,
-                     const float* X, long long n, int raw, float* Y);
+void launch_mlp_eval(hipStream_t s, const bf16x8* pk, const float* th, const float2* tab,
+                     const float* stats, const float* X, long long n, int raw, float* Y);
 
 }  // namespace hca

@@ -22,6 +22,7 @@ struct hca_mlp_trainer {
   float* stats = nullptr;               // kStN
   float *theta = nullptr, *m1 = nullptr, *m2 = nullptr;
   bf16x8* packed = nullptr;
+  float2* gelu_tab = nullptr;           // kGeluN + 1
   float* partial = nullptr;             // kMaxBatch / 64 workgroups
   int* idx = nullptr;                   // kMaxBatch
   float* losses = nullptr;              // device, grows with n_steps
@@ -55,7 +56,7 @@ hipError_t talloc(T** p, size_t count) {
 }
 
 void tfree(hca_mlp_trainer* t) {
-  void* bufs[] = {t->Xs, t->Ys, t->stats, t->theta, t->m1, t->m2, (void*)t->packed,
+  void* bufs[] = {t->Xs, t->Ys, t->stats, t->theta, t->m1, t->m2, (void*)t->packed, t->gelu_tab,
                   t->partial, t->idx, t->losses, t->loss1};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
@@ -101,7 +102,7 @@ hca_status hca_mlp_trainer_create(hca_mlp_trainer** out, const float* X, const f
     return bail(HCA_E_NOMEM);
   if (talloc(&t->stats, kStN) != hipSuccess || talloc(&t->theta, kMlpNparam) != hipSuccess ||
       talloc(&t->m1, kMlpNparam) != hipSuccess || talloc(&t->m2, kMlpNparam) != hipSuccess ||
-      talloc(&t->packed, kPackAll) != hipSuccess ||
+      talloc(&t->packed, kPackAll) != hipSuccess || talloc(&t->gelu_tab, kGeluN + 1) != hipSuccess ||
       talloc(&t->partial, (size_t)(kMaxBatch / 64) * kPartialStride) != hipSuccess ||
       talloc(&t->idx, kMaxBatch) != hipSuccess || talloc(&t->loss1, 1) != hipSuccess ||
       talloc(&part, (size_t)nblk * (kMlpIn + kMlpOut) * 4) != hipSuccess) {
@@ -111,6 +112,7 @@ hca_status hca_mlp_trainer_create(hca_mlp_trainer** out, const float* X, const f
   launch_mlp_moments(t->stream, X, Y, n_rows, part, nblk, t->stats);
   launch_mlp_standardize(t->stream, X, Y, n_rows, t->stats, t->Xs, t->Ys);
   launch_mlp_init(t->stream, seed, t->theta);
+  launch_mlp_gelu_table(t->stream, t->gelu_tab);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess)
     e = hipMemcpyAsync(t->h_stats, t->stats, sizeof t->h_stats, hipMemcpyDeviceToHost, t->stream);
@@ -179,7 +181,7 @@ hca_status hca_mlp_gradient(hca_mlp_trainer* t, const int32_t* idx, int batch, f
   if (!t || !idx || !grad) return HCA_E_INVALID;
   if (batch < 64 || batch > kMaxBatch || batch % 64) return tfail(t, HCA_E_RANGE, "batch size");
   launch_mlp_pack(t->stream, t->theta, t->packed);
-  launch_mlp_grad(t->stream, t->packed, t->theta, t->Xs, t->Ys, idx, batch, t->n, t->partial);
+  launch_mlp_grad(t->stream, t->packed, t->theta, t->gelu_tab, t->Xs, t->Ys, idx, batch, t->n, t->partial);
   launch_mlp_adam(t->stream, t->theta, t->m1, t->m2, t->partial, batch / 64, 1, 0.f, 0.9f, 0.999f,
                   1e-8f, 0, grad, t->loss1, batch);
   TCHK(t, hipGetLastError());
@@ -205,7 +207,7 @@ hca_status hca_mlp_train(hca_mlp_trainer* t, int n_steps, int batch, float lr, f
     const long long step = t->t + 1;
     launch_mlp_sample(t->stream, t->seed, step, t->n, batch, t->idx);
     launch_mlp_pack(t->stream, t->theta, t->packed);
-    launch_mlp_grad(t->stream, t->packed, t->theta, t->Xs, t->Ys, t->idx, batch, t->n, t->partial);
+    launch_mlp_grad(t->stream, t->packed, t->theta, t->gelu_tab, t->Xs, t->Ys, t->idx, batch, t->n, t->partial);
     launch_mlp_adam(t->stream, t->theta, t->m1, t->m2, t->partial, batch / 64, (int)step, lr, 0.9f,
                     0.999f, 1e-8f, 1, nullptr, t->losses + k, batch);
     t->t = step;
@@ -222,7 +224,7 @@ hca_status hca_mlp_eval(hca_mlp_trainer* t, const float* X, int64_t n, int raw, 
   if (!t || !X || !Y || n < 0) return HCA_E_INVALID;
   if (n == 0) return HCA_OK;
   launch_mlp_pack(t->stream, t->theta, t->packed);
-  launch_mlp_eval(t->stream, t->packed, t->theta, t->stats, X, n, raw ? 1 : 0, Y);
+  launch_mlp_eval(t->stream, t->packed, t->theta, t->gelu_tab, t->stats, X, n, raw ? 1 : 0, Y);
   TCHK(t, hipGetLastError());
   TCHK(t, hipStreamSynchronize(t->stream));
   return HCA_OK;

@@ -129,6 +129,7 @@ struct hca_ctx {
   MlpDev net{};
   float* d_theta = nullptr;
   bf16x8* d_pack = nullptr;
+  float2* d_gelu = nullptr;
   double* before = nullptr;       // 3 x ntot
   int* item_cnt = nullptr;        // per flat work item
   long long* item_off = nullptr;  // nflat + 1
@@ -983,7 +984,7 @@ void free_all(hca_ctx* c) {
                   c->sb.r, c->sb.z, c->sb.p0, c->sb.p1, c->sb.q, c->sb.dinv, c->sb.partial,
                   c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->d_step,
                   c->d_reps, c->d_flat, c->d_tiles, c->d_sys, c->d_sflat, c->d_stiles, c->d_cnt,
-                  (void*)c->d_fields, c->d_bad, c->d_theta, (void*)c->d_pack, c->before,
+                  (void*)c->d_fields, c->d_bad, c->d_theta, (void*)c->d_pack, (void*)c->d_gelu, c->before,
                   c->item_cnt, c->item_off};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
@@ -1313,6 +1314,8 @@ hca_status hca_set_surrogate(hca_ctx* c, const hca_mlp* net, double margin) {
   if (!c->d_theta) {
     HIPCHK(c, dalloc(&c->d_theta, kMlpNparam));
     HIPCHK(c, dalloc(&c->d_pack, kPackAll));
+    HIPCHK(c, dalloc(&c->d_gelu, kGeluN + 1));
+    launch_mlp_gelu_table(c->stream, c->d_gelu);
   }
   HIPCHK(c, hipMemcpyAsync(c->d_theta, net->theta, sizeof(float) * kMlpNparam,
                            net->theta_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
@@ -1323,6 +1326,7 @@ hca_status hca_set_surrogate(hca_ctx* c, const hca_mlp* net, double margin) {
   MlpDev& d = c->net;
   d.packed = c->d_pack;
   d.theta = c->d_theta;
+  d.gelu_tab = c->d_gelu;
   for (int f = 0; f < HCA_MLP_NIN; ++f) {
     d.in_mean[f] = net->in_mean[f];
     d.in_scale[f] = net->in_scale[f];
