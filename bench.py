@@ -105,9 +105,9 @@ def cpu_baseline(budget_s=12.0):
                       f"thread; host: {cpu_model()}, {os.cpu_count()} logical CPUs"}
 
 
-def timed_run(reps, params, steps, stream, net=None, margin=1e-3):
+def timed_run(reps, params, steps, stream, net=None, margin=1e-3, tile_shapes=False):
     """Steps `steps` coupled steps of a fresh context; returns wall time,
-    per-replicate stats and kernel times."""
+    per-replicate stats and kernel times (and the tile shapes)."""
     import torch
 
     from paper_2105_00448_amd import hca
@@ -124,7 +124,10 @@ def timed_run(reps, params, steps, stream, net=None, margin=1e-3):
     el = time.perf_counter() - t0
     st = [sim.stats(r) for r in range(len(reps))]
     kt = sim.kernel_times()
+    shapes = [sim.tile_shape(r) for r in range(len(reps))]
     sim.close()
+    if tile_shapes:
+        return el, st, kt, shapes
     return el, st, kt
 
 
@@ -249,9 +252,15 @@ def batched_leg(stream, steps=None):
     nvox = sum(r[0].size for r in reps)
     print(f"[bench:batched] {len(reps)} replicates, {nvox} voxels, {steps} steps",
           file=sys.stderr, flush=True)
-    el, st, _ = timed_run(reps, hca.default_params(), steps, stream)
-    return {"workload": cfg["workload"], "value": nvox * steps / el, "unit": "voxel-steps/s",
-            "voxels": nvox, "steps": steps, "ms_per_step": el / steps * 1e3}
+    el, st, _, shapes = timed_run(reps, hca.default_params(autotune=1), steps, stream,
+                                  tile_shapes=True)
+    dist = {}
+    for t in shapes:
+        k = "x".join(map(str, t))
+        dist[k] = dist.get(k, 0) + 1
+    return {"workload": cfg["workload"] + "; stencil tiles from the autotuner",
+            "value": nvox * steps / el, "unit": "voxel-steps/s", "voxels": nvox, "steps": steps,
+            "ms_per_step": el / steps * 1e3, "tile_shapes_txtytz": dist}
 
 
 def main():
@@ -266,6 +275,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--graphs", type=int, default=1, help="1: replay captured CG iterations")
+    ap.add_argument("--autotune", type=int, default=0, help="1: tile plan from the autotuner")
     ap.add_argument("--repeats", type=int, default=5,
                     help="timed repeats from a fresh context; value = median")
     ap.add_argument("--no-legs", action="store_true", help="plain workload only")
@@ -302,7 +312,7 @@ def main():
               flush=True)
     print(f"[bench] generating workload {args.workload}", file=sys.stderr, flush=True)
     reps, cfg, cfg_steps = make_workload(args.workload)
-    solver_kw = {"precond": args.precond, "graphs": args.graphs}
+    solver_kw = {"precond": args.precond, "graphs": args.graphs, "autotune": args.autotune}
     if args.mg_coarse_max is not None:
         solver_kw["mg_coarse_max"] = args.mg_coarse_max
     steps = args.steps if args.steps is not None else cfg_steps

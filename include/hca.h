@@ -102,6 +102,10 @@ typedef struct hca_params {
                               0 off, 1 every kernel class, k + 2 class k only  */
   int32_t graphs;          /* 1: replay captured HIP graphs of CG iterations
                               (only while profile = 0); 0: direct launches     */
+  int32_t autotune;        /* 1: pick the stencil tiling of the batch by
+                              timing candidates at init (hca_tile_shape);
+                              0: fixed heuristic from each lattice's size
+                              (bit-identical alone or in any batch)           */
 } hca_params;
 
 /* One replicate's inputs.  hca_init deep-copies every array; the caller keeps
@@ -257,6 +261,10 @@ hca_status hca_mlp_train(hca_mlp_trainer* t, int n_steps, int batch, float lr, f
 hca_status hca_mlp_eval(hca_mlp_trainer* t, const float* X, int64_t n, int raw, float* Y);
 const char* hca_mlp_trainer_last_error(const hca_mlp_trainer* t);
 void hca_mlp_trainer_destroy(hca_mlp_trainer* t);
+
+/* Stencil tile of replicate `rep`: tx x ty voxel columns, tz planes deep
+ * (the autotuner's choice with params.autotune = 1). */
+hca_status hca_tile_shape(hca_ctx* c, int rep, int32_t* tx, int32_t* ty, int32_t* tz);
 
 /* Block the host until all work of the context has finished. */
 hca_status hca_synchronize(hca_ctx* c);

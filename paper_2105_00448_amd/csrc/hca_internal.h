@@ -154,6 +154,9 @@ void launch_cg_reduce(hipStream_t s, const Work& w, const SolverBufs& sb, int ki
 // parity (the direction p alternates between p0 and p1).
 void launch_cg_apply(hipStream_t s, const Work& w, const double* c,
                      const SolverBufs& sb, int parity);
+// The apply kernel alone (no reduce), for the tile autotuner.
+void launch_cg_apply_kernel(hipStream_t s, const Work& w, const double* c, const SolverBufs& sb,
+                            int parity);
 void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, double* x,
                       const SolverBufs& sb, int parity);
 

@@ -345,12 +345,17 @@ void launch_cg_start(hipStream_t s, const Work& w, double rtol, int maxit, const
   launch_cg_reduce(s, w, sb, RED_START, rtol, maxit, field_mask, nrep);
 }
 
-void launch_cg_apply(hipStream_t s, const Work& w, const double* c, const SolverBufs& sb,
-                     int parity) {
+void launch_cg_apply_kernel(hipStream_t s, const Work& w, const double* c, const SolverBufs& sb,
+                            int parity) {
   const double* pold = parity ? sb.p1 : sb.p0;
   double* pnew = parity ? sb.p0 : sb.p1;
-  hipLaunchKernelGGL(k_cg_apply, dim3(grid_for(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c, sb.z, pold, pnew, sb.q,
-                     sb);
+  hipLaunchKernelGGL(k_cg_apply, dim3(grid_for(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c,
+                     sb.z, pold, pnew, sb.q, sb);
+}
+
+void launch_cg_apply(hipStream_t s, const Work& w, const double* c, const SolverBufs& sb,
+                     int parity) {
+  launch_cg_apply_kernel(s, w, c, sb, parity);
   launch_cg_reduce(s, w, sb, RED_APPLY, 0.0, 0);
 }
 

@@ -73,6 +73,7 @@ struct RepHost {
   int nx, ny, nz;
   long long off, n;
   uint64_t seed;
+  int tx, tz;   // stencil tile: tx x (256/tx) columns, tz planes deep
 };
 
 struct ProfEntry {
@@ -320,8 +321,11 @@ DevParams make_dev_params(const hca_params& p) {
   return d;
 }
 
+// Tile width (tiles are tx x 256/tx columns): 32 x 8 unless the lattice is
+// at most 16 wide.  (HCA_TILE_WIDE=1 restores 64 x 4 above 32.)
+int g_tile_wide = 0;
 int pick_tx(int nx) {
-  if (nx > 32) return 64;
+  if (g_tile_wide && nx > 32) return 64;
   if (nx > 16) return 32;
   return 16;
 }
@@ -576,7 +580,8 @@ hca_status validate_params(const hca_params* p, std::string& msg) {
   if (!std::isfinite(p->k2pp) || p->b_int[0] < 1 || p->b_int[1] < 1 || p->b_int[0] > 64 ||
       p->b_int[1] > 64 || p->ode_substeps < 1 || p->cg_maxit < 1 || p->init_maxit < 1 ||
       (p->precond != 0 && p->precond != 1) || p->mg_coarse_max < 1 || p->profile < 0 ||
-      p->profile > KC_COUNT + 1 || (p->graphs != 0 && p->graphs != 1)) {
+      p->profile > KC_COUNT + 1 || (p->graphs != 0 && p->graphs != 1) ||
+      (p->autotune != 0 && p->autotune != 1)) {
     msg = "integer parameter out of range";
     return HCA_E_INVALID;
   }
@@ -609,8 +614,14 @@ void add_tiles(std::vector<Tile>& v, int rep, int nx, int ny, int nz, int tx, in
       }
 }
 
-// Stencil tiles per lattice the z-chunking aims at (tuning knob HCA_TILE_TARGET).
+// Stencil tiles are g_tile_depth planes deep (at most nz; tuning knob
+// HCA_TILE_DEPTH, 0 = instead aim at HCA_TILE_TARGET tiles per lattice).
+// Deep tiles keep the z-halo re-reads of the plane-marching stencils small;
+// batches and large lattices supply the parallelism.
 double g_tile_target = 1024.0;
+int g_tile_depth = 16;
+// Tiles per system the coarser multigrid levels aim at (HCA_MG_TILE_TARGET).
+double g_mg_tile_target = 512.0;
 
 template <typename T>
 hca_status upload(hca_ctx* c, T** p, const std::vector<T>& v) {
@@ -642,12 +653,139 @@ RepDev lattice_entry(const RepHost& R, long long off, int idx, std::vector<FlatB
     fb.end = R.n * (k + 1) / d.flat_nb;
     flat.push_back(fb);
   }
-  d.tx = pick_tx(R.nx);
-  const int tz = pick_tz(R.nx, R.ny, R.nz, d.tx, g_tile_target);
+  d.tx = R.tx;
   d.tile_b0 = (int)tiles.size();
-  add_tiles(tiles, idx, R.nx, R.ny, R.nz, d.tx, tz);
+  add_tiles(tiles, idx, R.nx, R.ny, R.nz, R.tx, R.tz);
   d.tile_nb = (int)tiles.size() - d.tile_b0;
   return d;
+}
+
+// ---- tile autotuner ---------------------------------------------------------------
+
+// Stencil tile shape of every lattice: tx from nx (pick_tx), g_tile_depth
+// planes deep; with params.autotune, the depth (2 ... 32 planes) and the width
+// policy (pick_tx, 64 x 4 on wide lattices, or 16 x 16) are instead the
+// fastest of 15 candidates, timed on the CG apply kernel (the dominant
+// stencil) over the whole batch at once on scratch arrays of the batch's
+// shape (one warm-up launch, then the best of three), so the choice accounts
+// for the parallelism the batch already has.  Tiles fix the order of the
+// dot-product partial sums, so a tuned context agrees with an untuned one to
+// rounding, not bit for bit.
+hca_status plan_tiles(hca_ctx* c) {
+  // width policy 0: pick_tx; 1: 64 x 4 where nx > 32; 2: 16 x 16
+  auto apply_plan = [&](int depth, int policy) {
+    for (RepHost& R : c->reps) {
+      R.tx = pick_tx(R.nx);
+      if (policy == 1 && R.nx > 32) R.tx = 64;
+      if (policy == 2) R.tx = 16;
+      R.tz = depth > 0 ? std::min(depth, R.nz) : pick_tz(R.nx, R.ny, R.nz, R.tx, g_tile_target);
+    }
+  };
+  apply_plan(g_tile_depth, 0);
+  if (!c->prm.autotune) return HCA_OK;
+  const long long n = c->ntot;
+  std::vector<void*> mem;
+  auto scratch = [&](size_t bytes) -> void* {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(bytes, 8)) != hipSuccess) return nullptr;
+    mem.push_back(p);
+    return p;
+  };
+  auto release = [&]() {
+    for (void* p : mem) (void)hipFree(p);
+    mem.clear();
+  };
+  const int R = c->nreps;
+  size_t maxtiles = 1;   // most tiles any candidate can make (tz >= 1)
+  for (int tx : {16, 32, 64}) {
+    size_t t = 0;
+    for (const RepHost& H : c->reps)
+      t += (size_t)((H.nx + tx - 1) / tx) * (size_t)((H.ny + kBlock / tx - 1) / (kBlock / tx)) * H.nz;
+    maxtiles = std::max(maxtiles, t);
+  }
+  double* cb = (double*)scratch(8 * n);
+  SolverBufs tsb{};
+  tsb.z = (double*)scratch(8 * n);
+  tsb.p0 = (double*)scratch(8 * n);
+  tsb.p1 = (double*)scratch(8 * n);
+  tsb.q = (double*)scratch(8 * n);
+  tsb.partial = (double*)scratch(3 * 8 * maxtiles);
+  tsb.ss = (SolveScal*)scratch(sizeof(SolveScal) * R);
+  RepDev* drep = (RepDev*)scratch(sizeof(RepDev) * R);
+  Tile* dtiles = (Tile*)scratch(sizeof(Tile) * maxtiles);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!cb || !tsb.z || !tsb.p0 || !tsb.p1 || !tsb.q || !tsb.partial || !tsb.ss || !drep || !dtiles ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    release();
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(c, HCA_E_NOMEM, "autotune: scratch allocation failed");
+  }
+  hca_status st = HCA_OK;
+  auto check = [&](hipError_t e) {
+    if (e != hipSuccess && st == HCA_OK)
+      st = fail(c, HCA_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+  };
+  for (void* p : {(void*)cb, (void*)tsb.z, (void*)tsb.p0, (void*)tsb.p1})
+    check(hipMemsetAsync(p, 0, 8 * n, c->stream));
+  check(hipMemsetAsync(tsb.ss, 0, sizeof(SolveScal) * R, c->stream));
+  float tbest = 1e30f;
+  int best_depth = g_tile_depth;
+  int best_policy = 0;
+  for (int policy = 0; policy < 3 && st == HCA_OK; ++policy)
+    for (int depth : {2, 4, 8, 16, 32}) {
+      apply_plan(depth, policy);
+      std::vector<RepDev> rd;
+      std::vector<Tile> tiles;
+      for (int r = 0; r < R; ++r) {
+        const RepHost& H = c->reps[r];
+        RepDev d;
+        memset(&d, 0, sizeof d);
+        d.nx = H.nx;
+        d.ny = H.ny;
+        d.nz = H.nz;
+        d.off = H.off;
+        d.n = H.n;
+        d.tx = H.tx;
+        d.tile_b0 = (int)tiles.size();
+        add_tiles(tiles, r, H.nx, H.ny, H.nz, H.tx, H.tz);
+        d.tile_nb = (int)tiles.size() - d.tile_b0;
+        d.a = c->dp.aG;
+        rd.push_back(d);
+      }
+      check(hipMemcpyAsync(drep, rd.data(), sizeof(RepDev) * R, hipMemcpyHostToDevice, c->stream));
+      check(hipMemcpyAsync(dtiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice,
+                           c->stream));
+      Work w{};
+      w.nreps = R;
+      w.reps = drep;
+      w.tiles = dtiles;
+      w.ntiles = (int)tiles.size();
+      w.max_blocks = c->work.max_blocks;
+      launch_cg_apply_kernel(c->stream, w, cb, tsb, 0);
+      float tmin = 1e30f;
+      for (int k = 0; k < 3; ++k) {
+        check(hipEventRecord(e0, c->stream));
+        launch_cg_apply_kernel(c->stream, w, cb, tsb, 0);
+        check(hipEventRecord(e1, c->stream));
+        check(hipEventSynchronize(e1));
+        float ms = 0.f;
+        check(hipEventElapsedTime(&ms, e0, e1));
+        tmin = std::min(tmin, ms);
+      }
+      check(hipGetLastError());
+      if (tmin < tbest) {
+        tbest = tmin;
+        best_depth = depth;
+        best_policy = policy;
+      }
+    }
+  check(hipStreamSynchronize(c->stream));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  release();
+  if (st != HCA_OK) return st;
+  apply_plan(best_depth, best_policy);
+  return HCA_OK;
 }
 
 hca_status build_tables(hca_ctx* c, const hca_replicate* in) {
@@ -660,9 +798,20 @@ hca_status build_tables(hca_ctx* c, const hca_replicate* in) {
     if (v > 0) max_blocks = v;
   }
   if (const char* e = getenv("HCA_XCD_REMAP")) g_xcd_remap = atoi(e) != 0;
+  if (const char* e = getenv("HCA_TILE_WIDE")) g_tile_wide = atoi(e) != 0;
+  if (const char* e = getenv("HCA_TILE_DEPTH")) g_tile_depth = std::max(0, atoi(e));
+  if (const char* e = getenv("HCA_MG_TILE_TARGET")) {
+    const double v = atof(e);
+    if (v >= 1.0) g_mg_tile_target = v;
+  }
   if (const char* e = getenv("HCA_TILE_TARGET")) {
     const double v = atof(e);
     if (v >= 1.0) g_tile_target = v;
+  }
+  c->work.max_blocks = max_blocks;
+  {
+    hca_status st = plan_tiles(c);
+    if (st != HCA_OK) return st;
   }
   {
     std::vector<RepDev> rd;
@@ -861,7 +1010,7 @@ hca_status build_mg(hca_ctx* c) {
           m.tx = pick_tx(m.nx);
           m.off = off;
           off += (long long)m.nx * m.ny * m.nz;
-          const int tz = pick_tz(m.nx, m.ny, m.nz, m.tx, g_tile_target);
+          const int tz = pick_tz(m.nx, m.ny, m.nz, m.tx, g_mg_tile_target);
           if (m.active) {
             m.tile_b0 = (int)tiles.size();
             add_tiles(tiles, s, m.nx, m.ny, m.nz, m.tx, tz);
@@ -1062,6 +1211,7 @@ hca_status hca_default_params(hca_params* out) {
   out->init_maxit = 200;
   out->profile = 0;
   out->graphs = 1;
+  out->autotune = 0;
   return HCA_OK;
 }
 
@@ -1288,6 +1438,15 @@ hca_status hca_reset_kernel_time(hca_ctx* c) {
   if (!c) return HCA_E_INVALID;
   prof_flush(c, nullptr, 0);
   for (int k = 0; k < KC_COUNT; ++k) c->prof_ms[k] = c->prof_n[k] = c->prof_bytes[k] = 0;
+  return HCA_OK;
+}
+
+hca_status hca_tile_shape(hca_ctx* c, int rep, int32_t* tx, int32_t* ty, int32_t* tz) {
+  if (!c || !tx || !ty || !tz) return HCA_E_INVALID;
+  if (rep < 0 || rep >= c->nreps) return fail(c, HCA_E_RANGE, "replicate index out of range");
+  *tx = c->reps[rep].tx;
+  *ty = kBlock / c->reps[rep].tx;
+  *tz = c->reps[rep].tz;
   return HCA_OK;
 }
 

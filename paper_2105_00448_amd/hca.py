@@ -38,7 +38,7 @@ class Params(C.Structure):
         ("precond", C.c_int32), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
         ("mg_smooth", C.c_int32), ("mg_coarse_max", C.c_int32),
         ("init_rtol", C.c_double), ("init_maxit", C.c_int32), ("profile", C.c_int32),
-        ("graphs", C.c_int32),
+        ("graphs", C.c_int32), ("autotune", C.c_int32),
     ]
 
 
@@ -115,6 +115,7 @@ def lib():
         "hca_last_error": (C.c_char_p, [vp]),
         "hca_destroy": (None, [vp]),
         "hca_set_surrogate": (C.c_int, [vp, P(Mlp), C.c_double]),
+        "hca_tile_shape": (C.c_int, [vp, C.c_int, P(C.c_int32), P(C.c_int32), P(C.c_int32)]),
         "hca_harvest_step": (C.c_int, [vp, vp, vp, C.c_int64, P(C.c_int64)]),
         "hca_mlp_trainer_create": (C.c_int, [P(vp), vp, vp, C.c_int64, C.c_uint64, vp]),
         "hca_mlp_trainer_set_params": (C.c_int, [vp, vp, C.c_int]),
@@ -243,6 +244,12 @@ class Simulation:
         a = np.ascontiguousarray(arr, dtype=np.uint8 if f == F_CELL else np.float64)
         self._check(self._lib.hca_set_field(self._h, rep, f, a.ctypes.data, a.nbytes, 0),
                     "hca_set_field")
+
+    def tile_shape(self, rep=0):
+        tx, ty, tz = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self._lib.hca_tile_shape(self._h, rep, C.byref(tx), C.byref(ty), C.byref(tz)),
+                    "hca_tile_shape")
+        return tx.value, ty.value, tz.value
 
     def set_field_from_device(self, name, tensor, rep=0):
         """Overwrite a state field from a torch device tensor (device-to-device)."""

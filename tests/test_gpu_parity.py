@@ -258,6 +258,22 @@ def test_graph_replay_equals_direct_launches(case32, precond):
             assert np.array_equal(a, b)
 
 
+def test_autotuned_tiles_agree_with_heuristic_tiles(case32):
+    """The tile autotuner only changes the tiling (and so the order of the
+    dot-product partial sums): solves at rel. residual 1e-15 agree to
+    rounding and the cellular automaton takes the same decisions."""
+    tis, sched, _ = case32
+    with make_sim([(tis, sched)], autotune=1) as a, make_sim([(tis, sched)], autotune=0) as b:
+        tx, ty, tz = a.tile_shape()
+        assert tx in (16, 32, 64) and tx * ty == 256 and 1 <= tz <= 16
+        assert b.tile_shape() == (32, 8, b.tile_shape()[2])   # heuristic: tx from nx = 32
+        a.step(3)
+        b.step(3)
+        assert np.array_equal(a.field("L"), b.field("L"))
+        for n in ("K", "G1", "G2", "P", "Vc", "phi"):
+            assert relerr(a.field(n), b.field(n)) <= 1e-12, n
+
+
 def test_error_paths_on_device(case32):
     tis, sched, _ = case32
     with make_sim([(tis, sched)], cg_rtol=1e-10, init_rtol=1e-10) as sim:
