@@ -3,12 +3,34 @@
 // each kernel file exports to the runtime.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "hca.h"
 
 namespace hca {
+
+// Start/stop events for the next kernel launched through hca_launch: they
+// then bracket that kernel's own execution (the packet processor stamps
+// them), not the dispatch gap before it.  Set by the runtime's kernel timer,
+// consumed by one launch.
+struct KernelEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local KernelEvents g_kernel_events;
+
+template <typename F, typename... Args>
+inline void hca_launch(F kernel, dim3 grid, dim3 block, unsigned shmem, hipStream_t s,
+                       Args... args) {
+  if (g_kernel_events.start) {
+    const KernelEvents e = g_kernel_events;
+    g_kernel_events = KernelEvents{};
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, e.start, e.stop, 0u, args...);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+  }
+}
 
 constexpr int kBlock = 256;        // threads per workgroup for every kernel
 constexpr int kFlatChunk = 1024;   // voxels per flat work item (4 per thread)

@@ -276,37 +276,37 @@ __global__ void __launch_bounds__(kBlock) k_validate_cells(Work w, const uint8_t
 void launch_ca_propose(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
                        const uint8_t* L, const double* vw, const double* K, const double* G1,
                        const double* G2, const double* phi, uint8_t* code) {
-  hipLaunchKernelGGL(k_ca_propose, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, d_step, L, vw, K, G1,
+  hca_launch(k_ca_propose, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, d_step, L, vw, K, G1,
                      G2, phi, code);
 }
 
 void launch_ca_resolve(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
                        const double* phi, const uint8_t* code, uint8_t* win) {
-  hipLaunchKernelGGL(k_ca_resolve, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, vw, phi, code, win);
+  hca_launch(k_ca_resolve, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, vw, phi, code, win);
 }
 
 void launch_ca_finalize(hipStream_t s, const Work& w, uint8_t* L, double* phi, double* P,
                         double* Vc, const uint8_t* code, const uint8_t* win, Counters* cnt) {
-  hipLaunchKernelGGL(k_ca_finalize, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, phi, P, Vc, code, win,
+  hca_launch(k_ca_finalize, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, phi, P, Vc, code, win,
                      cnt);
 }
 
 void launch_stats(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
                   const double* const* fields, int nfields, Counters* cnt) {
-  hipLaunchKernelGGL(k_stats, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, vw, fields, nfields, cnt);
+  hca_launch(k_stats, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, vw, fields, nfields, cnt);
 }
 
 void launch_zero_counters(hipStream_t s, Counters* cnt, int nreps, int what) {
-  hipLaunchKernelGGL(k_zero_counters, dim3((nreps + 63) / 64), dim3(64), 0, s, cnt, nreps, what);
+  hca_launch(k_zero_counters, dim3((nreps + 63) / 64), dim3(64), 0, s, cnt, nreps, what);
 }
 
 void launch_advance(hipStream_t s, long long* d_step) {
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, d_step);
+  hca_launch(k_advance, dim3(1), dim3(1), 0, s, d_step);
 }
 
 void launch_validate_cells(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
                            int rep, unsigned long long* bad) {
-  hipLaunchKernelGGL(k_validate_cells, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, vw, rep, bad);
+  hca_launch(k_validate_cells, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, vw, rep, bad);
 }
 
 }  // namespace hca

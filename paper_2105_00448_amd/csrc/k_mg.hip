@@ -568,14 +568,14 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep*
 
 void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, const double* c) {
   if (mg.lev[0].ntiles)
-    hipLaunchKernelGGL(k_mg_prep0, dim3(grid_for(mg.lev[0].ntiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[0], c);
+    hca_launch(k_mg_prep0, dim3(grid_for(mg.lev[0].ntiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[0], c);
   for (int k = 0; k < mg.nlev_glob; ++k) {
     const MgLevel& Lc = mg.lev[k + 1];
     if (!Lc.nrtiles) continue;
     if (k == 0)
-      hipLaunchKernelGGL(k_mg_coarsen<true>, dim3(grid_for(Lc.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
+      hca_launch(k_mg_coarsen<true>, dim3(grid_for(Lc.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
     else
-      hipLaunchKernelGGL(k_mg_coarsen<false>, dim3(grid_for(Lc.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
+      hca_launch(k_mg_coarsen<false>, dim3(grid_for(Lc.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
   }
 }
 
@@ -590,11 +590,11 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_PRE0, 1);
-    hipLaunchKernelGGL((k_mg_pre<true, double>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
+    hca_launch((k_mg_pre<true, double>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
                        (const double*)sb.r, ss);
     H(MG_PRE0, 0);
     H(MG_RESTRICT0, 1);
-    hipLaunchKernelGGL((k_mg_restrict<true, double>), dim3(grid_for(C.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
+    hca_launch((k_mg_restrict<true, double>), dim3(grid_for(C.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
                        (const double*)sb.r, ss);
     H(MG_RESTRICT0, 0);
   }
@@ -604,15 +604,15 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
       const MgLevel& L = mg.lev[k];
       const MgLevel& C = mg.lev[k + 1];
       if (!L.ntiles) continue;
-      hipLaunchKernelGGL((k_mg_pre<false, float>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
+      hca_launch((k_mg_pre<false, float>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
                          (const float*)L.r, ss);
-      hipLaunchKernelGGL((k_mg_restrict<false, float>), dim3(grid_for(C.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
+      hca_launch((k_mg_restrict<false, float>), dim3(grid_for(C.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
                          (const float*)L.r, ss);
     }
     H(MG_DOWN, 0);
   }
   H(MG_COARSE, 1);
-  hipLaunchKernelGGL(k_mg_coarse, dim3(w.nreps), dim3(kCoarseThreads), mg.coarse_lds_bytes, s,
+  hca_launch(k_mg_coarse, dim3(w.nreps), dim3(kCoarseThreads), mg.coarse_lds_bytes, s,
                      mg.coarse, om, (const float* const*)mg.lev_c, (const float* const*)mg.lev_r,
                      (float* const*)mg.lev_u, ss);
   H(MG_COARSE, 0);
@@ -622,9 +622,9 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
       const MgLevel& L = mg.lev[k];
       const MgLevel& C = mg.lev[k + 1];
       if (!L.ntiles) continue;
-      hipLaunchKernelGGL((k_mg_post1<false, float>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, om,
+      hca_launch((k_mg_post1<false, float>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, om,
                          (const float*)L.r, ss);
-      hipLaunchKernelGGL((k_mg_post2<false, float>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
+      hca_launch((k_mg_post2<false, float>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
                          (const float*)L.r, sb);
     }
     H(MG_UP, 0);
@@ -633,11 +633,11 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_POST1_0, 1);
-    hipLaunchKernelGGL((k_mg_post1<true, double>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, om,
+    hca_launch((k_mg_post1<true, double>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, om,
                        (const double*)sb.r, ss);
     H(MG_POST1_0, 0);
     H(MG_POST2_0, 1);
-    hipLaunchKernelGGL((k_mg_post2<true, double>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
+    hca_launch((k_mg_post2<true, double>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
                        (const double*)sb.r, sb);
     H(MG_POST2_0, 0);
     launch_cg_reduce(s, w, sb, RED_RZ, 0.0, 0);

@@ -871,32 +871,32 @@ __global__ void __launch_bounds__(kBlock) k_mlp_eval(const bf16x8* __restrict__ 
 // ---- launchers --------------------------------------------------------------------
 
 void launch_mlp_gelu_table(hipStream_t s, float2* tab) {
-  hipLaunchKernelGGL(k_mlp_gelu_table, dim3((kGeluN + 1 + 255) / 256), dim3(256), 0, s, tab);
+  hca_launch(k_mlp_gelu_table, dim3((kGeluN + 1 + 255) / 256), dim3(256), 0, s, tab);
 }
 
 void launch_mlp_pack(hipStream_t s, const float* theta, bf16x8* packed) {
-  hipLaunchKernelGGL(k_mlp_pack, dim3((kPackAll + 255) / 256), dim3(256), 0, s, theta, packed);
+  hca_launch(k_mlp_pack, dim3((kPackAll + 255) / 256), dim3(256), 0, s, theta, packed);
 }
 
 void launch_mlp_apply(hipStream_t s, const Work& w, const DevParams& p, const MlpDev& net,
                       const uint8_t* L, const double* K, const double* G1, const double* G2,
                       double* P, double* Vc, double* phi, Counters* cnt) {
-  hipLaunchKernelGGL((k_mlp_apply<true, true>), dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock),
+  hca_launch((k_mlp_apply<true, true>), dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock),
                      0, s, w, p, net, L, K, G1, G2, P, Vc, phi, cnt);
 }
 
 void launch_mlp_count(hipStream_t s, const Work& w, const uint8_t* L, int* item_cnt) {
-  hipLaunchKernelGGL(k_mlp_count, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L,
+  hca_launch(k_mlp_count, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L,
                      item_cnt);
 }
 
 void launch_mlp_scan(hipStream_t s, int n, const int* cnt, long long* off) {
-  hipLaunchKernelGGL(k_mlp_scan, dim3(1), dim3(1024), 0, s, n, cnt, off);
+  hca_launch(k_mlp_scan, dim3(1), dim3(1024), 0, s, n, cnt, off);
 }
 
 void launch_mlp_save_state(hipStream_t s, const Work& w, const double* P, const double* Vc,
                            const double* phi, double* before) {
-  hipLaunchKernelGGL(k_mlp_save_state, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w,
+  hca_launch(k_mlp_save_state, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w,
                      P, Vc, phi, before);
 }
 
@@ -904,47 +904,47 @@ void launch_mlp_harvest(hipStream_t s, const Work& w, const DevParams& p, const 
                         const double* K, const double* G1, const double* G2, const double* P,
                         const double* Vc, const double* before, const long long* item_off,
                         float* X, float* Y) {
-  hipLaunchKernelGGL(k_mlp_harvest, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p,
+  hca_launch(k_mlp_harvest, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p,
                      L, K, G1, G2, P, Vc, before, item_off, X, Y);
 }
 
 void launch_mlp_moments(hipStream_t s, const float* X, const float* Y, long long n, double* part,
                         int nblk, float* stats) {
-  hipLaunchKernelGGL(k_mlp_moments_part, dim3(nblk), dim3(kBlock), 0, s, X, Y, n, part);
-  hipLaunchKernelGGL(k_mlp_moments_fin, dim3(1), dim3(64), 0, s, part, nblk, n, stats);
+  hca_launch(k_mlp_moments_part, dim3(nblk), dim3(kBlock), 0, s, X, Y, n, part);
+  hca_launch(k_mlp_moments_fin, dim3(1), dim3(64), 0, s, part, nblk, n, stats);
 }
 
 void launch_mlp_standardize(hipStream_t s, const float* X, const float* Y, long long n,
                             const float* stats, float* Xs, float* Ys) {
-  hipLaunchKernelGGL(k_mlp_standardize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, Y, n,
+  hca_launch(k_mlp_standardize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, Y, n,
                      stats, Xs, Ys);
 }
 
 void launch_mlp_init(hipStream_t s, uint64_t seed, float* theta) {
-  hipLaunchKernelGGL(k_mlp_init, dim3((kMlpNparam + 255) / 256), dim3(256), 0, s, seed, theta);
+  hca_launch(k_mlp_init, dim3((kMlpNparam + 255) / 256), dim3(256), 0, s, seed, theta);
 }
 
 void launch_mlp_sample(hipStream_t s, uint64_t seed, long long t, long long n, int batch, int* idx) {
-  hipLaunchKernelGGL(k_mlp_sample, dim3((batch + 255) / 256), dim3(256), 0, s, seed, t, n, batch, idx);
+  hca_launch(k_mlp_sample, dim3((batch + 255) / 256), dim3(256), 0, s, seed, t, n, batch, idx);
 }
 
 void launch_mlp_grad(hipStream_t s, const bf16x8* pk, const float* th, const float2* tab,
                      const float* Xs, const float* Ys, const int* idx, int batch, long long nrows,
                      float* partial) {
-  hipLaunchKernelGGL(k_mlp_grad, dim3(batch / kTS), dim3(128), 0, s, pk, th, tab, Xs, Ys, idx, batch,
+  hca_launch(k_mlp_grad, dim3(batch / kTS), dim3(128), 0, s, pk, th, tab, Xs, Ys, idx, batch,
                      nrows, partial);
 }
 
 void launch_mlp_adam(hipStream_t s, float* th, float* m1, float* m2, const float* partial, int nwg,
                      int t, float lr, float b1, float b2, float eps, int update, float* grad_out,
                      float* loss_out, int batch) {
-  hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpNparam + 1 + 255) / 256), dim3(256), 0, s, th, m1, m2,
+  hca_launch(k_mlp_adam, dim3((kMlpNparam + 1 + 255) / 256), dim3(256), 0, s, th, m1, m2,
                      partial, nwg, t, lr, b1, b2, eps, update, grad_out, loss_out, batch);
 }
 
 void launch_mlp_eval(hipStream_t s, const bf16x8* pk, const float* th, const float2* tab,
                      const float* stats, const float* X, long long n, int raw, float* Y) {
-  hipLaunchKernelGGL(k_mlp_eval, dim3((unsigned)((n + 255) / 256)), dim3(kBlock), 0, s, pk, th, tab,
+  hca_launch(k_mlp_eval, dim3((unsigned)((n + 255) / 256)), dim3(kBlock), 0, s, pk, th, tab,
                      stats, X, n, raw, Y);
 }
 

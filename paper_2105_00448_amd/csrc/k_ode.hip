@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(kBlock) k_ode(Work w, DevParams p, const uint8
 
 void launch_ode(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
                 const double* K, double* P, double* Vc, double* phi) {
-  hipLaunchKernelGGL(k_ode, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, K,
+  hca_launch(k_ode, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, K,
                      P, Vc, phi);
 }
 

@@ -136,31 +136,31 @@ __global__ void __launch_bounds__(kBlock) k_init_cells(Work w, DevParams p, cons
 void launch_plasma(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
                    const double* dose_t, const double* dose_a, double* g0) {
   const int nb = (w.nreps + 63) / 64;
-  hipLaunchKernelGGL(k_plasma, dim3(nb), dim3(64), 0, s, w.nreps, w.reps, p, d_step, dose_t,
+  hca_launch(k_plasma, dim3(nb), dim3(64), 0, s, w.nreps, w.reps, p, d_step, dose_t,
                      dose_a, g0);
 }
 
 void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
                      const double* vw, const double* K, double* c, double* b, int steady) {
-  hipLaunchKernelGGL(k_setup_o2, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, vw, K, c, b, steady);
+  hca_launch(k_setup_o2, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, vw, K, c, b, steady);
 }
 
 void launch_setup_drug(hipStream_t s, const Work& w, const DevParams& p, int drug,
                        const double* vw, const double* G, const double* g0, double* c,
                        double* b) {
-  hipLaunchKernelGGL(k_setup_drug, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, drug, vw, G, g0, c, b);
+  hca_launch(k_setup_drug, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, drug, vw, G, g0, c, b);
 }
 
 void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
                        const uint8_t* L, const double* vw, const double* F, const double* g0,
                        double* c, double* b) {
-  hipLaunchKernelGGL(k_setup_step, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot, L, vw, F, g0, c,
+  hca_launch(k_setup_step, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot, L, vw, F, g0, c,
                      b);
 }
 
 void launch_init_cells(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
                        const double* K, double* P, double* Vc, double* phi) {
-  hipLaunchKernelGGL(k_init_cells, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, K, P, Vc, phi);
+  hca_launch(k_init_cells, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, K, P, Vc, phi);
 }
 
 }  // namespace hca

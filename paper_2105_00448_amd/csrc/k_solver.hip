@@ -323,16 +323,16 @@ void launch_cg_reduce(hipStream_t s, const Work& w, const SolverBufs& sb, int ki
   const dim3 g(w.nreps), b(kBlock);
   switch (kind) {
     case RED_START:
-      hipLaunchKernelGGL(k_cg_reduce<RED_START>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
+      hca_launch(k_cg_reduce<RED_START>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
       break;
     case RED_APPLY:
-      hipLaunchKernelGGL(k_cg_reduce<RED_APPLY>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
+      hca_launch(k_cg_reduce<RED_APPLY>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
       break;
     case RED_UPDATE:
-      hipLaunchKernelGGL(k_cg_reduce<RED_UPDATE>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
+      hca_launch(k_cg_reduce<RED_UPDATE>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
       break;
     default:
-      hipLaunchKernelGGL(k_cg_reduce<RED_RZ>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
+      hca_launch(k_cg_reduce<RED_RZ>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
       break;
   }
 }
@@ -340,8 +340,8 @@ void launch_cg_reduce(hipStream_t s, const Work& w, const SolverBufs& sb, int ki
 void launch_cg_start(hipStream_t s, const Work& w, double rtol, int maxit, const double* c,
                      const double* b, const double* x, const SolverBufs& sb, unsigned field_mask,
                      int nrep) {
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, sb.ndone);
-  hipLaunchKernelGGL(k_cg_start, dim3(grid_for(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c, b, x, sb);
+  hca_launch(k_cg_start, dim3(grid_for(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c, b, x, sb);
+  hca_launch(k_zero_int, dim3(1), dim3(1), 0, s, sb.ndone);   // before the start reduce counts
   launch_cg_reduce(s, w, sb, RED_START, rtol, maxit, field_mask, nrep);
 }
 
@@ -349,7 +349,7 @@ void launch_cg_apply_kernel(hipStream_t s, const Work& w, const double* c, const
                             int parity) {
   const double* pold = parity ? sb.p1 : sb.p0;
   double* pnew = parity ? sb.p0 : sb.p1;
-  hipLaunchKernelGGL(k_cg_apply, dim3(grid_for(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c,
+  hca_launch(k_cg_apply, dim3(grid_for(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c,
                      sb.z, pold, pnew, sb.q, sb);
 }
 
@@ -362,7 +362,7 @@ void launch_cg_apply(hipStream_t s, const Work& w, const double* c, const Solver
 void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, double* x,
                       const SolverBufs& sb, int parity) {
   const double* pnew = parity ? sb.p0 : sb.p1;
-  hipLaunchKernelGGL(k_cg_update, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, x, pnew,
+  hca_launch(k_cg_update, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, x, pnew,
                      (const double*)sb.q, sb);
   launch_cg_reduce(s, w, sb, RED_UPDATE, rtol, maxit);
 }

@@ -25,6 +25,7 @@
 using namespace hca;
 
 namespace hca {
+thread_local KernelEvents g_kernel_events;
 int g_xcd_remap = 0;   // measured slower on the 128^3 workload (HCA_XCD_REMAP=1 to enable)
 }
 
@@ -200,22 +201,44 @@ inline bool prof_on(const hca_ctx* c, int kc) {
   return c->prm.profile == 1 || c->prm.profile == kc + 2;
 }
 
+// Times the launches issued while it is alive.  single: the first kernel
+// launched (through hca_launch) carries the start/stop events itself, so the
+// time is that kernel's execution; otherwise events are recorded on the
+// stream before and after (a segment of several kernels, gaps included).
 struct ProfScope {
   hca_ctx* c;
   int kc;
   int tag;
-  hipEvent_t a = nullptr;
-  ProfScope(hca_ctx* c_, int kc_, int tag_) : c(c_), kc(kc_), tag(tag_) {
-    if (prof_on(c, kc)) {
-      a = take_event(c);
-      if (a) (void)hipEventRecord(a, c->stream);
+  bool single;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(hca_ctx* c_, int kc_, int tag_, bool single_ = true)
+      : c(c_), kc(kc_), tag(tag_), single(single_) {
+    if (!prof_on(c, kc)) return;
+    a = take_event(c);
+    b = take_event(c);
+    if (!a || !b) {
+      if (a) c->free_events.push_back(a);
+      if (b) c->free_events.push_back(b);
+      a = b = nullptr;
+      return;
     }
+    if (single)
+      g_kernel_events = KernelEvents{a, b};
+    else
+      (void)hipEventRecord(a, c->stream);
   }
   ~ProfScope() {
     if (!a) return;
-    hipEvent_t b = take_event(c);
-    if (!b) return;
-    (void)hipEventRecord(b, c->stream);
+    if (single) {
+      if (g_kernel_events.start == a) {   // nothing was launched
+        g_kernel_events = KernelEvents{};
+        c->free_events.push_back(a);
+        c->free_events.push_back(b);
+        return;
+      }
+    } else {
+      (void)hipEventRecord(b, c->stream);
+    }
     c->pending.push_back(ProfEntry{kc, a, b, tag, bpv_of(c, kc)});
   }
 };
@@ -371,7 +394,7 @@ hca_status solve(hca_ctx* c, const Work& W, const MgBufs& mg, unsigned fmask, do
                  int maxit, int kind) {
   const int nsys = W.nreps;
   if (c->use_mg) {
-    ProfScope ps(c, KC_MG_PREP, kTagAll);
+    ProfScope ps(c, KC_MG_PREP, kTagAll, false);
     launch_mg_prepare(c->stream, W, mg, c->c);
   }
   {
