@@ -54,6 +54,24 @@ __device__ inline void work_range(int T, int& begin, int& end) {
   end = (int)((long long)(lb + 1) * T / G);
 }
 
+// Stencil tiles: with a grid that is a multiple of 8 * kXcdChunk the tiles
+// are dealt to the 8 XCDs in runs of kXcdChunk consecutive tiles, round robin
+// (run k to XCD k mod 8), one tile per workgroup: neighbouring tiles share
+// their frame rows in one XCD's L2 while every system's tiles still spread
+// over all XCDs (systems finish at different iterations).  Otherwise as
+// work_range.
+__device__ inline void tile_range(int T, int& begin, int& end) {
+  const int G = gridDim.x, b = blockIdx.x;
+  if (G % (8 * kXcdChunk) == 0) {
+    const int x = b % 8, j = b / 8;   // j-th workgroup of XCD x
+    const int t = ((j / kXcdChunk) * 8 + x) * kXcdChunk + j % kXcdChunk;
+    begin = min(t, T);
+    end = min(t + 1, T);
+    return;
+  }
+  work_range(T, begin, end);
+}
+
 // A workgroup's three partial sums, stored at its work-item slot (3 doubles);
 // a later reduce kernel (one workgroup per replicate) sums the slots of a
 // replicate in a fixed order.  The kernel boundary orders the two.

@@ -125,6 +125,22 @@ struct Work {
 // a multiple of 8 and workgroup b takes run b.
 extern int g_xcd_remap;
 
+// Tile kernels: runs of kXcdChunk consecutive tiles per XCD (tile_range)
+// when g_tile_remap is set; the grid is then n rounded up to 8 * kXcdChunk.
+constexpr int kXcdChunk = 16;
+extern int g_tile_remap;
+inline int grid_tiles(int n, int max_blocks) {
+  if (g_tile_remap && n <= max_blocks) return (n + 8 * kXcdChunk - 1) / (8 * kXcdChunk) * (8 * kXcdChunk);
+  int g = n < max_blocks ? n : max_blocks;
+  if (g < 1) g = 1;
+  if (g % (8 * kXcdChunk) == 0) g += 1;
+  if (g_xcd_remap)
+    g = (g + 7) / 8 * 8;
+  else if (g % 8 == 0)
+    g += 1;
+  return g;
+}
+
 // Grid of a launch over n work items, at most max_blocks workgroups.
 inline int grid_for(int n, int max_blocks) {
   int g = n < max_blocks ? n : max_blocks;

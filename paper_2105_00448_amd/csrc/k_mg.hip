@@ -195,7 +195,7 @@ __device__ inline TileXY tile_xy(const Tile* tiles, const MgRep* reps, int ti) {
 // Every kernel below loops over its workgroup's contiguous run of tiles.
 #define FOR_MY_TILES(ntiles)   \
   int tile_b_, tile_e_;        \
-  work_range((ntiles), tile_b_, tile_e_); \
+  tile_range((ntiles), tile_b_, tile_e_); \
   for (int ti = tile_b_; ti < tile_e_; ++ti)
 
 // ---- setup per solve -------------------------------------------------------
@@ -568,14 +568,14 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep*
 
 void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, const double* c) {
   if (mg.lev[0].ntiles)
-    hca_launch(k_mg_prep0, dim3(grid_for(mg.lev[0].ntiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[0], c);
+    hca_launch(k_mg_prep0, dim3(grid_tiles(mg.lev[0].ntiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[0], c);
   for (int k = 0; k < mg.nlev_glob; ++k) {
     const MgLevel& Lc = mg.lev[k + 1];
     if (!Lc.nrtiles) continue;
     if (k == 0)
-      hca_launch(k_mg_coarsen<true>, dim3(grid_for(Lc.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
+      hca_launch(k_mg_coarsen<true>, dim3(grid_tiles(Lc.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
     else
-      hca_launch(k_mg_coarsen<false>, dim3(grid_for(Lc.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
+      hca_launch(k_mg_coarsen<false>, dim3(grid_tiles(Lc.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
   }
 }
 
@@ -590,11 +590,11 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_PRE0, 1);
-    hca_launch((k_mg_pre<true, double>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
+    hca_launch((k_mg_pre<true, double>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
                        (const double*)sb.r, ss);
     H(MG_PRE0, 0);
     H(MG_RESTRICT0, 1);
-    hca_launch((k_mg_restrict<true, double>), dim3(grid_for(C.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
+    hca_launch((k_mg_restrict<true, double>), dim3(grid_tiles(C.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
                        (const double*)sb.r, ss);
     H(MG_RESTRICT0, 0);
   }
@@ -604,9 +604,9 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
       const MgLevel& L = mg.lev[k];
       const MgLevel& C = mg.lev[k + 1];
       if (!L.ntiles) continue;
-      hca_launch((k_mg_pre<false, float>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
+      hca_launch((k_mg_pre<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
                          (const float*)L.r, ss);
-      hca_launch((k_mg_restrict<false, float>), dim3(grid_for(C.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
+      hca_launch((k_mg_restrict<false, float>), dim3(grid_tiles(C.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
                          (const float*)L.r, ss);
     }
     H(MG_DOWN, 0);
@@ -622,9 +622,9 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
       const MgLevel& L = mg.lev[k];
       const MgLevel& C = mg.lev[k + 1];
       if (!L.ntiles) continue;
-      hca_launch((k_mg_post1<false, float>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, om,
+      hca_launch((k_mg_post1<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, om,
                          (const float*)L.r, ss);
-      hca_launch((k_mg_post2<false, float>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
+      hca_launch((k_mg_post2<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
                          (const float*)L.r, sb);
     }
     H(MG_UP, 0);
@@ -633,11 +633,11 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_POST1_0, 1);
-    hca_launch((k_mg_post1<true, double>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, om,
+    hca_launch((k_mg_post1<true, double>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, om,
                        (const double*)sb.r, ss);
     H(MG_POST1_0, 0);
     H(MG_POST2_0, 1);
-    hca_launch((k_mg_post2<true, double>), dim3(grid_for(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
+    hca_launch((k_mg_post2<true, double>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
                        (const double*)sb.r, sb);
     H(MG_POST2_0, 0);
     launch_cg_reduce(s, w, sb, RED_RZ, 0.0, 0);

@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_start(Work w, const double* __res
   __shared__ double lds4[4];
   __shared__ double lds[2][kPlaneMax];
   int t0, t1;
-  work_range(w.ntiles, t0, t1);
+  tile_range(w.ntiles, t0, t1);
   for (int ti = t0; ti < t1; ++ti) {
     const TileCoord tc = tile_coord(w, ti);
     const double a = tc.a;
@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, const double* __res
   __shared__ double lds4[4];
   __shared__ double lds[2][kPlaneMax];
   int t0, t1;
-  work_range(w.ntiles, t0, t1);
+  tile_range(w.ntiles, t0, t1);
   for (int ti = t0; ti < t1; ++ti) {
     const TileCoord tc = tile_coord(w, ti);
     const SolveScal* ssr = sb.ss + tc.rep;
@@ -340,7 +340,7 @@ void launch_cg_reduce(hipStream_t s, const Work& w, const SolverBufs& sb, int ki
 void launch_cg_start(hipStream_t s, const Work& w, double rtol, int maxit, const double* c,
                      const double* b, const double* x, const SolverBufs& sb, unsigned field_mask,
                      int nrep) {
-  hca_launch(k_cg_start, dim3(grid_for(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c, b, x, sb);
+  hca_launch(k_cg_start, dim3(grid_tiles(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c, b, x, sb);
   hca_launch(k_zero_int, dim3(1), dim3(1), 0, s, sb.ndone);   // before the start reduce counts
   launch_cg_reduce(s, w, sb, RED_START, rtol, maxit, field_mask, nrep);
 }
@@ -349,7 +349,7 @@ void launch_cg_apply_kernel(hipStream_t s, const Work& w, const double* c, const
                             int parity) {
   const double* pold = parity ? sb.p1 : sb.p0;
   double* pnew = parity ? sb.p0 : sb.p1;
-  hca_launch(k_cg_apply, dim3(grid_for(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c,
+  hca_launch(k_cg_apply, dim3(grid_tiles(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c,
                      sb.z, pold, pnew, sb.q, sb);
 }
 
