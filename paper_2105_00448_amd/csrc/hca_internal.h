@@ -234,6 +234,8 @@ struct MgCoarseRep {
   int dims[kMaxLevels][3];
   int lds_off[kMaxLevels];  // float offset of each level's (u, r, dinv) block
   long long off_kc;         // replicate offset in the level-kc arrays
+  long long pre_off;        // this system's block in MgBufs::coarse_pre
+  int pre_lev[kMaxLevels];  // level j's [D^-1 | gx | gy | gz] within the block
   float a;
 };
 
@@ -241,6 +243,7 @@ struct MgBufs {
   MgLevel lev[kMaxLevels];
   int nlev_glob;            // max over replicates of kc
   const MgCoarseRep* coarse;
+  float* coarse_pre;        // per solve: couplings and D^-1 of the coarse-solve levels
   int coarse_lds_bytes;
   float omega;
   float** lev_c;            // device arrays of the per-level pointers

@@ -407,10 +407,14 @@ __global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float omega,
 struct CoarseLevel {
   Geo<false> G;
   int n;
-  float *u, *r, *dinv;
+  float *u, *r, *dinv;        // LDS
+  const float *gx, *gy, *gz;  // couplings to the +x/+y/+z neighbour (0 at the edge), global
 };
 
-__device__ inline CoarseLevel coarse_level(const MgCoarseRep& cr, float* lds, int j, float a) {
+// Level j of a system's coarse solve: LDS block (u, r, D^-1) and the
+// precomputed block pre = [D^-1 | gx | gy | gz] (4 n floats, per solve).
+__device__ inline CoarseLevel coarse_level(const MgCoarseRep& cr, float* lds, const float* pre, int j,
+                                           float a) {
   CoarseLevel L;
   L.G.nx = cr.dims[j][0];
   L.G.ny = cr.dims[j][1];
@@ -424,6 +428,10 @@ __device__ inline CoarseLevel coarse_level(const MgCoarseRep& cr, float* lds, in
   L.u = lds + cr.lds_off[j];
   L.r = L.u + L.n;
   L.dinv = L.r + L.n;
+  const float* g = pre + cr.pre_off + cr.pre_lev[j];
+  L.gx = g + L.n;
+  L.gy = g + 2 * L.n;
+  L.gz = g + 3 * L.n;
   return L;
 }
 
@@ -434,16 +442,17 @@ __device__ inline void coords(int t, int nx, int ny, int& x, int& y, int& z) {
   z = q / ny;
 }
 
+// sum_J g_IJ v_J over the existing neighbours, in the order -x, +x, -y, +y, -z, +z
 __device__ inline float lds_nbsum(const CoarseLevel& L, const float* v, int t, int x, int y, int z) {
   const Geo<false>& G = L.G;
   const int plane = G.nx * G.ny;
   float s = 0.f;
-  if (x > 0) s += G.gx(x - 1, y, z) * v[t - 1];
-  if (x + 1 < G.nx) s += G.gx(x, y, z) * v[t + 1];
-  if (y > 0) s += G.gy(x, y - 1, z) * v[t - G.nx];
-  if (y + 1 < G.ny) s += G.gy(x, y, z) * v[t + G.nx];
-  if (z > 0) s += G.gz(x, y, z - 1) * v[t - plane];
-  if (z + 1 < G.nz) s += G.gz(x, y, z) * v[t + plane];
+  if (x > 0) s += L.gx[t - 1] * v[t - 1];
+  if (x + 1 < G.nx) s += L.gx[t] * v[t + 1];
+  if (y > 0) s += L.gy[t - G.nx] * v[t - G.nx];
+  if (y + 1 < G.ny) s += L.gy[t] * v[t + G.nx];
+  if (z > 0) s += L.gz[t - plane] * v[t - plane];
+  if (z + 1 < G.nz) s += L.gz[t] * v[t + plane];
   return s;
 }
 
@@ -467,32 +476,26 @@ __device__ inline void lds_jacobi(const CoarseLevel& L, float omega) {
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep* coarse,
-                                                              float omega, const float* const* lev_c,
-                                                              const float* const* lev_r,
-                                                              float* const* lev_u,
-                                                              const SolveScal* ss) {
+// Once per solve, one workgroup per system: coarse reaction terms of the
+// one-workgroup levels (summed from level kc, kept in the LDS u slots), then
+// each level's couplings and D^-1 into the system's precomputed block.
+__global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse_prep(const MgCoarseRep* coarse,
+                                                                   const float* const* lev_c,
+                                                                   float* __restrict__ pre) {
   extern __shared__ float lds[];
   const int rep = blockIdx.x;
-  if (ss[rep].done) return;
   const MgCoarseRep& cr = coarse[rep];
   const float a = cr.a;
   const int J = cr.nlev;
-  // load level kc: r, and c (into the u slot)
   {
-    const CoarseLevel L = coarse_level(cr, lds, 0, a);
+    const CoarseLevel L = coarse_level(cr, lds, pre, 0, a);
     const float* gc = lev_c[cr.kc] + cr.off_kc;
-    const float* gr = lev_r[cr.kc] + cr.off_kc;
-    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) {
-      L.u[t] = gc[t];
-      L.r[t] = gr[t];
-    }
+    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) L.u[t] = gc[t];
   }
   __syncthreads();
-  // coarser c by summation, then Dinv on every level
   for (int j = 1; j < J; ++j) {
-    const CoarseLevel F = coarse_level(cr, lds, j - 1, a);
-    const CoarseLevel C = coarse_level(cr, lds, j, a);
+    const CoarseLevel F = coarse_level(cr, lds, pre, j - 1, a);
+    const CoarseLevel C = coarse_level(cr, lds, pre, j, a);
     for (int t = threadIdx.x; t < C.n; t += kCoarseThreads) {
       int X, Y, Z;
       coords(t, C.G.nx, C.G.ny, X, Y, Z);
@@ -506,21 +509,53 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep*
     __syncthreads();
   }
   for (int j = 0; j < J; ++j) {
-    const CoarseLevel L = coarse_level(cr, lds, j, a);
+    const CoarseLevel L = coarse_level(cr, lds, pre, j, a);
+    float* g = pre + cr.pre_off + cr.pre_lev[j];
     for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) {
       int x, y, z;
       coords(t, L.G.nx, L.G.ny, x, y, z);
-      L.dinv[t] = 1.f / (L.u[t] + L.G.gsum(x, y, z));
+      g[t] = 1.f / (L.u[t] + L.G.gsum(x, y, z));
+      g[L.n + t] = x + 1 < L.G.nx ? L.G.gx(x, y, z) : 0.f;
+      g[2 * L.n + t] = y + 1 < L.G.ny ? L.G.gy(x, y, z) : 0.f;
+      g[3 * L.n + t] = z + 1 < L.G.nz ? L.G.gz(x, y, z) : 0.f;
     }
+  }
+}
+
+// The V-cycle of levels kc.. of one system in LDS (one workgroup per system):
+// pre-smooth, restrict, ..., the one-cell level solved exactly, prolong
+// (piecewise constant), post-smooth; the correction of level kc is written
+// to that level's global u.
+__global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep* coarse,
+                                                              float omega, const float* const* lev_r,
+                                                              float* const* lev_u,
+                                                              const float* __restrict__ pre,
+                                                              const SolveScal* ss) {
+  extern __shared__ float lds[];
+  const int rep = blockIdx.x;
+  if (ss[rep].done) return;
+  const MgCoarseRep& cr = coarse[rep];
+  const float a = cr.a;
+  const int J = cr.nlev;
+  // r of level kc and D^-1 of every level into LDS
+  {
+    const CoarseLevel L = coarse_level(cr, lds, pre, 0, a);
+    const float* gr = lev_r[cr.kc] + cr.off_kc;
+    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) L.r[t] = gr[t];
+  }
+  for (int j = 0; j < J; ++j) {
+    const CoarseLevel L = coarse_level(cr, lds, pre, j, a);
+    const float* g = pre + cr.pre_off + cr.pre_lev[j];
+    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) L.dinv[t] = g[t];
   }
   __syncthreads();
   // down
   for (int j = 0; j + 1 < J; ++j) {
-    const CoarseLevel L = coarse_level(cr, lds, j, a);
+    const CoarseLevel L = coarse_level(cr, lds, pre, j, a);
     for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) L.u[t] = omega * L.dinv[t] * L.r[t];
     __syncthreads();
     lds_jacobi(L, omega);
-    const CoarseLevel C = coarse_level(cr, lds, j + 1, a);
+    const CoarseLevel C = coarse_level(cr, lds, pre, j + 1, a);
     for (int t = threadIdx.x; t < C.n; t += kCoarseThreads) {
       int X, Y, Z;
       coords(t, C.G.nx, C.G.ny, X, Y, Z);
@@ -538,7 +573,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep*
   }
   // coarsest: one cell and no faces, so u = r / c exactly; larger: sweeps
   {
-    const CoarseLevel L = coarse_level(cr, lds, J - 1, a);
+    const CoarseLevel L = coarse_level(cr, lds, pre, J - 1, a);
     for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) L.u[t] = L.dinv[t] * L.r[t];
     __syncthreads();
     if (L.n > 1)
@@ -546,8 +581,8 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep*
   }
   // up
   for (int j = J - 2; j >= 0; --j) {
-    const CoarseLevel L = coarse_level(cr, lds, j, a);
-    const CoarseLevel C = coarse_level(cr, lds, j + 1, a);
+    const CoarseLevel L = coarse_level(cr, lds, pre, j, a);
+    const CoarseLevel C = coarse_level(cr, lds, pre, j + 1, a);
     for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) {
       int x, y, z;
       coords(t, L.G.nx, L.G.ny, x, y, z);
@@ -558,7 +593,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep*
     lds_jacobi(L, omega);
   }
   {
-    const CoarseLevel L = coarse_level(cr, lds, 0, a);
+    const CoarseLevel L = coarse_level(cr, lds, pre, 0, a);
     float* gu = lev_u[cr.kc] + cr.off_kc;
     for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) gu[t] = L.u[t];
   }
@@ -577,6 +612,8 @@ void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, const dou
     else
       hca_launch(k_mg_coarsen<false>, dim3(grid_tiles(Lc.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
   }
+  hca_launch(k_mg_coarse_prep, dim3(w.nreps), dim3(kCoarseThreads), mg.coarse_lds_bytes, s, mg.coarse,
+             (const float* const*)mg.lev_c, mg.coarse_pre);
 }
 
 void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const SolverBufs& sb,
@@ -612,9 +649,8 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
     H(MG_DOWN, 0);
   }
   H(MG_COARSE, 1);
-  hca_launch(k_mg_coarse, dim3(w.nreps), dim3(kCoarseThreads), mg.coarse_lds_bytes, s,
-                     mg.coarse, om, (const float* const*)mg.lev_c, (const float* const*)mg.lev_r,
-                     (float* const*)mg.lev_u, ss);
+  hca_launch(k_mg_coarse, dim3(w.nreps), dim3(kCoarseThreads), mg.coarse_lds_bytes, s, mg.coarse, om,
+             (const float* const*)mg.lev_r, (float* const*)mg.lev_u, (const float*)mg.coarse_pre, ss);
   H(MG_COARSE, 0);
   if (mg.nlev_glob > 1) {
     H(MG_UP, 1);

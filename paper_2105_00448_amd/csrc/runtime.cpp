@@ -1092,6 +1092,7 @@ hca_status build_mg(hca_ctx* c) {
   // coarse-solve descriptors
   std::vector<MgCoarseRep> cr(S);
   size_t lds_max = 0;
+  long long pre_total = 0;
   for (int s = 0; s < S; ++s) {
     const int r = s % R;
     MgCoarseRep& d = cr[s];
@@ -1100,24 +1101,30 @@ hca_status build_mg(hca_ctx* c) {
     d.nlev = (int)dims[r].size() - kcr[r];
     d.a = (float)sd[s].a;
     for (int i = 0; i < 3; ++i) d.n0[i] = dims[r][0][i];
-    int o = 0;
+    int o = 0, g = 0;
     for (int j = 0; j < d.nlev; ++j) {
       for (int i = 0; i < 3; ++i) d.dims[j][i] = dims[r][kcr[r] + j][i];
       d.lds_off[j] = o;
+      d.pre_lev[j] = g;
       o += 3 * d.dims[j][0] * d.dims[j][1] * d.dims[j][2];
+      g += 4 * d.dims[j][0] * d.dims[j][1] * d.dims[j][2];
     }
     lds_max = std::max(lds_max, (size_t)o * sizeof(float));
     d.off_kc = mreps[kcr[r]][s].off;
+    d.pre_off = pre_total;
+    pre_total += g;
   }
   MgCoarseRep* dcr = nullptr;
   hca_status st = mg_upload(c, &dcr, cr);
   if (st != HCA_OK) return st;
   mg.coarse = dcr;
   mg.coarse_lds_bytes = (int)lds_max;
+  if ((st = mg_alloc(c, &mg.coarse_pre, (size_t)pre_total)) != HCA_OK) return st;
   if ((st = mg_upload(c, &mg.lev_c, pc)) != HCA_OK || (st = mg_upload(c, &mg.lev_r, pr)) != HCA_OK ||
       (st = mg_upload(c, &mg.lev_u, pu)) != HCA_OK)
     return st;
   c->mg1.coarse = mg.coarse;
+  c->mg1.coarse_pre = mg.coarse_pre;
   c->mg1.coarse_lds_bytes = mg.coarse_lds_bytes;
   c->mg1.lev_c = mg.lev_c;
   c->mg1.lev_r = mg.lev_r;
