@@ -170,7 +170,9 @@ void launch_init_cells(hipStream_t s, const Work& w, const DevParams& p, const u
 
 // solver (k_solver.hip)
 struct SolverBufs {
-  double *r, *z, *p0, *p1, *q;
+  double *r, *z, *p0, *p1, *q;   // z: Jacobi preconditioner only
+  float* z32;                    // z of the multigrid preconditioner (FP32 result)
+  float* r32;                    // FP32 copy of r for the multigrid's fine level
   double* dinv;               // 1/diag(A), written by the start kernel (Jacobi)
   int jacobi;                 // 1: Jacobi preconditioner inside the update kernel
   double* partial;            // per work item

@@ -387,7 +387,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float omega,
       mg_plane(G, t, m.tx, m.off, lds, U4, [&](int, long long i, float u4, float s) {
         const float u5 = (1.f - omega) * u4 + omega * dinv[i] * ((float)r[i] + s);
         if (L0) {
-          sb.z[i] = (double)u5;
+          sb.z32[i] = u5;
           rz += (double)r[i] * (double)u5;
         } else {
           Lk.u[i] = u5;
@@ -627,12 +627,12 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_PRE0, 1);
-    hca_launch((k_mg_pre<true, double>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
-                       (const double*)sb.r, ss);
+    hca_launch((k_mg_pre<true, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
+                       (const float*)sb.r32, ss);
     H(MG_PRE0, 0);
     H(MG_RESTRICT0, 1);
-    hca_launch((k_mg_restrict<true, double>), dim3(grid_tiles(C.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
-                       (const double*)sb.r, ss);
+    hca_launch((k_mg_restrict<true, float>), dim3(grid_tiles(C.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
+                       (const float*)sb.r32, ss);
     H(MG_RESTRICT0, 0);
   }
   if (mg.nlev_glob > 1) {
@@ -669,8 +669,8 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_POST1_0, 1);
-    hca_launch((k_mg_post1<true, double>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, om,
-                       (const double*)sb.r, ss);
+    hca_launch((k_mg_post1<true, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, om,
+                       (const float*)sb.r32, ss);
     H(MG_POST1_0, 0);
     H(MG_POST2_0, 1);
     hca_launch((k_mg_post2<true, double>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,

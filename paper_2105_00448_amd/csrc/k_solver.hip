@@ -155,6 +155,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_start(Work w, const double* __res
                        const double bi = b[i];
                        const double r = bi - Ax;
                        sb.r[i] = r;
+                       if (!sb.jacobi) sb.r32[i] = (float)r;
                        bb += bi * bi;
                        rr += r * r;
                        if (sb.jacobi) {
@@ -174,6 +175,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_start(Work w, const double* __res
 }
 
 // p_new = z + beta p_old (p_new = z on the first iteration), q = A p_new.
+template <bool JAC>
 __global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, const double* __restrict__ c,
                                                      const double* __restrict__ z,
                                                      const double* __restrict__ pold,
@@ -191,7 +193,14 @@ __global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, const double* __res
     const bool first = ssr->first != 0;
     double pq = 0.0;
     {
-      auto U = [&](long long j) { return first ? z[j] : z[j] + beta * pold[j]; };
+      // z: FP64 (Jacobi) or the multigrid's FP32 result, widened exactly
+      auto Z = [&](long long j) {
+        if constexpr (JAC)
+          return z[j];
+        else
+          return (double)sb.z32[j];
+      };
+      auto U = [&](long long j) { return first ? Z(j) : Z(j) + beta * pold[j]; };
       plane_stencil(tc, c, lds, U, [&](long long i, int, double pc, double Ap) {
         pnew[i] = pc;
         q[i] = Ap;
@@ -204,12 +213,13 @@ __global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, const double* __res
 }
 
 // x += alpha p, r -= alpha q; partials of r.r, r.z_old and (Jacobi) r.z'.
+template <bool JAC>
 __global__ void __launch_bounds__(kBlock) k_cg_update(Work w, double* __restrict__ x,
                                                       const double* __restrict__ p,
                                                       const double* __restrict__ q,
                                                       SolverBufs sb) {
   __shared__ double lds4[4];
-  const bool jac = sb.jacobi != 0;
+  constexpr bool jac = JAC;
   int b0, b1;
   work_range(w.nflat, b0, b1);
   for (int it = b0; it < b1; ++it) {
@@ -223,7 +233,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(Work w, double* __restrict
       x[i] += alpha * p[i];
       const double r = sb.r[i] - alpha * q[i];
       sb.r[i] = r;
-      const double zold = sb.z[i];
+      if (!jac) sb.r32[i] = (float)r;   // the multigrid's copy
+      const double zold = jac ? sb.z[i] : (double)sb.z32[i];
       rr += r * r;
       rzo += r * zold;
       if (jac) {
@@ -349,8 +360,12 @@ void launch_cg_apply_kernel(hipStream_t s, const Work& w, const double* c, const
                             int parity) {
   const double* pold = parity ? sb.p1 : sb.p0;
   double* pnew = parity ? sb.p0 : sb.p1;
-  hca_launch(k_cg_apply, dim3(grid_tiles(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c,
-                     sb.z, pold, pnew, sb.q, sb);
+  if (sb.jacobi)
+    hca_launch(k_cg_apply<true>, dim3(grid_tiles(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c,
+               sb.z, pold, pnew, sb.q, sb);
+  else
+    hca_launch(k_cg_apply<false>, dim3(grid_tiles(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c,
+               sb.z, pold, pnew, sb.q, sb);
 }
 
 void launch_cg_apply(hipStream_t s, const Work& w, const double* c, const SolverBufs& sb,
@@ -362,8 +377,12 @@ void launch_cg_apply(hipStream_t s, const Work& w, const double* c, const Solver
 void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, double* x,
                       const SolverBufs& sb, int parity) {
   const double* pnew = parity ? sb.p0 : sb.p1;
-  hca_launch(k_cg_update, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, x, pnew,
-                     (const double*)sb.q, sb);
+  if (sb.jacobi)
+    hca_launch(k_cg_update<true>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, x,
+               pnew, (const double*)sb.q, sb);
+  else
+    hca_launch(k_cg_update<false>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, x,
+               pnew, (const double*)sb.q, sb);
   launch_cg_reduce(s, w, sb, RED_UPDATE, rtol, maxit);
 }
 

@@ -51,7 +51,7 @@ const double kBytesPerVoxel[KC_COUNT] = {
     0.0,          // plasma: per replicate only
     81.0,         // setup_step: read L, w, K, G1, G2; write c, b of three systems
     40.0,         // cg_start: read x, c, b; write r, (Jacobi: dinv, z)
-    40.0,         // cg_apply: read z, p_old, c; write p_new, q
+    36.0,         // cg_apply, multigrid: read z (4), p_old, c; write p_new, q
     72.0,         // cg_update, Jacobi: read x, p, r, q, z, dinv; write x, r, z
     57.0,         // ode: read L, K, P, Vc, phi; write P, Vc, phi
     10.0,         // ca_propose: read L, phi; write code
@@ -59,14 +59,15 @@ const double kBytesPerVoxel[KC_COUNT] = {
     2.0,          // ca_finalize: read code, win (writes only where cells change)
     57.0,         // stats: read L, w and six fields
     21.0,         // mg prepare: read c (8); write dinv0 (4); level 1: read c, write c1, dinv1
-    16.0,         // mg pre L0: read r (8), dinv (4); write u (4)
-    16.5,         // mg restrict L0: read u, r, dinv; write r1 (1/8 of 4)
+    12.0,         // mg pre L0: read r (FP32 copy, 4), dinv (4); write u (4)
+    12.5,         // mg restrict L0: read u, r (4), dinv; write r1 (1/8 of 4)
     0.0,          // coarser global levels
     0.0,          // coarse workgroup levels
-    20.5,         // mg post1 L0: read u, e (1/8), r, dinv; write ualt
-    24.0,         // mg post2 L0: read ualt, r, dinv; write z (8)
+    16.5,         // mg post1 L0: read u, e (1/8), r (4), dinv; write ualt
+    20.0,         // mg post2 L0: read ualt, r, dinv; write z (4)
     73.0};        // mlp apply: read L, K, G1, G2, P, Vc, phi; write P, Vc, phi
-constexpr double kBytesUpdateMg = 56.0;   // cg_update, multigrid: read x, p, r, q, z; write x, r
+constexpr double kBytesUpdateMg = 56.0;   // cg_update, multigrid: read x, p, r, q, z (4); write x, r, r (4)
+constexpr double kBytesApplyJacobi = 40.0;   // cg_apply, Jacobi: z is FP64
 
 constexpr int kTagState = -2;   // launches over every voxel of every replicate
 constexpr int kTagAll = -1;     // solver launches over every system
@@ -194,6 +195,7 @@ hipEvent_t take_event(hca_ctx* c) {
 
 double bpv_of(const hca_ctx* c, int kc) {
   if (kc == KC_CG_UPDATE && c->use_mg) return kBytesUpdateMg;
+  if (kc == KC_CG_APPLY && !c->use_mg) return kBytesApplyJacobi;
   return kBytesPerVoxel[kc];
 }
 
@@ -729,7 +731,7 @@ hca_status plan_tiles(hca_ctx* c) {
   }
   double* cb = (double*)scratch(8 * n);
   SolverBufs tsb{};
-  tsb.z = (double*)scratch(8 * n);
+  tsb.z32 = (float*)scratch(4 * n);   // multigrid layout (jacobi = 0)
   tsb.p0 = (double*)scratch(8 * n);
   tsb.p1 = (double*)scratch(8 * n);
   tsb.q = (double*)scratch(8 * n);
@@ -738,7 +740,7 @@ hca_status plan_tiles(hca_ctx* c) {
   RepDev* drep = (RepDev*)scratch(sizeof(RepDev) * R);
   Tile* dtiles = (Tile*)scratch(sizeof(Tile) * maxtiles);
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (!cb || !tsb.z || !tsb.p0 || !tsb.p1 || !tsb.q || !tsb.partial || !tsb.ss || !drep || !dtiles ||
+  if (!cb || !tsb.z32 || !tsb.p0 || !tsb.p1 || !tsb.q || !tsb.partial || !tsb.ss || !drep || !dtiles ||
       hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     release();
     if (e0) (void)hipEventDestroy(e0);
@@ -749,8 +751,9 @@ hca_status plan_tiles(hca_ctx* c) {
     if (e != hipSuccess && st == HCA_OK)
       st = fail(c, HCA_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
   };
-  for (void* p : {(void*)cb, (void*)tsb.z, (void*)tsb.p0, (void*)tsb.p1})
+  for (void* p : {(void*)cb, (void*)tsb.p0, (void*)tsb.p1})
     check(hipMemsetAsync(p, 0, 8 * n, c->stream));
+  check(hipMemsetAsync(tsb.z32, 0, 4 * n, c->stream));
   check(hipMemsetAsync(tsb.ss, 0, sizeof(SolveScal) * R, c->stream));
   float tbest = 1e30f;
   int best_depth = g_tile_depth;
@@ -916,9 +919,18 @@ hca_status alloc_all(hca_ctx* c) {
   double** f1[] = {&c->w, &c->P, &c->Vc, &c->phi};
   for (double** p : f1)
     if ((st = big(p, n)) != HCA_OK) return st;
-  double** f3[] = {&c->F, &c->c, &c->b, &c->sb.r, &c->sb.z, &c->sb.p0, &c->sb.p1, &c->sb.q};
+  double** f3[] = {&c->F, &c->c, &c->b, &c->sb.r, &c->sb.p0, &c->sb.p1, &c->sb.q};
   for (double** p : f3)
     if ((st = big(p, n3)) != HCA_OK) return st;
+  if (c->use_mg) {
+    for (float** p : {&c->sb.z32, &c->sb.r32}) {
+      hipError_t e = dalloc(p, n3);
+      if (e == hipErrorOutOfMemory) return fail(c, HCA_E_NOMEM, "device memory exhausted");
+      HIPCHK(c, e);
+    }
+  } else if ((st = big(&c->sb.z, n3)) != HCA_OK) {
+    return st;
+  }
   c->K = c->F;
   c->G1 = c->F + n;
   c->G2 = c->F + 2 * n;
@@ -1162,7 +1174,7 @@ hca_status steady_oxygen(hca_ctx* c) {
 
 void free_all(hca_ctx* c) {
   void* bufs[] = {c->L, c->code, c->win, c->w, c->P, c->Vc, c->phi, c->F, c->c, c->b,
-                  c->sb.r, c->sb.z, c->sb.p0, c->sb.p1, c->sb.q, c->sb.dinv, c->sb.partial,
+                  c->sb.r, c->sb.z, (void*)c->sb.z32, (void*)c->sb.r32, c->sb.p0, c->sb.p1, c->sb.q, c->sb.dinv, c->sb.partial,
                   c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->d_step,
                   c->d_reps, c->d_flat, c->d_tiles, c->d_sys, c->d_sflat, c->d_stiles, c->d_cnt,
                   (void*)c->d_fields, c->d_bad, c->d_theta, (void*)c->d_pack, (void*)c->d_gelu, c->before,
