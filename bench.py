@@ -64,6 +64,22 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size), or
+    None if the kernel's sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -394,9 +410,13 @@ def main():
         d = kt[dom]
         mean_s = d["ms"] / d["launches"] * 1e-3
         achieved = d["bytes_per_launch"] / mean_s / 1e9
+        kname = dom.split("<")[0]
+        wname = args.workload
         rec["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                           "traffic": None, "mean_launch_us": mean_s * 1e6,
+                           "traffic": measured_traffic(kname, wname),
+                           "traffic_source": f"profiles/{kname}_{wname}_traffic.json",
+                           "mean_launch_us": mean_s * 1e6,
                            "launches": d["launches"],
                            "bytes_per_launch": d["bytes_per_launch"]}
         if warm_share:
