@@ -273,10 +273,19 @@ void launch_ca_propose(hipStream_t s, const Work& w, const DevParams& p, const l
                        const double* G2, const double* phi, uint8_t* code);
 void launch_ca_resolve(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
                        const double* phi, const uint8_t* code, uint8_t* win);
+// Event and census counts: each flat work item stores kCounterSlots partials
+// (part[item * kCounterSlots + k]); a one-workgroup-per-replicate reduce
+// then writes the replicate's counters.
+constexpr int kCounterSlots = 8;
+enum CounterKind { CNT_CA = 0, CNT_STATS = 1, CNT_SUR = 2 };
+void launch_counters_reduce(hipStream_t s, const Work& w, const unsigned long long* part,
+                            Counters* cnt, int kind);
 void launch_ca_finalize(hipStream_t s, const Work& w, uint8_t* L, double* phi, double* P,
-                        double* Vc, const uint8_t* code, const uint8_t* win, Counters* cnt);
+                        double* Vc, const uint8_t* code, const uint8_t* win,
+                        unsigned long long* part, Counters* cnt);
 void launch_stats(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
-                  const double* const* fields, int nfields, Counters* cnt);
+                  const double* const* fields, int nfields, unsigned long long* part,
+                  Counters* cnt);
 // what: 1 CA events, 0 census and non-finite count, 2 surrogate counts.
 void launch_zero_counters(hipStream_t s, Counters* cnt, int nreps, int what);
 void launch_advance(hipStream_t s, long long* d_step);

@@ -46,7 +46,7 @@ __device__ inline bool neighbour(const RepDev& rp, const VoxelCoord& v, int d, l
 }
 
 // f(rep, replicate, local voxel index) over this workgroup's work items;
-// end_item(rep) after each item (per-replicate counter flushes).
+// end_item(rep, item) after each item (per-item counter partials).
 template <typename F, typename E>
 __device__ inline void for_each_voxel_ca(const Work& w, F f, E end_item) {
   int b0, b1;
@@ -55,13 +55,13 @@ __device__ inline void for_each_voxel_ca(const Work& w, F f, E end_item) {
     const FlatBlk fb = w.flat[it];
     const RepDev rp = w.reps[fb.rep];
     for (long long li = fb.begin + threadIdx.x; li < fb.end; li += kBlock) f(fb.rep, rp, li);
-    end_item(fb.rep);
+    end_item(fb.rep, it);
   }
 }
 
 template <typename F>
 __device__ inline void for_each_voxel_ca(const Work& w, F f) {
-  for_each_voxel_ca(w, f, [](int) {});
+  for_each_voxel_ca(w, f, [](int, int) {});
 }
 
 __device__ inline double kill_probability(double G, double Gref, int b) {
@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(kBlock) k_ca_finalize(Work w, uint8_t* __restr
                                                         double* __restrict__ Vc,
                                                         const uint8_t* __restrict__ code,
                                                         const uint8_t* __restrict__ win,
-                                                        Counters* cnt) {
+                                                        unsigned long long* __restrict__ part) {
   __shared__ unsigned long long lds4[4];
   unsigned long long n_com = 0, n_kill = 0, n_div = 0, n_nosp = 0, n_lost = 0;
   for_each_voxel_ca(w, [&](int, const RepDev& rp, long long li) {
@@ -188,22 +188,12 @@ __global__ void __launch_bounds__(kBlock) k_ca_finalize(Work w, uint8_t* __restr
       P[i] = 0.0;
       Vc[i] = 0.0;
     }
-  }, [&](int rep) {
-    const unsigned long long a = block_sum_u64(n_com, lds4);
-    const unsigned long long b = block_sum_u64(n_kill, lds4);
-    const unsigned long long c = block_sum_u64(n_div, lds4);
-    const unsigned long long d = block_sum_u64(n_nosp, lds4);
-    const unsigned long long e = block_sum_u64(n_lost, lds4);
-    if (threadIdx.x == 0) {
-      Counters* cr = cnt + rep;
-      if (a) atomicAdd(&cr->committed, a);
-      if (b) atomicAdd(&cr->kills, b);
-      if (c) atomicAdd(&cr->divisions, c);
-      if (c) atomicAdd(&cr->total_divisions, c);
-      if (b) atomicAdd(&cr->total_kills, b);
-      if (d) atomicAdd(&cr->nospace, d);
-      if (e) atomicAdd(&cr->lost, e);
-    }
+  }, [&](int, int it) {
+    const unsigned long long v[5] = {block_sum_u64(n_com, lds4), block_sum_u64(n_kill, lds4),
+                                     block_sum_u64(n_div, lds4), block_sum_u64(n_nosp, lds4),
+                                     block_sum_u64(n_lost, lds4)};
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 5; ++k) part[(size_t)it * kCounterSlots + k] = v[k];
     n_com = n_kill = n_div = n_nosp = n_lost = 0;
   });
 }
@@ -212,7 +202,7 @@ __global__ void __launch_bounds__(kBlock) k_ca_finalize(Work w, uint8_t* __restr
 __global__ void __launch_bounds__(kBlock) k_stats(Work w, const uint8_t* __restrict__ L,
                                                   const double* __restrict__ vw,
                                                   const double* const* fields, int nfields,
-                                                  Counters* cnt) {
+                                                  unsigned long long* __restrict__ part) {
   __shared__ unsigned long long lds4[4];
   unsigned long long nc = 0, ns = 0, ne = 0, nv = 0, bad = 0;
   for_each_voxel_ca(w, [&](int, const RepDev& rp, long long li) {
@@ -223,20 +213,12 @@ __global__ void __launch_bounds__(kBlock) k_stats(Work w, const uint8_t* __restr
     ne += l == 0;
     nv += vw[i] != 0.0;
     for (int f = 0; f < nfields; ++f) bad += !isfinite(fields[f][i]);
-  }, [&](int rep) {
-    const unsigned long long a = block_sum_u64(nc, lds4);
-    const unsigned long long b = block_sum_u64(ns, lds4);
-    const unsigned long long c = block_sum_u64(ne, lds4);
-    const unsigned long long d = block_sum_u64(nv, lds4);
-    const unsigned long long e = block_sum_u64(bad, lds4);
-    if (threadIdx.x == 0) {
-      Counters* cr = cnt + rep;
-      if (a) atomicAdd(&cr->n_cancer, a);
-      if (b) atomicAdd(&cr->n_stroma, b);
-      if (c) atomicAdd(&cr->n_empty, c);
-      if (d) atomicAdd(&cr->n_vessel, d);
-      if (e) atomicAdd(&cr->nonfinite, e);
-    }
+  }, [&](int, int it) {
+    const unsigned long long v[5] = {block_sum_u64(nc, lds4), block_sum_u64(ns, lds4),
+                                     block_sum_u64(ne, lds4), block_sum_u64(nv, lds4),
+                                     block_sum_u64(bad, lds4)};
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 5; ++k) part[(size_t)it * kCounterSlots + k] = v[k];
     nc = ns = ne = nv = bad = 0;
   });
 }
@@ -253,6 +235,56 @@ __global__ void k_zero_counters(Counters* cnt, int nreps, int what) {
     c.n_cancer = c.n_stroma = c.n_empty = c.n_vessel = c.nonfinite = 0;
   } else {
     c.sur_voxels = c.sur_fallbacks = 0;
+  }
+}
+
+// One workgroup per replicate: sums the per-item partials of the
+// replicate's flat items in a fixed order into its counters (plain stores, no
+// contended atomics; the cumulative totals are added to).
+template <int KIND>
+__global__ void __launch_bounds__(kBlock) k_counters_reduce(Work w,
+                                                            const unsigned long long* __restrict__ part,
+                                                            Counters* cnt) {
+  __shared__ unsigned long long lds4[4];
+  const int rep = blockIdx.x;
+  const RepDev rp = w.reps[rep];
+  constexpr int K = KIND == CNT_SUR ? 2 : 5;
+  unsigned long long v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0;
+  for (int j = threadIdx.x; j < rp.flat_nb; j += kBlock)
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += part[(size_t)(rp.flat_b0 + j) * kCounterSlots + k];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = block_sum_u64(v[k], lds4);
+  if (threadIdx.x != 0) return;
+  Counters& c = cnt[rep];
+  if (KIND == CNT_CA) {
+    c.committed = v[0];
+    c.kills = v[1];
+    c.divisions = v[2];
+    c.nospace = v[3];
+    c.lost = v[4];
+    c.total_kills += v[1];
+    c.total_divisions += v[2];
+  } else if (KIND == CNT_STATS) {
+    c.n_cancer = v[0];
+    c.n_stroma = v[1];
+    c.n_empty = v[2];
+    c.n_vessel = v[3];
+    c.nonfinite = v[4];
+  } else {
+    c.sur_voxels = v[0];
+    c.sur_fallbacks = v[1];
+  }
+}
+
+void launch_counters_reduce(hipStream_t s, const Work& w, const unsigned long long* part,
+                            Counters* cnt, int kind) {
+  switch (kind) {
+    case CNT_CA: hca_launch(k_counters_reduce<CNT_CA>, dim3(w.nreps), dim3(kBlock), 0, s, w, part, cnt); break;
+    case CNT_STATS: hca_launch(k_counters_reduce<CNT_STATS>, dim3(w.nreps), dim3(kBlock), 0, s, w, part, cnt); break;
+    default: hca_launch(k_counters_reduce<CNT_SUR>, dim3(w.nreps), dim3(kBlock), 0, s, w, part, cnt); break;
   }
 }
 
@@ -286,14 +318,19 @@ void launch_ca_resolve(hipStream_t s, const Work& w, const uint8_t* L, const dou
 }
 
 void launch_ca_finalize(hipStream_t s, const Work& w, uint8_t* L, double* phi, double* P,
-                        double* Vc, const uint8_t* code, const uint8_t* win, Counters* cnt) {
-  hca_launch(k_ca_finalize, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, phi, P, Vc, code, win,
-                     cnt);
+                        double* Vc, const uint8_t* code, const uint8_t* win,
+                        unsigned long long* part, Counters* cnt) {
+  hca_launch(k_ca_finalize, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, phi, P,
+             Vc, code, win, part);
+  launch_counters_reduce(s, w, part, cnt, CNT_CA);
 }
 
 void launch_stats(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
-                  const double* const* fields, int nfields, Counters* cnt) {
-  hca_launch(k_stats, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, vw, fields, nfields, cnt);
+                  const double* const* fields, int nfields, unsigned long long* part,
+                  Counters* cnt) {
+  hca_launch(k_stats, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, vw, fields,
+             nfields, part);
+  launch_counters_reduce(s, w, part, cnt, CNT_STATS);
 }
 
 void launch_zero_counters(hipStream_t s, Counters* cnt, int nreps, int what) {

@@ -304,7 +304,8 @@ __global__ void __launch_bounds__(kBlock) k_mlp_apply(Work w, DevParams p, MlpDe
                                                       const double* __restrict__ G1,
                                                       const double* __restrict__ G2,
                                                       double* __restrict__ P, double* __restrict__ Vc,
-                                                      double* __restrict__ phi, Counters* cnt) {
+                                                      double* __restrict__ phi,
+                                                      unsigned long long* __restrict__ part) {
   __shared__ unsigned long long lds4[4];
   __shared__ int list[kFlatChunk];
   __shared__ int fb_list[kFlatChunk];
@@ -420,8 +421,8 @@ __global__ void __launch_bounds__(kBlock) k_mlp_apply(Work w, DevParams p, MlpDe
     }
     const unsigned long long a = block_sum_u64(n_sur, lds4);
     if (threadIdx.x == 0) {
-      if (a) atomicAdd(&cnt[fb.rep].sur_voxels, a);
-      if (n_fbk) atomicAdd(&cnt[fb.rep].sur_fallbacks, n_fbk);
+      part[(size_t)it * kCounterSlots + 0] = a;
+      part[(size_t)it * kCounterSlots + 1] = n_fbk;
     }
   }
 }
@@ -880,9 +881,11 @@ void launch_mlp_pack(hipStream_t s, const float* theta, bf16x8* packed) {
 
 void launch_mlp_apply(hipStream_t s, const Work& w, const DevParams& p, const MlpDev& net,
                       const uint8_t* L, const double* K, const double* G1, const double* G2,
-                      double* P, double* Vc, double* phi, Counters* cnt) {
+                      double* P, double* Vc, double* phi, unsigned long long* part,
+                      Counters* cnt) {
   hca_launch((k_mlp_apply<true, true>), dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock),
-                     0, s, w, p, net, L, K, G1, G2, P, Vc, phi, cnt);
+                     0, s, w, p, net, L, K, G1, G2, P, Vc, phi, part);
+  launch_counters_reduce(s, w, part, cnt, CNT_SUR);
 }
 
 void launch_mlp_count(hipStream_t s, const Work& w, const uint8_t* L, int* item_cnt) {

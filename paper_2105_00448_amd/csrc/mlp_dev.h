@@ -72,7 +72,8 @@ void launch_mlp_pack(hipStream_t s, const float* theta, bf16x8* packed);
 void launch_mlp_gelu_table(hipStream_t s, float2* tab);
 void launch_mlp_apply(hipStream_t s, const Work& w, const DevParams& p, const MlpDev& net,
                       const uint8_t* L, const double* K, const double* G1, const double* G2,
-                      double* P, double* Vc, double* phi, Counters* cnt);
+                      double* P, double* Vc, double* phi, unsigned long long* part,
+                      Counters* cnt);
 // Training pairs of one coupled step: before the plain ODE phase,
 // save_state keeps (P, Vc, phi); after it, harvest writes one row per
 // occupied voxel, in voxel order, at row item_off[item] + rank in the item.

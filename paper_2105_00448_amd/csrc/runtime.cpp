@@ -126,6 +126,7 @@ struct hca_ctx {
   Work sys3{}, sys1{};
   std::vector<long long> sys_n;
   Counters* d_cnt = nullptr;
+  unsigned long long* d_cpart = nullptr;   // per flat item x kCounterSlots
   const double** d_fields = nullptr;
   unsigned long long* d_bad = nullptr;
   // ODE surrogate (hca_set_surrogate) and training-pair harvest buffers
@@ -481,17 +482,15 @@ hca_status run_phases(hca_ctx* c, unsigned mask) {
   }
   if (mask & HCA_PH_ODE) {
     if (c->sur_on) {
-      launch_zero_counters(s, c->d_cnt, c->nreps, 2);
       ProfScope ps(c, KC_MLP_APPLY, kTagState);
       launch_mlp_apply(s, wk, c->dp, c->net, c->L, c->K, c->G1, c->G2, c->P, c->Vc, c->phi,
-                       c->d_cnt);
+                       c->d_cpart, c->d_cnt);
     } else {
       ProfScope ps(c, KC_ODE, kTagState);
       launch_ode(s, wk, c->dp, c->L, c->K, c->P, c->Vc, c->phi);
     }
   }
   if (mask & HCA_PH_CA) {
-    launch_zero_counters(s, c->d_cnt, c->nreps, 1);
     {
       ProfScope ps(c, KC_CA_PROPOSE, kTagState);
       launch_ca_propose(s, wk, c->dp, c->d_step, c->L, c->w, c->K, c->G1, c->G2, c->phi, c->code);
@@ -502,13 +501,12 @@ hca_status run_phases(hca_ctx* c, unsigned mask) {
     }
     {
       ProfScope ps(c, KC_CA_FINALIZE, kTagState);
-      launch_ca_finalize(s, wk, c->L, c->phi, c->P, c->Vc, c->code, c->win, c->d_cnt);
+      launch_ca_finalize(s, wk, c->L, c->phi, c->P, c->Vc, c->code, c->win, c->d_cpart, c->d_cnt);
     }
   }
   if (mask & HCA_PH_STATS) {
-    launch_zero_counters(s, c->d_cnt, c->nreps, 0);
     ProfScope ps(c, KC_STATS, kTagState);
-    launch_stats(s, wk, c->L, c->w, c->d_fields, 6, c->d_cnt);
+    launch_stats(s, wk, c->L, c->w, c->d_fields, 6, c->d_cpart, c->d_cnt);
   }
   if (mask & HCA_PH_ADVANCE) {
     launch_advance(s, c->d_step);
@@ -948,6 +946,7 @@ hca_status alloc_all(hca_ctx* c) {
   HIPCHK(c, dalloc(&c->g0, (size_t)c->nreps * 2));
   HIPCHK(c, dalloc(&c->d_step, 1));
   HIPCHK(c, dalloc(&c->d_cnt, c->nreps));
+  HIPCHK(c, dalloc(&c->d_cpart, (size_t)c->work.nflat * kCounterSlots));
   HIPCHK(c, hipMemset(c->d_cnt, 0, sizeof(Counters) * c->nreps));
   HIPCHK(c, dalloc(&c->d_fields, 6));
   HIPCHK(c, dalloc(&c->d_bad, 1));
@@ -1176,7 +1175,7 @@ void free_all(hca_ctx* c) {
   void* bufs[] = {c->L, c->code, c->win, c->w, c->P, c->Vc, c->phi, c->F, c->c, c->b,
                   c->sb.r, c->sb.z, (void*)c->sb.z32, (void*)c->sb.r32, c->sb.p0, c->sb.p1, c->sb.q, c->sb.dinv, c->sb.partial,
                   c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->d_step,
-                  c->d_reps, c->d_flat, c->d_tiles, c->d_sys, c->d_sflat, c->d_stiles, c->d_cnt,
+                  c->d_reps, c->d_flat, c->d_tiles, c->d_sys, c->d_sflat, c->d_stiles, c->d_cnt, (void*)c->d_cpart,
                   (void*)c->d_fields, c->d_bad, c->d_theta, (void*)c->d_pack, (void*)c->d_gelu, c->before,
                   c->item_cnt, c->item_off};
   for (void* p : bufs)
@@ -1340,7 +1339,7 @@ hca_status hca_init(hca_ctx** out, const hca_params* p, const hca_replicate* rep
     return bail(HCA_E_DEVICE);
   launch_zero_counters(c->stream, c->d_cnt, n_reps, 1);
   launch_zero_counters(c->stream, c->d_cnt, n_reps, 0);
-  launch_stats(c->stream, c->work, c->L, c->w, c->d_fields, 6, c->d_cnt);
+  launch_stats(c->stream, c->work, c->L, c->w, c->d_fields, 6, c->d_cpart, c->d_cnt);
   if (hipGetLastError() != hipSuccess) return bail(HCA_E_DEVICE);
   if ((st = check_after(c)) != HCA_OK) return bail(st);
   c->last_it[0] = 0;
