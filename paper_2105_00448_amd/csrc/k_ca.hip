@@ -29,12 +29,22 @@ struct VoxelCoord {
 
 __device__ inline VoxelCoord coord_of(long long li, const RepDev& rp) {
   VoxelCoord v;
+  if (rp.n <= 0x7fffffffLL) {   // 32-bit arithmetic when the lattice allows it
+    const int l = (int)li;
+    v.x = l % rp.nx;
+    const int t = l / rp.nx;
+    v.y = t % rp.ny;
+    v.z = t / rp.ny;
+    return v;
+  }
   v.x = (int)(li % rp.nx);
   const long long t = li / rp.nx;
   v.y = (int)(t % rp.ny);
   v.z = (int)(t / rp.ny);
   return v;
 }
+
+
 
 __device__ inline bool neighbour(const RepDev& rp, const VoxelCoord& v, int d, long long& nli) {
   int dx, dy, dz;
@@ -43,6 +53,15 @@ __device__ inline bool neighbour(const RepDev& rp, const VoxelCoord& v, int d, l
   if (x < 0 || y < 0 || z < 0 || x >= rp.nx || y >= rp.ny || z >= rp.nz) return false;
   nli = x + (long long)rp.nx * (y + (long long)rp.ny * z);
   return true;
+}
+
+// Local indices of the 26 Moore neighbours (ascending gid order), -1 outside.
+__device__ inline void moore_neighbours(const RepDev& rp, const VoxelCoord& v, long long (&nb)[26]) {
+#pragma unroll
+  for (int d = 0; d < 26; ++d) {
+    long long j;
+    nb[d] = neighbour(rp, v, d, j) ? j : -1;
+  }
 }
 
 // f(rep, replicate, local voxel index) over this workgroup's work items;
@@ -97,16 +116,25 @@ __global__ void __launch_bounds__(kBlock) k_ca_propose(Work w, DevParams p,
         cd = kCodeKill;
       } else {
         const VoxelCoord v = coord_of(li, rp);
+        long long nb[26];
+        moore_neighbours(rp, v, nb);
+        // all neighbour loads issued before any decision (one memory latency)
+        uint8_t ln[26];
+        double wn[26], kn[26];
+#pragma unroll
+        for (int d = 0; d < 26; ++d) {
+          const long long j = rp.off + (nb[d] < 0 ? li : nb[d]);
+          ln[d] = L[j];
+          wn[d] = vw[j];
+          kn[d] = K[j];
+        }
         double best = -INFINITY;
         cd = kCodeNoSpace;
+#pragma unroll
         for (int d = 0; d < 26; ++d) {
-          long long nli;
-          if (!neighbour(rp, v, d, nli)) continue;
-          const long long j = rp.off + nli;
-          if (L[j] != 0 || vw[j] != 0.0) continue;
-          const double kj = K[j];
-          if (kj > best) {
-            best = kj;
+          if (nb[d] < 0 || ln[d] != 0 || wn[d] != 0.0) continue;
+          if (kn[d] > best) {
+            best = kn[d];
             cd = (uint8_t)d;
           }
         }
@@ -126,13 +154,16 @@ __global__ void __launch_bounds__(kBlock) k_ca_resolve(Work w, const uint8_t* __
     uint8_t wn = kCodeNone;
     if (L[i] == 0 && vw[i] == 0.0) {
       const VoxelCoord v = coord_of(li, rp);
+      long long nb[26];
+      moore_neighbours(rp, v, nb);
+      uint8_t cn[26];
+#pragma unroll
+      for (int d = 0; d < 26; ++d) cn[d] = code[rp.off + (nb[d] < 0 ? li : nb[d])];
       double best = -INFINITY;
+#pragma unroll
       for (int d = 0; d < 26; ++d) {   // ascending parent gid: strict > keeps the lowest
-        long long nli;
-        if (!neighbour(rp, v, d, nli)) continue;
-        const long long j = rp.off + nli;
-        if (code[j] != (uint8_t)moore_opposite(d)) continue;
-        const double ph = phi[j];
+        if (nb[d] < 0 || cn[d] != (uint8_t)moore_opposite(d)) continue;
+        const double ph = phi[rp.off + nb[d]];
         if (ph > best) {
           best = ph;
           wn = (uint8_t)d;
