@@ -64,56 +64,75 @@ __device__ inline TileCoord tile_coord(const Work& w, int ti) {
 constexpr int kPlaneMax = 400;
 
 // Marches the tile over [z0, z1) and calls f(i, deg, u_i, (A u)_i) for every
-// voxel of the tile inside the lattice, where u = U(j) is the operand
-// (possibly formed on the fly) and (A u)_i = (c_i + a deg) u_i - a sum_nb u_j.
-// Each plane of u, with its x/y frame, is formed once into LDS (double
-// buffered), so U is evaluated about once per voxel; outside the lattice the
-// frame holds 0, which adds nothing to the neighbour sum.  Called by the whole
-// workgroup (it synchronises).
-template <typename UF, typename F>
+// voxel of the tile inside the lattice, where u = op.value(op.load(j)) is the
+// operand (possibly formed on the fly from several arrays) and
+// (A u)_i = (c_i + a deg) u_i - a sum_nb u_j.  Each plane of u, with its x/y
+// frame, is formed once into LDS (double buffered); outside the lattice the
+// frame holds 0, which adds nothing to the neighbour sum.  Software
+// pipelined: the global loads of plane z+2 and of c on plane z+1 are issued
+// before plane z is computed, so their latency overlaps the compute and the
+// barrier instead of stalling each plane.  Called by the whole workgroup.
+template <typename OP, typename F>
 __device__ inline void plane_stencil(const TileCoord& tc, const double* __restrict__ c,
-                                     double (*lds)[kPlaneMax], UF U, F f) {
+                                     double (*lds)[kPlaneMax], const OP& op, F f) {
+  using Raw = typename OP::Raw;
   const double a = tc.a;
   const int W = tc.tx + 2;
   const int o = (tc.ly + 1) * W + tc.lx + 1;
   const int nframe = 2 * W + 2 * tc.ty;
   const long long plane = (long long)tc.nx * tc.ny;
-  auto fill = [&](double* buf, int z) {
+  // this thread's frame cell (at most one: nframe <= 256)
+  const int k = threadIdx.x;
+  const bool has_frame = k < nframe;
+  int hx = 0, hy = 0;
+  if (k < W) {
+    hx = k;
+    hy = 0;
+  } else if (k < 2 * W) {
+    hx = k - W;
+    hy = tc.ty + 1;
+  } else if (k < 2 * W + tc.ty) {
+    hx = 0;
+    hy = 1 + k - 2 * W;
+  } else {
+    hx = W - 1;
+    hy = 1 + k - 2 * W - tc.ty;
+  }
+  const int gx = tc.x0 + hx - 1, gy = tc.y0 + hy - 1;
+  const bool fin = has_frame && gx >= 0 && gx < tc.nx && gy >= 0 && gy < tc.ny;
+  const int fo = hy * W + hx;
+  const long long fidx = fin ? gx + (long long)tc.nx * gy : 0;
+  const long long iidx = tc.x + (long long)tc.nx * tc.y;
+  Raw ri = op.zero(), rf = op.zero();
+  auto load_plane = [&](int z) {
     const long long pz = tc.off + plane * z;
-    buf[o] = tc.valid ? U(pz + tc.x + (long long)tc.nx * tc.y) : 0.0;
-    for (int k = threadIdx.x; k < nframe; k += kBlock) {
-      int hx, hy;
-      if (k < W) {
-        hx = k;
-        hy = 0;
-      } else if (k < 2 * W) {
-        hx = k - W;
-        hy = tc.ty + 1;
-      } else if (k < 2 * W + tc.ty) {
-        hx = 0;
-        hy = 1 + k - 2 * W;
-      } else {
-        hx = W - 1;
-        hy = 1 + k - 2 * W - tc.ty;
-      }
-      const int gx = tc.x0 + hx - 1, gy = tc.y0 + hy - 1;
-      const bool in = gx >= 0 && gx < tc.nx && gy >= 0 && gy < tc.ny;
-      buf[hy * W + hx] = in ? U(pz + gx + (long long)tc.nx * gy) : 0.0;
-    }
+    if (tc.valid) ri = op.load(pz + iidx);
+    if (fin) rf = op.load(pz + fidx);
+  };
+  auto store_plane = [&](double* buf) {
+    buf[o] = tc.valid ? op.value(ri) : 0.0;
+    if (has_frame) buf[fo] = fin ? op.value(rf) : 0.0;
   };
   const bool xl = tc.x > 0, xr = tc.x + 1 < tc.nx, yl = tc.y > 0, yr = tc.y + 1 < tc.ny;
   const int deg_xy = (int)xl + (int)xr + (int)yl + (int)yr;
-  long long i = tc.off + tc.x + (long long)tc.nx * (tc.y + (long long)tc.ny * tc.z0);
+  long long i = tc.off + iidx + plane * tc.z0;
   double* cur = lds[0];
   double* nxt = lds[1];
   __syncthreads();   // the previous tile's readers are done with both buffers
-  fill(cur, tc.z0);
-  double um = (tc.valid && tc.z0 > 0) ? U(i - plane) : 0.0;
+  load_plane(tc.z0);
+  const double um0 = (tc.valid && tc.z0 > 0) ? op.value(op.load(i - plane)) : 0.0;
+  double cc = tc.valid ? c[i] : 0.0;
+  store_plane(cur);
+  if (tc.z0 + 1 < tc.nz) load_plane(tc.z0 + 1);
+  double um = um0;
   __syncthreads();
   double uc = cur[o];
   for (int z = tc.z0; z < tc.z1; ++z) {
     const bool zl = z > 0, zr = z + 1 < tc.nz;
-    if (zr) fill(nxt, z + 1);
+    const bool more = z + 1 < tc.z1;   // an iteration follows this one
+    if (zr) store_plane(nxt);          // plane z+1, loaded one iteration ago
+    if (more && z + 2 < tc.nz) load_plane(z + 2);
+    const double cn = (more && tc.valid) ? c[i + plane] : 0.0;
     double s = cur[o - 1];
     s += cur[o + 1];
     s += cur[o - W];
@@ -124,17 +143,54 @@ __device__ inline void plane_stencil(const TileCoord& tc, const double* __restri
     s += up;
     if (tc.valid) {
       const int deg = deg_xy + (int)zl + (int)zr;
-      const double Au = (c[i] + a * deg) * uc - a * s;
+      const double Au = (cc + a * deg) * uc - a * s;
       f(i, deg, uc, Au);
     }
     um = uc;
     uc = up;
+    cc = cn;
     double* t = cur;
     cur = nxt;
     nxt = t;
     i += plane;
   }
 }
+
+// Operands of the stencil: the iterate x (start), and p = z + beta p_old
+// formed on the fly (apply; z FP64 for Jacobi, the multigrid's FP32 result
+// otherwise).
+struct OpX {
+  struct Raw {
+    double x;
+  };
+  const double* __restrict__ x;
+  __device__ inline Raw zero() const { return Raw{0.0}; }
+  __device__ inline Raw load(long long j) const { return Raw{x[j]}; }
+  __device__ inline double value(const Raw& r) const { return r.x; }
+};
+
+template <bool JAC>
+struct OpP {
+  struct Raw {
+    double z, p;
+  };
+  const double* __restrict__ z;
+  const float* __restrict__ z32;
+  const double* __restrict__ pold;
+  double beta;
+  bool first;
+  __device__ inline Raw zero() const { return Raw{0.0, 0.0}; }
+  __device__ inline Raw load(long long j) const {
+    Raw r;
+    if constexpr (JAC)
+      r.z = z[j];
+    else
+      r.z = (double)z32[j];
+    r.p = first ? 0.0 : pold[j];
+    return r;
+  }
+  __device__ inline double value(const Raw& r) const { return first ? r.z : r.z + beta * r.p; }
+};
 
 // r = b - A x; Jacobi mode also Dinv = 1/diag(A), z = Dinv r.
 __global__ void __launch_bounds__(kBlock) k_cg_start(Work w, const double* __restrict__ c,
@@ -150,7 +206,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_start(Work w, const double* __res
     const double a = tc.a;
     double bb = 0.0, rr = 0.0, rz = 0.0;
     {
-      plane_stencil(tc, c, lds, [&](long long j) { return x[j]; },
+      plane_stencil(tc, c, lds, OpX{x},
                      [&](long long i, int deg, double, double Ax) {
                        const double bi = b[i];
                        const double r = bi - Ax;
@@ -193,15 +249,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, const double* __res
     const bool first = ssr->first != 0;
     double pq = 0.0;
     {
-      // z: FP64 (Jacobi) or the multigrid's FP32 result, widened exactly
-      auto Z = [&](long long j) {
-        if constexpr (JAC)
-          return z[j];
-        else
-          return (double)sb.z32[j];
-      };
-      auto U = [&](long long j) { return first ? Z(j) : Z(j) + beta * pold[j]; };
-      plane_stencil(tc, c, lds, U, [&](long long i, int, double pc, double Ap) {
+      const OpP<JAC> op{z, sb.z32, pold, beta, first};
+      plane_stencil(tc, c, lds, op, [&](long long i, int, double pc, double Ap) {
         pnew[i] = pc;
         q[i] = Ap;
         pq += pc * Ap;
