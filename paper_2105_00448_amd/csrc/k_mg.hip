@@ -99,15 +99,20 @@ __device__ inline float nb_sum_xy(const Geo<UNI>& G, int x, int y, int z, long l
 // LDS plane of one tile with a one-cell frame: (tx + 2) (256/tx + 2) values.
 constexpr int kPlaneMaxF = 400;
 
-// Marches a tile over [t.z0, t.z1) and calls f(z, i, v_i, sum_J g_IJ v_J)
-// for the tile's cells inside the level, v = V(x, y, z, index) possibly
-// formed on the fly.  Each plane of V with its x/y frame is formed once into
-// LDS (double buffered), so V is evaluated about once per cell instead of at
+// Marches a tile over [t.z0, t.z1) and calls f(z, i, v_i, sum_J g_IJ v_J, ctr)
+// for the tile's cells inside the level, v = op.value(op.load(x, y, z, j))
+// possibly formed on the fly and ctr = op.ctr(i) the cell's own further
+// operands (D^-1, r).  Each plane of v with its x/y frame is formed once into
+// LDS (double buffered), so v is evaluated about once per cell instead of at
 // every neighbour; the neighbour terms are added in the order -x, +x, -y, +y,
-// -z, +z.  Called by the whole workgroup (it synchronises).
-template <bool UNI, typename VF, typename F>
+// -z, +z.  Software pipelined: the loads of plane z+2 and the centre
+// operands of plane z+1 are issued before plane z is computed.  Called by the
+// whole workgroup (it synchronises).
+template <bool UNI, typename OP, typename F>
 __device__ inline void mg_plane(const Geo<UNI>& G, const Tile& t, int tx, long long base,
-                                float (*lds)[kPlaneMaxF], VF V, F f) {
+                                float (*lds)[kPlaneMaxF], const OP& op, F f) {
+  using Raw = typename OP::Raw;
+  using Ctr = typename OP::Ctr;
   const int ty = kBlock / tx;
   const int lx = (int)(threadIdx.x % tx), ly = (int)(threadIdx.x / tx);
   const int x = t.x0 + lx, y = t.y0 + ly;
@@ -116,41 +121,56 @@ __device__ inline void mg_plane(const Geo<UNI>& G, const Tile& t, int tx, long l
   const int o = (ly + 1) * W + lx + 1;
   const int nframe = 2 * W + 2 * ty;
   const long long plane = (long long)G.nx * G.ny;
-  auto fill = [&](float* buf, int z) {
+  // this thread's frame cell (at most one: nframe <= 256)
+  const int k = threadIdx.x;
+  const bool has_frame = k < nframe;
+  int hx = 0, hy = 0;
+  if (k < W) {
+    hx = k;
+    hy = 0;
+  } else if (k < 2 * W) {
+    hx = k - W;
+    hy = ty + 1;
+  } else if (k < 2 * W + ty) {
+    hx = 0;
+    hy = 1 + k - 2 * W;
+  } else {
+    hx = W - 1;
+    hy = 1 + k - 2 * W - ty;
+  }
+  const int gx = t.x0 + hx - 1, gy = t.y0 + hy - 1;
+  const bool fin = has_frame && gx >= 0 && gx < G.nx && gy >= 0 && gy < G.ny;
+  const int fo = hy * W + hx;
+  const long long fidx = fin ? gx + (long long)G.nx * gy : 0;
+  const long long iidx = x + (long long)G.nx * y;
+  Raw ri = op.zero(), rf = op.zero();
+  auto load_plane = [&](int z) {
     const long long pz = base + plane * z;
-    buf[o] = valid ? V(x, y, z, pz + x + (long long)G.nx * y) : 0.f;
-    for (int k = threadIdx.x; k < nframe; k += kBlock) {
-      int hx, hy;
-      if (k < W) {
-        hx = k;
-        hy = 0;
-      } else if (k < 2 * W) {
-        hx = k - W;
-        hy = ty + 1;
-      } else if (k < 2 * W + ty) {
-        hx = 0;
-        hy = 1 + k - 2 * W;
-      } else {
-        hx = W - 1;
-        hy = 1 + k - 2 * W - ty;
-      }
-      const int gx = t.x0 + hx - 1, gy = t.y0 + hy - 1;
-      const bool in = gx >= 0 && gx < G.nx && gy >= 0 && gy < G.ny;
-      buf[hy * W + hx] = in ? V(gx, gy, z, pz + gx + (long long)G.nx * gy) : 0.f;
-    }
+    if (valid) ri = op.load(x, y, z, pz + iidx);
+    if (fin) rf = op.load(gx, gy, z, pz + fidx);
+  };
+  auto store_plane = [&](float* buf) {
+    buf[o] = valid ? op.value(ri) : 0.f;
+    if (has_frame) buf[fo] = fin ? op.value(rf) : 0.f;
   };
   const int z0 = t.z0, z1 = t.z1;
-  long long i = base + x + (long long)G.nx * (y + (long long)G.ny * z0);
+  long long i = base + iidx + plane * z0;
   float* cur = lds[0];
   float* nxt = lds[1];
   __syncthreads();   // the previous tile's readers are done with both buffers
-  fill(cur, z0);
-  float vm = (valid && z0 > 0) ? V(x, y, z0 - 1, i - plane) : 0.f;
+  load_plane(z0);
+  float vm = (valid && z0 > 0) ? op.value(op.load(x, y, z0 - 1, i - plane)) : 0.f;
+  Ctr cc = valid ? op.ctr(i) : op.ctr_zero();
+  store_plane(cur);
+  if (z0 + 1 < G.nz) load_plane(z0 + 1);
   __syncthreads();
   float vc = cur[o];
   for (int z = z0; z < z1; ++z) {
     const bool zr = z + 1 < G.nz;
-    if (zr) fill(nxt, z + 1);
+    const bool more = z + 1 < z1;
+    if (zr) store_plane(nxt);
+    if (more && z + 2 < G.nz) load_plane(z + 2);
+    const Ctr cn = (more && valid) ? op.ctr(i + plane) : op.ctr_zero();
     float s = 0.f;
     if (valid) {
       if (x > 0) s += G.gx(x - 1, y, z) * cur[o - 1];
@@ -163,16 +183,24 @@ __device__ inline void mg_plane(const Geo<UNI>& G, const Tile& t, int tx, long l
     if (valid) {
       if (z > 0) s += G.gz(x, y, z - 1) * vm;
       if (zr) s += G.gz(x, y, z) * vp;
-      f(z, i, vc, s);
+      f(z, i, vc, s, cc);
     }
     vm = vc;
     vc = vp;
+    cc = cn;
     float* tmp = cur;
     cur = nxt;
     nxt = tmp;
     i += plane;
   }
 }
+
+// Centre operands of the smoothers: D^-1 and r of the cell.
+template <typename RT>
+struct CtrDR {
+  float dinv;
+  RT r;
+};
 
 struct TileXY {
   int rep, x, y, z0, z1;
@@ -249,24 +277,41 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarsen(MgLevel Lf, MgLevel Lc,
 
 // ---- V-cycle, global levels ------------------------------------------------
 
+// First sweep from zero, formed on the fly at the neighbours: u1 = w D^-1 r.
+template <typename RT>
+struct OpPre {
+  struct Raw {
+    float dinv;
+    RT r;
+  };
+  using Ctr = CtrDR<RT>;
+  const float* __restrict__ dinv;
+  const RT* __restrict__ r;
+  float omega;
+  __device__ inline Raw zero() const { return Raw{0.f, (RT)0}; }
+  __device__ inline Raw load(int, int, int, long long j) const { return Raw{dinv[j], r[j]}; }
+  __device__ inline float value(const Raw& v) const { return omega * v.dinv * (float)v.r; }
+  __device__ inline Ctr ctr_zero() const { return Ctr{0.f, (RT)0}; }
+  __device__ inline Ctr ctr(long long i) const { return Ctr{dinv[i], r[i]}; }
+};
+
 template <bool L0, typename RT>
 __global__ void __launch_bounds__(kBlock) k_mg_pre(MgLevel Lk, float omega,
                                                    const RT* __restrict__ r, const SolveScal* ss) {
   __shared__ float lds[2][kPlaneMaxF];
-  const float* __restrict__ dinv = Lk.dinv;
   float* __restrict__ u = Lk.u;
   FOR_MY_TILES(Lk.ntiles) {
     const Tile t = Lk.tiles[ti];
     if (ss[t.rep].done) continue;
     const MgRep m = Lk.reps[t.rep];
     const Geo<L0> G = geo_of<L0>(m);
-    auto U1 = [&](int, int, int, long long j) { return omega * dinv[j] * (float)r[j]; };
-    mg_plane(G, t, m.tx, m.off, lds, U1, [&](int, long long i, float u1, float s) {
-      u[i] = (1.f - omega) * u1 + omega * dinv[i] * ((float)r[i] + s);
-    });
+    const OpPre<RT> op{Lk.dinv, r, omega};
+    mg_plane(G, t, m.tx, m.off, lds, op,
+             [&](int, long long i, float u1, float s, const CtrDR<RT>& c) {
+               u[i] = (1.f - omega) * u1 + omega * c.dinv * ((float)c.r + s);
+             });
   }
 }
-
 // residual of level k at (x, y, z): r - A u = r - u/Dinv + sum g u_J
 template <bool UNI, typename RT>
 __device__ inline float level_residual(const Geo<UNI>& G, long long off, int x, int y, int z,
@@ -326,33 +371,65 @@ __device__ inline void lin_axis(int i, int nf, int nc, int& I, int& J, float& wJ
   }
 }
 
-// (P e) at fine cell (x, y, z): tensor product of the three axis weights,
-// summed in a fixed order.
-__device__ inline float prolong_lin(const float* __restrict__ e, const MgRep& mc, int nfx, int nfy,
-                                   int nfz, int x, int y, int z) {
-  int Ix, Jx, Iy, Jy, Iz, Jz;
-  float wx, wy, wz;
-  lin_axis(x, nfx, mc.nx, Ix, Jx, wx);
-  lin_axis(y, nfy, mc.ny, Iy, Jy, wy);
-  lin_axis(z, nfz, mc.nz, Iz, Jz, wz);
-  const long long sy = mc.nx, sz = (long long)mc.nx * mc.ny;
-  const float* b = e + mc.off;
-  auto row = [&](long long zy) {   // x-interpolated value on one coarse row
-    return (1.f - wx) * b[zy + Ix] + wx * b[zy + Jx];
+
+// u3 = u2 + P e at the neighbours: the eight coarse values and the axis
+// weights are loaded ahead, combined when the plane is formed.
+template <typename RT>
+struct OpPost1 {
+  struct Raw {
+    float u;
+    float e[8];
+    float wx, wy, wz;
   };
-  auto plane = [&](long long zz) {
-    return (1.f - wy) * row(zz + Iy * sy) + wy * row(zz + Jy * sy);
-  };
-  return (1.f - wz) * plane(Iz * sz) + wz * plane(Jz * sz);
-}
+  using Ctr = CtrDR<RT>;
+  const float* __restrict__ u;
+  const float* __restrict__ e;
+  const float* __restrict__ dinv;
+  const RT* __restrict__ r;
+  MgRep mc;
+  int nfx, nfy, nfz;
+  __device__ inline Raw zero() const {
+    Raw v{};
+    return v;
+  }
+  __device__ inline Raw load(int x, int y, int z, long long j) const {
+    int Ix, Jx, Iy, Jy, Iz, Jz;
+    Raw v;
+    lin_axis(x, nfx, mc.nx, Ix, Jx, v.wx);
+    lin_axis(y, nfy, mc.ny, Iy, Jy, v.wy);
+    lin_axis(z, nfz, mc.nz, Iz, Jz, v.wz);
+    const long long sy = mc.nx, sz = (long long)mc.nx * mc.ny;
+    const float* b = e + mc.off;
+    v.u = u[j];
+    v.e[0] = b[Iz * sz + Iy * sy + Ix];
+    v.e[1] = b[Iz * sz + Iy * sy + Jx];
+    v.e[2] = b[Iz * sz + Jy * sy + Ix];
+    v.e[3] = b[Iz * sz + Jy * sy + Jx];
+    v.e[4] = b[Jz * sz + Iy * sy + Ix];
+    v.e[5] = b[Jz * sz + Iy * sy + Jx];
+    v.e[6] = b[Jz * sz + Jy * sy + Ix];
+    v.e[7] = b[Jz * sz + Jy * sy + Jx];
+    return v;
+  }
+  // x first along each coarse row, then y, then z (a fixed order)
+  __device__ inline float value(const Raw& v) const {
+    const float wx = v.wx, wy = v.wy, wz = v.wz;
+    const float r00 = (1.f - wx) * v.e[0] + wx * v.e[1];
+    const float r01 = (1.f - wx) * v.e[2] + wx * v.e[3];
+    const float r10 = (1.f - wx) * v.e[4] + wx * v.e[5];
+    const float r11 = (1.f - wx) * v.e[6] + wx * v.e[7];
+    const float p0 = (1.f - wy) * r00 + wy * r01;
+    const float p1 = (1.f - wy) * r10 + wy * r11;
+    return v.u + ((1.f - wz) * p0 + wz * p1);
+  }
+  __device__ inline Ctr ctr_zero() const { return Ctr{0.f, (RT)0}; }
+  __device__ inline Ctr ctr(long long i) const { return Ctr{dinv[i], r[i]}; }
+};
 
 template <bool L0, typename RT>
 __global__ void __launch_bounds__(kBlock) k_mg_post1(MgLevel Lk, MgLevel Lc, float omega,
                                                      const RT* __restrict__ r, const SolveScal* ss) {
   __shared__ float lds[2][kPlaneMaxF];
-  const float* __restrict__ dinv = Lk.dinv;
-  const float* __restrict__ u = Lk.u;
-  const float* __restrict__ e = Lc.u;
   float* __restrict__ out = Lk.ualt;
   FOR_MY_TILES(Lk.ntiles) {
     const Tile t = Lk.tiles[ti];
@@ -360,22 +437,35 @@ __global__ void __launch_bounds__(kBlock) k_mg_post1(MgLevel Lk, MgLevel Lc, flo
     const MgRep m = Lk.reps[t.rep];
     const MgRep mc = Lc.reps[t.rep];
     const Geo<L0> G = geo_of<L0>(m);
-    auto U3 = [&](int x, int y, int z, long long j) {
-      return u[j] + prolong_lin(e, mc, m.nx, m.ny, m.nz, x, y, z);
-    };
-    mg_plane(G, t, m.tx, m.off, lds, U3, [&](int, long long i, float u3, float s) {
-      out[i] = (1.f - omega) * u3 + omega * dinv[i] * ((float)r[i] + s);
-    });
+    const OpPost1<RT> op{Lk.u, Lc.u, Lk.dinv, r, mc, m.nx, m.ny, m.nz};
+    mg_plane(G, t, m.tx, m.off, lds, op,
+             [&](int, long long i, float u3, float s, const CtrDR<RT>& c) {
+               out[i] = (1.f - omega) * u3 + omega * c.dinv * ((float)c.r + s);
+             });
   }
 }
+// Plain operand v = ualt (second post-sweep).
+template <typename RT>
+struct OpU {
+  struct Raw {
+    float u;
+  };
+  using Ctr = CtrDR<RT>;
+  const float* __restrict__ u;
+  const float* __restrict__ dinv;
+  const RT* __restrict__ r;
+  __device__ inline Raw zero() const { return Raw{0.f}; }
+  __device__ inline Raw load(int, int, int, long long j) const { return Raw{u[j]}; }
+  __device__ inline float value(const Raw& v) const { return v.u; }
+  __device__ inline Ctr ctr_zero() const { return Ctr{0.f, (RT)0}; }
+  __device__ inline Ctr ctr(long long i) const { return Ctr{dinv[i], r[i]}; }
+};
 
 template <bool L0, typename RT>
 __global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float omega,
                                                      const RT* __restrict__ r, SolverBufs sb) {
   __shared__ double lds4[4];
   __shared__ float lds[2][kPlaneMaxF];
-  const float* __restrict__ dinv = Lk.dinv;
-  const float* __restrict__ u = Lk.ualt;
   FOR_MY_TILES(Lk.ntiles) {
     const Tile t = Lk.tiles[ti];
     if (sb.ss[t.rep].done) continue;
@@ -383,16 +473,17 @@ __global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float omega,
     const Geo<L0> G = geo_of<L0>(m);
     double rz = 0.0;
     {
-      auto U4 = [&](int, int, int, long long j) { return u[j]; };
-      mg_plane(G, t, m.tx, m.off, lds, U4, [&](int, long long i, float u4, float s) {
-        const float u5 = (1.f - omega) * u4 + omega * dinv[i] * ((float)r[i] + s);
-        if (L0) {
-          sb.z32[i] = u5;
-          rz += (double)r[i] * (double)u5;
-        } else {
-          Lk.u[i] = u5;
-        }
-      });
+      const OpU<RT> op{Lk.ualt, Lk.dinv, r};
+      mg_plane(G, t, m.tx, m.off, lds, op,
+               [&](int, long long i, float u4, float s, const CtrDR<RT>& c) {
+                 const float u5 = (1.f - omega) * u4 + omega * c.dinv * ((float)c.r + s);
+                 if (L0) {
+                   sb.z32[i] = u5;
+                   rz += (double)c.r * (double)u5;
+                 } else {
+                   Lk.u[i] = u5;
+                 }
+               });
     }
     if (L0) {
       // level 0: partial r.z of this tile (finished by the RED_RZ reduce)
