@@ -108,9 +108,9 @@ constexpr int kPlaneMaxF = 400;
 // -z, +z.  Software pipelined: the loads of plane z+2 and the centre
 // operands of plane z+1 are issued before plane z is computed.  Called by the
 // whole workgroup (it synchronises).
-template <bool UNI, typename OP, typename F>
+template <bool UNI, typename OP, typename F, typename E>
 __device__ inline void mg_plane(const Geo<UNI>& G, const Tile& t, int tx, long long base,
-                                float (*lds)[kPlaneMaxF], const OP& op, F f) {
+                                float (*lds)[kPlaneMaxF], const OP& op, F f, E epilogue) {
   using Raw = typename OP::Raw;
   using Ctr = typename OP::Ctr;
   const int ty = kBlock / tx;
@@ -185,6 +185,7 @@ __device__ inline void mg_plane(const Geo<UNI>& G, const Tile& t, int tx, long l
       if (zr) s += G.gz(x, y, z) * vp;
       f(z, i, vc, s, cc);
     }
+    epilogue(z);   // every thread, every plane
     vm = vc;
     vc = vp;
     cc = cn;
@@ -193,6 +194,12 @@ __device__ inline void mg_plane(const Geo<UNI>& G, const Tile& t, int tx, long l
     nxt = tmp;
     i += plane;
   }
+}
+
+template <bool UNI, typename OP, typename F>
+__device__ inline void mg_plane(const Geo<UNI>& G, const Tile& t, int tx, long long base,
+                                float (*lds)[kPlaneMaxF], const OP& op, F f) {
+  mg_plane(G, t, tx, base, lds, op, f, [](int) {});
 }
 
 // Centre operands of the smoothers: D^-1 and r of the cell.
@@ -312,47 +319,62 @@ __global__ void __launch_bounds__(kBlock) k_mg_pre(MgLevel Lk, float omega,
              });
   }
 }
-// residual of level k at (x, y, z): r - A u = r - u/Dinv + sum g u_J
-template <bool UNI, typename RT>
-__device__ inline float level_residual(const Geo<UNI>& G, long long off, int x, int y, int z,
-                                       const RT* __restrict__ r, const float* __restrict__ dinv,
-                                       const float* __restrict__ u) {
-  const long long plane = (long long)G.nx * G.ny;
-  const long long i = off + x + (long long)G.nx * (y + (long long)G.ny * z);
-  auto V = [&](int, int, int, long long j) { return u[j]; };
-  float s = nb_sum_xy(G, x, y, z, i, V);
-  if (z > 0) s += G.gz(x, y, z - 1) * u[i - plane];
-  if (z + 1 < G.nz) s += G.gz(x, y, z) * u[i + plane];
-  return (float)r[i] - u[i] / dinv[i] + s;
-}
+// Plain operand v = u with the cell's (D^-1, r) (second post-sweep, and the
+// residual of the restriction).
+template <typename RT>
+struct OpU {
+  struct Raw {
+    float u;
+  };
+  using Ctr = CtrDR<RT>;
+  const float* __restrict__ u;
+  const float* __restrict__ dinv;
+  const RT* __restrict__ r;
+  __device__ inline Raw zero() const { return Raw{0.f}; }
+  __device__ inline Raw load(int, int, int, long long j) const { return Raw{u[j]}; }
+  __device__ inline float value(const Raw& v) const { return v.u; }
+  __device__ inline Ctr ctr_zero() const { return Ctr{0.f, (RT)0}; }
+  __device__ inline Ctr ctr(long long i) const { return Ctr{dinv[i], r[i]}; }
+};
 
+// Restriction r_{k+1}(I) = sum over the children of (r - A u), marched over
+// the fine level's tiles: each cell's residual from the LDS plane of u, the
+// 2 x 2 children of a coarse cell summed across lanes (tiles are 16 or 32
+// columns wide, so a cell's x-neighbour is lane ^ 1 and its y-neighbour
+// lane ^ tx, both in the same wavefront), the two child planes in a register.
+// Tile origins are even in x, y and z.
 template <bool L0, typename RT>
 __global__ void __launch_bounds__(kBlock) k_mg_restrict(MgLevel Lf, MgLevel Lc,
                                                         const RT* __restrict__ r,
                                                         const SolveScal* ss) {
-  FOR_MY_TILES(Lc.nrtiles) {
-    const TileXY t = tile_xy(Lc.rtiles, Lc.reps, ti);
-    if (ss[t.rep].done || !t.valid) continue;
-    const MgRep mc = Lc.reps[t.rep];
+  __shared__ float lds[2][kPlaneMaxF];
+  FOR_MY_TILES(Lf.ntiles) {
+    const Tile t = Lf.tiles[ti];
+    if (ss[t.rep].done) continue;
     const MgRep mf = Lf.reps[t.rep];
+    const MgRep mc = Lc.reps[t.rep];
     const Geo<L0> G = geo_of<L0>(mf);
-    for (int Z = t.z0; Z < t.z1; ++Z) {
-      float s = 0.f;
-      for (int dz = 0; dz < 2; ++dz) {
-        const int z = 2 * Z + dz;
-        if (z >= mf.nz) break;
-        for (int dy = 0; dy < 2; ++dy) {
-          const int y = 2 * t.y + dy;
-          if (y >= mf.ny) break;
-          for (int dx = 0; dx < 2; ++dx) {
-            const int x = 2 * t.x + dx;
-            if (x >= mf.nx) break;
-            s += level_residual(G, mf.off, x, y, z, r, Lf.dinv, Lf.u);
-          }
-        }
-      }
-      Lc.r[mc.off + t.x + (long long)mc.nx * (t.y + (long long)mc.ny * Z)] = s;
-    }
+    const int tx = mf.tx;
+    const int lx = (int)(threadIdx.x % tx), ly = (int)(threadIdx.x / tx);
+    const int x = t.x0 + lx, y = t.y0 + ly;
+    const bool lead = ((lx | ly) & 1) == 0 && x < mf.nx && y < mf.ny;
+    float res = 0.f, acc = 0.f;
+    const OpU<RT> op{Lf.u, Lf.dinv, r};
+    mg_plane(G, t, tx, mf.off, lds, op,
+             [&](int, long long, float uc, float s, const CtrDR<RT>& c) {
+               res = (float)c.r - uc / c.dinv + s;
+             },
+             [&](int z) {
+               float q = res + __shfl_xor(res, 1, 64);
+               q = q + __shfl_xor(q, tx, 64);
+               acc += q;
+               res = 0.f;
+               if ((z & 1) || z + 1 == mf.nz) {
+                 if (lead)
+                   Lc.r[mc.off + (x >> 1) + (long long)mc.nx * ((y >> 1) + (long long)mc.ny * (z >> 1))] = acc;
+                 acc = 0.f;
+               }
+             });
   }
 }
 
@@ -444,23 +466,6 @@ __global__ void __launch_bounds__(kBlock) k_mg_post1(MgLevel Lk, MgLevel Lc, flo
              });
   }
 }
-// Plain operand v = ualt (second post-sweep).
-template <typename RT>
-struct OpU {
-  struct Raw {
-    float u;
-  };
-  using Ctr = CtrDR<RT>;
-  const float* __restrict__ u;
-  const float* __restrict__ dinv;
-  const RT* __restrict__ r;
-  __device__ inline Raw zero() const { return Raw{0.f}; }
-  __device__ inline Raw load(int, int, int, long long j) const { return Raw{u[j]}; }
-  __device__ inline float value(const Raw& v) const { return v.u; }
-  __device__ inline Ctr ctr_zero() const { return Ctr{0.f, (RT)0}; }
-  __device__ inline Ctr ctr(long long i) const { return Ctr{dinv[i], r[i]}; }
-};
-
 template <bool L0, typename RT>
 __global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float omega,
                                                      const RT* __restrict__ r, SolverBufs sb) {
@@ -722,7 +727,7 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
                        (const float*)sb.r32, ss);
     H(MG_PRE0, 0);
     H(MG_RESTRICT0, 1);
-    hca_launch((k_mg_restrict<true, float>), dim3(grid_tiles(C.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
+    hca_launch((k_mg_restrict<true, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
                        (const float*)sb.r32, ss);
     H(MG_RESTRICT0, 0);
   }
@@ -734,7 +739,7 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
       if (!L.ntiles) continue;
       hca_launch((k_mg_pre<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
                          (const float*)L.r, ss);
-      hca_launch((k_mg_restrict<false, float>), dim3(grid_tiles(C.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
+      hca_launch((k_mg_restrict<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
                          (const float*)L.r, ss);
     }
     H(MG_DOWN, 0);

@@ -349,10 +349,9 @@ DevParams make_dev_params(const hca_params& p) {
 }
 
 // Tile width (tiles are tx x 256/tx columns): 32 x 8 unless the lattice is
-// at most 16 wide.  (HCA_TILE_WIDE=1 restores 64 x 4 above 32.)
-int g_tile_wide = 0;
+// at most 16 wide.  The restriction kernel relies on tx in {16, 32} (a cell's
+// y-neighbour in the same wavefront) and on even tile origins.
 int pick_tx(int nx) {
-  if (g_tile_wide && nx > 32) return 64;
   if (nx > 16) return 32;
   return 16;
 }
@@ -616,6 +615,12 @@ hca_status validate_params(const hca_params* p, std::string& msg) {
 
 // z-extent of a column tile: about `target` tiles per lattice (enough to fill
 // the chip for a lone lattice), at most 16 planes per tile.
+// Tile depth tz made even (at least 2) unless one chunk covers the lattice.
+int even_depth(int tz, int nz) {
+  if (tz >= nz) return nz;
+  return std::max(2, tz & ~1);
+}
+
 int pick_tz(int nx, int ny, int nz, int tx, double target) {
   const int ty = kBlock / tx;
   const double nxy = (double)((nx + tx - 1) / tx) * (double)((ny + ty - 1) / ty);
@@ -688,21 +693,19 @@ RepDev lattice_entry(const RepHost& R, long long off, int idx, std::vector<FlatB
 
 // Stencil tile shape of every lattice: tx from nx (pick_tx), g_tile_depth
 // planes deep; with params.autotune, the depth (2 ... 32 planes) and the width
-// policy (pick_tx, 64 x 4 on wide lattices, or 16 x 16) are instead the
-// fastest of 15 candidates, timed on the CG apply kernel (the dominant
+// policy (pick_tx, or 16 x 16) are instead the fastest of 10 candidates, timed on the CG apply kernel (the dominant
 // stencil) over the whole batch at once on scratch arrays of the batch's
 // shape (one warm-up launch, then the best of three), so the choice accounts
 // for the parallelism the batch already has.  Tiles fix the order of the
 // dot-product partial sums, so a tuned context agrees with an untuned one to
 // rounding, not bit for bit.
 hca_status plan_tiles(hca_ctx* c) {
-  // width policy 0: pick_tx; 1: 64 x 4 where nx > 32; 2: 16 x 16
+  // width policy 0: pick_tx; 1: 16 x 16 everywhere.  Depths are even (or the
+  // whole lattice), as the restriction needs even tile origins.
   auto apply_plan = [&](int depth, int policy) {
     for (RepHost& R : c->reps) {
-      R.tx = pick_tx(R.nx);
-      if (policy == 1 && R.nx > 32) R.tx = 64;
-      if (policy == 2) R.tx = 16;
-      R.tz = depth > 0 ? std::min(depth, R.nz) : pick_tz(R.nx, R.ny, R.nz, R.tx, g_tile_target);
+      R.tx = policy == 1 ? 16 : pick_tx(R.nx);
+      R.tz = even_depth(depth > 0 ? depth : pick_tz(R.nx, R.ny, R.nz, R.tx, g_tile_target), R.nz);
     }
   };
   apply_plan(g_tile_depth, 0);
@@ -756,7 +759,7 @@ hca_status plan_tiles(hca_ctx* c) {
   float tbest = 1e30f;
   int best_depth = g_tile_depth;
   int best_policy = 0;
-  for (int policy = 0; policy < 3 && st == HCA_OK; ++policy)
+  for (int policy = 0; policy < 2 && st == HCA_OK; ++policy)
     for (int depth : {2, 4, 8, 16, 32}) {
       apply_plan(depth, policy);
       std::vector<RepDev> rd;
@@ -824,7 +827,6 @@ hca_status build_tables(hca_ctx* c, const hca_replicate* in) {
   }
   if (const char* e = getenv("HCA_XCD_REMAP")) g_xcd_remap = atoi(e) != 0;
   if (const char* e = getenv("HCA_TILE_REMAP")) g_tile_remap = atoi(e) != 0;
-  if (const char* e = getenv("HCA_TILE_WIDE")) g_tile_wide = atoi(e) != 0;
   if (const char* e = getenv("HCA_TILE_DEPTH")) g_tile_depth = std::max(0, atoi(e));
   if (const char* e = getenv("HCA_MG_TILE_TARGET")) {
     const double v = atof(e);
@@ -1046,7 +1048,7 @@ hca_status build_mg(hca_ctx* c) {
           m.tx = pick_tx(m.nx);
           m.off = off;
           off += (long long)m.nx * m.ny * m.nz;
-          const int tz = pick_tz(m.nx, m.ny, m.nz, m.tx, g_mg_tile_target);
+          const int tz = even_depth(pick_tz(m.nx, m.ny, m.nz, m.tx, g_mg_tile_target), m.nz);
           if (m.active) {
             m.tile_b0 = (int)tiles.size();
             add_tiles(tiles, s, m.nx, m.ny, m.nz, m.tx, tz);

@@ -274,6 +274,23 @@ def test_autotuned_tiles_agree_with_heuristic_tiles(case32):
             assert relerr(a.field(n), b.field(n)) <= 1e-12, n
 
 
+@pytest.mark.parametrize("shape", [(32, 32, 32), (23, 17, 9), (40, 33, 1)], ids=str)
+def test_multigrid_keeps_iterations_low(shape):
+    """The V-cycle is only a preconditioner (parity cannot see a weak one), so
+    its quality is pinned by iteration counts: at rel. residual 1e-10 every
+    field converges in at most 14 flexible-CG iterations per step, on even,
+    odd (ragged aggregates at every level) and 2-D lattices."""
+    print(f"\n[mg iterations] {shape}", flush=True)
+    tis = synth.make_tissue(shape, 6, seed=3)
+    sched = synth.bolus_schedule([0])
+    with hca.Simulation([(tis.cell, tis.w, tis.seed, (sched.times, sched.amts))],
+                        hca.default_params()) as sim:
+        for _ in range(3):
+            sim.step(1)
+            it = sim.stats()["cg_iters"]
+            assert max(it) <= 14, it
+
+
 def test_error_paths_on_device(case32):
     tis, sched, _ = case32
     with make_sim([(tis, sched)], cg_rtol=1e-10, init_rtol=1e-10) as sim:
