@@ -91,9 +91,11 @@ typedef struct hca_params {
   int32_t precond;         /* 0 = Jacobi, 1 = geometric multigrid V-cycle       */
   double cg_rtol;          /* stop when ||r||_2 <= cg_rtol ||b||_2              */
   int32_t cg_maxit;        /* per solve                                          */
-  int32_t mg_smooth;       /* Jacobi sweeps before and after the coarse grid     */
-  int32_t mg_coarse_max;   /* levels with at most this many voxels are solved
-                              in one workgroup                                   */
+  int32_t mg_smooth;       /* Jacobi sweeps before and after the coarse grid;
+                              must be 2 (the fused smoothers)                    */
+  int32_t mg_coarse_max;   /* levels with at most this many voxels (and whose
+                              LDS block fits one workgroup) are solved in one
+                              workgroup; default 4096                            */
   /* initialisation */
   double init_rtol;        /* steady oxygen: Picard until the nonlinear residual
                               is below init_rtol ||b||                          */

@@ -204,6 +204,8 @@ void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, doub
 constexpr int kMaxLevels = 16;
 constexpr int kCoarseThreads = 1024;
 constexpr int kCoarseMaxCellsPerThread = 8;
+// LDS floats per cell of a coarse-solve level: two iterates, r, D^-1, gx, gy, gz
+constexpr int kCoarseLdsPerCell = 7;
 
 // One replicate at one multigrid level.  Level k cell I covers fine cells
 // [I 2^k, min((I+1) 2^k, n0)) per axis; dims n_k = ceil(n_{k-1} / 2).
@@ -234,10 +236,13 @@ struct MgCoarseRep {
   int kc;
   int n0[3];
   int dims[kMaxLevels][3];
-  int lds_off[kMaxLevels];  // float offset of each level's (u, r, dinv) block
+  // LDS: the system's precomputed block (pre_len floats, as in coarse_pre),
+  // then each level's (ua, ub, r) block at pre_len + lds_off[j]
+  int lds_off[kMaxLevels];
   long long off_kc;         // replicate offset in the level-kc arrays
-  long long pre_off;        // this system's block in MgBufs::coarse_pre
+  long long pre_off;        // this system's block in MgBufs::coarse_pre (a multiple of 4)
   int pre_lev[kMaxLevels];  // level j's [D^-1 | gx | gy | gz] within the block
+  int pre_len;              // floats in the block (a multiple of 4)
   float a;
 };
 
@@ -253,6 +258,8 @@ struct MgBufs {
   float** lev_u;
 };
 
+// Allow the coarse-solve kernels `bytes` of dynamic LDS (above 64 KiB).
+hipError_t mg_set_coarse_lds(int bytes);
 void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, const double* c);
 // One V-cycle on the residual sb.r, result in sb.z; finishes the flexible-CG
 // scalars (r.z, beta) with a RED_RZ reduce.

@@ -11,13 +11,12 @@
 // area over the centre distance, both in fine-voxel units,
 //     g = a * area / ((e_I + e_J) / 2),   e = extents along the face normal.
 // Restriction sums fine residuals over the aggregate; prolongation is
-// cell-centred linear interpolation on the multi-workgroup levels (about a
-// third fewer CG iterations than piecewise-constant for the diffusion-dominated
-// drug operator) and piecewise constant inside the one-workgroup coarse solve;
-// smoothing is weighted Jacobi (two sweeps before and two after the
-// coarse-grid correction).  Levels above `mg_coarse_max` cells run
-// as multi-workgroup kernels; the remaining levels of each replicate are one
-// workgroup working in LDS down to a single cell (solved exactly).
+// cell-centred linear interpolation (about a third fewer CG iterations than
+// piecewise-constant for the diffusion-dominated drug operator); smoothing is
+// weighted Jacobi (two sweeps before and two after the coarse-grid
+// correction).  Levels above `mg_coarse_max` cells run as multi-workgroup
+// kernels; the remaining levels of each system are one workgroup working in
+// LDS down to a single cell (solved exactly), the same cycle.
 //
 // Fused kernels per global level k:
 //   pre      u1 = w Dinv r (first sweep from zero, formed on the fly at the
@@ -498,19 +497,20 @@ __global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float omega,
   }
 }
 
-// ---- coarse levels: one workgroup per replicate, in LDS -----------------------
+// ---- coarse levels: one workgroup per system, in LDS --------------------------
 
 struct CoarseLevel {
   Geo<false> G;
   int n;
-  float *u, *r, *dinv;        // LDS
-  const float *gx, *gy, *gz;  // couplings to the +x/+y/+z neighbour (0 at the edge), global
+  float rnx, rny;   // 1/nx, 1/ny (coordinates without integer division)
+  // LDS: two Jacobi iterates and the residual, [ua | ub | r]; D^-1 and the
+  // couplings to the +x/+y/+z neighbour (0 at the edge), [D^-1 | gx | gy | gz],
+  // the level's part of the system's precomputed block copied into LDS.
+  float *ua, *ub, *r, *dinv, *gx, *gy, *gz;
 };
 
-// Level j of a system's coarse solve: LDS block (u, r, D^-1) and the
-// precomputed block pre = [D^-1 | gx | gy | gz] (4 n floats, per solve).
-__device__ inline CoarseLevel coarse_level(const MgCoarseRep& cr, float* lds, const float* pre, int j,
-                                           float a) {
+// Level j of a system's coarse solve (LDS pointers and geometry).
+__device__ inline CoarseLevel coarse_level(const MgCoarseRep& cr, float* lds, int j, float a) {
   CoarseLevel L;
   L.G.nx = cr.dims[j][0];
   L.G.ny = cr.dims[j][1];
@@ -521,96 +521,167 @@ __device__ inline CoarseLevel coarse_level(const MgCoarseRep& cr, float* lds, co
   L.G.n0z = cr.n0[2];
   L.G.a = a;
   L.n = L.G.nx * L.G.ny * L.G.nz;
-  L.u = lds + cr.lds_off[j];
-  L.r = L.u + L.n;
-  L.dinv = L.r + L.n;
-  const float* g = pre + cr.pre_off + cr.pre_lev[j];
-  L.gx = g + L.n;
-  L.gy = g + 2 * L.n;
-  L.gz = g + 3 * L.n;
+  L.rnx = 1.f / (float)L.G.nx;
+  L.rny = 1.f / (float)L.G.ny;
+  L.ua = lds + cr.pre_len + cr.lds_off[j];
+  L.ub = L.ua + L.n;
+  L.r = L.ub + L.n;
+  L.dinv = lds + cr.pre_lev[j];
+  L.gx = L.dinv + L.n;
+  L.gy = L.gx + L.n;
+  L.gz = L.gy + L.n;
   return L;
 }
 
-__device__ inline void coords(int t, int nx, int ny, int& x, int& y, int& z) {
-  x = t % nx;
-  const int q = t / nx;
-  y = q % ny;
-  z = q / ny;
+// Coordinates of cell t (t < 2^13): the float quotient (t + 1/2) / nx is at
+// least 1/(2 nx) from an integer and its rounding error far below that; the
+// fix-ups only guard the argument.
+__device__ inline void cell_xyz(const CoarseLevel& L, int t, int& x, int& y, int& z) {
+  int q = (int)(((float)t + 0.5f) * L.rnx);
+  x = t - q * L.G.nx;
+  if (x < 0) {
+    --q;
+    x += L.G.nx;
+  } else if (x >= L.G.nx) {
+    ++q;
+    x -= L.G.nx;
+  }
+  z = (int)(((float)q + 0.5f) * L.rny);
+  y = q - z * L.G.ny;
+  if (y < 0) {
+    --z;
+    y += L.G.ny;
+  } else if (y >= L.G.ny) {
+    ++z;
+    y -= L.G.ny;
+  }
 }
 
-// sum_J g_IJ v_J over the existing neighbours, in the order -x, +x, -y, +y, -z, +z
-__device__ inline float lds_nbsum(const CoarseLevel& L, const float* v, int t, int x, int y, int z) {
-  const Geo<false>& G = L.G;
-  const int plane = G.nx * G.ny;
-  float s = 0.f;
-  if (x > 0) s += L.gx[t - 1] * v[t - 1];
-  if (x + 1 < G.nx) s += L.gx[t] * v[t + 1];
-  if (y > 0) s += L.gy[t - G.nx] * v[t - G.nx];
-  if (y + 1 < G.ny) s += L.gy[t] * v[t + G.nx];
-  if (z > 0) s += L.gz[t - plane] * v[t - plane];
-  if (z + 1 < G.nz) s += L.gz[t] * v[t + plane];
+// Neighbours of cell t in LDS, branch-free: indices clamped to t where a
+// face is missing and the coupling of a missing face 0, so all reads of a
+// stencil are issued together instead of one per taken branch.  The stored
+// +x/+y/+z couplings are already 0 at the upper edges.
+struct CoarseNb {
+  int xm, xp, ym, yp, zm, zp;   // neighbour indices (t where absent)
+  float fxm, fym, fzm;          // 1 where the lower neighbour exists, else 0
+};
+
+__device__ inline CoarseNb coarse_nb(const CoarseLevel& L, int t, int x, int y, int z) {
+  const int nx = L.G.nx, plane = nx * L.G.ny;
+  CoarseNb b;
+  b.xm = x > 0 ? t - 1 : t;
+  b.xp = x + 1 < nx ? t + 1 : t;
+  b.ym = y > 0 ? t - nx : t;
+  b.yp = y + 1 < L.G.ny ? t + nx : t;
+  b.zm = z > 0 ? t - plane : t;
+  b.zp = z + 1 < L.G.nz ? t + plane : t;
+  b.fxm = x > 0 ? 1.f : 0.f;
+  b.fym = y > 0 ? 1.f : 0.f;
+  b.fzm = z > 0 ? 1.f : 0.f;
+  return b;
+}
+
+// sum_J g_IJ V(J) over the existing neighbours, in the order -x, +x, -y, +y, -z, +z
+template <typename VF>
+__device__ inline float lds_nbsum_f(const CoarseLevel& L, const CoarseNb& b, int t, VF V) {
+  const float gxm = b.fxm * L.gx[b.xm], gym = b.fym * L.gy[b.ym], gzm = b.fzm * L.gz[b.zm];
+  float s = gxm * V(b.xm);
+  s += L.gx[t] * V(b.xp);
+  s += gym * V(b.ym);
+  s += L.gy[t] * V(b.yp);
+  s += gzm * V(b.zm);
+  s += L.gz[t] * V(b.zp);
   return s;
 }
 
-__device__ inline void lds_jacobi(const CoarseLevel& L, float omega) {
-  float nv[kCoarseMaxCellsPerThread];
+__device__ inline float lds_nbsum(const CoarseLevel& L, const float* v, int t, int x, int y, int z) {
+  const CoarseNb b = coarse_nb(L, t, x, y, z);
+  return lds_nbsum_f(L, b, t, [&](int j) { return v[j]; });
+}
+
+// The cells of a level dealt to the workgroup's threads: t = thread + m * block.
+#define FOR_MY_CELLS(L, t) for (int t = (int)threadIdx.x; t < (L).n; t += kCoarseThreads)
+
+// One phase over the n cells of a level: value(t) of the cells a thread
+// holds is formed first (their LDS reads in flight together; tail slots repeat
+// cell n-1), then store(t, value) for the cells that exist; batches of four
+// cells per thread.  A phase reads no array it stores to, other than a cell's
+// own entry.
+template <int M, typename VF, typename SF>
+__device__ inline void coarse_phase_m(int base, int n, VF value, SF store) {
+  float v[M];
 #pragma unroll
-  for (int m = 0; m < kCoarseMaxCellsPerThread; ++m) {
-    const int t = threadIdx.x + m * kCoarseThreads;
-    if (t < L.n) {
-      int x, y, z;
-      coords(t, L.G.nx, L.G.ny, x, y, z);
-      nv[m] = (1.f - omega) * L.u[t] + omega * L.dinv[t] * (L.r[t] + lds_nbsum(L, L.u, t, x, y, z));
-    }
-  }
-  __syncthreads();
+  for (int m = 0; m < M; ++m) v[m] = value(min(base + (int)threadIdx.x + m * kCoarseThreads, n - 1));
 #pragma unroll
-  for (int m = 0; m < kCoarseMaxCellsPerThread; ++m) {
-    const int t = threadIdx.x + m * kCoarseThreads;
-    if (t < L.n) L.u[t] = nv[m];
+  for (int m = 0; m < M; ++m) {
+    const int t = base + (int)threadIdx.x + m * kCoarseThreads;
+    if (t < n) store(t, v[m]);
   }
-  __syncthreads();
+}
+
+template <typename VF, typename SF>
+__device__ inline void coarse_phase(int n, VF value, SF store) {
+  if (n <= kCoarseThreads) {
+    if ((int)threadIdx.x < n) store((int)threadIdx.x, value((int)threadIdx.x));
+  } else if (n <= 2 * kCoarseThreads) {
+    coarse_phase_m<2>(0, n, value, store);
+  } else {
+    for (int b = 0; b < n; b += 4 * kCoarseThreads) coarse_phase_m<4>(b, n, value, store);
+  }
+}
+
+// One weighted-Jacobi sweep, src -> dst (different buffers, so no barrier
+// between reading and writing).
+__device__ inline void lds_sweep(const CoarseLevel& L, const float* src, float* dst, float omega) {
+  coarse_phase(
+      L.n,
+      [&](int t) {
+        int x, y, z;
+        cell_xyz(L, t, x, y, z);
+        return (1.f - omega) * src[t] + omega * L.dinv[t] * (L.r[t] + lds_nbsum(L, src, t, x, y, z));
+      },
+      [&](int t, float v) { dst[t] = v; });
 }
 
 // Once per solve, one workgroup per system: coarse reaction terms of the
-// one-workgroup levels (summed from level kc, kept in the LDS u slots), then
+// one-workgroup levels (summed from level kc, kept in the LDS ua slots), then
 // each level's couplings and D^-1 into the system's precomputed block.
 __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse_prep(const MgCoarseRep* coarse,
                                                                    const float* const* lev_c,
                                                                    float* __restrict__ pre) {
-  extern __shared__ float lds[];
+  extern __shared__ __attribute__((aligned(16))) float lds[];
   const int rep = blockIdx.x;
   const MgCoarseRep& cr = coarse[rep];
   const float a = cr.a;
   const int J = cr.nlev;
   {
-    const CoarseLevel L = coarse_level(cr, lds, pre, 0, a);
+    const CoarseLevel L = coarse_level(cr, lds, 0, a);
     const float* gc = lev_c[cr.kc] + cr.off_kc;
-    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) L.u[t] = gc[t];
+    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) L.ua[t] = gc[t];
   }
   __syncthreads();
   for (int j = 1; j < J; ++j) {
-    const CoarseLevel F = coarse_level(cr, lds, pre, j - 1, a);
-    const CoarseLevel C = coarse_level(cr, lds, pre, j, a);
+    const CoarseLevel F = coarse_level(cr, lds, j - 1, a);
+    const CoarseLevel C = coarse_level(cr, lds, j, a);
     for (int t = threadIdx.x; t < C.n; t += kCoarseThreads) {
       int X, Y, Z;
-      coords(t, C.G.nx, C.G.ny, X, Y, Z);
+      cell_xyz(C, t, X, Y, Z);
       float s = 0.f;
       for (int dz = 0; dz < 2 && 2 * Z + dz < F.G.nz; ++dz)
         for (int dy = 0; dy < 2 && 2 * Y + dy < F.G.ny; ++dy)
           for (int dx = 0; dx < 2 && 2 * X + dx < F.G.nx; ++dx)
-            s += F.u[(2 * X + dx) + F.G.nx * ((2 * Y + dy) + F.G.ny * (2 * Z + dz))];
-      C.u[t] = s;
+            s += F.ua[(2 * X + dx) + F.G.nx * ((2 * Y + dy) + F.G.ny * (2 * Z + dz))];
+      C.ua[t] = s;
     }
     __syncthreads();
   }
   for (int j = 0; j < J; ++j) {
-    const CoarseLevel L = coarse_level(cr, lds, pre, j, a);
+    const CoarseLevel L = coarse_level(cr, lds, j, a);
     float* g = pre + cr.pre_off + cr.pre_lev[j];
     for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) {
       int x, y, z;
-      coords(t, L.G.nx, L.G.ny, x, y, z);
-      g[t] = 1.f / (L.u[t] + L.G.gsum(x, y, z));
+      cell_xyz(L, t, x, y, z);
+      g[t] = 1.f / (L.ua[t] + L.G.gsum(x, y, z));
       g[L.n + t] = x + 1 < L.G.nx ? L.G.gx(x, y, z) : 0.f;
       g[2 * L.n + t] = y + 1 < L.G.ny ? L.G.gy(x, y, z) : 0.f;
       g[3 * L.n + t] = z + 1 < L.G.nz ? L.G.gz(x, y, z) : 0.f;
@@ -618,50 +689,93 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse_prep(const MgCoars
   }
 }
 
-// The V-cycle of levels kc.. of one system in LDS (one workgroup per system):
-// pre-smooth, restrict, ..., the one-cell level solved exactly, prolong
-// (piecewise constant), post-smooth; the correction of level kc is written
-// to that level's global u.
+// The V-cycle of levels kc.. of one system in LDS (one workgroup per system),
+// the same cycle as the multi-workgroup levels: two sweeps, restriction by
+// aggregate sums, ..., the one-cell level solved exactly, cell-centred linear
+// prolongation, two sweeps; the correction of level kc is written to that
+// level's global u.  Every level's final iterate is left in its ua.
 __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep* coarse,
                                                               float omega, const float* const* lev_r,
                                                               float* const* lev_u,
                                                               const float* __restrict__ pre,
                                                               const SolveScal* ss) {
-  extern __shared__ float lds[];
+  extern __shared__ __attribute__((aligned(16))) float lds[];
   const int rep = blockIdx.x;
   if (ss[rep].done) return;
   const MgCoarseRep& cr = coarse[rep];
   const float a = cr.a;
   const int J = cr.nlev;
-  // r of level kc and D^-1 of every level into LDS
+  // r of level kc, and the precomputed block (D^-1 and the couplings of every
+  // level), into LDS; each pass issues all of its global loads before its
+  // first LDS store (one memory latency per pass, not one per element)
   {
-    const CoarseLevel L = coarse_level(cr, lds, pre, 0, a);
+    const CoarseLevel L = coarse_level(cr, lds, 0, a);
     const float* gr = lev_r[cr.kc] + cr.off_kc;
-    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) L.r[t] = gr[t];
-  }
-  for (int j = 0; j < J; ++j) {
-    const CoarseLevel L = coarse_level(cr, lds, pre, j, a);
-    const float* g = pre + cr.pre_off + cr.pre_lev[j];
-    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) L.dinv[t] = g[t];
+    float rv[kCoarseMaxCellsPerThread];
+#pragma unroll
+    for (int m = 0; m < kCoarseMaxCellsPerThread; ++m) {
+      const int t = (int)threadIdx.x + m * kCoarseThreads;
+      rv[m] = gr[min(t, L.n - 1)];
+    }
+    const float4* src = reinterpret_cast<const float4*>(pre + cr.pre_off);
+    float4* dst = reinterpret_cast<float4*>(lds);
+    const int n4 = cr.pre_len >> 2;
+    constexpr int kBatch = 6;
+    for (int b = 0; b < n4; b += kBatch * kCoarseThreads) {
+      float4 v[kBatch];
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const int i = b + (int)threadIdx.x + k * kCoarseThreads;
+        v[k] = src[min(i, n4 - 1)];
+      }
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const int i = b + (int)threadIdx.x + k * kCoarseThreads;
+        if (i < n4) dst[i] = v[k];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kCoarseMaxCellsPerThread; ++m) {
+      const int t = (int)threadIdx.x + m * kCoarseThreads;
+      if (t < L.n) L.r[t] = rv[m];
+    }
   }
   __syncthreads();
-  // down
+  // down: u2 of the two sweeps from zero (u1 = w D^-1 r, formed on the fly at
+  // the neighbours), then the aggregate sums of r - A u2
   for (int j = 0; j + 1 < J; ++j) {
-    const CoarseLevel L = coarse_level(cr, lds, pre, j, a);
-    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) L.u[t] = omega * L.dinv[t] * L.r[t];
+    const CoarseLevel L = coarse_level(cr, lds, j, a);
+    coarse_phase(
+        L.n,
+        [&](int t) {
+          int x, y, z;
+          cell_xyz(L, t, x, y, z);
+          const CoarseNb nb = coarse_nb(L, t, x, y, z);
+          const float s = lds_nbsum_f(L, nb, t, [&](int i) { return L.dinv[i] * L.r[i]; });
+          const float d = L.dinv[t], rr = L.r[t];
+          const float u1 = omega * d * rr;
+          return (1.f - omega) * u1 + omega * d * (rr + omega * s);
+        },
+        [&](int t, float v) { L.ua[t] = v; });
     __syncthreads();
-    lds_jacobi(L, omega);
-    const CoarseLevel C = coarse_level(cr, lds, pre, j + 1, a);
-    for (int t = threadIdx.x; t < C.n; t += kCoarseThreads) {
+    const CoarseLevel C = coarse_level(cr, lds, j + 1, a);
+    FOR_MY_CELLS(C, t) {
       int X, Y, Z;
-      coords(t, C.G.nx, C.G.ny, X, Y, Z);
+      cell_xyz(C, t, X, Y, Z);
+      // the up to eight children, every one evaluated (absent ones at a
+      // clamped index) and weighted 0 or 1, in the order x, then y, then z
       float s = 0.f;
-      for (int dz = 0; dz < 2 && 2 * Z + dz < L.G.nz; ++dz)
-        for (int dy = 0; dy < 2 && 2 * Y + dy < L.G.ny; ++dy)
-          for (int dx = 0; dx < 2 && 2 * X + dx < L.G.nx; ++dx) {
-            const int x = 2 * X + dx, y = 2 * Y + dy, z = 2 * Z + dz;
+#pragma unroll
+      for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < 2; ++dx) {
+            const bool in = 2 * X + dx < L.G.nx && 2 * Y + dy < L.G.ny && 2 * Z + dz < L.G.nz;
+            const int x = in ? 2 * X + dx : 2 * X, y = in ? 2 * Y + dy : 2 * Y, z = in ? 2 * Z + dz : 2 * Z;
             const int f = x + L.G.nx * (y + L.G.ny * z);
-            s += L.r[f] - L.u[f] / L.dinv[f] + lds_nbsum(L, L.u, f, x, y, z);
+            const float res = L.r[f] - L.ua[f] / L.dinv[f] + lds_nbsum(L, L.ua, f, x, y, z);
+            s += in ? res : 0.f;
           }
       C.r[t] = s;
     }
@@ -669,33 +783,65 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep*
   }
   // coarsest: one cell and no faces, so u = r / c exactly; larger: sweeps
   {
-    const CoarseLevel L = coarse_level(cr, lds, pre, J - 1, a);
-    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) L.u[t] = L.dinv[t] * L.r[t];
+    const CoarseLevel L = coarse_level(cr, lds, J - 1, a);
+    FOR_MY_CELLS(L, t) L.ua[t] = L.dinv[t] * L.r[t];
     __syncthreads();
-    if (L.n > 1)
-      for (int it = 0; it < 30; ++it) lds_jacobi(L, omega);
-  }
-  // up
-  for (int j = J - 2; j >= 0; --j) {
-    const CoarseLevel L = coarse_level(cr, lds, pre, j, a);
-    const CoarseLevel C = coarse_level(cr, lds, pre, j + 1, a);
-    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) {
-      int x, y, z;
-      coords(t, L.G.nx, L.G.ny, x, y, z);
-      L.u[t] += C.u[(x >> 1) + C.G.nx * ((y >> 1) + C.G.ny * (z >> 1))];
+    if (L.n > 1) {
+      for (int it = 0; it < 15; ++it) {
+        lds_sweep(L, L.ua, L.ub, omega);
+        __syncthreads();
+        lds_sweep(L, L.ub, L.ua, omega);
+        __syncthreads();
+      }
     }
-    __syncthreads();
-    lds_jacobi(L, omega);
-    lds_jacobi(L, omega);
   }
-  {
-    const CoarseLevel L = coarse_level(cr, lds, pre, 0, a);
+  // up: u3 = u2 + P e, two sweeps (the last of level kc straight to global)
+  for (int j = J - 2; j >= 0; --j) {
+    const CoarseLevel L = coarse_level(cr, lds, j, a);
+    const CoarseLevel C = coarse_level(cr, lds, j + 1, a);
+    coarse_phase(L.n, [&](int t) {
+      int x, y, z;
+      cell_xyz(L, t, x, y, z);
+      int Ix, Jx, Iy, Jy, Iz, Jz;
+      float wx, wy, wz;
+      lin_axis(x, L.G.nx, C.G.nx, Ix, Jx, wx);
+      lin_axis(y, L.G.ny, C.G.ny, Iy, Jy, wy);
+      lin_axis(z, L.G.nz, C.G.nz, Iz, Jz, wz);
+      const int sy = C.G.nx, sz = C.G.nx * C.G.ny;
+      const float* e = C.ua;
+      // x first along each coarse row, then y, then z (the global levels' order)
+      const float r00 = (1.f - wx) * e[Iz * sz + Iy * sy + Ix] + wx * e[Iz * sz + Iy * sy + Jx];
+      const float r01 = (1.f - wx) * e[Iz * sz + Jy * sy + Ix] + wx * e[Iz * sz + Jy * sy + Jx];
+      const float r10 = (1.f - wx) * e[Jz * sz + Iy * sy + Ix] + wx * e[Jz * sz + Iy * sy + Jx];
+      const float r11 = (1.f - wx) * e[Jz * sz + Jy * sy + Ix] + wx * e[Jz * sz + Jy * sy + Jx];
+      const float p0 = (1.f - wy) * r00 + wy * r01;
+      const float p1 = (1.f - wy) * r10 + wy * r11;
+      return L.ua[t] + ((1.f - wz) * p0 + wz * p1);
+    }, [&](int t, float v) { L.ua[t] = v; });
+    __syncthreads();
+    lds_sweep(L, L.ua, L.ub, omega);
+    __syncthreads();
+    if (j > 0) {
+      lds_sweep(L, L.ub, L.ua, omega);
+      __syncthreads();
+    } else {
+      lds_sweep(L, L.ub, lev_u[cr.kc] + cr.off_kc, omega);
+    }
+  }
+  if (J == 1) {   // level kc is the one-cell level itself
+    const CoarseLevel L = coarse_level(cr, lds, 0, a);
     float* gu = lev_u[cr.kc] + cr.off_kc;
-    for (int t = threadIdx.x; t < L.n; t += kCoarseThreads) gu[t] = L.u[t];
+    FOR_MY_CELLS(L, t) gu[t] = L.ua[t];
   }
 }
 
 // ---- launchers -------------------------------------------------------------
+
+hipError_t mg_set_coarse_lds(int bytes) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_mg_coarse, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_mg_coarse_prep, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
 
 void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, const double* c) {
   if (mg.lev[0].ntiles)
@@ -738,9 +884,9 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
       const MgLevel& C = mg.lev[k + 1];
       if (!L.ntiles) continue;
       hca_launch((k_mg_pre<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
-                         (const float*)L.r, ss);
+                 (const float*)L.r, ss);
       hca_launch((k_mg_restrict<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
-                         (const float*)L.r, ss);
+                 (const float*)L.r, ss);
     }
     H(MG_DOWN, 0);
   }
@@ -755,9 +901,9 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
       const MgLevel& C = mg.lev[k + 1];
       if (!L.ntiles) continue;
       hca_launch((k_mg_post1<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, om,
-                         (const float*)L.r, ss);
+                 (const float*)L.r, ss);
       hca_launch((k_mg_post2<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
-                         (const float*)L.r, sb);
+                 (const float*)L.r, sb);
     }
     H(MG_UP, 0);
   }

@@ -608,6 +608,10 @@ hca_status validate_params(const hca_params* p, std::string& msg) {
     msg = "integer parameter out of range";
     return HCA_E_INVALID;
   }
+  if (p->mg_smooth != 2) {
+    msg = "mg_smooth: the multigrid smoothers implement two sweeps before and after";
+    return HCA_E_INVALID;
+  }
   return HCA_OK;
 }
 
@@ -981,12 +985,16 @@ hca_status mg_upload(hca_ctx* c, T** p, const std::vector<T>& v) {
 // Hierarchy of every system (field-major, like the solver tables): level
 // dims by ceil halving down to one cell (at least two levels); kc, the first
 // level handed to the one-workgroup coarse solve (<= mg_coarse_max cells and
-// its LDS block within 64 KiB); level arrays, per-level tiles, coarse-solve
+// its LDS block within the device's per-workgroup LDS); level arrays, per-level tiles, coarse-solve
 // descriptors.  mg1 is the oxygen prefix (the first nreps systems) of mg3.
 hca_status build_mg(hca_ctx* c) {
   const int R = c->nreps;
   const int S = 3 * R;
-  constexpr size_t kLdsCap = 65536;
+  // LDS of one workgroup: the coarse solve's levels must fit (160 KiB on gfx950)
+  int lds_dev = 65536;
+  if (hipDeviceGetAttribute(&lds_dev, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
+    lds_dev = 65536;
+  const size_t kLdsCap = (size_t)std::max(lds_dev, 65536);
   auto cells = [](const std::array<int, 3>& a) { return (long long)a[0] * a[1] * a[2]; };
   std::vector<std::vector<std::array<int, 3>>> dims(R);
   std::vector<int> kcr(R, 1);
@@ -1000,7 +1008,7 @@ hca_status build_mg(hca_ctx* c) {
     }
     for (int k = 1; k < (int)d.size(); ++k) {
       size_t lds = 0;
-      for (int j = k; j < (int)d.size(); ++j) lds += 3 * sizeof(float) * (size_t)cells(d[j]);
+      for (int j = k; j < (int)d.size(); ++j) lds += kCoarseLdsPerCell * sizeof(float) * (size_t)cells(d[j]);
       const long long n = cells(d[k]);
       if (n <= c->prm.mg_coarse_max && n <= (long long)kCoarseThreads * kCoarseMaxCellsPerThread &&
           lds <= kLdsCap) {
@@ -1119,10 +1127,11 @@ hca_status build_mg(hca_ctx* c) {
       for (int i = 0; i < 3; ++i) d.dims[j][i] = dims[r][kcr[r] + j][i];
       d.lds_off[j] = o;
       d.pre_lev[j] = g;
-      o += 3 * d.dims[j][0] * d.dims[j][1] * d.dims[j][2];
+      o += (kCoarseLdsPerCell - 4) * d.dims[j][0] * d.dims[j][1] * d.dims[j][2];
       g += 4 * d.dims[j][0] * d.dims[j][1] * d.dims[j][2];
     }
-    lds_max = std::max(lds_max, (size_t)o * sizeof(float));
+    d.pre_len = g;
+    lds_max = std::max(lds_max, (size_t)(o + g) * sizeof(float));
     d.off_kc = mreps[kcr[r]][s].off;
     d.pre_off = pre_total;
     pre_total += g;
@@ -1132,6 +1141,7 @@ hca_status build_mg(hca_ctx* c) {
   if (st != HCA_OK) return st;
   mg.coarse = dcr;
   mg.coarse_lds_bytes = (int)lds_max;
+  if (lds_max > 65536) HIPCHK(c, mg_set_coarse_lds((int)lds_max));
   if ((st = mg_alloc(c, &mg.coarse_pre, (size_t)pre_total)) != HCA_OK) return st;
   if ((st = mg_upload(c, &mg.lev_c, pc)) != HCA_OK || (st = mg_upload(c, &mg.lev_r, pr)) != HCA_OK ||
       (st = mg_upload(c, &mg.lev_u, pu)) != HCA_OK)
@@ -1251,7 +1261,7 @@ hca_status hca_default_params(hca_params* out) {
   out->cg_rtol = 1.0e-10;
   out->cg_maxit = 2000;
   out->mg_smooth = 2;
-  out->mg_coarse_max = 512;
+  out->mg_coarse_max = 4096;
   out->init_rtol = 1.0e-10;
   out->init_maxit = 200;
   out->profile = 0;

@@ -118,6 +118,8 @@ def test_rejects_bad_params_and_arguments():
     assert init_status([(cell, w, NODOSE)], p) == hca.E_INVALID
     p = hca.default_params(precond=7)
     assert init_status([(cell, w, NODOSE)], p) == hca.E_INVALID
+    p = hca.default_params(mg_smooth=3)   # the smoothers implement two sweeps only
+    assert init_status([(cell, w, NODOSE)], p) == hca.E_INVALID
     lib = hca.lib()
     assert lib.hca_init(None, None, None, 0, None) == hca.E_INVALID
     assert lib.hca_step(None, 1) == hca.E_INVALID

@@ -68,17 +68,23 @@ def test_init_matches_oracle(case32):
 
 
 PRECONDS = pytest.mark.parametrize("precond", [0, 1], ids=["jacobi", "multigrid"])
+# solver variants: Jacobi; multigrid with the default one-workgroup coarse
+# solve (levels up to 4096 cells); multigrid with more multi-workgroup levels
+# (one-workgroup solve from 64 cells)
+SOLVERS = pytest.mark.parametrize(
+    "solver_kw", [dict(precond=0), dict(precond=1), dict(precond=1, mg_coarse_max=64)],
+    ids=["jacobi", "multigrid", "multigrid-coarse64"])
 
 
-@PRECONDS
-def test_solves_match_oracle_exact_solution(case32, precond):
+@SOLVERS
+def test_solves_match_oracle_exact_solution(case32, solver_kw):
     tis, sched, s0 = case32
     osched = oracle_sched(sched)
     # a state with drug already in the tissue: two oracle steps from init
     s = s0
     for _ in range(2):
         s, _ = om.step(s, tis.w, osched, tis.seed, OP)
-    with make_sim([(tis, sched)], precond=precond) as sim:
+    with make_sim([(tis, sched)], **solver_kw) as sim:
         push_state(sim, s)
         sim.run_phases(hca.PH_O2 | hca.PH_DRUGS)
         K, G1, G2 = om.solve_fields(s, tis.w, osched, OP)
@@ -175,11 +181,11 @@ def test_trajectory_20_steps_resynchronised(case32, precond):
     assert total_div > 0 and total_kill > 0
 
 
-@PRECONDS
+@SOLVERS
 @pytest.mark.parametrize("shape", [(9, 23, 17), (1, 40, 33), (70, 5, 5), (2, 2, 130), (1, 1, 1),
                                    (3, 1, 2)])
-def test_ragged_lattices(shape, precond):
-    print(f"\n[ragged] shape {shape} precond {precond}", flush=True)
+def test_ragged_lattices(shape, solver_kw):
+    print(f"\n[ragged] shape {shape} solver {solver_kw}", flush=True)
     tis = synth.make_tissue(shape, 4, seed=sum(shape))
     if not (tis.w > 0).any():
         tis.w.ravel()[0] = 1.0
@@ -187,7 +193,7 @@ def test_ragged_lattices(shape, precond):
     sched = synth.bolus_schedule([0, 2])
     osched = oracle_sched(sched)
     s = om.init_state(tis.cell, tis.w, tis.seed, OP)
-    with make_sim([(tis, sched)], precond=precond) as sim:
+    with make_sim([(tis, sched)], **solver_kw) as sim:
         assert relerr(sim.field("K"), s.K) <= FIELD_TOL
         for n in range(4):
             push_state(sim, s)
@@ -274,17 +280,18 @@ def test_autotuned_tiles_agree_with_heuristic_tiles(case32):
             assert relerr(a.field(n), b.field(n)) <= 1e-12, n
 
 
+@pytest.mark.parametrize("coarse_max", [64, 512, 4096])
 @pytest.mark.parametrize("shape", [(32, 32, 32), (23, 17, 9), (40, 33, 1)], ids=str)
-def test_multigrid_keeps_iterations_low(shape):
+def test_multigrid_keeps_iterations_low(shape, coarse_max):
     """The V-cycle is only a preconditioner (parity cannot see a weak one), so
     its quality is pinned by iteration counts: at rel. residual 1e-10 every
     field converges in at most 14 flexible-CG iterations per step, on even,
     odd (ragged aggregates at every level) and 2-D lattices."""
-    print(f"\n[mg iterations] {shape}", flush=True)
+    print(f"\n[mg iterations] {shape} coarse_max {coarse_max}", flush=True)
     tis = synth.make_tissue(shape, 6, seed=3)
     sched = synth.bolus_schedule([0])
     with hca.Simulation([(tis.cell, tis.w, tis.seed, (sched.times, sched.amts))],
-                        hca.default_params()) as sim:
+                        hca.default_params(mg_coarse_max=coarse_max)) as sim:
         for _ in range(3):
             sim.step(1)
             it = sim.stats()["cg_iters"]
