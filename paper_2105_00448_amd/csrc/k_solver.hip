@@ -63,19 +63,30 @@ __device__ inline TileCoord tile_coord(const Work& w, int ti) {
 // at most 66 x 6 (tx = 64).
 constexpr int kPlaneMax = 400;
 
+// Planes whose global loads are issued ahead of the plane being stored to
+// LDS (the ring depth of plane_stencil).  One, i.e. plane z+2's operand and c
+// in flight while plane z is computed, measured fastest for the CG kernels:
+// deeper rings hold more registers (fewer resident waves) and measured slower.
+constexpr int kStencilPrefetch = 1;
+
 // Marches the tile over [z0, z1) and calls f(i, deg, u_i, (A u)_i) for every
 // voxel of the tile inside the lattice, where u = op.value(op.load(j)) is the
 // operand (possibly formed on the fly from several arrays) and
 // (A u)_i = (c_i + a deg) u_i - a sum_nb u_j.  Each plane of u, with its x/y
 // frame, is formed once into LDS (double buffered); outside the lattice the
 // frame holds 0, which adds nothing to the neighbour sum.  Software
-// pipelined: the global loads of plane z+2 and of c on plane z+1 are issued
-// before plane z is computed, so their latency overlaps the compute and the
-// barrier instead of stalling each plane.  Called by the whole workgroup.
-template <typename OP, typename F>
+// pipelined: the global loads (operand and c) of planes z+2 .. z+1+PD are in
+// flight while plane z is computed, in a ring of registers (the z loop is
+// unrolled by PD so every ring slot is a fixed register), so their latency
+// overlaps the compute and the barrier.  Called by the whole workgroup.
+template <int PD, typename OP, typename F>
 __device__ inline void plane_stencil(const TileCoord& tc, const double* __restrict__ c,
                                      double (*lds)[kPlaneMax], const OP& op, F f) {
   using Raw = typename OP::Raw;
+  struct Slot {
+    Raw ri, rf;   // operand of the thread's cell and of its frame cell
+    double c;     // c of the thread's cell
+  };
   const double a = tc.a;
   const int W = tc.tx + 2;
   const int o = (tc.ly + 1) * W + tc.lx + 1;
@@ -103,56 +114,77 @@ __device__ inline void plane_stencil(const TileCoord& tc, const double* __restri
   const int fo = hy * W + hx;
   const long long fidx = fin ? gx + (long long)tc.nx * gy : 0;
   const long long iidx = tc.x + (long long)tc.nx * tc.y;
-  Raw ri = op.zero(), rf = op.zero();
-  auto load_plane = [&](int z) {
-    const long long pz = tc.off + plane * z;
-    if (tc.valid) ri = op.load(pz + iidx);
-    if (fin) rf = op.load(pz + fidx);
+  const int z0 = tc.z0, z1 = tc.z1;
+  // plane zp into a slot; planes beyond z1 are never needed, and the plane
+  // z1 only as the +z neighbour (no c)
+  auto load_slot = [&](Slot& sl, int zp) {
+    const long long pz = tc.off + plane * zp;
+    if (tc.valid) sl.ri = op.load(pz + iidx);
+    if (tc.valid && zp < z1) sl.c = c[pz + iidx];
+    if (fin) sl.rf = op.load(pz + fidx);
   };
-  auto store_plane = [&](double* buf) {
-    buf[o] = tc.valid ? op.value(ri) : 0.0;
-    if (has_frame) buf[fo] = fin ? op.value(rf) : 0.0;
+  auto store_slot = [&](const Slot& sl, double* buf) {
+    buf[o] = tc.valid ? op.value(sl.ri) : 0.0;
+    if (has_frame) buf[fo] = fin ? op.value(sl.rf) : 0.0;
   };
   const bool xl = tc.x > 0, xr = tc.x + 1 < tc.nx, yl = tc.y > 0, yr = tc.y + 1 < tc.ny;
   const int deg_xy = (int)xl + (int)xr + (int)yl + (int)yr;
-  long long i = tc.off + iidx + plane * tc.z0;
+  long long i = tc.off + iidx + plane * z0;
   double* cur = lds[0];
   double* nxt = lds[1];
+  // ring: plane zp (z0 < zp <= min(z1, nz - 1)) in slot (zp - z0 - 1) % PD
+  Slot ring[PD];
+#pragma unroll
+  for (int d = 0; d < PD; ++d) ring[d] = Slot{op.zero(), op.zero(), 0.0};
   __syncthreads();   // the previous tile's readers are done with both buffers
-  load_plane(tc.z0);
-  const double um0 = (tc.valid && tc.z0 > 0) ? op.value(op.load(i - plane)) : 0.0;
-  double cc = tc.valid ? c[i] : 0.0;
-  store_plane(cur);
-  if (tc.z0 + 1 < tc.nz) load_plane(tc.z0 + 1);
-  double um = um0;
+  double um, cc;
+  {
+    Slot s0{op.zero(), op.zero(), 0.0};
+    load_slot(s0, z0);
+    um = (tc.valid && z0 > 0) ? op.value(op.load(i - plane)) : 0.0;
+#pragma unroll
+    for (int d = 0; d < PD; ++d)
+      if (z0 + 1 + d <= z1 && z0 + 1 + d < tc.nz) load_slot(ring[d], z0 + 1 + d);
+    cc = s0.c;
+    store_slot(s0, cur);
+  }
   __syncthreads();
   double uc = cur[o];
-  for (int z = tc.z0; z < tc.z1; ++z) {
-    const bool zl = z > 0, zr = z + 1 < tc.nz;
-    const bool more = z + 1 < tc.z1;   // an iteration follows this one
-    if (zr) store_plane(nxt);          // plane z+1, loaded one iteration ago
-    if (more && z + 2 < tc.nz) load_plane(z + 2);
-    const double cn = (more && tc.valid) ? c[i + plane] : 0.0;
-    double s = cur[o - 1];
-    s += cur[o + 1];
-    s += cur[o - W];
-    s += cur[o + W];
-    __syncthreads();
-    const double up = zr ? nxt[o] : 0.0;
-    s += um;
-    s += up;
-    if (tc.valid) {
-      const int deg = deg_xy + (int)zl + (int)zr;
-      const double Au = (cc + a * deg) * uc - a * s;
-      f(i, deg, uc, Au);
+  for (int zb = z0; zb < z1; zb += PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const int z = zb + d;
+      if (z < z1) {   // uniform over the workgroup
+        const bool zl = z > 0, zr = z + 1 < tc.nz;
+        double cn = 0.0;
+        if (zr) {   // plane z+1 into LDS; its slot then takes plane z+1+PD
+          store_slot(ring[d], nxt);
+          cn = ring[d].c;
+          const int zq = z + 1 + PD;
+          if (zq <= z1 && zq < tc.nz) load_slot(ring[d], zq);
+        }
+        double s = cur[o - 1];
+        s += cur[o + 1];
+        s += cur[o - W];
+        s += cur[o + W];
+        __syncthreads();
+        const double up = zr ? nxt[o] : 0.0;
+        s += um;
+        s += up;
+        if (tc.valid) {
+          const int deg = deg_xy + (int)zl + (int)zr;
+          const double Au = (cc + a * deg) * uc - a * s;
+          f(i, deg, uc, Au);
+        }
+        um = uc;
+        uc = up;
+        cc = cn;
+        double* t = cur;
+        cur = nxt;
+        nxt = t;
+        i += plane;
+      }
     }
-    um = uc;
-    uc = up;
-    cc = cn;
-    double* t = cur;
-    cur = nxt;
-    nxt = t;
-    i += plane;
   }
 }
 
@@ -206,7 +238,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_start(Work w, const double* __res
     const double a = tc.a;
     double bb = 0.0, rr = 0.0, rz = 0.0;
     {
-      plane_stencil(tc, c, lds, OpX{x},
+      plane_stencil<kStencilPrefetch>(tc, c, lds, OpX{x},
                      [&](long long i, int deg, double, double Ax) {
                        const double bi = b[i];
                        const double r = bi - Ax;
@@ -250,7 +282,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, const double* __res
     double pq = 0.0;
     {
       const OpP<JAC> op{z, sb.z32, pold, beta, first};
-      plane_stencil(tc, c, lds, op, [&](long long i, int, double pc, double Ap) {
+      plane_stencil<kStencilPrefetch>(tc, c, lds, op, [&](long long i, int, double pc, double Ap) {
         pnew[i] = pc;
         q[i] = Ap;
         pq += pc * Ap;

@@ -1023,7 +1023,11 @@ hca_status build_mg(hca_ctx* c) {
   HIPCHK(c, hipMemcpy(sd.data(), c->d_sys, sizeof(RepDev) * S, hipMemcpyDeviceToHost));
   MgBufs& mg = c->mg3;
   mg.nlev_glob = nglob;
-  mg.omega = 0.8f;
+  // Jacobi damping 6/7, the weight that best damps the high-frequency half
+  // of the spectrum of the 7-point operator in 3-D (two-grid smoothing
+  // analysis); measured: the drug systems take fewer CG iterations than with
+  // 0.8, and 0.9 already more.
+  mg.omega = 6.f / 7.f;
   c->mg1 = mg;
   std::vector<float*> pc(kMaxLevels, nullptr), pr(kMaxLevels, nullptr), pu(kMaxLevels, nullptr);
   std::vector<std::vector<MgRep>> mreps(nglob + 1);
