@@ -252,7 +252,7 @@ struct MgBufs {
   const MgCoarseRep* coarse;
   float* coarse_pre;        // per solve: couplings and D^-1 of the coarse-solve levels
   int coarse_lds_bytes;
-  float omega;
+  float w_a, w_b;            // Jacobi weights: pre-sweeps (w_a, w_b), post-sweeps (w_b, w_a)
   float** lev_c;            // device arrays of the per-level pointers
   float** lev_r;
   float** lev_u;

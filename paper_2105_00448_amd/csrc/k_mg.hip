@@ -302,7 +302,7 @@ struct OpPre {
 };
 
 template <bool L0, typename RT>
-__global__ void __launch_bounds__(kBlock) k_mg_pre(MgLevel Lk, float omega,
+__global__ void __launch_bounds__(kBlock) k_mg_pre(MgLevel Lk, float wa, float wb,
                                                    const RT* __restrict__ r, const SolveScal* ss) {
   __shared__ float lds[2][kPlaneMaxF];
   float* __restrict__ u = Lk.u;
@@ -311,10 +311,10 @@ __global__ void __launch_bounds__(kBlock) k_mg_pre(MgLevel Lk, float omega,
     if (ss[t.rep].done) continue;
     const MgRep m = Lk.reps[t.rep];
     const Geo<L0> G = geo_of<L0>(m);
-    const OpPre<RT> op{Lk.dinv, r, omega};
+    const OpPre<RT> op{Lk.dinv, r, wa};
     mg_plane(G, t, m.tx, m.off, lds, op,
              [&](int, long long i, float u1, float s, const CtrDR<RT>& c) {
-               u[i] = (1.f - omega) * u1 + omega * c.dinv * ((float)c.r + s);
+               u[i] = (1.f - wb) * u1 + wb * c.dinv * ((float)c.r + s);
              });
   }
 }
@@ -695,7 +695,8 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse_prep(const MgCoars
 // prolongation, two sweeps; the correction of level kc is written to that
 // level's global u.  Every level's final iterate is left in its ua.
 __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep* coarse,
-                                                              float omega, const float* const* lev_r,
+                                                              float wa, float wb,
+                                                              const float* const* lev_r,
                                                               float* const* lev_u,
                                                               const float* __restrict__ pre,
                                                               const SolveScal* ss) {
@@ -753,8 +754,8 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep*
           const CoarseNb nb = coarse_nb(L, t, x, y, z);
           const float s = lds_nbsum_f(L, nb, t, [&](int i) { return L.dinv[i] * L.r[i]; });
           const float d = L.dinv[t], rr = L.r[t];
-          const float u1 = omega * d * rr;
-          return (1.f - omega) * u1 + omega * d * (rr + omega * s);
+          const float u1 = wa * d * rr;
+          return (1.f - wb) * u1 + wb * d * (rr + wa * s);
         },
         [&](int t, float v) { L.ua[t] = v; });
     __syncthreads();
@@ -788,9 +789,9 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep*
     __syncthreads();
     if (L.n > 1) {
       for (int it = 0; it < 15; ++it) {
-        lds_sweep(L, L.ua, L.ub, omega);
+        lds_sweep(L, L.ua, L.ub, wa);
         __syncthreads();
-        lds_sweep(L, L.ub, L.ua, omega);
+        lds_sweep(L, L.ub, L.ua, wb);
         __syncthreads();
       }
     }
@@ -819,13 +820,13 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep*
       return L.ua[t] + ((1.f - wz) * p0 + wz * p1);
     }, [&](int t, float v) { L.ua[t] = v; });
     __syncthreads();
-    lds_sweep(L, L.ua, L.ub, omega);
+    lds_sweep(L, L.ua, L.ub, wb);
     __syncthreads();
     if (j > 0) {
-      lds_sweep(L, L.ub, L.ua, omega);
+      lds_sweep(L, L.ub, L.ua, wa);
       __syncthreads();
     } else {
-      lds_sweep(L, L.ub, lev_u[cr.kc] + cr.off_kc, omega);
+      lds_sweep(L, L.ub, lev_u[cr.kc] + cr.off_kc, wa);
     }
   }
   if (J == 1) {   // level kc is the one-cell level itself
@@ -860,7 +861,8 @@ void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, const dou
 
 void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const SolverBufs& sb,
                       MgHook hook, void* hctx) {
-  const float om = mg.omega;
+  // pre-sweeps with weights (wa, wb), post-sweeps with (wb, wa)
+  const float wa = mg.w_a, wb = mg.w_b;
   const SolveScal* ss = sb.ss;
   auto H = [&](int seg, int begin) {
     if (hook) hook(hctx, seg, begin);
@@ -869,7 +871,7 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_PRE0, 1);
-    hca_launch((k_mg_pre<true, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
+    hca_launch((k_mg_pre<true, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, wa, wb,
                        (const float*)sb.r32, ss);
     H(MG_PRE0, 0);
     H(MG_RESTRICT0, 1);
@@ -883,7 +885,7 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
       const MgLevel& L = mg.lev[k];
       const MgLevel& C = mg.lev[k + 1];
       if (!L.ntiles) continue;
-      hca_launch((k_mg_pre<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
+      hca_launch((k_mg_pre<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, wa, wb,
                  (const float*)L.r, ss);
       hca_launch((k_mg_restrict<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
                  (const float*)L.r, ss);
@@ -891,7 +893,7 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
     H(MG_DOWN, 0);
   }
   H(MG_COARSE, 1);
-  hca_launch(k_mg_coarse, dim3(w.nreps), dim3(kCoarseThreads), mg.coarse_lds_bytes, s, mg.coarse, om,
+  hca_launch(k_mg_coarse, dim3(w.nreps), dim3(kCoarseThreads), mg.coarse_lds_bytes, s, mg.coarse, wa, wb,
              (const float* const*)mg.lev_r, (float* const*)mg.lev_u, (const float*)mg.coarse_pre, ss);
   H(MG_COARSE, 0);
   if (mg.nlev_glob > 1) {
@@ -900,9 +902,9 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
       const MgLevel& L = mg.lev[k];
       const MgLevel& C = mg.lev[k + 1];
       if (!L.ntiles) continue;
-      hca_launch((k_mg_post1<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, om,
+      hca_launch((k_mg_post1<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, wb,
                  (const float*)L.r, ss);
-      hca_launch((k_mg_post2<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
+      hca_launch((k_mg_post2<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, wa,
                  (const float*)L.r, sb);
     }
     H(MG_UP, 0);
@@ -911,11 +913,11 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_POST1_0, 1);
-    hca_launch((k_mg_post1<true, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, om,
+    hca_launch((k_mg_post1<true, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, wb,
                        (const float*)sb.r32, ss);
     H(MG_POST1_0, 0);
     H(MG_POST2_0, 1);
-    hca_launch((k_mg_post2<true, double>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, om,
+    hca_launch((k_mg_post2<true, double>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, wa,
                        (const double*)sb.r, sb);
     H(MG_POST2_0, 0);
     launch_cg_reduce(s, w, sb, RED_RZ, 0.0, 0);

@@ -1023,11 +1023,18 @@ hca_status build_mg(hca_ctx* c) {
   HIPCHK(c, hipMemcpy(sd.data(), c->d_sys, sizeof(RepDev) * S, hipMemcpyDeviceToHost));
   MgBufs& mg = c->mg3;
   mg.nlev_glob = nglob;
-  // Jacobi damping 6/7, the weight that best damps the high-frequency half
-  // of the spectrum of the 7-point operator in 3-D (two-grid smoothing
-  // analysis); measured: the drug systems take fewer CG iterations than with
-  // 0.8, and 0.9 already more.
-  mg.omega = 6.f / 7.f;
+  // Smoothing: each pair of weighted-Jacobi sweeps is the two-step Chebyshev
+  // polynomial (1 - w_a t)(1 - w_b t) of least maximum over t in [1/3, 2], the
+  // spectrum of D^-1 A on the oscillatory modes of the 7-point operator in
+  // 3-D (2 bounds D^-1 A by diagonal dominance; 1/3 is its smallest symbol
+  // value with some frequency at pi/2): 1/w are the Chebyshev points
+  // 7/6 -+ (5/6) cos(pi/4).  Its maximum there, 1/T_2(7/5) ~ 0.34, beats two
+  // equal sweeps at the best single weight 6/7, (5/7)^2 ~ 0.51.
+  {
+    const double mid = 7.0 / 6.0, half = 5.0 / 6.0, c4 = std::sqrt(0.5);
+    mg.w_a = (float)(1.0 / (mid + half * c4));
+    mg.w_b = (float)(1.0 / (mid - half * c4));
+  }
   c->mg1 = mg;
   std::vector<float*> pc(kMaxLevels, nullptr), pr(kMaxLevels, nullptr), pu(kMaxLevels, nullptr);
   std::vector<std::vector<MgRep>> mreps(nglob + 1);
