@@ -243,6 +243,8 @@ struct MgCoarseRep {
   long long pre_off;        // this system's block in MgBufs::coarse_pre (a multiple of 4)
   int pre_lev[kMaxLevels];  // level j's [D^-1 | gx | gy | gz] within the block
   int pre_len;              // floats in the block (a multiple of 4)
+  const float* r_kc;        // this system's level-kc r and u (level arrays + off_kc)
+  float* u_kc;
   float a;
 };
 

@@ -701,9 +701,20 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep*
                                                               const float* __restrict__ pre,
                                                               const SolveScal* ss) {
   extern __shared__ __attribute__((aligned(16))) float lds[];
+  __shared__ MgCoarseRep s_cr;
   const int rep = blockIdx.x;
-  if (ss[rep].done) return;
-  const MgCoarseRep& cr = coarse[rep];
+  // the system's descriptor into LDS (every later phase reads it there
+  // instead of from global memory)
+  {
+    static_assert(sizeof(MgCoarseRep) % 4 == 0 && sizeof(MgCoarseRep) / 4 <= kCoarseThreads, "descriptor copy");
+    constexpr int nw = (int)(sizeof(MgCoarseRep) / 4);
+    const int* src = reinterpret_cast<const int*>(coarse + rep);
+    const int v = (int)threadIdx.x < nw ? src[threadIdx.x] : 0;
+    if (ss[rep].done) return;
+    if ((int)threadIdx.x < nw) reinterpret_cast<int*>(&s_cr)[threadIdx.x] = v;
+  }
+  __syncthreads();
+  const MgCoarseRep& cr = s_cr;
   const float a = cr.a;
   const int J = cr.nlev;
   // r of level kc, and the precomputed block (D^-1 and the couplings of every
@@ -711,7 +722,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep*
   // first LDS store (one memory latency per pass, not one per element)
   {
     const CoarseLevel L = coarse_level(cr, lds, 0, a);
-    const float* gr = lev_r[cr.kc] + cr.off_kc;
+    const float* gr = cr.r_kc;
     float rv[kCoarseMaxCellsPerThread];
 #pragma unroll
     for (int m = 0; m < kCoarseMaxCellsPerThread; ++m) {
@@ -826,12 +837,12 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(const MgCoarseRep*
       lds_sweep(L, L.ub, L.ua, wa);
       __syncthreads();
     } else {
-      lds_sweep(L, L.ub, lev_u[cr.kc] + cr.off_kc, wa);
+      lds_sweep(L, L.ub, cr.u_kc, wa);
     }
   }
   if (J == 1) {   // level kc is the one-cell level itself
     const CoarseLevel L = coarse_level(cr, lds, 0, a);
-    float* gu = lev_u[cr.kc] + cr.off_kc;
+    float* gu = cr.u_kc;
     FOR_MY_CELLS(L, t) gu[t] = L.ua[t];
   }
 }

@@ -994,7 +994,8 @@ hca_status build_mg(hca_ctx* c) {
   int lds_dev = 65536;
   if (hipDeviceGetAttribute(&lds_dev, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
     lds_dev = 65536;
-  const size_t kLdsCap = (size_t)std::max(lds_dev, 65536);
+  // (less 1 KiB for the coarse kernel's static LDS)
+  const size_t kLdsCap = (size_t)std::max(lds_dev, 65536) - 1024;
   auto cells = [](const std::array<int, 3>& a) { return (long long)a[0] * a[1] * a[2]; };
   std::vector<std::vector<std::array<int, 3>>> dims(R);
   std::vector<int> kcr(R, 1);
@@ -1144,6 +1145,8 @@ hca_status build_mg(hca_ctx* c) {
     d.pre_len = g;
     lds_max = std::max(lds_max, (size_t)(o + g) * sizeof(float));
     d.off_kc = mreps[kcr[r]][s].off;
+    d.r_kc = pr[kcr[r]] + d.off_kc;
+    d.u_kc = pu[kcr[r]] + d.off_kc;
     d.pre_off = pre_total;
     pre_total += g;
   }
