@@ -29,8 +29,21 @@ __device__ inline double add_nocontract(double a, double b) {
   return a + b;
 }
 
+// 1/x for finite x > 0: the hardware reciprocal estimate refined by two
+// Newton steps for f(r) = 1/r - x, r <- r + r (1 - x r) (each step squares the
+// relative error), so the result is within an ulp or two of the rounded
+// quotient at about half the instructions of the IEEE division sequence.
+__device__ inline double recip_pos(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// J5 + V > 0 (J5 > 0, V >= 0).
 __device__ inline double vegf_rhs(double V, double Pt, double mu, const DevParams& p) {
-  return p.k2 + p.k2pp * Pt * V / (p.J5 + V) - mu * V;
+  return p.k2 + p.k2pp * Pt * V * recip_pos(p.J5 + V) - mu * V;
 }
 
 // Advances (P, Vc, phi) of one occupied voxel (cell code l) with oxygen kk.
