@@ -159,7 +159,13 @@ __device__ inline void mg_plane(const Geo<UNI>& G, const Tile& t, int tx, long l
   __syncthreads();   // the previous tile's readers are done with both buffers
   load_plane(z0);
   float vm = (valid && z0 > 0) ? op.value(op.load(x, y, z0 - 1, i - plane)) : 0.f;
-  Ctr cc = valid ? op.ctr(i) : op.ctr_zero();
+  Ctr cc = op.ctr_zero();
+  if (valid) {
+    if constexpr (OP::kCtrInRaw)
+      cc = op.ctr_of(ri);
+    else
+      cc = op.ctr(i);
+  }
   store_plane(cur);
   if (z0 + 1 < G.nz) load_plane(z0 + 1);
   __syncthreads();
@@ -167,9 +173,13 @@ __device__ inline void mg_plane(const Geo<UNI>& G, const Tile& t, int tx, long l
   for (int z = z0; z < z1; ++z) {
     const bool zr = z + 1 < G.nz;
     const bool more = z + 1 < z1;
+    Ctr cn = op.ctr_zero();
+    if constexpr (OP::kCtrInRaw) {   // plane z+1's raw operands are its centre operands
+      if (more && valid) cn = op.ctr_of(ri);
+    }
     if (zr) store_plane(nxt);
     if (more && z + 2 < G.nz) load_plane(z + 2);
-    const Ctr cn = (more && valid) ? op.ctr(i + plane) : op.ctr_zero();
+    if constexpr (!OP::kCtrInRaw) cn = (more && valid) ? op.ctr(i + plane) : op.ctr_zero();
     float s = 0.f;
     if (valid) {
       if (x > 0) s += G.gx(x - 1, y, z) * cur[o - 1];
@@ -291,6 +301,7 @@ struct OpPre {
     RT r;
   };
   using Ctr = CtrDR<RT>;
+  static constexpr bool kCtrInRaw = true;   // ctr_of(raw) instead of a second load
   const float* __restrict__ dinv;
   const RT* __restrict__ r;
   float omega;
@@ -299,6 +310,7 @@ struct OpPre {
   __device__ inline float value(const Raw& v) const { return omega * v.dinv * (float)v.r; }
   __device__ inline Ctr ctr_zero() const { return Ctr{0.f, (RT)0}; }
   __device__ inline Ctr ctr(long long i) const { return Ctr{dinv[i], r[i]}; }
+  __device__ inline Ctr ctr_of(const Raw& v) const { return Ctr{v.dinv, v.r}; }
 };
 
 template <bool L0, typename RT>
@@ -326,6 +338,7 @@ struct OpU {
     float u;
   };
   using Ctr = CtrDR<RT>;
+  static constexpr bool kCtrInRaw = false;
   const float* __restrict__ u;
   const float* __restrict__ dinv;
   const RT* __restrict__ r;
@@ -403,6 +416,7 @@ struct OpPost1 {
     float wx, wy, wz;
   };
   using Ctr = CtrDR<RT>;
+  static constexpr bool kCtrInRaw = false;
   const float* __restrict__ u;
   const float* __restrict__ e;
   const float* __restrict__ dinv;
