@@ -83,18 +83,6 @@ __device__ inline Geo<UNI> geo_of(const MgRep& m) {
   return g;
 }
 
-// sum_J g_IJ V(J) over the existing neighbours of (x, y, z); V(x,y,z,idx)
-// with idx the level-array index; z-neighbours come from the caller.
-template <bool UNI, typename VF>
-__device__ inline float nb_sum_xy(const Geo<UNI>& G, int x, int y, int z, long long i, VF V) {
-  float s = 0.f;
-  if (x > 0) s += G.gx(x - 1, y, z) * V(x - 1, y, z, i - 1);
-  if (x + 1 < G.nx) s += G.gx(x, y, z) * V(x + 1, y, z, i + 1);
-  if (y > 0) s += G.gy(x, y - 1, z) * V(x, y - 1, z, i - G.nx);
-  if (y + 1 < G.ny) s += G.gy(x, y, z) * V(x, y + 1, z, i + G.nx);
-  return s;
-}
-
 // LDS plane of one tile with a one-cell frame: (tx + 2) (256/tx + 2) values.
 constexpr int kPlaneMaxF = 400;
 
