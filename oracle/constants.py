@@ -41,6 +41,10 @@ class Params:
     K_phi: float = 1.4
     T_cycle: float = 3.74 * MIN_PER_DAY
     ode_substeps: int = 30      # V_c sub-steps of 1 min (the paper's VODE max step)
+    # time stepping of Eqs. (oxygen) and (chemo) inside one coupled step ------
+    pde_substeps: int = 1       # implicit substeps per coupled step (Algorithm 1's
+                                # 1-min PDE step is 30)
+    pde_theta: float = 1.0      # theta scheme: 1 = backward Euler, 1/2 = Crank-Nicolson
 
     @property
     def a_K(self):

@@ -9,6 +9,7 @@ One coupled step n -> n+1 (loop body of Algorithm 1, with the implicit Euler
 step dt of the cell-cycle update):
 
 1. plasma concentrations G_{i,0}(t^{n+1}) (intravascular module, closed form);
+   (steps 1-3 optionally in m theta-scheme substeps, see ``solve_fields``);
 2. oxygen, Eq. (oxygen) with s_K = 1, linearised as the paper does: the
    uptake phi_K K/(K1 + K) becomes phi_K K^{n+1}/(K1 + K^n):
        (1/dt + r_k w + phi_K chi_c/(K1 + K^n)) K^{n+1} - a_K Lap K^{n+1}
@@ -76,6 +77,40 @@ def drug_system(w, G_old, g0, p):
     return c, b
 
 
+def o2_substep_system(L, w, K_old, p, tau, theta):
+    """One theta-scheme substep of length tau of Eq. (oxygen), the uptake
+    linearised at the substep's old value as in the coupled step:
+        (1/tau + theta R) K' - theta a_K Lap K'
+            = (1/tau - (1 - theta) R) K + (1 - theta) a_K Lap K + r_k w K0,
+    R = r_k w + phi_K chi/(K1 + K) (the source r_k w K0 is constant in time).
+    theta = 1: backward Euler (with tau = dt exactly the coupled step's
+    system); theta = 1/2: Crank-Nicolson.  Returns (c, b) of the system with
+    coupling theta a_K."""
+    chi = (L != 0).astype(np.float64)
+    rw = p.r_k * w
+    up = p.phi_K * chi / (p.K1 + K_old)
+    c = 1.0 / tau + theta * rw + theta * up
+    b = K_old * (1.0 / tau - (1.0 - theta) * (rw + up)) + rw * p.K0
+    if theta < 1.0:
+        b = b + (1.0 - theta) * p.a_K * lattice.laplacian_apply(K_old)
+    return c, b
+
+
+def drug_substep_system(w, G_old, g_old, g_new, p, tau, theta):
+    """One theta-scheme substep of Eq. (chemo) with the plasma level at the
+    substep's ends:
+        (1/tau + theta R) G' - theta a_G Lap G'
+            = (1/tau - (1 - theta) R) G + (1 - theta) a_G Lap G
+              + kappa_G w (theta g_new + (1 - theta) g_old),
+    R = psi_G + kappa_G w.  Returns (c, b) of the system with coupling theta a_G."""
+    R = p.psi_G + p.kappa_G * w
+    c = 1.0 / tau + theta * R
+    b = G_old * (1.0 / tau - (1.0 - theta) * R) + p.kappa_G * w * (theta * g_new + (1.0 - theta) * g_old)
+    if theta < 1.0:
+        b = b + (1.0 - theta) * p.a_G * lattice.laplacian_apply(G_old)
+    return c, b
+
+
 def steady_o2_system(L, w, K_iter, p):
     chi = (L != 0).astype(np.float64)
     c = p.r_k * w + p.phi_K * chi / (p.K1 + K_iter)
@@ -112,16 +147,37 @@ def init_state(L, w, seed, p, method="cg"):
 
 
 def solve_fields(s, w, sched, p, method="cg"):
-    """Steps 1-3: returns (K^{n+1}, G1^{n+1}, G2^{n+1})."""
-    t1 = (s.step + 1) * p.dt_min
-    g0 = plasma_pair(t1, sched, p)
-    c, b = o2_system(s.L, w, s.K, p)
-    K = lattice.solve(c, p.a_K, b, x0=s.K, method=method)
-    c, b = drug_system(w, s.G1, g0[0], p)
-    G1 = lattice.solve(c, p.a_G, b, x0=s.G1, method=method)
-    c, b = drug_system(w, s.G2, g0[1], p)
-    G2 = lattice.solve(c, p.a_G, b, x0=s.G2, method=method)
-    return K, G1, G2
+    """Steps 1-3: returns (K^{n+1}, G1^{n+1}, G2^{n+1}).
+
+    With the defaults (one backward-Euler substep) this is one implicit solve
+    per field over the coupled step.  With ``p.pde_substeps = m`` the fields
+    advance by m substeps of dt/m (Algorithm 1's PDE step; m = 30 gives its
+    1-min step), each a theta-scheme solve (``p.pde_theta``: 1 backward
+    Euler, 1/2 Crank-Nicolson) with the plasma levels at the substep's ends
+    and the oxygen uptake linearised at the substep's start."""
+    m, theta = p.pde_substeps, p.pde_theta
+    if m == 1 and theta == 1.0:
+        t1 = (s.step + 1) * p.dt_min
+        g0 = plasma_pair(t1, sched, p)
+        c, b = o2_system(s.L, w, s.K, p)
+        K = lattice.solve(c, p.a_K, b, x0=s.K, method=method)
+        c, b = drug_system(w, s.G1, g0[0], p)
+        G1 = lattice.solve(c, p.a_G, b, x0=s.G1, method=method)
+        c, b = drug_system(w, s.G2, g0[1], p)
+        G2 = lattice.solve(c, p.a_G, b, x0=s.G2, method=method)
+        return K, G1, G2
+    tau = p.dt_min / m
+    K, G = s.K, [s.G1, s.G2]
+    for j in range(m):
+        t_old = s.step * p.dt_min + j * tau
+        g_old = plasma_pair(t_old, sched, p)
+        g_new = plasma_pair(t_old + tau, sched, p)
+        c, b = o2_substep_system(s.L, w, K, p, tau, theta)
+        K = lattice.solve(c, theta * p.a_K, b, x0=K, method=method)
+        for i in range(2):
+            c, b = drug_substep_system(w, G[i], g_old[i], g_new[i], p, tau, theta)
+            G[i] = lattice.solve(c, theta * p.a_G, b, x0=G[i], method=method)
+    return K, G[0], G[1]
 
 
 def step(s, w, sched, seed, p, method="cg"):
