@@ -108,6 +108,12 @@ typedef struct hca_params {
                               timing candidates at init (hca_tile_shape);
                               0: fixed heuristic from each lattice's size
                               (bit-identical alone or in any batch)           */
+  /* time stepping of the fields inside a coupled step (Algorithm 1 solves the
+     PDEs with a 1-min step, i.e. 30 substeps of the 30-min coupled step) */
+  int32_t pde_substeps;    /* m >= 1 implicit substeps of dt_min/m (1)          */
+  double pde_theta;        /* theta scheme in [1/2, 1]: 1 backward Euler (1),
+                              1/2 Crank-Nicolson; plasma levels at both ends
+                              of a substep, O2 uptake linearised at its start  */
 } hca_params;
 
 /* One replicate's inputs.  hca_init deep-copies every array; the caller keeps

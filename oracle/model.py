@@ -103,9 +103,9 @@ def drug_substep_system(w, G_old, g_old, g_new, p, tau, theta):
             = (1/tau - (1 - theta) R) G + (1 - theta) a_G Lap G
               + kappa_G w (theta g_new + (1 - theta) g_old),
     R = psi_G + kappa_G w.  Returns (c, b) of the system with coupling theta a_G."""
-    R = p.psi_G + p.kappa_G * w
-    c = 1.0 / tau + theta * R
-    b = G_old * (1.0 / tau - (1.0 - theta) * R) + p.kappa_G * w * (theta * g_new + (1.0 - theta) * g_old)
+    kw = p.kappa_G * w
+    c = 1.0 / tau + theta * p.psi_G + theta * kw
+    b = G_old * (1.0 / tau - (1.0 - theta) * (p.psi_G + kw)) + kw * (theta * g_new + (1.0 - theta) * g_old)
     if theta < 1.0:
         b = b + (1.0 - theta) * p.a_G * lattice.laplacian_apply(G_old)
     return c, b

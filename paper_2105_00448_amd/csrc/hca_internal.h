@@ -54,6 +54,9 @@ struct DevParams {
   int b_int[2];
   double k1, k1p, K_p53, k2, k2p, k2pp, J5, K_V, K_phi, T_cycle;
   int nsub;
+  // the field solves: nsub_pde theta-scheme substeps of tau = dt / nsub_pde
+  int nsub_pde;
+  double tau, inv_tau, theta;
 };
 
 // One replicate on the device, or (in the solver's tables) one linear system:
@@ -154,17 +157,20 @@ inline int grid_for(int n, int max_blocks) {
 
 // ---- launchers (defined in the .hip files) --------------------------------
 // setup / init / plasma kinetics (k_setup.hip)
+// Plasma levels at the ends of field substep j: g0[2 rep + drug] at the end,
+// g0[2 nreps + 2 rep + drug] at the start.
 void launch_plasma(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
-                   const double* dose_t, const double* dose_a, double* g0);
+                   int j, const double* dose_t, const double* dose_a, double* g0);
 void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
                      const double* vw, const double* K, double* c, double* b, int steady);
-void launch_setup_drug(hipStream_t s, const Work& w, const DevParams& p, int drug,
-                       const double* vw, const double* G, const double* g0, double* c, double* b);
-// All three systems of a coupled step at once: F = [K | G1 | G2] (3 x ntot),
+// All three systems of a field substep at once: F = [K | G1 | G2] (3 x ntot),
 // c and b of the same layout.
 void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
                        const uint8_t* L, const double* vw, const double* F, const double* g0,
                        double* c, double* b);
+// Crank-Nicolson-type substeps (theta < 1): b += (1 - theta) a Lap F per field.
+void launch_rhs_lap(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
+                    const double* F, double* b);
 void launch_init_cells(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
                        const double* K, double* P, double* Vc, double* phi);
 

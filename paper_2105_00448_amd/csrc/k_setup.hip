@@ -1,35 +1,50 @@
-// Plasma kinetics, coefficient / right-hand-side setup of the implicit-Euler
+// Plasma kinetics, coefficient / right-hand-side setup of the implicit
 // systems, and the cell-state initialisation of Algorithm 1.
 //
-// Every implicit-Euler update of Eqs. (oxygen) and (chemo) on the voxel
-// lattice is   c_i u_i - a (Lap u)_i = b_i   with a = D/h^2 and the
-// zero-flux 7-point Laplacian; these kernels produce c and b per voxel.
+// The fields advance over a coupled step dt in m substeps of tau = dt/m (one
+// by default; Algorithm 1's PDE step is 1 min), each a theta-scheme update of
+// Eqs. (oxygen) and (chemo): for u_t = -R u + a Lap u + S,
+//     (1/tau + theta R) u' - theta a Lap u'
+//         = (1/tau - (1 - theta) R) u + (1 - theta) a Lap u + theta S' + (1 - theta) S,
+// theta = 1 backward Euler, 1/2 Crank-Nicolson.  On the voxel lattice every
+// such update is  c_i u_i - a' (Lap u)_i = b_i  with the solver coupling
+// a' = theta a and the zero-flux 7-point Laplacian; these kernels produce c
+// and b per voxel.
 #include "dev_util.h"
 
 namespace hca {
 
-// G_{i,0}(t^{n+1}) of both drugs for every replicate: a_m G_ref e^{-k (t - t_m)}
+// G_{i,0}(t) of both drugs for every replicate: a_m G_ref e^{-k (t - t_m)}
 // for the latest bolus t_m <= t (reset at each dose), 0 before the first dose.
 // One-compartment linear elimination (Eq. intrachemo3; the fluorouracil model
 // in its linear regime).
-__global__ void k_plasma(int nreps, const RepDev* reps, DevParams p, const long long* d_step,
+__device__ inline double plasma_level(const RepDev& rp, const DevParams& p, const double* dose_t,
+                                      const double* dose_a, int i, double t) {
+  double g = 0.0;
+  double tm = -1.0;
+  for (int k = 0; k < rp.ndose[i]; ++k) {
+    const double td = dose_t[rp.dose_off + i * HCA_MAX_DOSES + k];
+    if (td <= t && td >= tm) {
+      tm = td;
+      g = dose_a[rp.dose_off + i * HCA_MAX_DOSES + k] * p.G_ref[i];
+    }
+  }
+  if (tm >= 0.0) g = g * exp(-p.k_pk[i] * (t - tm));
+  return g;
+}
+
+// Levels at the end (t^n + (j+1) tau; t^{n+1} for a single substep) and the
+// start (t^n + j tau) of field substep j.
+__global__ void k_plasma(int nreps, const RepDev* reps, DevParams p, const long long* d_step, int j,
                          const double* dose_t, const double* dose_a, double* g0) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nreps) return;
-  const double t = (double)(d_step[0] + 1) * p.dt;
+  const double t_old = (double)d_step[0] * p.dt + (double)j * p.tau;
+  const double t_new = p.nsub_pde == 1 ? (double)(d_step[0] + 1) * p.dt : t_old + p.tau;
   const RepDev rp = reps[r];
   for (int i = 0; i < 2; ++i) {
-    double g = 0.0;
-    double tm = -1.0;
-    for (int k = 0; k < rp.ndose[i]; ++k) {
-      const double td = dose_t[rp.dose_off + i * HCA_MAX_DOSES + k];
-      if (td <= t && td >= tm) {
-        tm = td;
-        g = dose_a[rp.dose_off + i * HCA_MAX_DOSES + k] * p.G_ref[i];
-      }
-    }
-    if (tm >= 0.0) g = g * exp(-p.k_pk[i] * (t - tm));
-    g0[2 * r + i] = g;
+    g0[2 * r + i] = plasma_level(rp, p, dose_t, dose_a, i, t_new);
+    g0[2 * nreps + 2 * r + i] = plasma_level(rp, p, dose_t, dose_a, i, t_old);
   }
 }
 
@@ -48,7 +63,8 @@ __device__ inline void for_each_voxel(const Work& w, F f) {
 // phi_K K/(K1 + K) becomes phi_K K^{n+1}/(K1 + K^n).  chi = [L != 0] marks the
 // cell delta functions, w weights the vessel sources.
 //   step:   c = 1/dt + r_k w + phi_K chi/(K1 + K^n),   b = K^n/dt + r_k w K0
-//   steady: c =        r_k w + phi_K chi/(K1 + K),     b =        r_k w K0
+//   steady: c =        r_k w + phi_K chi/(K1 + K),     b =        r_k w K0,
+//           both times theta (the solver's coupling is theta a_K)
 __global__ void __launch_bounds__(kBlock) k_setup_o2(Work w, DevParams p, const uint8_t* L,
                                                      const double* vw, const double* K,
                                                      double* c, double* b, int steady) {
@@ -58,8 +74,8 @@ __global__ void __launch_bounds__(kBlock) k_setup_o2(Work w, DevParams p, const 
     const double chi = L[g] != 0 ? 1.0 : 0.0;
     const double up = p.phi_K * chi / (p.K1 + k);
     if (steady) {
-      c[g] = p.r_k * wv + up;
-      b[g] = p.r_k * wv * p.K0;
+      c[g] = p.theta * (p.r_k * wv + up);
+      b[g] = p.theta * (p.r_k * wv * p.K0);
     } else {
       c[g] = p.inv_dt + p.r_k * wv + up;
       b[g] = k * p.inv_dt + p.r_k * wv * p.K0;
@@ -67,20 +83,15 @@ __global__ void __launch_bounds__(kBlock) k_setup_o2(Work w, DevParams p, const 
   });
 }
 
-// Drug i, Eq. (chemo): c = 1/dt + psi_G + kappa_G w,  b = G^n/dt + kappa_G w G_{i,0}.
-__global__ void __launch_bounds__(kBlock) k_setup_drug(Work w, DevParams p, int drug,
-                                                       const double* vw, const double* G,
-                                                       const double* g0, double* c, double* b) {
-  for_each_voxel(w, [&](int rep, const RepDev&, long long g) {
-    const double wv = vw[g];
-    const double gp = g0[2 * rep + drug];
-    c[g] = p.inv_dt + p.psi_G + p.kappa_G * wv;
-    b[g] = G[g] * p.inv_dt + p.kappa_G * wv * gp;
-  });
-}
-
-// The three systems of one coupled step (oxygen and both drugs, see above)
-// in one pass; F = [K | G1 | G2], c and b in the same 3 x ntot layout.
+// The three systems of one field substep in one pass (the pointwise terms of
+// the theta scheme above; the explicit Laplacian of a theta < 1 substep is
+// added by k_rhs_lap); F = [K | G1 | G2], c and b in the same 3 x ntot layout.
+//   oxygen: R = r_k w + phi_K chi/(K1 + K) (uptake linearised at the substep's
+//           start), S = r_k w K0 constant;
+//   drugs:  R = psi_G + kappa_G w, S = kappa_G w g0(t) with the plasma level
+//           at the substep's end (weight theta) and start (1 - theta).
+// With one backward-Euler substep these are the coupled step's systems
+// c = 1/dt + R, b = u/dt + S.
 __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long long ntot,
                                                        const uint8_t* __restrict__ L,
                                                        const double* __restrict__ vw,
@@ -88,17 +99,51 @@ __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long
                                                        const double* __restrict__ g0,
                                                        double* __restrict__ c,
                                                        double* __restrict__ b) {
+  const double th = p.theta, th1 = 1.0 - p.theta;
   for_each_voxel(w, [&](int rep, const RepDev&, long long g) {
     const double wv = vw[g];
     const double k = F[g];
     const double chi = L[g] != 0 ? 1.0 : 0.0;
-    c[g] = p.inv_dt + p.r_k * wv + p.phi_K * chi / (p.K1 + k);
-    b[g] = k * p.inv_dt + p.r_k * wv * p.K0;
-    const double cg = p.inv_dt + p.psi_G + p.kappa_G * wv;
+    const double rw = p.r_k * wv;
+    const double up = p.phi_K * chi / (p.K1 + k);
+    c[g] = p.inv_tau + th * rw + th * up;
+    b[g] = k * (p.inv_tau - th1 * (rw + up)) + rw * p.K0;
+    const double kw = p.kappa_G * wv;
+    const double cg = p.inv_tau + th * p.psi_G + th * kw;
+    const double rg = p.psi_G + kw;
     for (int i = 0; i < 2; ++i) {
       const long long j = g + (i + 1) * ntot;
       c[j] = cg;
-      b[j] = F[j] * p.inv_dt + p.kappa_G * wv * g0[2 * rep + i];
+      b[j] = F[j] * (p.inv_tau - th1 * rg) + kw * (th * g0[2 * rep + i] + th1 * g0[2 * w.nreps + 2 * rep + i]);
+    }
+  });
+}
+
+// b += (1 - theta) a Lap F for the three fields (theta < 1): the explicit half
+// of a Crank-Nicolson-type substep, Lap the zero-flux 7-point Laplacian
+// (neighbours in the order -x, +x, -y, +y, -z, +z).
+__global__ void __launch_bounds__(kBlock) k_rhs_lap(Work w, DevParams p, long long ntot,
+                                                    const double* __restrict__ F,
+                                                    double* __restrict__ b) {
+  const double sK = (1.0 - p.theta) * p.aK, sG = (1.0 - p.theta) * p.aG;
+  for_each_voxel(w, [&](int, const RepDev& rp, long long g) {
+    const long long i = g - rp.off;
+    const int x = (int)(i % rp.nx);
+    const long long q = i / rp.nx;
+    const int y = (int)(q % rp.ny);
+    const int z = (int)(q / rp.ny);
+    const long long sy = rp.nx, sz = (long long)rp.nx * rp.ny;
+    for (int f = 0; f < 3; ++f) {
+      const double* u = F + (long long)f * ntot;
+      const double uc = u[g];
+      double lap = 0.0;
+      if (x > 0) lap += u[g - 1] - uc;
+      if (x + 1 < rp.nx) lap += u[g + 1] - uc;
+      if (y > 0) lap += u[g - sy] - uc;
+      if (y + 1 < rp.ny) lap += u[g + sy] - uc;
+      if (z > 0) lap += u[g - sz] - uc;
+      if (z + 1 < rp.nz) lap += u[g + sz] - uc;
+      b[g + (long long)f * ntot] += (f == 0 ? sK : sG) * lap;
     }
   });
 }
@@ -134,10 +179,9 @@ __global__ void __launch_bounds__(kBlock) k_init_cells(Work w, DevParams p, cons
 }
 
 void launch_plasma(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
-                   const double* dose_t, const double* dose_a, double* g0) {
+                   int j, const double* dose_t, const double* dose_a, double* g0) {
   const int nb = (w.nreps + 63) / 64;
-  hca_launch(k_plasma, dim3(nb), dim3(64), 0, s, w.nreps, w.reps, p, d_step, dose_t,
-                     dose_a, g0);
+  hca_launch(k_plasma, dim3(nb), dim3(64), 0, s, w.nreps, w.reps, p, d_step, j, dose_t, dose_a, g0);
 }
 
 void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
@@ -145,17 +189,16 @@ void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uin
   hca_launch(k_setup_o2, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, vw, K, c, b, steady);
 }
 
-void launch_setup_drug(hipStream_t s, const Work& w, const DevParams& p, int drug,
-                       const double* vw, const double* G, const double* g0, double* c,
-                       double* b) {
-  hca_launch(k_setup_drug, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, drug, vw, G, g0, c, b);
-}
-
 void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
                        const uint8_t* L, const double* vw, const double* F, const double* g0,
                        double* c, double* b) {
   hca_launch(k_setup_step, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot, L, vw, F, g0, c,
                      b);
+}
+
+void launch_rhs_lap(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
+                    const double* F, double* b) {
+  hca_launch(k_rhs_lap, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot, F, b);
 }
 
 void launch_init_cells(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,

@@ -321,6 +321,10 @@ DevParams make_dev_params(const hca_params& p) {
   DevParams d{};
   d.dt = p.dt_min;
   d.inv_dt = 1.0 / p.dt_min;
+  d.nsub_pde = p.pde_substeps;
+  d.tau = p.dt_min / p.pde_substeps;
+  d.inv_tau = 1.0 / d.tau;
+  d.theta = p.pde_theta;
   d.aK = p.D_K / (p.h_um * p.h_um);
   d.aG = p.D_G / (p.h_um * p.h_um);
   d.r_k = p.r_k;
@@ -467,14 +471,16 @@ hca_status run_phases(hca_ctx* c, unsigned mask) {
   const Work& wk = c->work;
   hipStream_t s = c->stream;
   const unsigned fmask = ((mask & HCA_PH_O2) ? 1u : 0u) | ((mask & HCA_PH_DRUGS) ? 6u : 0u);
-  if (fmask) {
+  // the field solves: pde_substeps theta-scheme substeps (one by default)
+  for (int j = 0; fmask && j < c->dp.nsub_pde; ++j) {
     {
       ProfScope ps(c, KC_PLASMA, kTagState);
-      launch_plasma(s, wk, c->dp, c->d_step, c->dose_t, c->dose_a, c->g0);
+      launch_plasma(s, wk, c->dp, c->d_step, j, c->dose_t, c->dose_a, c->g0);
     }
     {
       ProfScope ps(c, KC_SETUP, kTagState);
       launch_setup_step(s, wk, c->dp, c->ntot, c->L, c->w, c->F, c->g0, c->c, c->b);
+      if (c->dp.theta < 1.0) launch_rhs_lap(s, wk, c->dp, c->ntot, c->F, c->b);
     }
     hca_status st = solve(c, c->sys3, c->mg3, fmask, c->prm.cg_rtol, c->prm.cg_maxit, 0);
     if (st != HCA_OK) return st;
@@ -606,6 +612,10 @@ hca_status validate_params(const hca_params* p, std::string& msg) {
       p->profile > KC_COUNT + 1 || (p->graphs != 0 && p->graphs != 1) ||
       (p->autotune != 0 && p->autotune != 1)) {
     msg = "integer parameter out of range";
+    return HCA_E_INVALID;
+  }
+  if (p->pde_substeps < 1 || p->pde_substeps > 1000 || !(p->pde_theta >= 0.5 && p->pde_theta <= 1.0)) {
+    msg = "pde_substeps in [1, 1000] and pde_theta in [0.5, 1] required";
     return HCA_E_INVALID;
   }
   if (p->mg_smooth != 2) {
@@ -878,7 +888,7 @@ hca_status build_tables(hca_ctx* c, const hca_replicate* in) {
       for (int r = 0; r < R; ++r) {
         RepDev d = lattice_entry(c->reps[r], (long long)f * c->ntot + c->reps[r].off, f * R + r,
                                  flat, tiles);
-        d.a = f == 0 ? c->dp.aK : c->dp.aG;
+        d.a = (f == 0 ? c->dp.aK : c->dp.aG) * c->dp.theta;   // the theta scheme's implicit coupling
         sd.push_back(d);
         c->sys_n.push_back(c->reps[r].n);
       }
@@ -949,7 +959,7 @@ hca_status alloc_all(hca_ctx* c) {
   HIPCHK(c, dalloc(&c->sb.ndone, 1));
   HIPCHK(c, dalloc(&c->dose_t, (size_t)c->nreps * 2 * HCA_MAX_DOSES));
   HIPCHK(c, dalloc(&c->dose_a, (size_t)c->nreps * 2 * HCA_MAX_DOSES));
-  HIPCHK(c, dalloc(&c->g0, (size_t)c->nreps * 2));
+  HIPCHK(c, dalloc(&c->g0, (size_t)c->nreps * 4));   // levels at both ends of a field substep
   HIPCHK(c, dalloc(&c->d_step, 1));
   HIPCHK(c, dalloc(&c->d_cnt, c->nreps));
   HIPCHK(c, dalloc(&c->d_cpart, (size_t)c->work.nflat * kCounterSlots));
@@ -1281,6 +1291,8 @@ hca_status hca_default_params(hca_params* out) {
   out->profile = 0;
   out->graphs = 1;
   out->autotune = 0;
+  out->pde_substeps = 1;
+  out->pde_theta = 1.0;
   return HCA_OK;
 }
 

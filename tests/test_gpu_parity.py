@@ -95,6 +95,31 @@ def test_solves_match_oracle_exact_solution(case32, solver_kw):
         assert all(i > 0 for i in it)
 
 
+@pytest.mark.parametrize("m,theta", [(3, 1.0), (3, 0.5), (2, 0.7)], ids=["be3", "cn3", "theta07x2"])
+@pytest.mark.parametrize("precond", [0, 1], ids=["jacobi", "multigrid"])
+def test_field_substeps_match_oracle(case32, m, theta, precond):
+    """The fields advanced in m theta-scheme substeps per coupled step (doses
+    on and between substep boundaries), against the oracle over two steps;
+    the steady-oxygen initialisation runs with the theta-scaled system."""
+    print(f"\n[substeps] m {m} theta {theta} precond {precond}", flush=True)
+    tis, _, s0 = case32
+    sched = synth.DoseSchedule(times=((10.0, 45.0), (20.0,)), amts=((1.0, 0.5), (0.8,)))
+    osched = oracle_sched(sched)
+    OPm = OP.with_(pde_substeps=m, pde_theta=theta)
+    with make_sim([(tis, sched)], precond=precond, pde_substeps=m, pde_theta=theta) as sim:
+        assert relerr(sim.field("K"), s0.K) <= FIELD_TOL
+        s = s0
+        for n in range(2):
+            push_state(sim, s)
+            sim.run_phases(hca.PH_O2 | hca.PH_DRUGS)
+            K, G1, G2 = om.solve_fields(s, tis.w, osched, OPm)
+            for name, ref in (("K", K), ("G1", G1), ("G2", G2)):
+                assert relerr(sim.field(name), ref) <= FIELD_TOL, (n, name)
+            s, _ = om.step(s, tis.w, osched, tis.seed, OPm)
+        it = sim.stats()["cg_iters"]
+        assert all(i > 0 for i in it)
+
+
 def test_ode_matches_oracle(case32):
     tis, sched, s0 = case32
     rng = np.random.default_rng(2)
