@@ -28,7 +28,11 @@ same metric beside the plain one:
              stepped plain and with the surrogate ODE phase (margin 1e-3), and
              the per-step error and decision-flip rate of the surrogate against
              the plain integrator on identical inputs;
-  batched    the batched64 ensemble.
+  batched    the batched64 ensemble;
+  substeps   the plain 128^3 workload with the paper's field time step: 30
+             implicit 1-min substeps per 30-min coupled step, backward Euler
+             and Crank-Nicolson (10 coupled steps each; off by default, add
+             with --legs).
 """
 import argparse
 import json
@@ -283,6 +287,25 @@ def batched_leg(stream, steps=None):
             "ms_per_step": el / steps * 1e3, "tile_shapes_txtytz": dist}
 
 
+def substeps_leg(stream, steps=10, m=30):
+    """The 128^3 workload with m field substeps per coupled step (backward
+    Euler and Crank-Nicolson); value counts coupled steps, as the plain
+    line does."""
+    from paper_2105_00448_amd import hca
+    reps, cfg, _ = make_workload("plain128")
+    nvox = sum(r[0].size for r in reps)
+    out = {"workload": f"plain 128^3 workload with {m} implicit field substeps of {30.0 / m:g} min per "
+                       f"30-min coupled step, {steps} coupled steps",
+           "unit": "voxel-steps/s"}
+    for name, theta in (("backward_euler", 1.0), ("crank_nicolson", 0.5)):
+        print(f"[bench:substeps] {name}, {m} substeps, {steps} steps", file=sys.stderr, flush=True)
+        el, st, _ = timed_run(reps, hca.default_params(pde_substeps=m, pde_theta=theta), steps, stream)
+        out[name] = {"value": nvox * steps / el, "ms_per_step": el / steps * 1e3,
+                     "ms_per_substep": el / steps / m * 1e3,
+                     "cg_iters_last_substep": list(st[0]["cg_iters"])}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,7 +323,7 @@ def main():
                     help="timed repeats from a fresh context; value = median")
     ap.add_argument("--no-legs", action="store_true", help="plain workload only")
     ap.add_argument("--legs", default="surrogate,batched",
-                    help="comma-separated further legs: surrogate, batched")
+                    help="comma-separated further legs: surrogate, batched, substeps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -439,6 +462,8 @@ def main():
         rec["surrogate"] = surrogate_leg(stream, args.sur_steps, args.train_steps)
     if "batched" in legs:
         rec["batched"] = batched_leg(stream)
+    if "substeps" in legs:
+        rec["substeps"] = substeps_leg(stream)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline()
