@@ -45,6 +45,8 @@ class Params:
     pde_substeps: int = 1       # implicit substeps per coupled step (Algorithm 1's
                                 # 1-min PDE step is 30)
     pde_theta: float = 1.0      # theta scheme: 1 = backward Euler, 1/2 = Crank-Nicolson
+    o2_newton: int = 0          # Newton iterations on the nonlinear oxygen uptake after
+                                # the linearised solve (0: the paper's linearisation)
 
     @property
     def a_K(self):

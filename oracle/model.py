@@ -111,6 +111,22 @@ def drug_substep_system(w, G_old, g_old, g_new, p, tau, theta):
     return c, b
 
 
+def o2_newton_system(L, w, K_it, b_lin, p, tau, theta):
+    """One Newton step on the implicit oxygen update with the uptake kept
+    nonlinear, phi_K K'/(K1 + K') at the new value:
+        (1/tau + theta r_k w) K' + theta phi_K chi K'/(K1 + K') - theta a_K Lap K' = b_lin,
+    b_lin the linearised substep's right-hand side (its explicit part uses the
+    old value in the uptake exactly as the nonlinear form does).  Linearised
+    at the iterate K_it the step solves
+        (1/tau + theta r_k w + theta phi_K chi K1/(K1 + K_it)^2) K'
+            - theta a_K Lap K' = b_lin - theta phi_K chi K_it^2/(K1 + K_it)^2."""
+    chi = (L != 0).astype(np.float64)
+    d = p.K1 + K_it
+    c = 1.0 / tau + theta * (p.r_k * w) + theta * (p.phi_K * chi * p.K1 / (d * d))
+    b = b_lin - theta * (p.phi_K * chi * K_it * K_it / (d * d))
+    return c, b
+
+
 def steady_o2_system(L, w, K_iter, p):
     chi = (L != 0).astype(np.float64)
     c = p.r_k * w + p.phi_K * chi / (p.K1 + K_iter)
@@ -154,9 +170,11 @@ def solve_fields(s, w, sched, p, method="cg"):
     advance by m substeps of dt/m (Algorithm 1's PDE step; m = 30 gives its
     1-min step), each a theta-scheme solve (``p.pde_theta``: 1 backward
     Euler, 1/2 Crank-Nicolson) with the plasma levels at the substep's ends
-    and the oxygen uptake linearised at the substep's start."""
+    and the oxygen uptake linearised at the substep's start; with
+    ``p.o2_newton = k`` the oxygen update then takes k Newton steps on the
+    uptake at the new value (the nonlinear form the paper linearises)."""
     m, theta = p.pde_substeps, p.pde_theta
-    if m == 1 and theta == 1.0:
+    if m == 1 and theta == 1.0 and p.o2_newton == 0:
         t1 = (s.step + 1) * p.dt_min
         g0 = plasma_pair(t1, sched, p)
         c, b = o2_system(s.L, w, s.K, p)
@@ -174,6 +192,9 @@ def solve_fields(s, w, sched, p, method="cg"):
         g_new = plasma_pair(t_old + tau, sched, p)
         c, b = o2_substep_system(s.L, w, K, p, tau, theta)
         K = lattice.solve(c, theta * p.a_K, b, x0=K, method=method)
+        for _ in range(p.o2_newton):   # the uptake at the new value (Newton)
+            cn, bn = o2_newton_system(s.L, w, K, b, p, tau, theta)
+            K = lattice.solve(cn, theta * p.a_K, bn, x0=K, method=method)
         for i in range(2):
             c, b = drug_substep_system(w, G[i], g_old[i], g_new[i], p, tau, theta)
             G[i] = lattice.solve(c, theta * p.a_G, b, x0=G[i], method=method)

@@ -137,3 +137,40 @@ def test_plasma_levels_enter_at_the_substep_ends(theta):
             x = ((1 / tau - (1 - theta) * R) * x + p.kappa_G * (theta * g[j + 1] + (1 - theta) * g[j])) \
                 / (1 / tau + theta * R)
         np.testing.assert_allclose(G, x, rtol=1e-12)
+
+
+@pytest.fixture(scope="module")
+def small_tissue():
+    from paper_2105_00448_amd import synth
+    return synth.make_tissue(10, 4, seed=5)
+
+
+def nonlinear_o2_residual(L, w, K_old, K_new, p, tau, theta):
+    """Residual of the implicit oxygen update with the uptake at the new value,
+    written out term by term (theta scheme, explicit uptake at the old value)."""
+    chi = (L != 0).astype(float)
+    lhs = (K_new / tau + theta * p.r_k * w * K_new + theta * p.phi_K * chi * K_new / (p.K1 + K_new)
+           - theta * p.a_K * lattice.laplacian_apply(K_new))
+    rhs = (K_old / tau - (1 - theta) * (p.r_k * w * K_old + p.phi_K * chi * K_old / (p.K1 + K_old))
+           + (1 - theta) * p.a_K * lattice.laplacian_apply(K_old) + p.r_k * w * p.K0)
+    return (lhs - rhs) / np.abs(rhs).max()
+
+
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+def test_newton_oxygen_solves_the_nonlinear_update(small_tissue, theta):
+    """Newton steps on the uptake drive the residual of the nonlinear implicit
+    update to rounding, converging quadratically; the linearised update (no
+    Newton step) leaves a residual of the size of the linearisation gap."""
+    t = small_tissue
+    p0 = P.with_(pde_theta=theta)
+    s = model.init_state(t.cell, t.w, 1, p0, method="lu")
+    s.K *= 0.8   # away from the steady state, so the update moves K
+    res = []
+    for k in range(4):
+        p = p0.with_(o2_newton=k)
+        K, _, _ = model.solve_fields(s, t.w, model.Schedule(), p, method="lu")
+        res.append(np.abs(nonlinear_o2_residual(t.cell, t.w, s.K, K, p, p.dt_min, theta)).max())
+    assert res[0] > 1e-6                    # the linearisation gap is visible
+    assert res[1] < 100 * res[0] ** 2       # quadratic convergence ...
+    assert res[2] < 100 * res[1] ** 2
+    assert res[3] < 1e-13                   # ... down to rounding
