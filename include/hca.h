@@ -114,6 +114,10 @@ typedef struct hca_params {
   double pde_theta;        /* theta scheme in [1/2, 1]: 1 backward Euler (1),
                               1/2 Crank-Nicolson; plasma levels at both ends
                               of a substep, O2 uptake linearised at its start  */
+  int32_t o2_newton;       /* 0: the paper's linearised O2 uptake (0); k > 0:
+                              then k Newton steps per substep on the uptake
+                              phi_K K/(K1 + K) at the new value (each one more
+                              O2 solve), 0 <= k <= 20                           */
 } hca_params;
 
 /* One replicate's inputs.  hca_init deep-copies every array; the caller keeps

@@ -168,6 +168,12 @@ void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uin
 void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
                        const uint8_t* L, const double* vw, const double* F, const double* g0,
                        double* c, double* b);
+// Newton step on the oxygen uptake at the new value: c, b of the oxygen
+// systems (the first ntot entries) from the iterate K and the linearised
+// substep's right-hand side b_lin.
+void launch_setup_o2_newton(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
+                            const double* vw, const double* K, const double* b_lin, double* c,
+                            double* b);
 // Crank-Nicolson-type substeps (theta < 1): b += (1 - theta) a Lap F per field.
 void launch_rhs_lap(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
                     const double* F, double* b);

@@ -119,6 +119,27 @@ __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long
   });
 }
 
+// Newton step on the implicit oxygen update with the uptake at the new value,
+//   (1/tau + theta r_k w) K' + theta phi_K chi K'/(K1 + K') - theta a_K Lap K' = b_lin,
+// linearised at the iterate K:
+//   c = 1/tau + theta r_k w + theta phi_K chi K1/(K1 + K)^2,
+//   b = b_lin - theta phi_K chi K^2/(K1 + K)^2.
+__global__ void __launch_bounds__(kBlock) k_setup_o2_newton(Work w, DevParams p,
+                                                            const uint8_t* __restrict__ L,
+                                                            const double* __restrict__ vw,
+                                                            const double* __restrict__ K,
+                                                            const double* __restrict__ b_lin,
+                                                            double* __restrict__ c,
+                                                            double* __restrict__ b) {
+  for_each_voxel(w, [&](int, const RepDev&, long long g) {
+    const double k = K[g];
+    const double chi = L[g] != 0 ? 1.0 : 0.0;
+    const double d = p.K1 + k;
+    c[g] = p.inv_tau + p.theta * (p.r_k * vw[g]) + p.theta * (p.phi_K * chi * p.K1 / (d * d));
+    b[g] = b_lin[g] - p.theta * (p.phi_K * chi * k * k / (d * d));
+  });
+}
+
 // b += (1 - theta) a Lap F for the three fields (theta < 1): the explicit half
 // of a Crank-Nicolson-type substep, Lap the zero-flux 7-point Laplacian
 // (neighbours in the order -x, +x, -y, +y, -z, +z).
@@ -194,6 +215,13 @@ void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long lo
                        double* c, double* b) {
   hca_launch(k_setup_step, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot, L, vw, F, g0, c,
                      b);
+}
+
+void launch_setup_o2_newton(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
+                            const double* vw, const double* K, const double* b_lin, double* c,
+                            double* b) {
+  hca_launch(k_setup_o2_newton, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, vw, K, b_lin,
+             c, b);
 }
 
 void launch_rhs_lap(hipStream_t s, const Work& w, const DevParams& p, long long ntot,

@@ -113,6 +113,7 @@ struct hca_ctx {
   MgBufs mg3{}, mg1{};                          // all systems / oxygen systems only
   std::vector<void*> mg_mem;
   double *dose_t = nullptr, *dose_a = nullptr, *g0 = nullptr;
+  double* b_o2lin = nullptr;                     // o2_newton: the linearised O2 right-hand side
   long long* d_step = nullptr;
   // replicate tables (state kernels)
   RepDev* d_reps = nullptr;
@@ -482,8 +483,20 @@ hca_status run_phases(hca_ctx* c, unsigned mask) {
       launch_setup_step(s, wk, c->dp, c->ntot, c->L, c->w, c->F, c->g0, c->c, c->b);
       if (c->dp.theta < 1.0) launch_rhs_lap(s, wk, c->dp, c->ntot, c->F, c->b);
     }
+    const bool newton = c->prm.o2_newton > 0 && (fmask & 1u);
+    if (newton)
+      HIPCHK(c, hipMemcpyAsync(c->b_o2lin, c->b, sizeof(double) * (size_t)c->ntot, hipMemcpyDeviceToDevice, s));
     hca_status st = solve(c, c->sys3, c->mg3, fmask, c->prm.cg_rtol, c->prm.cg_maxit, 0);
     if (st != HCA_OK) return st;
+    // Newton steps on the oxygen uptake at the new value, from the linearised solution
+    for (int k = 0; newton && k < c->prm.o2_newton; ++k) {
+      {
+        ProfScope ps(c, KC_SETUP, kTagState);
+        launch_setup_o2_newton(s, wk, c->dp, c->L, c->w, c->K, c->b_o2lin, c->c, c->b);
+      }
+      st = solve(c, c->sys1, c->mg1, 1u, c->prm.cg_rtol, c->prm.cg_maxit, 1);
+      if (st != HCA_OK) return st;
+    }
   }
   if (mask & HCA_PH_ODE) {
     if (c->sur_on) {
@@ -614,8 +627,9 @@ hca_status validate_params(const hca_params* p, std::string& msg) {
     msg = "integer parameter out of range";
     return HCA_E_INVALID;
   }
-  if (p->pde_substeps < 1 || p->pde_substeps > 1000 || !(p->pde_theta >= 0.5 && p->pde_theta <= 1.0)) {
-    msg = "pde_substeps in [1, 1000] and pde_theta in [0.5, 1] required";
+  if (p->pde_substeps < 1 || p->pde_substeps > 1000 || !(p->pde_theta >= 0.5 && p->pde_theta <= 1.0) ||
+      p->o2_newton < 0 || p->o2_newton > 20) {
+    msg = "pde_substeps in [1, 1000], pde_theta in [0.5, 1] and o2_newton in [0, 20] required";
     return HCA_E_INVALID;
   }
   if (p->mg_smooth != 2) {
@@ -960,6 +974,7 @@ hca_status alloc_all(hca_ctx* c) {
   HIPCHK(c, dalloc(&c->dose_t, (size_t)c->nreps * 2 * HCA_MAX_DOSES));
   HIPCHK(c, dalloc(&c->dose_a, (size_t)c->nreps * 2 * HCA_MAX_DOSES));
   HIPCHK(c, dalloc(&c->g0, (size_t)c->nreps * 4));   // levels at both ends of a field substep
+  if (c->prm.o2_newton > 0 && (st = big(&c->b_o2lin, (size_t)c->ntot)) != HCA_OK) return st;
   HIPCHK(c, dalloc(&c->d_step, 1));
   HIPCHK(c, dalloc(&c->d_cnt, c->nreps));
   HIPCHK(c, dalloc(&c->d_cpart, (size_t)c->work.nflat * kCounterSlots));
@@ -1210,7 +1225,7 @@ hca_status steady_oxygen(hca_ctx* c) {
 void free_all(hca_ctx* c) {
   void* bufs[] = {c->L, c->code, c->win, c->w, c->P, c->Vc, c->phi, c->F, c->c, c->b,
                   c->sb.r, c->sb.z, (void*)c->sb.z32, (void*)c->sb.r32, c->sb.p0, c->sb.p1, c->sb.q, c->sb.dinv, c->sb.partial,
-                  c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->d_step,
+                  c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->b_o2lin, c->d_step,
                   c->d_reps, c->d_flat, c->d_tiles, c->d_sys, c->d_sflat, c->d_stiles, c->d_cnt, (void*)c->d_cpart,
                   (void*)c->d_fields, c->d_bad, c->d_theta, (void*)c->d_pack, (void*)c->d_gelu, c->before,
                   c->item_cnt, c->item_off};
@@ -1293,6 +1308,7 @@ hca_status hca_default_params(hca_params* out) {
   out->autotune = 0;
   out->pde_substeps = 1;
   out->pde_theta = 1.0;
+  out->o2_newton = 0;
   return HCA_OK;
 }
 

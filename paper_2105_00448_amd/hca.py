@@ -39,7 +39,7 @@ class Params(C.Structure):
         ("mg_smooth", C.c_int32), ("mg_coarse_max", C.c_int32),
         ("init_rtol", C.c_double), ("init_maxit", C.c_int32), ("profile", C.c_int32),
         ("graphs", C.c_int32), ("autotune", C.c_int32),
-        ("pde_substeps", C.c_int32), ("pde_theta", C.c_double),
+        ("pde_substeps", C.c_int32), ("pde_theta", C.c_double), ("o2_newton", C.c_int32),
     ]
 
 

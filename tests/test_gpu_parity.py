@@ -120,6 +120,25 @@ def test_field_substeps_match_oracle(case32, m, theta, precond):
         assert all(i > 0 for i in it)
 
 
+@pytest.mark.parametrize("m,theta,newton", [(1, 1.0, 3), (3, 0.5, 2)], ids=["be1-newton3", "cn3-newton2"])
+def test_newton_oxygen_matches_oracle(case32, m, theta, newton):
+    """Newton steps on the oxygen uptake at the new value after each
+    linearised substep, against the oracle's, over two steps."""
+    print(f"\n[newton] m {m} theta {theta} newton {newton}", flush=True)
+    tis, sched, s0 = case32
+    osched = oracle_sched(sched)
+    OPn = OP.with_(pde_substeps=m, pde_theta=theta, o2_newton=newton)
+    with make_sim([(tis, sched)], pde_substeps=m, pde_theta=theta, o2_newton=newton) as sim:
+        s = s0
+        for n in range(2):
+            push_state(sim, s)
+            sim.run_phases(hca.PH_O2 | hca.PH_DRUGS)
+            K, G1, G2 = om.solve_fields(s, tis.w, osched, OPn)
+            for name, ref in (("K", K), ("G1", G1), ("G2", G2)):
+                assert relerr(sim.field(name), ref) <= FIELD_TOL, (n, name)
+            s, _ = om.step(s, tis.w, osched, tis.seed, OPn)
+
+
 def test_ode_matches_oracle(case32):
     tis, sched, s0 = case32
     rng = np.random.default_rng(2)
