@@ -32,7 +32,11 @@ same metric beside the plain one:
   substeps   the plain 128^3 workload with the paper's field time step: 30
              implicit 1-min substeps per 30-min coupled step, backward Euler
              and Crank-Nicolson (10 coupled steps each; off by default, add
-             with --legs).
+             with --legs);
+  newton     the plain 128^3 workload with 3 Newton steps on the nonlinear
+             oxygen uptake after each linearised solve: step time, and the
+             linearisation gap max|K_newton - K_linearised| / max K at matched
+             inputs over 5 steps (off by default, add with --legs).
 """
 import argparse
 import json
@@ -306,6 +310,49 @@ def substeps_leg(stream, steps=10, m=30):
     return out
 
 
+def newton_leg(stream, steps=20, compare=5, newton=3):
+    """The plain workload with `newton` Newton steps on the oxygen uptake:
+    its step time beside the linearised one, and the gap between the two
+    oxygen fields computed from the same state."""
+    from paper_2105_00448_amd import hca
+    reps, cfg, _ = make_workload("plain128")
+    nvox = sum(r[0].size for r in reps)
+    print(f"[bench:newton] {newton} Newton steps, {steps} steps", file=sys.stderr, flush=True)
+    el_n, st_n, _ = timed_run(reps, hca.default_params(o2_newton=newton), steps, stream)
+    el_l, _, _ = timed_run(reps, hca.default_params(), steps, stream)
+    names = ("L", "K", "G1", "G2", "P", "Vc", "phi")
+
+    def gaps_at_matched_inputs(m, n_steps):
+        """(max-norm, 2-norm) relative gaps of K per step, m field substeps."""
+        out = []
+        kw = dict(pde_substeps=m)
+        with hca.Simulation(reps, hca.default_params(**kw), stream=stream) as lin, \
+                hca.Simulation(reps, hca.default_params(o2_newton=newton, **kw), stream=stream) as nwt:
+            for k in range(n_steps):
+                state = {n: lin.field(n) for n in names}
+                lin.step(1)
+                for n in names:
+                    nwt.set_field(n, state[n])
+                nwt.set_step(k)
+                nwt.run_phases(hca.PH_O2 | hca.PH_DRUGS)
+                Kl, Kn = lin.field("K"), nwt.field("K")
+                out.append((float(np.abs(Kn - Kl).max() / np.abs(Kl).max()),
+                            float(np.linalg.norm(Kn - Kl) / np.linalg.norm(Kl))))
+        return out
+    g30 = gaps_at_matched_inputs(1, compare)
+    g1 = gaps_at_matched_inputs(30, 2)
+    return {"workload": f"plain 128^3 workload, oxygen uptake at the new value by {newton} Newton steps "
+                        f"after the linearised solve, {steps} steps",
+            "unit": "voxel-steps/s", "value": nvox * steps / el_n,
+            "ms_per_step": el_n / steps * 1e3, "ms_per_step_linearised": el_l / steps * 1e3,
+            "cg_iters_last_step": list(st_n[0]["cg_iters"]),
+            "linearisation_gap_30min_step": {"max_rel": max(g[0] for g in g30),
+                                             "l2_rel": max(g[1] for g in g30), "per_step": g30},
+            "linearisation_gap_1min_substeps": {"max_rel": max(g[0] for g in g1),
+                                                "l2_rel": max(g[1] for g in g1), "per_step": g1},
+            "paper_claim_gap": 3e-4}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -323,7 +370,7 @@ def main():
                     help="timed repeats from a fresh context; value = median")
     ap.add_argument("--no-legs", action="store_true", help="plain workload only")
     ap.add_argument("--legs", default="surrogate,batched",
-                    help="comma-separated further legs: surrogate, batched, substeps")
+                    help="comma-separated further legs: surrogate, batched, substeps, newton")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -464,6 +511,8 @@ def main():
         rec["batched"] = batched_leg(stream)
     if "substeps" in legs:
         rec["substeps"] = substeps_leg(stream)
+    if "newton" in legs:
+        rec["newton"] = newton_leg(stream)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline()
