@@ -36,7 +36,11 @@ same metric beside the plain one:
   newton     the plain 128^3 workload with 3 Newton steps on the nonlinear
              oxygen uptake after each linearised solve: step time, and the
              linearisation gap max|K_newton - K_linearised| / max K at matched
-             inputs over 5 steps (off by default, add with --legs).
+             inputs over 5 steps (off by default, add with --legs);
+  paper2d    the paper's solver-performance setting as synthetic input: a 2-D
+             1 mm^2 slice of 100 x 100 voxels of 10 um, cell and vascular
+             densities 0.4 and 0.12, 30 Crank-Nicolson 1-min field substeps
+             per 30-min update; one slice and a batch of 64 (off by default).
 """
 import argparse
 import json
@@ -353,6 +357,25 @@ def newton_leg(stream, steps=20, compare=5, newton=3):
             "paper_claim_gap": 3e-4}
 
 
+def paper2d_leg(stream, steps=10, batch=64):
+    """Time per 30-min update of the paper's 2-D performance setting."""
+    from paper_2105_00448_amd import hca, synth
+    prm = dict(h_um=10.0, pde_substeps=30, pde_theta=0.5)
+    sched = synth.bolus_schedule([0])
+    out = {"workload": "2-D slice 100 x 100 voxels of 10 um (1 mm^2), cell density 0.4, vascular density "
+                       "0.12 (uniform, synthetic), bolus of both drugs at step 0, 30 Crank-Nicolson field "
+                       f"substeps of 1 min per 30-min update, {steps} updates",
+           "unit": "voxel-steps/s"}
+    for n in (1, batch):
+        tis = [synth.uniform_tissue((1, 100, 100), 0.4, 0.12, seed=500 + r) for r in range(n)]
+        reps = [(t.cell, t.w, t.seed, (sched.times, sched.amts)) for t in tis]
+        print(f"[bench:paper2d] {n} slice(s), {steps} updates", file=sys.stderr, flush=True)
+        el, st, _ = timed_run(reps, hca.default_params(**prm), steps, stream)
+        out[f"slices_{n}"] = {"value": n * 10000 * steps / el, "ms_per_update": el / steps * 1e3,
+                              "cg_iters_last_substep": list(st[0]["cg_iters"])}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -370,7 +393,7 @@ def main():
                     help="timed repeats from a fresh context; value = median")
     ap.add_argument("--no-legs", action="store_true", help="plain workload only")
     ap.add_argument("--legs", default="surrogate,batched",
-                    help="comma-separated further legs: surrogate, batched, substeps, newton")
+                    help="comma-separated further legs: surrogate, batched, substeps, newton, paper2d")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -513,6 +536,8 @@ def main():
         rec["substeps"] = substeps_leg(stream)
     if "newton" in legs:
         rec["newton"] = newton_leg(stream)
+    if "paper2d" in legs:
+        rec["paper2d"] = paper2d_leg(stream)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline()

@@ -75,6 +75,24 @@ def make_tissue(shape, n_gauss, seed, vessel_frac=0.10, cancer_frac=0.8):
     return Tissue(cell=cell, w=w, seed=int(seed))
 
 
+def uniform_tissue(shape, cell_density, vessel_density, seed, cancer_frac=0.8):
+    """Cells and vessels scattered uniformly at the given voxel fractions (the
+    paper's solver-performance setting: cell density 0.4, vascular density
+    0.12): vessels Bernoulli(vessel_density) with w ~ lognormal(0, 0.5), cells
+    on the other voxels with probability cell_density / (1 - vessel_density),
+    cancer with probability ``cancer_frac`` else stroma."""
+    rng = _rng(seed, 1)
+    vessel = rng.random(shape) < vessel_density
+    w = np.zeros(shape)
+    w[vessel] = rng.lognormal(0.0, 0.5, size=int(vessel.sum()))
+    occ = (~vessel) & (rng.random(shape) < cell_density / (1.0 - vessel_density))
+    cancer = rng.random(shape) < cancer_frac
+    cell = np.zeros(shape, dtype=np.uint8)
+    cell[occ & cancer] = 1
+    cell[occ & ~cancer] = 2
+    return Tissue(cell=cell, w=w, seed=int(seed))
+
+
 @dataclass
 class DoseSchedule:
     """Bolus times (min) and amounts (multiples of the reference peak), per drug."""
