@@ -47,6 +47,11 @@ class Params:
     pde_theta: float = 1.0      # theta scheme: 1 = backward Euler, 1/2 = Crank-Nicolson
     o2_newton: int = 0          # Newton iterations on the nonlinear oxygen uptake after
                                 # the linearised solve (0: the paper's linearisation)
+    # drug 2 (fluorouracil) plasma elimination: 0 its linear regime (rate k_pk[1]),
+    # 1 the exact Michaelis-Menten model with v_max, k_m (Table 1)
+    pk_mm: int = 0
+    mm_vmax: float = 1.75       # ug/mL/min
+    mm_km: float = 27.0         # ug/mL
 
     @property
     def a_K(self):

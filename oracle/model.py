@@ -60,8 +60,12 @@ class State:
 
 
 def plasma_pair(t, sched, p):
-    return tuple(pk.plasma(t, sched.times[i], sched.amts[i], p.k_pk[i], p.G_ref[i])
-                 for i in range(2))
+    g1 = pk.plasma(t, sched.times[0], sched.amts[0], p.k_pk[0], p.G_ref[0])
+    if p.pk_mm:
+        g2 = pk.plasma_mm(t, sched.times[1], sched.amts[1], p.mm_vmax, p.mm_km, p.G_ref[1])
+    else:
+        g2 = pk.plasma(t, sched.times[1], sched.amts[1], p.k_pk[1], p.G_ref[1])
+    return g1, g2
 
 
 def o2_system(L, w, K_old, p):

@@ -120,3 +120,39 @@ def test_fluorouracil_linear_regime():
     sol = solve_ivp(lambda t, y: -vmax / (km + y) * y, (0, 60.0), [g0], rtol=1e-12, atol=1e-18)
     lin = pk.plasma(60.0, (0.0,), (g0,), PRM.k_pk[1], 1.0)
     assert abs(sol.y[0, -1] - lin) < 1e-4 * lin
+
+
+def test_fluorouracil_michaelis_menten_matches_integration():
+    """The exact Michaelis-Menten plasma model (Lambert W closed form) against
+    the integrated ODE with resets, in the nonlinear range G ~ k_m."""
+    vmax, km = 1.75, 27.0
+    times, amts = (0.0, 100.0, 2000.0), (60.0, 10.0, 27.0)
+    def integrate_to(t):
+        g, tc = 0.0, 0.0
+        for tm, am in zip(times, amts):
+            if tm > t:
+                break
+            if tm > tc:
+                g = solve_ivp(lambda s, y: -vmax * y / (km + y), (tc, tm), [g], rtol=1e-12, atol=1e-18).y[0, -1]
+            g, tc = am, tm
+        if t > tc:
+            g = solve_ivp(lambda s, y: -vmax * y / (km + y), (tc, t), [g], rtol=1e-12, atol=1e-18).y[0, -1]
+        return g
+    for t in (0.0, 5.0, 30.0, 99.0, 100.0, 130.0, 400.0, 2000.0, 2500.0):
+        ref = integrate_to(t)
+        got = pk.plasma_mm(t, times, amts, vmax, km, 1.0)
+        assert abs(got - ref) <= 1e-9 * ref + 1e-15, (t, got, ref)
+    assert pk.plasma_mm(-1.0, times, amts, vmax, km, 1.0) == 0.0
+
+
+def test_fluorouracil_michaelis_menten_limits():
+    """Small doses decay at the linear rate v_max/k_m; a dose far above k_m is
+    first eliminated at the saturated rate v_max (zero order)."""
+    vmax, km = 1.75, 27.0
+    small = pk.plasma_mm(120.0, (0.0,), (1e-6,), vmax, km, 1.0)
+    assert small == pytest.approx(1e-6 * math.exp(-vmax / km * 120.0), rel=1e-7)
+    big = 1e6   # exp(G0/k_m) overflows: the large-argument branch
+    g = pk.plasma_mm(10.0, (0.0,), (big,), vmax, km, 1.0)
+    assert g == pytest.approx(big - vmax * 10.0, rel=1e-9)   # zero-order elimination
+    # and the separated solution k_m ln(G/G0) + G - G0 = -v_max t holds to rounding
+    assert abs(km * math.log(g / big) + g - big + vmax * 10.0) < 1e-8
