@@ -118,6 +118,11 @@ typedef struct hca_params {
                               then k Newton steps per substep on the uptake
                               phi_K K/(K1 + K) at the new value (each one more
                               O2 solve), 0 <= k <= 20                           */
+  /* drug 2 (fluorouracil) plasma elimination */
+  int32_t pk_mm;           /* 0: linear regime, rate k_pk[1] (0); 1: the exact
+                              Michaelis-Menten model dG/dt = -v_max G/(k_m + G)  */
+  double mm_vmax;          /* v_max, ug/mL/min (1.75)                           */
+  double mm_km;            /* k_m, ug/mL (27)                                   */
 } hca_params;
 
 /* One replicate's inputs.  hca_init deep-copies every array; the caller keeps

@@ -57,6 +57,9 @@ struct DevParams {
   // the field solves: nsub_pde theta-scheme substeps of tau = dt / nsub_pde
   int nsub_pde;
   double tau, inv_tau, theta;
+  // drug 2 plasma: exact Michaelis-Menten elimination when pk_mm
+  int pk_mm;
+  double mm_vmax, mm_km;
 };
 
 // One replicate on the device, or (in the solver's tables) one linear system:

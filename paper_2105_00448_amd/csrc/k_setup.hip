@@ -18,6 +18,38 @@ namespace hca {
 // for the latest bolus t_m <= t (reset at each dose), 0 before the first dose.
 // One-compartment linear elimination (Eq. intrachemo3; the fluorouracil model
 // in its linear regime).
+// Principal-branch Lambert W of x = e^lx (x >= 0, the solution w >= 0 of
+// w e^w = x): Halley's iteration w <- w - f / (e^w (w + 1) - (w + 2) f / (2w + 2)),
+// f = w e^w - x, from w = log1p(x) >= W(x) (cubic convergence); where e^lx
+// would overflow, Newton's iteration on w + ln w = lx from lx - ln lx.
+__device__ inline double lambert_w_exp(double lx) {
+  if (lx < 700.0) {
+    const double x = exp(lx);
+    double w = log1p(x);
+    for (int k = 0; k < 30; ++k) {
+      const double ew = exp(w);
+      const double f = w * ew - x;
+      const double w1 = w + 1.0;
+      const double dw = f / (ew * w1 - (w + 2.0) * f / (2.0 * w1));
+      w -= dw;
+      if (!(fabs(dw) > 1e-16 * w)) break;
+    }
+    return w;
+  }
+  double w = lx - log(lx);
+  for (int k = 0; k < 50; ++k) {
+    const double dw = (w + log(w) - lx) / (1.0 + 1.0 / w);
+    w -= dw;
+    if (!(fabs(dw) > 1e-16 * w)) break;
+  }
+  return w;
+}
+
+// Drug i's plasma level at time t: reset to a_m G_ref at the latest bolus
+// t_m <= t (0 before the first dose), then the elimination: linear,
+// G e^{-k (t - t_m)}; or, for fluorouracil with pk_mm, the exact
+// Michaelis-Menten decay, separable into k_m ln(G/G_m) + G - G_m = -v_max (t - t_m),
+// i.e. G = k_m W((G_m/k_m) e^{(G_m - v_max (t - t_m))/k_m}).
 __device__ inline double plasma_level(const RepDev& rp, const DevParams& p, const double* dose_t,
                                       const double* dose_a, int i, double t) {
   double g = 0.0;
@@ -29,8 +61,10 @@ __device__ inline double plasma_level(const RepDev& rp, const DevParams& p, cons
       g = dose_a[rp.dose_off + i * HCA_MAX_DOSES + k] * p.G_ref[i];
     }
   }
-  if (tm >= 0.0) g = g * exp(-p.k_pk[i] * (t - tm));
-  return g;
+  if (tm < 0.0 || g == 0.0) return tm < 0.0 ? 0.0 : g;
+  if (i == 1 && p.pk_mm)
+    return p.mm_km * lambert_w_exp(log(g / p.mm_km) + (g - p.mm_vmax * (t - tm)) / p.mm_km);
+  return g * exp(-p.k_pk[i] * (t - tm));
 }
 
 // Levels at the end (t^n + (j+1) tau; t^{n+1} for a single substep) and the

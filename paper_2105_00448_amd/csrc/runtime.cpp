@@ -326,6 +326,9 @@ DevParams make_dev_params(const hca_params& p) {
   d.tau = p.dt_min / p.pde_substeps;
   d.inv_tau = 1.0 / d.tau;
   d.theta = p.pde_theta;
+  d.pk_mm = p.pk_mm;
+  d.mm_vmax = p.mm_vmax;
+  d.mm_km = p.mm_km;
   d.aK = p.D_K / (p.h_um * p.h_um);
   d.aG = p.D_G / (p.h_um * p.h_um);
   d.r_k = p.r_k;
@@ -630,6 +633,11 @@ hca_status validate_params(const hca_params* p, std::string& msg) {
   if (p->pde_substeps < 1 || p->pde_substeps > 1000 || !(p->pde_theta >= 0.5 && p->pde_theta <= 1.0) ||
       p->o2_newton < 0 || p->o2_newton > 20) {
     msg = "pde_substeps in [1, 1000], pde_theta in [0.5, 1] and o2_newton in [0, 20] required";
+    return HCA_E_INVALID;
+  }
+  if ((p->pk_mm != 0 && p->pk_mm != 1) || !(std::isfinite(p->mm_vmax) && p->mm_vmax >= 0.0) ||
+      !(std::isfinite(p->mm_km) && p->mm_km > 0.0)) {
+    msg = "pk_mm in {0, 1}, finite mm_vmax >= 0 and mm_km > 0 required";
     return HCA_E_INVALID;
   }
   if (p->mg_smooth != 2) {
@@ -1309,6 +1317,9 @@ hca_status hca_default_params(hca_params* out) {
   out->pde_substeps = 1;
   out->pde_theta = 1.0;
   out->o2_newton = 0;
+  out->pk_mm = 0;
+  out->mm_vmax = 1.75;
+  out->mm_km = 27.0;
   return HCA_OK;
 }
 

@@ -40,6 +40,7 @@ class Params(C.Structure):
         ("init_rtol", C.c_double), ("init_maxit", C.c_int32), ("profile", C.c_int32),
         ("graphs", C.c_int32), ("autotune", C.c_int32),
         ("pde_substeps", C.c_int32), ("pde_theta", C.c_double), ("o2_newton", C.c_int32),
+        ("pk_mm", C.c_int32), ("mm_vmax", C.c_double), ("mm_km", C.c_double),
     ]
 
 

@@ -139,6 +139,29 @@ def test_newton_oxygen_matches_oracle(case32, m, theta, newton):
             s, _ = om.step(s, tis.w, osched, tis.seed, OPn)
 
 
+@pytest.mark.parametrize("amt", [60.0, 2.0e4], ids=["halley", "log-newton"])
+@pytest.mark.parametrize("m,theta", [(1, 1.0), (3, 0.5)], ids=["be1", "cn3"])
+def test_michaelis_menten_plasma_matches_oracle(case32, amt, m, theta):
+    """Fluorouracil plasma levels from the exact Michaelis-Menten decay
+    (Lambert W; a bolus of 60 ug/mL takes the Halley branch, 2e4 ug/mL the
+    large-argument branch), seen through the drug-2 field over two steps."""
+    print(f"\n[mm] amount {amt} m {m} theta {theta}", flush=True)
+    tis, _, s0 = case32
+    sched = synth.DoseSchedule(times=((0.0,), (0.0, 45.0)), amts=((1.0,), (amt, 0.5 * amt)))
+    osched = oracle_sched(sched)
+    OPm = OP.with_(pde_substeps=m, pde_theta=theta, pk_mm=1)
+    with make_sim([(tis, sched)], pde_substeps=m, pde_theta=theta, pk_mm=1) as sim:
+        s = s0
+        for n in range(2):
+            push_state(sim, s)
+            sim.run_phases(hca.PH_O2 | hca.PH_DRUGS)
+            K, G1, G2 = om.solve_fields(s, tis.w, osched, OPm)
+            assert G2.max() > 0.0
+            for name, ref in (("K", K), ("G1", G1), ("G2", G2)):
+                assert relerr(sim.field(name), ref) <= FIELD_TOL, (n, name)
+            s, _ = om.step(s, tis.w, osched, tis.seed, OPm)
+
+
 def test_ode_matches_oracle(case32):
     tis, sched, s0 = case32
     rng = np.random.default_rng(2)
