@@ -52,6 +52,20 @@ class Params:
     pk_mm: int = 0
     mm_vmax: float = 1.75       # ug/mL/min
     mm_km: float = 27.0         # ug/mL
+    # extracellular VEGF, Eq. (vac_v) with no Avastin (A = C = 0), and the
+    # vascular module, Eq. (vascular_module); off by default ----------------
+    vegf: int = 0               # 1: solve V with the other fields and run the vessel
+                                # birth-death update every dv_min
+    D_V: float = 3.52e3         # diffusion, um^2/min (Table 1)
+    psi_V: float = 1.0e-2       # decay, 1/min (Table 1)
+    sec_V: float = 6.66e-6      # secretion slope a: source a V_c per occupied voxel, 1/min
+    dv_min: float = 720.0       # vessel update interval (Table 1), a multiple of dt_min
+    V_low: float = 1.0e-6       # lower viability threshold, ug/mL (Table 1)
+    V_high: float = 1.0e-4      # upper threshold: missing from Table 1, chosen
+    p_death: float = 0.05       # death probability per update outside the window (chosen)
+    birth_per_V: float = 100.0  # birth probability per update = birth_per_V * V inside
+                                # the window, mL/ug (chosen: 0.01 at V_high)
+    w_new: float = 1.0          # perfusion weight of a new vessel
 
     @property
     def a_K(self):
@@ -63,6 +77,16 @@ class Params:
         """Face coupling D_G/h^2 of the drug Laplacian, 1/min."""
         return self.D_G / (self.h_um * self.h_um)
 
+    @property
+    def a_V(self):
+        """Face coupling D_V/h^2 of the VEGF Laplacian, 1/min."""
+        return self.D_V / (self.h_um * self.h_um)
+
+    @property
+    def dv_steps(self):
+        """Coupled steps per vessel update."""
+        return int(round(self.dv_min / self.dt_min))
+
     def with_(self, **kw):
         return replace(self, **kw)
 
@@ -72,6 +96,7 @@ DEFAULT = Params()
 # Philox stream identifiers (third counter word)
 STREAM_INIT = 0
 STREAM_KILL = 1
+STREAM_VESSEL = 4   # (2 and 3 draw the surrogate trainer's weights and minibatches)
 
 # cell codes of the cellular module
 EMPTY, CANCER, STROMA = 0, 1, 2

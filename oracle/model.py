@@ -3,7 +3,9 @@
 Test infrastructure only.
 
 State at t^n = n dt:  L (uint8 cell map), K, G1, G2, P, Vc, phi (float64),
-with the static perfusion map w (0 = no vessel, > 0 = perfusion weight).
+with the perfusion map w (0 = no vessel, > 0 = perfusion weight), static
+unless the VEGF option is on; then the state also holds the extracellular
+VEGF V and its own w, which the vessel birth-death update changes.
 
 One coupled step n -> n+1 (loop body of Algorithm 1, with the implicit Euler
 step dt of the cell-cycle update):
@@ -21,6 +23,9 @@ step dt of the cell-cycle update):
            = G^n/dt + kappa_G w G_{i,0}(t^{n+1});
 4. intracellular ODEs with K^{n+1} frozen;
 5. cellular automaton on the state after 4.
+With ``p.vegf``: V^{n+1} from Eq. (vac_v) without Avastin (the V_c source of
+the state at t^n, see ``vegf_substep_system``) alongside steps 2-3, and after
+step 5 the vessel birth-death update (``vascular.vessel_update``) when due.
 
 Initialisation (Algorithm 1 before the loop): K^0 solves Eq. (oxygen) with
 s_K = 0 (Picard iteration on the uptake coefficient from K = K0 until the
@@ -32,7 +37,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import ca, lattice, ode, philox, pk
+from . import ca, lattice, ode, philox, pk, vascular
 from .constants import CANCER, STREAM_INIT
 
 
@@ -53,10 +58,14 @@ class State:
     Vc: np.ndarray
     phi: np.ndarray
     step: int = 0
+    V: np.ndarray = None        # extracellular VEGF (VEGF option)
+    w: np.ndarray = None        # the state's own vessel map (VEGF option)
 
     def copy(self):
+        cp = lambda a: None if a is None else a.copy()
         return State(self.L.copy(), self.K.copy(), self.G1.copy(), self.G2.copy(),
-                     self.P.copy(), self.Vc.copy(), self.phi.copy(), self.step)
+                     self.P.copy(), self.Vc.copy(), self.phi.copy(), self.step,
+                     cp(self.V), cp(self.w))
 
 
 def plasma_pair(t, sched, p):
@@ -115,6 +124,35 @@ def drug_substep_system(w, G_old, g_old, g_new, p, tau, theta):
     return c, b
 
 
+def vegf_substep_system(L, V_old, Vc, p, tau, theta):
+    """One theta-scheme substep of Eq. (vac_v) with no Avastin (A = C = 0, so
+    the binding terms vanish): V_t = D_V Lap V + a V_c chi - psi_V V, the
+    secretion a V_c chi (chi = [L != 0]: cancer and stroma cells release
+    VEGF) taken from the cell state at the start of the coupled step, so it is
+    the same at both ends of every substep:
+        (1/tau + theta psi_V) V' - theta a_V Lap V'
+            = (1/tau - (1 - theta) psi_V) V + (1 - theta) a_V Lap V + a V_c chi.
+    Returns (c, b) of the system with coupling theta a_V."""
+    chi = (L != 0).astype(np.float64)
+    c = np.full(L.shape, 1.0 / tau + theta * p.psi_V)
+    b = V_old * (1.0 / tau - (1.0 - theta) * p.psi_V) + p.sec_V * Vc * chi
+    if theta < 1.0:
+        b = b + (1.0 - theta) * p.a_V * lattice.laplacian_apply(V_old)
+    return c, b
+
+
+def solve_vegf(s, p, method="cg"):
+    """V^{n+1}: ``p.pde_substeps`` theta-scheme substeps of Eq. (vac_v) over
+    the coupled step (one backward-Euler solve by default)."""
+    m, theta = p.pde_substeps, p.pde_theta
+    tau = p.dt_min / m
+    V = s.V if s.V is not None else np.zeros(s.L.shape)
+    for _ in range(m):
+        c, b = vegf_substep_system(s.L, V, s.Vc, p, tau, theta)
+        V = lattice.solve(c, theta * p.a_V, b, x0=V, method=method)
+    return V
+
+
 def o2_newton_system(L, w, K_it, b_lin, p, tau, theta):
     """One Newton step on the implicit oxygen update with the uptake kept
     nonlinear, phi_K K'/(K1 + K') at the new value:
@@ -163,6 +201,8 @@ def init_state(L, w, seed, p, method="cg"):
     o0, _, _, _ = philox.block_vec(gids.astype(np.uint64), 0, STREAM_INIT, 0, (seed, 0))
     phi.ravel()[gids] = philox.to_unit_vec(o0)
     z = np.zeros(L.shape)
+    if p.vegf:   # V(., 0) = 0 (Algorithm 1) and the state's own vessel map
+        return State(L, K, z.copy(), z.copy(), P, Vc, phi, 0, z.copy(), np.array(w, dtype=np.float64))
     return State(L, K, z.copy(), z.copy(), P, Vc, phi, 0)
 
 
@@ -206,9 +246,19 @@ def solve_fields(s, w, sched, p, method="cg"):
 
 
 def step(s, w, sched, seed, p, method="cg"):
-    """One coupled step; returns (new state, CA event counts)."""
+    """One coupled step; returns (new state, CA event counts).  The vessel
+    map is ``s.w`` when the state holds one, else ``w``.  With ``p.vegf`` the
+    new state holds V^{n+1} and the vessel map after the birth-death update
+    (events "births", "deaths")."""
+    if s.w is not None:
+        w = s.w
     K, G1, G2 = solve_fields(s, w, sched, p, method)
+    V = solve_vegf(s, p, method) if p.vegf else s.V
     P, Vc, phi = ode.ode_step(s.L, K, s.P, s.Vc, s.phi, p)
     Ln, phin, Pn, Vn, ev, _, _ = ca.ca_update(s.L, w, K, G1, G2, phi, P, Vc,
                                               s.step, seed, p)
-    return State(Ln, K, G1, G2, Pn, Vn, phin, s.step + 1), ev
+    w_out = s.w
+    if p.vegf:
+        w_out, nb, nd = vascular.vessel_update(Ln, w, V, s.step, seed, p)
+        ev = dict(ev, births=nb, deaths=nd)
+    return State(Ln, K, G1, G2, Pn, Vn, phin, s.step + 1, V, w_out), ev
