@@ -40,7 +40,12 @@ same metric beside the plain one:
   paper2d    the paper's solver-performance setting as synthetic input: a 2-D
              1 mm^2 slice of 100 x 100 voxels of 10 um, cell and vascular
              densities 0.4 and 0.12, 30 Crank-Nicolson 1-min field substeps
-             per 30-min update; one slice and a batch of 64 (off by default).
+             per 30-min update; one slice and a batch of 64 (off by default);
+  vegf       the plain 128^3 workload with the extracellular VEGF field solved
+             in the same batch as the other three and the vessel birth-death
+             update every 720 min, 48 steps (two updates): step time beside
+             the plain one, vessel events, and the vessel kernel's duration
+             (off by default).
 """
 import argparse
 import json
@@ -357,6 +362,31 @@ def newton_leg(stream, steps=20, compare=5, newton=3):
             "paper_claim_gap": 3e-4}
 
 
+def vegf_leg(stream, steps=48):
+    """The plain workload with the VEGF option: step time and vessel events."""
+    from paper_2105_00448_amd import hca
+    reps, cfg, _ = make_workload("plain128")
+    nvox = sum(r[0].size for r in reps)
+    print(f"[bench:vegf] {steps} steps", file=sys.stderr, flush=True)
+    el_v, st_v, _ = timed_run(reps, hca.default_params(vegf=1), steps, stream)
+    el_p, _, _ = timed_run(reps, hca.default_params(), steps, stream)
+    names = [hca.lib().hca_kernel_name(k).decode() for k in range(hca.lib().hca_num_kernels())]
+    _, _, kt = timed_run(reps, hca.default_params(vegf=1, profile=1), steps, stream)
+    ves = kt["k_vessel"]
+    setup = kt["k_setup_step"]
+    return {"workload": f"plain 128^3 workload with extracellular VEGF (4 fields per batched solve) and "
+                        f"the vessel birth-death update every 720 min, {steps} steps",
+            "unit": "voxel-steps/s", "value": nvox * steps / el_v,
+            "ms_per_step": el_v / steps * 1e3, "ms_per_step_plain": el_p / steps * 1e3,
+            "cg_iters_last_step": list(st_v[0]["cg_iters"]) + [st_v[0]["cg_iters_vegf"]],
+            "vessel_births": st_v[0]["total_births"], "vessel_deaths": st_v[0]["total_deaths"],
+            "n_vessel_end": st_v[0]["n_vessel"],
+            "k_vessel_ms_per_launch": ves["ms"] / max(1, ves["launches"]),
+            "k_vessel_launches": ves["launches"],
+            "k_setup_step_ms_per_launch": setup["ms"] / max(1, setup["launches"]),
+            "kernel_classes": len(names)}
+
+
 def paper2d_leg(stream, steps=10, batch=64):
     """Time per 30-min update of the paper's 2-D performance setting."""
     from paper_2105_00448_amd import hca, synth
@@ -393,7 +423,7 @@ def main():
                     help="timed repeats from a fresh context; value = median")
     ap.add_argument("--no-legs", action="store_true", help="plain workload only")
     ap.add_argument("--legs", default="surrogate,batched",
-                    help="comma-separated further legs: surrogate, batched, substeps, newton, paper2d")
+                    help="comma-separated further legs: surrogate, batched, substeps, newton, paper2d, vegf")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -536,6 +566,8 @@ def main():
         rec["substeps"] = substeps_leg(stream)
     if "newton" in legs:
         rec["newton"] = newton_leg(stream)
+    if "vegf" in legs:
+        rec["vegf"] = vegf_leg(stream)
     if "paper2d" in legs:
         rec["paper2d"] = paper2d_leg(stream)
     if not args.no_cpu_baseline:

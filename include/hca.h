@@ -52,7 +52,8 @@ typedef enum hca_status {
 
 typedef enum hca_field {
   HCA_F_O2 = 0, HCA_F_DRUG1 = 1, HCA_F_DRUG2 = 2, HCA_F_CELL = 3 /* uint8 */,
-  HCA_F_P53 = 4, HCA_F_VEGF_IC = 5, HCA_F_PHI = 6, HCA_F_VESSEL_W = 7 /* read-only */
+  HCA_F_P53 = 4, HCA_F_VEGF_IC = 5, HCA_F_PHI = 6, HCA_F_VESSEL_W = 7,
+  HCA_F_VEGF = 8 /* extracellular VEGF V; only with params.vegf */
 } hca_field;
 
 /* Phases of one coupled step n -> n+1 (loop body of Algorithm 1). */
@@ -60,10 +61,13 @@ enum {
   HCA_PH_O2 = 1u << 0,      /* plasma kinetics + oxygen solve                 */
   HCA_PH_DRUGS = 1u << 1,   /* plasma kinetics + both drug solves             */
   HCA_PH_ODE = 1u << 2,     /* intracellular ODEs with the current K          */
-  HCA_PH_CA = 1u << 3,      /* cellular automaton propose/resolve/finalize    */
+  HCA_PH_CA = 1u << 3,      /* cellular automaton propose/resolve/finalize,
+                               then (params.vegf) the vessel update when due  */
   HCA_PH_STATS = 1u << 4,   /* counts and non-finite check                    */
   HCA_PH_ADVANCE = 1u << 5, /* n := n + 1 at the end                          */
-  HCA_PH_ALL = 63u
+  HCA_PH_VEGF = 1u << 6,    /* extracellular VEGF solve (params.vegf; batched
+                               with the O2 and drug solves of the same call)  */
+  HCA_PH_ALL = 127u
 };
 
 /* Model constants (Table 1) and numerical settings.  Fill with
@@ -123,6 +127,25 @@ typedef struct hca_params {
                               Michaelis-Menten model dG/dt = -v_max G/(k_m + G)  */
   double mm_vmax;          /* v_max, ug/mL/min (1.75)                           */
   double mm_km;            /* k_m, ug/mL (27)                                   */
+  /* extracellular VEGF, Eq. (vac_v) with no Avastin, and the vascular module,
+     Eq. (vascular_module).  With vegf = 1 the state gains the field V
+     (HCA_F_VEGF, 0 at init), solved in every coupled step with the source
+     sec_V V_c on occupied voxels (V_c of the step's start), and every dv_min
+     the vessel map changes: a vessel whose V is outside [V_low, V_high] is
+     removed with probability p_death; an empty non-vessel voxel with V inside
+     becomes a vessel of weight w_new with probability birth_per_V V (one
+     uniform per voxel: Philox counter (gid, n+1, 4, 0), key (seed, 0); an
+     event when u < probability). */
+  int32_t vegf;            /* 0 off (0), 1 on                                   */
+  double D_V;              /* diffusion, um^2/min (3.52e3)                      */
+  double psi_V;            /* decay, 1/min (1e-2)                               */
+  double sec_V;            /* secretion slope a, 1/min (6.66e-6)                */
+  double dv_min;           /* vessel update interval, min (720); a whole
+                              multiple of dt_min                                */
+  double V_low, V_high;    /* viability window, ug/mL (1e-6, 1e-4)             */
+  double p_death;          /* in [0, 1] (0.05)                                  */
+  double birth_per_V;      /* mL/ug, birth_per_V * V_high <= 1 (100)           */
+  double w_new;            /* perfusion weight of a new vessel, > 0 (1)         */
 } hca_params;
 
 /* One replicate's inputs.  hca_init deep-copies every array; the caller keeps
@@ -152,6 +175,11 @@ typedef struct hca_stats_s {
   /* last ODE phase with a surrogate set: occupied voxels advanced by the
    * network, and by the plain integrator (threshold margin or range) */
   int64_t sur_voxels, sur_fallbacks;
+  /* VEGF option: the last V solve, and the vessel events of the last step
+   * (0 between update times) and since init */
+  int32_t cg_iters_vegf;
+  double cg_relres_vegf;
+  int64_t vessel_births, vessel_deaths, total_births, total_deaths;
 } hca_stats_t;
 
 typedef struct hca_ctx hca_ctx;
@@ -205,9 +233,10 @@ hca_status hca_run_phases(hca_ctx* c, unsigned mask);
 hca_status hca_fields(hca_ctx* c, int rep, hca_field f, void* dst, size_t dst_bytes,
                       int dst_is_device);
 
-/* Overwrite replicate `rep`'s state field (checkpoint restore, tests).  The
- * vessel map is read-only.  A cell map with codes outside {0,1,2} or cells on
- * vessel voxels gives HCA_E_INVALID and leaves the state unchanged. */
+/* Overwrite replicate `rep`'s state field (checkpoint restore, tests).  A
+ * cell map with codes outside {0,1,2} or cells on vessel voxels, and a vessel
+ * map with non-finite or negative weights or vessels on cells, give
+ * HCA_E_INVALID and leave the state unchanged.  HCA_F_VEGF needs vegf = 1. */
 hca_status hca_set_field(hca_ctx* c, int rep, hca_field f, const void* src,
                          size_t src_bytes, int src_is_device);
 

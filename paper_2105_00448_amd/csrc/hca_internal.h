@@ -43,6 +43,7 @@ constexpr uint8_t kCodeNone = 255;
 
 constexpr uint64_t kStreamInit = 0;
 constexpr uint64_t kStreamKill = 1;
+constexpr uint64_t kStreamVessel = 4;   // (2, 3: the surrogate trainer's draws)
 
 // Model constants as the kernels use them.
 struct DevParams {
@@ -60,11 +61,18 @@ struct DevParams {
   // drug 2 plasma: exact Michaelis-Menten elimination when pk_mm
   int pk_mm;
   double mm_vmax, mm_km;
+  // extracellular VEGF (field 3 of the solver arrays) and the vessel update
+  int vegf;
+  int nf;                     // fields solved per replicate: 3, or 4 with vegf
+  double aV, psi_V, sec_V;
+  long long dv_steps;         // coupled steps per vessel update
+  double V_low, V_high, p_death, birth_per_V, w_new;
 };
 
 // One replicate on the device, or (in the solver's tables) one linear system:
-// system s = field * nreps + rep, field 0 oxygen, 1 and 2 the drugs, its
-// unknowns at [off, off + n) of the 3 x total-voxel solver arrays.
+// system s = field * nreps + rep, field 0 oxygen, 1 and 2 the drugs, 3 the
+// extracellular VEGF (vegf option), its unknowns at [off, off + n) of the
+// nf x total-voxel solver arrays.
 struct RepDev {
   int nx, ny, nz, pad0;
   long long off;              // first voxel in the concatenated arrays
@@ -112,7 +120,8 @@ struct Counters {
   unsigned long long nonfinite;
   unsigned long long total_divisions, total_kills;
   unsigned long long sur_voxels, sur_fallbacks;   // ODE phase with the surrogate
-  unsigned long long pad[2];
+  unsigned long long births, deaths;              // vessel update of the last step
+  unsigned long long total_births, total_deaths;
 };
 
 struct Work {
@@ -166,11 +175,11 @@ void launch_plasma(hipStream_t s, const Work& w, const DevParams& p, const long 
                    int j, const double* dose_t, const double* dose_a, double* g0);
 void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
                      const double* vw, const double* K, double* c, double* b, int steady);
-// All three systems of a field substep at once: F = [K | G1 | G2] (3 x ntot),
-// c and b of the same layout.
+// All systems of a field substep at once: F = [K | G1 | G2] (3 x ntot), or
+// [K | G1 | G2 | V] with vegf (V's source from Vc); c and b of the same layout.
 void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
-                       const uint8_t* L, const double* vw, const double* F, const double* g0,
-                       double* c, double* b);
+                       const uint8_t* L, const double* vw, const double* F, const double* Vc,
+                       const double* g0, double* c, double* b);
 // Newton step on the oxygen uptake at the new value: c, b of the oxygen
 // systems (the first ntot entries) from the iterate K and the linearised
 // substep's right-hand side b_lin.
@@ -301,7 +310,7 @@ void launch_ca_resolve(hipStream_t s, const Work& w, const uint8_t* L, const dou
 // (part[item * kCounterSlots + k]); a one-workgroup-per-replicate reduce
 // then writes the replicate's counters.
 constexpr int kCounterSlots = 8;
-enum CounterKind { CNT_CA = 0, CNT_STATS = 1, CNT_SUR = 2 };
+enum CounterKind { CNT_CA = 0, CNT_STATS = 1, CNT_SUR = 2, CNT_VESSEL = 3 };
 void launch_counters_reduce(hipStream_t s, const Work& w, const unsigned long long* part,
                             Counters* cnt, int kind);
 void launch_ca_finalize(hipStream_t s, const Work& w, uint8_t* L, double* phi, double* P,
@@ -310,9 +319,17 @@ void launch_ca_finalize(hipStream_t s, const Work& w, uint8_t* L, double* phi, d
 void launch_stats(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
                   const double* const* fields, int nfields, unsigned long long* part,
                   Counters* cnt);
+// Vessel birth-death update of the step n -> n+1 when (n + 1) is a multiple
+// of dv_steps (else only zero event counts), from V and the cell map after
+// the CA; updates vw in place.
+void launch_vessel(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
+                   const uint8_t* L, const double* V, double* vw, unsigned long long* part,
+                   Counters* cnt);
 // what: 1 CA events, 0 census and non-finite count, 2 surrogate counts.
 void launch_zero_counters(hipStream_t s, Counters* cnt, int nreps, int what);
 void launch_advance(hipStream_t s, long long* d_step);
+// Counts, in replicate rep, cell codes outside {0,1,2}, cells on vessel
+// voxels and non-finite or negative vessel weights.
 void launch_validate_cells(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
                            int rep, unsigned long long* bad);
 

@@ -229,6 +229,53 @@ __global__ void __launch_bounds__(kBlock) k_ca_finalize(Work w, uint8_t* __restr
   });
 }
 
+// Vascular module, Eq. (vascular_module), at the end of the step n -> n+1
+// when (n + 1) is a multiple of dv_steps: a vessel whose V lies outside
+// [V_low, V_high] is removed with probability p_death; an empty non-vessel
+// voxel whose V lies inside becomes a vessel of weight w_new with probability
+// birth_per_V V.  One uniform per candidate voxel (Philox key (seed, 0),
+// counter (gid, n+1, VESSEL, 0), first word); the event happens when
+// u < probability.  The rule is voxel-local and reads the cell map after the
+// CA, so the vessel map is updated in place.
+__global__ void __launch_bounds__(kBlock) k_vessel(Work w, DevParams p, const long long* d_step,
+                                                   const uint8_t* __restrict__ L,
+                                                   const double* __restrict__ V,
+                                                   double* __restrict__ vw,
+                                                   unsigned long long* __restrict__ part) {
+  __shared__ unsigned long long lds4[4];
+  const long long step = d_step[0];
+  const bool due = (step + 1) % p.dv_steps == 0;
+  unsigned long long nb = 0, nd = 0;
+  for_each_voxel_ca(w, [&](int, const RepDev& rp, long long li) {
+    if (!due) return;
+    const long long i = rp.off + li;
+    const double wv = vw[i];
+    const double v = V[i];
+    const bool inside = v >= p.V_low && v <= p.V_high;
+    const bool vessel = wv > 0.0;
+    const bool candidate = vessel ? !inside : (inside && L[i] == 0);
+    if (!candidate) return;
+    const U64x4 o = philox4x64_10((uint64_t)li, (uint64_t)(step + 1), kStreamVessel, 0ull, rp.seed, 0ull);
+    const double u = unit53(o.v[0]);
+    if (vessel) {
+      if (u < p.p_death) {
+        vw[i] = 0.0;
+        ++nd;
+      }
+    } else if (u < p.birth_per_V * v) {
+      vw[i] = p.w_new;
+      ++nb;
+    }
+  }, [&](int, int it) {
+    const unsigned long long a = block_sum_u64(nb, lds4), b = block_sum_u64(nd, lds4);
+    if (threadIdx.x == 0) {
+      part[(size_t)it * kCounterSlots + 0] = a;
+      part[(size_t)it * kCounterSlots + 1] = b;
+    }
+    nb = nd = 0;
+  });
+}
+
 // Cell-type counts and a non-finite scan of the listed fields.
 __global__ void __launch_bounds__(kBlock) k_stats(Work w, const uint8_t* __restrict__ L,
                                                   const double* __restrict__ vw,
@@ -279,7 +326,7 @@ __global__ void __launch_bounds__(kBlock) k_counters_reduce(Work w,
   __shared__ unsigned long long lds4[4];
   const int rep = blockIdx.x;
   const RepDev rp = w.reps[rep];
-  constexpr int K = KIND == CNT_SUR ? 2 : 5;
+  constexpr int K = (KIND == CNT_SUR || KIND == CNT_VESSEL) ? 2 : 5;
   unsigned long long v[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) v[k] = 0;
@@ -304,6 +351,11 @@ __global__ void __launch_bounds__(kBlock) k_counters_reduce(Work w,
     c.n_empty = v[2];
     c.n_vessel = v[3];
     c.nonfinite = v[4];
+  } else if (KIND == CNT_VESSEL) {
+    c.births = v[0];
+    c.deaths = v[1];
+    c.total_births += v[0];
+    c.total_deaths += v[1];
   } else {
     c.sur_voxels = v[0];
     c.sur_fallbacks = v[1];
@@ -315,13 +367,15 @@ void launch_counters_reduce(hipStream_t s, const Work& w, const unsigned long lo
   switch (kind) {
     case CNT_CA: hca_launch(k_counters_reduce<CNT_CA>, dim3(w.nreps), dim3(kBlock), 0, s, w, part, cnt); break;
     case CNT_STATS: hca_launch(k_counters_reduce<CNT_STATS>, dim3(w.nreps), dim3(kBlock), 0, s, w, part, cnt); break;
+    case CNT_VESSEL: hca_launch(k_counters_reduce<CNT_VESSEL>, dim3(w.nreps), dim3(kBlock), 0, s, w, part, cnt); break;
     default: hca_launch(k_counters_reduce<CNT_SUR>, dim3(w.nreps), dim3(kBlock), 0, s, w, part, cnt); break;
   }
 }
 
 __global__ void k_advance(long long* d_step) { d_step[0] += 1; }
 
-// Counts cell codes outside {0,1,2} and cells on vessel voxels of replicate rep.
+// Counts cell codes outside {0,1,2}, cells on vessel voxels and non-finite
+// or negative vessel weights of replicate rep.
 __global__ void __launch_bounds__(kBlock) k_validate_cells(Work w, const uint8_t* __restrict__ L,
                                                            const double* __restrict__ vw, int rep,
                                                            unsigned long long* bad) {
@@ -330,7 +384,8 @@ __global__ void __launch_bounds__(kBlock) k_validate_cells(Work w, const uint8_t
     if (r != rep) return;
     const long long i = rp.off + li;
     const uint8_t l = L[i];
-    nb += (l > 2) || (l != 0 && vw[i] != 0.0);
+    const double wv = vw[i];
+    nb += (l > 2) || (l != 0 && wv != 0.0) || !(wv >= 0.0 && isfinite(wv));
   });
   for (int o = 32; o > 0; o >>= 1) nb += __shfl_xor(nb, o, 64);
   if ((threadIdx.x & 63) == 0 && nb) atomicAdd(bad, nb);
@@ -354,6 +409,14 @@ void launch_ca_finalize(hipStream_t s, const Work& w, uint8_t* L, double* phi, d
   hca_launch(k_ca_finalize, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, phi, P,
              Vc, code, win, part);
   launch_counters_reduce(s, w, part, cnt, CNT_CA);
+}
+
+void launch_vessel(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
+                   const uint8_t* L, const double* V, double* vw, unsigned long long* part,
+                   Counters* cnt) {
+  hca_launch(k_vessel, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, d_step, L, V, vw,
+             part);
+  launch_counters_reduce(s, w, part, cnt, CNT_VESSEL);
 }
 
 void launch_stats(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,

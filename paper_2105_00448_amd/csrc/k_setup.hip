@@ -14,10 +14,6 @@
 
 namespace hca {
 
-// G_{i,0}(t) of both drugs for every replicate: a_m G_ref e^{-k (t - t_m)}
-// for the latest bolus t_m <= t (reset at each dose), 0 before the first dose.
-// One-compartment linear elimination (Eq. intrachemo3; the fluorouracil model
-// in its linear regime).
 // Principal-branch Lambert W of x = e^lx (x >= 0, the solution w >= 0 of
 // w e^w = x): Halley's iteration w <- w - f / (e^w (w + 1) - (w + 2) f / (2w + 2)),
 // f = w e^w - x, from w = log1p(x) >= W(x) (cubic convergence); where e^lx
@@ -45,9 +41,10 @@ __device__ inline double lambert_w_exp(double lx) {
   return w;
 }
 
-// Drug i's plasma level at time t: reset to a_m G_ref at the latest bolus
-// t_m <= t (0 before the first dose), then the elimination: linear,
-// G e^{-k (t - t_m)}; or, for fluorouracil with pk_mm, the exact
+// Drug i's plasma level at time t (intravascular module): reset to a_m G_ref
+// at the latest bolus t_m <= t (0 before the first dose), then the
+// elimination: one-compartment linear, G e^{-k (t - t_m)} (Eq. intrachemo3;
+// fluorouracil in its linear regime); or, for fluorouracil with pk_mm, the exact
 // Michaelis-Menten decay, separable into k_m ln(G/G_m) + G - G_m = -v_max (t - t_m),
 // i.e. G = k_m W((G_m/k_m) e^{(G_m - v_max (t - t_m))/k_m}).
 __device__ inline double plasma_level(const RepDev& rp, const DevParams& p, const double* dose_t,
@@ -124,12 +121,15 @@ __global__ void __launch_bounds__(kBlock) k_setup_o2(Work w, DevParams p, const 
 //           start), S = r_k w K0 constant;
 //   drugs:  R = psi_G + kappa_G w, S = kappa_G w g0(t) with the plasma level
 //           at the substep's end (weight theta) and start (1 - theta).
+//   VEGF (vegf): R = psi_V, S = sec_V V_c chi, Eq. (vac_v) with no Avastin,
+//           V_c of the coupled step's start at both ends of every substep.
 // With one backward-Euler substep these are the coupled step's systems
 // c = 1/dt + R, b = u/dt + S.
 __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long long ntot,
                                                        const uint8_t* __restrict__ L,
                                                        const double* __restrict__ vw,
                                                        const double* __restrict__ F,
+                                                       const double* __restrict__ Vc,
                                                        const double* __restrict__ g0,
                                                        double* __restrict__ c,
                                                        double* __restrict__ b) {
@@ -149,6 +149,11 @@ __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long
       const long long j = g + (i + 1) * ntot;
       c[j] = cg;
       b[j] = F[j] * (p.inv_tau - th1 * rg) + kw * (th * g0[2 * rep + i] + th1 * g0[2 * w.nreps + 2 * rep + i]);
+    }
+    if (p.vegf) {
+      const long long j = g + 3 * ntot;
+      c[j] = p.inv_tau + th * p.psi_V;
+      b[j] = F[j] * (p.inv_tau - th1 * p.psi_V) + p.sec_V * Vc[g] * chi;
     }
   });
 }
@@ -174,13 +179,14 @@ __global__ void __launch_bounds__(kBlock) k_setup_o2_newton(Work w, DevParams p,
   });
 }
 
-// b += (1 - theta) a Lap F for the three fields (theta < 1): the explicit half
+// b += (1 - theta) a Lap F for the nf fields (theta < 1): the explicit half
 // of a Crank-Nicolson-type substep, Lap the zero-flux 7-point Laplacian
 // (neighbours in the order -x, +x, -y, +y, -z, +z).
 __global__ void __launch_bounds__(kBlock) k_rhs_lap(Work w, DevParams p, long long ntot,
                                                     const double* __restrict__ F,
                                                     double* __restrict__ b) {
-  const double sK = (1.0 - p.theta) * p.aK, sG = (1.0 - p.theta) * p.aG;
+  const double sK = (1.0 - p.theta) * p.aK, sG = (1.0 - p.theta) * p.aG,
+               sV = (1.0 - p.theta) * p.aV;
   for_each_voxel(w, [&](int, const RepDev& rp, long long g) {
     const long long i = g - rp.off;
     const int x = (int)(i % rp.nx);
@@ -188,7 +194,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs_lap(Work w, DevParams p, long lo
     const int y = (int)(q % rp.ny);
     const int z = (int)(q / rp.ny);
     const long long sy = rp.nx, sz = (long long)rp.nx * rp.ny;
-    for (int f = 0; f < 3; ++f) {
+    for (int f = 0; f < p.nf; ++f) {
       const double* u = F + (long long)f * ntot;
       const double uc = u[g];
       double lap = 0.0;
@@ -198,7 +204,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs_lap(Work w, DevParams p, long lo
       if (y + 1 < rp.ny) lap += u[g + sy] - uc;
       if (z > 0) lap += u[g - sz] - uc;
       if (z + 1 < rp.nz) lap += u[g + sz] - uc;
-      b[g + (long long)f * ntot] += (f == 0 ? sK : sG) * lap;
+      b[g + (long long)f * ntot] += (f == 0 ? sK : f == 3 ? sV : sG) * lap;
     }
   });
 }
@@ -245,10 +251,10 @@ void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uin
 }
 
 void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
-                       const uint8_t* L, const double* vw, const double* F, const double* g0,
-                       double* c, double* b) {
-  hca_launch(k_setup_step, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot, L, vw, F, g0, c,
-                     b);
+                       const uint8_t* L, const double* vw, const double* F, const double* Vc,
+                       const double* g0, double* c, double* b) {
+  hca_launch(k_setup_step, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot, L, vw, F, Vc,
+             g0, c, b);
 }
 
 void launch_setup_o2_newton(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,

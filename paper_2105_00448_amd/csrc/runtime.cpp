@@ -36,14 +36,14 @@ enum KernelClass {
   KC_PLASMA = 0, KC_SETUP, KC_CG_START, KC_CG_APPLY, KC_CG_UPDATE, KC_ODE,
   KC_CA_PROPOSE, KC_CA_RESOLVE, KC_CA_FINALIZE, KC_STATS,
   KC_MG_PREP, KC_MG_PRE0, KC_MG_RESTRICT0, KC_MG_LEVELS, KC_MG_COARSE, KC_MG_POST1_0,
-  KC_MG_POST2_0, KC_MLP_APPLY, KC_COUNT
+  KC_MG_POST2_0, KC_MLP_APPLY, KC_VESSEL, KC_COUNT
 };
 
 const char* kKernelNames[KC_COUNT] = {
     "k_plasma", "k_setup_step", "k_cg_start", "k_cg_apply", "k_cg_update",
     "k_ode", "k_ca_propose", "k_ca_resolve", "k_ca_finalize", "k_stats",
     "k_mg_prep0+k_mg_coarsen", "k_mg_pre<L0>", "k_mg_restrict<L0>", "mg levels >= 1 (global)",
-    "k_mg_coarse", "k_mg_post1<L0>", "k_mg_post2<L0>", "k_mlp_apply"};
+    "k_mg_coarse", "k_mg_post1<L0>", "k_mg_post2<L0>", "k_mlp_apply", "k_vessel"};
 
 // Compulsory (algorithmic) HBM bytes per voxel of each kernel class; solver
 // classes per voxel of each active system (0: not priced, latency-bound).
@@ -65,7 +65,10 @@ const double kBytesPerVoxel[KC_COUNT] = {
     0.0,          // coarse workgroup levels
     16.5,         // mg post1 L0: read u, e (1/8), r (4), dinv; write ualt
     20.0,         // mg post2 L0: read ualt, r, dinv; write z (4)
-    73.0};        // mlp apply: read L, K, G1, G2, P, Vc, phi; write P, Vc, phi
+    73.0,         // mlp apply: read L, K, G1, G2, P, Vc, phi; write P, Vc, phi
+    17.0};        // vessel: read L, w, V (writes only where a vessel changes)
+constexpr double kBytesSetupVegf = 32.0;   // setup_step with vegf: + read V, Vc; write c, b
+constexpr double kBytesStatsVegf = 8.0;    // stats with vegf: + read V
 constexpr double kBytesUpdateMg = 56.0;   // cg_update, multigrid: read x, p, r, q, z (4); write x, r, r (4)
 constexpr double kBytesApplyJacobi = 40.0;   // cg_apply, Jacobi: z is FP64
 
@@ -104,13 +107,13 @@ struct hca_ctx {
   // state
   uint8_t *L = nullptr, *code = nullptr, *win = nullptr;
   double *w = nullptr, *P = nullptr, *Vc = nullptr, *phi = nullptr;
-  double* F = nullptr;                          // [K | G1 | G2]
-  double *K = nullptr, *G1 = nullptr, *G2 = nullptr;
-  // solver, 3 x ntot
+  double* F = nullptr;                          // [K | G1 | G2], with vegf [K | G1 | G2 | V]
+  double *K = nullptr, *G1 = nullptr, *G2 = nullptr, *V = nullptr;
+  // solver, nf x ntot (nf = dp.nf fields)
   double *c = nullptr, *b = nullptr;
   SolverBufs sb{};
   bool use_mg = false;
-  MgBufs mg3{}, mg1{};                          // all systems / oxygen systems only
+  MgBufs mg_all{}, mg1{};                       // all systems / oxygen systems only
   std::vector<void*> mg_mem;
   double *dose_t = nullptr, *dose_a = nullptr, *g0 = nullptr;
   double* b_o2lin = nullptr;                     // o2_newton: the linearised O2 right-hand side
@@ -120,11 +123,11 @@ struct hca_ctx {
   FlatBlk* d_flat = nullptr;
   Tile* d_tiles = nullptr;
   Work work{};
-  // system tables (solver kernels); sys1 is the oxygen prefix of sys3
+  // system tables (solver kernels); sys1 is the oxygen prefix of sys_all
   RepDev* d_sys = nullptr;
   FlatBlk* d_sflat = nullptr;
   Tile* d_stiles = nullptr;
-  Work sys3{}, sys1{};
+  Work sys_all{}, sys1{};
   std::vector<long long> sys_n;
   Counters* d_cnt = nullptr;
   unsigned long long* d_cpart = nullptr;   // per flat item x kCounterSlots
@@ -198,6 +201,8 @@ hipEvent_t take_event(hca_ctx* c) {
 double bpv_of(const hca_ctx* c, int kc) {
   if (kc == KC_CG_UPDATE && c->use_mg) return kBytesUpdateMg;
   if (kc == KC_CG_APPLY && !c->use_mg) return kBytesApplyJacobi;
+  if (kc == KC_SETUP && c->dp.vegf) return kBytesPerVoxel[kc] + kBytesSetupVegf;
+  if (kc == KC_STATS && c->dp.vegf) return kBytesPerVoxel[kc] + kBytesStatsVegf;
   return kBytesPerVoxel[kc];
 }
 
@@ -329,6 +334,17 @@ DevParams make_dev_params(const hca_params& p) {
   d.pk_mm = p.pk_mm;
   d.mm_vmax = p.mm_vmax;
   d.mm_km = p.mm_km;
+  d.vegf = p.vegf;
+  d.nf = p.vegf ? 4 : 3;
+  d.aV = p.D_V / (p.h_um * p.h_um);
+  d.psi_V = p.psi_V;
+  d.sec_V = p.sec_V;
+  d.dv_steps = std::llround(p.dv_min / p.dt_min);
+  d.V_low = p.V_low;
+  d.V_high = p.V_high;
+  d.p_death = p.p_death;
+  d.birth_per_V = p.birth_per_V;
+  d.w_new = p.w_new;
   d.aK = p.D_K / (p.h_um * p.h_um);
   d.aG = p.D_G / (p.h_um * p.h_um);
   d.r_k = p.r_k;
@@ -396,7 +412,7 @@ bool capture_iterations(hca_ctx* c, const Work& W, const MgBufs& mg, double rtol
   return true;
 }
 
-// Flexible CG on the systems of W (all systems: sys3, oxygen only: sys1) for
+// Flexible CG on the systems of W (all systems: sys_all, oxygen only: sys1) for
 // (diag(c) - a Lap) x = b, x = the field array F.  Systems of fields outside
 // `fmask` are marked finished at the start.  Iterations are launched in
 // batches sized from the previous solve of the same kind, with a poll of the
@@ -474,7 +490,8 @@ hca_status solve(hca_ctx* c, const Work& W, const MgBufs& mg, unsigned fmask, do
 hca_status run_phases(hca_ctx* c, unsigned mask) {
   const Work& wk = c->work;
   hipStream_t s = c->stream;
-  const unsigned fmask = ((mask & HCA_PH_O2) ? 1u : 0u) | ((mask & HCA_PH_DRUGS) ? 6u : 0u);
+  const unsigned fmask = ((mask & HCA_PH_O2) ? 1u : 0u) | ((mask & HCA_PH_DRUGS) ? 6u : 0u) |
+                         (((mask & HCA_PH_VEGF) && c->dp.vegf) ? 8u : 0u);
   // the field solves: pde_substeps theta-scheme substeps (one by default)
   for (int j = 0; fmask && j < c->dp.nsub_pde; ++j) {
     {
@@ -483,13 +500,13 @@ hca_status run_phases(hca_ctx* c, unsigned mask) {
     }
     {
       ProfScope ps(c, KC_SETUP, kTagState);
-      launch_setup_step(s, wk, c->dp, c->ntot, c->L, c->w, c->F, c->g0, c->c, c->b);
+      launch_setup_step(s, wk, c->dp, c->ntot, c->L, c->w, c->F, c->Vc, c->g0, c->c, c->b);
       if (c->dp.theta < 1.0) launch_rhs_lap(s, wk, c->dp, c->ntot, c->F, c->b);
     }
     const bool newton = c->prm.o2_newton > 0 && (fmask & 1u);
     if (newton)
       HIPCHK(c, hipMemcpyAsync(c->b_o2lin, c->b, sizeof(double) * (size_t)c->ntot, hipMemcpyDeviceToDevice, s));
-    hca_status st = solve(c, c->sys3, c->mg3, fmask, c->prm.cg_rtol, c->prm.cg_maxit, 0);
+    hca_status st = solve(c, c->sys_all, c->mg_all, fmask, c->prm.cg_rtol, c->prm.cg_maxit, 0);
     if (st != HCA_OK) return st;
     // Newton steps on the oxygen uptake at the new value, from the linearised solution
     for (int k = 0; newton && k < c->prm.o2_newton; ++k) {
@@ -524,10 +541,14 @@ hca_status run_phases(hca_ctx* c, unsigned mask) {
       ProfScope ps(c, KC_CA_FINALIZE, kTagState);
       launch_ca_finalize(s, wk, c->L, c->phi, c->P, c->Vc, c->code, c->win, c->d_cpart, c->d_cnt);
     }
+    if (c->dp.vegf) {
+      ProfScope ps(c, KC_VESSEL, kTagState);
+      launch_vessel(s, wk, c->dp, c->d_step, c->L, c->V, c->w, c->d_cpart, c->d_cnt);
+    }
   }
   if (mask & HCA_PH_STATS) {
     ProfScope ps(c, KC_STATS, kTagState);
-    launch_stats(s, wk, c->L, c->w, c->d_fields, 6, c->d_cpart, c->d_cnt);
+    launch_stats(s, wk, c->L, c->w, c->d_fields, c->dp.vegf ? 7 : 6, c->d_cpart, c->d_cnt);
   }
   if (mask & HCA_PH_ADVANCE) {
     launch_advance(s, c->d_step);
@@ -639,6 +660,22 @@ hca_status validate_params(const hca_params* p, std::string& msg) {
       !(std::isfinite(p->mm_km) && p->mm_km > 0.0)) {
     msg = "pk_mm in {0, 1}, finite mm_vmax >= 0 and mm_km > 0 required";
     return HCA_E_INVALID;
+  }
+  {
+    const double ratio = p->dv_min / p->dt_min;
+    const bool whole = std::isfinite(ratio) && ratio >= 1.0 && ratio <= 1e9 &&
+                       std::fabs(ratio - std::round(ratio)) <= 1e-9 * ratio;
+    const bool fin = std::isfinite(p->D_V) && std::isfinite(p->psi_V) && std::isfinite(p->sec_V) &&
+                     std::isfinite(p->V_low) && std::isfinite(p->V_high) &&
+                     std::isfinite(p->birth_per_V) && std::isfinite(p->w_new);
+    if ((p->vegf != 0 && p->vegf != 1) || !fin || !(p->D_V > 0.0) || !(p->psi_V >= 0.0) ||
+        !(p->sec_V >= 0.0) || !whole || !(p->V_low >= 0.0) || !(p->V_high >= p->V_low) ||
+        !(p->p_death >= 0.0 && p->p_death <= 1.0) || !(p->birth_per_V >= 0.0) ||
+        !(p->birth_per_V * p->V_high <= 1.0) || !(p->w_new > 0.0)) {
+      msg = "vegf in {0, 1}; D_V > 0, psi_V >= 0, sec_V >= 0; dv_min a whole multiple of dt_min; "
+            "0 <= V_low <= V_high; p_death in [0, 1]; 0 <= birth_per_V <= 1 / V_high; w_new > 0";
+      return HCA_E_INVALID;
+    }
   }
   if (p->mg_smooth != 2) {
     msg = "mg_smooth: the multigrid smoothers implement two sweeps before and after";
@@ -906,11 +943,12 @@ hca_status build_tables(hca_ctx* c, const hca_replicate* in) {
     std::vector<Tile> tiles;
     int nflat1 = 0, ntiles1 = 0;
     c->sys_n.clear();
-    for (int f = 0; f < 3; ++f) {
+    for (int f = 0; f < c->dp.nf; ++f) {
       for (int r = 0; r < R; ++r) {
         RepDev d = lattice_entry(c->reps[r], (long long)f * c->ntot + c->reps[r].off, f * R + r,
                                  flat, tiles);
-        d.a = (f == 0 ? c->dp.aK : c->dp.aG) * c->dp.theta;   // the theta scheme's implicit coupling
+        // the theta scheme's implicit coupling
+        d.a = (f == 0 ? c->dp.aK : f == 3 ? c->dp.aV : c->dp.aG) * c->dp.theta;
         sd.push_back(d);
         c->sys_n.push_back(c->reps[r].n);
       }
@@ -923,14 +961,14 @@ hca_status build_tables(hca_ctx* c, const hca_replicate* in) {
     if ((st = upload(c, &c->d_sys, sd)) != HCA_OK || (st = upload(c, &c->d_sflat, flat)) != HCA_OK ||
         (st = upload(c, &c->d_stiles, tiles)) != HCA_OK)
       return st;
-    c->sys3.nreps = 3 * R;
-    c->sys3.reps = c->d_sys;
-    c->sys3.flat = c->d_sflat;
-    c->sys3.nflat = (int)flat.size();
-    c->sys3.tiles = c->d_stiles;
-    c->sys3.ntiles = (int)tiles.size();
-    c->sys3.max_blocks = max_blocks;
-    c->sys1 = c->sys3;
+    c->sys_all.nreps = c->dp.nf * R;
+    c->sys_all.reps = c->d_sys;
+    c->sys_all.flat = c->d_sflat;
+    c->sys_all.nflat = (int)flat.size();
+    c->sys_all.tiles = c->d_stiles;
+    c->sys_all.ntiles = (int)tiles.size();
+    c->sys_all.max_blocks = max_blocks;
+    c->sys1 = c->sys_all;
     c->sys1.nreps = R;
     c->sys1.nflat = nflat1;
     c->sys1.ntiles = ntiles1;
@@ -940,8 +978,8 @@ hca_status build_tables(hca_ctx* c, const hca_replicate* in) {
 
 hca_status alloc_all(hca_ctx* c) {
   const size_t n = (size_t)c->ntot;
-  const size_t n3 = 3 * n;
-  const int nsys = 3 * c->nreps;
+  const size_t n3 = (size_t)c->dp.nf * n;   // solver arrays: nf fields
+  const int nsys = c->dp.nf * c->nreps;
   auto big = [&](double** p, size_t count) -> hca_status {
     hipError_t e = dalloc(p, count);
     if (e == hipErrorOutOfMemory) return fail(c, HCA_E_NOMEM, "device memory exhausted");
@@ -970,9 +1008,10 @@ hca_status alloc_all(hca_ctx* c) {
   c->K = c->F;
   c->G1 = c->F + n;
   c->G2 = c->F + 2 * n;
+  c->V = c->dp.vegf ? c->F + 3 * n : nullptr;
   c->sb.jacobi = c->use_mg ? 0 : 1;
   if (!c->use_mg && (st = big(&c->sb.dinv, n3)) != HCA_OK) return st;
-  const size_t nwork = (size_t)std::max(c->sys3.ntiles, c->sys3.nflat);
+  const size_t nwork = (size_t)std::max(c->sys_all.ntiles, c->sys_all.nflat);
   HIPCHK(c, dalloc(&c->sb.partial, 3 * nwork));
   HIPCHK(c, dalloc(&c->sb.counter, nsys));
   HIPCHK(c, hipMemset(c->sb.counter, 0, sizeof(unsigned) * nsys));
@@ -987,9 +1026,9 @@ hca_status alloc_all(hca_ctx* c) {
   HIPCHK(c, dalloc(&c->d_cnt, c->nreps));
   HIPCHK(c, dalloc(&c->d_cpart, (size_t)c->work.nflat * kCounterSlots));
   HIPCHK(c, hipMemset(c->d_cnt, 0, sizeof(Counters) * c->nreps));
-  HIPCHK(c, dalloc(&c->d_fields, 6));
+  HIPCHK(c, dalloc(&c->d_fields, 7));
   HIPCHK(c, dalloc(&c->d_bad, 1));
-  const double* fl[6] = {c->K, c->G1, c->G2, c->P, c->Vc, c->phi};
+  const double* fl[7] = {c->K, c->G1, c->G2, c->P, c->Vc, c->phi, c->V};
   HIPCHK(c, hipMemcpy(c->d_fields, fl, sizeof fl, hipMemcpyHostToDevice));
   HIPCHK(c, hipHostMalloc((void**)&c->h_ss, sizeof(SolveScal) * nsys, hipHostMallocDefault));
   HIPCHK(c, hipHostMalloc((void**)&c->h_cnt, sizeof(Counters) * c->nreps, hipHostMallocDefault));
@@ -1019,10 +1058,10 @@ hca_status mg_upload(hca_ctx* c, T** p, const std::vector<T>& v) {
 // dims by ceil halving down to one cell (at least two levels); kc, the first
 // level handed to the one-workgroup coarse solve (<= mg_coarse_max cells and
 // its LDS block within the device's per-workgroup LDS); level arrays, per-level tiles, coarse-solve
-// descriptors.  mg1 is the oxygen prefix (the first nreps systems) of mg3.
+// descriptors.  mg1 is the oxygen prefix (the first nreps systems) of mg_all.
 hca_status build_mg(hca_ctx* c) {
   const int R = c->nreps;
-  const int S = 3 * R;
+  const int S = c->dp.nf * R;
   // LDS of one workgroup: the coarse solve's levels must fit (160 KiB on gfx950)
   int lds_dev = 65536;
   if (hipDeviceGetAttribute(&lds_dev, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
@@ -1055,7 +1094,7 @@ hca_status build_mg(hca_ctx* c) {
   for (int r = 0; r < R; ++r) nglob = std::max(nglob, kcr[r]);
   std::vector<RepDev> sd(S);
   HIPCHK(c, hipMemcpy(sd.data(), c->d_sys, sizeof(RepDev) * S, hipMemcpyDeviceToHost));
-  MgBufs& mg = c->mg3;
+  MgBufs& mg = c->mg_all;
   mg.nlev_glob = nglob;
   // Smoothing: each pair of weighted-Jacobi sweeps is the two-step Chebyshev
   // polynomial (1 - w_a t)(1 - w_b t) of least maximum over t in [1/3, 2], the
@@ -1124,9 +1163,9 @@ hca_status build_mg(hca_ctx* c) {
     L.reps = d_mr;
     if (k == 0) {
       L.tiles = c->d_stiles;
-      L.ntiles = c->sys3.ntiles;
+      L.ntiles = c->sys_all.ntiles;
       ntiles1 = c->sys1.ntiles;
-      const size_t n = 3 * (size_t)c->ntot;
+      const size_t n = (size_t)c->dp.nf * c->ntot;
       if ((st = mg_alloc(c, &L.dinv, n)) != HCA_OK || (st = mg_alloc(c, &L.u, n)) != HCA_OK ||
           (st = mg_alloc(c, &L.ualt, n)) != HCA_OK)
         return st;
@@ -1266,6 +1305,7 @@ void* field_ptr(hca_ctx* c, hca_field f, size_t& elem) {
     case HCA_F_VEGF_IC: return c->Vc;
     case HCA_F_PHI: return c->phi;
     case HCA_F_VESSEL_W: return c->w;
+    case HCA_F_VEGF: return c->V;
   }
   return nullptr;
 }
@@ -1320,6 +1360,16 @@ hca_status hca_default_params(hca_params* out) {
   out->pk_mm = 0;
   out->mm_vmax = 1.75;
   out->mm_km = 27.0;
+  out->vegf = 0;
+  out->D_V = 3.52e3;
+  out->psi_V = 1.0e-2;
+  out->sec_V = 6.66e-6;
+  out->dv_min = 720.0;
+  out->V_low = 1.0e-6;
+  out->V_high = 1.0e-4;
+  out->p_death = 0.05;
+  out->birth_per_V = 100.0;
+  out->w_new = 1.0;
   return HCA_OK;
 }
 
@@ -1402,9 +1452,11 @@ hca_status hca_init(hca_ctx** out, const hca_params* p, const hca_replicate* rep
   launch_init_cells(c->stream, c->work, c->dp, c->L, c->K, c->P, c->Vc, c->phi);
   if (hipMemsetAsync(c->G1, 0, (size_t)c->ntot * 16, c->stream) != hipSuccess)   // G1 and G2
     return bail(HCA_E_DEVICE);
+  if (c->V && hipMemsetAsync(c->V, 0, (size_t)c->ntot * 8, c->stream) != hipSuccess)
+    return bail(HCA_E_DEVICE);
   launch_zero_counters(c->stream, c->d_cnt, n_reps, 1);
   launch_zero_counters(c->stream, c->d_cnt, n_reps, 0);
-  launch_stats(c->stream, c->work, c->L, c->w, c->d_fields, 6, c->d_cpart, c->d_cnt);
+  launch_stats(c->stream, c->work, c->L, c->w, c->d_fields, c->dp.vegf ? 7 : 6, c->d_cpart, c->d_cnt);
   if (hipGetLastError() != hipSuccess) return bail(HCA_E_DEVICE);
   if ((st = check_after(c)) != HCA_OK) return bail(st);
   c->last_it[0] = 0;
@@ -1452,7 +1504,6 @@ hca_status hca_set_field(hca_ctx* c, int rep, hca_field f, const void* src, size
                          int src_is_device) {
   if (!c || !src) return HCA_E_INVALID;
   if (rep < 0 || rep >= c->nreps) return fail(c, HCA_E_RANGE, "replicate index out of range");
-  if (f == HCA_F_VESSEL_W) return HCA_E_INVALID;
   size_t elem = 0;
   char* dst = (char*)field_ptr(c, f, elem);
   if (!dst) return HCA_E_INVALID;
@@ -1473,6 +1524,22 @@ hca_status hca_set_field(hca_ctx* c, int rep, hca_field f, const void* src, size
       return HCA_E_INVALID;
     }
     HIPCHK(c, hipMemcpyAsync(dst + R.off, c->code + R.off, bytes, hipMemcpyDeviceToDevice,
+                             c->stream));
+  } else if (f == HCA_F_VESSEL_W) {
+    // stage in the solver's right-hand side (rewritten by every setup) and
+    // validate against the current cell map
+    double* stage = c->b;
+    HIPCHK(c, hipMemcpyAsync(stage + R.off, src, bytes, kind, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_bad, 0, sizeof(unsigned long long), c->stream));
+    launch_validate_cells(c->stream, c->work, c->L, stage, rep, c->d_bad);
+    unsigned long long bad = 0;
+    HIPCHK(c, hipMemcpyAsync(&bad, c->d_bad, sizeof bad, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (bad) {
+      c->err = "vessel map has non-finite or negative weights or vessels on cells";
+      return HCA_E_INVALID;
+    }
+    HIPCHK(c, hipMemcpyAsync(dst + (size_t)R.off * elem, stage + R.off, bytes, hipMemcpyDeviceToDevice,
                              c->stream));
   } else {
     HIPCHK(c, hipMemcpyAsync(dst + (size_t)R.off * elem, src, bytes, kind, c->stream));
@@ -1510,17 +1577,27 @@ hca_status hca_stats(hca_ctx* c, int rep, hca_stats_t* out) {
   out->lost = (int64_t)k.lost;
   out->total_divisions = (int64_t)k.total_divisions;
   out->total_kills = (int64_t)k.total_kills;
-  if ((int)c->last_ss.size() == 3 * c->nreps) {
-    for (int f = 0; f < 3; ++f) {
+  if ((int)c->last_ss.size() == c->dp.nf * c->nreps) {
+    for (int f = 0; f < c->dp.nf; ++f) {
       const SolveScal& s = c->last_ss[f * c->nreps + rep];
-      out->cg_iters[f] = s.it;
-      out->cg_relres[f] = s.bb > 0 ? std::sqrt(s.rr / s.bb) : 0.0;
+      const double rel = s.bb > 0 ? std::sqrt(s.rr / s.bb) : 0.0;
+      if (f < 3) {
+        out->cg_iters[f] = s.it;
+        out->cg_relres[f] = rel;
+      } else {
+        out->cg_iters_vegf = s.it;
+        out->cg_relres_vegf = rel;
+      }
     }
   }
   out->nonfinite = k.nonfinite ? 1 : 0;
   out->init_picard_iters = c->picard_iters;
   out->sur_voxels = (int64_t)k.sur_voxels;
   out->sur_fallbacks = (int64_t)k.sur_fallbacks;
+  out->vessel_births = (int64_t)k.births;
+  out->vessel_deaths = (int64_t)k.deaths;
+  out->total_births = (int64_t)k.total_births;
+  out->total_deaths = (int64_t)k.total_deaths;
   return HCA_OK;
 }
 
@@ -1628,7 +1705,7 @@ hca_status hca_harvest_step(hca_ctx* c, float* X, float* Y, int64_t cap_rows, in
   HIPCHK(c, hipMemcpyAsync(&total, c->item_off + wk.nflat, sizeof total, hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   if (total > cap_rows) return fail(c, HCA_E_RANGE, "harvest: more occupied voxels than cap_rows");
-  hca_status st = run_phases(c, HCA_PH_O2 | HCA_PH_DRUGS);
+  hca_status st = run_phases(c, HCA_PH_O2 | HCA_PH_DRUGS | HCA_PH_VEGF);
   if (st != HCA_OK) return st;
   launch_mlp_save_state(s, wk, c->P, c->Vc, c->phi, c->before);
   {

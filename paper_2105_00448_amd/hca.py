@@ -15,12 +15,12 @@ OK, E_INVALID, E_NOMEM, E_DEVICE, E_NOCONV, E_NONFINITE, E_SINGULAR, E_RANGE = 0
 STATUS_NAMES = {0: "HCA_OK", -1: "HCA_E_INVALID", -2: "HCA_E_NOMEM", -3: "HCA_E_DEVICE",
                 -4: "HCA_E_NOCONV", -5: "HCA_E_NONFINITE", -6: "HCA_E_SINGULAR", -7: "HCA_E_RANGE"}
 
-F_O2, F_DRUG1, F_DRUG2, F_CELL, F_P53, F_VEGF_IC, F_PHI, F_VESSEL_W = range(8)
+F_O2, F_DRUG1, F_DRUG2, F_CELL, F_P53, F_VEGF_IC, F_PHI, F_VESSEL_W, F_VEGF = range(9)
 FIELDS = {"K": F_O2, "G1": F_DRUG1, "G2": F_DRUG2, "L": F_CELL, "P": F_P53, "Vc": F_VEGF_IC,
-          "phi": F_PHI, "w": F_VESSEL_W}
+          "phi": F_PHI, "w": F_VESSEL_W, "V": F_VEGF}
 
-PH_O2, PH_DRUGS, PH_ODE, PH_CA, PH_STATS, PH_ADVANCE = 1, 2, 4, 8, 16, 32
-PH_ALL = 63
+PH_O2, PH_DRUGS, PH_ODE, PH_CA, PH_STATS, PH_ADVANCE, PH_VEGF = 1, 2, 4, 8, 16, 32, 64
+PH_ALL = 127
 MAX_DOSES = 64
 
 
@@ -41,6 +41,9 @@ class Params(C.Structure):
         ("graphs", C.c_int32), ("autotune", C.c_int32),
         ("pde_substeps", C.c_int32), ("pde_theta", C.c_double), ("o2_newton", C.c_int32),
         ("pk_mm", C.c_int32), ("mm_vmax", C.c_double), ("mm_km", C.c_double),
+        ("vegf", C.c_int32), ("D_V", C.c_double), ("psi_V", C.c_double), ("sec_V", C.c_double),
+        ("dv_min", C.c_double), ("V_low", C.c_double), ("V_high", C.c_double),
+        ("p_death", C.c_double), ("birth_per_V", C.c_double), ("w_new", C.c_double),
     ]
 
 
@@ -63,6 +66,9 @@ class Stats(C.Structure):
         ("cg_iters", C.c_int32 * 3), ("cg_relres", C.c_double * 3),
         ("nonfinite", C.c_int32), ("init_picard_iters", C.c_int32),
         ("sur_voxels", C.c_int64), ("sur_fallbacks", C.c_int64),
+        ("cg_iters_vegf", C.c_int32), ("cg_relres_vegf", C.c_double),
+        ("vessel_births", C.c_int64), ("vessel_deaths", C.c_int64),
+        ("total_births", C.c_int64), ("total_deaths", C.c_int64),
     ]
 
     def as_dict(self):

@@ -36,7 +36,9 @@ def test_default_params_match_the_oracle_transcription_of_table1():
     p = hca.default_params()
     for name in ["h_um", "dt_min", "D_K", "r_k", "K0", "phi_K", "K1", "D_G", "psi_G", "kappa_G",
                  "k1", "k1p", "K_p53", "k2", "k2p", "k2pp", "J5", "K_V", "K_phi", "T_cycle",
-                 "ode_substeps", "pde_substeps", "pde_theta", "o2_newton", "pk_mm", "mm_vmax", "mm_km"]:
+                 "ode_substeps", "pde_substeps", "pde_theta", "o2_newton", "pk_mm", "mm_vmax", "mm_km",
+                 "vegf", "D_V", "psi_V", "sec_V", "dv_min", "V_low", "V_high", "p_death",
+                 "birth_per_V", "w_new"]:
         assert getattr(p, name) == getattr(ORACLE, name), name
     assert list(p.k_pk) == list(ORACLE.k_pk)
     assert list(p.G_ref) == list(ORACLE.G_ref)
@@ -122,7 +124,9 @@ def test_rejects_bad_params_and_arguments():
     assert init_status([(cell, w, NODOSE)], p) == hca.E_INVALID
     for kw in (dict(pde_substeps=0), dict(pde_theta=0.4), dict(pde_theta=float("nan")), dict(o2_newton=-1),
                dict(o2_newton=21), dict(pk_mm=2), dict(mm_km=0.0), dict(mm_vmax=-1.0),
-               dict(mm_vmax=float("inf"))):
+               dict(mm_vmax=float("inf")), dict(vegf=2), dict(D_V=0.0), dict(psi_V=-1.0),
+               dict(dv_min=45.0), dict(dv_min=15.0), dict(V_low=2e-4), dict(p_death=1.5),
+               dict(birth_per_V=2.0e4), dict(w_new=0.0), dict(sec_V=float("nan"))):
         assert init_status([(cell, w, NODOSE)], hca.default_params(**kw)) == hca.E_INVALID, kw
     lib = hca.lib()
     assert lib.hca_init(None, None, None, 0, None) == hca.E_INVALID
