@@ -6,7 +6,8 @@ Rules (section "Stochastic cellular automaton for the cellular module" and
 the numerical treatment of the CA; conflict priority from Algorithm 2):
 
 * A cancer cell is committed when its cycle phi >= 1 (after this step's ODE).
-* A committed cell is killed by drug i with probability
+* A committed cell is killed by drug i (two drugs, three with the third-drug
+  option) with probability
   I(G_i / G_ref_i; 1, b_i), the regularised incomplete beta function, which
   for a = 1 equals 1 - (1 - x)^b.  Each drug is an independent trial with its
   own uniform; the cell dies if any trial kills.  x is clipped to [0, 1] and
@@ -74,12 +75,12 @@ def kill_probability(G, G_ref, b):
 
 
 def kill_uniforms(gids, step, seed):
-    o0, o1, _, _ = philox.block_vec(gids.astype(np.uint64), step + 1, STREAM_KILL, 0,
-                                    (seed, 0))
-    return philox.to_unit_vec(o0), philox.to_unit_vec(o1)
+    o0, o1, o2, _ = philox.block_vec(gids.astype(np.uint64), step + 1, STREAM_KILL, 0,
+                                     (seed, 0))
+    return philox.to_unit_vec(o0), philox.to_unit_vec(o1), philox.to_unit_vec(o2)
 
 
-def propose(L, w, K, G1, G2, phi, step, seed, p):
+def propose(L, w, K, G1, G2, phi, step, seed, p, G3=None):
     """Proposal code per voxel: direction 0..25, NOSPACE, KILL or NONE."""
     shape = L.shape
     code = np.full(shape, CODE_NONE, dtype=np.uint8)
@@ -87,10 +88,12 @@ def propose(L, w, K, G1, G2, phi, step, seed, p):
     gids = np.flatnonzero(committed)
     if gids.size == 0:
         return code
-    u0, u1 = kill_uniforms(gids, step, seed)
+    u0, u1, u2 = kill_uniforms(gids, step, seed)
     p1 = kill_probability(G1.ravel()[gids], p.G_ref[0], p.b_int[0])
     p2 = kill_probability(G2.ravel()[gids], p.G_ref[1], p.b_int[1])
     killed = (u0 < p1) | (u1 < p2)
+    if G3 is not None:   # third drug: its own trial with the third uniform
+        killed = killed | (u2 < kill_probability(G3.ravel()[gids], p.G_ref3, p.b_int3))
 
     best_k = np.full(gids.size, -np.inf)
     best_d = np.full(gids.size, CODE_NOSPACE, dtype=np.uint8)
@@ -163,7 +166,7 @@ def finalize(L, phi, P, Vc, code, win):
     return Ln, phin, Pn, Vn, ev
 
 
-def ca_update(L, w, K, G1, G2, phi, P, Vc, step, seed, p):
-    code = propose(L, w, K, G1, G2, phi, step, seed, p)
+def ca_update(L, w, K, G1, G2, phi, P, Vc, step, seed, p, G3=None):
+    code = propose(L, w, K, G1, G2, phi, step, seed, p, G3)
     win = resolve(L, w, phi, code)
     return finalize(L, phi, P, Vc, code, win) + (code, win)

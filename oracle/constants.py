@@ -66,6 +66,19 @@ class Params:
     birth_per_V: float = 100.0  # birth probability per update = birth_per_V * V inside
                                 # the window, mL/ug (chosen: 0.01 at V_high)
     w_new: float = 1.0          # perfusion weight of a new vessel
+    # third drug, epirubicin: three-compartment plasma kinetics (Table 1's
+    # volumes in mL; its clearances, printed in garbled units, read as mL/min),
+    # its own tissue field G3 (Eq. chemo with the drugs' D_G, psi_G, kappa_G)
+    # and a third kill trial; off by default -------------------------------
+    drug3: int = 0
+    epi_w1: float = 18.0e3      # plasma compartment volume, mL
+    epi_w2: float = 957.0e3     # peripheral compartment volumes, mL
+    epi_w3: float = 25.0e3
+    epi_q2: float = 0.918e3     # intercompartmental clearances, mL/min
+    epi_q3: float = 0.25e3
+    epi_cl: float = 0.983e3     # elimination clearance, mL/min
+    G_ref3: float = 1.0         # kill-probability normalisation
+    b_int3: int = 1             # dose-response shape (Table 1 alpha = 1)
 
     @property
     def a_K(self):

@@ -43,7 +43,8 @@ from .constants import CANCER, STREAM_INIT
 
 @dataclass
 class Schedule:
-    """Dose times (min) and amounts (multiples of G_ref) per drug."""
+    """Dose times (min) and amounts (multiples of G_ref) per drug (a third
+    entry for the third drug)."""
     times: tuple = ((), ())
     amts: tuple = ((), ())
 
@@ -60,12 +61,13 @@ class State:
     step: int = 0
     V: np.ndarray = None        # extracellular VEGF (VEGF option)
     w: np.ndarray = None        # the state's own vessel map (VEGF option)
+    G3: np.ndarray = None       # third drug in the tissue (third-drug option)
 
     def copy(self):
         cp = lambda a: None if a is None else a.copy()
         return State(self.L.copy(), self.K.copy(), self.G1.copy(), self.G2.copy(),
                      self.P.copy(), self.Vc.copy(), self.phi.copy(), self.step,
-                     cp(self.V), cp(self.w))
+                     cp(self.V), cp(self.w), cp(self.G3))
 
 
 def plasma_pair(t, sched, p):
@@ -153,6 +155,23 @@ def solve_vegf(s, p, method="cg"):
     return V
 
 
+def solve_drug3(s, w, sched, p, method="cg"):
+    """G3^{n+1}: the third drug (epirubicin) by the drugs' Eq. (chemo) in
+    ``p.pde_substeps`` theta-scheme substeps, its vessel source from the
+    three-compartment plasma level at the substep ends."""
+    m, theta = p.pde_substeps, p.pde_theta
+    tau = p.dt_min / m
+    G = s.G3 if s.G3 is not None else np.zeros(s.L.shape)
+    for j in range(m):
+        t_old = s.step * p.dt_min + j * tau
+        t_new = (s.step + 1) * p.dt_min if m == 1 else t_old + tau
+        g_old = pk.plasma_epi(t_old, sched.times[2], sched.amts[2], p)
+        g_new = pk.plasma_epi(t_new, sched.times[2], sched.amts[2], p)
+        c, b = drug_substep_system(w, G, g_old, g_new, p, tau, theta)
+        G = lattice.solve(c, theta * p.a_G, b, x0=G, method=method)
+    return G
+
+
 def o2_newton_system(L, w, K_it, b_lin, p, tau, theta):
     """One Newton step on the implicit oxygen update with the uptake kept
     nonlinear, phi_K K'/(K1 + K') at the new value:
@@ -201,9 +220,12 @@ def init_state(L, w, seed, p, method="cg"):
     o0, _, _, _ = philox.block_vec(gids.astype(np.uint64), 0, STREAM_INIT, 0, (seed, 0))
     phi.ravel()[gids] = philox.to_unit_vec(o0)
     z = np.zeros(L.shape)
+    s = State(L, K, z.copy(), z.copy(), P, Vc, phi, 0)
     if p.vegf:   # V(., 0) = 0 (Algorithm 1) and the state's own vessel map
-        return State(L, K, z.copy(), z.copy(), P, Vc, phi, 0, z.copy(), np.array(w, dtype=np.float64))
-    return State(L, K, z.copy(), z.copy(), P, Vc, phi, 0)
+        s.V, s.w = z.copy(), np.array(w, dtype=np.float64)
+    if p.drug3:
+        s.G3 = z.copy()
+    return s
 
 
 def solve_fields(s, w, sched, p, method="cg"):
@@ -254,11 +276,12 @@ def step(s, w, sched, seed, p, method="cg"):
         w = s.w
     K, G1, G2 = solve_fields(s, w, sched, p, method)
     V = solve_vegf(s, p, method) if p.vegf else s.V
+    G3 = solve_drug3(s, w, sched, p, method) if p.drug3 else s.G3
     P, Vc, phi = ode.ode_step(s.L, K, s.P, s.Vc, s.phi, p)
     Ln, phin, Pn, Vn, ev, _, _ = ca.ca_update(s.L, w, K, G1, G2, phi, P, Vc,
-                                              s.step, seed, p)
+                                              s.step, seed, p, G3 if p.drug3 else None)
     w_out = s.w
     if p.vegf:
         w_out, nb, nd = vascular.vessel_update(Ln, w, V, s.step, seed, p)
         ev = dict(ev, births=nb, deaths=nd)
-    return State(Ln, K, G1, G2, Pn, Vn, phin, s.step + 1, V, w_out), ev
+    return State(Ln, K, G1, G2, Pn, Vn, phin, s.step + 1, V, w_out, G3), ev

@@ -18,9 +18,24 @@ dG/dt = -v_max G/(k_m + G) instead of its linear regime: separating variables,
 k_m ln(G/G_m) + G - G_m = -v_max (t - t_m), i.e.
 G = k_m W((G_m/k_m) exp((G_m - v_max (t - t_m))/k_m)) with W the principal
 branch of the Lambert W function.
+
+``plasma_epi`` is epirubicin's three-compartment model (the third drug): a
+plasma compartment G0 exchanging with two peripheral compartments G1, G2,
+all three expressed as amounts over the plasma volume w1 (so G0 is the
+plasma concentration), with the rate constants of Table 1's volumes and
+clearances, k10 = cl/w1, k12 = q2/w1, k21 = q2/w2, k13 = q3/w1, k31 = q3/w3:
+    dG0/dt = -(k10 + k12 + k13) G0 + k21 G1 + k31 G2
+    dG1/dt = k12 G0 - k21 G1
+    dG2/dt = k13 G0 - k31 G2
+(the printed plasma equation has G_{2,1}, G_{2,2} where its two outflow
+terms need G_{2,0}; the peripheral equations are as printed).  A bolus resets
+the plasma level to a_m G_ref, the peripheral compartments keep their
+content.  Between doses the state follows exp(M dt), M the rate matrix above.
 """
 import math
 
+import numpy as np
+from scipy.linalg import expm
 from scipy.special import lambertw
 
 
@@ -62,3 +77,31 @@ def plasma_mm(t, dose_times, dose_amts, vmax, km, G_ref):
         if abs(dw) <= 1e-16 * w:
             break
     return km * w
+
+
+def epi_rate_matrix(p):
+    """Rate matrix M of the three-compartment model (state G0, G1, G2)."""
+    k10, k12, k13 = p.epi_cl / p.epi_w1, p.epi_q2 / p.epi_w1, p.epi_q3 / p.epi_w1
+    k21, k31 = p.epi_q2 / p.epi_w2, p.epi_q3 / p.epi_w3
+    return np.array([[-(k10 + k12 + k13), k21, k31],
+                     [k12, -k21, 0.0],
+                     [k13, 0.0, -k31]])
+
+
+def plasma_epi(t, dose_times, dose_amts, p):
+    """Epirubicin plasma level at t: doses in ascending time order, each
+    resetting G0 to a_m G_ref3 after the state has followed exp(M dt) from the
+    previous dose; 0 before the first dose."""
+    M = epi_rate_matrix(p)
+    x = np.zeros(3)
+    tc = None
+    for tm, am in zip(dose_times, dose_amts):
+        if tm > t:
+            break
+        if tc is not None:
+            x = expm(M * (tm - tc)) @ x
+        x[0] = am * p.G_ref3
+        tc = tm
+    if tc is None:
+        return 0.0
+    return float((expm(M * (t - tc)) @ x)[0])
