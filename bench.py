@@ -45,7 +45,13 @@ same metric beside the plain one:
              in the same batch as the other three and the vessel birth-death
              update every 720 min, 48 steps (two updates): step time beside
              the plain one, vessel events, and the vessel kernel's duration
-             (off by default).
+             (off by default);
+  fec        the plain 128^3 workload with the full FEC cocktail: epirubicin
+             as a third drug (three-compartment plasma kinetics, its own
+             tissue field and kill trial) dosed with the other two, 48 steps;
+             alone, and with every option at once (exact Michaelis-Menten
+             fluorouracil, VEGF and vessel updates: five fields per batched
+             solve) (off by default).
 """
 import argparse
 import json
@@ -387,6 +393,25 @@ def vegf_leg(stream, steps=48):
             "kernel_classes": len(names)}
 
 
+def fec_leg(stream, steps=48):
+    """The plain workload with the third drug, and with every option."""
+    from paper_2105_00448_amd import hca
+    reps, _, _ = make_workload("plain128")
+    cell, w, seed, (times, amts) = reps[0]
+    reps3 = [(cell, w, seed, (times + (times[0],), amts + (amts[0],)))]
+    nvox = cell.size
+    out = {"workload": f"plain 128^3 workload with epirubicin as a third drug dosed with the other two "
+                       f"(steps 0 and 50), {steps} steps", "unit": "voxel-steps/s"}
+    for name, kw in (("plain", {}), ("drug3", dict(drug3=1)),
+                     ("all_options", dict(drug3=1, vegf=1, pk_mm=1))):
+        print(f"[bench:fec] {name}, {steps} steps", file=sys.stderr, flush=True)
+        el, st, _ = timed_run(reps3, hca.default_params(**kw), steps, stream)
+        out[name] = {"value": nvox * steps / el, "ms_per_step": el / steps * 1e3,
+                     "cg_iters_last_step": list(st[0]["cg_iters"]) + [st[0]["cg_iters_drug3"]],
+                     "kills": st[0]["total_kills"], "cancer_end": st[0]["n_cancer"]}
+    return out
+
+
 def paper2d_leg(stream, steps=10, batch=64):
     """Time per 30-min update of the paper's 2-D performance setting."""
     from paper_2105_00448_amd import hca, synth
@@ -423,7 +448,8 @@ def main():
                     help="timed repeats from a fresh context; value = median")
     ap.add_argument("--no-legs", action="store_true", help="plain workload only")
     ap.add_argument("--legs", default="surrogate,batched",
-                    help="comma-separated further legs: surrogate, batched, substeps, newton, paper2d, vegf")
+                    help="comma-separated further legs: surrogate, batched, substeps, newton, paper2d, "
+                         "vegf, fec")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -568,6 +594,8 @@ def main():
         rec["newton"] = newton_leg(stream)
     if "vegf" in legs:
         rec["vegf"] = vegf_leg(stream)
+    if "fec" in legs:
+        rec["fec"] = fec_leg(stream)
     if "paper2d" in legs:
         rec["paper2d"] = paper2d_leg(stream)
     if not args.no_cpu_baseline:

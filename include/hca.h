@@ -53,13 +53,15 @@ typedef enum hca_status {
 typedef enum hca_field {
   HCA_F_O2 = 0, HCA_F_DRUG1 = 1, HCA_F_DRUG2 = 2, HCA_F_CELL = 3 /* uint8 */,
   HCA_F_P53 = 4, HCA_F_VEGF_IC = 5, HCA_F_PHI = 6, HCA_F_VESSEL_W = 7,
-  HCA_F_VEGF = 8 /* extracellular VEGF V; only with params.vegf */
+  HCA_F_VEGF = 8 /* extracellular VEGF V; only with params.vegf */,
+  HCA_F_DRUG3 = 9 /* third drug (epirubicin) in the tissue; only with params.drug3 */
 } hca_field;
 
 /* Phases of one coupled step n -> n+1 (loop body of Algorithm 1). */
 enum {
   HCA_PH_O2 = 1u << 0,      /* plasma kinetics + oxygen solve                 */
-  HCA_PH_DRUGS = 1u << 1,   /* plasma kinetics + both drug solves             */
+  HCA_PH_DRUGS = 1u << 1,   /* plasma kinetics + the drug solves (two; three
+                               with params.drug3)                            */
   HCA_PH_ODE = 1u << 2,     /* intracellular ODEs with the current K          */
   HCA_PH_CA = 1u << 3,      /* cellular automaton propose/resolve/finalize,
                                then (params.vegf) the vessel update when due  */
@@ -146,6 +148,22 @@ typedef struct hca_params {
   double p_death;          /* in [0, 1] (0.05)                                  */
   double birth_per_V;      /* mL/ug, birth_per_V * V_high <= 1 (100)           */
   double w_new;            /* perfusion weight of a new vessel, > 0 (1)         */
+  /* third drug, epirubicin: three-compartment plasma kinetics with the
+     plasma level G0 and two peripheral compartments (amounts over the plasma
+     volume w1), k10 = cl/w1, k12 = q2/w1, k21 = q2/w2, k13 = q3/w1, k31 = q3/w3:
+       G0' = -(k10 + k12 + k13) G0 + k21 G1 + k31 G2, G1' = k12 G0 - k21 G1,
+       G2' = k13 G0 - k31 G2;
+     a bolus (hca_replicate.dose_*3) resets G0 to amount x G_ref3, the
+     peripheral compartments keep their content.  With drug3 = 1 the tissue
+     field G3 (HCA_F_DRUG3, 0 at init) follows Eq. (chemo) with D_G, psi_G,
+     kappa_G, and a committed cell draws a third kill trial
+     I(G3/G_ref3; 1, b_int3) with the third word of its kill Philox block. */
+  int32_t drug3;           /* 0 off (0), 1 on                                   */
+  double epi_w1, epi_w2, epi_w3;   /* compartment volumes, mL (18e3, 957e3, 25e3) */
+  double epi_q2, epi_q3;   /* intercompartmental clearances, mL/min (918, 250)  */
+  double epi_cl;           /* elimination clearance, mL/min (983)               */
+  double G_ref3;           /* kill-probability normalisation (1)                */
+  int32_t b_int3;          /* dose-response shape, 1..64 (1)                     */
 } hca_params;
 
 /* One replicate's inputs.  hca_init deep-copies every array; the caller keeps
@@ -158,6 +176,9 @@ typedef struct hca_replicate {
   int32_t n_doses[2];          /* doses per drug, <= HCA_MAX_DOSES             */
   const double* dose_t_min[2]; /* dose times (min), ascending                  */
   const double* dose_amt[2];   /* dose amounts, multiples of G_ref             */
+  int32_t n_doses3;            /* third drug (read only with params.drug3)      */
+  const double* dose_t_min3;
+  const double* dose_amt3;
 } hca_replicate;
 
 typedef struct hca_stats_s {
@@ -180,6 +201,9 @@ typedef struct hca_stats_s {
   int32_t cg_iters_vegf;
   double cg_relres_vegf;
   int64_t vessel_births, vessel_deaths, total_births, total_deaths;
+  /* third-drug option: its last solve */
+  int32_t cg_iters_drug3;
+  double cg_relres_drug3;
 } hca_stats_t;
 
 typedef struct hca_ctx hca_ctx;

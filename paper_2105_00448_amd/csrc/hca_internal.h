@@ -67,12 +67,19 @@ struct DevParams {
   double aV, psi_V, sec_V;
   long long dv_steps;         // coupled steps per vessel update
   double V_low, V_high, p_death, birth_per_V, w_new;
+  // third drug (field 3 of the solver arrays): three-compartment plasma
+  // propagator exp(M t) = S diag(e^{lam t}) S^-1 (row-major 3x3), its kill
+  // trial; fV = the VEGF field's index (3 + drug3)
+  int drug3, fV;
+  double epi_lam[3], epi_S[9], epi_Si[9];
+  double G_ref3;
+  int b3;
 };
 
 // One replicate on the device, or (in the solver's tables) one linear system:
-// system s = field * nreps + rep, field 0 oxygen, 1 and 2 the drugs, 3 the
-// extracellular VEGF (vegf option), its unknowns at [off, off + n) of the
-// nf x total-voxel solver arrays.
+// system s = field * nreps + rep, field 0 oxygen, 1 and 2 the drugs, then
+// the third drug (drug3 option) and the extracellular VEGF (vegf option), its
+// unknowns at [off, off + n) of the nf x total-voxel solver arrays.
 struct RepDev {
   int nx, ny, nz, pad0;
   long long off;              // first voxel in the concatenated arrays
@@ -80,8 +87,8 @@ struct RepDev {
   unsigned long long seed;
   int flat_b0, flat_nb;       // range in the flat block table
   int tile_b0, tile_nb;       // range in the stencil tile table
-  int ndose[2];
-  int dose_off;               // into the dose arrays (2*HCA_MAX_DOSES per rep)
+  int ndose[3];
+  int dose_off;               // into the dose arrays (3*HCA_MAX_DOSES per rep)
   int tx;                     // stencil tile width (tile = tx x (kBlock/tx) columns)
   double a;                   // systems: face coupling D/h^2 of the field
 };
@@ -169,14 +176,14 @@ inline int grid_for(int n, int max_blocks) {
 
 // ---- launchers (defined in the .hip files) --------------------------------
 // setup / init / plasma kinetics (k_setup.hip)
-// Plasma levels at the ends of field substep j: g0[2 rep + drug] at the end,
-// g0[2 nreps + 2 rep + drug] at the start.
+// Plasma levels at the ends of field substep j: g0[3 rep + drug] at the end,
+// g0[3 nreps + 3 rep + drug] at the start (drug 2, the third, with drug3).
 void launch_plasma(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
                    int j, const double* dose_t, const double* dose_a, double* g0);
 void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
                      const double* vw, const double* K, double* c, double* b, int steady);
-// All systems of a field substep at once: F = [K | G1 | G2] (3 x ntot), or
-// [K | G1 | G2 | V] with vegf (V's source from Vc); c and b of the same layout.
+// All systems of a field substep at once: F = [K | G1 | G2] (3 x ntot), then
+// G3 (drug3) and V (vegf, its source from Vc); c and b of the same layout.
 void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
                        const uint8_t* L, const double* vw, const double* F, const double* Vc,
                        const double* g0, double* c, double* b);
@@ -303,7 +310,7 @@ void launch_ode(hipStream_t s, const Work& w, const DevParams& p, const uint8_t*
 // CA and stats (k_ca.hip)
 void launch_ca_propose(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
                        const uint8_t* L, const double* vw, const double* K, const double* G1,
-                       const double* G2, const double* phi, uint8_t* code);
+                       const double* G2, const double* G3, const double* phi, uint8_t* code);
 void launch_ca_resolve(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
                        const double* phi, const uint8_t* code, uint8_t* win);
 // Event and census counts: each flat work item stores kCounterSlots partials

@@ -4,7 +4,7 @@
 //
 // propose   a cancer cell with phi >= 1 is committed.  One Philox4x64-10 block
 //           (key (seed, 0), counter (gid, n+1, KILL, 0)) gives one uniform per
-//           drug; drug i kills with probability I(x_i; 1, b_i) = 1 - (1-x_i)^b_i,
+//           drug (words 0, 1, and 2 for the third drug); drug i kills with probability I(x_i; 1, b_i) = 1 - (1-x_i)^b_i,
 //           x_i = clip(G_i / G_ref_i, 0, 1), the power by repeated products.
 //           A surviving cell proposes the empty non-vessel Moore neighbour of
 //           highest oxygen (first strict maximum in ascending gid order), else
@@ -100,6 +100,7 @@ __global__ void __launch_bounds__(kBlock) k_ca_propose(Work w, DevParams p,
                                                        const double* __restrict__ K,
                                                        const double* __restrict__ G1,
                                                        const double* __restrict__ G2,
+                                                       const double* __restrict__ G3,
                                                        const double* __restrict__ phi,
                                                        uint8_t* __restrict__ code) {
   const long long step = d_step[0];
@@ -112,7 +113,9 @@ __global__ void __launch_bounds__(kBlock) k_ca_propose(Work w, DevParams p,
       const double u0 = unit53(o.v[0]), u1 = unit53(o.v[1]);
       const double p1 = kill_probability(G1[i], p.G_ref[0], p.b_int[0]);
       const double p2 = kill_probability(G2[i], p.G_ref[1], p.b_int[1]);
-      if (u0 < p1 || u1 < p2) {
+      // the third drug (drug3) draws its trial from the block's third word
+      const bool kill3 = p.drug3 && unit53(o.v[2]) < kill_probability(G3[i], p.G_ref3, p.b3);
+      if (u0 < p1 || u1 < p2 || kill3) {
         cd = kCodeKill;
       } else {
         const VoxelCoord v = coord_of(li, rp);
@@ -393,9 +396,9 @@ __global__ void __launch_bounds__(kBlock) k_validate_cells(Work w, const uint8_t
 
 void launch_ca_propose(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
                        const uint8_t* L, const double* vw, const double* K, const double* G1,
-                       const double* G2, const double* phi, uint8_t* code) {
+                       const double* G2, const double* G3, const double* phi, uint8_t* code) {
   hca_launch(k_ca_propose, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, d_step, L, vw, K, G1,
-                     G2, phi, code);
+             G2, G3, phi, code);
 }
 
 void launch_ca_resolve(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,

@@ -64,6 +64,37 @@ __device__ inline double plasma_level(const RepDev& rp, const DevParams& p, cons
   return g * exp(-p.k_pk[i] * (t - tm));
 }
 
+// x <- exp(M dt) x for the three-compartment state, M = S diag(lam) S^-1.
+__device__ inline void epi_propagate(const DevParams& p, double (&x)[3], double dt) {
+  double y[3];
+  for (int i = 0; i < 3; ++i)
+    y[i] = (p.epi_Si[3 * i] * x[0] + p.epi_Si[3 * i + 1] * x[1] + p.epi_Si[3 * i + 2] * x[2]) *
+           exp(p.epi_lam[i] * dt);
+  for (int i = 0; i < 3; ++i) x[i] = p.epi_S[3 * i] * y[0] + p.epi_S[3 * i + 1] * y[1] + p.epi_S[3 * i + 2] * y[2];
+}
+
+// The third drug's (epirubicin's) plasma level at t: from an empty state,
+// each bolus t_k <= t (ascending) resets the plasma compartment to
+// a_k G_ref3 after the state has followed the three-compartment model from
+// the previous bolus; 0 before the first.
+__device__ inline double epi_level(const RepDev& rp, const DevParams& p, const double* dose_t,
+                                   const double* dose_a, double t) {
+  double x[3] = {0.0, 0.0, 0.0};
+  double tc = 0.0;
+  bool any = false;
+  for (int k = 0; k < rp.ndose[2]; ++k) {
+    const double td = dose_t[rp.dose_off + 2 * HCA_MAX_DOSES + k];
+    if (td > t) break;
+    if (any) epi_propagate(p, x, td - tc);
+    x[0] = dose_a[rp.dose_off + 2 * HCA_MAX_DOSES + k] * p.G_ref3;
+    tc = td;
+    any = true;
+  }
+  if (!any) return 0.0;
+  epi_propagate(p, x, t - tc);
+  return x[0];
+}
+
 // Levels at the end (t^n + (j+1) tau; t^{n+1} for a single substep) and the
 // start (t^n + j tau) of field substep j.
 __global__ void k_plasma(int nreps, const RepDev* reps, DevParams p, const long long* d_step, int j,
@@ -74,8 +105,12 @@ __global__ void k_plasma(int nreps, const RepDev* reps, DevParams p, const long 
   const double t_new = p.nsub_pde == 1 ? (double)(d_step[0] + 1) * p.dt : t_old + p.tau;
   const RepDev rp = reps[r];
   for (int i = 0; i < 2; ++i) {
-    g0[2 * r + i] = plasma_level(rp, p, dose_t, dose_a, i, t_new);
-    g0[2 * nreps + 2 * r + i] = plasma_level(rp, p, dose_t, dose_a, i, t_old);
+    g0[3 * r + i] = plasma_level(rp, p, dose_t, dose_a, i, t_new);
+    g0[3 * nreps + 3 * r + i] = plasma_level(rp, p, dose_t, dose_a, i, t_old);
+  }
+  if (p.drug3) {
+    g0[3 * r + 2] = epi_level(rp, p, dose_t, dose_a, t_new);
+    g0[3 * nreps + 3 * r + 2] = epi_level(rp, p, dose_t, dose_a, t_old);
   }
 }
 
@@ -120,7 +155,8 @@ __global__ void __launch_bounds__(kBlock) k_setup_o2(Work w, DevParams p, const 
 //   oxygen: R = r_k w + phi_K chi/(K1 + K) (uptake linearised at the substep's
 //           start), S = r_k w K0 constant;
 //   drugs:  R = psi_G + kappa_G w, S = kappa_G w g0(t) with the plasma level
-//           at the substep's end (weight theta) and start (1 - theta).
+//           at the substep's end (weight theta) and start (1 - theta); the
+//           third drug (drug3) likewise in field 3;
 //   VEGF (vegf): R = psi_V, S = sec_V V_c chi, Eq. (vac_v) with no Avastin,
 //           V_c of the coupled step's start at both ends of every substep.
 // With one backward-Euler substep these are the coupled step's systems
@@ -145,13 +181,13 @@ __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long
     const double kw = p.kappa_G * wv;
     const double cg = p.inv_tau + th * p.psi_G + th * kw;
     const double rg = p.psi_G + kw;
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < 2 + p.drug3; ++i) {   // drug i in field i + 1
       const long long j = g + (i + 1) * ntot;
       c[j] = cg;
-      b[j] = F[j] * (p.inv_tau - th1 * rg) + kw * (th * g0[2 * rep + i] + th1 * g0[2 * w.nreps + 2 * rep + i]);
+      b[j] = F[j] * (p.inv_tau - th1 * rg) + kw * (th * g0[3 * rep + i] + th1 * g0[3 * w.nreps + 3 * rep + i]);
     }
     if (p.vegf) {
-      const long long j = g + 3 * ntot;
+      const long long j = g + (long long)p.fV * ntot;
       c[j] = p.inv_tau + th * p.psi_V;
       b[j] = F[j] * (p.inv_tau - th1 * p.psi_V) + p.sec_V * Vc[g] * chi;
     }
@@ -204,7 +240,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs_lap(Work w, DevParams p, long lo
       if (y + 1 < rp.ny) lap += u[g + sy] - uc;
       if (z > 0) lap += u[g - sz] - uc;
       if (z + 1 < rp.nz) lap += u[g + sz] - uc;
-      b[g + (long long)f * ntot] += (f == 0 ? sK : f == 3 ? sV : sG) * lap;
+      b[g + (long long)f * ntot] += (f == 0 ? sK : (p.vegf && f == p.fV) ? sV : sG) * lap;
     }
   });
 }

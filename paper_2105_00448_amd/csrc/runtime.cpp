@@ -68,7 +68,8 @@ const double kBytesPerVoxel[KC_COUNT] = {
     73.0,         // mlp apply: read L, K, G1, G2, P, Vc, phi; write P, Vc, phi
     17.0};        // vessel: read L, w, V (writes only where a vessel changes)
 constexpr double kBytesSetupVegf = 32.0;   // setup_step with vegf: + read V, Vc; write c, b
-constexpr double kBytesStatsVegf = 8.0;    // stats with vegf: + read V
+constexpr double kBytesSetupDrug3 = 24.0;  // setup_step with drug3: + read G3; write c, b
+constexpr double kBytesStatsField = 8.0;   // stats: per extra field scanned (V, G3)
 constexpr double kBytesUpdateMg = 56.0;   // cg_update, multigrid: read x, p, r, q, z (4); write x, r, r (4)
 constexpr double kBytesApplyJacobi = 40.0;   // cg_apply, Jacobi: z is FP64
 
@@ -108,7 +109,8 @@ struct hca_ctx {
   uint8_t *L = nullptr, *code = nullptr, *win = nullptr;
   double *w = nullptr, *P = nullptr, *Vc = nullptr, *phi = nullptr;
   double* F = nullptr;                          // [K | G1 | G2], with vegf [K | G1 | G2 | V]
-  double *K = nullptr, *G1 = nullptr, *G2 = nullptr, *V = nullptr;
+  double *K = nullptr, *G1 = nullptr, *G2 = nullptr, *G3 = nullptr, *V = nullptr;
+  int nstat_fields = 6;                         // fields of the non-finite scan
   // solver, nf x ntot (nf = dp.nf fields)
   double *c = nullptr, *b = nullptr;
   SolverBufs sb{};
@@ -201,8 +203,9 @@ hipEvent_t take_event(hca_ctx* c) {
 double bpv_of(const hca_ctx* c, int kc) {
   if (kc == KC_CG_UPDATE && c->use_mg) return kBytesUpdateMg;
   if (kc == KC_CG_APPLY && !c->use_mg) return kBytesApplyJacobi;
-  if (kc == KC_SETUP && c->dp.vegf) return kBytesPerVoxel[kc] + kBytesSetupVegf;
-  if (kc == KC_STATS && c->dp.vegf) return kBytesPerVoxel[kc] + kBytesStatsVegf;
+  if (kc == KC_SETUP)
+    return kBytesPerVoxel[kc] + (c->dp.vegf ? kBytesSetupVegf : 0.0) + (c->dp.drug3 ? kBytesSetupDrug3 : 0.0);
+  if (kc == KC_STATS) return kBytesPerVoxel[kc] + (c->nstat_fields - 6) * kBytesStatsField;
   return kBytesPerVoxel[kc];
 }
 
@@ -323,6 +326,71 @@ void run_vcycle(hca_ctx* c, const Work& W, const MgBufs& mg, int tag) {
   launch_mg_vcycle(c->stream, W, mg, c->sb, mg_hook, &mp);
 }
 
+// The third drug's propagator exp(M t) = S diag(e^{lam t}) S^-1.  M (state
+// G0, G1, G2) is similar to the symmetric Ms = D^{1/2} M D^{-1/2} with
+// D = diag(1, w1/w2, w1/w3): Ms_00 = -(k10 + k12 + k13), Ms_11 = -k21,
+// Ms_22 = -k31, Ms_01 = q2/sqrt(w1 w2), Ms_02 = q3/sqrt(w1 w3), Ms_12 = 0.
+// Cyclic Jacobi rotations give Ms = Q diag(lam) Q^T; then S = D^{-1/2} Q and
+// S^-1 = Q^T D^{1/2}.
+void epi_propagator(const hca_params& p, DevParams& d) {
+  const double k10 = p.epi_cl / p.epi_w1, k12 = p.epi_q2 / p.epi_w1, k13 = p.epi_q3 / p.epi_w1;
+  const double k21 = p.epi_q2 / p.epi_w2, k31 = p.epi_q3 / p.epi_w3;
+  double A[3][3] = {{-(k10 + k12 + k13), p.epi_q2 / std::sqrt(p.epi_w1 * p.epi_w2),
+                     p.epi_q3 / std::sqrt(p.epi_w1 * p.epi_w3)},
+                    {0.0, -k21, 0.0},
+                    {0.0, 0.0, -k31}};
+  A[1][0] = A[0][1];
+  A[2][0] = A[0][2];
+  double Q[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (off <= 1e-34 * dia) break;
+    for (int a = 0; a < 2; ++a)
+      for (int b = a + 1; b < 3; ++b) {
+        if (A[a][b] == 0.0) continue;
+        // rotation in the (a, b) plane that zeroes A[a][b]
+        const double th = (A[b][b] - A[a][a]) / (2.0 * A[a][b]);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        double J[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+        J[a][a] = cs;
+        J[b][b] = cs;
+        J[a][b] = sn;
+        J[b][a] = -sn;
+        double T[3][3], N[3][3], Qn[3][3];
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) {
+            T[i][j] = 0.0;
+            for (int k = 0; k < 3; ++k) T[i][j] += A[i][k] * J[k][j];
+          }
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) {
+            N[i][j] = 0.0;
+            Qn[i][j] = 0.0;
+            for (int k = 0; k < 3; ++k) {
+              N[i][j] += J[k][i] * T[k][j];
+              Qn[i][j] += Q[i][k] * J[k][j];
+            }
+          }
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) {
+            A[i][j] = N[i][j];
+            Q[i][j] = Qn[i][j];
+          }
+        A[a][b] = A[b][a] = 0.0;
+      }
+  }
+  const double dd[3] = {1.0, p.epi_w1 / p.epi_w2, p.epi_w1 / p.epi_w3};
+  for (int i = 0; i < 3; ++i) {
+    d.epi_lam[i] = A[i][i];
+    for (int j = 0; j < 3; ++j) {
+      d.epi_S[3 * i + j] = Q[i][j] / std::sqrt(dd[i]);
+      d.epi_Si[3 * i + j] = Q[j][i] * std::sqrt(dd[j]);
+    }
+  }
+}
+
 DevParams make_dev_params(const hca_params& p) {
   DevParams d{};
   d.dt = p.dt_min;
@@ -335,7 +403,12 @@ DevParams make_dev_params(const hca_params& p) {
   d.mm_vmax = p.mm_vmax;
   d.mm_km = p.mm_km;
   d.vegf = p.vegf;
-  d.nf = p.vegf ? 4 : 3;
+  d.drug3 = p.drug3;
+  d.nf = 3 + p.drug3 + p.vegf;
+  d.fV = 3 + p.drug3;
+  d.G_ref3 = p.G_ref3;
+  d.b3 = p.b_int3;
+  if (p.drug3) epi_propagator(p, d);
   d.aV = p.D_V / (p.h_um * p.h_um);
   d.psi_V = p.psi_V;
   d.sec_V = p.sec_V;
@@ -490,8 +563,9 @@ hca_status solve(hca_ctx* c, const Work& W, const MgBufs& mg, unsigned fmask, do
 hca_status run_phases(hca_ctx* c, unsigned mask) {
   const Work& wk = c->work;
   hipStream_t s = c->stream;
-  const unsigned fmask = ((mask & HCA_PH_O2) ? 1u : 0u) | ((mask & HCA_PH_DRUGS) ? 6u : 0u) |
-                         (((mask & HCA_PH_VEGF) && c->dp.vegf) ? 8u : 0u);
+  const unsigned drugs = c->dp.drug3 ? 14u : 6u;   // fields 1, 2 (and 3)
+  const unsigned fmask = ((mask & HCA_PH_O2) ? 1u : 0u) | ((mask & HCA_PH_DRUGS) ? drugs : 0u) |
+                         (((mask & HCA_PH_VEGF) && c->dp.vegf) ? (1u << c->dp.fV) : 0u);
   // the field solves: pde_substeps theta-scheme substeps (one by default)
   for (int j = 0; fmask && j < c->dp.nsub_pde; ++j) {
     {
@@ -531,7 +605,8 @@ hca_status run_phases(hca_ctx* c, unsigned mask) {
   if (mask & HCA_PH_CA) {
     {
       ProfScope ps(c, KC_CA_PROPOSE, kTagState);
-      launch_ca_propose(s, wk, c->dp, c->d_step, c->L, c->w, c->K, c->G1, c->G2, c->phi, c->code);
+      launch_ca_propose(s, wk, c->dp, c->d_step, c->L, c->w, c->K, c->G1, c->G2, c->G3, c->phi,
+                        c->code);
     }
     {
       ProfScope ps(c, KC_CA_RESOLVE, kTagState);
@@ -548,7 +623,7 @@ hca_status run_phases(hca_ctx* c, unsigned mask) {
   }
   if (mask & HCA_PH_STATS) {
     ProfScope ps(c, KC_STATS, kTagState);
-    launch_stats(s, wk, c->L, c->w, c->d_fields, c->dp.vegf ? 7 : 6, c->d_cpart, c->d_cnt);
+    launch_stats(s, wk, c->L, c->w, c->d_fields, c->nstat_fields, c->d_cpart, c->d_cnt);
   }
   if (mask & HCA_PH_ADVANCE) {
     launch_advance(s, c->d_step);
@@ -606,17 +681,18 @@ hca_status validate_reps(const hca_replicate* reps, int n, std::string& msg, int
       nves += wv > 0.0;
     }
     if (nves == 0 && singular < 0) singular = r;
-    for (int d = 0; d < 2; ++d) {
-      if (R.n_doses[d] < 0 || R.n_doses[d] > HCA_MAX_DOSES ||
-          (R.n_doses[d] > 0 && (!R.dose_t_min[d] || !R.dose_amt[d]))) {
+    for (int d = 0; d < 3; ++d) {
+      const int nd = d < 2 ? R.n_doses[d] : R.n_doses3;
+      const double* ts = d < 2 ? R.dose_t_min[d] : R.dose_t_min3;
+      const double* as = d < 2 ? R.dose_amt[d] : R.dose_amt3;
+      if (nd < 0 || nd > HCA_MAX_DOSES || (nd > 0 && (!ts || !as))) {
         snprintf(buf, sizeof buf, "replicate %d drug %d: bad dose list", r, d);
         msg = buf;
         return HCA_E_INVALID;
       }
-      for (int k = 0; k < R.n_doses[d]; ++k) {
-        if (!std::isfinite(R.dose_t_min[d][k]) || !std::isfinite(R.dose_amt[d][k]) ||
-            R.dose_t_min[d][k] < 0.0 || R.dose_amt[d][k] < 0.0 ||
-            (k > 0 && R.dose_t_min[d][k] < R.dose_t_min[d][k - 1])) {
+      for (int k = 0; k < nd; ++k) {
+        if (!std::isfinite(ts[k]) || !std::isfinite(as[k]) || ts[k] < 0.0 || as[k] < 0.0 ||
+            (k > 0 && ts[k] < ts[k - 1])) {
           snprintf(buf, sizeof buf, "replicate %d drug %d: dose %d not finite, negative or unsorted",
                    r, d, k);
           msg = buf;
@@ -674,6 +750,16 @@ hca_status validate_params(const hca_params* p, std::string& msg) {
         !(p->birth_per_V * p->V_high <= 1.0) || !(p->w_new > 0.0)) {
       msg = "vegf in {0, 1}; D_V > 0, psi_V >= 0, sec_V >= 0; dv_min a whole multiple of dt_min; "
             "0 <= V_low <= V_high; p_death in [0, 1]; 0 <= birth_per_V <= 1 / V_high; w_new > 0";
+      return HCA_E_INVALID;
+    }
+  }
+  {
+    auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+    auto nonneg = [](double v) { return std::isfinite(v) && v >= 0.0; };
+    if ((p->drug3 != 0 && p->drug3 != 1) || !pos(p->epi_w1) || !pos(p->epi_w2) || !pos(p->epi_w3) ||
+        !nonneg(p->epi_q2) || !nonneg(p->epi_q3) || !nonneg(p->epi_cl) || !pos(p->G_ref3) ||
+        p->b_int3 < 1 || p->b_int3 > 64) {
+      msg = "drug3 in {0, 1}; epi_w* > 0; epi_q2, epi_q3, epi_cl >= 0; G_ref3 > 0; b_int3 in 1..64";
       return HCA_E_INVALID;
     }
   }
@@ -920,9 +1006,10 @@ hca_status build_tables(hca_ctx* c, const hca_replicate* in) {
     std::vector<Tile> tiles;
     for (int r = 0; r < R; ++r) {
       RepDev d = lattice_entry(c->reps[r], c->reps[r].off, r, flat, tiles);
-      d.dose_off = r * 2 * HCA_MAX_DOSES;
+      d.dose_off = r * 3 * HCA_MAX_DOSES;
       d.ndose[0] = in[r].n_doses[0];
       d.ndose[1] = in[r].n_doses[1];
+      d.ndose[2] = in[r].n_doses3;
       rd.push_back(d);
     }
     hca_status st;
@@ -948,7 +1035,7 @@ hca_status build_tables(hca_ctx* c, const hca_replicate* in) {
         RepDev d = lattice_entry(c->reps[r], (long long)f * c->ntot + c->reps[r].off, f * R + r,
                                  flat, tiles);
         // the theta scheme's implicit coupling
-        d.a = (f == 0 ? c->dp.aK : f == 3 ? c->dp.aV : c->dp.aG) * c->dp.theta;
+        d.a = (f == 0 ? c->dp.aK : (c->dp.vegf && f == c->dp.fV) ? c->dp.aV : c->dp.aG) * c->dp.theta;
         sd.push_back(d);
         c->sys_n.push_back(c->reps[r].n);
       }
@@ -1008,7 +1095,8 @@ hca_status alloc_all(hca_ctx* c) {
   c->K = c->F;
   c->G1 = c->F + n;
   c->G2 = c->F + 2 * n;
-  c->V = c->dp.vegf ? c->F + 3 * n : nullptr;
+  c->G3 = c->dp.drug3 ? c->F + 3 * n : nullptr;
+  c->V = c->dp.vegf ? c->F + (size_t)c->dp.fV * n : nullptr;
   c->sb.jacobi = c->use_mg ? 0 : 1;
   if (!c->use_mg && (st = big(&c->sb.dinv, n3)) != HCA_OK) return st;
   const size_t nwork = (size_t)std::max(c->sys_all.ntiles, c->sys_all.nflat);
@@ -1018,17 +1106,20 @@ hca_status alloc_all(hca_ctx* c) {
   HIPCHK(c, dalloc(&c->sb.ss, nsys));
   HIPCHK(c, hipMemset(c->sb.ss, 0, sizeof(SolveScal) * nsys));
   HIPCHK(c, dalloc(&c->sb.ndone, 1));
-  HIPCHK(c, dalloc(&c->dose_t, (size_t)c->nreps * 2 * HCA_MAX_DOSES));
-  HIPCHK(c, dalloc(&c->dose_a, (size_t)c->nreps * 2 * HCA_MAX_DOSES));
-  HIPCHK(c, dalloc(&c->g0, (size_t)c->nreps * 4));   // levels at both ends of a field substep
+  HIPCHK(c, dalloc(&c->dose_t, (size_t)c->nreps * 3 * HCA_MAX_DOSES));
+  HIPCHK(c, dalloc(&c->dose_a, (size_t)c->nreps * 3 * HCA_MAX_DOSES));
+  HIPCHK(c, dalloc(&c->g0, (size_t)c->nreps * 6));   // levels at both ends of a field substep
   if (c->prm.o2_newton > 0 && (st = big(&c->b_o2lin, (size_t)c->ntot)) != HCA_OK) return st;
   HIPCHK(c, dalloc(&c->d_step, 1));
   HIPCHK(c, dalloc(&c->d_cnt, c->nreps));
   HIPCHK(c, dalloc(&c->d_cpart, (size_t)c->work.nflat * kCounterSlots));
   HIPCHK(c, hipMemset(c->d_cnt, 0, sizeof(Counters) * c->nreps));
-  HIPCHK(c, dalloc(&c->d_fields, 7));
+  HIPCHK(c, dalloc(&c->d_fields, 8));
   HIPCHK(c, dalloc(&c->d_bad, 1));
-  const double* fl[7] = {c->K, c->G1, c->G2, c->P, c->Vc, c->phi, c->V};
+  const double* fl[8] = {c->K, c->G1, c->G2, c->P, c->Vc, c->phi, nullptr, nullptr};
+  c->nstat_fields = 6;
+  if (c->V) fl[c->nstat_fields++] = c->V;
+  if (c->G3) fl[c->nstat_fields++] = c->G3;
   HIPCHK(c, hipMemcpy(c->d_fields, fl, sizeof fl, hipMemcpyHostToDevice));
   HIPCHK(c, hipHostMalloc((void**)&c->h_ss, sizeof(SolveScal) * nsys, hipHostMallocDefault));
   HIPCHK(c, hipHostMalloc((void**)&c->h_cnt, sizeof(Counters) * c->nreps, hipHostMallocDefault));
@@ -1306,6 +1397,7 @@ void* field_ptr(hca_ctx* c, hca_field f, size_t& elem) {
     case HCA_F_PHI: return c->phi;
     case HCA_F_VESSEL_W: return c->w;
     case HCA_F_VEGF: return c->V;
+    case HCA_F_DRUG3: return c->G3;
   }
   return nullptr;
 }
@@ -1370,6 +1462,15 @@ hca_status hca_default_params(hca_params* out) {
   out->p_death = 0.05;
   out->birth_per_V = 100.0;
   out->w_new = 1.0;
+  out->drug3 = 0;
+  out->epi_w1 = 18.0e3;
+  out->epi_w2 = 957.0e3;
+  out->epi_w3 = 25.0e3;
+  out->epi_q2 = 0.918e3;
+  out->epi_q3 = 0.25e3;
+  out->epi_cl = 0.983e3;
+  out->G_ref3 = 1.0;
+  out->b_int3 = 1;
   return HCA_OK;
 }
 
@@ -1429,18 +1530,22 @@ hca_status hca_init(hca_ctx** out, const hca_params* p, const hca_replicate* rep
   if ((st = alloc_all(c)) != HCA_OK) return bail(st);
   if (c->use_mg && (st = build_mg(c)) != HCA_OK) return bail(st);
   // upload inputs and dose tables
-  std::vector<double> dt((size_t)n_reps * 2 * HCA_MAX_DOSES, 0.0), da(dt.size(), 0.0);
+  std::vector<double> dt((size_t)n_reps * 3 * HCA_MAX_DOSES, 0.0), da(dt.size(), 0.0);
   for (int r = 0; r < n_reps; ++r) {
     const RepHost& R = c->reps[r];
     if (hipMemcpy(c->L + R.off, reps[r].cell, (size_t)R.n, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->w + R.off, reps[r].vessel_w, (size_t)R.n * 8, hipMemcpyHostToDevice) !=
             hipSuccess)
       return bail(HCA_E_DEVICE);
-    for (int d = 0; d < 2; ++d)
-      for (int k = 0; k < reps[r].n_doses[d]; ++k) {
-        dt[(size_t)r * 2 * HCA_MAX_DOSES + d * HCA_MAX_DOSES + k] = reps[r].dose_t_min[d][k];
-        da[(size_t)r * 2 * HCA_MAX_DOSES + d * HCA_MAX_DOSES + k] = reps[r].dose_amt[d][k];
+    for (int d = 0; d < 3; ++d) {
+      const int nd = d < 2 ? reps[r].n_doses[d] : reps[r].n_doses3;
+      const double* ts = d < 2 ? reps[r].dose_t_min[d] : reps[r].dose_t_min3;
+      const double* as = d < 2 ? reps[r].dose_amt[d] : reps[r].dose_amt3;
+      for (int k = 0; k < nd; ++k) {
+        dt[(size_t)r * 3 * HCA_MAX_DOSES + d * HCA_MAX_DOSES + k] = ts[k];
+        da[(size_t)r * 3 * HCA_MAX_DOSES + d * HCA_MAX_DOSES + k] = as[k];
       }
+    }
   }
   if (hipMemcpy(c->dose_t, dt.data(), dt.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->dose_a, da.data(), da.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
@@ -1454,9 +1559,11 @@ hca_status hca_init(hca_ctx** out, const hca_params* p, const hca_replicate* rep
     return bail(HCA_E_DEVICE);
   if (c->V && hipMemsetAsync(c->V, 0, (size_t)c->ntot * 8, c->stream) != hipSuccess)
     return bail(HCA_E_DEVICE);
+  if (c->G3 && hipMemsetAsync(c->G3, 0, (size_t)c->ntot * 8, c->stream) != hipSuccess)
+    return bail(HCA_E_DEVICE);
   launch_zero_counters(c->stream, c->d_cnt, n_reps, 1);
   launch_zero_counters(c->stream, c->d_cnt, n_reps, 0);
-  launch_stats(c->stream, c->work, c->L, c->w, c->d_fields, c->dp.vegf ? 7 : 6, c->d_cpart, c->d_cnt);
+  launch_stats(c->stream, c->work, c->L, c->w, c->d_fields, c->nstat_fields, c->d_cpart, c->d_cnt);
   if (hipGetLastError() != hipSuccess) return bail(HCA_E_DEVICE);
   if ((st = check_after(c)) != HCA_OK) return bail(st);
   c->last_it[0] = 0;
@@ -1584,9 +1691,12 @@ hca_status hca_stats(hca_ctx* c, int rep, hca_stats_t* out) {
       if (f < 3) {
         out->cg_iters[f] = s.it;
         out->cg_relres[f] = rel;
-      } else {
+      } else if (c->dp.vegf && f == c->dp.fV) {
         out->cg_iters_vegf = s.it;
         out->cg_relres_vegf = rel;
+      } else {
+        out->cg_iters_drug3 = s.it;
+        out->cg_relres_drug3 = rel;
       }
     }
   }

@@ -15,9 +15,9 @@ OK, E_INVALID, E_NOMEM, E_DEVICE, E_NOCONV, E_NONFINITE, E_SINGULAR, E_RANGE = 0
 STATUS_NAMES = {0: "HCA_OK", -1: "HCA_E_INVALID", -2: "HCA_E_NOMEM", -3: "HCA_E_DEVICE",
                 -4: "HCA_E_NOCONV", -5: "HCA_E_NONFINITE", -6: "HCA_E_SINGULAR", -7: "HCA_E_RANGE"}
 
-F_O2, F_DRUG1, F_DRUG2, F_CELL, F_P53, F_VEGF_IC, F_PHI, F_VESSEL_W, F_VEGF = range(9)
+F_O2, F_DRUG1, F_DRUG2, F_CELL, F_P53, F_VEGF_IC, F_PHI, F_VESSEL_W, F_VEGF, F_DRUG3 = range(10)
 FIELDS = {"K": F_O2, "G1": F_DRUG1, "G2": F_DRUG2, "L": F_CELL, "P": F_P53, "Vc": F_VEGF_IC,
-          "phi": F_PHI, "w": F_VESSEL_W, "V": F_VEGF}
+          "phi": F_PHI, "w": F_VESSEL_W, "V": F_VEGF, "G3": F_DRUG3}
 
 PH_O2, PH_DRUGS, PH_ODE, PH_CA, PH_STATS, PH_ADVANCE, PH_VEGF = 1, 2, 4, 8, 16, 32, 64
 PH_ALL = 127
@@ -44,6 +44,9 @@ class Params(C.Structure):
         ("vegf", C.c_int32), ("D_V", C.c_double), ("psi_V", C.c_double), ("sec_V", C.c_double),
         ("dv_min", C.c_double), ("V_low", C.c_double), ("V_high", C.c_double),
         ("p_death", C.c_double), ("birth_per_V", C.c_double), ("w_new", C.c_double),
+        ("drug3", C.c_int32), ("epi_w1", C.c_double), ("epi_w2", C.c_double), ("epi_w3", C.c_double),
+        ("epi_q2", C.c_double), ("epi_q3", C.c_double), ("epi_cl", C.c_double),
+        ("G_ref3", C.c_double), ("b_int3", C.c_int32),
     ]
 
 
@@ -53,6 +56,8 @@ class Replicate(C.Structure):
         ("cell", C.POINTER(C.c_uint8)), ("vessel_w", C.POINTER(C.c_double)),
         ("n_doses", C.c_int32 * 2),
         ("dose_t_min", C.POINTER(C.c_double) * 2), ("dose_amt", C.POINTER(C.c_double) * 2),
+        ("n_doses3", C.c_int32), ("dose_t_min3", C.POINTER(C.c_double)),
+        ("dose_amt3", C.POINTER(C.c_double)),
     ]
 
 
@@ -69,6 +74,7 @@ class Stats(C.Structure):
         ("cg_iters_vegf", C.c_int32), ("cg_relres_vegf", C.c_double),
         ("vessel_births", C.c_int64), ("vessel_deaths", C.c_int64),
         ("total_births", C.c_int64), ("total_deaths", C.c_int64),
+        ("cg_iters_drug3", C.c_int32), ("cg_relres_drug3", C.c_double),
     ]
 
     def as_dict(self):
@@ -173,7 +179,8 @@ class Simulation:
     """One context: a batch of replicates stepped together.
 
     ``replicates``: list of (cell uint8 (nz,ny,nx), w float64 (nz,ny,nx), seed,
-    (dose_times, dose_amts) per drug as a pair of sequences).
+    (dose_times, dose_amts) per drug as a pair of sequences; a third entry in
+    each is the third drug's schedule).
     """
 
     def __init__(self, replicates, params=None, stream=None):
@@ -201,6 +208,13 @@ class Simulation:
                 R.n_doses[d] = len(t)
                 R.dose_t_min[d] = _dptr(t)
                 R.dose_amt[d] = _dptr(a)
+                keep += [t, a]
+            if len(times) > 2:
+                t = np.ascontiguousarray(times[2], dtype=np.float64)
+                a = np.ascontiguousarray(amts[2], dtype=np.float64)
+                R.n_doses3 = len(t)
+                R.dose_t_min3 = _dptr(t)
+                R.dose_amt3 = _dptr(a)
                 keep += [t, a]
         h = C.c_void_p()
         st = self._lib.hca_init(C.byref(h), C.byref(self.params), reps, len(replicates),

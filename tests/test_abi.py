@@ -38,7 +38,8 @@ def test_default_params_match_the_oracle_transcription_of_table1():
                  "k1", "k1p", "K_p53", "k2", "k2p", "k2pp", "J5", "K_V", "K_phi", "T_cycle",
                  "ode_substeps", "pde_substeps", "pde_theta", "o2_newton", "pk_mm", "mm_vmax", "mm_km",
                  "vegf", "D_V", "psi_V", "sec_V", "dv_min", "V_low", "V_high", "p_death",
-                 "birth_per_V", "w_new"]:
+                 "birth_per_V", "w_new", "drug3", "epi_w1", "epi_w2", "epi_w3", "epi_q2", "epi_q3",
+                 "epi_cl", "G_ref3", "b_int3"]:
         assert getattr(p, name) == getattr(ORACLE, name), name
     assert list(p.k_pk) == list(ORACLE.k_pk)
     assert list(p.G_ref) == list(ORACLE.G_ref)
@@ -71,6 +72,13 @@ def init_status(reps, params=None):
             R.n_doses[d] = len(t)
             R.dose_t_min[d] = t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             R.dose_amt[d] = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if len(doses) > 2:   # the third drug's list
+            t = np.asarray(doses[2][0], dtype=np.float64)
+            a = np.asarray(doses[2][1], dtype=np.float64)
+            keep += [t, a]
+            R.n_doses3 = len(t)
+            R.dose_t_min3 = t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            R.dose_amt3 = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     h = ctypes.c_void_p()
     st = lib.hca_init(ctypes.byref(h), ctypes.byref(params), arr, len(reps), None)
     assert not h.value
@@ -104,6 +112,10 @@ def test_rejects_unsorted_or_negative_doses():
     assert init_status([(cell, w, doses)]) == hca.E_INVALID
     doses = (((0.0,), (-1.0,)), ((), ()))
     assert init_status([(cell, w, doses)]) == hca.E_INVALID
+    doses = (((), ()), ((), ()), ((60.0, 30.0), (1.0, 1.0)))      # third drug's list too
+    assert init_status([(cell, w, doses)]) == hca.E_INVALID
+    doses = (((), ()), ((), ()), ((0.0,) * 65, (1.0,) * 65))       # beyond HCA_MAX_DOSES
+    assert init_status([(cell, w, doses)]) == hca.E_INVALID
 
 
 def test_no_vessel_is_singular():
@@ -126,7 +138,9 @@ def test_rejects_bad_params_and_arguments():
                dict(o2_newton=21), dict(pk_mm=2), dict(mm_km=0.0), dict(mm_vmax=-1.0),
                dict(mm_vmax=float("inf")), dict(vegf=2), dict(D_V=0.0), dict(psi_V=-1.0),
                dict(dv_min=45.0), dict(dv_min=15.0), dict(V_low=2e-4), dict(p_death=1.5),
-               dict(birth_per_V=2.0e4), dict(w_new=0.0), dict(sec_V=float("nan"))):
+               dict(birth_per_V=2.0e4), dict(w_new=0.0), dict(sec_V=float("nan")), dict(drug3=2),
+               dict(epi_w1=0.0), dict(epi_q2=-1.0), dict(epi_cl=float("inf")), dict(G_ref3=0.0),
+               dict(b_int3=0), dict(b_int3=65)):
         assert init_status([(cell, w, NODOSE)], hca.default_params(**kw)) == hca.E_INVALID, kw
     lib = hca.lib()
     assert lib.hca_init(None, None, None, 0, None) == hca.E_INVALID
