@@ -12,9 +12,13 @@
  *   P   intracellular p53                                  (Eq. odep53)
  *   Vc  intracellular VEGF                                 (Eq. odevegf)
  *   phi cell-cycle clock                                   (Eq. cellcycle)
- * on a cubic voxel lattice with a static perfusion map w (0 = no vessel), by
- * the coupled step of Algorithm 1: implicit-Euler reaction-diffusion solves of
- * oxygen and both drugs, the intracellular ODEs, then the cellular automaton.
+ * on a cubic voxel lattice with a perfusion map w (0 = no vessel), by the
+ * coupled step of Algorithm 1: implicit reaction-diffusion solves of oxygen
+ * and the drugs, the intracellular ODEs, then the cellular automaton.
+ * Options (hca_params): a third drug G3 (epirubicin), the extracellular VEGF
+ * V with the vessel birth-death update (w then changes), field substeps with
+ * a theta scheme, Newton steps on the oxygen uptake, exact Michaelis-Menten
+ * fluorouracil kinetics.
  *
  * Layout: every per-voxel array is x-fastest, gid = x + nx*(y + ny*z),
  * FP64 for fields and uint8 for the cell map.  All replicates live in one

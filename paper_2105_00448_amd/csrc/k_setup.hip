@@ -149,9 +149,10 @@ __global__ void __launch_bounds__(kBlock) k_setup_o2(Work w, DevParams p, const 
   });
 }
 
-// The three systems of one field substep in one pass (the pointwise terms of
-// the theta scheme above; the explicit Laplacian of a theta < 1 substep is
-// added by k_rhs_lap); F = [K | G1 | G2], c and b in the same 3 x ntot layout.
+// All systems of one field substep in one pass (the pointwise terms of the
+// theta scheme above; the explicit Laplacian of a theta < 1 substep is added
+// by k_rhs_lap); F = [K | G1 | G2 (| G3) (| V)], c and b in the same
+// nf x ntot layout.
 //   oxygen: R = r_k w + phi_K chi/(K1 + K) (uptake linearised at the substep's
 //           start), S = r_k w K0 constant;
 //   drugs:  R = psi_G + kappa_G w, S = kappa_G w g0(t) with the plasma level

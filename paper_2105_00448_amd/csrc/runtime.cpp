@@ -2,11 +2,12 @@
 // tables, the per-step phase sequence of Algorithm 1, the CG driver and the
 // C ABI.
 //
-// The three implicit-Euler solves of a step (oxygen and two drugs) are
-// independent given the state at t^n, so they run as one batch of 3 x nreps
-// linear systems (system s = field * nreps + rep) through the same launches;
-// the fields live in one allocation [K | G1 | G2] and the solver arrays have
-// the same 3 x total-voxel layout.
+// The implicit solves of a step (oxygen, the two drugs, and with the options
+// the third drug and the extracellular VEGF) are independent given the state
+// at t^n, so they run as one batch of nf x nreps linear systems (system
+// s = field * nreps + rep) through the same launches; the fields live in one
+// allocation [K | G1 | G2 (| G3) (| V)] and the solver arrays have the same
+// nf x total-voxel layout.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -145,7 +146,7 @@ struct hca_ctx {
   int* item_cnt = nullptr;        // per flat work item
   long long* item_off = nullptr;  // nflat + 1
 
-  SolveScal* h_ss = nullptr;     // pinned, 3 x nreps
+  SolveScal* h_ss = nullptr;     // pinned, nf x nreps
   Counters* h_cnt = nullptr;     // pinned
   long long step = 0;
   int last_it[2] = {0, 0};       // iterations of the last step solve / init solve
