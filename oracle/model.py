@@ -21,6 +21,9 @@ step dt of the cell-cycle update):
 3. each drug, Eq. (chemo):
        (1/dt + psi_G + kappa_G w) G^{n+1} - a_G Lap G^{n+1}
            = G^n/dt + kappa_G w G_{i,0}(t^{n+1});
+   Below K = 0, reachable only through the oscillation of a theta < 1
+   substep, the uptake is continued linearly with its slope at 0,
+   phi_K K/K1 (``uptake_den``): every oxygen system stays an M-matrix;
 4. intracellular ODEs with K^{n+1} frozen;
 5. cellular automaton on the state after 4.
 With ``p.vegf``: V^{n+1} from Eq. (vac_v) without Avastin (the V_c source of
@@ -79,9 +82,15 @@ def plasma_pair(t, sched, p):
     return g1, g2
 
 
+def uptake_den(K, p):
+    """Denominator K1 + max(K, 0) of the oxygen uptake phi_K K/(K1 + K), which
+    for K < 0 continues the uptake by its tangent at 0."""
+    return p.K1 + np.maximum(K, 0.0)
+
+
 def o2_system(L, w, K_old, p):
     chi = (L != 0).astype(np.float64)
-    c = 1.0 / p.dt_min + p.r_k * w + p.phi_K * chi / (p.K1 + K_old)
+    c = 1.0 / p.dt_min + p.r_k * w + p.phi_K * chi / uptake_den(K_old, p)
     b = K_old / p.dt_min + p.r_k * w * p.K0
     return c, b
 
@@ -103,7 +112,7 @@ def o2_substep_system(L, w, K_old, p, tau, theta):
     coupling theta a_K."""
     chi = (L != 0).astype(np.float64)
     rw = p.r_k * w
-    up = p.phi_K * chi / (p.K1 + K_old)
+    up = p.phi_K * chi / uptake_den(K_old, p)
     c = 1.0 / tau + theta * rw + theta * up
     b = K_old * (1.0 / tau - (1.0 - theta) * (rw + up)) + rw * p.K0
     if theta < 1.0:
@@ -180,17 +189,21 @@ def o2_newton_system(L, w, K_it, b_lin, p, tau, theta):
     old value in the uptake exactly as the nonlinear form does).  Linearised
     at the iterate K_it the step solves
         (1/tau + theta r_k w + theta phi_K chi K1/(K1 + K_it)^2) K'
-            - theta a_K Lap K' = b_lin - theta phi_K chi K_it^2/(K1 + K_it)^2."""
+            - theta a_K Lap K' = b_lin - theta phi_K chi K_it^2/(K1 + K_it)^2;
+    below K = 0 the uptake's linear continuation phi_K K/K1 gives, with
+    K+ = max(K_it, 0), the diagonal term K1/(K1 + K+)^2 and the right-hand
+    side term K_it K+/(K1 + K+)^2 (the same expressions for K_it >= 0)."""
     chi = (L != 0).astype(np.float64)
-    d = p.K1 + K_it
+    kp = np.maximum(K_it, 0.0)
+    d = p.K1 + kp
     c = 1.0 / tau + theta * (p.r_k * w) + theta * (p.phi_K * chi * p.K1 / (d * d))
-    b = b_lin - theta * (p.phi_K * chi * K_it * K_it / (d * d))
+    b = b_lin - theta * (p.phi_K * chi * K_it * kp / (d * d))
     return c, b
 
 
 def steady_o2_system(L, w, K_iter, p):
     chi = (L != 0).astype(np.float64)
-    c = p.r_k * w + p.phi_K * chi / (p.K1 + K_iter)
+    c = p.r_k * w + p.phi_K * chi / uptake_den(K_iter, p)
     b = p.r_k * w * p.K0
     return c, b
 

@@ -3,7 +3,9 @@
 Test infrastructure only.  All functions are vectorised over voxels, FP64.
 
 Oxygen K is frozen over the coupled step at the value just solved for
-(Algorithm 1 computes K first, then the ODEs "using K").
+(Algorithm 1 computes K first, then the ODEs "using K"); the cells see
+max(K, 0) (a negative value is an artifact of a Crank-Nicolson-type field
+substep's oscillation, not an oxygen level).
 
 * p53 (Eq. odep53) is linear in P with constant coefficients while K is
   frozen, so the paper's explicit form is exact:
@@ -69,6 +71,7 @@ def ode_step(L, K, P, Vc, phi, p):
 
     Returns new (P, Vc, phi); empty voxels are left as they are.
     """
+    K = np.maximum(K, 0.0)
     occ = L != 0
     can = L == 1
     Pn, Vn, phin = P.copy(), Vc.copy(), phi.copy()

@@ -127,7 +127,10 @@ __device__ inline void for_each_voxel(const Work& w, F f) {
 
 // Oxygen, Eq. (oxygen) linearised as in the paper: the uptake
 // phi_K K/(K1 + K) becomes phi_K K^{n+1}/(K1 + K^n).  chi = [L != 0] marks the
-// cell delta functions, w weights the vessel sources.
+// cell delta functions, w weights the vessel sources.  Below K = 0, which
+// only a Crank-Nicolson-type substep's oscillation can reach, the uptake is
+// continued linearly with its slope at 0, phi_K K/K1: every denominator is
+// K1 + max(K, 0), so every oxygen system stays an M-matrix.
 //   step:   c = 1/dt + r_k w + phi_K chi/(K1 + K^n),   b = K^n/dt + r_k w K0
 //   steady: c =        r_k w + phi_K chi/(K1 + K),     b =        r_k w K0,
 //           both times theta (the solver's coupling is theta a_K)
@@ -138,7 +141,7 @@ __global__ void __launch_bounds__(kBlock) k_setup_o2(Work w, DevParams p, const 
     const double k = K[g];
     const double wv = vw[g];
     const double chi = L[g] != 0 ? 1.0 : 0.0;
-    const double up = p.phi_K * chi / (p.K1 + k);
+    const double up = p.phi_K * chi / (p.K1 + fmax(k, 0.0));
     if (steady) {
       c[g] = p.theta * (p.r_k * wv + up);
       b[g] = p.theta * (p.r_k * wv * p.K0);
@@ -176,7 +179,7 @@ __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long
     const double k = F[g];
     const double chi = L[g] != 0 ? 1.0 : 0.0;
     const double rw = p.r_k * wv;
-    const double up = p.phi_K * chi / (p.K1 + k);
+    const double up = p.phi_K * chi / (p.K1 + fmax(k, 0.0));
     c[g] = p.inv_tau + th * rw + th * up;
     b[g] = k * (p.inv_tau - th1 * (rw + up)) + rw * p.K0;
     const double kw = p.kappa_G * wv;
@@ -199,7 +202,9 @@ __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long
 //   (1/tau + theta r_k w) K' + theta phi_K chi K'/(K1 + K') - theta a_K Lap K' = b_lin,
 // linearised at the iterate K:
 //   c = 1/tau + theta r_k w + theta phi_K chi K1/(K1 + K)^2,
-//   b = b_lin - theta phi_K chi K^2/(K1 + K)^2.
+//   b = b_lin - theta phi_K chi K^2/(K1 + K)^2;
+// with the linear continuation below K = 0 (K+ = max(K, 0)):
+//   c = ... K1/(K1 + K+)^2,  b = b_lin - theta phi_K chi K K+/(K1 + K+)^2.
 __global__ void __launch_bounds__(kBlock) k_setup_o2_newton(Work w, DevParams p,
                                                             const uint8_t* __restrict__ L,
                                                             const double* __restrict__ vw,
@@ -209,10 +214,11 @@ __global__ void __launch_bounds__(kBlock) k_setup_o2_newton(Work w, DevParams p,
                                                             double* __restrict__ b) {
   for_each_voxel(w, [&](int, const RepDev&, long long g) {
     const double k = K[g];
+    const double kp = fmax(k, 0.0);
     const double chi = L[g] != 0 ? 1.0 : 0.0;
-    const double d = p.K1 + k;
+    const double d = p.K1 + kp;
     c[g] = p.inv_tau + p.theta * (p.r_k * vw[g]) + p.theta * (p.phi_K * chi * p.K1 / (d * d));
-    b[g] = b_lin[g] - p.theta * (p.phi_K * chi * k * k / (d * d));
+    b[g] = b_lin[g] - p.theta * (p.phi_K * chi * k * kp / (d * d));
   });
 }
 

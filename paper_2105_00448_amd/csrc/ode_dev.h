@@ -46,9 +46,12 @@ __device__ inline double vegf_rhs(double V, double Pt, double mu, const DevParam
   return p.k2 + p.k2pp * Pt * V * recip_pos(p.J5 + V) - mu * V;
 }
 
-// Advances (P, Vc, phi) of one occupied voxel (cell code l) with oxygen kk.
+// Advances (P, Vc, phi) of one occupied voxel (cell code l) with oxygen kk,
+// seen as max(kk, 0) (a negative value can only come from the oscillation of
+// a Crank-Nicolson-type field substep).
 __device__ inline void ode_voxel(const DevParams& p, uint8_t l, double kk, double& P, double& Vc,
                                  double& phi) {
+  kk = fmax(kk, 0.0);
   const double h = p.dt / p.nsub;
   const double P0 = P;
   const double lam = p.k1p * kk / (p.K_p53 + kk);

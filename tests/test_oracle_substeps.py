@@ -174,3 +174,46 @@ def test_newton_oxygen_solves_the_nonlinear_update(small_tissue, theta):
     assert res[1] < 100 * res[0] ** 2       # quadratic convergence ...
     assert res[2] < 100 * res[1] ** 2
     assert res[3] < 1e-13                   # ... down to rounding
+
+
+def test_uptake_continued_linearly_below_zero():
+    """For K < 0 (reachable only through a theta < 1 substep's oscillation)
+    the uptake is phi_K K/K1, the tangent at 0: the linearised coefficient is
+    phi_K/K1, the oxygen diagonal stays >= 1/tau (an M-matrix), and the Newton
+    terms join the K >= 0 ones continuously (C^1 at 0)."""
+    shape = (2, 3, 4)
+    L = np.ones(shape, dtype=np.uint8)
+    w = np.zeros(shape)
+    tau, theta = 15.0, 0.5
+    Kneg = np.full(shape, -30.0)
+    c, _ = model.o2_substep_system(L, w, Kneg, P, tau, theta)
+    c0, _ = model.o2_substep_system(L, w, np.zeros(shape), P, tau, theta)
+    assert np.array_equal(c, c0) and np.all(c >= 1.0 / tau)
+    b_lin = np.ones(shape)
+    for eps in (1e-7, 1e-9):
+        cm, bm = model.o2_newton_system(L, w, np.full(shape, -eps), b_lin, P, tau, theta)
+        cp, bp = model.o2_newton_system(L, w, np.full(shape, eps), b_lin, P, tau, theta)
+        np.testing.assert_allclose(cm, cp, rtol=10 * eps)
+        np.testing.assert_allclose(bm, bp, rtol=10 * eps)
+    cn, bn = model.o2_newton_system(L, w, Kneg, b_lin, P, tau, theta)
+    assert np.all(cn == c0) and np.all(bn == b_lin)      # linear uptake: no Newton correction
+
+
+def test_crank_nicolson_after_vessel_changes_stays_well_posed():
+    """Crank-Nicolson substeps right after vessel births and deaths (the
+    stiff vessel source makes the scheme oscillate): every oxygen system keeps
+    a positive diagonal and the fields stay finite."""
+    from paper_2105_00448_amd import synth
+    p = P.with_(vegf=1, pde_substeps=2, pde_theta=0.5, dv_min=60.0, V_high=5.0e-5, p_death=0.5,
+                birth_per_V=0.4 / 5.0e-5)
+    sched = model.Schedule(times=((0.0,), (0.0, 40.0)), amts=((1.0,), (1.0, 0.5)))
+    tis = synth.make_tissue((2, 2, 130), 4, seed=138)
+    s = model.init_state(tis.cell, tis.w, tis.seed, p)
+    changes = 0
+    for _ in range(4):
+        c, _ = model.o2_substep_system(s.L, s.w, np.minimum(s.K, -1.0), p, 15.0, 0.5)
+        assert c.min() > 0.0
+        s, ev = model.step(s, None, sched, tis.seed, p)
+        changes += ev["births"] + ev["deaths"]
+        assert np.all(np.isfinite(s.K)) and np.all(np.isfinite(s.Vc))
+    assert changes > 0
