@@ -168,6 +168,15 @@ typedef struct hca_params {
   double epi_cl;           /* elimination clearance, mL/min (983)               */
   double G_ref3;           /* kill-probability normalisation (1)                */
   int32_t b_int3;          /* dose-response shape, 1..64 (1)                     */
+  /* initial guess of each field solve, from the field's value u at this
+     solve and u_prev at the previous solve of the same field (a value written
+     with hca_set_field restarts it): 0 u; 1 the linear extrapolation
+     2u - u_prev; 2 (default) the geometric one u (u / u_prev) where the
+     voxel's value is positive and decaying (0 < u < u_prev), else u.  The
+     stopping rule, hence the solve's accuracy, is the same for all three;
+     2 lets the drug fields' solves between boluses stop after 0-2
+     iterations. */
+  int32_t x0_extrapolate;
 } hca_params;
 
 /* One replicate's inputs.  hca_init deep-copies every array; the caller keeps

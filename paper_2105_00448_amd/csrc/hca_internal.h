@@ -196,6 +196,11 @@ void launch_setup_o2_newton(hipStream_t s, const Work& w, const DevParams& p, co
 // Crank-Nicolson-type substeps (theta < 1): b += (1 - theta) a Lap F per field.
 void launch_rhs_lap(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
                     const double* F, double* b);
+// Initial guess of the solves of the fields in fmask (mode 1: F <- 2F - Fprev;
+// mode 2: F <- F (F / Fprev) where 0 < F < Fprev) and Fprev <- F (the values
+// at the previous solve of each field).
+void launch_extrapolate(hipStream_t s, const Work& w, long long ntot, int nf, unsigned fmask, int mode,
+                        double* F, double* Fprev);
 void launch_init_cells(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
                        const double* K, double* P, double* Vc, double* phi);
 

@@ -252,6 +252,29 @@ __global__ void __launch_bounds__(kBlock) k_rhs_lap(Work w, DevParams p, long lo
   });
 }
 
+// Extrapolation in time of the solved fields as the solver's initial guess,
+// the previous solve's value kept in Fprev: mode 1 linear, u + (u - u_prev);
+// mode 2 geometric, u (u / u_prev), on positive decaying values only (a
+// drug field between boluses decays nearly geometrically), else u.
+__global__ void __launch_bounds__(kBlock) k_extrapolate(Work w, long long ntot, int nf, unsigned fmask,
+                                                        int mode, double* __restrict__ F,
+                                                        double* __restrict__ Fprev) {
+  for_each_voxel(w, [&](int, const RepDev&, long long g) {
+    for (int f = 0; f < nf; ++f) {
+      if (!((fmask >> f) & 1u)) continue;
+      const long long j = g + (long long)f * ntot;
+      const double u = F[j];
+      const double up = Fprev[j];
+      Fprev[j] = u;
+      if (mode == 1) {
+        F[j] = u + (u - up);
+      } else if (up > 0.0 && u > 0.0 && u < up) {   // geometric, decaying values only
+        F[j] = u * (u / up);
+      }
+    }
+  });
+}
+
 // Algorithm 1 initialisation of the cell state at the initial oxygen K^0:
 // P, V_c at the steady states of Eqs. (odep53), (odevegf) on occupied voxels,
 // phi ~ U(0,1) for cancer cells (Philox counter (gid, 0, INIT, 0), key (seed, 0)).
@@ -310,6 +333,12 @@ void launch_setup_o2_newton(hipStream_t s, const Work& w, const DevParams& p, co
 void launch_rhs_lap(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
                     const double* F, double* b) {
   hca_launch(k_rhs_lap, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot, F, b);
+}
+
+void launch_extrapolate(hipStream_t s, const Work& w, long long ntot, int nf, unsigned fmask, int mode,
+                        double* F, double* Fprev) {
+  hca_launch(k_extrapolate, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, ntot, nf, fmask,
+             mode, F, Fprev);
 }
 
 void launch_init_cells(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,

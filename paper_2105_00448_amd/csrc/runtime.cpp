@@ -120,6 +120,7 @@ struct hca_ctx {
   std::vector<void*> mg_mem;
   double *dose_t = nullptr, *dose_a = nullptr, *g0 = nullptr;
   double* b_o2lin = nullptr;                     // o2_newton: the linearised O2 right-hand side
+  double* Fprev = nullptr;                       // x0_extrapolate: fields of the previous solve
   long long* d_step = nullptr;
   // replicate tables (state kernels)
   RepDev* d_reps = nullptr;
@@ -578,6 +579,10 @@ hca_status run_phases(hca_ctx* c, unsigned mask) {
       launch_setup_step(s, wk, c->dp, c->ntot, c->L, c->w, c->F, c->Vc, c->g0, c->c, c->b);
       if (c->dp.theta < 1.0) launch_rhs_lap(s, wk, c->dp, c->ntot, c->F, c->b);
     }
+    if (c->Fprev) {
+      ProfScope ps(c, KC_SETUP, kTagState);
+      launch_extrapolate(s, wk, c->ntot, c->dp.nf, fmask, c->prm.x0_extrapolate, c->F, c->Fprev);
+    }
     const bool newton = c->prm.o2_newton > 0 && (fmask & 1u);
     if (newton)
       HIPCHK(c, hipMemcpyAsync(c->b_o2lin, c->b, sizeof(double) * (size_t)c->ntot, hipMemcpyDeviceToDevice, s));
@@ -763,6 +768,10 @@ hca_status validate_params(const hca_params* p, std::string& msg) {
       msg = "drug3 in {0, 1}; epi_w* > 0; epi_q2, epi_q3, epi_cl >= 0; G_ref3 > 0; b_int3 in 1..64";
       return HCA_E_INVALID;
     }
+  }
+  if (p->x0_extrapolate < 0 || p->x0_extrapolate > 2) {
+    msg = "x0_extrapolate in {0, 1, 2}";
+    return HCA_E_INVALID;
   }
   if (p->mg_smooth != 2) {
     msg = "mg_smooth: the multigrid smoothers implement two sweeps before and after";
@@ -1111,6 +1120,7 @@ hca_status alloc_all(hca_ctx* c) {
   HIPCHK(c, dalloc(&c->dose_a, (size_t)c->nreps * 3 * HCA_MAX_DOSES));
   HIPCHK(c, dalloc(&c->g0, (size_t)c->nreps * 6));   // levels at both ends of a field substep
   if (c->prm.o2_newton > 0 && (st = big(&c->b_o2lin, (size_t)c->ntot)) != HCA_OK) return st;
+  if (c->prm.x0_extrapolate && (st = big(&c->Fprev, n3)) != HCA_OK) return st;
   HIPCHK(c, dalloc(&c->d_step, 1));
   HIPCHK(c, dalloc(&c->d_cnt, c->nreps));
   HIPCHK(c, dalloc(&c->d_cpart, (size_t)c->work.nflat * kCounterSlots));
@@ -1364,7 +1374,7 @@ hca_status steady_oxygen(hca_ctx* c) {
 void free_all(hca_ctx* c) {
   void* bufs[] = {c->L, c->code, c->win, c->w, c->P, c->Vc, c->phi, c->F, c->c, c->b,
                   c->sb.r, c->sb.z, (void*)c->sb.z32, (void*)c->sb.r32, c->sb.p0, c->sb.p1, c->sb.q, c->sb.dinv, c->sb.partial,
-                  c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->b_o2lin, c->d_step,
+                  c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->b_o2lin, c->Fprev, c->d_step,
                   c->d_reps, c->d_flat, c->d_tiles, c->d_sys, c->d_sflat, c->d_stiles, c->d_cnt, (void*)c->d_cpart,
                   (void*)c->d_fields, c->d_bad, c->d_theta, (void*)c->d_pack, (void*)c->d_gelu, c->before,
                   c->item_cnt, c->item_off};
@@ -1472,6 +1482,7 @@ hca_status hca_default_params(hca_params* out) {
   out->epi_cl = 0.983e3;
   out->G_ref3 = 1.0;
   out->b_int3 = 1;
+  out->x0_extrapolate = 2;
   return HCA_OK;
 }
 
@@ -1562,6 +1573,9 @@ hca_status hca_init(hca_ctx** out, const hca_params* p, const hca_replicate* rep
     return bail(HCA_E_DEVICE);
   if (c->G3 && hipMemsetAsync(c->G3, 0, (size_t)c->ntot * 8, c->stream) != hipSuccess)
     return bail(HCA_E_DEVICE);
+  if (c->Fprev && hipMemcpyAsync(c->Fprev, c->F, (size_t)c->dp.nf * c->ntot * 8, hipMemcpyDeviceToDevice,
+                                 c->stream) != hipSuccess)
+    return bail(HCA_E_DEVICE);
   launch_zero_counters(c->stream, c->d_cnt, n_reps, 1);
   launch_zero_counters(c->stream, c->d_cnt, n_reps, 0);
   launch_stats(c->stream, c->work, c->L, c->w, c->d_fields, c->nstat_fields, c->d_cpart, c->d_cnt);
@@ -1651,6 +1665,12 @@ hca_status hca_set_field(hca_ctx* c, int rep, hca_field f, const void* src, size
                              c->stream));
   } else {
     HIPCHK(c, hipMemcpyAsync(dst + (size_t)R.off * elem, src, bytes, kind, c->stream));
+    // a solved field restarts its extrapolation from the new value
+    const double* fd = (const double*)dst;
+    if (c->Fprev && fd >= c->F && fd < c->F + (size_t)c->dp.nf * c->ntot) {
+      const size_t off = (size_t)(fd - c->F) + (size_t)R.off;
+      HIPCHK(c, hipMemcpyAsync(c->Fprev + off, c->F + off, bytes, hipMemcpyDeviceToDevice, c->stream));
+    }
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return HCA_OK;

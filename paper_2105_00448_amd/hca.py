@@ -47,6 +47,7 @@ class Params(C.Structure):
         ("drug3", C.c_int32), ("epi_w1", C.c_double), ("epi_w2", C.c_double), ("epi_w3", C.c_double),
         ("epi_q2", C.c_double), ("epi_q3", C.c_double), ("epi_cl", C.c_double),
         ("G_ref3", C.c_double), ("b_int3", C.c_int32),
+        ("x0_extrapolate", C.c_int32),
     ]
 
 
