@@ -123,7 +123,10 @@ typedef struct hca_params {
   int32_t pde_substeps;    /* m >= 1 implicit substeps of dt_min/m (1)          */
   double pde_theta;        /* theta scheme in [1/2, 1]: 1 backward Euler (1),
                               1/2 Crank-Nicolson; plasma levels at both ends
-                              of a substep, O2 uptake linearised at its start  */
+                              of a substep, O2 uptake linearised at its start;
+                              theta < 1 can oscillate below K = 0 after a
+                              vessel change, where the uptake is continued by
+                              its tangent phi_K K/K1 and the ODEs see 0        */
   int32_t o2_newton;       /* 0: the paper's linearised O2 uptake (0); k > 0:
                               then k Newton steps per substep on the uptake
                               phi_K K/(K1 + K) at the new value (each one more
