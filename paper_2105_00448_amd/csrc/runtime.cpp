@@ -491,10 +491,18 @@ bool capture_iterations(hca_ctx* c, const Work& W, const MgBufs& mg, double rtol
 // (diag(c) - a Lap) x = b, x = the field array F.  Systems of fields outside
 // `fmask` are marked finished at the start.  Iterations are launched in
 // batches sized from the previous solve of the same kind, with a poll of the
-// per-system scalars between batches.
-hca_status solve(hca_ctx* c, const Work& W, const MgBufs& mg, unsigned fmask, double rtol,
+// per-system scalars between batches.  In a solve of all fields, once every
+// system but the oxygen ones has converged (the drugs often need only a few
+// iterations), the remaining iterations run on the oxygen prefix's tables
+// (sys1, mg1: the same arrays, fewer workgroups) and its captured graph.
+hca_status solve(hca_ctx* c, const Work& W_all, const MgBufs& mg_all, unsigned fmask, double rtol,
                  int maxit, int kind) {
-  const int nsys = W.nreps;
+  const int nsys = W_all.nreps;
+  const Work* Wp = &W_all;
+  const MgBufs* mgp = &mg_all;
+  int gk = kind;   // graph of the active tables
+  const Work& W = W_all;
+  const MgBufs& mg = mg_all;
   if (c->use_mg) {
     ProfScope ps(c, KC_MG_PREP, kTagAll, false);
     launch_mg_prepare(c->stream, W, mg, c->c);
@@ -510,19 +518,19 @@ hca_status solve(hca_ctx* c, const Work& W, const MgBufs& mg, unsigned fmask, do
   auto iteration = [&](int it) {
     {
       ProfScope ps(c, KC_CG_APPLY, it);
-      launch_cg_apply(c->stream, W, c->c, c->sb, it & 1);
+      launch_cg_apply(c->stream, *Wp, c->c, c->sb, it & 1);
     }
     {
       ProfScope ps(c, KC_CG_UPDATE, it);
-      launch_cg_update(c->stream, W, rtol, maxit, c->F, c->sb, it & 1);
+      launch_cg_update(c->stream, *Wp, rtol, maxit, c->F, c->sb, it & 1);
     }
     // z = M r for the next direction (work only where this iteration did not converge)
-    if (c->use_mg) run_vcycle(c, W, mg, it + 1);
+    if (c->use_mg) run_vcycle(c, *Wp, *mgp, it + 1);
   };
   // Replays of a captured pair of iterations (even, odd) when no kernel is
   // being timed; finished systems make the extra launches no-ops.
-  const bool graphs = c->prm.graphs && c->prm.profile == 0 && !c->graph_failed &&
-                      (c->iter_graph[kind] || capture_iterations(c, W, mg, rtol, maxit, kind));
+  bool graphs = c->prm.graphs && c->prm.profile == 0 && !c->graph_failed &&
+                (c->iter_graph[kind] || capture_iterations(c, W, mg, rtol, maxit, kind));
   for (;;) {
     batch = std::min(batch, maxit - launched);
     int k = 0;
@@ -533,7 +541,7 @@ hca_status solve(hca_ctx* c, const Work& W, const MgBufs& mg, unsigned fmask, do
         ++launched;
       }
       for (; k + 2 <= batch; k += 2, launched += 2)
-        HIPCHK(c, hipGraphLaunch(c->iter_graph[kind], c->stream));
+        HIPCHK(c, hipGraphLaunch(c->iter_graph[gk], c->stream));
     }
     for (; k < batch; ++k, ++launched) iteration(launched);
     HIPCHK(c, hipMemcpyAsync(c->h_ss, c->sb.ss, sizeof(SolveScal) * nsys, hipMemcpyDeviceToHost,
@@ -547,6 +555,16 @@ hca_status solve(hca_ctx* c, const Work& W, const MgBufs& mg, unsigned fmask, do
     }
     if (all || launched >= maxit) break;
     batch = 2;
+    if (kind == 0 && Wp != &c->sys1 && nsys > c->nreps) {
+      bool rest = true;
+      for (int s = c->nreps; s < nsys; ++s) rest = rest && c->h_ss[s].done;
+      if (rest) {
+        Wp = &c->sys1;
+        mgp = &c->mg1;
+        gk = 1;
+        graphs = graphs && (c->iter_graph[1] || capture_iterations(c, c->sys1, c->mg1, rtol, maxit, 1));
+      }
+    }
   }
   prof_flush(c, c->h_ss, nsys);
   c->last_it[kind] = real;
