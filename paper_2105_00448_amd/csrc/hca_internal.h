@@ -291,6 +291,7 @@ struct MgBufs {
   float* coarse_pre;        // per solve: couplings and D^-1 of the coarse-solve levels
   int coarse_lds_bytes;
   float w_a, w_b;            // Jacobi weights: pre-sweeps (w_a, w_b), post-sweeps (w_b, w_a)
+  float w0[3];              // level 0: pre-sweeps (w0[0], w0[1], w0[2]), post-sweeps reversed
   float** lev_c;            // device arrays of the per-level pointers
   float** lev_r;
   float** lev_u;
@@ -303,7 +304,7 @@ void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, const dou
 // scalars (r.z, beta) with a RED_RZ reduce.
 // `hook(ctx, segment, begin)` brackets the launches of each segment (for
 // kernel timing); segments: see MgSegment.
-enum MgSegment { MG_PRE0 = 0, MG_RESTRICT0, MG_DOWN, MG_COARSE, MG_UP, MG_POST1_0, MG_POST2_0 };
+enum MgSegment { MG_PRE0 = 0, MG_RESTRICT0, MG_DOWN, MG_COARSE, MG_UP, MG_POST1_0, MG_POST2_0, MG_SWEEP0 };
 typedef void (*MgHook)(void* ctx, int segment, int begin);
 void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const SolverBufs& sb,
                       MgHook hook, void* hook_ctx);

@@ -303,9 +303,9 @@ struct OpPre {
 
 template <bool L0, typename RT>
 __global__ void __launch_bounds__(kBlock) k_mg_pre(MgLevel Lk, float wa, float wb,
-                                                   const RT* __restrict__ r, const SolveScal* ss) {
+                                                   const RT* __restrict__ r, float* __restrict__ u,
+                                                   const SolveScal* ss) {
   __shared__ float lds[2][kPlaneMaxF];
-  float* __restrict__ u = Lk.u;
   FOR_MY_TILES(Lk.ntiles) {
     const Tile t = Lk.tiles[ti];
     if (ss[t.rep].done) continue;
@@ -467,8 +467,28 @@ __global__ void __launch_bounds__(kBlock) k_mg_post1(MgLevel Lk, MgLevel Lc, flo
              });
   }
 }
+// One weighted-Jacobi sweep out = in + omega D^-1 (r - A in) (level 0's third
+// pre- and post-sweep).
 template <bool L0, typename RT>
-__global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float omega,
+__global__ void __launch_bounds__(kBlock) k_mg_sweep(MgLevel Lk, float omega, const float* __restrict__ in,
+                                                     float* __restrict__ out, const RT* __restrict__ r,
+                                                     const SolveScal* ss) {
+  __shared__ float lds[2][kPlaneMaxF];
+  FOR_MY_TILES(Lk.ntiles) {
+    const Tile t = Lk.tiles[ti];
+    if (ss[t.rep].done) continue;
+    const MgRep m = Lk.reps[t.rep];
+    const Geo<L0> G = geo_of<L0>(m);
+    const OpU<RT> op{in, Lk.dinv, r};
+    mg_plane(G, t, m.tx, m.off, lds, op,
+             [&](int, long long i, float v, float s, const CtrDR<RT>& c) {
+               out[i] = (1.f - omega) * v + omega * c.dinv * ((float)c.r + s);
+             });
+  }
+}
+
+template <bool L0, typename RT>
+__global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float omega, const float* __restrict__ in,
                                                      const RT* __restrict__ r, SolverBufs sb) {
   __shared__ double lds4[4];
   __shared__ float lds[2][kPlaneMaxF];
@@ -479,7 +499,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float omega,
     const Geo<L0> G = geo_of<L0>(m);
     double rz = 0.0;
     {
-      const OpU<RT> op{Lk.ualt, Lk.dinv, r};
+      const OpU<RT> op{in, Lk.dinv, r};
       mg_plane(G, t, m.tx, m.off, lds, op,
                [&](int, long long i, float u4, float s, const CtrDR<RT>& c) {
                  const float u5 = (1.f - omega) * u4 + omega * c.dinv * ((float)c.r + s);
@@ -874,8 +894,10 @@ void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, const dou
 
 void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const SolverBufs& sb,
                       MgHook hook, void* hctx) {
-  // pre-sweeps with weights (wa, wb), post-sweeps with (wb, wa)
+  // levels >= 1: pre-sweeps with weights (wa, wb), post-sweeps with (wb, wa);
+  // level 0: three sweeps (w0[0], w0[1], w0[2]) before, reversed after
   const float wa = mg.w_a, wb = mg.w_b;
+  const float* w0 = mg.w0;
   const SolveScal* ss = sb.ss;
   auto H = [&](int seg, int begin) {
     if (hook) hook(hctx, seg, begin);
@@ -884,9 +906,13 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_PRE0, 1);
-    hca_launch((k_mg_pre<true, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, wa, wb,
-                       (const float*)sb.r32, ss);
+    hca_launch((k_mg_pre<true, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, w0[0],
+               w0[1], (const float*)sb.r32, L.ualt, ss);
     H(MG_PRE0, 0);
+    H(MG_SWEEP0, 1);
+    hca_launch((k_mg_sweep<true, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, w0[2],
+               (const float*)L.ualt, L.u, (const float*)sb.r32, ss);
+    H(MG_SWEEP0, 0);
     H(MG_RESTRICT0, 1);
     hca_launch((k_mg_restrict<true, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
                        (const float*)sb.r32, ss);
@@ -899,7 +925,7 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
       const MgLevel& C = mg.lev[k + 1];
       if (!L.ntiles) continue;
       hca_launch((k_mg_pre<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, wa, wb,
-                 (const float*)L.r, ss);
+                 (const float*)L.r, L.u, ss);
       hca_launch((k_mg_restrict<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
                  (const float*)L.r, ss);
     }
@@ -918,7 +944,7 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
       hca_launch((k_mg_post1<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, wb,
                  (const float*)L.r, ss);
       hca_launch((k_mg_post2<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, wa,
-                 (const float*)L.r, sb);
+                 (const float*)L.ualt, (const float*)L.r, sb);
     }
     H(MG_UP, 0);
   }
@@ -926,12 +952,16 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_POST1_0, 1);
-    hca_launch((k_mg_post1<true, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, wb,
-                       (const float*)sb.r32, ss);
+    hca_launch((k_mg_post1<true, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
+               w0[2], (const float*)sb.r32, ss);
     H(MG_POST1_0, 0);
+    H(MG_SWEEP0, 1);
+    hca_launch((k_mg_sweep<true, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, w0[1],
+               (const float*)L.ualt, L.u, (const float*)sb.r32, ss);
+    H(MG_SWEEP0, 0);
     H(MG_POST2_0, 1);
-    hca_launch((k_mg_post2<true, double>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, wa,
-                       (const double*)sb.r, sb);
+    hca_launch((k_mg_post2<true, double>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, w0[0],
+               (const float*)L.u, (const double*)sb.r, sb);
     H(MG_POST2_0, 0);
     launch_cg_reduce(s, w, sb, RED_RZ, 0.0, 0);
   }

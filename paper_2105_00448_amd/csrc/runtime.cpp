@@ -37,14 +37,14 @@ enum KernelClass {
   KC_PLASMA = 0, KC_SETUP, KC_CG_START, KC_CG_APPLY, KC_CG_UPDATE, KC_ODE,
   KC_CA_PROPOSE, KC_CA_RESOLVE, KC_CA_FINALIZE, KC_STATS,
   KC_MG_PREP, KC_MG_PRE0, KC_MG_RESTRICT0, KC_MG_LEVELS, KC_MG_COARSE, KC_MG_POST1_0,
-  KC_MG_POST2_0, KC_MLP_APPLY, KC_VESSEL, KC_COUNT
+  KC_MG_POST2_0, KC_MLP_APPLY, KC_VESSEL, KC_MG_SWEEP0, KC_COUNT
 };
 
 const char* kKernelNames[KC_COUNT] = {
     "k_plasma", "k_setup_step", "k_cg_start", "k_cg_apply", "k_cg_update",
     "k_ode", "k_ca_propose", "k_ca_resolve", "k_ca_finalize", "k_stats",
     "k_mg_prep0+k_mg_coarsen", "k_mg_pre<L0>", "k_mg_restrict<L0>", "mg levels >= 1 (global)",
-    "k_mg_coarse", "k_mg_post1<L0>", "k_mg_post2<L0>", "k_mlp_apply", "k_vessel"};
+    "k_mg_coarse", "k_mg_post1<L0>", "k_mg_post2<L0>", "k_mlp_apply", "k_vessel", "k_mg_sweep<L0>"};
 
 // Compulsory (algorithmic) HBM bytes per voxel of each kernel class; solver
 // classes per voxel of each active system (0: not priced, latency-bound).
@@ -60,14 +60,15 @@ const double kBytesPerVoxel[KC_COUNT] = {
     2.0,          // ca_finalize: read code, win (writes only where cells change)
     57.0,         // stats: read L, w and six fields
     21.0,         // mg prepare: read c (8); write dinv0 (4); level 1: read c, write c1, dinv1
-    12.0,         // mg pre L0: read r (FP32 copy, 4), dinv (4); write u (4)
+    12.0,         // mg pre L0: read r (FP32 copy, 4), dinv (4); write ualt (4)
     12.5,         // mg restrict L0: read u, r (4), dinv; write r1 (1/8 of 4)
     0.0,          // coarser global levels
     0.0,          // coarse workgroup levels
     16.5,         // mg post1 L0: read u, e (1/8), r (4), dinv; write ualt
     20.0,         // mg post2 L0: read ualt, r, dinv; write z (4)
     73.0,         // mlp apply: read L, K, G1, G2, P, Vc, phi; write P, Vc, phi
-    17.0};        // vessel: read L, w, V (writes only where a vessel changes)
+    17.0,         // vessel: read L, w, V (writes only where a vessel changes)
+    16.0};        // mg sweep L0: read u (4), r (4), dinv (4); write u' (4)
 constexpr double kBytesSetupVegf = 32.0;   // setup_step with vegf: + read V, Vc; write c, b
 constexpr double kBytesSetupDrug3 = 24.0;  // setup_step with drug3: + read G3; write c, b
 constexpr double kBytesStatsField = 8.0;   // stats: per extra field scanned (V, G3)
@@ -299,6 +300,7 @@ int mg_segment_class(int seg) {
     case MG_COARSE: return KC_MG_COARSE;
     case MG_POST1_0: return KC_MG_POST1_0;
     case MG_POST2_0: return KC_MG_POST2_0;
+    case MG_SWEEP0: return KC_MG_SWEEP0;
     default: return KC_MG_LEVELS;
   }
 }
@@ -1228,6 +1230,14 @@ hca_status build_mg(hca_ctx* c) {
     mg.w_a = (float)(1.0 / (mid + half * c4));
     mg.w_b = (float)(1.0 / (mid - half * c4));
   }
+  // Level 0 smooths with the three-step Chebyshev polynomial of least
+  // maximum over t in [0.2, 2] (1/w = 1.1 + 0.9 cos((2k - 1) pi / 6)): the
+  // finest level's smoothing is what limits the oxygen operator's
+  // convergence (its vessel voxels' reaction terms are orders of magnitude
+  // above the couplings); a third sweep there takes the oxygen solve from 8 to
+  // 6 iterations at 128^3, one on the coarser levels changes nothing.
+  for (int k = 0; k < 3; ++k)
+    mg.w0[k] = (float)(1.0 / (1.1 + 0.9 * std::cos((2 * k + 1) * M_PI / 6.0)));
   c->mg1 = mg;
   std::vector<float*> pc(kMaxLevels, nullptr), pr(kMaxLevels, nullptr), pu(kMaxLevels, nullptr);
   std::vector<std::vector<MgRep>> mreps(nglob + 1);
