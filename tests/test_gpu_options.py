@@ -79,3 +79,19 @@ def test_all_options_batch_equals_single_runs(precond):
                     assert a[k] == b[k], (r, k)
                 events += a["total_births"] + a["total_deaths"]
         assert events > 0
+
+
+def test_all_options_graph_replay_equals_direct_launches():
+    """With every option on, CG iterations replayed from captured HIP graphs
+    (five batched fields, the oxygen-prefix graph after the others converge)
+    give the same state, bit for bit, as direct launches."""
+    tis = tissue((20, 24, 28), 11)
+    rep = (tis.cell, tis.w, tis.seed, (TIMES, AMTS))
+    out = []
+    for graphs in (1, 0):
+        prm = hca.default_params(cg_rtol=1e-10, init_rtol=1e-10, graphs=graphs, **OPTS)
+        with hca.Simulation([rep], prm) as sim:
+            sim.step(4)
+            out.append({n: sim.field(n) for n in ("L", "K", "G1", "G2", "G3", "V", "P", "Vc", "phi", "w")})
+    for name in out[0]:
+        assert np.array_equal(out[0][name], out[1][name]), name
