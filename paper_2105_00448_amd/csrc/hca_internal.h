@@ -117,6 +117,11 @@ struct SolveScal {
   double pq;        // p.Ap
   double alpha, beta;
   double rr0;       // ||r_0||^2 of this solve
+  // The multigrid works in FP32 on r sc (r32 = r sc) and returns z sc: sc is a
+  // power of two near 1/rms(r), so the scaling is exact and keeps a decayed
+  // field's tiny residual inside FP32's range; isc = 1/sc unscales z in FP64
+  // (isc_prev: the scale of the previous z).
+  double sc, isc, isc_prev;
   int it, done, conv, first;
 };
 

@@ -498,14 +498,17 @@ __global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float omega, co
     const MgRep m = Lk.reps[t.rep];
     const Geo<L0> G = geo_of<L0>(m);
     double rz = 0.0;
+    // level 0 reads the FP64 residual (for r.z): the cycle works on r sc
+    const double sc = L0 ? sb.ss[t.rep].sc : 1.0, isc = L0 ? sb.ss[t.rep].isc : 1.0;
     {
       const OpU<RT> op{in, Lk.dinv, r};
       mg_plane(G, t, m.tx, m.off, lds, op,
                [&](int, long long i, float u4, float s, const CtrDR<RT>& c) {
-                 const float u5 = (1.f - omega) * u4 + omega * c.dinv * ((float)c.r + s);
+                 const float rs = L0 ? (float)((double)c.r * sc) : (float)c.r;
+                 const float u5 = (1.f - omega) * u4 + omega * c.dinv * (rs + s);
                  if (L0) {
                    sb.z32[i] = u5;
-                   rz += (double)c.r * (double)u5;
+                   rz += (double)c.r * ((double)u5 * isc);
                  } else {
                    Lk.u[i] = u5;
                  }

@@ -449,3 +449,42 @@ def test_negative_oxygen_matches_oracle(case32, theta):
         assert relerr(sim.field("P"), P) <= FIELD_TOL
         assert relerr(sim.field("Vc"), Vc) <= FIELD_TOL
         assert np.array_equal(sim.field("phi"), phi)
+
+
+@pytest.mark.parametrize("scale", [1e-60, 1e-120], ids=["1e-60", "1e-120"])
+def test_tiny_drug_fields_match_oracle(case32, scale):
+    """Drug fields far below FP32's range (long after the last dose): the
+    multigrid's FP32 residual is scaled by a power of two per system, so the
+    solves still converge and match the oracle."""
+    tis, _, s0 = case32
+    sched = synth.DoseSchedule(times=((), ()), amts=((), ()))
+    osched = oracle_sched(sched)
+    rng = np.random.default_rng(33)
+    s = s0.copy()
+    s.G1 = scale * rng.random(s0.K.shape)
+    s.G2 = scale * 1e-3 * rng.random(s0.K.shape)
+    with make_sim([(tis, sched)]) as sim:
+        push_state(sim, s)
+        sim.run_phases(hca.PH_O2 | hca.PH_DRUGS)
+        K, G1, G2 = om.solve_fields(s, tis.w, osched, OP)
+        for name, ref in (("K", K), ("G1", G1), ("G2", G2)):
+            assert relerr(sim.field(name), ref) <= FIELD_TOL, name
+        assert min(sim.stats()["cg_iters"][1:]) > 0
+
+
+def test_negligible_drug_fields_count_as_solved(case32):
+    """A drug field so small that its squared norms would leave FP64's normal
+    range (||b||^2 < 1e-280) is left at its initial guess without error."""
+    tis, _, s0 = case32
+    sched = synth.DoseSchedule(times=((), ()), amts=((), ()))
+    s = s0.copy()
+    s.G1 = np.full(s0.K.shape, 1e-200)
+    s.G2 = np.full(s0.K.shape, 1e-300)
+    with make_sim([(tis, sched)]) as sim:
+        push_state(sim, s)
+        sim.run_phases(hca.PH_O2 | hca.PH_DRUGS)
+        st = sim.stats()
+        assert st["cg_iters"][1:] == [0, 0]
+        for name in ("G1", "G2"):
+            g = sim.field(name)
+            assert np.isfinite(g).all() and np.abs(g).max() <= 1e-199
