@@ -488,3 +488,17 @@ def test_negligible_drug_fields_count_as_solved(case32):
         for name in ("G1", "G2"):
             g = sim.field(name)
             assert np.isfinite(g).all() and np.abs(g).max() <= 1e-199
+
+
+def test_long_run_past_the_last_dose(case32):
+    """700 steps after a single bolus (the drug fields decay through FP32's
+    range and towards FP64's): every solve converges and the state stays
+    finite."""
+    tis, sched, _ = case32
+    with make_sim([(tis, sched)], cg_rtol=1e-10, init_rtol=1e-10) as sim:
+        for _ in range(7):
+            sim.step(100)
+        st = sim.stats()
+        assert st["step"] == 700 and not st["nonfinite"]
+        g2 = sim.field("G2")
+        assert np.isfinite(g2).all() and 0.0 < np.abs(g2).max() < 1e-30
