@@ -457,8 +457,8 @@ def main():
     ap.add_argument("--train-steps", type=int, default=4000)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(replicates and z-slabs would shard across GPUs; see the design notes).",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(replicates and z-slabs would shard across GPUs).",
               file=sys.stderr)
         raise SystemExit(2)
 
