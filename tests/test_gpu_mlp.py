@@ -1,7 +1,7 @@
 """The ODE surrogate on the GPU, through the C ABI, against the oracle.
 
-Tolerances (bfloat16 operands, FP32 accumulation; the derivation is the
-parity section of the design notes):
+Tolerances (bfloat16 operands, FP32 accumulation), derived from the
+arithmetic:
 
 * forward vs the oracle's quantised forward (bf16 weights and activations,
   FP64 accumulation): the two differ only by accumulation order (~1e-6
