@@ -319,11 +319,24 @@ void launch_ode(hipStream_t s, const Work& w, const DevParams& p, const uint8_t*
                 const double* K, double* P, double* Vc, double* phi);
 
 // CA and stats (k_ca.hip)
+// The committed cancer cells (phi >= 1) of a step, listed by the propose
+// pass's scan per flat work item: item it's cells (local voxel indices, in
+// voxel order) at cells[first voxel of the item ...], item_n[it] of them.
+struct CaList {
+  long long* cells;   // one slot per voxel
+  int* item_n;        // per flat work item
+};
+// code = win = NONE everywhere, the committed cells listed, then each listed
+// cell's decision (kill, NOSPACE or the daughter's direction) into code.
 void launch_ca_propose(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
                        const uint8_t* L, const double* vw, const double* K, const double* G1,
-                       const double* G2, const double* G3, const double* phi, uint8_t* code);
-void launch_ca_resolve(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
-                       const double* phi, const uint8_t* code, uint8_t* win);
+                       const double* G2, const double* G3, const double* phi, uint8_t* code,
+                       uint8_t* win, CaList list);
+// For each listed cell that proposes a daughter site: the winner among the
+// site's proposing neighbours into win (every proposer of a site writes the
+// same value).
+void launch_ca_resolve(hipStream_t s, const Work& w, const double* phi, const uint8_t* code,
+                       uint8_t* win, CaList list);
 // Event and census counts: each flat work item stores kCounterSlots partials
 // (part[item * kCounterSlots + k]); a one-workgroup-per-replicate reduce
 // then writes the replicate's counters.

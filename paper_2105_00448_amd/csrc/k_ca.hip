@@ -1,17 +1,21 @@
-// Stochastic cellular automaton of the cellular module, as three gather-only
-// passes over the lattice (no atomics on the state, no scatter), so the
-// result cannot depend on thread scheduling or tiling:
+// Stochastic cellular automaton of the cellular module in three passes whose
+// result cannot depend on thread scheduling or tiling (no atomics on the
+// state; the only atomic is the position counter of a list whose order does
+// not matter):
 //
-// propose   a cancer cell with phi >= 1 is committed.  One Philox4x64-10 block
-//           (key (seed, 0), counter (gid, n+1, KILL, 0)) gives one uniform per
-//           drug (words 0, 1, and 2 for the third drug); drug i kills with probability I(x_i; 1, b_i) = 1 - (1-x_i)^b_i,
+// propose   a cancer cell with phi >= 1 is committed; a scan of the lattice
+//           lists the committed cells, and each listed cell decides: one
+//           Philox4x64-10 block (key (seed, 0), counter (gid, n+1, KILL, 0))
+//           gives one uniform per drug (words 0, 1, and 2 for the third
+//           drug); drug i kills with probability I(x_i; 1, b_i) = 1 - (1-x_i)^b_i,
 //           x_i = clip(G_i / G_ref_i, 0, 1), the power by repeated products.
 //           A surviving cell proposes the empty non-vessel Moore neighbour of
 //           highest oxygen (first strict maximum in ascending gid order), else
 //           NOSPACE.
-// resolve   every empty non-vessel voxel picks, among the neighbours proposing
-//           it, the one with the largest phi (Algorithm 2's priority), equal phi
-//           -> lowest gid.
+// resolve   every proposed site takes, among the neighbours proposing it, the
+//           one with the largest phi (Algorithm 2's priority), equal phi ->
+//           lowest gid; evaluated by a gather at the site for each of its
+//           proposers, which all write the same winner.
 // finalize  each voxel applies its own outcome from the codes of the previous
 //           passes: killed -> emptied and zeroed; won -> phi = P = Vc = 0;
 //           lost or NOSPACE -> phi = 0; daughter site -> cancer with zero state.
@@ -93,23 +97,70 @@ __device__ inline double kill_probability(double G, double Gref, int b) {
   return 1.0 - pw;
 }
 
-__global__ void __launch_bounds__(kBlock) k_ca_propose(Work w, DevParams p,
-                                                       const long long* d_step,
-                                                       const uint8_t* __restrict__ L,
-                                                       const double* __restrict__ vw,
-                                                       const double* __restrict__ K,
-                                                       const double* __restrict__ G1,
-                                                       const double* __restrict__ G2,
-                                                       const double* __restrict__ G3,
-                                                       const double* __restrict__ phi,
-                                                       uint8_t* __restrict__ code) {
+// Scan: code = win = NONE for every voxel; each work item's committed cancer
+// cells (phi >= 1) listed in voxel order in the item's own slots (a
+// workgroup prefix sum, no global atomics).  Light, so it runs at full
+// occupancy; the gathers of the committed cells' decisions run in the list
+// kernels below.
+__global__ void __launch_bounds__(kBlock) k_ca_scan(Work w, const uint8_t* __restrict__ L,
+                                                    const double* __restrict__ phi,
+                                                    uint8_t* __restrict__ code, uint8_t* __restrict__ win,
+                                                    CaList list) {
+  __shared__ int wcnt[kBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int b0, b1;
+  work_range(w.nflat, b0, b1);
+  for (int it = b0; it < b1; ++it) {
+    const FlatBlk fb = w.flat[it];
+    const long long off = w.reps[fb.rep].off;
+    long long* slots = list.cells + off + fb.begin;
+    int n = 0;
+    for (long long base = fb.begin; base < fb.end; base += kBlock) {
+      const long long li = base + threadIdx.x;
+      bool com = false;
+      if (li < fb.end) {
+        const long long i = off + li;
+        code[i] = kCodeNone;
+        win[i] = kCodeNone;
+        com = L[i] == 1 && phi[i] >= 1.0;
+      }
+      const unsigned long long bal = __ballot(com);
+      if (lane == 0) wcnt[wave] = __popcll(bal);
+      __syncthreads();
+      int woff = n;
+      for (int k = 0; k < wave; ++k) woff += wcnt[k];
+      if (com) slots[woff + __popcll(bal & ((1ull << lane) - 1ull))] = li;
+      for (int k = 0; k < kBlock / 64; ++k) n += wcnt[k];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) list.item_n[it] = n;
+  }
+}
+
+// The decision of each listed committed cell.
+__global__ void __launch_bounds__(kBlock) k_ca_propose_list(Work w, DevParams p,
+                                                            const long long* d_step,
+                                                            const uint8_t* __restrict__ L,
+                                                            const double* __restrict__ vw,
+                                                            const double* __restrict__ K,
+                                                            const double* __restrict__ G1,
+                                                            const double* __restrict__ G2,
+                                                            const double* __restrict__ G3,
+                                                            CaList list, uint8_t* __restrict__ code) {
   const long long step = d_step[0];
-  for_each_voxel_ca(w, [&](int, const RepDev& rp, long long li) {
-    const long long i = rp.off + li;
-    uint8_t cd = kCodeNone;
-    if (L[i] == 1 && phi[i] >= 1.0) {
-      const U64x4 o = philox4x64_10((uint64_t)li, (uint64_t)(step + 1), kStreamKill, 0ull,
-                                    rp.seed, 0ull);
+  int b0, b1;
+  work_range(w.nflat, b0, b1);
+  for (int it = b0; it < b1; ++it) {
+    const int n = list.item_n[it];
+    if (n == 0) continue;
+    const FlatBlk fb = w.flat[it];
+    const RepDev rp = w.reps[fb.rep];
+    const long long* slots = list.cells + rp.off + fb.begin;
+    for (int k = threadIdx.x; k < n; k += kBlock) {
+      const long long li = slots[k];
+      const long long i = rp.off + li;
+      uint8_t cd;
+      const U64x4 o = philox4x64_10((uint64_t)li, (uint64_t)(step + 1), kStreamKill, 0ull, rp.seed, 0ull);
       const double u0 = unit53(o.v[0]), u1 = unit53(o.v[1]);
       const double p1 = kill_probability(G1[i], p.G_ref[0], p.b_int[0]);
       const double p2 = kill_probability(G2[i], p.G_ref[1], p.b_int[1]);
@@ -124,7 +175,7 @@ __global__ void __launch_bounds__(kBlock) k_ca_propose(Work w, DevParams p,
         // all neighbour loads issued before any decision (one memory latency)
         uint8_t ln[26];
         double wn[26], kn[26];
-#pragma unroll
+  #pragma unroll
         for (int d = 0; d < 26; ++d) {
           const long long j = rp.off + (nb[d] < 0 ? li : nb[d]);
           ln[d] = L[j];
@@ -133,7 +184,7 @@ __global__ void __launch_bounds__(kBlock) k_ca_propose(Work w, DevParams p,
         }
         double best = -INFINITY;
         cd = kCodeNoSpace;
-#pragma unroll
+  #pragma unroll
         for (int d = 0; d < 26; ++d) {
           if (nb[d] < 0 || ln[d] != 0 || wn[d] != 0.0) continue;
           if (kn[d] > best) {
@@ -142,28 +193,39 @@ __global__ void __launch_bounds__(kBlock) k_ca_propose(Work w, DevParams p,
           }
         }
       }
+      code[i] = cd;
     }
-    code[i] = cd;
-  });
+  }
 }
 
-__global__ void __launch_bounds__(kBlock) k_ca_resolve(Work w, const uint8_t* __restrict__ L,
-                                                       const double* __restrict__ vw,
-                                                       const double* __restrict__ phi,
-                                                       const uint8_t* __restrict__ code,
-                                                       uint8_t* __restrict__ win) {
-  for_each_voxel_ca(w, [&](int, const RepDev& rp, long long li) {
-    const long long i = rp.off + li;
-    uint8_t wn = kCodeNone;
-    if (L[i] == 0 && vw[i] == 0.0) {
-      const VoxelCoord v = coord_of(li, rp);
+// The target site of each listed cell that proposes a daughter: among the
+// site's neighbours proposing it, the one with the largest phi (Algorithm 2),
+// equal phi -> lowest gid (strict > in ascending gid order).
+__global__ void __launch_bounds__(kBlock) k_ca_resolve_list(Work w, const double* __restrict__ phi,
+                                                            const uint8_t* __restrict__ code,
+                                                            CaList list, uint8_t* __restrict__ win) {
+  int b0, b1;
+  work_range(w.nflat, b0, b1);
+  for (int it = b0; it < b1; ++it) {
+    const int n = list.item_n[it];
+    if (n == 0) continue;
+    const FlatBlk fb = w.flat[it];
+    const RepDev rp = w.reps[fb.rep];
+    const long long* slots = list.cells + rp.off + fb.begin;
+    for (int k = threadIdx.x; k < n; k += kBlock) {
+      const long long li = slots[k];
+      const uint8_t cd = code[rp.off + li];
+      if (cd >= 26) continue;   // killed or no space
+      long long tl = 0;
+      neighbour(rp, coord_of(li, rp), cd, tl);   // exists: propose chose it
       long long nb[26];
-      moore_neighbours(rp, v, nb);
+      moore_neighbours(rp, coord_of(tl, rp), nb);
       uint8_t cn[26];
-#pragma unroll
-      for (int d = 0; d < 26; ++d) cn[d] = code[rp.off + (nb[d] < 0 ? li : nb[d])];
+  #pragma unroll
+      for (int d = 0; d < 26; ++d) cn[d] = code[rp.off + (nb[d] < 0 ? tl : nb[d])];
       double best = -INFINITY;
-#pragma unroll
+      uint8_t wn = kCodeNone;
+  #pragma unroll
       for (int d = 0; d < 26; ++d) {   // ascending parent gid: strict > keeps the lowest
         if (nb[d] < 0 || cn[d] != (uint8_t)moore_opposite(d)) continue;
         const double ph = phi[rp.off + nb[d]];
@@ -172,9 +234,9 @@ __global__ void __launch_bounds__(kBlock) k_ca_resolve(Work w, const uint8_t* __
           wn = (uint8_t)d;
         }
       }
+      win[rp.off + tl] = wn;
     }
-    win[i] = wn;
-  });
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_ca_finalize(Work w, uint8_t* __restrict__ L,
@@ -396,14 +458,17 @@ __global__ void __launch_bounds__(kBlock) k_validate_cells(Work w, const uint8_t
 
 void launch_ca_propose(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
                        const uint8_t* L, const double* vw, const double* K, const double* G1,
-                       const double* G2, const double* G3, const double* phi, uint8_t* code) {
-  hca_launch(k_ca_propose, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, d_step, L, vw, K, G1,
-             G2, G3, phi, code);
+                       const double* G2, const double* G3, const double* phi, uint8_t* code,
+                       uint8_t* win, CaList list) {
+  hca_launch(k_ca_scan, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, phi, code, win, list);
+  hca_launch(k_ca_propose_list, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, d_step, L, vw,
+             K, G1, G2, G3, list, code);
 }
 
-void launch_ca_resolve(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
-                       const double* phi, const uint8_t* code, uint8_t* win) {
-  hca_launch(k_ca_resolve, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, vw, phi, code, win);
+void launch_ca_resolve(hipStream_t s, const Work& w, const double* phi, const uint8_t* code,
+                       uint8_t* win, CaList list) {
+  hca_launch(k_ca_resolve_list, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, phi, code, list,
+             win);
 }
 
 void launch_ca_finalize(hipStream_t s, const Work& w, uint8_t* L, double* phi, double* P,

@@ -55,8 +55,9 @@ const double kBytesPerVoxel[KC_COUNT] = {
     36.0,         // cg_apply, multigrid: read z (4), p_old, c; write p_new, q
     72.0,         // cg_update, Jacobi: read x, p, r, q, z, dinv; write x, r, z
     57.0,         // ode: read L, K, P, Vc, phi; write P, Vc, phi
-    10.0,         // ca_propose: read L, phi; write code
-    11.0,         // ca_resolve: read L, w, code; write win
+    11.0,         // ca_propose: scan (read L, phi; write code, win); the list's decisions
+                  // gather per committed cell, not per voxel
+    0.0,          // ca_resolve: gathers per proposing cell only
     2.0,          // ca_finalize: read code, win (writes only where cells change)
     57.0,         // stats: read L, w and six fields
     21.0,         // mg prepare: read c (8); write dinv0 (4); level 1: read c, write c1, dinv1
@@ -109,6 +110,7 @@ struct hca_ctx {
 
   // state
   uint8_t *L = nullptr, *code = nullptr, *win = nullptr;
+  CaList ca_list{};                             // committed cells of the CA pass
   double *w = nullptr, *P = nullptr, *Vc = nullptr, *phi = nullptr;
   double* F = nullptr;                          // [K | G1 | G2], with vegf [K | G1 | G2 | V]
   double *K = nullptr, *G1 = nullptr, *G2 = nullptr, *G3 = nullptr, *V = nullptr;
@@ -630,13 +632,13 @@ hca_status run_phases(hca_ctx* c, unsigned mask) {
   }
   if (mask & HCA_PH_CA) {
     {
-      ProfScope ps(c, KC_CA_PROPOSE, kTagState);
+      ProfScope ps(c, KC_CA_PROPOSE, kTagState, false);
       launch_ca_propose(s, wk, c->dp, c->d_step, c->L, c->w, c->K, c->G1, c->G2, c->G3, c->phi,
-                        c->code);
+                        c->code, c->win, c->ca_list);
     }
     {
       ProfScope ps(c, KC_CA_RESOLVE, kTagState);
-      launch_ca_resolve(s, wk, c->L, c->w, c->phi, c->code, c->win);
+      launch_ca_resolve(s, wk, c->phi, c->code, c->win, c->ca_list);
     }
     {
       ProfScope ps(c, KC_CA_FINALIZE, kTagState);
@@ -1106,6 +1108,8 @@ hca_status alloc_all(hca_ctx* c) {
   HIPCHK(c, dalloc(&c->L, n));
   HIPCHK(c, dalloc(&c->code, n));
   HIPCHK(c, dalloc(&c->win, n));
+  HIPCHK(c, dalloc(&c->ca_list.cells, n));
+  HIPCHK(c, dalloc(&c->ca_list.item_n, (size_t)c->work.nflat));
   hca_status st;
   double** f1[] = {&c->w, &c->P, &c->Vc, &c->phi};
   for (double** p : f1)
@@ -1400,7 +1404,7 @@ hca_status steady_oxygen(hca_ctx* c) {
 }
 
 void free_all(hca_ctx* c) {
-  void* bufs[] = {c->L, c->code, c->win, c->w, c->P, c->Vc, c->phi, c->F, c->c, c->b,
+  void* bufs[] = {c->L, c->code, c->win, (void*)c->ca_list.cells, (void*)c->ca_list.item_n, c->w, c->P, c->Vc, c->phi, c->F, c->c, c->b,
                   c->sb.r, c->sb.z, (void*)c->sb.z32, (void*)c->sb.r32, c->sb.p0, c->sb.p1, c->sb.q, c->sb.dinv, c->sb.partial,
                   c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->b_o2lin, c->Fprev, c->d_step,
                   c->d_reps, c->d_flat, c->d_tiles, c->d_sys, c->d_sflat, c->d_stiles, c->d_cnt, (void*)c->d_cpart,
