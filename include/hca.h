@@ -342,6 +342,13 @@ hca_status hca_mlp_gradient(hca_mlp_trainer* t, const int32_t* idx, int batch, f
  * (j, step, 3, 0), key (seed, 0)); losses[k] (host, may be NULL) = loss of
  * step k's batch before its update. */
 hca_status hca_mlp_train(hca_mlp_trainer* t, int n_steps, int batch, float lr, float* losses);
+/* One Adam step (the trainer's next step t, bias-corrected, the moments and
+ * constants of hca_mlp_train) from a caller's gradient of HCA_MLP_NPARAM
+ * values (host or device, is_device), e.g. one reduced over several trainers'
+ * hca_mlp_gradient results.  lr > 0 and finite, else HCA_E_INVALID.  Adam
+ * as defined by Kingma and Ba: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * theta -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), in FP32. */
+hca_status hca_mlp_apply_gradient(hca_mlp_trainer* t, const float* grad, int is_device, float lr);
 /* Network outputs for n rows of X (device) into Y (device): raw = 1 takes
  * and returns model values, raw = 0 standardised ones. */
 hca_status hca_mlp_eval(hca_mlp_trainer* t, const float* X, int64_t n, int raw, float* Y);

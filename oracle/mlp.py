@@ -10,11 +10,14 @@ Parameters are one flat vector in the order W1 (64x6), b1, W2 (64x64), b2,
 W3 (64x64), b3, W4 (3x64), b4 - the same order the HIP library uses for its
 gradient and Adam buffers.
 
-``forward`` / ``backward`` are the plain definitions; ``quantised_forward``
-rounds weights and every activation to bfloat16 (round to nearest even) and
-accumulates in float64, which is what the MFMA kernels compute up to the
-accumulation order, so GPU results can be compared at a tolerance derived from
-bfloat16 rounding.
+``forward`` / ``backward`` are the plain definitions.  ``quantised_forward``
+and ``quantised_backward`` define the network evaluated with bfloat16
+operands: every operand of every matrix product (inputs, weights, hidden
+activations, dL/dy and the back-propagated dZ) is rounded to bfloat16 (round
+to nearest even), biases stay unrounded, products and sums are exact
+(float64).  That is what matrix cores with bfloat16 inputs compute up to the
+accumulation order, so GPU results can be compared with them at a tolerance
+derived from that order alone.
 """
 import numpy as np
 from scipy.special import erf
@@ -119,6 +122,32 @@ def quantised_forward(theta, X):
     for i in (1, 2, 3):
         h = bf16(gelu(h @ W[f"W{i}"].T + W[f"b{i}"]))
     return h @ W["W4"].T + W["b4"]
+
+
+def quantised_backward(theta, X, Y, rnd=bf16):
+    """Loss and gradient of the network with bfloat16 operands (see the
+    module docstring): the forward of ``quantised_forward``; dL/dy rounded;
+    each layer's dZ = rnd((dZ_next W_next) * GELU'(z)) with the rounded
+    weights; weight gradients dZ^T H and bias gradients sum(dZ) from the
+    rounded dZ and activations.  ``rnd`` = identity gives ``backward``."""
+    p = unpack(theta)
+    B = X.shape[0]
+    W = {k: rnd(v) for k, v in p.items() if k.startswith("W")}
+    h = [rnd(X)]
+    z = []
+    for i in (1, 2, 3):
+        z.append(h[-1] @ W[f"W{i}"].T + p[f"b{i}"])
+        h.append(rnd(gelu(z[-1])))
+    y = h[3] @ W["W4"].T + p["b4"]
+    d = y - Y
+    L = float(np.mean(d * d))
+    dz = rnd(2.0 * d / (B * NOUT))
+    g = {"W4": dz.T @ h[3], "b4": dz.sum(0)}
+    for i in (3, 2, 1):
+        dz = rnd((dz @ W[f"W{i + 1}"]) * gelu_grad(z[i - 1]))
+        g[f"W{i}"] = dz.T @ h[i - 1]
+        g[f"b{i}"] = dz.sum(0)
+    return L, pack(g)
 
 
 def adam_step(theta, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):

@@ -220,6 +220,21 @@ hca_status hca_mlp_train(hca_mlp_trainer* t, int n_steps, int batch, float lr, f
   return HCA_OK;
 }
 
+hca_status hca_mlp_apply_gradient(hca_mlp_trainer* t, const float* grad, int is_device, float lr) {
+  if (!t || !grad || !std::isfinite(lr) || lr <= 0.f) return HCA_E_INVALID;
+  // the gradient takes the place of a single workgroup partial (its loss
+  // slot is not read: no loss is reported)
+  TCHK(t, hipMemcpyAsync(t->partial, grad, sizeof(float) * kMlpNparam,
+                         is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, t->stream));
+  const long long step = t->t + 1;
+  launch_mlp_adam(t->stream, t->theta, t->m1, t->m2, t->partial, 1, (int)step, lr, 0.9f, 0.999f,
+                  1e-8f, 1, nullptr, nullptr, 1);
+  TCHK(t, hipGetLastError());
+  TCHK(t, hipStreamSynchronize(t->stream));
+  t->t = step;
+  return HCA_OK;
+}
+
 hca_status hca_mlp_eval(hca_mlp_trainer* t, const float* X, int64_t n, int raw, float* Y) {
   if (!t || !X || !Y || n < 0) return HCA_E_INVALID;
   if (n == 0) return HCA_OK;

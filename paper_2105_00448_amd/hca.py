@@ -140,6 +140,7 @@ def lib():
         "hca_mlp_gradient": (C.c_int, [vp, vp, C.c_int, vp, P(C.c_float)]),
         "hca_mlp_train": (C.c_int, [vp, C.c_int, C.c_int, C.c_float, vp]),
         "hca_mlp_eval": (C.c_int, [vp, vp, C.c_int64, C.c_int, vp]),
+        "hca_mlp_apply_gradient": (C.c_int, [vp, vp, C.c_int, C.c_float]),
         "hca_mlp_trainer_last_error": (C.c_char_p, [vp]),
         "hca_mlp_trainer_destroy": (None, [vp]),
     }
@@ -390,6 +391,18 @@ class Trainer:
         self._check(self._lib.hca_mlp_train(self._h, steps, batch, float(lr), out.ctypes.data),
                     "train")
         return out
+
+    def apply_gradient(self, grad, lr):
+        """One Adam step from a gradient (numpy float32 array on the host, or
+        a float32 device tensor)."""
+        if isinstance(grad, np.ndarray):
+            a = np.ascontiguousarray(grad, dtype=np.float32)
+            if a.shape != (MLP_NPARAM,):
+                raise ValueError("grad must have HCA_MLP_NPARAM values")
+            st = self._lib.hca_mlp_apply_gradient(self._h, a.ctypes.data, 0, float(lr))
+        else:
+            st = self._lib.hca_mlp_apply_gradient(self._h, grad.data_ptr(), 1, float(lr))
+        self._check(st, "apply_gradient")
 
     def eval(self, X, Y, raw=True):
         self._check(self._lib.hca_mlp_eval(self._h, X.data_ptr(), X.shape[0], 1 if raw else 0,

@@ -22,6 +22,8 @@ import pytest
 import torch
 
 from oracle import mlp as omlp
+from oracle import ode as oode
+from oracle.constants import DEFAULT as OP
 from paper_2105_00448_amd import hca, synth
 
 pytestmark = pytest.mark.gpu
@@ -342,3 +344,241 @@ def test_surrogate_error_and_flip_rate(trained):
         assert e["P"] <= 1e-2 and e["Vc"] <= 1e-2 and e["phi"] <= 1e-2
         # the margin sends every cell near the threshold to the plain integrator
         assert e["flips"] == 0
+
+
+# ---- Adam, the gradient element by element, the in-step apply kernel ---------------
+
+def test_adam_matches_oracle():
+    """Three Adam steps of the library (FP32) from fixed parameters and fixed
+    gradients against the oracle's adam_step in FP64, element by element.
+    The oracle takes the kernel's own FP32 constants (b1, b2, eps, lr as
+    float32 values), so the two differ only by FP32 rounding: each step's
+    update lr m^/(sqrt(v^) + eps) carries a relative error of a few 2^-24
+    (about ten roundings, powf within 2 ulp), and each theta -= update one
+    rounding of theta: |d theta| <= 3 (16 * 2^-24 lr + 2^-24 |theta|)."""
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((256, 6)).astype(np.float32)
+    Y = rng.standard_normal((256, 3)).astype(np.float32)
+    tr, _, _ = trainer_on(X, Y)
+    theta0 = random_theta(4)
+    tr.set_params(theta0)
+    lr = np.float32(2e-3)
+    # gradients over many decades, some exact zeros, changing sign between steps
+    grads = []
+    for k in range(3):
+        g = rng.standard_normal(hca.MLP_NPARAM) * 10.0 ** rng.uniform(-6, 1, hca.MLP_NPARAM)
+        g[rng.random(hca.MLP_NPARAM) < 0.02] = 0.0
+        grads.append(g.astype(np.float32))
+    th = theta0.astype(np.float64)
+    m = np.zeros(hca.MLP_NPARAM)
+    v = np.zeros(hca.MLP_NPARAM)
+    f32 = lambda x: float(np.float32(x))
+    for k, g in enumerate(grads):
+        if k == 1:   # once from a device tensor
+            tr.apply_gradient(torch.tensor(g, device=DEV), float(lr))
+        else:
+            tr.apply_gradient(g, float(lr))
+        th, m, v = omlp.adam_step(th, m, v, g.astype(np.float64), k + 1, float(lr), b1=f32(0.9),
+                                  b2=f32(0.999), eps=f32(1e-8))
+    got = tr.params().astype(np.float64)
+    u = 2.0 ** -24
+    tol = 3 * (16 * u * float(lr) + u * np.abs(th))
+    err = np.abs(got - th)
+    assert np.all(err <= tol), (err / tol).max()
+    # the parameters did move (by about lr per step where the gradient is not 0)
+    assert np.abs(got - theta0).max() > 2 * float(lr)
+    # and the next trainer step continues from step 4 (bias correction of t = 4)
+    tr.apply_gradient(grads[0], float(lr))
+    th, m, v = omlp.adam_step(th, m, v, grads[0].astype(np.float64), 4, float(lr), b1=f32(0.9),
+                              b2=f32(0.999), eps=f32(1e-8))
+    assert np.all(np.abs(tr.params() - th) <= 4 * (16 * u * float(lr) + u * np.abs(th)))
+    with pytest.raises(hca.HcaError):
+        tr.apply_gradient(grads[0], -1.0)
+    tr.close()
+
+
+def abs_term_sums(theta, X, Y):
+    """Per gradient element, the sum over the batch of the magnitudes of the
+    products it adds up, |dZ| |H| (|dZ| for a bias), with the bfloat16
+    operands of oracle.mlp.quantised_backward."""
+    q = omlp.bf16
+    p = omlp.unpack(theta)
+    B = X.shape[0]
+    W = {k: q(v) for k, v in p.items() if k.startswith("W")}
+    h = [q(X)]
+    z = []
+    for i in (1, 2, 3):
+        z.append(h[-1] @ W[f"W{i}"].T + p[f"b{i}"])
+        h.append(q(omlp.gelu(z[-1])))
+    y = h[3] @ W["W4"].T + p["b4"]
+    dz = q(2.0 * (y - Y) / (B * omlp.NOUT))
+    A = {"W4": np.abs(dz).T @ np.abs(h[3]), "b4": np.abs(dz).sum(0)}
+    for i in (3, 2, 1):
+        dz = q((dz @ W[f"W{i + 1}"]) * omlp.gelu_grad(z[i - 1]))
+        A[f"W{i}"] = np.abs(dz).T @ np.abs(h[i - 1])
+        A[f"b{i}"] = np.abs(dz).sum(0)
+    return omlp.pack(A)
+
+
+@pytest.mark.parametrize("batch", [64, 1024])
+def test_gradient_elementwise_matches_quantised_oracle(batch):
+    """The library's gradient against the oracle's gradient of the network
+    with bfloat16 operands (oracle.mlp.quantised_backward), element by
+    element.  The two differ by the kernel's FP32 accumulation (relative
+    2^-24 per addition) and its tabulated forward GELU (error <= 8e-6 |z|);
+    both can move an FP32 value across a bfloat16 rounding boundary, which
+    changes that one operand by one bfloat16 step (at most 2^-7 of it).  A
+    gradient element is a sum of products whose magnitudes add up to A_i,
+    so the bar is |g_i - g_i,ref| <= 2^-7 A_i (an emulation of the kernel's
+    rounding points stayed below 0.6 of it).  A wrong operand, packing slot,
+    transposition, missing GELU' factor or bias term moves an element by
+    O(|g_i|) ~ A_i/4.  Also normwise against the exact FP64 backward, the
+    bfloat16 quantisation itself: <= 3e-2 per block."""
+    print(f"\n[mlp gradient elementwise] batch={batch}", flush=True)
+    rng = np.random.default_rng(100 + batch)
+    n = 4000
+    X = (rng.standard_normal((n, 6)) * 2 + 1).astype(np.float32)
+    Xr = X.astype(np.float64)
+    Y = np.stack([np.sin(Xr[:, 0]), Xr[:, 1] * Xr[:, 2], np.tanh(Xr[:, 3] - Xr[:, 5])], 1)
+    tr, _, _ = trainer_on(X, Y.astype(np.float32))
+    theta = random_theta(13)
+    tr.set_params(theta)
+    Xs = torch.empty((n, 6), device=DEV)
+    Ys = torch.empty((n, 3), device=DEV)
+    tr.data(Xs, Ys)
+    idx = rng.integers(0, n, batch).astype(np.int32)
+    g = torch.empty(hca.MLP_NPARAM, dtype=torch.float32, device=DEV)
+    loss = tr.gradient(torch.tensor(idx, device=DEV), g)
+    Xb = Xs.cpu().numpy().astype(np.float64)[idx]
+    Yb = Ys.cpu().numpy().astype(np.float64)[idx]
+    th = theta.astype(np.float64)
+    Lq, gq = omlp.quantised_backward(th, Xb, Yb)
+    A = abs_term_sums(th, Xb, Yb)
+    got = g.cpu().numpy().astype(np.float64)
+    ratio = np.abs(got - gq) / (2.0 ** -7 * A + 1e-30)
+    worst = int(np.argmax(ratio))
+    print(f"[mlp gradient elementwise] max |dg|/(2^-7 A) {ratio.max():.3f}, median "
+          f"{np.median(ratio):.2e}; A/|g| median {np.median(A / (np.abs(gq) + 1e-30)):.2f}",
+          flush=True)
+    assert ratio.max() <= 1.0, (worst, got[worst], gq[worst], A[worst])
+    assert abs(loss - Lq) <= 1e-3 * Lq
+    _, gx = omlp.backward(th, Xb, Yb)
+    for name, blk in blocks(got).items():
+        ref = blocks(gx)[name]
+        assert np.linalg.norm(blk - ref) <= 3e-2 * np.linalg.norm(ref), name
+    tr.close()
+
+
+def test_surrogate_apply_matches_oracle(case_sur):
+    """The ODE phase with a surrogate set, on an oracle state, against the
+    oracle: voxels advanced by the network equal input + the oracle's
+    quantised forward of the standardised input (bfloat16 weights and
+    activations; tolerance in standardised units as for the forward test:
+    max 5e-3, RMS 5e-4), voxels sent to the plain integrator equal the
+    oracle's ode_step (P, V_c <= 1e-10, phi bit-exact), empty voxels and
+    stroma clocks are untouched.  The network is the oracle's initial
+    parameters with random biases, its statistics computed here from the
+    inputs, so every input comes from the oracle side.  A margin of 0.02
+    around phi = 1 sends a few hundred cells to the plain integrator;
+    voxels within the forward tolerance of that edge may go either way."""
+    tis, sched, s, theta, stats = case_sur
+    margin = 0.02
+    net = hca.Mlp()
+    th32 = np.ascontiguousarray(theta, dtype=np.float32)
+    net.theta = th32.ctypes.data
+    net.theta_is_device = 0
+    for k, v in stats.items():
+        arr = getattr(net, k)
+        for i, x in enumerate(v):
+            arr[i] = float(x)
+    net.box_check = 0
+    with hca.Simulation([(tis.cell, tis.w, tis.seed, (sched.times, sched.amts))],
+                        hca.default_params()) as sim:
+        for name in ("L", "K", "G1", "G2", "P", "Vc", "phi"):
+            sim.set_field(name, getattr(s, name))
+        sim.set_surrogate(net, margin)
+        sim.run_phases(hca.PH_ODE)
+        got = {k: sim.field(k).ravel() for k in ("P", "Vc", "phi")}
+        st = sim.stats()
+    L = s.L.ravel()
+    occ = L != 0
+    cancer = L == 1
+    raw = np.stack([getattr(s, k).ravel() for k in ("K", "G1", "G2", "P", "Vc", "phi")], 1)
+    # the kernel's FP32 standardisation, done identically in float32 here
+    xs = (raw.astype(np.float32) - stats["in_mean"]) * stats["in_scale"]
+    y = omlp.quantised_forward(theta.astype(np.float64), xs[occ].astype(np.float64))
+    sc = stats["out_scale"].astype(np.float64)
+    mu = stats["out_mean"].astype(np.float64)
+    upd = np.zeros((L.size, 3))
+    upd[occ] = y * sc + mu
+    tol = 5e-3 * sc                          # model units
+    Pp, Vp, php = oode.ode_step(s.L, s.K, s.P, s.Vc, s.phi, OP)
+    Pp, Vp, php = Pp.ravel(), Vp.ravel(), php.ravel()
+    gap = np.abs(s.phi.ravel() + upd[:, 2] - 1.0)
+    edge = np.abs(gap - margin) <= tol[2] + 1e-12
+    fb_sure = cancer & (gap < margin) & ~edge
+    net_sure = occ & ~fb_sure & ~(cancer & edge)
+    undecided = cancer & edge
+    assert fb_sure.sum() > 50 and net_sure.sum() > 5000
+    # counts
+    assert st["sur_voxels"] + st["sur_fallbacks"] == occ.sum()
+    assert fb_sure.sum() <= st["sur_fallbacks"] <= fb_sure.sum() + undecided.sum()
+    # plain-integrator voxels: the oracle's ODE step
+    scaleP, scaleV = np.abs(Pp[occ]).max(), np.abs(Vp[occ]).max()
+    assert np.abs(got["P"][fb_sure] - Pp[fb_sure]).max() <= 1e-10 * scaleP
+    assert np.abs(got["Vc"][fb_sure] - Vp[fb_sure]).max() <= 1e-10 * scaleV
+    assert np.array_equal(got["phi"][fb_sure], php[fb_sure])
+    # network voxels: input + the quantised forward, in standardised units
+    d = {}
+    for k, j, base in (("P", 0, s.P.ravel()), ("Vc", 1, s.Vc.ravel())):
+        d[k] = ((got[k] - base) - upd[:, j])[net_sure] / sc[j]
+    m = net_sure & cancer
+    d["phi"] = ((got["phi"] - s.phi.ravel()) - upd[:, 2])[m] / sc[2]
+    for k, v in d.items():
+        print(f"[surrogate apply] {k}: max {np.abs(v).max():.2e} rms {np.sqrt((v ** 2).mean()):.2e}",
+              flush=True)
+        assert np.abs(v).max() <= 5e-3, k
+        assert np.sqrt((v ** 2).mean()) <= 5e-4, k
+    # stroma carries no clock; empty voxels are untouched
+    stroma = L == 2
+    assert np.array_equal(got["phi"][stroma], s.phi.ravel()[stroma])
+    for k in ("P", "Vc", "phi"):
+        assert np.array_equal(got[k][~occ], getattr(s, k).ravel()[~occ])
+    # the undecided voxels took one of the two results
+    for i in np.flatnonzero(undecided):
+        plain = (abs(got["P"][i] - Pp[i]) <= 1e-10 * scaleP and got["phi"][i] == php[i])
+        netw = abs((got["P"][i] - s.P.ravel()[i]) - upd[i, 0]) <= tol[0]
+        assert plain or netw, i
+
+
+@pytest.fixture(scope="module")
+def case_sur():
+    """An oracle state after three oracle steps of the 32^3 workload (seed 9)
+    with this step's fields solved, and a network: the oracle's initial
+    parameters (seed 3) with biases ~ 0.3 N(0, 1), input statistics of the
+    state's occupied voxels, output scales of a plausible update size."""
+    from oracle import model as om
+    print("\n[case_sur] oracle state, 32^3 seed 9", flush=True)
+    tis = synth.make_tissue(32, 8, seed=9)
+    sched = synth.bolus_schedule([0])
+    osched = om.Schedule(times=sched.times, amts=sched.amts)
+    s = om.init_state(tis.cell, tis.w, tis.seed, OP)
+    for _ in range(3):
+        s, _ = om.step(s, tis.w, osched, tis.seed, OP)
+    K, G1, G2 = om.solve_fields(s, tis.w, osched, OP)
+    s = om.State(s.L, K, G1, G2, s.P, s.Vc, s.phi, s.step)
+    rng = np.random.default_rng(17)
+    p = omlp.unpack(omlp.init_params(3))
+    for k in p:
+        if k.startswith("b"):
+            p[k] = 0.3 * rng.standard_normal(p[k].shape)
+    theta = omlp.pack(p).astype(np.float32).astype(np.float64)
+    occ = s.L.ravel() != 0
+    raw = np.stack([getattr(s, k).ravel() for k in ("K", "G1", "G2", "P", "Vc", "phi")], 1)[occ]
+    sd = raw.std(0)
+    stats = dict(in_mean=raw.mean(0).astype(np.float32),
+                 in_scale=np.where(sd > 0, 1.0 / np.where(sd > 0, sd, 1.0), 1.0).astype(np.float32),
+                 out_mean=np.array([1e-5, -2e-5, 5e-3], np.float32),
+                 out_scale=np.array([3e-5, 4e-5, 2e-3], np.float32),
+                 in_lo=raw.min(0).astype(np.float32), in_hi=raw.max(0).astype(np.float32))
+    return tis, sched, s, theta, stats

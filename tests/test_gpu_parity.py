@@ -502,3 +502,111 @@ def test_long_run_past_the_last_dose(case32):
         assert st["step"] == 700 and not st["nonfinite"]
         g2 = sim.field("G2")
         assert np.isfinite(g2).all() and 0.0 < np.abs(g2).max() < 1e-30
+
+
+# ---- a batched context against the oracle, replicate by replicate -----------------
+
+BATCH_SPECS = [
+    # (shape (nz, ny, nx), seed, dose schedule)
+    ((12, 10, 9), 31, synth.bolus_schedule([0])),
+    ((1, 20, 17), 32, synth.bolus_schedule([0, 2])),                   # 2-D slice
+    ((16, 16, 16), 33, synth.DoseSchedule(times=((), ()), amts=((), ()))),   # drug-free control
+    ((9, 23, 17), 34, synth.DoseSchedule(times=((30.0,), (30.0,)), amts=((1.3,), (0.6,)))),
+    ((24, 8, 13), 35, synth.bolus_schedule([0, 2], amount=0.7)),
+]
+
+
+@PRECONDS
+def test_batched_context_matches_oracle_per_replicate(precond):
+    """One context holding five uneven replicates (incl. a 2-D slice and a
+    drug-free control) against the oracle's step of each replicate on its
+    own: every step restarts all replicates from the oracle's states; the
+    batched solves <= 1e-10 per replicate; the ODE and CA on the shared
+    fields bit-exact in L and phi (P, V_c <= 1e-10) with the same events."""
+    cases = []
+    for shape, seed, sched in BATCH_SPECS:
+        t = synth.make_tissue(shape, 4, seed=seed)
+        assert (t.w > 0).any()
+        cases.append((t, sched))
+    states = [om.init_state(t.cell, t.w, t.seed, OP) for t, _ in cases]
+    totals = dict(divisions=0, kills=0)
+    with make_sim(cases, precond=precond) as sim:
+        for r, s in enumerate(states):
+            assert relerr(sim.field("K", r), s.K) <= FIELD_TOL, r
+            assert np.array_equal(sim.field("phi", r), s.phi), r
+        for n in range(4):
+            print(f"[batched vs oracle] precond {precond} step {n}", flush=True)
+            for r, s in enumerate(states):
+                push_state(sim, s, r)
+            sim.run_phases(hca.PH_O2 | hca.PH_DRUGS)
+            solved = []
+            for r, ((t, sched), s) in enumerate(zip(cases, states)):
+                K, G1, G2 = om.solve_fields(s, t.w, oracle_sched(sched), OP)
+                for name, ref in (("K", K), ("G1", G1), ("G2", G2)):
+                    assert relerr(sim.field(name, r), ref) <= FIELD_TOL, (n, r, name)
+                if r == 2:
+                    assert not sim.field("G1", r).any() and not sim.field("G2", r).any()
+                solved.append((K, G1, G2))
+                for name, v in (("K", K), ("G1", G1), ("G2", G2)):
+                    sim.set_field(name, v, r)
+            sim.run_phases(hca.PH_ODE | hca.PH_CA | hca.PH_STATS | hca.PH_ADVANCE)
+            nxt = []
+            for r, ((t, sched), s, (K, G1, G2)) in enumerate(zip(cases, states, solved)):
+                P, Vc, phi = oode.ode_step(s.L, K, s.P, s.Vc, s.phi, OP)
+                Ln, phin, Pn, Vn, ev, _, _ = oca.ca_update(s.L, t.w, K, G1, G2, phi, P, Vc,
+                                                           s.step, t.seed, OP)
+                assert np.array_equal(sim.field("L", r), Ln), (n, r)
+                assert np.array_equal(sim.field("phi", r), phin), (n, r)
+                assert relerr(sim.field("P", r), Pn) <= FIELD_TOL, (n, r)
+                assert relerr(sim.field("Vc", r), Vn) <= FIELD_TOL, (n, r)
+                st = sim.stats(r)
+                assert st["step"] == n + 1
+                for k in ("committed", "kills", "divisions", "nospace", "lost"):
+                    assert st[k] == ev[k], (n, r, k)
+                totals["divisions"] += ev["divisions"]
+                totals["kills"] += ev["kills"]
+                if r == 2:
+                    assert ev["kills"] == 0
+                nxt.append(om.State(Ln, K, G1, G2, Pn, Vn, phin, s.step + 1))
+            states = nxt
+    assert totals["divisions"] > 0 and totals["kills"] > 0, totals
+
+
+# ---- a lattice with three multi-workgroup multigrid levels --------------------------
+
+@pytest.mark.slow
+def test_96cube_three_global_mg_levels_match_oracle():
+    """96^3 (32 Gaussians, ~86 % occupied) with the default one-workgroup
+    coarse solve from 4096 cells: the V-cycle smooths 96^3, 48^3 and 24^3 with
+    the multi-workgroup kernels before the 12^3 coarse solve.  Steady-oxygen
+    init and one step's solves <= 1e-10 against the oracle, then the ODE and
+    the CA on the shared fields bit-exact."""
+    print("\n[96^3] oracle init (about 30 s)", flush=True)
+    tis = synth.make_tissue(96, 32, seed=5)
+    sched = synth.bolus_schedule([0])
+    osched = oracle_sched(sched)
+    s0 = om.init_state(tis.cell, tis.w, tis.seed, OP)
+    with make_sim([(tis, sched)]) as sim:
+        assert relerr(sim.field("K"), s0.K) <= FIELD_TOL
+        assert np.array_equal(sim.field("phi"), s0.phi)
+        sim.run_phases(hca.PH_O2 | hca.PH_DRUGS)
+        print("[96^3] oracle solves (about 30 s)", flush=True)
+        K, G1, G2 = om.solve_fields(s0, tis.w, osched, OP)
+        for name, ref in (("K", K), ("G1", G1), ("G2", G2)):
+            err = relerr(sim.field(name), ref)
+            print(f"[96^3] {name} rel. err {err:.2e}", flush=True)
+            assert err <= FIELD_TOL, name
+        for name, v in (("K", K), ("G1", G1), ("G2", G2)):
+            sim.set_field(name, v)
+        sim.run_phases(hca.PH_ODE | hca.PH_CA | hca.PH_STATS)
+        P, Vc, phi = oode.ode_step(s0.L, K, s0.P, s0.Vc, s0.phi, OP)
+        Ln, phin, Pn, Vn, ev, _, _ = oca.ca_update(s0.L, tis.w, K, G1, G2, phi, P, Vc, 0,
+                                                   tis.seed, OP)
+        assert np.array_equal(sim.field("L"), Ln)
+        assert np.array_equal(sim.field("phi"), phin)
+        assert relerr(sim.field("P"), Pn) <= FIELD_TOL
+        assert relerr(sim.field("Vc"), Vn) <= FIELD_TOL
+        st = sim.stats()
+        for k in ("committed", "kills", "divisions", "nospace", "lost"):
+            assert st[k] == ev[k], k
+        assert ev["divisions"] > 100 and ev["kills"] > 100
