@@ -18,6 +18,7 @@
 // GELU(z) = z Phi(z) with erf from Abramowitz & Stegun 7.1.26 (absolute error
 // <= 1.5e-7, far below the bfloat16 rounding of the activations), hardware
 // reciprocal and exp2; its derivative Phi(z) + z phi(z) reuses the exponential.
+#include <cmath>
 #include <type_traits>
 
 #include "dev_util.h"
@@ -814,12 +815,14 @@ __global__ void __launch_bounds__(128) k_mlp_grad(const bf16x8* __restrict__ pk,
   if (threadIdx.x == 0) pg[kMlpNparam] = sloss[0] + sloss[1];
 }
 
-// Sums the workgroup partials in workgroup order; with `update`, Adam step t
-// (t counts from 1, bias-corrected).  Slot kMlpNparam is the batch's summed
+// Sums the workgroup partials in workgroup order; with `update`, an Adam step
+// with the bias corrections bc1 = 1/(1 - b1^t), bc2 = 1/(1 - b2^t) of step t
+// (from the launcher, in FP64: 1 - b2^t evaluated in FP32 would lose about
+// 2^-24 / (1 - b2^t) of its relative accuracy to cancellation).  Slot kMlpNparam is the batch's summed
 // squared error, reported as the mean loss.
 __global__ void k_mlp_adam(float* __restrict__ th, float* __restrict__ m1, float* __restrict__ m2,
-                           const float* __restrict__ partial, int nwg, int t, float lr, float b1,
-                           float b2, float eps, int update, float* __restrict__ grad_out,
+                           const float* __restrict__ partial, int nwg, float bc1, float bc2, float lr,
+                           float b1, float b2, float eps, int update, float* __restrict__ grad_out,
                            float* __restrict__ loss_out, int batch) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p > kMlpNparam) return;
@@ -835,8 +838,8 @@ __global__ void k_mlp_adam(float* __restrict__ th, float* __restrict__ m1, float
   const float v = b2 * m2[p] + (1.0f - b2) * g * g;
   m1[p] = a;
   m2[p] = v;
-  const float ah = a / (1.0f - powf(b1, (float)t));
-  const float vh = v / (1.0f - powf(b2, (float)t));
+  const float ah = a * bc1;
+  const float vh = v * bc2;
   th[p] -= lr * ah / (sqrtf(vh) + eps);
 }
 
@@ -941,8 +944,10 @@ void launch_mlp_grad(hipStream_t s, const bf16x8* pk, const float* th, const flo
 void launch_mlp_adam(hipStream_t s, float* th, float* m1, float* m2, const float* partial, int nwg,
                      int t, float lr, float b1, float b2, float eps, int update, float* grad_out,
                      float* loss_out, int batch) {
+  const float bc1 = (float)(1.0 / (1.0 - std::pow((double)b1, (double)t)));
+  const float bc2 = (float)(1.0 / (1.0 - std::pow((double)b2, (double)t)));
   hca_launch(k_mlp_adam, dim3((kMlpNparam + 1 + 255) / 256), dim3(256), 0, s, th, m1, m2,
-                     partial, nwg, t, lr, b1, b2, eps, update, grad_out, loss_out, batch);
+                     partial, nwg, bc1, bc2, lr, b1, b2, eps, update, grad_out, loss_out, batch);
 }
 
 void launch_mlp_eval(hipStream_t s, const bf16x8* pk, const float* th, const float2* tab,
