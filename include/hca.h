@@ -352,6 +352,24 @@ hca_status hca_mlp_apply_gradient(hca_mlp_trainer* t, const float* grad, int is_
 /* Network outputs for n rows of X (device) into Y (device): raw = 1 takes
  * and returns model values, raw = 0 standardised ones. */
 hca_status hca_mlp_eval(hca_mlp_trainer* t, const float* X, int64_t n, int raw, float* Y);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, training or serving loops that forbid hipMalloc): the gradient and
+ * loss of hca_mlp_gradient without a trainer and without any allocation.
+ * theta (HCA_MLP_NPARAM), Xs (n_rows x 6) and Ys (n_rows x 3, standardised
+ * rows as hca_mlp_trainer_data returns them) and idx (batch int32 row
+ * indices, clamped to [0, n_rows)) are device inputs; grad (HCA_MLP_NPARAM)
+ * and loss (one float, may be NULL: the batch's mean squared error) are
+ * device outputs.  batch must be a positive multiple of 64 of at most
+ * HCA_MLP_NOALLOC_MAX_BATCH, else HCA_E_RANGE before any work.  The work is
+ * only enqueued on `stream` (NULL: the null stream); the caller synchronises.
+ * The scratch (about 2.4 MB: packed operands, GELU table, per-64-sample
+ * partials) is one static device array per GPU, held until the process ends
+ * and shared by every call on that GPU: calls that overlap on one GPU (other
+ * streams or threads) race and must be serialised by the caller. */
+#define HCA_MLP_NOALLOC_MAX_BATCH 4096
+hca_status hca_mlp_gradient_noalloc(const float* theta, const float* Xs, const float* Ys,
+                                    int64_t n_rows, const int32_t* idx, int batch, float* grad,
+                                    float* loss, void* stream);
 const char* hca_mlp_trainer_last_error(const hca_mlp_trainer* t);
 void hca_mlp_trainer_destroy(hca_mlp_trainer* t);
 

@@ -32,7 +32,8 @@ EXTRA = {
     "k_ca.hip": ["-ffp-contract=off"],
 }
 SOURCES = ["runtime.cpp", "mlp_runtime.cpp", "k_setup.hip", "k_solver.hip", "k_ode.hip", "k_ca.hip", "k_mg.hip",
-           "k_mlp.hip"]
+           "k_mlp.hip",
+           "noalloc.hip"]
 
 
 def hipcc():

@@ -141,6 +141,7 @@ def lib():
         "hca_mlp_train": (C.c_int, [vp, C.c_int, C.c_int, C.c_float, vp]),
         "hca_mlp_eval": (C.c_int, [vp, vp, C.c_int64, C.c_int, vp]),
         "hca_mlp_apply_gradient": (C.c_int, [vp, vp, C.c_int, C.c_float]),
+        "hca_mlp_gradient_noalloc": (C.c_int, [vp, vp, vp, C.c_int64, vp, C.c_int, vp, vp, vp]),
         "hca_mlp_trainer_last_error": (C.c_char_p, [vp]),
         "hca_mlp_trainer_destroy": (None, [vp]),
     }
@@ -334,6 +335,18 @@ class Simulation:
 
     def __exit__(self, *a):
         self.close()
+
+
+def mlp_gradient_noalloc(theta, Xs, Ys, idx, grad, loss=None, stream=None):
+    """hca_mlp_gradient_noalloc on device tensors (theta, Xs, Ys float32;
+    idx int32; grad float32 NPARAM; loss a one-element float32 tensor or
+    None); enqueues only."""
+    st = lib().hca_mlp_gradient_noalloc(theta.data_ptr(), Xs.data_ptr(), Ys.data_ptr(),
+                                        Xs.shape[0], idx.data_ptr(), idx.numel(), grad.data_ptr(),
+                                        loss.data_ptr() if loss is not None else None,
+                                        C.c_void_p(stream) if stream else None)
+    if st != OK:
+        raise HcaError(st, "hca_mlp_gradient_noalloc")
 
 
 def schedule_tuple(sched):
