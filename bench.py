@@ -1,57 +1,42 @@
 """Benchmark of the coupled HCA time step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload plain128]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config5] [--legs ...]
 
-Workloads (all synthetic, seeded; generator recipe in paper_2105_00448_amd/synth.py):
-  plain128   128^3 lattice, density from 64 Gaussians, 10% vessels, both drugs
-             dosed at steps 0 and 50, 100 coupled steps of 30 min, FP64 fields,
-             solves to relative residual 1e-10.   (default)
-  batched64  64 replicates, cubic edges ~ U{48..96}, per-replicate seed and
-             schedule (dose x U[0.5,1.5] on day {0,1,2}), 50 steps, one launch
-             per phase kernel for the whole batch.
+Headline (default ``--workload config5``), the metric "voxel-steps/s per GPU:
+plain vs surrogate+batched at matched error/flip rate" on its largest
+single-GPU configuration: 4 replicates (seeds 5000..5003) of a 384^3 lattice
+(56.6M voxels each, 226M in one context), density from 512 Gaussians, 10 %
+lognormal vessels, both drugs dosed at steps 0 and 100, 200 coupled steps of
+30 min (K of them timed with --steps), FP64 fields.  The ODE surrogate is
+trained first on the GPU (10^6 pairs harvested from the plain integrator on
+32^3 lattices, 4000 Adam steps); then two contexts of the same lattices, each
+init + W warm-up steps + K timed steps (inputs resident, no events, CG
+iterations replayed from HIP graphs), then a few event-timed steps of the same
+context for the kernel shares, the roofline kernel and the MFMA kernel:
+  ``plain``   the plain intracellular integrator;
+  ``value``   surrogate ODE (fallback within 1e-3 of phi = 1) + batched.
+Also: the per-step error and decision-flip rate of the surrogate against the
+plain integrator on identical inputs (replicate 0, 3 steps), the whole step's
+algorithmic HBM bytes per voxel-step and their rate, the MFMA utilisation of
+the surrogate kernel, and the paper's own CPU-cluster figures as context.
+``cpu_baseline`` times the FP64 CPU oracle on one core on a 32^3 block of the
+headline workload's first replicate.
 
-Prints ONE JSON line.  ``value`` is voxel-steps/s = voxels x steps / wall time
-of the timed steps (inputs resident in HBM, init excluded), the median of
-``--repeats`` timed runs from a fresh context each.  ``roofline`` is the
-dominant kernel's algorithmic bytes per launch / its mean duration, from
-start/stop events carried by that kernel's launches on the library's stream
-during one further timed run of the same workload (events on every launch of
-the other runs would slow them; that run's step time is reported as
-``profiled_repeat_ms_per_step``).
-``cpu_baseline`` times the FP64 CPU oracle on a bounded sample on one core.
+Legs (``--legs``, comma-separated; default plain128,batched):
+  plain128   the 128^3 plain workload (64 Gaussians, boluses at steps 0 and
+             50), median of 3 runs from fresh contexts, with its roofline;
+  batched    64 replicates of cubic edge U{48..96}, per-replicate seed and
+             schedule, 50 steps, autotuned tiles;
+  fp32       the headline lattices plain and surrogate with the solved fields
+             stored in FP32 (precision 32);
+  cpu_wide   the oracle on the 128^3 workload's first 5 steps (extrapolated)
+             and on 4 ensemble replicates in 4 processes (minutes);
+  surrogate  the 256^3 surrogate workload; substeps, newton, paper2d, vegf,
+             fec: the options of the model on the 128^3 workload (see the
+             leg functions).
 
-Two further legs (skip with --no-legs) report the other throughputs of the
-same metric beside the plain one:
-  surrogate  10^6 training pairs harvested from the plain integrator on 32^3
-             lattices (seeds 1..6, 20 steps each), the network trained on the GPU,
-             then the 256^3 lattice (64 Gaussians, bolus at steps 0 and 50)
-             stepped plain and with the surrogate ODE phase (margin 1e-3), and
-             the per-step error and decision-flip rate of the surrogate against
-             the plain integrator on identical inputs;
-  batched    the batched64 ensemble;
-  substeps   the plain 128^3 workload with the paper's field time step: 30
-             implicit 1-min substeps per 30-min coupled step, backward Euler
-             and Crank-Nicolson (10 coupled steps each; off by default, add
-             with --legs);
-  newton     the plain 128^3 workload with 3 Newton steps on the nonlinear
-             oxygen uptake after each linearised solve: step time, and the
-             linearisation gap max|K_newton - K_linearised| / max K at matched
-             inputs over 5 steps (off by default, add with --legs);
-  paper2d    the paper's solver-performance setting as synthetic input: a 2-D
-             1 mm^2 slice of 100 x 100 voxels of 10 um, cell and vascular
-             densities 0.4 and 0.12, 30 Crank-Nicolson 1-min field substeps
-             per 30-min update; one slice and a batch of 64 (off by default);
-  vegf       the plain 128^3 workload with the extracellular VEGF field solved
-             in the same batch as the other three and the vessel birth-death
-             update every 720 min, 48 steps (two updates): step time beside
-             the plain one, vessel events, and the vessel kernel's duration
-             (off by default);
-  fec        the plain 128^3 workload with the full FEC cocktail: epirubicin
-             as a third drug (three-compartment plasma kinetics, its own
-             tissue field and kill trial) dosed with the other two, 48 steps;
-             alone, and with every option at once (exact Michaelis-Menten
-             fluorouracil, VEGF and vessel updates: five fields per batched
-             solve) (off by default).
+``--profile-only`` (for rocprofv3 runs): one context of the workload stepped
+W + K times, nothing else timed.
 """
 import argparse
 import json
@@ -79,6 +64,22 @@ def make_workload(name):
                            "implicit Euler dt=30min, FP64 CG to rel. res. 1e-10",
                "lattice": [128, 128, 128], "replicates": 1, "seed": 2, "config_steps": 100}
         return reps, cfg, 100
+    if name == "config5":
+        reps = []
+        sched = synth.bolus_schedule([0, 100])
+        for r in range(4):
+            tis = synth.make_tissue(384, 512, seed=5000 + r)
+            reps.append((tis.cell, tis.w, tis.seed, (sched.times, sched.amts)))
+        cfg = {"workload": "largest single-GPU domain: 4 replicates (Philox seeds 5000..5003) of a "
+                           "384^3 lattice (h=20um, 56.6M voxels each, 226M in one context), "
+                           "heterogeneous density from 512 Gaussians, 10% lognormal vessels, O2 + 2 "
+                           "drugs (bolus of both at steps 0 and 100), implicit Euler dt=30min, FP64 "
+                           "MG-CG to rel. res. 1e-10; surrogate ODE (MLP 6-64-64-64-3, BF16 MFMA) with "
+                           "plain-integrator fallback within 1e-3 of phi = 1; all replicates batched "
+                           "in one launch per phase",
+               "lattice": [384, 384, 384], "replicates": 4, "seeds": [5000, 5001, 5002, 5003],
+               "gaussians": 512, "config_steps": 200}
+        return reps, cfg, 200
     if name == "batched64":
         ens = synth.ensemble(64, seed0=1000)
         reps = [(t.cell, t.w, t.seed, (s.times, s.amts)) for t, s in ens]
@@ -91,10 +92,12 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, bytes_per_launch=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size), or
-    None if the kernel's sources changed since the counters were taken."""
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size): its
+    measured bytes per voxel times this launch's active voxels (algorithmic
+    bytes per launch / algorithmic bytes per voxel); None if the kernel's
+    sources changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     try:
@@ -104,7 +107,11 @@ def measured_traffic(kernel, workload):
             h.update(open(os.path.join(ROOT, f), "rb").read())
     except (OSError, KeyError, ValueError):
         return None
-    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    if "traffic_bytes_per_voxel" in rec and bytes_per_launch:
+        return rec["traffic_bytes_per_voxel"] / rec["algorithmic_bytes_per_voxel"] * bytes_per_launch
+    return rec.get("traffic_bytes_per_launch")
 
 
 def cpu_model():
@@ -117,35 +124,91 @@ def cpu_model():
     return platform.processor()
 
 
-def cpu_baseline(budget_s=12.0):
+def cpu_baseline(crop=None, budget_s=12.0):
     """The oracle as it stands (CG solves to rel. residual 1e-15, NumPy ODE and
-    CA) on one core: the small workload in full (32^3 lattice, 8-Gaussian
-    density, seed 1, bolus of both drugs at step 0, 20 coupled steps from
-    init), repeated until about `budget_s` seconds of stepping."""
+    CA) on one core, repeated until about `budget_s` seconds of stepping:
+    20 coupled steps from init of `crop` = (cell, w, seed, (times, amts)), a
+    32^3 block of the headline workload's first replicate (same generator,
+    its dose schedule; zero-flux faces at the block's edges), or of the 32^3
+    8-Gaussian workload (seed 1, bolus at step 0) without one."""
     from threadpoolctl import threadpool_limits
 
     from oracle import model as om
     from oracle.constants import DEFAULT as OP
     from paper_2105_00448_amd import synth
-    tis = synth.make_tissue(32, 8, seed=1)
-    sched = synth.bolus_schedule([0])
-    osched = om.Schedule(times=sched.times, amts=sched.amts)
+    if crop is None:
+        tis = synth.make_tissue(32, 8, seed=1)
+        sched = synth.bolus_schedule([0])
+        cell, w, seed, (times, amts) = tis.cell, tis.w, tis.seed, (sched.times, sched.amts)
+        what = "the 32^3 workload (8-Gaussian density, seed 1, bolus at step 0) in full"
+    else:
+        cell, w, seed, (times, amts) = crop
+        what = ("a 32^3 block (voxels [0,32)^3) of the headline workload's first 384^3 replicate "
+                f"(512-Gaussian density, seed {seed}, its bolus at step 0)")
+    osched = om.Schedule(times=times, amts=amts)
     el, n, runs = 0.0, 0, 0
     with threadpool_limits(limits=1):
         while el < budget_s:
-            s = om.init_state(tis.cell, tis.w, tis.seed, OP)
+            s = om.init_state(cell, w, seed, OP)
             t0 = time.perf_counter()
             for _ in range(20):
-                s, _ = om.step(s, tis.w, osched, tis.seed, OP)
+                s, _ = om.step(s, w, osched, seed, OP)
             el += time.perf_counter() - t0
             n += 20
             runs += 1
-    vox = tis.cell.size
+    vox = cell.size
     return {"value": vox * n / el, "unit": "voxel-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"the 32^3 workload (8-Gaussian density, seed 1, bolus at step 0) in full, "
-                      f"20 coupled steps from init, {runs} runs ({n} steps, {el:.1f}s of stepping, "
-                      f"init excluded); FP64 diagonally scaled CG to rel. residual 1e-15, single "
-                      f"thread; host: {cpu_model()}, {os.cpu_count()} logical CPUs"}
+            "sample": f"{what}, 20 coupled steps from init, {runs} runs ({n} steps, {el:.1f}s of "
+                      f"stepping, init excluded); FP64 diagonally scaled CG to rel. residual 1e-15, "
+                      f"single thread; host: {cpu_model()}, {os.cpu_count()} logical CPUs"}
+
+
+def _oracle_steps(args):
+    """Worker of cpu_wide: (cell, w, seed, times, amts, steps) -> (voxels, steps, seconds)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import model as om
+    from oracle.constants import DEFAULT as OP
+    cell, w, seed, times, amts, steps = args
+    with threadpool_limits(limits=1):
+        s = om.init_state(cell, w, seed, OP)
+        sched = om.Schedule(times=times, amts=amts)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s, _ = om.step(s, w, sched, seed, OP)
+        return cell.size, steps, time.perf_counter() - t0
+
+
+def cpu_wide():
+    """The oracle on the larger workloads (minutes of CPU time; off by
+    default): the 128^3 workload over its first 5 steps (its 100-step run
+    extrapolated from them, labelled so), and 4 replicates of the
+    64-replicate ensemble, one process each."""
+    import multiprocessing as mp
+    reps, _, _ = make_workload("plain128")
+    cell, w, seed, (times, amts) = reps[0]
+    print("[bench:cpu_wide] oracle, 128^3, 5 steps", file=sys.stderr, flush=True)
+    nv, ns, el = _oracle_steps((cell, w, seed, times, amts, 5))
+    out = {"plain128_first5": {"value": nv * ns / el, "unit": "voxel-steps/s", "cores": 1,
+                               "seconds_5_steps": el,
+                               "extrapolated_100_steps_s": el * 20,
+                               "note": "5 steps after init, extrapolated linearly to 100"}}
+    ens, _, _ = make_workload("batched64")
+    jobs = [(c, ww, sd, tm, am, 50) for c, ww, sd, (tm, am) in ens[:4]]
+    print("[bench:cpu_wide] oracle, 4 ensemble replicates x 50 steps, 4 processes",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(4) as pool:
+        res = pool.map(_oracle_steps, jobs)
+    wall = time.perf_counter() - t0
+    vs = sum(r[0] * r[1] for r in res)
+    out["batched4"] = {"value": vs / max(r[2] for r in res), "unit": "voxel-steps/s", "cores": 4,
+                       "replicates": [list(c.shape) for c, *_ in jobs], "steps": 50,
+                       "wall_s_incl_init": wall,
+                       "note": "4 of the 64 replicates, one process each; value from the slowest "
+                               "process's stepping time (init excluded)"}
+    out["host"] = f"{cpu_model()}, {os.cpu_count()} logical CPUs"
+    return out
 
 
 def timed_run(reps, params, steps, stream, net=None, margin=1e-3, tile_shapes=False):
@@ -431,56 +494,332 @@ def paper2d_leg(stream, steps=10, batch=64):
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="plain128")
-    ap.add_argument("--precond", type=int, default=1, help="0 Jacobi, 1 multigrid")
-    ap.add_argument("--mg-coarse-max", type=int, default=None,
-                    help="levels with at most this many cells go to the one-workgroup solve")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--graphs", type=int, default=1, help="1: replay captured CG iterations")
-    ap.add_argument("--autotune", type=int, default=0, help="1: tile plan from the autotuner")
-    ap.add_argument("--repeats", type=int, default=5,
-                    help="timed repeats from a fresh context; value = median")
-    ap.add_argument("--no-legs", action="store_true", help="plain workload only")
-    ap.add_argument("--legs", default="surrogate,batched",
-                    help="comma-separated further legs: surrogate, batched, substeps, newton, paper2d, "
-                         "vegf, fec")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="first copy MIB MiB device-to-device three times (a kernel of known "
-                         "traffic for scaling hardware byte counters)")
-    ap.add_argument("--sur-steps", type=int, default=100)
-    ap.add_argument("--train-steps", type=int, default=4000)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: the library has no multi-GPU path "
-              "(replicates and z-slabs would shard across GPUs).",
-              file=sys.stderr)
-        raise SystemExit(2)
+# MI355X dense bf16 MFMA peak (no sparsity), FLOP/s
+MFMA_BF16_PEAK = 2.5e15
+# network flops per voxel: algorithmic (2 x multiply-adds of 6-64-64-64-3) and as
+# executed on 32x32x16 tiles (6 inputs padded to 16, 3 outputs to 32)
+MLP_FLOP_ALG = 2 * (6 * 64 + 64 * 64 + 64 * 64 + 64 * 3)
+MLP_FLOP_EXEC = 2 * (64 * 16 + 64 * 64 + 64 * 64 + 32 * 64)
+# the paper's own CPU figures for this path (its weak-scaling tables), context only
+PAPER_CONTEXT = {
+    "hardware": "Saga (NTNU): Intel Xeon Gold 6138 @ 2.0 GHz, 40 cores and 192 GiB per node, "
+                "1 to 80 cores; FEniCS 2019.1.0 + PETSc + hypre BoomerAMG",
+    "discretisation": "2-D P1 finite elements on a 4x refined mesh (~16 dofs per lattice node), "
+                      "Crank-Nicolson, 30 x 1-min PDE steps per 30-min update; not like-for-like",
+    "chemo_update_1core": {"dofs": 159197, "assembly_s": 2.9177, "solve_s": 6.2043},
+    "chemo_update_80cores": {"dofs": 12809237, "assembly_s": 3.7708, "solve_s": 15.784},
+    "o2_linearised_update_1core": {"assembly_s": 2.6657, "solve_s": 3.0532},
+    "o2_linearised_update_80cores": {"assembly_s": 3.5985, "solve_s": 6.8429},
+    "derived_dof_steps_per_s_1core_o2": 8.4e5,
+    "derived_dof_steps_per_s_80cores_o2": 3.7e7,
+}
 
+
+def train_surrogate(stream, train_steps, n_pairs=1_000_000):
+    """Training pairs harvested from the plain integrator on 32^3 lattices
+    (seeds 1..6, 20 steps each, truncated to n_pairs), the network trained
+    on the GPU by the library's kernels; returns (trainer, net, info)."""
+    import torch
+
+    from paper_2105_00448_amd import hca, synth
+    dev = torch.device("cuda", 0)
+    log = lambda m: print(f"[bench:train] {m}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    Xs, Ys = [], []
+    for seed in range(1, 7):
+        tis = synth.make_tissue(32, 8, seed=seed)
+        sched = synth.bolus_schedule([0])
+        with hca.Simulation([(tis.cell, tis.w, tis.seed, (sched.times, sched.amts))],
+                            hca.default_params(), stream=stream) as sim:
+            X = torch.empty((tis.cell.size, 6), device=dev)
+            Y = torch.empty((tis.cell.size, 3), device=dev)
+            for _ in range(20):
+                n = sim.harvest_step(X, Y)
+                Xs.append(X[:n].clone())
+                Ys.append(Y[:n].clone())
+    X, Y = torch.cat(Xs)[:n_pairs].contiguous(), torch.cat(Ys)[:n_pairs].contiguous()
+    del Xs, Ys
+    t_harvest = time.perf_counter() - t0
+    log(f"{X.shape[0]} pairs in {t_harvest:.1f}s; training {train_steps} steps")
+    tr = hca.Trainer(X, Y, seed=1, stream=stream)
+    batch = 4096
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    l1 = tr.train(train_steps // 2, batch=batch, lr=2e-3)
+    l2 = tr.train(train_steps - train_steps // 2, batch=batch, lr=5e-4)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    losses = np.concatenate([l1, l2])
+    flop_per_sample = 3 * MLP_FLOP_ALG   # forward + two backward products
+    info = {"pairs": int(X.shape[0]), "harvest_s": t_harvest, "steps": train_steps,
+            "batch": batch, "seconds": t_train, "samples_per_s": train_steps * batch / t_train,
+            "tflops": train_steps * batch * flop_per_sample / t_train / 1e12,
+            "loss_first": float(losses[:10].mean()), "loss_last": float(losses[-50:].mean())}
+    return tr, tr.export(), info
+
+
+def kernel_window(sim, names, steps, profile):
+    """`steps` further coupled steps of a live context with params.profile =
+    `profile`; returns the kernel table of that window."""
+    sim.set_profile(profile)
+    sim.reset_kernel_times()
+    sim.step(steps)
+    kt = sim.kernel_times()
+    sim.set_profile(0)
+    return kt
+
+
+def run_context(reps, params, warmup, steps, stream, net=None, margin=1e-3, prof_steps=3,
+                label=""):
+    """Init a context, `warmup` untimed steps, `steps` timed steps (no events,
+    graphs replayed), then two short profiled windows on the same context:
+    every kernel class (time shares, algorithmic bytes of a step) and the
+    dominant class alone (its launch durations)."""
     import torch
 
     from paper_2105_00448_amd import hca
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream().cuda_stream
+    names = [hca.lib().hca_kernel_name(k).decode() for k in range(hca.lib().hca_num_kernels())]
+    t0 = time.perf_counter()
+    sim = hca.Simulation(reps, params, stream=stream)
+    t_init = time.perf_counter() - t0
+    if net is not None:
+        sim.set_surrogate(net, margin)
+    print(f"[bench:{label}] init {t_init:.1f}s; {warmup} warm-up steps", file=sys.stderr, flush=True)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.synchronize()
+    print(f"[bench:{label}] timing {steps} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = [sim.stats(r) for r in range(len(reps))]
+    if prof_steps == 0:
+        print(f"[bench:{label}] {steps} steps in {el:.2f}s", file=sys.stderr, flush=True)
+        return {"el": el, "init_s": t_init, "stats": st, "sim": sim, "dom": None}
+    print(f"[bench:{label}] {steps} steps in {el:.2f}s; profiling {prof_steps} + {prof_steps} "
+          f"steps", file=sys.stderr, flush=True)
+    kt_all = kernel_window(sim, names, prof_steps, 1)
+    real = {k: v for k, v in kt_all.items() if v["launches"] > 0 and v["bytes_per_launch"] > 0}
+    dom = max(real, key=lambda k: real[k]["ms"])
+    kt_dom = kernel_window(sim, names, prof_steps, names.index(dom) + 2)
+    kt_mlp = None
+    if net is not None:
+        kt_mlp = kernel_window(sim, names, prof_steps, names.index("k_mlp_apply") + 2)["k_mlp_apply"]
+    out = {"el": el, "init_s": t_init, "stats": st, "kt_all": kt_all, "dom": dom,
+           "kt_dom": kt_dom[dom], "kt_mlp": kt_mlp, "sim": sim}
+    return out
 
-    if args.copy_calibration > 0:
-        n = args.copy_calibration * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        print(f"[bench] copy calibration: 3 x {args.copy_calibration} MiB", file=sys.stderr,
-              flush=True)
-    print(f"[bench] generating workload {args.workload}", file=sys.stderr, flush=True)
-    reps, cfg, cfg_steps = make_workload(args.workload)
+
+def surrogate_error_matched(reps, net, stream, err_steps=3, margin=1e-3):
+    """Per-step error and decision flips of the surrogate ODE phase against
+    the plain integrator on identical inputs (the first replicate: the plain
+    context's state copied into the surrogate context before each phase)."""
+    import torch
+
+    from paper_2105_00448_amd import hca
+    dev = torch.device("cuda", 0)
+    rep0 = reps[:1]
+    nvox = rep0[0][0].size
+    errs = []
+    with hca.Simulation(rep0, hca.default_params(), stream=stream) as p, \
+            hca.Simulation(rep0, hca.default_params(), stream=stream) as s:
+        s.set_surrogate(net, margin)
+        buf8 = torch.empty(nvox, dtype=torch.float64, device=dev)
+        buf1 = torch.empty(nvox, dtype=torch.uint8, device=dev)
+        for _ in range(err_steps):
+            p.run_phases(hca.PH_O2 | hca.PH_DRUGS)
+            for k in ("L", "K", "G1", "G2", "P", "Vc", "phi"):
+                b = buf1 if k == "L" else buf8
+                p.field_to_device(k, b)
+                s.set_field_from_device(k, b)
+            p.run_phases(hca.PH_ODE)
+            s.run_phases(hca.PH_ODE)
+            L = p.field_to_device("L", torch.empty(nvox, dtype=torch.uint8, device=dev))
+            occ, can = L != 0, L == 1
+            e = {}
+            for k in ("P", "Vc", "phi"):
+                a = s.field_to_device(k, torch.empty(nvox, dtype=torch.float64, device=dev))
+                b = p.field_to_device(k, torch.empty(nvox, dtype=torch.float64, device=dev))
+                m = can if k == "phi" else occ
+                d = (a[m] - b[m]).abs()
+                e[k] = (d.max() / b[m].abs().max()).item()
+                e[k + "_rms"] = (d.pow(2).mean().sqrt() / b[m].pow(2).mean().sqrt()).item()
+                if k == "phi":
+                    e["flips"] = int(((a[can] >= 1.0) != (b[can] >= 1.0)).sum().item())
+                    e["cancer"] = int(can.sum().item())
+            e["fallbacks"] = s.stats()["sur_fallbacks"]
+            e["occupied"] = int(occ.sum().item())
+            errs.append(e)
+            p.run_phases(hca.PH_CA | hca.PH_STATS | hca.PH_ADVANCE)
+    return {
+        "steps": err_steps, "replicate": 0,
+        "P_max_rel": max(e["P"] for e in errs), "Vc_max_rel": max(e["Vc"] for e in errs),
+        "phi_max_rel": max(e["phi"] for e in errs),
+        "P_rms_rel": max(e["P_rms"] for e in errs), "Vc_rms_rel": max(e["Vc_rms"] for e in errs),
+        "phi_rms_rel": max(e["phi_rms"] for e in errs),
+        "flip_rate": sum(e["flips"] for e in errs) / max(1, sum(e["cancer"] for e in errs)),
+        "flips": sum(e["flips"] for e in errs),
+        "fallback_frac": sum(e["fallbacks"] for e in errs) / max(1, sum(e["occupied"] for e in errs)),
+    }
+
+
+def step_bytes(kt_all, steps):
+    """Algorithmic HBM bytes per coupled step summed over every kernel class
+    of a profiled window, and the kernel time per step."""
+    b = sum(v["launches"] * v["bytes_per_launch"] for v in kt_all.values())
+    ms = sum(v["ms"] for v in kt_all.values())
+    return b / steps, ms / steps
+
+
+def roofline_of(kt_dom, dom, workload, elem=8):
+    """Roofline object of the dominant kernel from its event-timed launches."""
+    mean_s = kt_dom["ms"] / kt_dom["launches"] * 1e-3
+    achieved = kt_dom["bytes_per_launch"] / mean_s / 1e9
+    kname = dom.replace("<L0>", "_L0").split("<")[0]
+    r = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": achieved / HBM_PEAK_GBS,
+         "traffic": measured_traffic(kname, workload, kt_dom["bytes_per_launch"]),
+         "traffic_source": f"profiles/{kname}_{workload}_traffic.json",
+         "mean_launch_us": mean_s * 1e6, "launches": kt_dom["launches"],
+         "bytes_per_launch": kt_dom["bytes_per_launch"]}
+    if kname == "k_cg_update":
+        # the kernel moves 8 B per voxel more than the CG's compulsory 6 stored
+        # values (the multigrid's FP32 z read and r copy written)
+        r["frac_incl_fp32_copies"] = r["frac"] * (6 * elem + 8.0) / (6 * elem)
+    return r
+
+
+def config5_headline(args, stream):
+    """The metric's configuration: plain vs surrogate+batched on 4 x 384^3."""
+    import torch
+
+    from paper_2105_00448_amd import hca
+    print("[bench] generating workload config5 (4 x 384^3, 512 Gaussians)", file=sys.stderr,
+          flush=True)
+    t0 = time.perf_counter()
+    reps, cfg, cfg_steps = make_workload("config5")
+    print(f"[bench] generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    steps = args.steps if args.steps is not None else cfg_steps
+    nvox = sum(r[0].size for r in reps)
+    cell0, w0, seed0, sched0 = reps[0]
+    crop = (np.ascontiguousarray(cell0[:32, :32, :32]), np.ascontiguousarray(w0[:32, :32, :32]),
+            seed0, sched0)
+    tr, net, train_info = train_surrogate(stream, args.train_steps)
+    kw = {"graphs": args.graphs}
+
+    def summary(run, label, elem=8):
+        st = run["stats"]
+        kt = run["kt_all"]
+        b_step, kms = step_bytes(kt, 3)
+        ms = run["el"] / steps * 1e3
+        tot = sum(v["ms"] for v in kt.values())
+        out = {"value": nvox * steps / run["el"], "ms_per_step": ms, "init_s": run["init_s"],
+               "cg_iters_last_step": st[0]["cg_iters"],
+               "roofline": roofline_of(run["kt_dom"], run["dom"],
+                                       "config5" if elem == 8 else "config5_fp32", elem),
+               "hbm_whole_step": {"bytes_per_voxel_step_algorithmic": b_step / nvox,
+                                  "achieved_gbs": b_step / (ms * 1e-3) / 1e9,
+                                  "frac": b_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                  "kernel_ms_per_step_profiled": kms},
+               "kernel_share": {k: round(v["ms"] / tot, 4) for k, v in kt.items() if v["ms"] > 0},
+               "cells": {"cancer": sum(x["n_cancer"] for x in st),
+                         "divisions": sum(x["total_divisions"] for x in st),
+                         "kills": sum(x["total_kills"] for x in st)}}
+        ode = kt.get("k_ode", {})
+        if ode.get("launches"):
+            out["ode_phase_ms"] = ode["ms"] / ode["launches"]
+        return out
+
+    plain = run_context(reps, hca.default_params(**kw), args.warmup, steps, stream, label="plain")
+    plain_rec = summary(plain, "plain")
+    plain["sim"].close()
+    del plain
+    torch.cuda.empty_cache()
+    sur = run_context(reps, hca.default_params(**kw), args.warmup, steps, stream, net=net,
+                      label="surrogate")
+    sur_rec = summary(sur, "surrogate")
+    st = sur["stats"]
+    m = sur["kt_mlp"]
+    mlp_s = m["ms"] / max(1, m["launches"]) * 1e-3
+    net_vox = sum(x["sur_voxels"] for x in st)
+    mfma = {"kernel": "k_mlp_apply", "mean_launch_us": mlp_s * 1e6,
+            "network_voxels_per_launch": net_vox,
+            "fallback_voxels_per_launch": sum(x["sur_fallbacks"] for x in st),
+            "flop_per_voxel_algorithmic": MLP_FLOP_ALG, "flop_per_voxel_executed": MLP_FLOP_EXEC,
+            "achieved_tflops": net_vox * MLP_FLOP_ALG / mlp_s / 1e12,
+            "peak_tflops_bf16_dense": MFMA_BF16_PEAK / 1e12,
+            "utilisation": net_vox * MLP_FLOP_ALG / mlp_s / MFMA_BF16_PEAK,
+            "utilisation_executed": net_vox * MLP_FLOP_EXEC / mlp_s / MFMA_BF16_PEAK,
+            "hbm_gbs": m["bytes_per_launch"] / mlp_s / 1e9,
+            "ode_phase_ms_surrogate": mlp_s * 1e3,
+            "ode_phase_ms_plain": plain_rec.get("ode_phase_ms")}
+    sur["sim"].close()
+    del sur
+    torch.cuda.empty_cache()
+    print("[bench] error at matched inputs, 3 steps on replicate 0", file=sys.stderr, flush=True)
+    err = surrogate_error_matched(reps, net, stream)
+    fp32 = None
+    if "fp32" in args.legs.split(",") and not args.no_legs:
+        # the same lattices with the solved fields stored in FP32 (solves to
+        # relative residual 1e-8, the FP32 floor)
+        fp32 = {"workload": "the headline lattices (4 x 384^3) with precision 32: solved fields and "
+                            "solver arrays stored in FP32, FP64 arithmetic, solves to rel. res. 1e-8"}
+        for label, use_net in (("plain", None), ("surrogate", net)):
+            run = run_context(reps, hca.default_params(precision=32, **kw), args.warmup, steps,
+                              stream, net=use_net, label=f"fp32-{label}")
+            fp32[label] = summary(run, label, elem=4)
+            run["sim"].close()
+            del run
+            torch.cuda.empty_cache()
+        fp32["speedup_vs_fp64_plain"] = fp32["plain"]["value"] / plain_rec["value"]
+        fp32["speedup_vs_fp64_surrogate"] = fp32["surrogate"]["value"] / sur_rec["value"]
+    tr.close()
+    rec = {
+        "metric": "voxel-steps/s per GPU: plain vs surrogate+batched at matched error/flip rate",
+        "value": sur_rec["value"],
+        "unit": "voxel-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": sur_rec["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": dict(cfg, mode="surrogate ODE + batched ensemble (4 replicates in one context)"),
+        "roofline": sur_rec["roofline"],
+        "plain": {k: plain_rec[k] for k in ("value", "ms_per_step", "init_s", "cg_iters_last_step",
+                                             "roofline", "hbm_whole_step", "ode_phase_ms")
+                  if k in plain_rec},
+        "speedup_vs_plain": sur_rec["value"] / plain_rec["value"],
+        "error_matched_inputs": err,
+        "hbm_whole_step": sur_rec["hbm_whole_step"],
+        "mfma": mfma,
+        "kernel_share": sur_rec["kernel_share"],
+        "init_s": sur_rec["init_s"],
+        "cells": sur_rec["cells"],
+        "cells_plain": plain_rec["cells"],
+        "training": train_info,
+        "paper_context": PAPER_CONTEXT,
+        "_cpu_sample": crop,
+    }
+    if fp32 is not None:
+        rec["fp32"] = fp32
+    return rec
+
+
+def single_workload(args, stream, workload, repeats):
+    """One workload (plain128, batched64) stepped from fresh contexts: the
+    median of `repeats` timed runs, the dominant kernel's roofline from one
+    further event-timed run."""
+    import torch
+
+    from paper_2105_00448_amd import hca
+    print(f"[bench] generating workload {workload}", file=sys.stderr, flush=True)
+    reps, cfg, cfg_steps = make_workload(workload)
     solver_kw = {"precond": args.precond, "graphs": args.graphs, "autotune": args.autotune}
     if args.mg_coarse_max is not None:
         solver_kw["mg_coarse_max"] = args.mg_coarse_max
@@ -534,7 +873,7 @@ def main():
         return el_, st_, kt_, mg_max
 
     times = []
-    for rep_i in range(args.repeats):
+    for rep_i in range(repeats):
         el1, st, _, mg_coarse_max = timed_repeat(0, f"repeat {rep_i}")
         times.append(el1)
     kt, el_prof = None, None
@@ -567,7 +906,7 @@ def main():
         mean_s = d["ms"] / d["launches"] * 1e-3
         achieved = d["bytes_per_launch"] / mean_s / 1e9
         kname = dom.split("<")[0]
-        wname = args.workload
+        wname = workload
         rec["profiled_repeat_ms_per_step"] = el_prof / steps * 1e3
         rec["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -583,7 +922,86 @@ def main():
     rec["cells"] = {"cancer": sum(s["n_cancer"] for s in st),
                     "divisions": sum(s["total_divisions"] for s in st),
                     "kills": sum(s["total_kills"] for s in st)}
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="config5", help="config5 (headline), plain128, batched64")
+    ap.add_argument("--precond", type=int, default=1, help="0 Jacobi, 1 multigrid")
+    ap.add_argument("--mg-coarse-max", type=int, default=None,
+                    help="levels with at most this many cells go to the one-workgroup solve")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--graphs", type=int, default=1, help="1: replay captured CG iterations")
+    ap.add_argument("--autotune", type=int, default=0, help="1: tile plan from the autotuner")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed repeats from a fresh context; value = median")
+    ap.add_argument("--no-legs", action="store_true", help="plain workload only")
+    ap.add_argument("--legs", default="plain128,batched",
+                    help="comma-separated further legs: plain128, batched, surrogate, substeps, newton, "
+                         "paper2d, vegf, fec, cpu_wide")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device three times (a kernel of known "
+                         "traffic for scaling hardware byte counters)")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="for profiler runs: train the network, then init one context of the "
+                         "workload (config5: surrogate + batched; --precision) and step it "
+                         "--warmup + --steps times; prints a short JSON line")
+    ap.add_argument("--precision", type=int, default=64, help="with --profile-only: 64 or 32")
+    ap.add_argument("--sur-steps", type=int, default=100)
+    ap.add_argument("--train-steps", type=int, default=4000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(replicates and z-slabs would shard across GPUs).",
+              file=sys.stderr)
+        raise SystemExit(2)
+
+    import torch
+
+    from paper_2105_00448_amd import hca
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"[bench] copy calibration: 3 x {args.copy_calibration} MiB", file=sys.stderr,
+              flush=True)
+    if args.profile_only:
+        reps, cfg, cfg_steps = make_workload(args.workload)
+        steps = args.steps if args.steps is not None else cfg_steps
+        net = None
+        if args.workload == "config5":
+            tr, net, _ = train_surrogate(stream, args.train_steps)
+        p = hca.default_params(precision=args.precision, graphs=args.graphs)
+        run = run_context(reps, p, args.warmup, steps, stream, net=net, prof_steps=0,
+                          label="profile-only")
+        nvox = sum(r[0].size for r in reps)
+        print(json.dumps({"workload": args.workload, "precision": args.precision, "steps": steps,
+                          "ms_per_step": run["el"] / steps * 1e3,
+                          "value": nvox * steps / run["el"],
+                          "dominant_kernel": run["dom"]}), flush=True)
+        run["sim"].close()
+        return
+    if args.workload == "config5":
+        rec = config5_headline(args, stream)
+    else:
+        rec = single_workload(args, stream, args.workload, args.repeats)
     legs = [] if args.no_legs else [x for x in args.legs.split(",") if x]
+    crop = rec.pop("_cpu_sample", None)
+    if "plain128" in legs and args.workload != "plain128":
+        rec["plain128"] = single_workload(args, stream, "plain128", 3)
     if "surrogate" in legs:
         rec["surrogate"] = surrogate_leg(stream, args.sur_steps, args.train_steps)
     if "batched" in legs:
@@ -600,7 +1018,9 @@ def main():
         rec["paper2d"] = paper2d_leg(stream)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
-        rec["cpu_baseline"] = cpu_baseline()
+        rec["cpu_baseline"] = cpu_baseline(crop)
+    if "cpu_wide" in legs:
+        rec["cpu_wide"] = cpu_wide()
     print(json.dumps(rec), flush=True)
 
 

@@ -180,6 +180,16 @@ typedef struct hca_params {
      2 lets the drug fields' solves between boluses stop after 0-2
      iterations. */
   int32_t x0_extrapolate;
+  /* storage precision of the solved fields (K, G1, G2, G3, V), their solver
+     arrays and their guess history: 64 (default) FP64; 32 FP32, half the
+     bytes of the solves (the arithmetic stays FP64; a value is rounded to
+     FP32 where it is stored).  The solves then stop at a relative residual of
+     max(cg_rtol, 1e-8), FP32 storage bounding what they can attain, and the
+     steady-oxygen initialisation runs in FP64 (its operator amplifies
+     residuals about 1e4-fold) before the state is rounded to FP32.  P, V_c,
+     phi, the vessel map and the cellular automaton are FP64 either way;
+     hca_fields, hca_set_field and the state blobs stay FP64 (converted). */
+  int32_t precision;
 } hca_params;
 
 /* One replicate's inputs.  hca_init deep-copies every array; the caller keeps
@@ -283,6 +293,44 @@ hca_status hca_set_field(hca_ctx* c, int rep, hca_field f, const void* src,
 /* Set the step index n of the current state (resume from a checkpoint). */
 hca_status hca_set_step(hca_ctx* c, int64_t step);
 
+/* ---- checkpoint and resume ----------------------------------------------------
+ * A replicate's complete state as one self-describing blob, so that a run
+ * continued from a saved state is bit-identical to the uninterrupted run (the
+ * reproducibility the paper asks of its random numbers, here of the whole
+ * state): the cell map, the vessel map, every solved field (K, G1, G2, and G3
+ * / V with their options), P, V_c, phi, the solves' initial-guess history
+ * (each field at its previous solve), the step index, the seed and the
+ * cumulative event counts.  Layout: a 96-byte header (magic "HCASTATE",
+ * version 1, option flags, nx, ny, nz, field count, step, seed, cumulative
+ * counts), then the uint8 cell map padded to 8 bytes and FP64 arrays, all
+ * x-fastest.  A context advances its replicates together, so replicates of
+ * one context share the step index. */
+/* Bytes of replicate rep's state blob. */
+hca_status hca_state_bytes(hca_ctx* c, int rep, size_t* bytes);
+/* Write replicate rep's state into dst (host or device, dst_is_device);
+ * HCA_E_RANGE if dst_bytes is too small. */
+hca_status hca_export_state(hca_ctx* c, int rep, void* dst, size_t dst_bytes, int dst_is_device);
+/* Overwrite replicate rep's state with a blob of hca_export_state (host or
+ * device).  The blob must have the replicate's lattice and seed and the
+ * context's options (third drug, VEGF), and in a context of several
+ * replicates the context's step; its maps are validated as hca_set_field
+ * does.  Violations give HCA_E_INVALID (HCA_E_RANGE for a short buffer) and
+ * leave the state unchanged.  A blob without guess history restarts the
+ * extrapolation from the restored fields.  The last step's event counts
+ * restart at 0. */
+hca_status hca_import_state(hca_ctx* c, int rep, const void* src, size_t src_bytes,
+                            int src_is_device);
+/* Algorithm 1's time loop resumed from saved states instead of its
+ * initialisation: like hca_init, but replicate r's cell and vessel maps, fields,
+ * cell state, guess history, step and counts come from states[r] (a host
+ * blob of state_bytes[r] bytes from hca_export_state), and reps[r] supplies
+ * the seed, which must match, and the dose lists (its cell and vessel_w are
+ * ignored).  All states must be at the same step.  No steady-oxygen solve is
+ * run. */
+hca_status hca_init_from_state(hca_ctx** out, const hca_params* p, const hca_replicate* reps,
+                               const void* const* states, const size_t* state_bytes, int n_reps,
+                               void* stream);
+
 hca_status hca_stats(hca_ctx* c, int rep, hca_stats_t* out);
 
 /* With params.profile set: accumulated device time (ms) and launch count of
@@ -292,6 +340,10 @@ hca_status hca_kernel_time(hca_ctx* c, int kernel, double* ms, int64_t* launches
 const char* hca_kernel_name(int kernel);
 int hca_num_kernels(void);
 hca_status hca_reset_kernel_time(hca_ctx* c);
+/* Change params.profile of a live context (0 off, 1 every kernel class,
+ * k + 2 class k only), e.g. to time a few steps after an untimed run. */
+hca_status hca_set_profile(hca_ctx* c, int profile);
+
 
 /* Replace the plain integrator of the ODE phase (Eqs. odep53, odevegf,
  * cellcycle) by the surrogate network: every occupied voxel takes the

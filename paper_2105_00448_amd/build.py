@@ -31,9 +31,11 @@ COMMON = [
 EXTRA = {
     "k_ca.hip": ["-ffp-contract=off"],
 }
-SOURCES = ["runtime.cpp", "mlp_runtime.cpp", "k_setup.hip", "k_solver.hip", "k_ode.hip", "k_ca.hip", "k_mg.hip",
-           "k_mlp.hip",
-           "noalloc.hip"]
+SOURCES = ["runtime.cpp", "runtime.cpp:32", "capi.cpp", "mlp_runtime.cpp", "k_setup.hip", "k_solver.hip",
+           "k_ode.hip", "k_ca.hip", "k_mg.hip", "k_mlp.hip", "noalloc.hip"]
+# runtime.cpp is compiled once per field storage precision ("runtime.cpp:32":
+# FP32 storage, its own namespace)
+VARIANTS = {"32": ["-DHCA_REAL=float", "-DHCA_RT_NS=rt32"]}
 
 
 def hipcc():
@@ -43,17 +45,19 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, src + ".o")
+def _compile(unit):
+    src, _, variant = unit.partition(":")
+    obj = os.path.join(BUILD, src + (f".{variant}" if variant else "") + ".o")
     lang = ["-x", "hip"] if src.endswith(".cpp") else []
-    cmd = [hipcc(), "-c"] + lang + [os.path.join(CSRC, src), "-o", obj] + COMMON + EXTRA.get(src, [])
+    cmd = ([hipcc(), "-c"] + lang + [os.path.join(CSRC, src), "-o", obj] + COMMON + EXTRA.get(src, [])
+           + VARIANTS.get(variant, []))
     r = subprocess.run(cmd, capture_output=True, text=True)
-    return src, obj, r
+    return unit, obj, r
 
 
 def build(verbose=True):
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s.partition(":")[0]))]
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         results = list(ex.map(_compile, srcs))
     objs = []

@@ -9,6 +9,12 @@
 
 #include "hca.h"
 
+// What every context starts with: the storage precision of its solved
+// fields (64 or 32), which selects the runtime instance that owns it.
+struct hca_ctx {
+  int precision;
+};
+
 namespace hca {
 
 // Start/stop events for the next kernel launched through hca_launch: they
@@ -185,36 +191,50 @@ inline int grid_for(int n, int max_blocks) {
 // g0[3 nreps + 3 rep + drug] at the start (drug 2, the third, with drug3).
 void launch_plasma(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
                    int j, const double* dose_t, const double* dose_a, double* g0);
+// Field storage: T = double (precision 64) or float (precision 32) for the
+// solved fields, their solver arrays and their guess history; arithmetic is
+// FP64 in both (a value is rounded to T when it is stored).  P, V_c, phi and
+// the vessel map are FP64 in both.
+template <typename T>
 void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
-                     const double* vw, const double* K, double* c, double* b, int steady);
+                     const double* vw, const T* K, T* c, T* b, int steady);
 // All systems of a field substep at once: F = [K | G1 | G2] (3 x ntot), then
 // G3 (drug3) and V (vegf, its source from Vc); c and b of the same layout.
+template <typename T>
 void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
-                       const uint8_t* L, const double* vw, const double* F, const double* Vc,
-                       const double* g0, double* c, double* b);
+                       const uint8_t* L, const double* vw, const T* F, const double* Vc,
+                       const double* g0, T* c, T* b);
 // Newton step on the oxygen uptake at the new value: c, b of the oxygen
 // systems (the first ntot entries) from the iterate K and the linearised
 // substep's right-hand side b_lin.
+template <typename T>
 void launch_setup_o2_newton(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
-                            const double* vw, const double* K, const double* b_lin, double* c,
-                            double* b);
+                            const double* vw, const T* K, const T* b_lin, T* c, T* b);
 // Crank-Nicolson-type substeps (theta < 1): b += (1 - theta) a Lap F per field.
-void launch_rhs_lap(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
-                    const double* F, double* b);
+template <typename T>
+void launch_rhs_lap(hipStream_t s, const Work& w, const DevParams& p, long long ntot, const T* F,
+                    T* b);
 // Initial guess of the solves of the fields in fmask (mode 1: F <- 2F - Fprev;
 // mode 2: F <- F (F / Fprev) where 0 < F < Fprev) and Fprev <- F (the values
 // at the previous solve of each field).
+template <typename T>
 void launch_extrapolate(hipStream_t s, const Work& w, long long ntot, int nf, unsigned fmask, int mode,
-                        double* F, double* Fprev);
+                        T* F, T* Fprev);
+template <typename T>
 void launch_init_cells(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
-                       const double* K, double* P, double* Vc, double* phi);
+                       const T* K, double* P, double* Vc, double* phi);
+// dst[i] = src[i] for i < n between the two storage types (hca_fields and
+// the state blobs are FP64 at the boundary).
+void launch_convert(hipStream_t s, const float* src, double* dst, long long n);
+void launch_convert(hipStream_t s, const double* src, float* dst, long long n);
 
 // solver (k_solver.hip)
-struct SolverBufs {
-  double *r, *z, *p0, *p1, *q;   // z: Jacobi preconditioner only
+template <typename T>
+struct SolverBufsT {
+  T *r, *z, *p0, *p1, *q;        // z: Jacobi preconditioner only
   float* z32;                    // z of the multigrid preconditioner (FP32 result)
   float* r32;                    // FP32 copy of r for the multigrid's fine level
-  double* dinv;               // 1/diag(A), written by the start kernel (Jacobi)
+  T* dinv;                    // 1/diag(A), written by the start kernel (Jacobi)
   int jacobi;                 // 1: Jacobi preconditioner inside the update kernel
   double* partial;            // per work item
   unsigned* counter;          // per replicate
@@ -222,24 +242,27 @@ struct SolverBufs {
   int* ndone;                 // replicates finished
 };
 // Systems whose field (s / nrep) is not in field_mask are marked finished.
-void launch_cg_start(hipStream_t s, const Work& w, double rtol, int maxit, const double* c,
-                     const double* b, const double* x, const SolverBufs& sb, unsigned field_mask,
-                     int nrep);
+template <typename T>
+void launch_cg_start(hipStream_t s, const Work& w, double rtol, int maxit, const T* c, const T* b,
+                     const T* x, const SolverBufsT<T>& sb, unsigned field_mask, int nrep);
 // Reduce kernels (one workgroup per replicate) that follow the kernels
 // producing partial sums: start (b.b, r.r, r.z), apply (p.q), update
 // (r.r, r.z_old, r.z'), and the preconditioner's r.z'.
 enum ReduceKind { RED_START = 0, RED_APPLY = 1, RED_UPDATE = 2, RED_RZ = 3 };
-void launch_cg_reduce(hipStream_t s, const Work& w, const SolverBufs& sb, int kind, double rtol,
+template <typename T>
+void launch_cg_reduce(hipStream_t s, const Work& w, const SolverBufsT<T>& sb, int kind, double rtol,
                       int maxit, unsigned field_mask = 7u, int nrep = 1);
 // One iteration is launch_cg_apply then launch_cg_update with the same
 // parity (the direction p alternates between p0 and p1).
-void launch_cg_apply(hipStream_t s, const Work& w, const double* c,
-                     const SolverBufs& sb, int parity);
+template <typename T>
+void launch_cg_apply(hipStream_t s, const Work& w, const T* c, const SolverBufsT<T>& sb, int parity);
 // The apply kernel alone (no reduce), for the tile autotuner.
-void launch_cg_apply_kernel(hipStream_t s, const Work& w, const double* c, const SolverBufs& sb,
+template <typename T>
+void launch_cg_apply_kernel(hipStream_t s, const Work& w, const T* c, const SolverBufsT<T>& sb,
                             int parity);
-void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, double* x,
-                      const SolverBufs& sb, int parity);
+template <typename T>
+void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, T* x,
+                      const SolverBufsT<T>& sb, int parity);
 
 // ---- geometric multigrid (k_mg.hip) ---------------------------------------
 constexpr int kMaxLevels = 16;
@@ -304,19 +327,22 @@ struct MgBufs {
 
 // Allow the coarse-solve kernels `bytes` of dynamic LDS (above 64 KiB).
 hipError_t mg_set_coarse_lds(int bytes);
-void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, const double* c);
+template <typename T>
+void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, const T* c);
 // One V-cycle on the residual sb.r, result in sb.z; finishes the flexible-CG
 // scalars (r.z, beta) with a RED_RZ reduce.
 // `hook(ctx, segment, begin)` brackets the launches of each segment (for
 // kernel timing); segments: see MgSegment.
 enum MgSegment { MG_PRE0 = 0, MG_RESTRICT0, MG_DOWN, MG_COARSE, MG_UP, MG_POST1_0, MG_POST2_0, MG_SWEEP0 };
 typedef void (*MgHook)(void* ctx, int segment, int begin);
-void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const SolverBufs& sb,
+template <typename T>
+void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const SolverBufsT<T>& sb,
                       MgHook hook, void* hook_ctx);
 
 // ODE (k_ode.hip)
-void launch_ode(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
-                const double* K, double* P, double* Vc, double* phi);
+template <typename T>
+void launch_ode(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L, const T* K,
+                double* P, double* Vc, double* phi);
 
 // CA and stats (k_ca.hip)
 // The committed cancer cells (phi >= 1) of a step, listed by the propose
@@ -328,10 +354,10 @@ struct CaList {
 };
 // code = win = NONE everywhere, the committed cells listed, then each listed
 // cell's decision (kill, NOSPACE or the daughter's direction) into code.
+template <typename T>
 void launch_ca_propose(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
-                       const uint8_t* L, const double* vw, const double* K, const double* G1,
-                       const double* G2, const double* G3, const double* phi, uint8_t* code,
-                       uint8_t* win, CaList list);
+                       const uint8_t* L, const double* vw, const T* K, const T* G1, const T* G2,
+                       const T* G3, const double* phi, uint8_t* code, uint8_t* win, CaList list);
 // For each listed cell that proposes a daughter site: the winner among the
 // site's proposing neighbours into win (every proposer of a site writes the
 // same value).
@@ -347,15 +373,17 @@ void launch_counters_reduce(hipStream_t s, const Work& w, const unsigned long lo
 void launch_ca_finalize(hipStream_t s, const Work& w, uint8_t* L, double* phi, double* P,
                         double* Vc, const uint8_t* code, const uint8_t* win,
                         unsigned long long* part, Counters* cnt);
-void launch_stats(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
-                  const double* const* fields, int nfields, unsigned long long* part,
-                  Counters* cnt);
+// The non-finite scan covers the nf solved fields (F, nf x ntot) and P, V_c, phi.
+template <typename T>
+void launch_stats(hipStream_t s, const Work& w, const uint8_t* L, const double* vw, const T* F,
+                  int nf, long long ntot, const double* P, const double* Vc, const double* phi,
+                  unsigned long long* part, Counters* cnt);
 // Vessel birth-death update of the step n -> n+1 when (n + 1) is a multiple
 // of dv_steps (else only zero event counts), from V and the cell map after
 // the CA; updates vw in place.
+template <typename T>
 void launch_vessel(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
-                   const uint8_t* L, const double* V, double* vw, unsigned long long* part,
-                   Counters* cnt);
+                   const uint8_t* L, const T* V, double* vw, unsigned long long* part, Counters* cnt);
 // what: 1 CA events, 0 census and non-finite count, 2 surrogate counts.
 void launch_zero_counters(hipStream_t s, Counters* cnt, int nreps, int what);
 void launch_advance(hipStream_t s, long long* d_step);

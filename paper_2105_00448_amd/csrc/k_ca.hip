@@ -138,14 +138,15 @@ __global__ void __launch_bounds__(kBlock) k_ca_scan(Work w, const uint8_t* __res
 }
 
 // The decision of each listed committed cell.
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_ca_propose_list(Work w, DevParams p,
                                                             const long long* d_step,
                                                             const uint8_t* __restrict__ L,
                                                             const double* __restrict__ vw,
-                                                            const double* __restrict__ K,
-                                                            const double* __restrict__ G1,
-                                                            const double* __restrict__ G2,
-                                                            const double* __restrict__ G3,
+                                                            const T* __restrict__ K,
+                                                            const T* __restrict__ G1,
+                                                            const T* __restrict__ G2,
+                                                            const T* __restrict__ G3,
                                                             CaList list, uint8_t* __restrict__ code) {
   const long long step = d_step[0];
   int b0, b1;
@@ -302,9 +303,10 @@ __global__ void __launch_bounds__(kBlock) k_ca_finalize(Work w, uint8_t* __restr
 // counter (gid, n+1, VESSEL, 0), first word); the event happens when
 // u < probability.  The rule is voxel-local and reads the cell map after the
 // CA, so the vessel map is updated in place.
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_vessel(Work w, DevParams p, const long long* d_step,
                                                    const uint8_t* __restrict__ L,
-                                                   const double* __restrict__ V,
+                                                   const T* __restrict__ V,
                                                    double* __restrict__ vw,
                                                    unsigned long long* __restrict__ part) {
   __shared__ unsigned long long lds4[4];
@@ -341,10 +343,15 @@ __global__ void __launch_bounds__(kBlock) k_vessel(Work w, DevParams p, const lo
   });
 }
 
-// Cell-type counts and a non-finite scan of the listed fields.
+// Cell-type counts and a non-finite scan of the solved fields (nf x ntot in
+// F) and of P, V_c, phi.
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_stats(Work w, const uint8_t* __restrict__ L,
                                                   const double* __restrict__ vw,
-                                                  const double* const* fields, int nfields,
+                                                  const T* __restrict__ F, int nf, long long ntot,
+                                                  const double* __restrict__ P,
+                                                  const double* __restrict__ Vc,
+                                                  const double* __restrict__ phi,
                                                   unsigned long long* __restrict__ part) {
   __shared__ unsigned long long lds4[4];
   unsigned long long nc = 0, ns = 0, ne = 0, nv = 0, bad = 0;
@@ -355,7 +362,8 @@ __global__ void __launch_bounds__(kBlock) k_stats(Work w, const uint8_t* __restr
     ns += l == 2;
     ne += l == 0;
     nv += vw[i] != 0.0;
-    for (int f = 0; f < nfields; ++f) bad += !isfinite(fields[f][i]);
+    for (int f = 0; f < nf; ++f) bad += !isfinite(F[i + (long long)f * ntot]);
+    bad += !isfinite(P[i]) + !isfinite(Vc[i]) + !isfinite(phi[i]);
   }, [&](int, int it) {
     const unsigned long long v[5] = {block_sum_u64(nc, lds4), block_sum_u64(ns, lds4),
                                      block_sum_u64(ne, lds4), block_sum_u64(nv, lds4),
@@ -456,13 +464,13 @@ __global__ void __launch_bounds__(kBlock) k_validate_cells(Work w, const uint8_t
   if ((threadIdx.x & 63) == 0 && nb) atomicAdd(bad, nb);
 }
 
+template <typename T>
 void launch_ca_propose(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
-                       const uint8_t* L, const double* vw, const double* K, const double* G1,
-                       const double* G2, const double* G3, const double* phi, uint8_t* code,
-                       uint8_t* win, CaList list) {
+                       const uint8_t* L, const double* vw, const T* K, const T* G1, const T* G2,
+                       const T* G3, const double* phi, uint8_t* code, uint8_t* win, CaList list) {
   hca_launch(k_ca_scan, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, phi, code, win, list);
-  hca_launch(k_ca_propose_list, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, d_step, L, vw,
-             K, G1, G2, G3, list, code);
+  hca_launch(k_ca_propose_list<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, d_step, L,
+             vw, K, G1, G2, G3, list, code);
 }
 
 void launch_ca_resolve(hipStream_t s, const Work& w, const double* phi, const uint8_t* code,
@@ -479,19 +487,20 @@ void launch_ca_finalize(hipStream_t s, const Work& w, uint8_t* L, double* phi, d
   launch_counters_reduce(s, w, part, cnt, CNT_CA);
 }
 
+template <typename T>
 void launch_vessel(hipStream_t s, const Work& w, const DevParams& p, const long long* d_step,
-                   const uint8_t* L, const double* V, double* vw, unsigned long long* part,
-                   Counters* cnt) {
-  hca_launch(k_vessel, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, d_step, L, V, vw,
-             part);
+                   const uint8_t* L, const T* V, double* vw, unsigned long long* part, Counters* cnt) {
+  hca_launch(k_vessel<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, d_step, L, V,
+             vw, part);
   launch_counters_reduce(s, w, part, cnt, CNT_VESSEL);
 }
 
-void launch_stats(hipStream_t s, const Work& w, const uint8_t* L, const double* vw,
-                  const double* const* fields, int nfields, unsigned long long* part,
-                  Counters* cnt) {
-  hca_launch(k_stats, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, vw, fields,
-             nfields, part);
+template <typename T>
+void launch_stats(hipStream_t s, const Work& w, const uint8_t* L, const double* vw, const T* F,
+                  int nf, long long ntot, const double* P, const double* Vc, const double* phi,
+                  unsigned long long* part, Counters* cnt) {
+  hca_launch(k_stats<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, vw, F, nf,
+             ntot, P, Vc, phi, part);
   launch_counters_reduce(s, w, part, cnt, CNT_STATS);
 }
 
@@ -507,5 +516,18 @@ void launch_validate_cells(hipStream_t s, const Work& w, const uint8_t* L, const
                            int rep, unsigned long long* bad) {
   hca_launch(k_validate_cells, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, L, vw, rep, bad);
 }
+
+#define HCA_CA_INST(T)                                                                             \
+  template void launch_ca_propose<T>(hipStream_t, const Work&, const DevParams&, const long long*, \
+                                     const uint8_t*, const double*, const T*, const T*, const T*,  \
+                                     const T*, const double*, uint8_t*, uint8_t*, CaList);         \
+  template void launch_vessel<T>(hipStream_t, const Work&, const DevParams&, const long long*,     \
+                                 const uint8_t*, const T*, double*, unsigned long long*,           \
+                                 Counters*);                                                       \
+  template void launch_stats<T>(hipStream_t, const Work&, const uint8_t*, const double*, const T*, \
+                                int, long long, const double*, const double*, const double*,       \
+                                unsigned long long*, Counters*);
+HCA_CA_INST(double)
+HCA_CA_INST(float)
 
 }  // namespace hca

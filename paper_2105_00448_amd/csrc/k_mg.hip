@@ -233,7 +233,8 @@ __device__ inline TileXY tile_xy(const Tile* tiles, const MgRep* reps, int ti) {
 // ---- setup per solve -------------------------------------------------------
 
 // Level 0: Dinv = 1 / (c + a deg).
-__global__ void __launch_bounds__(kBlock) k_mg_prep0(MgLevel L0, const double* __restrict__ c) {
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_mg_prep0(MgLevel L0, const T* __restrict__ c) {
   FOR_MY_TILES(L0.ntiles) {
     const TileXY t = tile_xy(L0.tiles, L0.reps, ti);
     if (!t.valid) continue;
@@ -242,14 +243,14 @@ __global__ void __launch_bounds__(kBlock) k_mg_prep0(MgLevel L0, const double* _
     long long i = m.off + t.x + (long long)m.nx * (t.y + (long long)m.ny * t.z0);
     const long long plane = (long long)m.nx * m.ny;
     for (int z = t.z0; z < t.z1; ++z, i += plane)
-      L0.dinv[i] = (float)(1.0 / (c[i] + (double)G.gsum(t.x, t.y, z)));
+      L0.dinv[i] = (float)(1.0 / ((double)c[i] + (double)G.gsum(t.x, t.y, z)));
   }
 }
 
 // Level k+1 from level k: c_{k+1} = sum of the children's c, Dinv_{k+1}.
-template <bool FROM0>
+template <bool FROM0, typename T>
 __global__ void __launch_bounds__(kBlock) k_mg_coarsen(MgLevel Lf, MgLevel Lc,
-                                                       const double* __restrict__ c0) {
+                                                       const T* __restrict__ c0) {
   FOR_MY_TILES(Lc.nrtiles) {
     const TileXY t = tile_xy(Lc.rtiles, Lc.reps, ti);
     if (!t.valid) continue;
@@ -487,9 +488,9 @@ __global__ void __launch_bounds__(kBlock) k_mg_sweep(MgLevel Lk, float omega, co
   }
 }
 
-template <bool L0, typename RT>
+template <bool L0, typename RT, typename ST>
 __global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float omega, const float* __restrict__ in,
-                                                     const RT* __restrict__ r, SolverBufs sb) {
+                                                     const RT* __restrict__ r, SolverBufsT<ST> sb) {
   __shared__ double lds4[4];
   __shared__ float lds[2][kPlaneMaxF];
   FOR_MY_TILES(Lk.ntiles) {
@@ -880,22 +881,24 @@ hipError_t mg_set_coarse_lds(int bytes) {
   return hipFuncSetAttribute((const void*)k_mg_coarse_prep, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, const double* c) {
+template <typename T>
+void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, const T* c) {
   if (mg.lev[0].ntiles)
-    hca_launch(k_mg_prep0, dim3(grid_tiles(mg.lev[0].ntiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[0], c);
+    hca_launch(k_mg_prep0<T>, dim3(grid_tiles(mg.lev[0].ntiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[0], c);
   for (int k = 0; k < mg.nlev_glob; ++k) {
     const MgLevel& Lc = mg.lev[k + 1];
     if (!Lc.nrtiles) continue;
     if (k == 0)
-      hca_launch(k_mg_coarsen<true>, dim3(grid_tiles(Lc.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
+      hca_launch(k_mg_coarsen<true, T>, dim3(grid_tiles(Lc.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
     else
-      hca_launch(k_mg_coarsen<false>, dim3(grid_tiles(Lc.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
+      hca_launch(k_mg_coarsen<false, T>, dim3(grid_tiles(Lc.nrtiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[k], Lc, c);
   }
   hca_launch(k_mg_coarse_prep, dim3(w.nreps), dim3(kCoarseThreads), mg.coarse_lds_bytes, s, mg.coarse,
              (const float* const*)mg.lev_c, mg.coarse_pre);
 }
 
-void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const SolverBufs& sb,
+template <typename T>
+void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const SolverBufsT<T>& sb,
                       MgHook hook, void* hctx) {
   // levels >= 1: pre-sweeps with weights (wa, wb), post-sweeps with (wb, wa);
   // level 0: three sweeps (w0[0], w0[1], w0[2]) before, reversed after
@@ -946,7 +949,7 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
       if (!L.ntiles) continue;
       hca_launch((k_mg_post1<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, wb,
                  (const float*)L.r, ss);
-      hca_launch((k_mg_post2<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, wa,
+      hca_launch((k_mg_post2<false, float, T>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, wa,
                  (const float*)L.ualt, (const float*)L.r, sb);
     }
     H(MG_UP, 0);
@@ -963,11 +966,18 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
                (const float*)L.ualt, L.u, (const float*)sb.r32, ss);
     H(MG_SWEEP0, 0);
     H(MG_POST2_0, 1);
-    hca_launch((k_mg_post2<true, double>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, w0[0],
-               (const float*)L.u, (const double*)sb.r, sb);
+    hca_launch((k_mg_post2<true, T, T>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, w0[0],
+               (const float*)L.u, (const T*)sb.r, sb);
     H(MG_POST2_0, 0);
     launch_cg_reduce(s, w, sb, RED_RZ, 0.0, 0);
   }
 }
+
+template void launch_mg_prepare<double>(hipStream_t, const Work&, const MgBufs&, const double*);
+template void launch_mg_prepare<float>(hipStream_t, const Work&, const MgBufs&, const float*);
+template void launch_mg_vcycle<double>(hipStream_t, const Work&, const MgBufs&,
+                                       const SolverBufsT<double>&, MgHook, void*);
+template void launch_mg_vcycle<float>(hipStream_t, const Work&, const MgBufs&,
+                                      const SolverBufsT<float>&, MgHook, void*);
 
 }  // namespace hca

@@ -298,12 +298,12 @@ __device__ inline void forward32(const NET& net, const float (&x)[kMlpIn], int l
 // REGW: weights in registers, else staged in LDS.  The four variants measure
 // within 8 % of each other on the 256^3 workload; the launcher uses
 // <true, true>.
-template <bool WIDE, bool REGW>
+template <bool WIDE, bool REGW, typename T>
 __global__ void __launch_bounds__(kBlock) k_mlp_apply(Work w, DevParams p, MlpDev net,
                                                       const uint8_t* __restrict__ L,
-                                                      const double* __restrict__ K,
-                                                      const double* __restrict__ G1,
-                                                      const double* __restrict__ G2,
+                                                      const T* __restrict__ K,
+                                                      const T* __restrict__ G1,
+                                                      const T* __restrict__ G2,
                                                       double* __restrict__ P, double* __restrict__ Vc,
                                                       double* __restrict__ phi,
                                                       unsigned long long* __restrict__ part) {
@@ -498,11 +498,12 @@ __global__ void __launch_bounds__(kBlock) k_mlp_save_state(Work w, const double*
 // cycle-clock increment a cancer cell receives at this oxygen (stroma carries
 // no clock, but shares the same (K, P, Vc) dynamics, so its rows teach the
 // same map).
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_mlp_harvest(Work w, DevParams p,
                                                         const uint8_t* __restrict__ L,
-                                                        const double* __restrict__ K,
-                                                        const double* __restrict__ G1,
-                                                        const double* __restrict__ G2,
+                                                        const T* __restrict__ K,
+                                                        const T* __restrict__ G1,
+                                                        const T* __restrict__ G2,
                                                         const double* __restrict__ P,
                                                         const double* __restrict__ Vc,
                                                         const double* __restrict__ before,
@@ -882,11 +883,11 @@ void launch_mlp_pack(hipStream_t s, const float* theta, bf16x8* packed) {
   hca_launch(k_mlp_pack, dim3((kPackAll + 255) / 256), dim3(256), 0, s, theta, packed);
 }
 
+template <typename T>
 void launch_mlp_apply(hipStream_t s, const Work& w, const DevParams& p, const MlpDev& net,
-                      const uint8_t* L, const double* K, const double* G1, const double* G2,
-                      double* P, double* Vc, double* phi, unsigned long long* part,
-                      Counters* cnt) {
-  hca_launch((k_mlp_apply<true, true>), dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock),
+                      const uint8_t* L, const T* K, const T* G1, const T* G2, double* P,
+                      double* Vc, double* phi, unsigned long long* part, Counters* cnt) {
+  hca_launch((k_mlp_apply<true, true, T>), dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock),
                      0, s, w, p, net, L, K, G1, G2, P, Vc, phi, part);
   launch_counters_reduce(s, w, part, cnt, CNT_SUR);
 }
@@ -906,11 +907,11 @@ void launch_mlp_save_state(hipStream_t s, const Work& w, const double* P, const 
                      P, Vc, phi, before);
 }
 
+template <typename T>
 void launch_mlp_harvest(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
-                        const double* K, const double* G1, const double* G2, const double* P,
-                        const double* Vc, const double* before, const long long* item_off,
-                        float* X, float* Y) {
-  hca_launch(k_mlp_harvest, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p,
+                        const T* K, const T* G1, const T* G2, const double* P, const double* Vc,
+                        const double* before, const long long* item_off, float* X, float* Y) {
+  hca_launch(k_mlp_harvest<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p,
                      L, K, G1, G2, P, Vc, before, item_off, X, Y);
 }
 
@@ -955,5 +956,15 @@ void launch_mlp_eval(hipStream_t s, const bf16x8* pk, const float* th, const flo
   hca_launch(k_mlp_eval, dim3((unsigned)((n + 255) / 256)), dim3(kBlock), 0, s, pk, th, tab,
                      stats, X, n, raw, Y);
 }
+
+#define HCA_MLP_INST(T)                                                                            \
+  template void launch_mlp_apply<T>(hipStream_t, const Work&, const DevParams&, const MlpDev&,     \
+                                    const uint8_t*, const T*, const T*, const T*, double*,         \
+                                    double*, double*, unsigned long long*, Counters*);             \
+  template void launch_mlp_harvest<T>(hipStream_t, const Work&, const DevParams&, const uint8_t*,  \
+                                      const T*, const T*, const T*, const double*, const double*,  \
+                                      const double*, const long long*, float*, float*);
+HCA_MLP_INST(double)
+HCA_MLP_INST(float)
 
 }  // namespace hca

@@ -9,8 +9,9 @@
 
 namespace hca {
 
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_ode(Work w, DevParams p, const uint8_t* __restrict__ L,
-                                                const double* __restrict__ K,
+                                                const T* __restrict__ K,
                                                 double* __restrict__ P,
                                                 double* __restrict__ Vc,
                                                 double* __restrict__ phi) {
@@ -52,10 +53,15 @@ __global__ void __launch_bounds__(kBlock) k_ode(Work w, DevParams p, const uint8
   }
 }
 
-void launch_ode(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
-                const double* K, double* P, double* Vc, double* phi) {
-  hca_launch(k_ode, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, K,
-                     P, Vc, phi);
+template <typename T>
+void launch_ode(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L, const T* K,
+                double* P, double* Vc, double* phi) {
+  hca_launch(k_ode<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, K, P, Vc, phi);
 }
+
+template void launch_ode<double>(hipStream_t, const Work&, const DevParams&, const uint8_t*,
+                                 const double*, double*, double*, double*);
+template void launch_ode<float>(hipStream_t, const Work&, const DevParams&, const uint8_t*,
+                                const float*, double*, double*, double*);
 
 }  // namespace hca

@@ -10,6 +10,8 @@
 // such update is  c_i u_i - a' (Lap u)_i = b_i  with the solver coupling
 // a' = theta a and the zero-flux 7-point Laplacian; these kernels produce c
 // and b per voxel.
+#include <algorithm>
+
 #include "dev_util.h"
 
 namespace hca {
@@ -134,20 +136,21 @@ __device__ inline void for_each_voxel(const Work& w, F f) {
 //   step:   c = 1/dt + r_k w + phi_K chi/(K1 + K^n),   b = K^n/dt + r_k w K0
 //   steady: c =        r_k w + phi_K chi/(K1 + K),     b =        r_k w K0,
 //           both times theta (the solver's coupling is theta a_K)
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_setup_o2(Work w, DevParams p, const uint8_t* L,
-                                                     const double* vw, const double* K,
-                                                     double* c, double* b, int steady) {
+                                                     const double* vw, const T* K, T* c, T* b,
+                                                     int steady) {
   for_each_voxel(w, [&](int, const RepDev&, long long g) {
     const double k = K[g];
     const double wv = vw[g];
     const double chi = L[g] != 0 ? 1.0 : 0.0;
     const double up = p.phi_K * chi / (p.K1 + fmax(k, 0.0));
     if (steady) {
-      c[g] = p.theta * (p.r_k * wv + up);
-      b[g] = p.theta * (p.r_k * wv * p.K0);
+      c[g] = (T)(p.theta * (p.r_k * wv + up));
+      b[g] = (T)(p.theta * (p.r_k * wv * p.K0));
     } else {
-      c[g] = p.inv_dt + p.r_k * wv + up;
-      b[g] = k * p.inv_dt + p.r_k * wv * p.K0;
+      c[g] = (T)(p.inv_dt + p.r_k * wv + up);
+      b[g] = (T)(k * p.inv_dt + p.r_k * wv * p.K0);
     }
   });
 }
@@ -165,14 +168,14 @@ __global__ void __launch_bounds__(kBlock) k_setup_o2(Work w, DevParams p, const 
 //           V_c of the coupled step's start at both ends of every substep.
 // With one backward-Euler substep these are the coupled step's systems
 // c = 1/dt + R, b = u/dt + S.
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long long ntot,
                                                        const uint8_t* __restrict__ L,
                                                        const double* __restrict__ vw,
-                                                       const double* __restrict__ F,
+                                                       const T* __restrict__ F,
                                                        const double* __restrict__ Vc,
                                                        const double* __restrict__ g0,
-                                                       double* __restrict__ c,
-                                                       double* __restrict__ b) {
+                                                       T* __restrict__ c, T* __restrict__ b) {
   const double th = p.theta, th1 = 1.0 - p.theta;
   for_each_voxel(w, [&](int rep, const RepDev&, long long g) {
     const double wv = vw[g];
@@ -180,20 +183,21 @@ __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long
     const double chi = L[g] != 0 ? 1.0 : 0.0;
     const double rw = p.r_k * wv;
     const double up = p.phi_K * chi / (p.K1 + fmax(k, 0.0));
-    c[g] = p.inv_tau + th * rw + th * up;
-    b[g] = k * (p.inv_tau - th1 * (rw + up)) + rw * p.K0;
+    c[g] = (T)(p.inv_tau + th * rw + th * up);
+    b[g] = (T)(k * (p.inv_tau - th1 * (rw + up)) + rw * p.K0);
     const double kw = p.kappa_G * wv;
     const double cg = p.inv_tau + th * p.psi_G + th * kw;
     const double rg = p.psi_G + kw;
     for (int i = 0; i < 2 + p.drug3; ++i) {   // drug i in field i + 1
       const long long j = g + (i + 1) * ntot;
-      c[j] = cg;
-      b[j] = F[j] * (p.inv_tau - th1 * rg) + kw * (th * g0[3 * rep + i] + th1 * g0[3 * w.nreps + 3 * rep + i]);
+      c[j] = (T)cg;
+      b[j] = (T)((double)F[j] * (p.inv_tau - th1 * rg) +
+                 kw * (th * g0[3 * rep + i] + th1 * g0[3 * w.nreps + 3 * rep + i]));
     }
     if (p.vegf) {
       const long long j = g + (long long)p.fV * ntot;
-      c[j] = p.inv_tau + th * p.psi_V;
-      b[j] = F[j] * (p.inv_tau - th1 * p.psi_V) + p.sec_V * Vc[g] * chi;
+      c[j] = (T)(p.inv_tau + th * p.psi_V);
+      b[j] = (T)((double)F[j] * (p.inv_tau - th1 * p.psi_V) + p.sec_V * Vc[g] * chi);
     }
   });
 }
@@ -205,29 +209,29 @@ __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long
 //   b = b_lin - theta phi_K chi K^2/(K1 + K)^2;
 // with the linear continuation below K = 0 (K+ = max(K, 0)):
 //   c = ... K1/(K1 + K+)^2,  b = b_lin - theta phi_K chi K K+/(K1 + K+)^2.
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_setup_o2_newton(Work w, DevParams p,
                                                             const uint8_t* __restrict__ L,
                                                             const double* __restrict__ vw,
-                                                            const double* __restrict__ K,
-                                                            const double* __restrict__ b_lin,
-                                                            double* __restrict__ c,
-                                                            double* __restrict__ b) {
+                                                            const T* __restrict__ K,
+                                                            const T* __restrict__ b_lin,
+                                                            T* __restrict__ c, T* __restrict__ b) {
   for_each_voxel(w, [&](int, const RepDev&, long long g) {
     const double k = K[g];
     const double kp = fmax(k, 0.0);
     const double chi = L[g] != 0 ? 1.0 : 0.0;
     const double d = p.K1 + kp;
-    c[g] = p.inv_tau + p.theta * (p.r_k * vw[g]) + p.theta * (p.phi_K * chi * p.K1 / (d * d));
-    b[g] = b_lin[g] - p.theta * (p.phi_K * chi * k * kp / (d * d));
+    c[g] = (T)(p.inv_tau + p.theta * (p.r_k * vw[g]) + p.theta * (p.phi_K * chi * p.K1 / (d * d)));
+    b[g] = (T)((double)b_lin[g] - p.theta * (p.phi_K * chi * k * kp / (d * d)));
   });
 }
 
 // b += (1 - theta) a Lap F for the nf fields (theta < 1): the explicit half
 // of a Crank-Nicolson-type substep, Lap the zero-flux 7-point Laplacian
 // (neighbours in the order -x, +x, -y, +y, -z, +z).
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_rhs_lap(Work w, DevParams p, long long ntot,
-                                                    const double* __restrict__ F,
-                                                    double* __restrict__ b) {
+                                                    const T* __restrict__ F, T* __restrict__ b) {
   const double sK = (1.0 - p.theta) * p.aK, sG = (1.0 - p.theta) * p.aG,
                sV = (1.0 - p.theta) * p.aV;
   for_each_voxel(w, [&](int, const RepDev& rp, long long g) {
@@ -238,16 +242,17 @@ __global__ void __launch_bounds__(kBlock) k_rhs_lap(Work w, DevParams p, long lo
     const int z = (int)(q / rp.ny);
     const long long sy = rp.nx, sz = (long long)rp.nx * rp.ny;
     for (int f = 0; f < p.nf; ++f) {
-      const double* u = F + (long long)f * ntot;
+      const T* u = F + (long long)f * ntot;
       const double uc = u[g];
       double lap = 0.0;
-      if (x > 0) lap += u[g - 1] - uc;
-      if (x + 1 < rp.nx) lap += u[g + 1] - uc;
-      if (y > 0) lap += u[g - sy] - uc;
-      if (y + 1 < rp.ny) lap += u[g + sy] - uc;
-      if (z > 0) lap += u[g - sz] - uc;
-      if (z + 1 < rp.nz) lap += u[g + sz] - uc;
-      b[g + (long long)f * ntot] += (f == 0 ? sK : (p.vegf && f == p.fV) ? sV : sG) * lap;
+      if (x > 0) lap += (double)u[g - 1] - uc;
+      if (x + 1 < rp.nx) lap += (double)u[g + 1] - uc;
+      if (y > 0) lap += (double)u[g - sy] - uc;
+      if (y + 1 < rp.ny) lap += (double)u[g + sy] - uc;
+      if (z > 0) lap += (double)u[g - sz] - uc;
+      if (z + 1 < rp.nz) lap += (double)u[g + sz] - uc;
+      const long long j = g + (long long)f * ntot;
+      b[j] = (T)((double)b[j] + (f == 0 ? sK : (p.vegf && f == p.fV) ? sV : sG) * lap);
     }
   });
 }
@@ -256,20 +261,21 @@ __global__ void __launch_bounds__(kBlock) k_rhs_lap(Work w, DevParams p, long lo
 // the previous solve's value kept in Fprev: mode 1 linear, u + (u - u_prev);
 // mode 2 geometric, u (u / u_prev), on positive decaying values only (a
 // drug field between boluses decays nearly geometrically), else u.
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_extrapolate(Work w, long long ntot, int nf, unsigned fmask,
-                                                        int mode, double* __restrict__ F,
-                                                        double* __restrict__ Fprev) {
+                                                        int mode, T* __restrict__ F,
+                                                        T* __restrict__ Fprev) {
   for_each_voxel(w, [&](int, const RepDev&, long long g) {
     for (int f = 0; f < nf; ++f) {
       if (!((fmask >> f) & 1u)) continue;
       const long long j = g + (long long)f * ntot;
       const double u = F[j];
       const double up = Fprev[j];
-      Fprev[j] = u;
+      Fprev[j] = (T)u;
       if (mode == 1) {
-        F[j] = u + (u - up);
+        F[j] = (T)(u + (u - up));
       } else if (up > 0.0 && u > 0.0 && u < up) {   // geometric, decaying values only
-        F[j] = u * (u / up);
+        F[j] = (T)(u * (u / up));
       }
     }
   });
@@ -278,8 +284,9 @@ __global__ void __launch_bounds__(kBlock) k_extrapolate(Work w, long long ntot, 
 // Algorithm 1 initialisation of the cell state at the initial oxygen K^0:
 // P, V_c at the steady states of Eqs. (odep53), (odevegf) on occupied voxels,
 // phi ~ U(0,1) for cancer cells (Philox counter (gid, 0, INIT, 0), key (seed, 0)).
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_init_cells(Work w, DevParams p, const uint8_t* L,
-                                                       const double* K, double* P, double* Vc,
+                                                       const T* K, double* P, double* Vc,
                                                        double* phi) {
   for_each_voxel(w, [&](int, const RepDev& rp, long long g) {
     const uint8_t l = L[g];
@@ -311,39 +318,83 @@ void launch_plasma(hipStream_t s, const Work& w, const DevParams& p, const long 
   hca_launch(k_plasma, dim3(nb), dim3(64), 0, s, w.nreps, w.reps, p, d_step, j, dose_t, dose_a, g0);
 }
 
+template <typename T>
 void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
-                     const double* vw, const double* K, double* c, double* b, int steady) {
-  hca_launch(k_setup_o2, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, vw, K, c, b, steady);
+                     const double* vw, const T* K, T* c, T* b, int steady) {
+  hca_launch(k_setup_o2<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, vw, K,
+             c, b, steady);
 }
 
+template <typename T>
 void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
-                       const uint8_t* L, const double* vw, const double* F, const double* Vc,
-                       const double* g0, double* c, double* b) {
-  hca_launch(k_setup_step, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot, L, vw, F, Vc,
-             g0, c, b);
+                       const uint8_t* L, const double* vw, const T* F, const double* Vc,
+                       const double* g0, T* c, T* b) {
+  hca_launch(k_setup_step<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot, L,
+             vw, F, Vc, g0, c, b);
 }
 
+template <typename T>
 void launch_setup_o2_newton(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
-                            const double* vw, const double* K, const double* b_lin, double* c,
-                            double* b) {
-  hca_launch(k_setup_o2_newton, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, vw, K, b_lin,
-             c, b);
+                            const double* vw, const T* K, const T* b_lin, T* c, T* b) {
+  hca_launch(k_setup_o2_newton<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L,
+             vw, K, b_lin, c, b);
 }
 
-void launch_rhs_lap(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
-                    const double* F, double* b) {
-  hca_launch(k_rhs_lap, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot, F, b);
+template <typename T>
+void launch_rhs_lap(hipStream_t s, const Work& w, const DevParams& p, long long ntot, const T* F,
+                    T* b) {
+  hca_launch(k_rhs_lap<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot, F, b);
 }
 
+template <typename T>
 void launch_extrapolate(hipStream_t s, const Work& w, long long ntot, int nf, unsigned fmask, int mode,
-                        double* F, double* Fprev) {
-  hca_launch(k_extrapolate, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, ntot, nf, fmask,
-             mode, F, Fprev);
+                        T* F, T* Fprev) {
+  hca_launch(k_extrapolate<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, ntot, nf,
+             fmask, mode, F, Fprev);
 }
 
+template <typename T>
 void launch_init_cells(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
-                       const double* K, double* P, double* Vc, double* phi) {
-  hca_launch(k_init_cells, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, K, P, Vc, phi);
+                       const T* K, double* P, double* Vc, double* phi) {
+  hca_launch(k_init_cells<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, K, P,
+             Vc, phi);
 }
+
+template <typename S, typename D>
+__global__ void __launch_bounds__(kBlock) k_convert(const S* __restrict__ src, D* __restrict__ dst,
+                                                    long long n) {
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+    dst[i] = (D)src[i];
+}
+
+void launch_convert(hipStream_t s, const float* src, double* dst, long long n) {
+  const long long nb = std::min<long long>((n + kBlock - 1) / kBlock, 65536);
+  hca_launch(k_convert<float, double>, dim3((unsigned)std::max<long long>(nb, 1)), dim3(kBlock), 0, s,
+             src, dst, n);
+}
+
+void launch_convert(hipStream_t s, const double* src, float* dst, long long n) {
+  const long long nb = std::min<long long>((n + kBlock - 1) / kBlock, 65536);
+  hca_launch(k_convert<double, float>, dim3((unsigned)std::max<long long>(nb, 1)), dim3(kBlock), 0, s,
+             src, dst, n);
+}
+
+#define HCA_SETUP_INST(T)                                                                          \
+  template void launch_setup_o2<T>(hipStream_t, const Work&, const DevParams&, const uint8_t*,     \
+                                   const double*, const T*, T*, T*, int);                          \
+  template void launch_setup_step<T>(hipStream_t, const Work&, const DevParams&, long long,        \
+                                     const uint8_t*, const double*, const T*, const double*,       \
+                                     const double*, T*, T*);                                       \
+  template void launch_setup_o2_newton<T>(hipStream_t, const Work&, const DevParams&,              \
+                                          const uint8_t*, const double*, const T*, const T*, T*,   \
+                                          T*);                                                     \
+  template void launch_rhs_lap<T>(hipStream_t, const Work&, const DevParams&, long long, const T*, \
+                                  T*);                                                             \
+  template void launch_extrapolate<T>(hipStream_t, const Work&, long long, int, unsigned, int, T*, \
+                                      T*);                                                         \
+  template void launch_init_cells<T>(hipStream_t, const Work&, const DevParams&, const uint8_t*,   \
+                                     const T*, double*, double*, double*);
+HCA_SETUP_INST(double)
+HCA_SETUP_INST(float)
 
 }  // namespace hca

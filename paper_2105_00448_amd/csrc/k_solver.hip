@@ -79,9 +79,14 @@ constexpr int kStencilPrefetch = 1;
 // flight while plane z is computed, in a ring of registers (the z loop is
 // unrolled by PD so every ring slot is a fixed register), so their latency
 // overlaps the compute and the barrier.  Called by the whole workgroup.
-template <int PD, typename OP, typename F>
-__device__ inline void plane_stencil(const TileCoord& tc, const double* __restrict__ c,
-                                     double (*lds)[kPlaneMax], const OP& op, F f) {
+//
+// T is the storage type of the fields (double, or float in precision 32):
+// the operand is rounded to T once (into LDS, and for a neighbour read from
+// global memory), so every tile sees the same value at a voxel; the stencil
+// arithmetic is FP64 in both.
+template <int PD, typename T, typename OP, typename F>
+__device__ inline void plane_stencil(const TileCoord& tc, const T* __restrict__ c,
+                                     T (*lds)[kPlaneMax], const OP& op, F f) {
   using Raw = typename OP::Raw;
   struct Slot {
     Raw ri, rf;   // operand of the thread's cell and of its frame cell
@@ -123,15 +128,15 @@ __device__ inline void plane_stencil(const TileCoord& tc, const double* __restri
     if (tc.valid && zp < z1) sl.c = c[pz + iidx];
     if (fin) sl.rf = op.load(pz + fidx);
   };
-  auto store_slot = [&](const Slot& sl, double* buf) {
-    buf[o] = tc.valid ? op.value(sl.ri) : 0.0;
-    if (has_frame) buf[fo] = fin ? op.value(sl.rf) : 0.0;
+  auto store_slot = [&](const Slot& sl, T* buf) {
+    buf[o] = tc.valid ? (T)op.value(sl.ri) : (T)0;
+    if (has_frame) buf[fo] = fin ? (T)op.value(sl.rf) : (T)0;
   };
   const bool xl = tc.x > 0, xr = tc.x + 1 < tc.nx, yl = tc.y > 0, yr = tc.y + 1 < tc.ny;
   const int deg_xy = (int)xl + (int)xr + (int)yl + (int)yr;
   long long i = tc.off + iidx + plane * z0;
-  double* cur = lds[0];
-  double* nxt = lds[1];
+  T* cur = lds[0];
+  T* nxt = lds[1];
   // ring: plane zp (z0 < zp <= min(z1, nz - 1)) in slot (zp - z0 - 1) % PD
   Slot ring[PD];
 #pragma unroll
@@ -141,7 +146,7 @@ __device__ inline void plane_stencil(const TileCoord& tc, const double* __restri
   {
     Slot s0{op.zero(), op.zero(), 0.0};
     load_slot(s0, z0);
-    um = (tc.valid && z0 > 0) ? op.value(op.load(i - plane)) : 0.0;
+    um = (tc.valid && z0 > 0) ? (double)(T)op.value(op.load(i - plane)) : 0.0;
 #pragma unroll
     for (int d = 0; d < PD; ++d)
       if (z0 + 1 + d <= z1 && z0 + 1 + d < tc.nz) load_slot(ring[d], z0 + 1 + d);
@@ -164,11 +169,11 @@ __device__ inline void plane_stencil(const TileCoord& tc, const double* __restri
           if (zq <= z1 && zq < tc.nz) load_slot(ring[d], zq);
         }
         double s = cur[o - 1];
-        s += cur[o + 1];
-        s += cur[o - W];
-        s += cur[o + W];
+        s += (double)cur[o + 1];
+        s += (double)cur[o - W];
+        s += (double)cur[o + W];
         __syncthreads();
-        const double up = zr ? nxt[o] : 0.0;
+        const double up = zr ? (double)nxt[o] : 0.0;
         s += um;
         s += up;
         if (tc.valid) {
@@ -179,7 +184,7 @@ __device__ inline void plane_stencil(const TileCoord& tc, const double* __restri
         um = uc;
         uc = up;
         cc = cn;
-        double* t = cur;
+        T* t = cur;
         cur = nxt;
         nxt = t;
         i += plane;
@@ -191,24 +196,25 @@ __device__ inline void plane_stencil(const TileCoord& tc, const double* __restri
 // Operands of the stencil: the iterate x (start), and p = z + beta p_old
 // formed on the fly (apply; z FP64 for Jacobi, the multigrid's FP32 result
 // otherwise).
+template <typename T>
 struct OpX {
   struct Raw {
     double x;
   };
-  const double* __restrict__ x;
+  const T* __restrict__ x;
   __device__ inline Raw zero() const { return Raw{0.0}; }
   __device__ inline Raw load(long long j) const { return Raw{x[j]}; }
   __device__ inline double value(const Raw& r) const { return r.x; }
 };
 
-template <bool JAC>
+template <bool JAC, typename T>
 struct OpP {
   struct Raw {
     double z, p;
   };
-  const double* __restrict__ z;
+  const T* __restrict__ z;
   const float* __restrict__ z32;
-  const double* __restrict__ pold;
+  const T* __restrict__ pold;
   double beta;
   double isc;   // multigrid: z = z32 / sc
   bool first;
@@ -226,12 +232,13 @@ struct OpP {
 };
 
 // r = b - A x; Jacobi mode also Dinv = 1/diag(A), z = Dinv r.
-__global__ void __launch_bounds__(kBlock) k_cg_start(Work w, const double* __restrict__ c,
-                                                     const double* __restrict__ b,
-                                                     const double* __restrict__ x,
-                                                     SolverBufs sb) {
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cg_start(Work w, const T* __restrict__ c,
+                                                     const T* __restrict__ b,
+                                                     const T* __restrict__ x,
+                                                     SolverBufsT<T> sb) {
   __shared__ double lds4[4];
-  __shared__ double lds[2][kPlaneMax];
+  __shared__ T lds[2][kPlaneMax];
   int t0, t1;
   tile_range(w.ntiles, t0, t1);
   for (int ti = t0; ti < t1; ++ti) {
@@ -239,18 +246,18 @@ __global__ void __launch_bounds__(kBlock) k_cg_start(Work w, const double* __res
     const double a = tc.a;
     double bb = 0.0, rr = 0.0, rz = 0.0;
     {
-      plane_stencil<kStencilPrefetch>(tc, c, lds, OpX{x},
+      plane_stencil<kStencilPrefetch>(tc, c, lds, OpX<T>{x},
                      [&](long long i, int deg, double, double Ax) {
                        const double bi = b[i];
-                       const double r = bi - Ax;
-                       sb.r[i] = r;
+                       const double r = (double)(T)(bi - Ax);
+                       sb.r[i] = (T)r;
                        bb += bi * bi;
                        rr += r * r;
                        if (sb.jacobi) {
-                         const double di = 1.0 / (c[i] + a * deg);
-                         const double zz = r * di;
-                         sb.dinv[i] = di;
-                         sb.z[i] = zz;
+                         const double di = (double)(T)(1.0 / ((double)c[i] + a * deg));
+                         const double zz = (double)(T)(r * di);
+                         sb.dinv[i] = (T)di;
+                         sb.z[i] = (T)zz;
                          rz += r * zz;
                        }
                      });
@@ -263,14 +270,14 @@ __global__ void __launch_bounds__(kBlock) k_cg_start(Work w, const double* __res
 }
 
 // p_new = z + beta p_old (p_new = z on the first iteration), q = A p_new.
-template <bool JAC>
-__global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, const double* __restrict__ c,
-                                                     const double* __restrict__ z,
-                                                     const double* __restrict__ pold,
-                                                     double* __restrict__ pnew,
-                                                     double* __restrict__ q, SolverBufs sb) {
+template <bool JAC, typename T>
+__global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, const T* __restrict__ c,
+                                                     const T* __restrict__ z,
+                                                     const T* __restrict__ pold,
+                                                     T* __restrict__ pnew,
+                                                     T* __restrict__ q, SolverBufsT<T> sb) {
   __shared__ double lds4[4];
-  __shared__ double lds[2][kPlaneMax];
+  __shared__ T lds[2][kPlaneMax];
   int t0, t1;
   tile_range(w.ntiles, t0, t1);
   for (int ti = t0; ti < t1; ++ti) {
@@ -281,11 +288,12 @@ __global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, const double* __res
     const bool first = ssr->first != 0;
     double pq = 0.0;
     {
-      const OpP<JAC> op{z, sb.z32, pold, beta, ssr->isc, first};
+      const OpP<JAC, T> op{z, sb.z32, pold, beta, ssr->isc, first};
       plane_stencil<kStencilPrefetch>(tc, c, lds, op, [&](long long i, int, double pc, double Ap) {
-        pnew[i] = pc;
-        q[i] = Ap;
-        pq += pc * Ap;
+        const T qi = (T)Ap;
+        pnew[i] = (T)pc;
+        q[i] = qi;
+        pq += pc * (double)qi;
       });
     }
     pq = block_sum(pq, lds4);
@@ -294,11 +302,11 @@ __global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, const double* __res
 }
 
 // x += alpha p, r -= alpha q; partials of r.r, r.z_old and (Jacobi) r.z'.
-template <bool JAC>
-__global__ void __launch_bounds__(kBlock) k_cg_update(Work w, double* __restrict__ x,
-                                                      const double* __restrict__ p,
-                                                      const double* __restrict__ q,
-                                                      SolverBufs sb) {
+template <bool JAC, typename T>
+__global__ void __launch_bounds__(kBlock) k_cg_update(Work w, T* __restrict__ x,
+                                                      const T* __restrict__ p,
+                                                      const T* __restrict__ q,
+                                                      SolverBufsT<T> sb) {
   __shared__ double lds4[4];
   constexpr bool jac = JAC;
   int b0, b1;
@@ -311,18 +319,39 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(Work w, double* __restrict
     const double alpha = ssr->alpha;
     const double sc = ssr->sc, isc_prev = ssr->isc_prev;
     double rr = 0.0, rzo = 0.0, rzn = 0.0;
-    for (long long i = off + fb.begin + threadIdx.x; i < off + fb.end; i += kBlock) {
-      x[i] += alpha * p[i];
-      const double r = sb.r[i] - alpha * q[i];
-      sb.r[i] = r;
-      if (!jac) sb.r32[i] = (float)(r * sc);   // the multigrid's scaled copy
-      const double zold = jac ? sb.z[i] : (double)sb.z32[i] * isc_prev;
-      rr += r * r;
-      rzo += r * zold;
-      if (jac) {
-        const double znew = r * sb.dinv[i];
-        sb.z[i] = znew;
-        rzn += r * znew;
+    // kUpd voxels per thread per trip, every load issued before any use, so
+    // enough bytes are in flight per CU to stream at HBM rate on long items
+    constexpr int kUpd = 4;
+    const long long end = off + fb.end;
+    for (long long i0 = off + fb.begin + threadIdx.x; i0 < end; i0 += kUpd * kBlock) {
+      double xv[kUpd], pv[kUpd], rv[kUpd], qv[kUpd], zo[kUpd], dv[kUpd];
+#pragma unroll
+      for (int u = 0; u < kUpd; ++u) {
+        const long long i = i0 + (long long)u * kBlock;
+        if (i < end) {
+          xv[u] = x[i];
+          pv[u] = p[i];
+          rv[u] = sb.r[i];
+          qv[u] = q[i];
+          zo[u] = jac ? (double)sb.z[i] : (double)sb.z32[i] * isc_prev;
+          dv[u] = jac ? (double)sb.dinv[i] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kUpd; ++u) {
+        const long long i = i0 + (long long)u * kBlock;
+        if (i >= end) continue;
+        x[i] = (T)(xv[u] + alpha * pv[u]);
+        const double r = (double)(T)(rv[u] - alpha * qv[u]);
+        sb.r[i] = (T)r;
+        if (!jac) sb.r32[i] = (float)(r * sc);   // the multigrid's scaled copy
+        rr += r * r;
+        rzo += r * zo[u];
+        if (jac) {
+          const double znew = (double)(T)(r * dv[u]);
+          sb.z[i] = (T)znew;
+          rzn += r * znew;
+        }
       }
     }
     rr = block_sum(rr, lds4);
@@ -340,7 +369,8 @@ __device__ inline double residual_scale(double rr, long long n) {
 }
 
 // r32 = r sc of the systems still iterating (after the start reduce).
-__global__ void __launch_bounds__(kBlock) k_cg_r32(Work w, SolverBufs sb) {
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cg_r32(Work w, SolverBufsT<T> sb) {
   int b0, b1;
   work_range(w.nflat, b0, b1);
   for (int it = b0; it < b1; ++it) {
@@ -350,7 +380,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_r32(Work w, SolverBufs sb) {
     const long long off = w.reps[fb.rep].off;
     const double sc = ssr->sc;
     for (long long i = off + fb.begin + threadIdx.x; i < off + fb.end; i += kBlock)
-      sb.r32[i] = (float)(sb.r[i] * sc);
+      sb.r32[i] = (float)((double)sb.r[i] * sc);
   }
 }
 
@@ -363,8 +393,8 @@ __device__ inline double sum_partials(const double* partial, int b0, int nb, int
 
 // One workgroup per replicate: finish the reduction of the preceding kernel
 // and advance the replicate's CG scalars.
-template <int KIND>
-__global__ void __launch_bounds__(kBlock) k_cg_reduce(Work w, SolverBufs sb, double rtol, int maxit,
+template <int KIND, typename T>
+__global__ void __launch_bounds__(kBlock) k_cg_reduce(Work w, SolverBufsT<T> sb, double rtol, int maxit,
                                                       unsigned fmask, int nrep) {
   __shared__ double lds4[4];
   const int rep = blockIdx.x;
@@ -444,62 +474,80 @@ __global__ void __launch_bounds__(kBlock) k_cg_reduce(Work w, SolverBufs sb, dou
 
 __global__ void k_zero_int(int* p) { *p = 0; }
 
-void launch_cg_reduce(hipStream_t s, const Work& w, const SolverBufs& sb, int kind, double rtol,
+template <typename T>
+void launch_cg_reduce(hipStream_t s, const Work& w, const SolverBufsT<T>& sb, int kind, double rtol,
                       int maxit, unsigned fm, int nrep) {
   const dim3 g(w.nreps), b(kBlock);
   switch (kind) {
     case RED_START:
-      hca_launch(k_cg_reduce<RED_START>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
+      hca_launch(k_cg_reduce<RED_START, T>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
       break;
     case RED_APPLY:
-      hca_launch(k_cg_reduce<RED_APPLY>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
+      hca_launch(k_cg_reduce<RED_APPLY, T>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
       break;
     case RED_UPDATE:
-      hca_launch(k_cg_reduce<RED_UPDATE>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
+      hca_launch(k_cg_reduce<RED_UPDATE, T>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
       break;
     default:
-      hca_launch(k_cg_reduce<RED_RZ>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
+      hca_launch(k_cg_reduce<RED_RZ, T>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
       break;
   }
 }
 
-void launch_cg_start(hipStream_t s, const Work& w, double rtol, int maxit, const double* c,
-                     const double* b, const double* x, const SolverBufs& sb, unsigned field_mask,
-                     int nrep) {
-  hca_launch(k_cg_start, dim3(grid_tiles(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c, b, x, sb);
+template <typename T>
+void launch_cg_start(hipStream_t s, const Work& w, double rtol, int maxit, const T* c, const T* b,
+                     const T* x, const SolverBufsT<T>& sb, unsigned field_mask, int nrep) {
+  hca_launch(k_cg_start<T>, dim3(grid_tiles(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c, b, x,
+             sb);
   hca_launch(k_zero_int, dim3(1), dim3(1), 0, s, sb.ndone);   // before the start reduce counts
   launch_cg_reduce(s, w, sb, RED_START, rtol, maxit, field_mask, nrep);
-  if (!sb.jacobi) hca_launch(k_cg_r32, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, sb);
+  if (!sb.jacobi)
+    hca_launch(k_cg_r32<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, sb);
 }
 
-void launch_cg_apply_kernel(hipStream_t s, const Work& w, const double* c, const SolverBufs& sb,
+template <typename T>
+void launch_cg_apply_kernel(hipStream_t s, const Work& w, const T* c, const SolverBufsT<T>& sb,
                             int parity) {
-  const double* pold = parity ? sb.p1 : sb.p0;
-  double* pnew = parity ? sb.p0 : sb.p1;
+  const T* pold = parity ? sb.p1 : sb.p0;
+  T* pnew = parity ? sb.p0 : sb.p1;
   if (sb.jacobi)
-    hca_launch(k_cg_apply<true>, dim3(grid_tiles(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c,
-               sb.z, pold, pnew, sb.q, sb);
+    hca_launch(k_cg_apply<true, T>, dim3(grid_tiles(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c,
+               (const T*)sb.z, pold, pnew, sb.q, sb);
   else
-    hca_launch(k_cg_apply<false>, dim3(grid_tiles(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c,
-               sb.z, pold, pnew, sb.q, sb);
+    hca_launch(k_cg_apply<false, T>, dim3(grid_tiles(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c,
+               (const T*)sb.z, pold, pnew, sb.q, sb);
 }
 
-void launch_cg_apply(hipStream_t s, const Work& w, const double* c, const SolverBufs& sb,
-                     int parity) {
+template <typename T>
+void launch_cg_apply(hipStream_t s, const Work& w, const T* c, const SolverBufsT<T>& sb, int parity) {
   launch_cg_apply_kernel(s, w, c, sb, parity);
   launch_cg_reduce(s, w, sb, RED_APPLY, 0.0, 0);
 }
 
-void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, double* x,
-                      const SolverBufs& sb, int parity) {
-  const double* pnew = parity ? sb.p0 : sb.p1;
+template <typename T>
+void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, T* x,
+                      const SolverBufsT<T>& sb, int parity) {
+  const T* pnew = parity ? sb.p0 : sb.p1;
   if (sb.jacobi)
-    hca_launch(k_cg_update<true>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, x,
-               pnew, (const double*)sb.q, sb);
+    hca_launch(k_cg_update<true, T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, x,
+               pnew, (const T*)sb.q, sb);
   else
-    hca_launch(k_cg_update<false>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, x,
-               pnew, (const double*)sb.q, sb);
+    hca_launch(k_cg_update<false, T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, x,
+               pnew, (const T*)sb.q, sb);
   launch_cg_reduce(s, w, sb, RED_UPDATE, rtol, maxit);
 }
+
+#define HCA_SOLVER_INST(T)                                                                         \
+  template void launch_cg_reduce<T>(hipStream_t, const Work&, const SolverBufsT<T>&, int, double,  \
+                                    int, unsigned, int);                                           \
+  template void launch_cg_start<T>(hipStream_t, const Work&, double, int, const T*, const T*,      \
+                                   const T*, const SolverBufsT<T>&, unsigned, int);                \
+  template void launch_cg_apply_kernel<T>(hipStream_t, const Work&, const T*,                      \
+                                          const SolverBufsT<T>&, int);                             \
+  template void launch_cg_apply<T>(hipStream_t, const Work&, const T*, const SolverBufsT<T>&, int); \
+  template void launch_cg_update<T>(hipStream_t, const Work&, double, int, T*,                     \
+                                    const SolverBufsT<T>&, int);
+HCA_SOLVER_INST(double)
+HCA_SOLVER_INST(float)
 
 }  // namespace hca

@@ -70,10 +70,10 @@ struct MlpDev {
 // Launchers (k_mlp.hip).
 void launch_mlp_pack(hipStream_t s, const float* theta, bf16x8* packed);
 void launch_mlp_gelu_table(hipStream_t s, float2* tab);
+template <typename T>
 void launch_mlp_apply(hipStream_t s, const Work& w, const DevParams& p, const MlpDev& net,
-                      const uint8_t* L, const double* K, const double* G1, const double* G2,
-                      double* P, double* Vc, double* phi, unsigned long long* part,
-                      Counters* cnt);
+                      const uint8_t* L, const T* K, const T* G1, const T* G2, double* P,
+                      double* Vc, double* phi, unsigned long long* part, Counters* cnt);
 // Training pairs of one coupled step: before the plain ODE phase,
 // save_state keeps (P, Vc, phi); after it, harvest writes one row per
 // occupied voxel, in voxel order, at row item_off[item] + rank in the item.
@@ -81,10 +81,10 @@ void launch_mlp_count(hipStream_t s, const Work& w, const uint8_t* L, int* item_
 void launch_mlp_scan(hipStream_t s, int n, const int* cnt, long long* off);
 void launch_mlp_save_state(hipStream_t s, const Work& w, const double* P, const double* Vc,
                            const double* phi, double* before);
+template <typename T>
 void launch_mlp_harvest(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L,
-                        const double* K, const double* G1, const double* G2, const double* P,
-                        const double* Vc, const double* before, const long long* item_off,
-                        float* X, float* Y);
+                        const T* K, const T* G1, const T* G2, const double* P, const double* Vc,
+                        const double* before, const long long* item_off, float* X, float* Y);
 // Training set statistics: per column mean, scale and range of X (6) and Y (3).
 void launch_mlp_moments(hipStream_t s, const float* X, const float* Y, long long n, double* part,
                         int nblk, float* stats);

@@ -23,13 +23,42 @@
 #include "hca_internal.h"
 #include "mlp_dev.h"
 
+// This file is compiled twice: with HCA_REAL = double into namespace
+// hca::rt64 (precision 64, the primary instance, which also defines the
+// process-wide knobs and the precision-independent C entry points) and with
+// HCA_REAL = float into hca::rt32 (precision 32: the solved fields, their
+// solver arrays and guess history stored in FP32).  capi.cpp dispatches each
+// call to the instance that owns the context.
+#ifndef HCA_REAL
+#define HCA_REAL double
+#define HCA_RT_NS rt64
+#define HCA_RT_PRIMARY 1
+#endif
+#ifndef HCA_RT_PRIMARY
+#define HCA_RT_PRIMARY 0
+#endif
+
+#include "rt_api.h"
+
 using namespace hca;
 
+#if HCA_RT_PRIMARY
 namespace hca {
 thread_local KernelEvents g_kernel_events;
 int g_xcd_remap = 0;    // flat kernels: measured slower (HCA_XCD_REMAP=1 to enable)
 int g_tile_remap = 1;   // tile kernels: measured 4-8 % faster (HCA_TILE_REMAP=0 to disable)
-}
+}  // namespace hca
+#endif
+
+namespace hca {
+namespace HCA_RT_NS {
+
+using Real = HCA_REAL;
+using SolverBufs = SolverBufsT<Real>;
+constexpr int kPrecision = sizeof(Real) == 8 ? 64 : 32;
+// precision 32: FP32 storage limits the attainable relative residual, so the
+// solves stop at no less than this
+constexpr double kRtolFloor = sizeof(Real) == 8 ? 0.0 : 1e-8;
 
 namespace {
 
@@ -40,7 +69,7 @@ enum KernelClass {
   KC_MG_POST2_0, KC_MLP_APPLY, KC_VESSEL, KC_MG_SWEEP0, KC_COUNT
 };
 
-const char* kKernelNames[KC_COUNT] = {
+[[maybe_unused]] const char* kKernelNames[KC_COUNT] = {
     "k_plasma", "k_setup_step", "k_cg_start", "k_cg_apply", "k_cg_update",
     "k_ode", "k_ca_propose", "k_ca_resolve", "k_ca_finalize", "k_stats",
     "k_mg_prep0+k_mg_coarsen", "k_mg_pre<L0>", "k_mg_restrict<L0>", "mg levels >= 1 (global)",
@@ -48,33 +77,39 @@ const char* kKernelNames[KC_COUNT] = {
 
 // Compulsory (algorithmic) HBM bytes per voxel of each kernel class; solver
 // classes per voxel of each active system (0: not priced, latency-bound).
+// e = bytes of a stored field value (8, or 4 in precision 32); the cell map
+// is 1 byte, P, V_c, phi and the vessel map 8, the multigrid arrays 4.
+constexpr double kE = sizeof(Real);
 const double kBytesPerVoxel[KC_COUNT] = {
-    0.0,          // plasma: per replicate only
-    81.0,         // setup_step: read L, w, K, G1, G2; write c, b of three systems
-    40.0,         // cg_start: read x, c, b; write r, (Jacobi: dinv, z)
-    36.0,         // cg_apply, multigrid: read z (4), p_old, c; write p_new, q
-    72.0,         // cg_update, Jacobi: read x, p, r, q, z, dinv; write x, r, z
-    57.0,         // ode: read L, K, P, Vc, phi; write P, Vc, phi
-    11.0,         // ca_propose: scan (read L, phi; write code, win); the list's decisions
-                  // gather per committed cell, not per voxel
-    0.0,          // ca_resolve: gathers per proposing cell only
-    2.0,          // ca_finalize: read code, win (writes only where cells change)
-    57.0,         // stats: read L, w and six fields
-    21.0,         // mg prepare: read c (8); write dinv0 (4); level 1: read c, write c1, dinv1
-    12.0,         // mg pre L0: read r (FP32 copy, 4), dinv (4); write ualt (4)
-    12.5,         // mg restrict L0: read u, r (4), dinv; write r1 (1/8 of 4)
-    0.0,          // coarser global levels
-    0.0,          // coarse workgroup levels
-    16.5,         // mg post1 L0: read u, e (1/8), r (4), dinv; write ualt
-    20.0,         // mg post2 L0: read ualt, r, dinv; write z (4)
-    73.0,         // mlp apply: read L, K, G1, G2, P, Vc, phi; write P, Vc, phi
-    17.0,         // vessel: read L, w, V (writes only where a vessel changes)
-    16.0};        // mg sweep L0: read u (4), r (4), dinv (4); write u' (4)
-constexpr double kBytesSetupVegf = 32.0;   // setup_step with vegf: + read V, Vc; write c, b
-constexpr double kBytesSetupDrug3 = 24.0;  // setup_step with drug3: + read G3; write c, b
-constexpr double kBytesStatsField = 8.0;   // stats: per extra field scanned (V, G3)
-constexpr double kBytesUpdateMg = 56.0;   // cg_update, multigrid: read x, p, r, q, z (4); write x, r, r (4)
-constexpr double kBytesApplyJacobi = 40.0;   // cg_apply, Jacobi: z is FP64
+    0.0,            // plasma: per replicate only
+    9.0 + 9 * kE,   // setup_step: read L, w, K, G1, G2; write c, b of three systems
+    5 * kE,         // cg_start: read x, c, b; write r, (Jacobi: dinv, z)
+    4.0 + 4 * kE,   // cg_apply, multigrid: read z (4), p_old, c; write p_new, q
+    9 * kE,         // cg_update, Jacobi: read x, p, r, q, z, dinv; write x, r, z
+    49.0 + kE,      // ode: read L, K, P, Vc, phi; write P, Vc, phi
+    11.0,           // ca_propose: scan (read L, phi; write code, win); the list's decisions
+                    // gather per committed cell, not per voxel
+    0.0,            // ca_resolve: gathers per proposing cell only
+    2.0,            // ca_finalize: read code, win (writes only where cells change)
+    33.0 + 3 * kE,  // stats: read L, w, K, G1, G2, P, Vc, phi
+    13.0 + kE,      // mg prepare: read c; write dinv0 (4); level 1: read c, write c1, dinv1
+    12.0,           // mg pre L0: read r (FP32 copy, 4), dinv (4); write ualt (4)
+    12.5,           // mg restrict L0: read u, r (4), dinv; write r1 (1/8 of 4)
+    0.0,            // coarser global levels
+    0.0,            // coarse workgroup levels
+    16.5,           // mg post1 L0: read u, e (1/8), r (4), dinv; write ualt
+    12.0 + kE,      // mg post2 L0: read ualt, r, dinv; write z (4)
+    49.0 + 3 * kE,  // mlp apply: read L, K, G1, G2, P, Vc, phi; write P, Vc, phi
+    9.0 + kE,       // vessel: read L, w, V (writes only where a vessel changes)
+    16.0};          // mg sweep L0: read u (4), r (4), dinv (4); write u' (4)
+constexpr double kBytesSetupVegf = 8.0 + 3 * kE;   // setup_step with vegf: + read V, Vc; write c, b
+constexpr double kBytesSetupDrug3 = 3 * kE;        // setup_step with drug3: + read G3; write c, b
+constexpr double kBytesStatsField = kE;            // stats: per extra field scanned (V, G3)
+// cg_update, multigrid: the compulsory x, p, r, q read and x, r written (the
+// CG's own traffic); the kernel also reads the FP32 z and writes the FP32
+// copy of r for the multigrid (8 B more per voxel, not counted here)
+constexpr double kBytesUpdateMg = 6 * kE;
+constexpr double kBytesApplyJacobi = 5 * kE;       // cg_apply, Jacobi: z is a stored field value
 
 constexpr int kTagState = -2;   // launches over every voxel of every replicate
 constexpr int kTagAll = -1;     // solver launches over every system
@@ -95,7 +130,8 @@ struct ProfEntry {
 
 }  // namespace
 
-struct hca_ctx {
+struct Ctx : ::hca_ctx {
+  Ctx() { precision = kPrecision; }
   hca_params prm;
   DevParams dp;
   int nreps = 0;
@@ -112,18 +148,17 @@ struct hca_ctx {
   uint8_t *L = nullptr, *code = nullptr, *win = nullptr;
   CaList ca_list{};                             // committed cells of the CA pass
   double *w = nullptr, *P = nullptr, *Vc = nullptr, *phi = nullptr;
-  double* F = nullptr;                          // [K | G1 | G2], with vegf [K | G1 | G2 | V]
-  double *K = nullptr, *G1 = nullptr, *G2 = nullptr, *G3 = nullptr, *V = nullptr;
-  int nstat_fields = 6;                         // fields of the non-finite scan
+  Real* F = nullptr;                            // [K | G1 | G2 (| G3) (| V)]
+  Real *K = nullptr, *G1 = nullptr, *G2 = nullptr, *G3 = nullptr, *V = nullptr;
   // solver, nf x ntot (nf = dp.nf fields)
-  double *c = nullptr, *b = nullptr;
+  Real *c = nullptr, *b = nullptr;
   SolverBufs sb{};
   bool use_mg = false;
   MgBufs mg_all{}, mg1{};                       // all systems / oxygen systems only
   std::vector<void*> mg_mem;
   double *dose_t = nullptr, *dose_a = nullptr, *g0 = nullptr;
-  double* b_o2lin = nullptr;                     // o2_newton: the linearised O2 right-hand side
-  double* Fprev = nullptr;                       // x0_extrapolate: fields of the previous solve
+  Real* b_o2lin = nullptr;                       // o2_newton: the linearised O2 right-hand side
+  Real* Fprev = nullptr;                         // x0_extrapolate: fields of the previous solve
   long long* d_step = nullptr;
   // replicate tables (state kernels)
   RepDev* d_reps = nullptr;
@@ -138,7 +173,6 @@ struct hca_ctx {
   std::vector<long long> sys_n;
   Counters* d_cnt = nullptr;
   unsigned long long* d_cpart = nullptr;   // per flat item x kCounterSlots
-  const double** d_fields = nullptr;
   unsigned long long* d_bad = nullptr;
   // ODE surrogate (hca_set_surrogate) and training-pair harvest buffers
   bool sur_on = false;
@@ -170,7 +204,7 @@ struct hca_ctx {
 
 namespace {
 
-hca_status fail(hca_ctx* c, hca_status st, const std::string& msg) {
+hca_status fail(Ctx* c, hca_status st, const std::string& msg) {
   if (c) {
     c->err = msg;
     if (st != HCA_E_RANGE) c->failed = true;
@@ -192,7 +226,7 @@ hipError_t dalloc(T** p, size_t count) {
 
 // ---- kernel timing (params.profile) ----------------------------------------
 
-hipEvent_t take_event(hca_ctx* c) {
+hipEvent_t take_event(Ctx* c) {
   if (!c->free_events.empty()) {
     hipEvent_t e = c->free_events.back();
     c->free_events.pop_back();
@@ -205,17 +239,17 @@ hipEvent_t take_event(hca_ctx* c) {
   return e;
 }
 
-double bpv_of(const hca_ctx* c, int kc) {
+double bpv_of(const Ctx* c, int kc) {
   if (kc == KC_CG_UPDATE && c->use_mg) return kBytesUpdateMg;
   if (kc == KC_CG_APPLY && !c->use_mg) return kBytesApplyJacobi;
   if (kc == KC_SETUP)
     return kBytesPerVoxel[kc] + (c->dp.vegf ? kBytesSetupVegf : 0.0) + (c->dp.drug3 ? kBytesSetupDrug3 : 0.0);
-  if (kc == KC_STATS) return kBytesPerVoxel[kc] + (c->nstat_fields - 6) * kBytesStatsField;
+  if (kc == KC_STATS) return kBytesPerVoxel[kc] + (c->dp.nf - 3) * kBytesStatsField;
   return kBytesPerVoxel[kc];
 }
 
 // params.profile: 0 off, 1 every kernel class, k + 2 class k only.
-inline bool prof_on(const hca_ctx* c, int kc) {
+inline bool prof_on(const Ctx* c, int kc) {
   return c->prm.profile == 1 || c->prm.profile == kc + 2;
 }
 
@@ -224,12 +258,12 @@ inline bool prof_on(const hca_ctx* c, int kc) {
 // time is that kernel's execution; otherwise events are recorded on the
 // stream before and after (a segment of several kernels, gaps included).
 struct ProfScope {
-  hca_ctx* c;
+  Ctx* c;
   int kc;
   int tag;
   bool single;
   hipEvent_t a = nullptr, b = nullptr;
-  ProfScope(hca_ctx* c_, int kc_, int tag_, bool single_ = true)
+  ProfScope(Ctx* c_, int kc_, int tag_, bool single_ = true)
       : c(c_), kc(kc_), tag(tag_), single(single_) {
     if (!prof_on(c, kc)) return;
     a = take_event(c);
@@ -264,7 +298,7 @@ struct ProfScope {
 // Accumulate the pending timings.  A solver launch with tag t does work for
 // the systems still iterating (iterations > t); launches that found every
 // system finished are dropped, the others are priced on the active voxels.
-void prof_flush(hca_ctx* c, const SolveScal* ss, int nsys) {
+void prof_flush(Ctx* c, const SolveScal* ss, int nsys) {
   if (c->pending.empty()) return;
   (void)hipEventSynchronize(c->pending.back().b);
   for (const ProfEntry& e : c->pending) {
@@ -290,7 +324,7 @@ void prof_flush(hca_ctx* c, const SolveScal* ss, int nsys) {
 
 // Event pairs around the V-cycle's launch segments.
 struct MgProf {
-  hca_ctx* c;
+  Ctx* c;
   hipEvent_t start[8];
   int tag;
 };
@@ -309,7 +343,7 @@ int mg_segment_class(int seg) {
 
 void mg_hook(void* p, int seg, int begin) {
   MgProf* m = (MgProf*)p;
-  hca_ctx* c = m->c;
+  Ctx* c = m->c;
   if (!prof_on(c, mg_segment_class(seg))) return;
   if (begin) {
     m->start[seg] = take_event(c);
@@ -325,7 +359,7 @@ void mg_hook(void* p, int seg, int begin) {
   m->start[seg] = nullptr;
 }
 
-void run_vcycle(hca_ctx* c, const Work& W, const MgBufs& mg, int tag) {
+void run_vcycle(Ctx* c, const Work& W, const MgBufs& mg, int tag) {
   MgProf mp{};
   mp.c = c;
   mp.tag = tag;
@@ -464,7 +498,7 @@ int pick_tx(int nx) {
 // Captures two CG iterations (parities 0 and 1, with their V-cycles) of the
 // systems of W into a HIP graph on the capture-only stream.  On failure the
 // context falls back to direct launches for good.
-bool capture_iterations(hca_ctx* c, const Work& W, const MgBufs& mg, double rtol, int maxit,
+bool capture_iterations(Ctx* c, const Work& W, const MgBufs& mg, double rtol, int maxit,
                         int kind) {
   hipStream_t cs = c->cap_stream;
   if (!cs) return false;
@@ -499,7 +533,7 @@ bool capture_iterations(hca_ctx* c, const Work& W, const MgBufs& mg, double rtol
 // system but the oxygen ones has converged (the drugs often need only a few
 // iterations), the remaining iterations run on the oxygen prefix's tables
 // (sys1, mg1: the same arrays, fewer workgroups) and its captured graph.
-hca_status solve(hca_ctx* c, const Work& W_all, const MgBufs& mg_all, unsigned fmask, double rtol,
+hca_status solve(Ctx* c, const Work& W_all, const MgBufs& mg_all, unsigned fmask, double rtol,
                  int maxit, int kind) {
   const int nsys = W_all.nreps;
   const Work* Wp = &W_all;
@@ -584,7 +618,11 @@ hca_status solve(hca_ctx* c, const Work& W_all, const MgBufs& mg_all, unsigned f
   return HCA_OK;
 }
 
-hca_status run_phases(hca_ctx* c, unsigned mask) {
+// The solves' stopping tolerance: cg_rtol, and no less than FP32 storage can
+// attain in precision 32.
+inline double solve_rtol(const Ctx* c) { return std::max(c->prm.cg_rtol, kRtolFloor); }
+
+hca_status run_phases(Ctx* c, unsigned mask) {
   const Work& wk = c->work;
   hipStream_t s = c->stream;
   const unsigned drugs = c->dp.drug3 ? 14u : 6u;   // fields 1, 2 (and 3)
@@ -607,8 +645,8 @@ hca_status run_phases(hca_ctx* c, unsigned mask) {
     }
     const bool newton = c->prm.o2_newton > 0 && (fmask & 1u);
     if (newton)
-      HIPCHK(c, hipMemcpyAsync(c->b_o2lin, c->b, sizeof(double) * (size_t)c->ntot, hipMemcpyDeviceToDevice, s));
-    hca_status st = solve(c, c->sys_all, c->mg_all, fmask, c->prm.cg_rtol, c->prm.cg_maxit, 0);
+      HIPCHK(c, hipMemcpyAsync(c->b_o2lin, c->b, sizeof(Real) * (size_t)c->ntot, hipMemcpyDeviceToDevice, s));
+    hca_status st = solve(c, c->sys_all, c->mg_all, fmask, solve_rtol(c), c->prm.cg_maxit, 0);
     if (st != HCA_OK) return st;
     // Newton steps on the oxygen uptake at the new value, from the linearised solution
     for (int k = 0; newton && k < c->prm.o2_newton; ++k) {
@@ -616,7 +654,7 @@ hca_status run_phases(hca_ctx* c, unsigned mask) {
         ProfScope ps(c, KC_SETUP, kTagState);
         launch_setup_o2_newton(s, wk, c->dp, c->L, c->w, c->K, c->b_o2lin, c->c, c->b);
       }
-      st = solve(c, c->sys1, c->mg1, 1u, c->prm.cg_rtol, c->prm.cg_maxit, 1);
+      st = solve(c, c->sys1, c->mg1, 1u, solve_rtol(c), c->prm.cg_maxit, 1);
       if (st != HCA_OK) return st;
     }
   }
@@ -651,7 +689,7 @@ hca_status run_phases(hca_ctx* c, unsigned mask) {
   }
   if (mask & HCA_PH_STATS) {
     ProfScope ps(c, KC_STATS, kTagState);
-    launch_stats(s, wk, c->L, c->w, c->d_fields, c->nstat_fields, c->d_cpart, c->d_cnt);
+    launch_stats(s, wk, c->L, c->w, c->F, c->dp.nf, c->ntot, c->P, c->Vc, c->phi, c->d_cpart, c->d_cnt);
   }
   if (mask & HCA_PH_ADVANCE) {
     launch_advance(s, c->d_step);
@@ -661,7 +699,7 @@ hca_status run_phases(hca_ctx* c, unsigned mask) {
   return HCA_OK;
 }
 
-hca_status check_after(hca_ctx* c) {
+hca_status check_after(Ctx* c) {
   HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(Counters) * c->nreps, hipMemcpyDeviceToHost,
                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -733,6 +771,10 @@ hca_status validate_reps(const hca_replicate* reps, int n, std::string& msg, int
 }
 
 hca_status validate_params(const hca_params* p, std::string& msg) {
+  if (p->precision != kPrecision) {
+    msg = "precision must be 64 or 32";
+    return HCA_E_INVALID;
+  }
   const double pos[] = {p->h_um, p->dt_min, p->D_K, p->D_G, p->K1, p->G_ref[0], p->G_ref[1],
                         p->K_p53, p->J5, p->K_V, p->K_phi, p->T_cycle, p->cg_rtol, p->init_rtol};
   for (double v : pos)
@@ -844,7 +886,7 @@ int g_tile_depth = 16;
 double g_mg_tile_target = 512.0;
 
 template <typename T>
-hca_status upload(hca_ctx* c, T** p, const std::vector<T>& v) {
+hca_status upload(Ctx* c, T** p, const std::vector<T>& v) {
   HIPCHK(c, dalloc(p, v.size()));
   if (!v.empty()) HIPCHK(c, hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   return HCA_OK;
@@ -890,7 +932,7 @@ RepDev lattice_entry(const RepHost& R, long long off, int idx, std::vector<FlatB
 // for the parallelism the batch already has.  Tiles fix the order of the
 // dot-product partial sums, so a tuned context agrees with an untuned one to
 // rounding, not bit for bit.
-hca_status plan_tiles(hca_ctx* c) {
+hca_status plan_tiles(Ctx* c) {
   // width policy 0: pick_tx; 1: 16 x 16 everywhere.  Depths are even (or the
   // whole lattice), as the restriction needs even tile origins.
   auto apply_plan = [&](int depth, int policy) {
@@ -921,12 +963,12 @@ hca_status plan_tiles(hca_ctx* c) {
       t += (size_t)((H.nx + tx - 1) / tx) * (size_t)((H.ny + kBlock / tx - 1) / (kBlock / tx)) * H.nz;
     maxtiles = std::max(maxtiles, t);
   }
-  double* cb = (double*)scratch(8 * n);
+  Real* cb = (Real*)scratch(sizeof(Real) * n);
   SolverBufs tsb{};
   tsb.z32 = (float*)scratch(4 * n);   // multigrid layout (jacobi = 0)
-  tsb.p0 = (double*)scratch(8 * n);
-  tsb.p1 = (double*)scratch(8 * n);
-  tsb.q = (double*)scratch(8 * n);
+  tsb.p0 = (Real*)scratch(sizeof(Real) * n);
+  tsb.p1 = (Real*)scratch(sizeof(Real) * n);
+  tsb.q = (Real*)scratch(sizeof(Real) * n);
   tsb.partial = (double*)scratch(3 * 8 * maxtiles);
   tsb.ss = (SolveScal*)scratch(sizeof(SolveScal) * R);
   RepDev* drep = (RepDev*)scratch(sizeof(RepDev) * R);
@@ -944,7 +986,7 @@ hca_status plan_tiles(hca_ctx* c) {
       st = fail(c, HCA_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
   };
   for (void* p : {(void*)cb, (void*)tsb.p0, (void*)tsb.p1})
-    check(hipMemsetAsync(p, 0, 8 * n, c->stream));
+    check(hipMemsetAsync(p, 0, sizeof(Real) * n, c->stream));
   check(hipMemsetAsync(tsb.z32, 0, 4 * n, c->stream));
   check(hipMemsetAsync(tsb.ss, 0, sizeof(SolveScal) * R, c->stream));
   float tbest = 1e30f;
@@ -1007,7 +1049,7 @@ hca_status plan_tiles(hca_ctx* c) {
   return HCA_OK;
 }
 
-hca_status build_tables(hca_ctx* c, const hca_replicate* in) {
+hca_status build_tables(Ctx* c, const hca_replicate* in) {
   const int R = c->nreps;
   // work-item kernels: one item per workgroup unless HCA_MAX_BLOCKS caps the
   // grid (then each workgroup loops over a contiguous run of items)
@@ -1095,11 +1137,11 @@ hca_status build_tables(hca_ctx* c, const hca_replicate* in) {
   return HCA_OK;
 }
 
-hca_status alloc_all(hca_ctx* c) {
+hca_status alloc_all(Ctx* c) {
   const size_t n = (size_t)c->ntot;
   const size_t n3 = (size_t)c->dp.nf * n;   // solver arrays: nf fields
   const int nsys = c->dp.nf * c->nreps;
-  auto big = [&](double** p, size_t count) -> hca_status {
+  auto big = [&](auto** p, size_t count) -> hca_status {
     hipError_t e = dalloc(p, count);
     if (e == hipErrorOutOfMemory) return fail(c, HCA_E_NOMEM, "device memory exhausted");
     HIPCHK(c, e);
@@ -1114,8 +1156,8 @@ hca_status alloc_all(hca_ctx* c) {
   double** f1[] = {&c->w, &c->P, &c->Vc, &c->phi};
   for (double** p : f1)
     if ((st = big(p, n)) != HCA_OK) return st;
-  double** f3[] = {&c->F, &c->c, &c->b, &c->sb.r, &c->sb.p0, &c->sb.p1, &c->sb.q};
-  for (double** p : f3)
+  Real** f3[] = {&c->F, &c->c, &c->b, &c->sb.r, &c->sb.p0, &c->sb.p1, &c->sb.q};
+  for (Real** p : f3)
     if ((st = big(p, n3)) != HCA_OK) return st;
   if (c->use_mg) {
     for (float** p : {&c->sb.z32, &c->sb.r32}) {
@@ -1126,6 +1168,14 @@ hca_status alloc_all(hca_ctx* c) {
   } else if ((st = big(&c->sb.z, n3)) != HCA_OK) {
     return st;
   }
+  // every state and solver array starts at 0 (a state is imported replicate
+  // by replicate; the solver reads the whole nf x ntot arrays)
+  for (void* p : {(void*)c->w, (void*)c->P, (void*)c->Vc, (void*)c->phi})
+    HIPCHK(c, hipMemset(p, 0, sizeof(double) * n));
+  for (void* p : {(void*)c->F, (void*)c->c, (void*)c->b, (void*)c->sb.r, (void*)c->sb.p0, (void*)c->sb.p1,
+                  (void*)c->sb.q})
+    HIPCHK(c, hipMemset(p, 0, sizeof(Real) * n3));
+  HIPCHK(c, hipMemset(c->L, 0, n));
   c->K = c->F;
   c->G1 = c->F + n;
   c->G2 = c->F + 2 * n;
@@ -1149,13 +1199,7 @@ hca_status alloc_all(hca_ctx* c) {
   HIPCHK(c, dalloc(&c->d_cnt, c->nreps));
   HIPCHK(c, dalloc(&c->d_cpart, (size_t)c->work.nflat * kCounterSlots));
   HIPCHK(c, hipMemset(c->d_cnt, 0, sizeof(Counters) * c->nreps));
-  HIPCHK(c, dalloc(&c->d_fields, 8));
   HIPCHK(c, dalloc(&c->d_bad, 1));
-  const double* fl[8] = {c->K, c->G1, c->G2, c->P, c->Vc, c->phi, nullptr, nullptr};
-  c->nstat_fields = 6;
-  if (c->V) fl[c->nstat_fields++] = c->V;
-  if (c->G3) fl[c->nstat_fields++] = c->G3;
-  HIPCHK(c, hipMemcpy(c->d_fields, fl, sizeof fl, hipMemcpyHostToDevice));
   HIPCHK(c, hipHostMalloc((void**)&c->h_ss, sizeof(SolveScal) * nsys, hipHostMallocDefault));
   HIPCHK(c, hipHostMalloc((void**)&c->h_cnt, sizeof(Counters) * c->nreps, hipHostMallocDefault));
   return HCA_OK;
@@ -1164,7 +1208,7 @@ hca_status alloc_all(hca_ctx* c) {
 // ---- multigrid hierarchy -------------------------------------------------------
 
 template <typename T>
-hca_status mg_alloc(hca_ctx* c, T** p, size_t count) {
+hca_status mg_alloc(Ctx* c, T** p, size_t count) {
   hipError_t e = dalloc(p, count);
   if (e == hipErrorOutOfMemory) return fail(c, HCA_E_NOMEM, "device memory exhausted (multigrid)");
   HIPCHK(c, e);
@@ -1173,7 +1217,7 @@ hca_status mg_alloc(hca_ctx* c, T** p, size_t count) {
 }
 
 template <typename T>
-hca_status mg_upload(hca_ctx* c, T** p, const std::vector<T>& v) {
+hca_status mg_upload(Ctx* c, T** p, const std::vector<T>& v) {
   hca_status st = mg_alloc(c, p, v.size());
   if (st != HCA_OK) return st;
   if (!v.empty()) HIPCHK(c, hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
@@ -1185,7 +1229,7 @@ hca_status mg_upload(hca_ctx* c, T** p, const std::vector<T>& v) {
 // level handed to the one-workgroup coarse solve (<= mg_coarse_max cells and
 // its LDS block within the device's per-workgroup LDS); level arrays, per-level tiles, coarse-solve
 // descriptors.  mg1 is the oxygen prefix (the first nreps systems) of mg_all.
-hca_status build_mg(hca_ctx* c) {
+hca_status build_mg(Ctx* c) {
   const int R = c->nreps;
   const int S = c->dp.nf * R;
   // LDS of one workgroup: the coarse solve's levels must fit (160 KiB on gfx950)
@@ -1378,15 +1422,15 @@ hca_status build_mg(hca_ctx* c) {
 // Algorithm 1, steady oxygen: Picard on the uptake coefficient, each iterate
 // one CG solve of the oxygen systems; stops when the nonlinear residual of the
 // current iterate (the solve's initial residual) is below init_rtol ||b||.
-hca_status steady_oxygen(hca_ctx* c) {
+hca_status steady_oxygen(Ctx* c) {
   const Work& wk = c->work;
-  std::vector<double> k0((size_t)c->ntot, c->prm.K0);
-  HIPCHK(c, hipMemcpyAsync(c->K, k0.data(), k0.size() * sizeof(double), hipMemcpyHostToDevice,
+  std::vector<Real> k0((size_t)c->ntot, (Real)c->prm.K0);
+  HIPCHK(c, hipMemcpyAsync(c->K, k0.data(), k0.size() * sizeof(Real), hipMemcpyHostToDevice,
                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (int m = 0; m < c->prm.init_maxit; ++m) {
     launch_setup_o2(c->stream, wk, c->dp, c->L, c->w, c->K, c->c, c->b, 1);
-    launch_cg_start(c->stream, c->sys1, c->prm.init_rtol, c->prm.cg_maxit, c->c, c->b, c->F,
+    launch_cg_start(c->stream, c->sys1, std::max(c->prm.init_rtol, kRtolFloor), c->prm.cg_maxit, c->c, c->b, c->F,
                     c->sb, 1u, c->nreps);
     HIPCHK(c, hipMemcpyAsync(c->h_ss, c->sb.ss, sizeof(SolveScal) * c->nreps,
                              hipMemcpyDeviceToHost, c->stream));
@@ -1397,18 +1441,18 @@ hca_status steady_oxygen(hca_ctx* c) {
       c->picard_iters = m;
       return HCA_OK;
     }
-    hca_status st = solve(c, c->sys1, c->mg1, 1u, c->prm.cg_rtol, c->prm.cg_maxit, 1);
+    hca_status st = solve(c, c->sys1, c->mg1, 1u, solve_rtol(c), c->prm.cg_maxit, 1);
     if (st != HCA_OK) return st;
   }
   return fail(c, HCA_E_NOCONV, "steady oxygen Picard iteration did not converge");
 }
 
-void free_all(hca_ctx* c) {
+void free_all(Ctx* c) {
   void* bufs[] = {c->L, c->code, c->win, (void*)c->ca_list.cells, (void*)c->ca_list.item_n, c->w, c->P, c->Vc, c->phi, c->F, c->c, c->b,
                   c->sb.r, c->sb.z, (void*)c->sb.z32, (void*)c->sb.r32, c->sb.p0, c->sb.p1, c->sb.q, c->sb.dinv, c->sb.partial,
                   c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->b_o2lin, c->Fprev, c->d_step,
                   c->d_reps, c->d_flat, c->d_tiles, c->d_sys, c->d_sflat, c->d_stiles, c->d_cnt, (void*)c->d_cpart,
-                  (void*)c->d_fields, c->d_bad, c->d_theta, (void*)c->d_pack, (void*)c->d_gelu, c->before,
+                  c->d_bad, c->d_theta, (void*)c->d_pack, (void*)c->d_gelu, c->before,
                   c->item_cnt, c->item_off};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
@@ -1428,7 +1472,58 @@ void free_all(hca_ctx* c) {
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
 }
 
-void* field_ptr(hca_ctx* c, hca_field f, size_t& elem) {
+// n stored field values (device, Real) out as FP64 into dst (host or device).
+template <typename R>
+hca_status field_out(Ctx* c, const R* src, size_t n, void* dst, int dst_is_device) {
+  if constexpr (sizeof(R) == sizeof(double)) {
+    HIPCHK(c, hipMemcpyAsync(dst, src, sizeof(double) * n,
+                             dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  } else if (dst_is_device) {
+    launch_convert(c->stream, src, static_cast<double*>(dst), (long long)n);
+    HIPCHK(c, hipGetLastError());
+  } else {
+    std::vector<R> tmp(n);
+    HIPCHK(c, hipMemcpyAsync(tmp.data(), src, sizeof(R) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<double> d(tmp.begin(), tmp.end());
+    memcpy(dst, d.data(), sizeof(double) * n);
+  }
+  return HCA_OK;
+}
+
+// n FP64 values (host or device) into stored field values (device, Real),
+// rounded to Real.  Returns after the copy has completed.
+template <typename R>
+hca_status field_in(Ctx* c, const void* src, size_t n, int src_is_device, R* dst) {
+  if constexpr (sizeof(R) == sizeof(double)) {
+    HIPCHK(c, hipMemcpyAsync(dst, src, sizeof(double) * n,
+                             src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  } else if (src_is_device) {
+    launch_convert(c->stream, static_cast<const double*>(src), dst, (long long)n);
+    HIPCHK(c, hipGetLastError());
+  } else {
+    std::vector<double> d(n);
+    memcpy(d.data(), src, sizeof(double) * n);
+    std::vector<R> tmp(d.begin(), d.end());
+    HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), sizeof(R) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return HCA_OK;
+}
+
+// A solved field (stored as Real) or nullptr.
+Real* real_field(Ctx* c, hca_field f) {
+  switch (f) {
+    case HCA_F_O2: return c->K;
+    case HCA_F_DRUG1: return c->G1;
+    case HCA_F_DRUG2: return c->G2;
+    case HCA_F_VEGF: return c->V;
+    case HCA_F_DRUG3: return c->G3;
+    default: return nullptr;
+  }
+}
+
+void* field_ptr(Ctx* c, hca_field f, size_t& elem) {
   elem = 8;
   switch (f) {
     case HCA_F_O2: return c->K;
@@ -1445,11 +1540,242 @@ void* field_ptr(hca_ctx* c, hca_field f, size_t& elem) {
   return nullptr;
 }
 
+// ---- checkpoint / resume ---------------------------------------------------------
+//
+// State blob of one replicate (host or device memory, little-endian):
+//   header (StateHeader, 96 bytes)
+//   L     uint8 cell map, n bytes, padded to a multiple of 8
+//   w     FP64 vessel map, n
+//   F     FP64 solved fields in solver order K, G1, G2 (G3 with drug3, V with
+//         vegf), nf x n
+//   cells FP64 P, Vc, phi, 3 x n
+//   Fprev FP64 each solved field at its previous solve (the initial-guess
+//         history), nf x n, present with flag bit 2
+// n = nx ny nz, arrays x-fastest as everywhere.
+
+constexpr uint64_t kStateMagic = 0x4554415453414348ull;   // "HCASTATE"
+constexpr uint32_t kStateVersion = 1;
+constexpr uint32_t kStateVegf = 1u, kStateDrug3 = 2u, kStatePrev = 4u;
+
+struct StateHeader {
+  uint64_t magic;
+  uint32_t version, flags;
+  int32_t nx, ny, nz, nf;
+  int64_t step;
+  uint64_t seed;
+  int64_t total_divisions, total_kills, total_births, total_deaths;
+  uint64_t reserved[2];
+};
+static_assert(sizeof(StateHeader) == 96, "state header layout");
+
+struct StateLayout {
+  StateHeader hdr;
+  size_t n, off_L, off_w, off_F, off_cell, off_prev, bytes;
+};
+
+StateLayout state_layout(const StateHeader& h) {
+  StateLayout l;
+  l.hdr = h;
+  l.n = (size_t)h.nx * h.ny * h.nz;
+  l.off_L = sizeof(StateHeader);
+  l.off_w = l.off_L + (l.n + 7) / 8 * 8;
+  l.off_F = l.off_w + 8 * l.n;
+  l.off_cell = l.off_F + 8 * (size_t)h.nf * l.n;
+  l.off_prev = l.off_cell + 24 * l.n;
+  l.bytes = l.off_prev + ((h.flags & kStatePrev) ? 8 * (size_t)h.nf * l.n : 0);
+  return l;
+}
+
+StateHeader context_header(const Ctx* c, int rep) {
+  StateHeader h{};
+  const RepHost& R = c->reps[rep];
+  h.magic = kStateMagic;
+  h.version = kStateVersion;
+  h.flags = (c->dp.vegf ? kStateVegf : 0u) | (c->dp.drug3 ? kStateDrug3 : 0u) |
+            (c->Fprev ? kStatePrev : 0u);
+  h.nx = R.nx;
+  h.ny = R.ny;
+  h.nz = R.nz;
+  h.nf = c->dp.nf;
+  h.step = c->step;
+  h.seed = R.seed;
+  return h;
+}
+
+// Header checks against a replicate's lattice and seed; msg names the problem.
+hca_status check_header(const StateHeader& h, size_t bytes, int nx, int ny, int nz, uint64_t seed,
+                        StateLayout& lay, std::string& msg) {
+  if (bytes < sizeof(StateHeader)) {
+    msg = "state buffer shorter than its header";
+    return HCA_E_RANGE;
+  }
+  if (h.magic != kStateMagic || h.version != kStateVersion) {
+    msg = "not a state blob of this library version";
+    return HCA_E_INVALID;
+  }
+  if (h.nx != nx || h.ny != ny || h.nz != nz || h.nf < 3 || h.nf > 5) {
+    msg = "state lattice differs from the replicate's";
+    return HCA_E_INVALID;
+  }
+  if (h.seed != seed) {
+    msg = "state seed differs from the replicate's";
+    return HCA_E_INVALID;
+  }
+  if (h.step < 0) {
+    msg = "negative step index";
+    return HCA_E_INVALID;
+  }
+  lay = state_layout(h);
+  if (bytes < lay.bytes) {
+    msg = "state buffer shorter than its arrays";
+    return HCA_E_RANGE;
+  }
+  return HCA_OK;
+}
+
+hca_status parse_state_host(const void* src, size_t bytes, const hca_replicate& R, StateLayout& lay,
+                            std::string& msg) {
+  if (!src) {
+    msg = "null state";
+    return HCA_E_INVALID;
+  }
+  StateHeader h{};
+  if (bytes >= sizeof h) memcpy(&h, src, sizeof h);
+  return check_header(h, bytes, R.nx, R.ny, R.nz, R.seed, lay, msg);
+}
+
+hca_status export_state(Ctx* c, int rep, void* dst, size_t dst_bytes, int dst_is_device) {
+  const RepHost& R = c->reps[rep];
+  const StateLayout lay = state_layout(context_header(c, rep));
+  if (dst_bytes < lay.bytes) return fail(c, HCA_E_RANGE, "state buffer too small");
+  StateHeader h = lay.hdr;
+  HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(Counters) * c->nreps, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  h.total_divisions = (int64_t)c->h_cnt[rep].total_divisions;
+  h.total_kills = (int64_t)c->h_cnt[rep].total_kills;
+  h.total_births = (int64_t)c->h_cnt[rep].total_births;
+  h.total_deaths = (int64_t)c->h_cnt[rep].total_deaths;
+  char* d = static_cast<char*>(dst);
+  const hipMemcpyKind out = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  const size_t n = lay.n;
+  HIPCHK(c, hipMemcpyAsync(d, &h, sizeof h, dst_is_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost,
+                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(d + lay.off_L, c->L + R.off, n, out, c->stream));
+  HIPCHK(c, hipMemcpyAsync(d + lay.off_w, c->w + R.off, 8 * n, out, c->stream));
+  hca_status st;
+  for (int f = 0; f < c->dp.nf; ++f)
+    if ((st = field_out(c, c->F + (size_t)f * c->ntot + R.off, n, d + lay.off_F + 8 * n * f,
+                        dst_is_device)) != HCA_OK)
+      return st;
+  const double* cell[3] = {c->P, c->Vc, c->phi};
+  for (int k = 0; k < 3; ++k)
+    HIPCHK(c, hipMemcpyAsync(d + lay.off_cell + 8 * n * k, cell[k] + R.off, 8 * n, out, c->stream));
+  if (c->Fprev)
+    for (int f = 0; f < c->dp.nf; ++f)
+      if ((st = field_out(c, c->Fprev + (size_t)f * c->ntot + R.off, n, d + lay.off_prev + 8 * n * f,
+                          dst_is_device)) != HCA_OK)
+        return st;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return HCA_OK;
+}
+
+// check = false: leave the census and the non-finite check to the caller
+// (a resume imports every replicate first: until then the others hold no state)
+hca_status import_state(Ctx* c, int rep, const void* src, size_t src_bytes, int src_is_device,
+                        bool check = true) {
+  const RepHost& R = c->reps[rep];
+  StateHeader h{};
+  if (src_bytes >= sizeof h) {
+    HIPCHK(c, hipMemcpyAsync(&h, src, sizeof h, src_is_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  StateLayout lay;
+  std::string msg;
+  hca_status st = check_header(h, src_bytes, R.nx, R.ny, R.nz, R.seed, lay, msg);
+  if (st == HCA_OK && (h.nf != c->dp.nf || ((h.flags & kStateVegf) != 0) != (c->dp.vegf != 0) ||
+                       ((h.flags & kStateDrug3) != 0) != (c->dp.drug3 != 0))) {
+    msg = "state fields (third drug, VEGF) differ from the context's options";
+    st = HCA_E_INVALID;
+  }
+  if (st == HCA_OK && c->nreps > 1 && h.step != c->step) {
+    msg = "state step differs from the context's (a context advances its replicates together)";
+    st = HCA_E_INVALID;
+  }
+  if (st != HCA_OK) {
+    c->err = msg;
+    return st;
+  }
+  const char* s = static_cast<const char*>(src);
+  const hipMemcpyKind in = src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  const size_t n = lay.n;
+  // the maps staged in the proposal buffer and the right-hand side (both
+  // rewritten before their next use) and validated together
+  double* wstage = reinterpret_cast<double*>(c->b);   // nf x ntot Real values: room for ntot doubles
+  HIPCHK(c, hipMemcpyAsync(c->code + R.off, s + lay.off_L, n, in, c->stream));
+  HIPCHK(c, hipMemcpyAsync(wstage + R.off, s + lay.off_w, 8 * n, in, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_bad, 0, sizeof(unsigned long long), c->stream));
+  launch_validate_cells(c->stream, c->work, c->code, wstage, rep, c->d_bad);
+  unsigned long long bad = 0;
+  HIPCHK(c, hipMemcpyAsync(&bad, c->d_bad, sizeof bad, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (bad) {
+    c->err = "state cell map has codes outside {0,1,2}, cells on vessel voxels or bad weights";
+    return HCA_E_INVALID;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->L + R.off, c->code + R.off, n, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->w + R.off, wstage + R.off, 8 * n, hipMemcpyDeviceToDevice, c->stream));
+  for (int f = 0; f < c->dp.nf; ++f)
+    if ((st = field_in(c, s + lay.off_F + 8 * n * f, n, src_is_device, c->F + (size_t)f * c->ntot + R.off)) !=
+        HCA_OK)
+      return st;
+  double* cell[3] = {c->P, c->Vc, c->phi};
+  for (int k = 0; k < 3; ++k)
+    HIPCHK(c, hipMemcpyAsync(cell[k] + R.off, s + lay.off_cell + 8 * n * k, 8 * n, in, c->stream));
+  if (c->Fprev)
+    for (int f = 0; f < c->dp.nf; ++f) {
+      Real* dstp = c->Fprev + (size_t)f * c->ntot + R.off;
+      if (h.flags & kStatePrev) {
+        if ((st = field_in(c, s + lay.off_prev + 8 * n * f, n, src_is_device, dstp)) != HCA_OK) return st;
+      } else {   // no history saved: the extrapolation restarts from the state
+        HIPCHK(c, hipMemcpyAsync(dstp, c->F + (size_t)f * c->ntot + R.off, sizeof(Real) * n,
+                                 hipMemcpyDeviceToDevice, c->stream));
+      }
+    }
+  // cumulative counts of the replicate; the last step's events restart at 0
+  HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(Counters) * c->nreps, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  Counters k = c->h_cnt[rep];
+  k.committed = k.kills = k.divisions = k.nospace = k.lost = 0;
+  k.births = k.deaths = 0;
+  k.total_divisions = (unsigned long long)h.total_divisions;
+  k.total_kills = (unsigned long long)h.total_kills;
+  k.total_births = (unsigned long long)h.total_births;
+  k.total_deaths = (unsigned long long)h.total_deaths;
+  HIPCHK(c, hipMemcpyAsync(c->d_cnt + rep, &k, sizeof k, hipMemcpyHostToDevice, c->stream));
+  if (h.step != c->step) {
+    long long st64 = h.step;
+    HIPCHK(c, hipMemcpyAsync(c->d_step, &st64, sizeof st64, hipMemcpyHostToDevice, c->stream));
+    c->step = h.step;
+  }
+  if (!check) return HCA_OK;
+  launch_stats(c->stream, c->work, c->L, c->w, c->F, c->dp.nf, c->ntot, c->P, c->Vc, c->phi,
+               c->d_cpart, c->d_cnt);
+  HIPCHK(c, hipGetLastError());
+  return check_after(c);
+}
+
+hca_status init_impl(::hca_ctx** out, const hca_params* p, const hca_replicate* reps, int n_reps,
+                     void* stream, const void* const* states, const size_t* state_bytes,
+                     int states_on_device);
+
 }  // namespace
 
-extern "C" {
 
-hca_status hca_default_params(hca_params* out) {
+#if HCA_RT_PRIMARY
+extern "C" hca_status hca_default_params(hca_params* out) {
   if (!out) return HCA_E_INVALID;
   memset(out, 0, sizeof *out);
   out->h_um = 20.0;
@@ -1515,11 +1841,78 @@ hca_status hca_default_params(hca_params* out) {
   out->G_ref3 = 1.0;
   out->b_int3 = 1;
   out->x0_extrapolate = 2;
+  out->precision = 64;
   return HCA_OK;
 }
+#endif
 
-hca_status hca_init(hca_ctx** out, const hca_params* p, const hca_replicate* reps, int n_reps,
+hca_status api_init(::hca_ctx** out, const hca_params* p, const hca_replicate* reps, int n_reps,
                     void* stream) {
+  if constexpr (sizeof(Real) == sizeof(double)) {
+    return init_impl(out, p, reps, n_reps, stream, nullptr, nullptr, 0);
+  } else {
+    // precision 32: Algorithm 1's initialisation (the steady oxygen, whose
+    // operator amplifies residuals ~1e4-fold) in FP64, then the state rounded
+    // to FP32 through device-resident state blobs
+    if (!out || !p || !reps || n_reps < 1) return HCA_E_INVALID;
+    *out = nullptr;
+    hca_params p64 = *p;
+    p64.precision = 64;
+    ::hca_ctx* c64 = nullptr;
+    hca_status st = hca::rt64::api_init(&c64, &p64, reps, n_reps, stream);
+    if (st != HCA_OK) return st;
+    std::vector<void*> blobs((size_t)n_reps, nullptr);
+    std::vector<size_t> bytes((size_t)n_reps, 0);
+    for (int r = 0; r < n_reps && st == HCA_OK; ++r) {
+      st = hca::rt64::api_state_bytes(c64, r, &bytes[r]);
+      if (st == HCA_OK && hipMalloc(&blobs[r], bytes[r]) != hipSuccess) st = HCA_E_NOMEM;
+      if (st == HCA_OK) st = hca::rt64::api_export_state(c64, r, blobs[r], bytes[r], 1);
+    }
+    hca::rt64::api_destroy(c64);
+    if (st == HCA_OK) st = init_impl(out, p, reps, n_reps, stream, blobs.data(), bytes.data(), 1);
+    for (void* b : blobs)
+      if (b) (void)hipFree(b);
+    return st;
+  }
+}
+
+hca_status api_init_from_state(::hca_ctx** out, const hca_params* p, const hca_replicate* reps,
+                               const void* const* states, const size_t* state_bytes, int n_reps,
+                               void* stream) {
+  if (!out || !p || !reps || !states || !state_bytes || n_reps < 1) return HCA_E_INVALID;
+  *out = nullptr;
+  // the cell and vessel maps come from the states (validated with the
+  // replicates' dose lists before anything is allocated)
+  std::vector<hca_replicate> rr(reps, reps + n_reps);
+  int64_t step0 = -1;
+  for (int r = 0; r < n_reps; ++r) {
+    StateLayout lay;
+    std::string msg;
+    const hca_status st = parse_state_host(states[r], state_bytes[r], reps[r], lay, msg);
+    if (st != HCA_OK) {
+      fprintf(stderr, "hca_init_from_state: replicate %d: %s\n", r, msg.c_str());
+      return st;
+    }
+    if (step0 >= 0 && lay.hdr.step != step0) {
+      fprintf(stderr, "hca_init_from_state: replicate %d is at step %lld, replicate 0 at %lld "
+                      "(a context advances its replicates together)\n",
+              r, (long long)lay.hdr.step, (long long)step0);
+      return HCA_E_INVALID;
+    }
+    step0 = lay.hdr.step;
+    const char* base = static_cast<const char*>(states[r]);
+    rr[r].cell = reinterpret_cast<const uint8_t*>(base + lay.off_L);
+    rr[r].vessel_w = reinterpret_cast<const double*>(base + lay.off_w);
+  }
+  return init_impl(out, p, rr.data(), n_reps, stream, states, state_bytes, 0);
+}
+
+
+namespace {
+
+hca_status init_impl(::hca_ctx** out, const hca_params* p, const hca_replicate* reps, int n_reps,
+                     void* stream, const void* const* states, const size_t* state_bytes,
+                     int states_on_device) {
   if (!out || !p || !reps || n_reps < 1) return HCA_E_INVALID;
   *out = nullptr;
   std::string msg;
@@ -1531,11 +1924,11 @@ hca_status hca_init(hca_ctx** out, const hca_params* p, const hca_replicate* rep
     fprintf(stderr, "hca_init: %s\n", msg.c_str());
     return st;
   }
-  if (singular >= 0) {
+  if (singular >= 0 && !states) {
     fprintf(stderr, "hca_init: replicate %d has no vessel: steady oxygen is zero\n", singular);
     return HCA_E_SINGULAR;
   }
-  hca_ctx* c = new (std::nothrow) hca_ctx();
+  Ctx* c = new (std::nothrow) Ctx();
   if (!c) return HCA_E_NOMEM;
   c->prm = *p;
   c->dp = make_dev_params(*p);
@@ -1597,20 +1990,46 @@ hca_status hca_init(hca_ctx** out, const hca_params* p, const hca_replicate* rep
   long long zero = 0;
   if (hipMemcpy(c->d_step, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess)
     return bail(HCA_E_DEVICE);
+  if (states) {   // resume: every replicate's state from its blob (all at one step)
+    StateHeader h0{};
+    if (states_on_device) {
+      if (hipMemcpy(&h0, states[0], sizeof h0, hipMemcpyDeviceToHost) != hipSuccess) return bail(HCA_E_DEVICE);
+    } else {
+      memcpy(&h0, states[0], sizeof h0);
+    }
+    long long s0 = h0.step;
+    if (hipMemcpy(c->d_step, &s0, sizeof s0, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(HCA_E_DEVICE);
+    c->step = h0.step;
+    launch_zero_counters(c->stream, c->d_cnt, n_reps, 1);
+    launch_zero_counters(c->stream, c->d_cnt, n_reps, 0);
+    for (int r = 0; r < n_reps; ++r)
+      if ((st = import_state(c, r, states[r], state_bytes[r], states_on_device, false)) != HCA_OK)
+        return bail(st);
+    launch_stats(c->stream, c->work, c->L, c->w, c->F, c->dp.nf, c->ntot, c->P, c->Vc, c->phi,
+                 c->d_cpart, c->d_cnt);
+    if (hipGetLastError() != hipSuccess) return bail(HCA_E_DEVICE);
+    if ((st = check_after(c)) != HCA_OK) return bail(st);
+    c->last_it[0] = 0;
+    for (int k = 0; k < KC_COUNT; ++k) c->prof_ms[k] = c->prof_n[k] = c->prof_bytes[k] = 0;
+    *out = c;
+    return HCA_OK;
+  }
   if ((st = steady_oxygen(c)) != HCA_OK) return bail(st);
   launch_init_cells(c->stream, c->work, c->dp, c->L, c->K, c->P, c->Vc, c->phi);
-  if (hipMemsetAsync(c->G1, 0, (size_t)c->ntot * 16, c->stream) != hipSuccess)   // G1 and G2
+  if (hipMemsetAsync(c->G1, 0, (size_t)c->ntot * 2 * sizeof(Real), c->stream) != hipSuccess)   // G1 and G2
     return bail(HCA_E_DEVICE);
-  if (c->V && hipMemsetAsync(c->V, 0, (size_t)c->ntot * 8, c->stream) != hipSuccess)
+  if (c->V && hipMemsetAsync(c->V, 0, (size_t)c->ntot * sizeof(Real), c->stream) != hipSuccess)
     return bail(HCA_E_DEVICE);
-  if (c->G3 && hipMemsetAsync(c->G3, 0, (size_t)c->ntot * 8, c->stream) != hipSuccess)
+  if (c->G3 && hipMemsetAsync(c->G3, 0, (size_t)c->ntot * sizeof(Real), c->stream) != hipSuccess)
     return bail(HCA_E_DEVICE);
-  if (c->Fprev && hipMemcpyAsync(c->Fprev, c->F, (size_t)c->dp.nf * c->ntot * 8, hipMemcpyDeviceToDevice,
+  if (c->Fprev && hipMemcpyAsync(c->Fprev, c->F, (size_t)c->dp.nf * c->ntot * sizeof(Real), hipMemcpyDeviceToDevice,
                                  c->stream) != hipSuccess)
     return bail(HCA_E_DEVICE);
   launch_zero_counters(c->stream, c->d_cnt, n_reps, 1);
   launch_zero_counters(c->stream, c->d_cnt, n_reps, 0);
-  launch_stats(c->stream, c->work, c->L, c->w, c->d_fields, c->nstat_fields, c->d_cpart, c->d_cnt);
+  launch_stats(c->stream, c->work, c->L, c->w, c->F, c->dp.nf, c->ntot, c->P, c->Vc, c->phi,
+               c->d_cpart, c->d_cnt);
   if (hipGetLastError() != hipSuccess) return bail(HCA_E_DEVICE);
   if ((st = check_after(c)) != HCA_OK) return bail(st);
   c->last_it[0] = 0;
@@ -1619,7 +2038,11 @@ hca_status hca_init(hca_ctx** out, const hca_params* p, const hca_replicate* rep
   return HCA_OK;
 }
 
-hca_status hca_run_phases(hca_ctx* c, unsigned mask) {
+}  // namespace
+
+
+hca_status api_run_phases(::hca_ctx* c_, unsigned mask) {
+  Ctx* c = static_cast<Ctx*>(c_);
   if (!c) return HCA_E_INVALID;
   if (c->failed) return HCA_E_INVALID;
   hca_status st = run_phases(c, mask);
@@ -1627,7 +2050,8 @@ hca_status hca_run_phases(hca_ctx* c, unsigned mask) {
   return check_after(c);
 }
 
-hca_status hca_step(hca_ctx* c, int n_steps) {
+hca_status api_step(::hca_ctx* c_, int n_steps) {
+  Ctx* c = static_cast<Ctx*>(c_);
   if (!c || n_steps < 0) return HCA_E_INVALID;
   if (c->failed) return HCA_E_INVALID;
   for (int k = 0; k < n_steps; ++k) {
@@ -1637,8 +2061,9 @@ hca_status hca_step(hca_ctx* c, int n_steps) {
   return check_after(c);
 }
 
-hca_status hca_fields(hca_ctx* c, int rep, hca_field f, void* dst, size_t dst_bytes,
+hca_status api_fields(::hca_ctx* c_, int rep, hca_field f, void* dst, size_t dst_bytes,
                       int dst_is_device) {
+  Ctx* c = static_cast<Ctx*>(c_);
   if (!c || !dst) return HCA_E_INVALID;
   if (rep < 0 || rep >= c->nreps) return fail(c, HCA_E_RANGE, "replicate index out of range");
   size_t elem = 0;
@@ -1647,6 +2072,12 @@ hca_status hca_fields(hca_ctx* c, int rep, hca_field f, void* dst, size_t dst_by
   const RepHost& R = c->reps[rep];
   const size_t bytes = (size_t)R.n * elem;
   if (dst_bytes < bytes) return fail(c, HCA_E_RANGE, "destination buffer too small");
+  if (Real* rf = real_field(c, f)) {   // stored as Real, delivered as FP64
+    hca_status st = field_out(c, rf + R.off, (size_t)R.n, dst, dst_is_device);
+    if (st != HCA_OK) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return HCA_OK;
+  }
   HIPCHK(c, hipMemcpyAsync(dst, src + (size_t)R.off * elem, bytes,
                            dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                            c->stream));
@@ -1654,8 +2085,9 @@ hca_status hca_fields(hca_ctx* c, int rep, hca_field f, void* dst, size_t dst_by
   return HCA_OK;
 }
 
-hca_status hca_set_field(hca_ctx* c, int rep, hca_field f, const void* src, size_t src_bytes,
+hca_status api_set_field(::hca_ctx* c_, int rep, hca_field f, const void* src, size_t src_bytes,
                          int src_is_device) {
+  Ctx* c = static_cast<Ctx*>(c_);
   if (!c || !src) return HCA_E_INVALID;
   if (rep < 0 || rep >= c->nreps) return fail(c, HCA_E_RANGE, "replicate index out of range");
   size_t elem = 0;
@@ -1682,7 +2114,7 @@ hca_status hca_set_field(hca_ctx* c, int rep, hca_field f, const void* src, size
   } else if (f == HCA_F_VESSEL_W) {
     // stage in the solver's right-hand side (rewritten by every setup) and
     // validate against the current cell map
-    double* stage = c->b;
+    double* stage = reinterpret_cast<double*>(c->b);   // nf x ntot Real values: room for ntot doubles
     HIPCHK(c, hipMemcpyAsync(stage + R.off, src, bytes, kind, c->stream));
     HIPCHK(c, hipMemsetAsync(c->d_bad, 0, sizeof(unsigned long long), c->stream));
     launch_validate_cells(c->stream, c->work, c->L, stage, rep, c->d_bad);
@@ -1695,20 +2127,24 @@ hca_status hca_set_field(hca_ctx* c, int rep, hca_field f, const void* src, size
     }
     HIPCHK(c, hipMemcpyAsync(dst + (size_t)R.off * elem, stage + R.off, bytes, hipMemcpyDeviceToDevice,
                              c->stream));
+  } else if (Real* rf = real_field(c, f)) {   // FP64 in, stored as Real
+    hca_status st = field_in(c, src, (size_t)R.n, src_is_device, rf + R.off);
+    if (st != HCA_OK) return st;
+    // a solved field restarts its extrapolation from the new value
+    if (c->Fprev) {
+      const size_t off = (size_t)(rf - c->F) + (size_t)R.off;
+      HIPCHK(c, hipMemcpyAsync(c->Fprev + off, c->F + off, sizeof(Real) * (size_t)R.n,
+                               hipMemcpyDeviceToDevice, c->stream));
+    }
   } else {
     HIPCHK(c, hipMemcpyAsync(dst + (size_t)R.off * elem, src, bytes, kind, c->stream));
-    // a solved field restarts its extrapolation from the new value
-    const double* fd = (const double*)dst;
-    if (c->Fprev && fd >= c->F && fd < c->F + (size_t)c->dp.nf * c->ntot) {
-      const size_t off = (size_t)(fd - c->F) + (size_t)R.off;
-      HIPCHK(c, hipMemcpyAsync(c->Fprev + off, c->F + off, bytes, hipMemcpyDeviceToDevice, c->stream));
-    }
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return HCA_OK;
 }
 
-hca_status hca_set_step(hca_ctx* c, int64_t step) {
+hca_status api_set_step(::hca_ctx* c_, int64_t step) {
+  Ctx* c = static_cast<Ctx*>(c_);
   if (!c || step < 0) return HCA_E_INVALID;
   long long s = step;
   HIPCHK(c, hipMemcpyAsync(c->d_step, &s, sizeof s, hipMemcpyHostToDevice, c->stream));
@@ -1717,7 +2153,30 @@ hca_status hca_set_step(hca_ctx* c, int64_t step) {
   return HCA_OK;
 }
 
-hca_status hca_stats(hca_ctx* c, int rep, hca_stats_t* out) {
+hca_status api_state_bytes(::hca_ctx* c_, int rep, size_t* bytes) {
+  Ctx* c = static_cast<Ctx*>(c_);
+  if (!c || !bytes) return HCA_E_INVALID;
+  if (rep < 0 || rep >= c->nreps) return fail(c, HCA_E_RANGE, "replicate index out of range");
+  *bytes = state_layout(context_header(c, rep)).bytes;
+  return HCA_OK;
+}
+
+hca_status api_export_state(::hca_ctx* c_, int rep, void* dst, size_t dst_bytes, int dst_is_device) {
+  Ctx* c = static_cast<Ctx*>(c_);
+  if (!c || !dst) return HCA_E_INVALID;
+  if (rep < 0 || rep >= c->nreps) return fail(c, HCA_E_RANGE, "replicate index out of range");
+  return export_state(c, rep, dst, dst_bytes, dst_is_device);
+}
+
+hca_status api_import_state(::hca_ctx* c_, int rep, const void* src, size_t src_bytes, int src_is_device) {
+  Ctx* c = static_cast<Ctx*>(c_);
+  if (!c || !src) return HCA_E_INVALID;
+  if (rep < 0 || rep >= c->nreps) return fail(c, HCA_E_RANGE, "replicate index out of range");
+  return import_state(c, rep, src, src_bytes, src_is_device);
+}
+
+hca_status api_stats(::hca_ctx* c_, int rep, hca_stats_t* out) {
+  Ctx* c = static_cast<Ctx*>(c_);
   if (!c || !out) return HCA_E_INVALID;
   if (rep < 0 || rep >= c->nreps) return fail(c, HCA_E_RANGE, "replicate index out of range");
   HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(Counters) * c->nreps, hipMemcpyDeviceToHost,
@@ -1764,15 +2223,18 @@ hca_status hca_stats(hca_ctx* c, int rep, hca_stats_t* out) {
   return HCA_OK;
 }
 
-int hca_num_kernels(void) { return KC_COUNT; }
+#if HCA_RT_PRIMARY
+extern "C" int hca_num_kernels(void) { return KC_COUNT; }
 
-const char* hca_kernel_name(int kernel) {
+extern "C" const char* hca_kernel_name(int kernel) {
   if (kernel < 0 || kernel >= KC_COUNT) return "";
   return kKernelNames[kernel];
 }
+#endif
 
-hca_status hca_kernel_time(hca_ctx* c, int kernel, double* ms, int64_t* launches,
+hca_status api_kernel_time(::hca_ctx* c_, int kernel, double* ms, int64_t* launches,
                            double* bytes_per_launch) {
+  Ctx* c = static_cast<Ctx*>(c_);
   if (!c || kernel < 0 || kernel >= KC_COUNT) return HCA_E_INVALID;
   prof_flush(c, nullptr, 0);
   if (ms) *ms = c->prof_ms[kernel];
@@ -1782,14 +2244,23 @@ hca_status hca_kernel_time(hca_ctx* c, int kernel, double* ms, int64_t* launches
   return HCA_OK;
 }
 
-hca_status hca_reset_kernel_time(hca_ctx* c) {
+hca_status api_set_profile(::hca_ctx* c_, int profile) {
+  Ctx* c = static_cast<Ctx*>(c_);
+  if (!c || profile < 0 || profile >= KC_COUNT + 2) return HCA_E_INVALID;
+  c->prm.profile = profile;
+  return HCA_OK;
+}
+
+hca_status api_reset_kernel_time(::hca_ctx* c_) {
+  Ctx* c = static_cast<Ctx*>(c_);
   if (!c) return HCA_E_INVALID;
   prof_flush(c, nullptr, 0);
   for (int k = 0; k < KC_COUNT; ++k) c->prof_ms[k] = c->prof_n[k] = c->prof_bytes[k] = 0;
   return HCA_OK;
 }
 
-hca_status hca_tile_shape(hca_ctx* c, int rep, int32_t* tx, int32_t* ty, int32_t* tz) {
+hca_status api_tile_shape(::hca_ctx* c_, int rep, int32_t* tx, int32_t* ty, int32_t* tz) {
+  Ctx* c = static_cast<Ctx*>(c_);
   if (!c || !tx || !ty || !tz) return HCA_E_INVALID;
   if (rep < 0 || rep >= c->nreps) return fail(c, HCA_E_RANGE, "replicate index out of range");
   *tx = c->reps[rep].tx;
@@ -1798,7 +2269,8 @@ hca_status hca_tile_shape(hca_ctx* c, int rep, int32_t* tx, int32_t* ty, int32_t
   return HCA_OK;
 }
 
-hca_status hca_set_surrogate(hca_ctx* c, const hca_mlp* net, double margin) {
+hca_status api_set_surrogate(::hca_ctx* c_, const hca_mlp* net, double margin) {
+  Ctx* c = static_cast<Ctx*>(c_);
   if (!c) return HCA_E_INVALID;
   if (!net) {
     c->sur_on = false;
@@ -1850,7 +2322,8 @@ hca_status hca_set_surrogate(hca_ctx* c, const hca_mlp* net, double margin) {
   return HCA_OK;
 }
 
-hca_status hca_harvest_step(hca_ctx* c, float* X, float* Y, int64_t cap_rows, int64_t* n_rows) {
+hca_status api_harvest_step(::hca_ctx* c_, float* X, float* Y, int64_t cap_rows, int64_t* n_rows) {
+  Ctx* c = static_cast<Ctx*>(c_);
   if (!c || !X || !Y || !n_rows || cap_rows < 0) return HCA_E_INVALID;
   if (c->failed) return HCA_E_INVALID;
   *n_rows = 0;
@@ -1885,19 +2358,25 @@ hca_status hca_harvest_step(hca_ctx* c, float* X, float* Y, int64_t cap_rows, in
   return HCA_OK;
 }
 
-hca_status hca_synchronize(hca_ctx* c) {
+hca_status api_synchronize(::hca_ctx* c_) {
+  Ctx* c = static_cast<Ctx*>(c_);
   if (!c) return HCA_E_INVALID;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return HCA_OK;
 }
 
-const char* hca_last_error(const hca_ctx* c) { return c ? c->err.c_str() : ""; }
+const char* api_last_error(const ::hca_ctx* c_) {
+  const Ctx* c = static_cast<const Ctx*>(c_);
+  return c ? c->err.c_str() : "";
+}
 
-void hca_destroy(hca_ctx* c) {
+void api_destroy(::hca_ctx* c_) {
+  Ctx* c = static_cast<Ctx*>(c_);
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   free_all(c);
   delete c;
 }
 
-}  // extern "C"
+}  // namespace HCA_RT_NS
+}  // namespace hca

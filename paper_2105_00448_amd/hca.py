@@ -48,6 +48,7 @@ class Params(C.Structure):
         ("epi_q2", C.c_double), ("epi_q3", C.c_double), ("epi_cl", C.c_double),
         ("G_ref3", C.c_double), ("b_int3", C.c_int32),
         ("x0_extrapolate", C.c_int32),
+        ("precision", C.c_int32),
     ]
 
 
@@ -121,11 +122,17 @@ def lib():
         "hca_fields": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_size_t, C.c_int]),
         "hca_set_field": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_size_t, C.c_int]),
         "hca_set_step": (C.c_int, [vp, C.c_int64]),
+        "hca_state_bytes": (C.c_int, [vp, C.c_int, P(C.c_size_t)]),
+        "hca_export_state": (C.c_int, [vp, C.c_int, vp, C.c_size_t, C.c_int]),
+        "hca_import_state": (C.c_int, [vp, C.c_int, vp, C.c_size_t, C.c_int]),
+        "hca_init_from_state": (C.c_int, [P(vp), P(Params), P(Replicate), P(vp), P(C.c_size_t),
+                                          C.c_int, vp]),
         "hca_stats": (C.c_int, [vp, C.c_int, P(Stats)]),
         "hca_kernel_time": (C.c_int, [vp, C.c_int, P(C.c_double), P(C.c_int64), P(C.c_double)]),
         "hca_kernel_name": (C.c_char_p, [C.c_int]),
         "hca_num_kernels": (C.c_int, []),
         "hca_reset_kernel_time": (C.c_int, [vp]),
+        "hca_set_profile": (C.c_int, [vp, C.c_int]),
         "hca_synchronize": (C.c_int, [vp]),
         "hca_last_error": (C.c_char_p, [vp]),
         "hca_destroy": (None, [vp]),
@@ -186,24 +193,32 @@ class Simulation:
     each is the third drug's schedule).
     """
 
-    def __init__(self, replicates, params=None, stream=None):
+    def __init__(self, replicates, params=None, stream=None, states=None):
+        """``states``: optional list of state blobs (uint8 numpy arrays from
+        ``export_state``), one per replicate: the context then resumes from
+        them (hca_init_from_state) and each replicate's cell and w may be
+        None, its shape taken from the blob."""
         self._lib = lib()
         self.params = params if params is not None else default_params()
         self.shapes = []
         keep = []
         reps = (Replicate * len(replicates))()
         for r, (cell, w, seed, sched) in enumerate(replicates):
-            cell = np.ascontiguousarray(cell, dtype=np.uint8)
-            w = np.ascontiguousarray(w, dtype=np.float64)
-            if cell.shape != w.shape or cell.ndim != 3:
-                raise ValueError("cell and w must be (nz, ny, nx) arrays of one shape")
-            nz, ny, nx = cell.shape
-            self.shapes.append(cell.shape)
             R = reps[r]
+            if states is not None and cell is None:
+                hdr = np.frombuffer(states[r][:32].tobytes(), dtype=np.int32)
+                nx, ny, nz = int(hdr[4]), int(hdr[5]), int(hdr[6])
+            else:
+                cell = np.ascontiguousarray(cell, dtype=np.uint8)
+                w = np.ascontiguousarray(w, dtype=np.float64)
+                if cell.shape != w.shape or cell.ndim != 3:
+                    raise ValueError("cell and w must be (nz, ny, nx) arrays of one shape")
+                nz, ny, nx = cell.shape
+                R.cell = cell.ctypes.data_as(C.POINTER(C.c_uint8))
+                R.vessel_w = _dptr(w)
+                keep += [cell, w]
+            self.shapes.append((nz, ny, nx))
             R.nx, R.ny, R.nz, R.seed = nx, ny, nz, int(seed)
-            R.cell = cell.ctypes.data_as(C.POINTER(C.c_uint8))
-            R.vessel_w = _dptr(w)
-            keep += [cell, w]
             times, amts = sched
             for d in range(2):
                 t = np.ascontiguousarray(times[d], dtype=np.float64)
@@ -220,8 +235,16 @@ class Simulation:
                 R.dose_amt3 = _dptr(a)
                 keep += [t, a]
         h = C.c_void_p()
-        st = self._lib.hca_init(C.byref(h), C.byref(self.params), reps, len(replicates),
-                                C.c_void_p(stream) if stream else None)
+        if states is None:
+            st = self._lib.hca_init(C.byref(h), C.byref(self.params), reps, len(replicates),
+                                    C.c_void_p(stream) if stream else None)
+        else:
+            blobs = [np.ascontiguousarray(b, dtype=np.uint8) for b in states]
+            keep += blobs
+            ptrs = (C.c_void_p * len(blobs))(*[b.ctypes.data for b in blobs])
+            sizes = (C.c_size_t * len(blobs))(*[b.nbytes for b in blobs])
+            st = self._lib.hca_init_from_state(C.byref(h), C.byref(self.params), reps, ptrs, sizes,
+                                               len(replicates), C.c_void_p(stream) if stream else None)
         if st != OK:
             raise HcaError(st, "hca_init failed (details on stderr)")
         self._h = h
@@ -270,6 +293,23 @@ class Simulation:
         self._check(self._lib.hca_set_field(self._h, rep, f, a.ctypes.data, a.nbytes, 0),
                     "hca_set_field")
 
+    def state_bytes(self, rep=0):
+        n = C.c_size_t()
+        self._check(self._lib.hca_state_bytes(self._h, rep, C.byref(n)), "hca_state_bytes")
+        return n.value
+
+    def export_state(self, rep=0):
+        """The replicate's complete state (hca_export_state) as a uint8 array."""
+        out = np.empty(self.state_bytes(rep), dtype=np.uint8)
+        self._check(self._lib.hca_export_state(self._h, rep, out.ctypes.data, out.nbytes, 0),
+                    "hca_export_state")
+        return out
+
+    def import_state(self, blob, rep=0):
+        b = np.ascontiguousarray(blob, dtype=np.uint8)
+        self._check(self._lib.hca_import_state(self._h, rep, b.ctypes.data, b.nbytes, 0),
+                    "hca_import_state")
+
     def tile_shape(self, rep=0):
         tx, ty, tz = C.c_int32(), C.c_int32(), C.c_int32()
         self._check(self._lib.hca_tile_shape(self._h, rep, C.byref(tx), C.byref(ty), C.byref(tz)),
@@ -297,6 +337,9 @@ class Simulation:
             out[self._lib.hca_kernel_name(k).decode()] = dict(ms=ms.value, launches=n.value,
                                                               bytes_per_launch=b.value)
         return out
+
+    def set_profile(self, profile):
+        self._check(self._lib.hca_set_profile(self._h, int(profile)), "hca_set_profile")
 
     def reset_kernel_times(self):
         self._check(self._lib.hca_reset_kernel_time(self._h), "hca_reset_kernel_time")

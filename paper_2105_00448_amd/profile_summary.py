@@ -1,14 +1,16 @@
-"""Summaries of rocprofv3 runs of the plain 128^3 bench workload.
+"""Summaries of rocprofv3 runs of a bench workload, written under profiles/.
 
-Reads three rocprofv3 output folders of the same command (a kernel trace,
-a FETCH_SIZE pass and a WRITE_SIZE pass, each started with
-`--copy-calibration 256` so that the runtime's copy of 256 MiB calibrates the
-counters) and writes, under profiles/:
+Reads three rocprofv3 output folders of the same `bench.py --profile-only`
+command (a kernel trace, a FETCH_SIZE pass and a WRITE_SIZE pass, each
+started with `--copy-calibration 256` so that the runtime's copy of 256 MiB
+calibrates the counters) and writes:
 
-  plain128_kernel_stats.md                per-kernel durations of the timed context
-  <kernel>_plain128_traffic.{json,md}     HBM bytes per launch of the CG kernels
+  <workload>_kernel_stats.md              per-kernel durations of the stepped context
+  <kernel>_<workload>_traffic.{json,md}   HBM bytes per voxel of the solver's
+                                          streaming kernels (CG and level-0
+                                          multigrid), against their algorithmic bytes
 
-Usage: python -m paper_2105_00448_amd.profile_summary KT_DIR FETCH_DIR WRITE_DIR BENCH_JSON COMMAND
+Usage: python -m paper_2105_00448_amd.profile_summary WORKLOAD PRECISION KT_DIR FETCH_DIR WRITE_DIR COMMAND
 """
 import collections
 import csv
@@ -19,10 +21,30 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SOURCES = ["paper_2105_00448_amd/csrc/k_solver.hip", "paper_2105_00448_amd/csrc/dev_util.h",
-           "paper_2105_00448_amd/csrc/hca_internal.h"]
-KERNELS = {"k_cg_apply": "k_cg_apply<false>", "k_cg_update": "k_cg_update<false>"}
+SOURCES = ["paper_2105_00448_amd/csrc/k_solver.hip", "paper_2105_00448_amd/csrc/k_mg.hip",
+           "paper_2105_00448_amd/csrc/dev_util.h", "paper_2105_00448_amd/csrc/hca_internal.h"]
 COPY_KIB = 256 * 1024
+# the counter passes collect only these dispatches (--kernel-include-regex)
+PMC_REGEX = ("k_cg_update|k_cg_apply|k_mg_pre|k_mg_sweep|k_mg_restrict|k_mg_post1|k_mg_post2|"
+             "k_init_cells|copyBuffer")
+# voxels (of one system) of each workload, and its systems per solve
+WORKLOADS = {"config5": (384 ** 3, 4), "plain128": (128 ** 3, 1)}
+
+
+def kernels(e):
+    """Streaming kernels of the solve (demangled-name prefix -> (short name,
+    algorithmic bytes per active voxel)); e = bytes of a stored field value.
+    Level 0 of the multigrid is the <true, ...> instance."""
+    fp = "double" if e == 8 else "float"
+    return {
+        f"k_cg_update<false, {fp}>": ("k_cg_update", 6 * e),
+        f"k_cg_apply<false, {fp}>": ("k_cg_apply", 4 + 4 * e),
+        "k_mg_pre<true, float>": ("k_mg_pre_L0", 12.0),
+        "k_mg_sweep<true, float>": ("k_mg_sweep_L0", 16.0),
+        "k_mg_restrict<true, float>": ("k_mg_restrict_L0", 12.5),
+        "k_mg_post1<true, float>": ("k_mg_post1_L0", 16.5),
+        f"k_mg_post2<true, {fp}, {fp}>": ("k_mg_post2_L0", 12 + e),
+    }
 
 
 def name(r):
@@ -36,48 +58,45 @@ def one_csv(folder, suffix):
     return list(csv.DictReader(open(hits[0])))
 
 
-def timed_context(rows, key):
+def stepped_context(rows, key):
     """Dispatches after the last context initialisation (k_init_cells)."""
     rows = sorted(rows, key=lambda r: int(r[key]))
     last = max(i for i, r in enumerate(rows) if "k_init_cells" in r["Kernel_Name"])
     return rows, rows[last + 1:]
 
 
-def main(kt_dir, f_dir, w_dir, bench_json, command):
-    bench = json.load(open(bench_json))
-    _, kt = timed_context(one_csv(kt_dir, "kernel_trace.csv"), "Start_Timestamp")
+def pmc_command(command, counter):
+    """The counter pass of the kernel-trace command `command`."""
+    return (command.replace("--kernel-trace --stats",
+                            f"--pmc {counter} --kernel-include-regex '{PMC_REGEX}'")
+            .replace("P_kt", "P_f" if counter == "FETCH_SIZE" else "P_w"))
+
+
+def main(workload, precision, kt_dir, f_dir, w_dir, command):
+    e = 8 if int(precision) == 64 else 4
+    ks = kernels(e)
+    nvox, nrep = WORKLOADS[workload]
+    tag = workload if e == 8 else f"{workload}_fp32"
+    _, kt = stepped_context(one_csv(kt_dir, "kernel_trace.csv"), "Start_Timestamp")
     dur = collections.defaultdict(list)
     for r in kt:
         dur[name(r)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     total = sum(sum(v) for v in dur.values())
     span = (int(kt[-1]["End_Timestamp"]) - int(kt[0]["Start_Timestamp"])) / 1e6
-    out = [f"# Kernel statistics: plain 128^3 workload (multigrid-preconditioned CG)", "",
+    out = [f"# Kernel statistics: {tag} (multigrid-preconditioned CG, precision {precision})", "",
            "Command (repository root, one MI355X):", "", f"    {command}", "",
-           "The bench's plain leg: one timed repeat (100 coupled steps, captured CG",
-           "iterations replayed as HIP graphs), then one more repeat in a fresh context",
-           "with start/stop events carried by the launches of the dominant kernel (every",
-           "kernel launched directly there).  Durations are rocprofv3's dispatch",
-           "timestamps over that last context, after its initialisation",
-           f"({len(kt)} dispatches, span {span:.2f} ms, kernel time {total / 1e3:.2f} ms).", "",
+           "One context of the workload after its initialisation (warm-up and timed steps,",
+           "captured CG iterations replayed as HIP graphs); durations are rocprofv3's",
+           f"dispatch timestamps ({len(kt)} dispatches, span {span:.2f} ms, kernel time "
+           f"{total / 1e3:.2f} ms).", "",
            "| kernel | calls | total ms | mean us | % |", "|---|---:|---:|---:|---:|"]
-    for k, v in sorted(dur.items(), key=lambda kv: -sum(kv[1]))[:26]:
-        out.append(f"| {k} | {len(v)} | {sum(v) / 1e3:.2f} | {sum(v) / len(v):.1f} | {100 * sum(v) / total:.1f} |")
-    rl = bench.get("roofline", {})
-    out += ["", f"Bench line of this traced run: {bench['ms_per_step']:.3f} ms per step; roofline kernel "
-            f"`{rl.get('kernel')}`, {rl.get('mean_launch_us', 0):.1f} us per launch from HIP events "
-            f"({rl.get('launches')} launches, {rl.get('bytes_per_launch', 0) / 1e6:.1f} MB algorithmic each)."]
-    for short, full in KERNELS.items():
-        v = [x for x in dur.get(full, []) if x > 10.0]
-        if v:
-            out.append(f"rocprofv3 `{full}`: {len(v)} working dispatches (> 10 us; the others found every "
-                       f"system finished), mean {sum(v) / len(v):.1f} us.")
-    out += ["", "Under the tracer the HIP events read a few microseconds above the dispatch",
-            "timestamps of the same launches; the untraced bench's events for the roofline",
-            "kernel are the figure to compare with the working-dispatch mean above."]
-    open(os.path.join(ROOT, "profiles", "plain128_kernel_stats.md"), "w").write("\n".join(out) + "\n")
+    for k, v in sorted(dur.items(), key=lambda kv: -sum(kv[1]))[:30]:
+        out.append(f"| {k} | {len(v)} | {sum(v) / 1e3:.2f} | {sum(v) / len(v):.1f} | "
+                   f"{100 * sum(v) / total:.1f} |")
+    open(os.path.join(ROOT, "profiles", f"{tag}_kernel_stats.md"), "w").write("\n".join(out) + "\n")
 
     def counters(folder):
-        allr, ctx = timed_context(one_csv(folder, "counter_collection.csv"), "Dispatch_Id")
+        allr, ctx = stepped_context(one_csv(folder, "counter_collection.csv"), "Dispatch_Id")
         first = min(i for i, r in enumerate(allr) if "k_init_cells" in r["Kernel_Name"])
         copies = [float(r["Counter_Value"]) for r in allr[:first]
                   if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) > 100000]
@@ -88,45 +107,52 @@ def main(kt_dir, f_dir, w_dir, bench_json, command):
     h = hashlib.sha256()
     for f in SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    bpv = {"k_cg_apply": 36.0, "k_cg_update": 56.0}
-    nvox = 3 * 128 ** 3
-    for short, full in KERNELS.items():
-        fa = [float(r["Counter_Value"]) for r in F if name(r) == full]
-        wa = [float(r["Counter_Value"]) for r in W if name(r) == full]
-        act = [x for x in fa if x > 1024.0]   # all-finished dispatches read almost nothing
-        n = len(act)
-        fetch = sum(fa) * 1024 * ffac / n
-        write = sum(wa) * 1024 * wfac / n
-        rec = {"kernel": short, "workload": "plain128", "sources": SOURCES, "sources_sha256": h.hexdigest(),
-               "fetch_factor": ffac, "write_factor": wfac, "fetch_bytes_per_launch": fetch,
-               "write_bytes_per_launch": write, "traffic_bytes_per_launch": fetch + write, "launches": n,
-               "command": command.replace("--kernel-trace --stats", "--pmc FETCH_SIZE|WRITE_SIZE")}
-        json.dump(rec, open(os.path.join(ROOT, "profiles", f"{short}_plain128_traffic.json"), "w"), indent=1)
-        md = [f"# HBM traffic of {short} on the plain 128^3 workload", "",
-              "Commands (repository root, one MI355X), one counter per run:", "",
-              "    " + command.replace("--kernel-trace --stats", "--pmc FETCH_SIZE").replace("P_kt", "P_f"),
-              "    " + command.replace("--kernel-trace --stats", "--pmc WRITE_SIZE").replace("P_kt", "P_w"), "",
-              f"Calibration: `--copy-calibration 256` first copies 256 MiB device to device (runtime",
-              f"blit kernel); per copy FETCH_SIZE reads {sum(cf) / len(cf):.0f} KiB and WRITE_SIZE",
-              f"{sum(cw) / len(cw):.0f} KiB for {COPY_KIB} KiB moved each way: scale factors",
-              f"{ffac:.3f} (fetch) and {wfac:.3f} (write).", "",
-              f"{full}, dispatches of the timed context, averaged over the {n} dispatches",
-              "with at least one system iterating (all-finished dispatches read almost nothing",
-              "and are summed in, not counted):", "",
-              "| quantity | per launch |", "|---|---:|",
-              f"| FETCH_SIZE x {ffac:.3f} | {fetch / 1e6:.1f} MB |",
-              f"| WRITE_SIZE x {wfac:.3f} | {write / 1e6:.1f} MB |",
-              f"| traffic | {(fetch + write) / 1e6:.1f} MB |",
-              f"| algorithmic, all three systems iterating ({bpv[short]:.0f} B x {nvox} voxels) | "
-              f"{bpv[short] * nvox / 1e6:.1f} MB |", "",
-              f"`profiles/{short}_plain128_traffic.json` holds these numbers with the SHA-256 of the",
-              "kernel's source files; `bench.py` reports them as `roofline.traffic` only while",
-              "those sources are unchanged."]
-        open(os.path.join(ROOT, "profiles", f"{short}_plain128_traffic.md"), "w").write("\n".join(md) + "\n")
-    print("wrote profiles/plain128_kernel_stats.md and the traffic summaries")
+    table = ["| kernel | dispatches (all systems iterating) | FETCH B/voxel | WRITE B/voxel | "
+             "measured B/voxel | algorithmic B/voxel | ratio |", "|---|---:|---:|---:|---:|---:|---:|"]
+    ktimes = {}
+    for full, (short, bpv) in ks.items():
+        fd = [(int(r["Dispatch_Id"]), float(r["Counter_Value"])) for r in F if name(r) == full]
+        wd = {int(r["Dispatch_Id"]): float(r["Counter_Value"]) for r in W if name(r) == full}
+        if not fd:
+            continue
+        top = max(v for _, v in fd)
+        full_disp = [(d, v) for d, v in fd if v >= 0.9 * top]   # every system still iterating
+        # the all-systems dispatches of the FETCH pass; WRITE of the same dispatch order
+        fetch = sum(v for _, v in full_disp) / len(full_disp) * 1024 * ffac
+        wvals = sorted(wd.values(), reverse=True)[:len(full_disp)]
+        write = sum(wvals) / len(wvals) * 1024 * wfac
+        vox = 3 * nvox * nrep
+        mb = (fetch + write) / vox
+        durs = [x for x in dur.get(full, [])]
+        ktimes[short] = durs
+        rec = {"kernel": short, "workload": workload, "precision": int(precision), "sources": SOURCES,
+               "sources_sha256": h.hexdigest(), "fetch_factor": ffac, "write_factor": wfac,
+               "voxels_all_systems": vox, "dispatches_all_systems": len(full_disp),
+               "fetch_bytes_per_voxel": fetch / vox, "write_bytes_per_voxel": write / vox,
+               "traffic_bytes_per_voxel": mb, "algorithmic_bytes_per_voxel": bpv,
+               "commands": [pmc_command(command, "FETCH_SIZE"), pmc_command(command, "WRITE_SIZE")]}
+        json.dump(rec, open(os.path.join(ROOT, "profiles", f"{short}_{tag}_traffic.json"), "w"), indent=1)
+        table.append(f"| {full} | {len(full_disp)} | {fetch / vox:.2f} | {write / vox:.2f} | {mb:.2f} | "
+                     f"{bpv:.1f} | {mb / bpv:.3f} |")
+    md = [f"# HBM traffic of the solver's streaming kernels: {tag}", "",
+          "Commands (repository root, one MI355X), one counter per run:", "",
+          "    " + pmc_command(command, "FETCH_SIZE"),
+          "    " + pmc_command(command, "WRITE_SIZE"), "",
+          "Calibration: `--copy-calibration 256` first copies 256 MiB device to device (the",
+          f"runtime's blit kernel); per copy FETCH_SIZE reads {sum(cf) / len(cf):.0f} KiB and WRITE_SIZE",
+          f"{sum(cw) / len(cw):.0f} KiB for {COPY_KIB} KiB moved each way: scale factors",
+          f"{ffac:.3f} (fetch) and {wfac:.3f} (write).", "",
+          f"Per voxel of all {3 * nrep} systems ({3 * nvox * nrep} voxels), on the dispatches where every",
+          "system still iterates (counter within 10 % of the kernel's largest; later",
+          "dispatches skip finished systems):", ""] + table + [
+          "", "`profiles/<kernel>_" + tag + "_traffic.json` hold these numbers with the SHA-256 of the",
+          "solver's sources; `bench.py` reports them as `roofline.traffic` only while those",
+          "sources are unchanged."]
+    open(os.path.join(ROOT, "profiles", f"solver_{tag}_traffic.md"), "w").write("\n".join(md) + "\n")
+    print(f"wrote profiles/{tag}_kernel_stats.md, profiles/solver_{tag}_traffic.md and the json records")
 
 
 if __name__ == "__main__":
-    if len(sys.argv) != 6:
+    if len(sys.argv) != 7:
         raise SystemExit(__doc__)
     main(*sys.argv[1:])
