@@ -352,6 +352,11 @@ struct CaList {
   long long* cells;   // one slot per voxel
   int* item_n;        // per flat work item
 };
+// The plain integrator (as launch_ode) on the voxels listed per flat work
+// item, list.item_n[it] of them at list.cells[first voxel of the item ...].
+template <typename T>
+void launch_ode_list(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L, const T* K,
+                     double* P, double* Vc, double* phi, CaList list);
 // code = win = NONE everywhere, the committed cells listed, then each listed
 // cell's decision (kill, NOSPACE or the daughter's direction) into code.
 template <typename T>

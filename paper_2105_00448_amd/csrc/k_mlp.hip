@@ -151,32 +151,6 @@ struct GlobalNet {
   __device__ inline float b4(int o) const { return th[kOb4 + o]; }
 };
 
-// The forward weights held in registers for a wavefront's lifetime (88
-// VGPRs); biases and the GELU table as in LdsNet.
-struct RegNet {
-  bf16x8 w[kPackFwd / 64];
-  const float* sb;
-  const float2* tab;
-  float ob[kMlpOut];
-  int lane;
-  __device__ inline float gelu(float z) const { return gelu_lut(tab, z); }
-  __device__ inline bf16x8 A(int blk) const { return w[blk]; }
-  __device__ inline f32x16 bias(int L, int mt) const {
-    const float4* q = reinterpret_cast<const float4*>(sb + ((L * 2 + mt) * 2 + (lane >> 5)) * 16);
-    f32x16 acc;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const float4 v = q[k];
-      acc[4 * k + 0] = v.x;
-      acc[4 * k + 1] = v.y;
-      acc[4 * k + 2] = v.z;
-      acc[4 * k + 3] = v.w;
-    }
-    return acc;
-  }
-  __device__ inline float b4(int o) const { return ob[o]; }
-};
-
 // The forward operands staged once per workgroup in LDS (22.5 KB of packed
 // weights); hidden biases in D-row order, sb[((L*2 + mt)*2 + h)*16 + j].
 struct LdsNet {
@@ -287,29 +261,31 @@ __device__ inline void forward32(const NET& net, const float (&x)[kMlpIn], int l
 
 // Per flat work item, in runs of at most kFlatChunk voxels:
 //  1. the item's occupied voxels are listed in LDS, in voxel order;
-//  2. each wavefront evaluates the network on 64 (or 32) listed voxels at a
-//     time; a voxel takes (P, Vc) += update and, for a cancer cell,
-//     phi += update;
+//  2. each wavefront evaluates the network on 32 listed voxels at a time
+//     (one 32-sample MFMA tile; every lane takes part in the GELUs); a voxel
+//     takes (P, Vc) += update and, for a cancer cell, phi += update;
 //  3. a cancer cell whose predicted phi lands within `margin` of the division
 //     threshold 1, or (box mode) a voxel whose inputs leave the training
-//     range, is queued instead and, after the network pass, advanced by the
-//     plain integrator, the queue spread over all lanes.
-// WIDE: 64 voxels per wavefront step (two 32-sample tiles), else 32;
-// REGW: weights in registers, else staged in LDS.  The four variants measure
-// within 8 % of each other on the 256^3 workload; the launcher uses
-// <true, true>.
-template <bool WIDE, bool REGW, typename T>
-__global__ void __launch_bounds__(kBlock) k_mlp_apply(Work w, DevParams p, MlpDev net,
-                                                      const uint8_t* __restrict__ L,
-                                                      const T* __restrict__ K,
-                                                      const T* __restrict__ G1,
-                                                      const T* __restrict__ G2,
-                                                      double* __restrict__ P, double* __restrict__ Vc,
-                                                      double* __restrict__ phi,
-                                                      unsigned long long* __restrict__ part) {
+//     range, is left untouched and listed in fb (slots from the item's first
+//     voxel, in any order: voxels are independent); launch_ode_list then
+//     advances those by the plain integrator.
+// The weights and biases stay in LDS and are re-read on every pass (the
+// empty asm with a memory clobber keeps the compiler from hoisting them
+// into registers for the whole loop, which took the kernel to one wavefront
+// per SIMD); with them in LDS the kernel runs at four.
+template <typename T>
+__global__ void __launch_bounds__(kBlock, 4) k_mlp_apply(Work w, MlpDev net,
+                                                         const uint8_t* __restrict__ L,
+                                                         const T* __restrict__ K,
+                                                         const T* __restrict__ G1,
+                                                         const T* __restrict__ G2,
+                                                         double* __restrict__ P,
+                                                         double* __restrict__ Vc,
+                                                         double* __restrict__ phi,
+                                                         unsigned long long* __restrict__ part,
+                                                         CaList fbl) {
   __shared__ unsigned long long lds4[4];
   __shared__ int list[kFlatChunk];
-  __shared__ int fb_list[kFlatChunk];
   __shared__ int wcnt[4];
   __shared__ int n_fb_s;
   __shared__ __attribute__((aligned(16))) float sbias[192];
@@ -317,20 +293,14 @@ __global__ void __launch_bounds__(kBlock) k_mlp_apply(Work w, DevParams p, MlpDe
   __shared__ bf16x8 sw[kPackFwd];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   load_gelu_table(net.gelu_tab, stab);
-  if (!REGW)
-    for (int k = threadIdx.x; k < kPackFwd; k += kBlock) sw[k] = net.packed[k];
+  for (int k = threadIdx.x; k < kPackFwd; k += kBlock) sw[k] = net.packed[k];
   for (int k = threadIdx.x; k < 192; k += kBlock) {
     const int j = k & 15, h = (k >> 4) & 1, mt = (k >> 5) & 1, Ly = k >> 6;
     const int ob = Ly == 0 ? kOb1 : Ly == 1 ? kOb2 : kOb3;
     sbias[k] = net.theta[ob + drow(mt, j, h)];
   }
-  typename std::conditional<REGW, RegNet, LdsNet>::type R;
-  if constexpr (REGW) {
-#pragma unroll
-    for (int b = 0; b < kPackFwd / 64; ++b) R.w[b] = net.packed[b * 64 + lane];
-  } else {
-    R.w = sw;
-  }
+  LdsNet R;
+  R.w = sw;
 #pragma unroll
   for (int o = 0; o < kMlpOut; ++o) R.ob[o] = net.theta[kOb4 + o];
   R.sb = sbias;
@@ -340,13 +310,15 @@ __global__ void __launch_bounds__(kBlock) k_mlp_apply(Work w, DevParams p, MlpDe
   work_range(w.nflat, b0, b1);
   for (int it = b0; it < b1; ++it) {
     const FlatBlk fb = w.flat[it];
-    unsigned long long n_sur = 0, n_fbk = 0;
+    const long long roff = w.reps[fb.rep].off;
+    long long* const slots = fbl.cells + roff + fb.begin;
+    unsigned long long n_sur = 0;
+    if (threadIdx.x == 0) n_fb_s = 0;
     // the item in runs of at most kFlatChunk voxels (the LDS list size)
     for (long long c0 = fb.begin; c0 < fb.end; c0 += kFlatChunk) {
-      const long long off = w.reps[fb.rep].off + c0;
+      const long long off = roff + c0;
       const int len = (int)min((long long)kFlatChunk, fb.end - c0);
       // 1. list the occupied voxels (index within the run), in order
-      if (threadIdx.x == 0) n_fb_s = 0;
       int n = 0;
       for (int base = 0; base < len; base += kBlock) {
         const int li = base + (int)threadIdx.x;
@@ -362,11 +334,12 @@ __global__ void __launch_bounds__(kBlock) k_mlp_apply(Work w, DevParams p, MlpDe
         __syncthreads();
       }
       // 2. network pass, 32 listed voxels per wavefront step (lanes 0..31)
-      constexpr int kStep = WIDE ? 64 : 32;
-      for (int s0 = kStep * wave; s0 < n; s0 += kStep * (kBlock / 64)) {
-        const int si = s0 + (WIDE ? lane : (lane & 31));
-        const bool act = si < n && (WIDE || lane < 32);
-        const long long i = off + (act ? list[si] : 0);
+      for (int s0 = 32 * wave; s0 < n; s0 += 32 * (kBlock / 64)) {
+        asm volatile("" ::: "memory");   // network operands re-read from LDS per pass
+        const int si = s0 + (lane & 31);
+        const bool act = si < n && lane < 32;
+        const int li = act ? list[si] : 0;
+        const long long i = off + li;
         double raw[kMlpIn] = {0, 0, 0, 0, 0, 0};
         uint8_t l = 0;
         if (act) {
@@ -387,43 +360,31 @@ __global__ void __launch_bounds__(kBlock) k_mlp_apply(Work w, DevParams p, MlpDe
           x[f] = act ? (r - net.in_mean[f]) * net.in_scale[f] : 0.0f;
         }
         float y[kMlpOut];
-        if constexpr (WIDE)
-          forward64(R, x, lane, y);
-        else
-          forward32(R, x, lane, y);
+        forward32(R, x, lane, y);
         if (!act) continue;
+        // the state again (cached) rather than held in registers over the pass
+        asm volatile("" ::: "memory");
+        const double p0 = P[i], v0 = Vc[i], f0 = phi[i];
         const double dphi = (double)(y[2] * net.out_scale[2] + net.out_mean[2]);
         const bool fallback =
-            (net.box && !inbox) || (l == 1 && fabs(raw[5] + dphi - 1.0) < net.margin);
+            (net.box && !inbox) || (l == 1 && fabs(f0 + dphi - 1.0) < net.margin);
         if (fallback) {
-          fb_list[atomicAdd(&n_fb_s, 1)] = si;
+          slots[atomicAdd(&n_fb_s, 1)] = c0 + li;
         } else {
-          P[i] = raw[3] + (double)(y[0] * net.out_scale[0] + net.out_mean[0]);
-          Vc[i] = raw[4] + (double)(y[1] * net.out_scale[1] + net.out_mean[1]);
-          if (l == 1) phi[i] = raw[5] + dphi;
+          P[i] = p0 + (double)(y[0] * net.out_scale[0] + net.out_mean[0]);
+          Vc[i] = v0 + (double)(y[1] * net.out_scale[1] + net.out_mean[1]);
+          if (l == 1) phi[i] = f0 + dphi;
           ++n_sur;
         }
       }
-      __syncthreads();
-      // 3. the queued voxels by the plain integrator (voxels are independent,
-      //    so the queue order does not matter)
-      const int nfb = n_fb_s;
-      for (int q = threadIdx.x; q < nfb; q += kBlock) {
-        const long long i = off + list[fb_list[q]];
-        const uint8_t l = L[i];
-        double pv = P[i], vv = Vc[i], ph = phi[i];
-        ode_voxel(p, l, K[i], pv, vv, ph);
-        P[i] = pv;
-        Vc[i] = vv;
-        if (l == 1) phi[i] = ph;
-      }
-      n_fbk += (unsigned long long)nfb;
-      __syncthreads();   // list, fb_list and n_fb_s are reused by the next run
+      __syncthreads();   // the list is rewritten by the next run
     }
     const unsigned long long a = block_sum_u64(n_sur, lds4);
     if (threadIdx.x == 0) {
+      const int nfb = n_fb_s;
+      fbl.item_n[it] = nfb;
       part[(size_t)it * kCounterSlots + 0] = a;
-      part[(size_t)it * kCounterSlots + 1] = n_fbk;
+      part[(size_t)it * kCounterSlots + 1] = (unsigned long long)nfb;
     }
   }
 }
@@ -886,9 +847,10 @@ void launch_mlp_pack(hipStream_t s, const float* theta, bf16x8* packed) {
 template <typename T>
 void launch_mlp_apply(hipStream_t s, const Work& w, const DevParams& p, const MlpDev& net,
                       const uint8_t* L, const T* K, const T* G1, const T* G2, double* P,
-                      double* Vc, double* phi, unsigned long long* part, Counters* cnt) {
-  hca_launch((k_mlp_apply<true, true, T>), dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock),
-                     0, s, w, p, net, L, K, G1, G2, P, Vc, phi, part);
+                      double* Vc, double* phi, unsigned long long* part, Counters* cnt, CaList fb) {
+  hca_launch(k_mlp_apply<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, net, L,
+             K, G1, G2, P, Vc, phi, part, fb);
+  launch_ode_list(s, w, p, L, K, P, Vc, phi, fb);
   launch_counters_reduce(s, w, part, cnt, CNT_SUR);
 }
 
@@ -960,7 +922,7 @@ void launch_mlp_eval(hipStream_t s, const bf16x8* pk, const float* th, const flo
 #define HCA_MLP_INST(T)                                                                            \
   template void launch_mlp_apply<T>(hipStream_t, const Work&, const DevParams&, const MlpDev&,     \
                                     const uint8_t*, const T*, const T*, const T*, double*,         \
-                                    double*, double*, unsigned long long*, Counters*);             \
+                                    double*, double*, unsigned long long*, Counters*, CaList);     \
   template void launch_mlp_harvest<T>(hipStream_t, const Work&, const DevParams&, const uint8_t*,  \
                                       const T*, const T*, const T*, const double*, const double*,  \
                                       const double*, const long long*, float*, float*);

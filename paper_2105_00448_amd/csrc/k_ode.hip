@@ -59,6 +59,45 @@ void launch_ode(hipStream_t s, const Work& w, const DevParams& p, const uint8_t*
   hca_launch(k_ode<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, K, P, Vc, phi);
 }
 
+// The plain integrator on listed voxels only: flat work item it's voxels
+// (local indices) at list.cells[first voxel of the item ...], list.item_n[it]
+// of them (the surrogate's fallback voxels).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_ode_list(Work w, DevParams p, const uint8_t* __restrict__ L,
+                                                     const T* __restrict__ K, double* __restrict__ P,
+                                                     double* __restrict__ Vc, double* __restrict__ phi,
+                                                     CaList list) {
+  int b0, b1;
+  work_range(w.nflat, b0, b1);
+  for (int it = b0; it < b1; ++it) {
+    const int n = list.item_n[it];
+    if (n == 0) continue;
+    const FlatBlk fb = w.flat[it];
+    const RepDev rp = w.reps[fb.rep];
+    const long long* slots = list.cells + rp.off + fb.begin;
+    for (int k = threadIdx.x; k < n; k += kBlock) {
+      const long long i = rp.off + slots[k];
+      const uint8_t l = L[i];
+      double pv = P[i], vv = Vc[i], ph = phi[i];
+      ode_voxel(p, l, K[i], pv, vv, ph);
+      P[i] = pv;
+      Vc[i] = vv;
+      if (l == 1) phi[i] = ph;
+    }
+  }
+}
+
+template <typename T>
+void launch_ode_list(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L, const T* K,
+                     double* P, double* Vc, double* phi, CaList list) {
+  hca_launch(k_ode_list<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, K, P, Vc,
+             phi, list);
+}
+
+template void launch_ode_list<double>(hipStream_t, const Work&, const DevParams&, const uint8_t*,
+                                      const double*, double*, double*, double*, CaList);
+template void launch_ode_list<float>(hipStream_t, const Work&, const DevParams&, const uint8_t*,
+                                     const float*, double*, double*, double*, CaList);
 template void launch_ode<double>(hipStream_t, const Work&, const DevParams&, const uint8_t*,
                                  const double*, double*, double*, double*);
 template void launch_ode<float>(hipStream_t, const Work&, const DevParams&, const uint8_t*,

@@ -662,7 +662,7 @@ hca_status run_phases(Ctx* c, unsigned mask) {
     if (c->sur_on) {
       ProfScope ps(c, KC_MLP_APPLY, kTagState);
       launch_mlp_apply(s, wk, c->dp, c->net, c->L, c->K, c->G1, c->G2, c->P, c->Vc, c->phi,
-                       c->d_cpart, c->d_cnt);
+                       c->d_cpart, c->d_cnt, c->ca_list);
     } else {
       ProfScope ps(c, KC_ODE, kTagState);
       launch_ode(s, wk, c->dp, c->L, c->K, c->P, c->Vc, c->phi);

@@ -543,15 +543,7 @@ def test_surrogate_apply_matches_oracle(case_sur):
     either way and must match one of the two results."""
     tis, sched, s, theta, stats = case_sur
     margin = 0.02
-    net = hca.Mlp()
-    th32 = np.ascontiguousarray(theta, dtype=np.float32)
-    net.theta = th32.ctypes.data
-    net.theta_is_device = 0
-    for k, v in stats.items():
-        arr = getattr(net, k)
-        for i, x in enumerate(v):
-            arr[i] = float(x)
-    net.box_check = 0
+    net, th32 = host_net(theta, stats)
     with hca.Simulation([(tis.cell, tis.w, tis.seed, (sched.times, sched.amts))],
                         hca.default_params()) as sim:
         for name in ("L", "K", "G1", "G2", "P", "Vc", "phi"):
@@ -612,6 +604,55 @@ def test_surrogate_apply_matches_oracle(case_sur):
         plain = (abs(got["P"][i] - Pp[i]) <= 1e-10 * scaleP and got["phi"][i] == php[i])
         netw = abs((got["P"][i] - base[i, 0]) - upd[i, 0]) <= tol[i, 0]
         assert plain or netw, i
+
+
+def host_net(theta, stats):
+    """An Mlp descriptor of FP32 host parameters (kept alive by the caller
+    through the returned array) and the given statistics, box check off."""
+    net = hca.Mlp()
+    th32 = np.ascontiguousarray(theta, dtype=np.float32)
+    net.theta = th32.ctypes.data
+    net.theta_is_device = 0
+    for k, v in stats.items():
+        arr = getattr(net, k)
+        for i, x in enumerate(v):
+            arr[i] = float(x)
+    net.box_check = 0
+    return net, th32
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_surrogate_apply_on_a_tiled_lattice_is_the_tiled_result(case_sur, precision):
+    """Each voxel's surrogate update depends on that voxel alone (its own
+    MFMA column; the plain integrator for fallbacks), so the ODE phase on
+    the 32^3 state tiled 72 times along x (2.36 M voxels: work items of
+    1152 voxels, each listed in two runs, the fallback list spanning both)
+    is the 32^3 result tiled, bit for bit, with 72 times the counts."""
+    tis, sched, s, theta, stats = case_sur
+    margin = 0.02
+    net, th32 = host_net(theta, stats)
+    reps = 72
+    names = ("L", "K", "G1", "G2", "P", "Vc", "phi")
+    params = hca.default_params(precision=precision)
+
+    def run(tile):
+        cell = np.tile(tis.cell, (1, 1, tile))
+        w = np.tile(tis.w, (1, 1, tile))
+        with hca.Simulation([(cell, w, tis.seed, (sched.times, sched.amts))], params) as sim:
+            for name in names:
+                sim.set_field(name, np.tile(getattr(s, name), (1, 1, tile)))
+            sim.set_surrogate(net, margin)
+            sim.run_phases(hca.PH_ODE)
+            return {k: sim.field(k) for k in ("P", "Vc", "phi")}, sim.stats()
+
+    print(f"\n[surrogate tiled] precision {precision}: 32^3 and 32 x 32 x {32 * reps}", flush=True)
+    small, st1 = run(1)
+    big, stn = run(reps)
+    assert st1["sur_fallbacks"] > 50
+    assert stn["sur_fallbacks"] == reps * st1["sur_fallbacks"]
+    assert stn["sur_voxels"] == reps * st1["sur_voxels"]
+    for k in ("P", "Vc", "phi"):
+        assert np.array_equal(big[k], np.tile(small[k], (1, 1, reps))), k
 
 
 @pytest.fixture(scope="module")
