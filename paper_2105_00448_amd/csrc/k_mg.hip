@@ -395,59 +395,50 @@ __device__ inline void lin_axis(int i, int nf, int nc, int& I, int& J, float& wJ
 }
 
 
-// u3 = u2 + P e at the neighbours: the eight coarse values and the axis
-// weights are loaded ahead, combined when the plane is formed.
-template <typename RT>
-struct OpPost1 {
-  struct Raw {
-    float u;
-    float e[8];
-    float wx, wy, wz;
-  };
-  using Ctr = CtrDR<RT>;
-  static constexpr bool kCtrInRaw = false;
-  const float* __restrict__ u;
-  const float* __restrict__ e;
-  const float* __restrict__ dinv;
-  const RT* __restrict__ r;
-  MgRep mc;
-  int nfx, nfy, nfz;
-  __device__ inline Raw zero() const {
-    Raw v{};
-    return v;
-  }
-  __device__ inline Raw load(int x, int y, int z, long long j) const {
-    int Ix, Jx, Iy, Jy, Iz, Jz;
-    Raw v;
-    lin_axis(x, nfx, mc.nx, Ix, Jx, v.wx);
-    lin_axis(y, nfy, mc.ny, Iy, Jy, v.wy);
-    lin_axis(z, nfz, mc.nz, Iz, Jz, v.wz);
-    const long long sy = mc.nx, sz = (long long)mc.nx * mc.ny;
-    const float* b = e + mc.off;
-    v.u = u[j];
-    v.e[0] = b[Iz * sz + Iy * sy + Ix];
-    v.e[1] = b[Iz * sz + Iy * sy + Jx];
-    v.e[2] = b[Iz * sz + Jy * sy + Ix];
-    v.e[3] = b[Iz * sz + Jy * sy + Jx];
-    v.e[4] = b[Jz * sz + Iy * sy + Ix];
-    v.e[5] = b[Jz * sz + Iy * sy + Jx];
-    v.e[6] = b[Jz * sz + Jy * sy + Ix];
-    v.e[7] = b[Jz * sz + Jy * sy + Jx];
-    return v;
-  }
-  // x first along each coarse row, then y, then z (a fixed order)
-  __device__ inline float value(const Raw& v) const {
-    const float wx = v.wx, wy = v.wy, wz = v.wz;
-    const float r00 = (1.f - wx) * v.e[0] + wx * v.e[1];
-    const float r01 = (1.f - wx) * v.e[2] + wx * v.e[3];
-    const float r10 = (1.f - wx) * v.e[4] + wx * v.e[5];
-    const float r11 = (1.f - wx) * v.e[6] + wx * v.e[7];
-    const float p0 = (1.f - wy) * r00 + wy * r01;
-    const float p1 = (1.f - wy) * r10 + wy * r11;
-    return v.u + ((1.f - wz) * p0 + wz * p1);
-  }
-  __device__ inline Ctr ctr_zero() const { return Ctr{0.f, (RT)0}; }
-  __device__ inline Ctr ctr(long long i) const { return Ctr{dinv[i], r[i]}; }
+// Post-smoothing after the coarse-grid correction: u3 = u2 + P e, then one
+// weighted-Jacobi sweep of u3 into ualt.  P e is separable: a coarse plane Z
+// interpolated in x and y to one of this thread's fine columns,
+//     E_Z = (1 - wy) ((1 - wx) e[Z,Iy,Ix] + wx e[Z,Iy,Jx])
+//           + wy ((1 - wx) e[Z,Jy,Ix] + wx e[Z,Jy,Jx]),
+// serves every fine plane whose z interpolation takes Z (four of them), and a
+// fine plane takes (1 - wz) E_Iz + wz E_Jz.  Each thread owns two columns (its
+// interior cell and at most one frame cell of the tile) and keeps E of the
+// coarse planes I - 1, I, I + 1 around the current fine plane's I = z / 2 in
+// registers, the four coarse values of plane I + 2 in flight: four coarse
+// loads per column per two fine planes instead of eight per cell.  The
+// marching (one plane of u3 with its frame in LDS, double buffered, the
+// loads of plane z + 2 issued before plane z is computed, neighbour terms in
+// the order -x, +x, -y, +y, -z, +z) is that of mg_plane.
+struct PCol {
+  int o[4];    // offsets of (Iy,Ix), (Iy,Jx), (Jy,Ix), (Jy,Jx) within a coarse plane
+  float wx, wy;
+};
+
+__device__ inline PCol pcol(int x, int y, int nfx, int nfy, const MgRep& mc) {
+  int Ix, Jx, Iy, Jy;
+  PCol c;
+  lin_axis(x, nfx, mc.nx, Ix, Jx, c.wx);
+  lin_axis(y, nfy, mc.ny, Iy, Jy, c.wy);
+  c.o[0] = Iy * mc.nx + Ix;
+  c.o[1] = Iy * mc.nx + Jx;
+  c.o[2] = Jy * mc.nx + Ix;
+  c.o[3] = Jy * mc.nx + Jx;
+  return c;
+}
+
+// E of coarse plane Z (x first along each coarse row, then y)
+__device__ inline float pcol_interp(const PCol& c, const float (&g)[4]) {
+  const float r0 = (1.f - c.wx) * g[0] + c.wx * g[1];
+  const float r1 = (1.f - c.wx) * g[2] + c.wx * g[3];
+  return (1.f - c.wy) * r0 + c.wy * r1;
+}
+
+// The coarse-plane window of one column: E of planes I-1, I, I+1 and the raw
+// values of plane I+2 (planes outside the level read as 0; they only ever
+// enter with weight 0).
+struct PWin {
+  float em, e0, ep;
+  float g[4];
 };
 
 template <bool L0, typename RT>
@@ -455,17 +446,167 @@ __global__ void __launch_bounds__(kBlock) k_mg_post1(MgLevel Lk, MgLevel Lc, flo
                                                      const RT* __restrict__ r, const SolveScal* ss) {
   __shared__ float lds[2][kPlaneMaxF];
   float* __restrict__ out = Lk.ualt;
+  const float* __restrict__ u = Lk.u;
+  const float* __restrict__ dinv = Lk.dinv;
   FOR_MY_TILES(Lk.ntiles) {
     const Tile t = Lk.tiles[ti];
     if (ss[t.rep].done) continue;
     const MgRep m = Lk.reps[t.rep];
     const MgRep mc = Lc.reps[t.rep];
     const Geo<L0> G = geo_of<L0>(m);
-    const OpPost1<RT> op{Lk.u, Lc.u, Lk.dinv, r, mc, m.nx, m.ny, m.nz};
-    mg_plane(G, t, m.tx, m.off, lds, op,
-             [&](int, long long i, float u3, float s, const CtrDR<RT>& c) {
-               out[i] = (1.f - omega) * u3 + omega * c.dinv * ((float)c.r + s);
-             });
+    const int tx = m.tx, ty = kBlock / tx;
+    const int lx = (int)(threadIdx.x % tx), ly = (int)(threadIdx.x / tx);
+    const int x = t.x0 + lx, y = t.y0 + ly;
+    const bool valid = x < G.nx && y < G.ny;
+    const int W = tx + 2;
+    const int o = (ly + 1) * W + lx + 1;
+    const int nframe = 2 * W + 2 * ty;
+    const int k = threadIdx.x;
+    const bool has_frame = k < nframe;
+    int hx = 0, hy = 0;
+    if (k < W) {
+      hx = k;
+      hy = 0;
+    } else if (k < 2 * W) {
+      hx = k - W;
+      hy = ty + 1;
+    } else if (k < 2 * W + ty) {
+      hx = 0;
+      hy = 1 + k - 2 * W;
+    } else {
+      hx = W - 1;
+      hy = 1 + k - 2 * W - ty;
+    }
+    const int fx = t.x0 + hx - 1, fy = t.y0 + hy - 1;
+    const bool fin = has_frame && fx >= 0 && fx < G.nx && fy >= 0 && fy < G.ny;
+    const int fo = hy * W + hx;
+    const long long plane = (long long)G.nx * G.ny;
+    const long long fidx = fin ? fx + (long long)G.nx * fy : 0;
+    const long long iidx = x + (long long)G.nx * y;
+    const PCol ci = pcol(valid ? x : 0, valid ? y : 0, G.nx, G.ny, mc);
+    const PCol cf = pcol(fin ? fx : 0, fin ? fy : 0, G.nx, G.ny, mc);
+    const float* __restrict__ eb = Lc.u + mc.off;
+    const long long csz = (long long)mc.nx * mc.ny;
+    auto gather = [&](const PCol& c, bool on, int Z, float (&g)[4]) {
+      if (on && Z >= 0 && Z < mc.nz) {
+        const float* b = eb + csz * Z;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[q] = b[c.o[q]];
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[q] = 0.f;
+      }
+    };
+    PWin wi, wf;
+    int Iw;
+    // window centred on coarse plane I (prologue: E of I-1, I, I+1 directly)
+    auto win_start = [&](int I) {
+      Iw = I;
+      float g[4];
+      gather(ci, valid, I - 1, g);
+      wi.em = pcol_interp(ci, g);
+      gather(ci, valid, I, g);
+      wi.e0 = pcol_interp(ci, g);
+      gather(ci, valid, I + 1, g);
+      wi.ep = pcol_interp(ci, g);
+      gather(ci, valid, I + 2, wi.g);
+      gather(cf, fin, I - 1, g);
+      wf.em = pcol_interp(cf, g);
+      gather(cf, fin, I, g);
+      wf.e0 = pcol_interp(cf, g);
+      gather(cf, fin, I + 1, g);
+      wf.ep = pcol_interp(cf, g);
+      gather(cf, fin, I + 2, wf.g);
+    };
+    auto win_step = [&](PWin& w, const PCol& c, bool on) {
+      w.em = w.e0;
+      w.e0 = w.ep;
+      w.ep = pcol_interp(c, w.g);
+      gather(c, on, Iw + 2, w.g);
+    };
+    // P e of fine plane z at a column (the window moved to z / 2 first)
+    auto pe = [&](const PWin& w, int z) {
+      int Iz, Jz;
+      float wz;
+      lin_axis(z, G.nz, mc.nz, Iz, Jz, wz);
+      if (Jz == Iz) return w.e0;
+      return (1.f - wz) * w.e0 + wz * (Jz < Iz ? w.em : w.ep);
+    };
+    auto win_to = [&](int z) {
+      if ((z >> 1) != Iw) {   // planes are formed in increasing z: one step
+        ++Iw;
+        win_step(wi, ci, valid);
+        win_step(wf, cf, fin);
+      }
+    };
+    float ui = 0.f, uf = 0.f;   // raw u of the next plane to form
+    auto load_plane = [&](int z) {
+      const long long pz = m.off + plane * z;
+      if (valid) ui = u[pz + iidx];
+      if (fin) uf = u[pz + fidx];
+    };
+    auto store_plane = [&](float* buf, int z) {
+      win_to(z);
+      buf[o] = valid ? ui + pe(wi, z) : 0.f;
+      if (has_frame) buf[fo] = fin ? uf + pe(wf, z) : 0.f;
+    };
+    const int z0 = t.z0, z1 = t.z1;
+    long long i = m.off + iidx + plane * z0;
+    float* cur = lds[0];
+    float* nxt = lds[1];
+    __syncthreads();   // the previous tile's readers are done with both buffers
+    win_start((z0 > 0 ? z0 - 1 : z0) >> 1);
+    load_plane(z0);
+    float vm = 0.f;
+    if (z0 > 0) {
+      const float um = valid ? u[i - plane] : 0.f;
+      win_to(z0 - 1);
+      vm = valid ? um + pe(wi, z0 - 1) : 0.f;
+    }
+    float cd = 0.f;
+    RT cr = (RT)0;
+    if (valid) {
+      cd = dinv[i];
+      cr = r[i];
+    }
+    store_plane(cur, z0);
+    if (z0 + 1 < G.nz) load_plane(z0 + 1);
+    __syncthreads();
+    float vc = cur[o];
+    for (int z = z0; z < z1; ++z) {
+      const bool zr = z + 1 < G.nz;
+      const bool more = z + 1 < z1;
+      if (zr) store_plane(nxt, z + 1);
+      if (more && z + 2 < G.nz) load_plane(z + 2);
+      float nd = 0.f;
+      RT nr = (RT)0;
+      if (more && valid) {
+        nd = dinv[i + plane];
+        nr = r[i + plane];
+      }
+      float s = 0.f;
+      if (valid) {
+        if (x > 0) s += G.gx(x - 1, y, z) * cur[o - 1];
+        if (x + 1 < G.nx) s += G.gx(x, y, z) * cur[o + 1];
+        if (y > 0) s += G.gy(x, y - 1, z) * cur[o - W];
+        if (y + 1 < G.ny) s += G.gy(x, y, z) * cur[o + W];
+      }
+      __syncthreads();
+      const float vp = zr ? nxt[o] : 0.f;
+      if (valid) {
+        if (z > 0) s += G.gz(x, y, z - 1) * vm;
+        if (zr) s += G.gz(x, y, z) * vp;
+        out[i] = (1.f - omega) * vc + omega * cd * ((float)cr + s);
+      }
+      vm = vc;
+      vc = vp;
+      cd = nd;
+      cr = nr;
+      float* tmp = cur;
+      cur = nxt;
+      nxt = tmp;
+      i += plane;
+    }
   }
 }
 // One weighted-Jacobi sweep out = in + omega D^-1 (r - A in) (level 0's third
