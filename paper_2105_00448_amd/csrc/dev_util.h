@@ -72,6 +72,17 @@ __device__ inline void tile_range(int T, int& begin, int& end) {
   work_range(T, begin, end);
 }
 
+// Fused-smoothing tiles: workgroup b (dispatched to XCD b mod 8) takes a tile
+// of the runs of `chunk` consecutive tiles dealt round robin to the XCDs.  A
+// run spans about eight rows of tiles of one z-slab, so the tiles whose
+// extended planes overlap (x and y neighbours) mostly run on one XCD at the
+// same time and share their halo reads in its L2.  Returns -1 past the end.
+__device__ inline int ftile_of(int T, int chunk) {
+  const int b = blockIdx.x, x = b % 8, j = b / 8;
+  const int t = ((j / chunk) * 8 + x) * chunk + j % chunk;
+  return t < T ? t : -1;
+}
+
 // A workgroup's three partial sums, stored at its work-item slot (3 doubles);
 // a later reduce kernel (one workgroup per replicate) sums the slots of a
 // replicate in a fixed order.  The kernel boundary orders the two.

@@ -38,7 +38,8 @@ inline void hca_launch(F kernel, dim3 grid, dim3 block, unsigned shmem, hipStrea
   }
 }
 
-constexpr int kBlock = 256;        // threads per workgroup for every kernel
+constexpr int kBlock = 256;        // threads per workgroup (all kernels but the two below)
+constexpr int kF3Block = 512;      // level 0's fused smoothing passes (tiles tx x 512/tx)
 constexpr int kFlatChunk = 1024;   // voxels per flat work item (4 per thread)
 constexpr int kMaxFlatBlocksPerRep = 2048;
 
@@ -93,6 +94,7 @@ struct RepDev {
   unsigned long long seed;
   int flat_b0, flat_nb;       // range in the flat block table
   int tile_b0, tile_nb;       // range in the stencil tile table
+  int ftile_b0, ftile_nb;     // systems: range in level 0's fused-smoothing tile table
   int ndose[3];
   int dose_off;               // into the dose arrays (3*HCA_MAX_DOSES per rep)
   int tx;                     // stencil tile width (tile = tx x (kBlock/tx) columns)
@@ -174,6 +176,13 @@ inline int grid_tiles(int n, int max_blocks) {
   return g;
 }
 
+// Grid of a launch over the n fused-smoothing tiles: one workgroup per tile,
+// a multiple of 8 runs of `chunk` tiles (see ftile_of).
+inline int grid_ftiles(int n, int chunk) {
+  const int r = 8 * chunk;
+  return (n + r - 1) / r * r;
+}
+
 // Grid of a launch over n work items, at most max_blocks workgroups.
 inline int grid_for(int n, int max_blocks) {
   int g = n < max_blocks ? n : max_blocks;
@@ -248,7 +257,8 @@ void launch_cg_start(hipStream_t s, const Work& w, double rtol, int maxit, const
 // Reduce kernels (one workgroup per replicate) that follow the kernels
 // producing partial sums: start (b.b, r.r, r.z), apply (p.q), update
 // (r.r, r.z_old, r.z'), and the preconditioner's r.z'.
-enum ReduceKind { RED_START = 0, RED_APPLY = 1, RED_UPDATE = 2, RED_RZ = 3 };
+// RED_RZ sums partials per stencil tile, RED_RZF per fused-smoothing tile.
+enum ReduceKind { RED_START = 0, RED_APPLY = 1, RED_UPDATE = 2, RED_RZ = 3, RED_RZF = 4 };
 template <typename T>
 void launch_cg_reduce(hipStream_t s, const Work& w, const SolverBufsT<T>& sb, int kind, double rtol,
                       int maxit, unsigned field_mask = 7u, int nrep = 1);
@@ -291,6 +301,9 @@ struct MgLevel {
   int ntiles;
   const Tile* rtiles;       // restriction-target tiles, reps with 1 <= k <= kc
   int nrtiles;
+  const Tile* ftiles;       // level 0: tiles of the fused smoothing passes (deeper in z)
+  int nftiles;
+  int fchunk;               // level 0: fused tiles per XCD run (about eight rows of tiles)
   float *c, *dinv, *r, *u, *ualt;
 };
 
@@ -320,6 +333,7 @@ struct MgBufs {
   int coarse_lds_bytes;
   float w_a, w_b;            // Jacobi weights: pre-sweeps (w_a, w_b), post-sweeps (w_b, w_a)
   float w0[3];              // level 0: pre-sweeps (w0[0], w0[1], w0[2]), post-sweeps reversed
+  int fused;                // level 0: the fused pre and post passes (k_mg_pre3, k_mg_post3)
   float** lev_c;            // device arrays of the per-level pointers
   float** lev_r;
   float** lev_u;
@@ -333,7 +347,8 @@ void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, const T* 
 // scalars (r.z, beta) with a RED_RZ reduce.
 // `hook(ctx, segment, begin)` brackets the launches of each segment (for
 // kernel timing); segments: see MgSegment.
-enum MgSegment { MG_PRE0 = 0, MG_RESTRICT0, MG_DOWN, MG_COARSE, MG_UP, MG_POST1_0, MG_POST2_0, MG_SWEEP0 };
+enum MgSegment { MG_PRE0 = 0, MG_RESTRICT0, MG_DOWN, MG_COARSE, MG_UP, MG_POST1_0, MG_POST2_0, MG_SWEEP0,
+                 MG_PRE3_0, MG_POST3_0 };
 typedef void (*MgHook)(void* ctx, int segment, int begin);
 template <typename T>
 void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const SolverBufsT<T>& sb,

@@ -664,6 +664,389 @@ __global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float omega, co
   }
 }
 
+// ---- level 0: three stencil stages per pass (temporal blocking) ---------------
+//
+// Level 0's couplings are uniform (a), so a sweep needs only the sum of the
+// six neighbours.  Each kernel below runs three dependent stencil stages over
+// a tile in one pass.  A tile of tx x ty output columns (kF3Block of them)
+// over [z0, z1) is extended by three rings of columns in x and y
+// (EX = tx + 6, EY = ty + 6).  Stage 0 forms its values on every column from
+// global memory; stage s = 1, 2, 3 on the columns of rings < 4 - s (ring 0:
+// the tile's own columns), from stage s-1's values.  In the step for plane z
+// the stages work on the planes z+3, z+2, z+1 and z.
+//
+// Each thread owns one tile column (lane layout of the other stencil
+// kernels) and at most one ring column (dealt round robin over the
+// wavefronts).  A column's values of the planes around the current ones (its
+// own z-neighbours, and r and D^-1 of the four planes in flight) stay in the
+// owner's registers; only the x/y neighbours go through LDS, one plane per
+// stage, double buffered: stage s in step z reads the plane stage s-1 wrote in
+// step z-1, so one barrier per step orders everything.  Values outside the
+// lattice are 0, which makes the neighbour sum the sum over the existing
+// faces.
+//   pre:  stage 0 u1 = w0 D^-1 r; stages 1, 2 sweeps (w1, w2), u3 written to
+//         level 0's u; stage 3 the residual r - A u3, summed over the 2 x 2 x 2
+//         children into level 1's r.
+//   post: stage 0 u3 + P e; stages 1, 2, 3 sweeps (w2, w1, w0); stage 3's
+//         plane is the CG's z (FP32, scaled) and feeds its r.z partial.
+// The intermediate iterates never leave the workgroup: the pre-smoothing
+// reads r and D^-1 once and writes u3 and r1 (12.5 B per voxel instead of
+// 40.5 B over three kernels), the post-smoothing reads u3, e, r, D^-1 and the
+// stored r once and writes z (16.5 B + one stored value, instead of 44.5 B +
+// one).  Ring columns are computed by every tile that needs them, with the
+// same arithmetic.  The fused tiles are dealt to the XCDs in runs of about
+// eight tile rows (ftile_of), so neighbouring tiles' halo reads meet in L2.
+constexpr int kF3Max = 848;   // extended plane: (32 + 6)(16 + 6) = (16 + 6)(32 + 6) = 836
+
+struct F3Own {
+  int EX;
+  int p[2];      // LDS index of the owned columns: tile column, ring column (-1: none)
+  int ring1;     // ring of the ring column (1..3; 4: none)
+  int col[2];    // column within a plane (-1: outside the lattice)
+};
+
+// Ring column k (rings 1, 2, 3 in turn; each ring top row, bottom row, left
+// and right column) of a tx x ty tile: LDS index and ring, or ring 4 if none.
+__device__ inline void f3_ring_cell(int k, int tx, int ty, int EX, int& p, int& ring) {
+  for (int rho = 1; rho <= 3; ++rho) {
+    const int w = tx + 2 * rho, h = ty + 2 * rho - 2, n = 2 * w + 2 * h;
+    if (k < n) {
+      const int o = 3 - rho;   // the ring's first row and column in the extended tile
+      int hx, hy;
+      if (k < w) {
+        hx = o + k;
+        hy = o;
+      } else if (k < 2 * w) {
+        hx = o + k - w;
+        hy = o + h + 1;
+      } else if (k < 2 * w + h) {
+        hx = o;
+        hy = o + 1 + k - 2 * w;
+      } else {
+        hx = o + w - 1;
+        hy = o + 1 + k - 2 * w - h;
+      }
+      p = hy * EX + hx;
+      ring = rho;
+      return;
+    }
+    k -= n;
+  }
+  p = -1;
+  ring = 4;
+}
+
+__device__ inline F3Own f3_own(const Tile& t, const MgRep& m) {
+  F3Own f;
+  const int tx = m.tx, ty = kF3Block / tx;
+  f.EX = tx + 6;
+  const int q = (int)threadIdx.x;
+  f.p[0] = (q / tx + 3) * f.EX + q % tx + 3;
+  constexpr int nw = kF3Block / 64;
+  f3_ring_cell((q & 63) * nw + (q >> 6), tx, ty, f.EX, f.p[1], f.ring1);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    f.col[j] = -1;
+    if (f.p[j] >= 0) {
+      const int x = t.x0 + f.p[j] % f.EX - 3, y = t.y0 + f.p[j] / f.EX - 3;
+      if (x >= 0 && x < m.nx && y >= 0 && y < m.ny) f.col[j] = x + m.nx * y;
+    }
+  }
+  return f;
+}
+
+// Shift a plane history (index 0 the newest).  (Unrolling the steps by four
+// so that the history slots become compile-time indices removes these moves
+// but holds more registers, and measured slower; so did compile-time tile
+// widths.)
+template <int N>
+__device__ inline void f3_push(float (&h)[N], float v) {
+#pragma unroll
+  for (int k = N - 1; k > 0; --k) h[k] = h[k - 1];
+  h[0] = v;
+}
+
+// Sum of the x/y neighbours of LDS cell p in plane buffer b.
+__device__ inline float f3_xy(const float* b, int p, int EX) {
+  return (b[p - 1] + b[p + 1]) + (b[p - EX] + b[p + EX]);
+}
+
+// ring of slot j's column (slot 0: the tile column)
+#define F3_RING(j) ((j) == 0 ? 0 : f.ring1)
+
+template <typename RT>
+__global__ void __launch_bounds__(kF3Block) k_mg_pre3(MgLevel Lk, MgLevel Lc, float w0, float w1, float w2,
+                                                      const float* __restrict__ r, const SolveScal* ss) {
+  __shared__ float sV0[2][kF3Max], sV1[2][kF3Max], sV2[2][kF3Max];
+  const int ti = ftile_of(Lk.nftiles, Lk.fchunk);
+  if (ti < 0) return;
+  const Tile t = Lk.ftiles[ti];
+  if (ss[t.rep].done) return;
+  const MgRep m = Lk.reps[t.rep];
+  const MgRep mc = Lc.reps[t.rep];
+  const F3Own f = f3_own(t, m);
+  const int EX = f.EX, nz = m.nz, tx = m.tx;
+  const float a = m.a;
+  const int plane = m.nx * m.ny;   // a system's level 0 holds < 2^31 cells
+  const float* __restrict__ rS = r + m.off;
+  const float* __restrict__ dS = Lk.dinv + m.off;
+  float* __restrict__ uS = Lk.u + m.off;
+  const int z0 = t.z0, z1 = t.z1;
+  float rh[2][4], dh[2][4];             // r, D^-1 of planes z+3, z+2, z+1, z
+  float h0[2][3], h1[2][3], h2[2][3];   // stage outputs, newest first
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      rh[j][k] = dh[j][k] = 0.f;
+      if (k < 3) h0[j][k] = h1[j][k] = h2[j][k] = 0.f;
+    }
+  float nr[2], nd[2];   // stage-0 operands of the next plane
+  auto fetch = [&](int z) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      nr[j] = 0.f;
+      nd[j] = 0.f;
+      if (f.col[j] >= 0 && z >= 0 && z < nz) {
+        const int i = plane * z + f.col[j];
+        nr[j] = rS[i];
+        nd[j] = dS[i];
+      }
+    }
+  };
+  const int lx = (int)threadIdx.x % tx, ly = (int)threadIdx.x / tx;
+  const int x = t.x0 + lx, y = t.y0 + ly;
+  const bool lead = ((lx | ly) & 1) == 0 && f.col[0] >= 0;
+  float acc = 0.f;
+  fetch(z0 - 3);
+  for (int zz = z0 - 6; zz < z1; ++zz) {
+    const int wb = (zz + 6) & 1, rb = wb ^ 1;   // write this step's planes, read the last step's
+    {   // stage 0 at plane zz + 3: u1 = w0 D^-1 r
+      const int z = zz + 3;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        if (F3_RING(j) > 3) continue;
+        f3_push(rh[j], nr[j]);
+        f3_push(dh[j], nd[j]);
+        const float v = w0 * nd[j] * nr[j];
+        f3_push(h0[j], v);
+        sV0[wb][f.p[j]] = v;
+      }
+      if (z + 1 <= z1 + 2) fetch(z + 1);
+    }
+    {   // stage 1 at plane zz + 2: u2 (rings 0..2)
+      const int z = zz + 2;
+      if (z >= z0 - 2 && z <= z1 + 1) {
+        const bool in = z >= 0 && z < nz;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if (F3_RING(j) > 2) continue;
+          float v = 0.f;
+          if (in && f.col[j] >= 0) {
+            const float nb = f3_xy(sV0[rb], f.p[j], EX) + (h0[j][2] + h0[j][0]);
+            v = (1.f - w1) * h0[j][1] + w1 * dh[j][1] * (rh[j][1] + a * nb);
+          }
+          f3_push(h1[j], v);
+          sV1[wb][f.p[j]] = v;
+        }
+      }
+    }
+    {   // stage 2 at plane zz + 1: u3 (rings 0..1), the tile's columns to u
+      const int z = zz + 1;
+      if (z >= z0 - 1 && z <= z1) {
+        const bool in = z >= 0 && z < nz;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if (F3_RING(j) > 1) continue;
+          float v = 0.f;
+          if (in && f.col[j] >= 0) {
+            const float nb = f3_xy(sV1[rb], f.p[j], EX) + (h1[j][2] + h1[j][0]);
+            v = (1.f - w2) * h1[j][1] + w2 * dh[j][2] * (rh[j][2] + a * nb);
+            if (j == 0 && z >= z0 && z < z1) uS[plane * z + f.col[0]] = v;
+          }
+          f3_push(h2[j], v);
+          sV2[wb][f.p[j]] = v;
+        }
+      }
+    }
+    if (zz >= z0) {   // stage 3 at plane zz: r - A u3, summed into level 1's r
+      const int z = zz;
+      float res = 0.f;
+      if (f.col[0] >= 0) {
+        const float nb = f3_xy(sV2[rb], f.p[0], EX) + (h2[0][2] + h2[0][0]);
+        res = rh[0][3] - h2[0][1] * __builtin_amdgcn_rcpf(dh[0][3]) + a * nb;
+      }
+      float q = res + __shfl_xor(res, 1, 64);
+      q = q + __shfl_xor(q, tx, 64);
+      acc += q;
+      if ((z & 1) || z + 1 == nz) {
+        if (lead)
+          Lc.r[mc.off + (x >> 1) + (long long)mc.nx * ((y >> 1) + (long long)mc.ny * (z >> 1))] = acc;
+        acc = 0.f;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename RT, typename ST>
+__global__ void __launch_bounds__(kF3Block) k_mg_post3(MgLevel Lk, MgLevel Lc, float w2, float w1, float w0,
+                                                       const float* __restrict__ r, const RT* __restrict__ r64,
+                                                       SolverBufsT<ST> sb) {
+  __shared__ double lds8[kF3Block / 64];
+  __shared__ float sV0[2][kF3Max], sV1[2][kF3Max], sV2[2][kF3Max];
+  __shared__ float sE[4][kF3Max];   // coarse plane Z interpolated in x, y (slot Z & 3); owner-private
+  const int ti = ftile_of(Lk.nftiles, Lk.fchunk);
+  if (ti < 0) return;
+  const Tile t = Lk.ftiles[ti];
+  if (sb.ss[t.rep].done) return;
+  const MgRep m = Lk.reps[t.rep];
+  const MgRep mc = Lc.reps[t.rep];
+  const F3Own f = f3_own(t, m);
+  const int EX = f.EX, nz = m.nz;
+  const float a = m.a;
+  const int plane = m.nx * m.ny;
+  const float* __restrict__ rS = r + m.off;
+  const float* __restrict__ dS = Lk.dinv + m.off;
+  const float* __restrict__ uS = Lk.u + m.off;
+  const RT* __restrict__ r64S = r64 + m.off;
+  float* __restrict__ zS = sb.z32 + m.off;
+  const int z0 = t.z0, z1 = t.z1;
+  const double isc = sb.ss[t.rep].isc;
+  const float* __restrict__ eb = Lc.u + mc.off;
+  const int csz = mc.nx * mc.ny;
+  // E of coarse plane Z at the owned columns
+  auto make_e = [&](int Z) {
+    const float* b = eb + csz * Z;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (f.col[j] < 0) continue;
+      int Ix, Jx, Iy, Jy;
+      float wx, wy;
+      lin_axis(t.x0 + f.p[j] % EX - 3, m.nx, mc.nx, Ix, Jx, wx);
+      lin_axis(t.y0 + f.p[j] / EX - 3, m.ny, mc.ny, Iy, Jy, wy);
+      const float g0 = b[Iy * mc.nx + Ix], g1 = b[Iy * mc.nx + Jx];
+      const float g2 = b[Jy * mc.nx + Ix], g3 = b[Jy * mc.nx + Jx];
+      const float e0 = (1.f - wx) * g0 + wx * g1;
+      const float e1 = (1.f - wx) * g2 + wx * g3;
+      sE[Z & 3][f.p[j]] = (1.f - wy) * e0 + wy * e1;
+    }
+  };
+  int ehi = -(1 << 20);   // highest coarse plane in sE
+  float rh[2][4], dh[2][4];
+  float h0[2][3], h1[2][3], h2[2][3];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      rh[j][k] = dh[j][k] = 0.f;
+      if (k < 3) h0[j][k] = h1[j][k] = h2[j][k] = 0.f;
+    }
+  float nu[2], nr[2], nd[2];
+  auto fetch = [&](int z) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      nu[j] = 0.f;
+      nr[j] = 0.f;
+      nd[j] = 0.f;
+      if (f.col[j] >= 0 && z >= 0 && z < nz) {
+        const int i = plane * z + f.col[j];
+        nu[j] = uS[i];
+        nr[j] = rS[i];
+        nd[j] = dS[i];
+      }
+    }
+  };
+  RT r64n = (RT)0;   // the stored r of the tile column, next stage-3 plane
+  auto fetch64 = [&](int z) {
+    if (f.col[0] >= 0 && z >= z0 && z < z1) r64n = r64S[plane * z + f.col[0]];
+  };
+  double rz = 0.0;
+  fetch(z0 - 3);
+  for (int zz = z0 - 6; zz < z1; ++zz) {
+    const int wb = (zz + 6) & 1, rb = wb ^ 1;
+    const RT r64c = r64n;
+    fetch64(zz + 1);
+    {   // stage 0 at plane zz + 3: u3 + P e
+      const int z = zz + 3;
+      int Iz = 0, Jz = 0;
+      float wz = 0.f;
+      const bool in = z >= 0 && z < nz;
+      if (in) {
+        lin_axis(z, nz, mc.nz, Iz, Jz, wz);
+        if (ehi < min(Iz, Jz) - 1) ehi = min(Iz, Jz) - 1;
+        while (ehi < max(Iz, Jz)) make_e(++ehi);
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        if (F3_RING(j) > 3) continue;
+        f3_push(rh[j], nr[j]);
+        f3_push(dh[j], nd[j]);
+        float v = 0.f;
+        if (in && f.col[j] >= 0) {
+          const float eI = sE[Iz & 3][f.p[j]];
+          v = nu[j] + (Jz == Iz ? eI : (1.f - wz) * eI + wz * sE[Jz & 3][f.p[j]]);
+        }
+        f3_push(h0[j], v);
+        sV0[wb][f.p[j]] = v;
+      }
+      if (z + 1 <= z1 + 2) fetch(z + 1);
+    }
+    {   // stage 1 at plane zz + 2 (rings 0..2)
+      const int z = zz + 2;
+      if (z >= z0 - 2 && z <= z1 + 1) {
+        const bool in = z >= 0 && z < nz;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if (F3_RING(j) > 2) continue;
+          float v = 0.f;
+          if (in && f.col[j] >= 0) {
+            const float nb = f3_xy(sV0[rb], f.p[j], EX) + (h0[j][2] + h0[j][0]);
+            v = (1.f - w2) * h0[j][1] + w2 * dh[j][1] * (rh[j][1] + a * nb);
+          }
+          f3_push(h1[j], v);
+          sV1[wb][f.p[j]] = v;
+        }
+      }
+    }
+    {   // stage 2 at plane zz + 1 (rings 0..1)
+      const int z = zz + 1;
+      if (z >= z0 - 1 && z <= z1) {
+        const bool in = z >= 0 && z < nz;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if (F3_RING(j) > 1) continue;
+          float v = 0.f;
+          if (in && f.col[j] >= 0) {
+            const float nb = f3_xy(sV1[rb], f.p[j], EX) + (h1[j][2] + h1[j][0]);
+            v = (1.f - w1) * h1[j][1] + w1 * dh[j][2] * (rh[j][2] + a * nb);
+          }
+          f3_push(h2[j], v);
+          sV2[wb][f.p[j]] = v;
+        }
+      }
+    }
+    if (zz >= z0 && f.col[0] >= 0) {   // stage 3 at plane zz: z of the CG and r.z
+      const float nb = f3_xy(sV2[rb], f.p[0], EX) + (h2[0][2] + h2[0][0]);
+      const float v = (1.f - w0) * h2[0][1] + w0 * dh[0][3] * (rh[0][3] + a * nb);
+      zS[plane * zz + f.col[0]] = v;
+      rz += (double)r64c * ((double)v * isc);
+    }
+    __syncthreads();
+  }
+  // the tile's r.z partial (fixed order)
+  for (int o = 32; o > 0; o >>= 1) rz += __shfl_xor(rz, o, 64);
+  if ((threadIdx.x & 63) == 0) lds8[threadIdx.x >> 6] = rz;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tsum = 0.0;
+    for (int k = 0; k < kF3Block / 64; ++k) tsum += lds8[k];
+    store_partials(sb.partial + (size_t)ti * 3, tsum, 0.0, 0.0);
+  }
+}
+
+#undef F3_RING
+
 // ---- coarse levels: one workgroup per system, in LDS --------------------------
 
 struct CoarseLevel {
@@ -1049,7 +1432,14 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
   auto H = [&](int seg, int begin) {
     if (hook) hook(hctx, seg, begin);
   };
-  {
+  if (mg.fused) {
+    const MgLevel& L = mg.lev[0];
+    const MgLevel& C = mg.lev[1];
+    H(MG_PRE3_0, 1);
+    hca_launch(k_mg_pre3<float>, dim3(grid_ftiles(L.nftiles, L.fchunk)), dim3(kF3Block), 0, s, L, C, w0[0],
+               w0[1], w0[2], (const float*)sb.r32, ss);
+    H(MG_PRE3_0, 0);
+  } else {
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_PRE0, 1);
@@ -1095,7 +1485,15 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
     }
     H(MG_UP, 0);
   }
-  {
+  if (mg.fused) {
+    const MgLevel& L = mg.lev[0];
+    const MgLevel& C = mg.lev[1];
+    H(MG_POST3_0, 1);
+    hca_launch((k_mg_post3<T, T>), dim3(grid_ftiles(L.nftiles, L.fchunk)), dim3(kF3Block), 0, s, L, C, w0[2],
+               w0[1], w0[0], (const float*)sb.r32, (const T*)sb.r, sb);
+    H(MG_POST3_0, 0);
+    launch_cg_reduce(s, w, sb, RED_RZF, 0.0, 0);
+  } else {
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_POST1_0, 1);

@@ -412,8 +412,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_reduce(Work w, SolverBufsT<T> sb,
   }
   const RepDev rp = w.reps[rep];
   const bool tiles = KIND != RED_UPDATE;
-  const int b0 = tiles ? rp.tile_b0 : rp.flat_b0;
-  const int nb = tiles ? rp.tile_nb : rp.flat_nb;
+  const int b0 = KIND == RED_RZF ? rp.ftile_b0 : tiles ? rp.tile_b0 : rp.flat_b0;
+  const int nb = KIND == RED_RZF ? rp.ftile_nb : tiles ? rp.tile_nb : rp.flat_nb;
   const double t0 = sum_partials(sb.partial, b0, nb, 0, lds4);
   const double t1 = (KIND == RED_START || KIND == RED_UPDATE) ? sum_partials(sb.partial, b0, nb, 1, lds4) : 0.0;
   const double t2 = (KIND == RED_START || KIND == RED_UPDATE) ? sum_partials(sb.partial, b0, nb, 2, lds4) : 0.0;
@@ -465,7 +465,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_reduce(Work w, SolverBufsT<T> sb,
       s.done = 1;
       atomicAdd(sb.ndone, 1);
     }
-  } else {   // RED_RZ: r.z' of the preconditioner, beta of the flexible CG
+  } else {   // RED_RZ, RED_RZF: r.z' of the preconditioner, beta of the flexible CG
     s.rzn = t0;
     s.beta = s.first ? 0.0 : (t0 - s.rzo) / s.rz;
     s.rz = t0;
@@ -487,6 +487,9 @@ void launch_cg_reduce(hipStream_t s, const Work& w, const SolverBufsT<T>& sb, in
       break;
     case RED_UPDATE:
       hca_launch(k_cg_reduce<RED_UPDATE, T>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
+      break;
+    case RED_RZF:
+      hca_launch(k_cg_reduce<RED_RZF, T>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);
       break;
     default:
       hca_launch(k_cg_reduce<RED_RZ, T>, g, b, 0, s, w, sb, rtol, maxit, fm, nrep);

@@ -66,14 +66,15 @@ enum KernelClass {
   KC_PLASMA = 0, KC_SETUP, KC_CG_START, KC_CG_APPLY, KC_CG_UPDATE, KC_ODE,
   KC_CA_PROPOSE, KC_CA_RESOLVE, KC_CA_FINALIZE, KC_STATS,
   KC_MG_PREP, KC_MG_PRE0, KC_MG_RESTRICT0, KC_MG_LEVELS, KC_MG_COARSE, KC_MG_POST1_0,
-  KC_MG_POST2_0, KC_MLP_APPLY, KC_VESSEL, KC_MG_SWEEP0, KC_COUNT
+  KC_MG_POST2_0, KC_MLP_APPLY, KC_VESSEL, KC_MG_SWEEP0, KC_MG_PRE3_0, KC_MG_POST3_0, KC_COUNT
 };
 
 [[maybe_unused]] const char* kKernelNames[KC_COUNT] = {
     "k_plasma", "k_setup_step", "k_cg_start", "k_cg_apply", "k_cg_update",
     "k_ode", "k_ca_propose", "k_ca_resolve", "k_ca_finalize", "k_stats",
     "k_mg_prep0+k_mg_coarsen", "k_mg_pre<L0>", "k_mg_restrict<L0>", "mg levels >= 1 (global)",
-    "k_mg_coarse", "k_mg_post1<L0>", "k_mg_post2<L0>", "k_mlp_apply", "k_vessel", "k_mg_sweep<L0>"};
+    "k_mg_coarse", "k_mg_post1<L0>", "k_mg_post2<L0>", "k_mlp_apply", "k_vessel", "k_mg_sweep<L0>",
+    "k_mg_pre3<L0>", "k_mg_post3<L0>"};
 
 // Compulsory (algorithmic) HBM bytes per voxel of each kernel class; solver
 // classes per voxel of each active system (0: not priced, latency-bound).
@@ -101,7 +102,9 @@ const double kBytesPerVoxel[KC_COUNT] = {
     12.0 + kE,      // mg post2 L0: read ualt, r, dinv; write z (4)
     49.0 + 3 * kE,  // mlp apply: read L, K, G1, G2, P, Vc, phi; write P, Vc, phi
     9.0 + kE,       // vessel: read L, w, V (writes only where a vessel changes)
-    16.0};          // mg sweep L0: read u (4), r (4), dinv (4); write u' (4)
+    16.0,           // mg sweep L0: read u (4), r (4), dinv (4); write u' (4)
+    12.5,           // mg pre3 L0 (fused): read r (4), dinv (4); write u3 (4), r1 (1/8 of 4)
+    16.5 + kE};     // mg post3 L0 (fused): read u3 (4), e (1/8), r (4), dinv (4), r (stored); write z (4)
 constexpr double kBytesSetupVegf = 8.0 + 3 * kE;   // setup_step with vegf: + read V, Vc; write c, b
 constexpr double kBytesSetupDrug3 = 3 * kE;        // setup_step with drug3: + read G3; write c, b
 constexpr double kBytesStatsField = kE;            // stats: per extra field scanned (V, G3)
@@ -169,6 +172,9 @@ struct Ctx : ::hca_ctx {
   RepDev* d_sys = nullptr;
   FlatBlk* d_sflat = nullptr;
   Tile* d_stiles = nullptr;
+  Tile* d_ftiles = nullptr;        // level 0's fused-smoothing tiles (systems)
+  int nftiles_all = 0, nftiles1 = 0;
+  int fchunk = 16;                 // fused tiles per XCD run
   Work sys_all{}, sys1{};
   std::vector<long long> sys_n;
   Counters* d_cnt = nullptr;
@@ -325,7 +331,7 @@ void prof_flush(Ctx* c, const SolveScal* ss, int nsys) {
 // Event pairs around the V-cycle's launch segments.
 struct MgProf {
   Ctx* c;
-  hipEvent_t start[8];
+  hipEvent_t start[10];   // per MgSegment
   int tag;
 };
 
@@ -337,6 +343,8 @@ int mg_segment_class(int seg) {
     case MG_POST1_0: return KC_MG_POST1_0;
     case MG_POST2_0: return KC_MG_POST2_0;
     case MG_SWEEP0: return KC_MG_SWEEP0;
+    case MG_PRE3_0: return KC_MG_PRE3_0;
+    case MG_POST3_0: return KC_MG_POST3_0;
     default: return KC_MG_LEVELS;
   }
 }
@@ -793,7 +801,7 @@ hca_status validate_params(const hca_params* p, std::string& msg) {
       p->b_int[1] > 64 || p->ode_substeps < 1 || p->cg_maxit < 1 || p->init_maxit < 1 ||
       (p->precond != 0 && p->precond != 1) || p->mg_coarse_max < 1 || p->profile < 0 ||
       p->profile > KC_COUNT + 1 || (p->graphs != 0 && p->graphs != 1) ||
-      (p->autotune != 0 && p->autotune != 1)) {
+      (p->autotune != 0 && p->autotune != 1) || (p->mg_fuse != 0 && p->mg_fuse != 1)) {
     msg = "integer parameter out of range";
     return HCA_E_INVALID;
   }
@@ -854,6 +862,16 @@ int even_depth(int tz, int nz) {
   return std::max(2, tz & ~1);
 }
 
+// Depth of level 0's fused-smoothing tiles: each tile recomputes three planes
+// below and above its own, so deeper tiles (up to 64 planes) while a system
+// still has about 512 of them.
+int fused_depth(int nx, int ny, int nz, int tx) {
+  const int ty = kF3Block / tx;
+  const double nxy = (double)((nx + tx - 1) / tx) * (double)((ny + ty - 1) / ty);
+  const int tz = (int)std::floor(nz * nxy / 512.0);
+  return even_depth(std::max(8, std::min(64, tz)), nz);
+}
+
 int pick_tz(int nx, int ny, int nz, int tx, double target) {
   const int ty = kBlock / tx;
   const double nxy = (double)((nx + tx - 1) / tx) * (double)((ny + ty - 1) / ty);
@@ -861,8 +879,8 @@ int pick_tz(int nx, int ny, int nz, int tx, double target) {
   return std::max(1, std::min(16, tz));
 }
 
-void add_tiles(std::vector<Tile>& v, int rep, int nx, int ny, int nz, int tx, int tz) {
-  const int ty = kBlock / tx;
+void add_tiles(std::vector<Tile>& v, int rep, int nx, int ny, int nz, int tx, int tz, int ty = 0) {
+  if (ty == 0) ty = kBlock / tx;
   for (int z0 = 0; z0 < nz; z0 += tz)
     for (int y0 = 0; y0 < ny; y0 += ty)
       for (int x0 = 0; x0 < nx; x0 += tx) {
@@ -1101,13 +1119,20 @@ hca_status build_tables(Ctx* c, const hca_replicate* in) {
   {
     std::vector<RepDev> sd;
     std::vector<FlatBlk> flat;
-    std::vector<Tile> tiles;
-    int nflat1 = 0, ntiles1 = 0;
+    std::vector<Tile> tiles, ftiles;
+    int nflat1 = 0, ntiles1 = 0, nftiles1 = 0;
     c->sys_n.clear();
     for (int f = 0; f < c->dp.nf; ++f) {
       for (int r = 0; r < R; ++r) {
         RepDev d = lattice_entry(c->reps[r], (long long)f * c->ntot + c->reps[r].off, f * R + r,
                                  flat, tiles);
+        const RepHost& H = c->reps[r];
+        d.ftile_b0 = (int)ftiles.size();
+        add_tiles(ftiles, f * R + r, H.nx, H.ny, H.nz, H.tx, fused_depth(H.nx, H.ny, H.nz, H.tx),
+                  kF3Block / H.tx);
+        d.ftile_nb = (int)ftiles.size() - d.ftile_b0;
+        const int ftx = (H.nx + H.tx - 1) / H.tx;   // tiles per row
+        c->fchunk = std::max(c->fchunk, std::min(8 * ftx, 256));
         // the theta scheme's implicit coupling
         d.a = (f == 0 ? c->dp.aK : (c->dp.vegf && f == c->dp.fV) ? c->dp.aV : c->dp.aG) * c->dp.theta;
         sd.push_back(d);
@@ -1116,12 +1141,15 @@ hca_status build_tables(Ctx* c, const hca_replicate* in) {
       if (f == 0) {
         nflat1 = (int)flat.size();
         ntiles1 = (int)tiles.size();
+        nftiles1 = (int)ftiles.size();
       }
     }
     hca_status st;
     if ((st = upload(c, &c->d_sys, sd)) != HCA_OK || (st = upload(c, &c->d_sflat, flat)) != HCA_OK ||
-        (st = upload(c, &c->d_stiles, tiles)) != HCA_OK)
+        (st = upload(c, &c->d_stiles, tiles)) != HCA_OK || (st = upload(c, &c->d_ftiles, ftiles)) != HCA_OK)
       return st;
+    c->nftiles_all = (int)ftiles.size();
+    c->nftiles1 = nftiles1;
     c->sys_all.nreps = c->dp.nf * R;
     c->sys_all.reps = c->d_sys;
     c->sys_all.flat = c->d_sflat;
@@ -1183,7 +1211,7 @@ hca_status alloc_all(Ctx* c) {
   c->V = c->dp.vegf ? c->F + (size_t)c->dp.fV * n : nullptr;
   c->sb.jacobi = c->use_mg ? 0 : 1;
   if (!c->use_mg && (st = big(&c->sb.dinv, n3)) != HCA_OK) return st;
-  const size_t nwork = (size_t)std::max(c->sys_all.ntiles, c->sys_all.nflat);
+  const size_t nwork = (size_t)std::max({c->sys_all.ntiles, c->sys_all.nflat, c->nftiles_all});
   HIPCHK(c, dalloc(&c->sb.partial, 3 * nwork));
   HIPCHK(c, dalloc(&c->sb.counter, nsys));
   HIPCHK(c, hipMemset(c->sb.counter, 0, sizeof(unsigned) * nsys));
@@ -1286,6 +1314,7 @@ hca_status build_mg(Ctx* c) {
   // 6 iterations at 128^3, one on the coarser levels changes nothing.
   for (int k = 0; k < 3; ++k)
     mg.w0[k] = (float)(1.0 / (1.1 + 0.9 * std::cos((2 * k + 1) * M_PI / 6.0)));
+  mg.fused = c->prm.mg_fuse;
   c->mg1 = mg;
   std::vector<float*> pc(kMaxLevels, nullptr), pr(kMaxLevels, nullptr), pu(kMaxLevels, nullptr);
   std::vector<std::vector<MgRep>> mreps(nglob + 1);
@@ -1343,6 +1372,9 @@ hca_status build_mg(Ctx* c) {
       L.tiles = c->d_stiles;
       L.ntiles = c->sys_all.ntiles;
       ntiles1 = c->sys1.ntiles;
+      L.ftiles = c->d_ftiles;
+      L.nftiles = c->nftiles_all;
+      L.fchunk = c->fchunk;
       const size_t n = (size_t)c->dp.nf * c->ntot;
       if ((st = mg_alloc(c, &L.dinv, n)) != HCA_OK || (st = mg_alloc(c, &L.u, n)) != HCA_OK ||
           (st = mg_alloc(c, &L.ualt, n)) != HCA_OK)
@@ -1367,6 +1399,7 @@ hca_status build_mg(Ctx* c) {
     }
     c->mg1.lev[k] = L;
     c->mg1.lev[k].ntiles = ntiles1;
+    if (k == 0) c->mg1.lev[k].nftiles = c->nftiles1;
     c->mg1.lev[k].nrtiles = k == 0 ? 0 : nrtiles1;
   }
   int nglob1 = 1;
@@ -1451,7 +1484,7 @@ void free_all(Ctx* c) {
   void* bufs[] = {c->L, c->code, c->win, (void*)c->ca_list.cells, (void*)c->ca_list.item_n, c->w, c->P, c->Vc, c->phi, c->F, c->c, c->b,
                   c->sb.r, c->sb.z, (void*)c->sb.z32, (void*)c->sb.r32, c->sb.p0, c->sb.p1, c->sb.q, c->sb.dinv, c->sb.partial,
                   c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->b_o2lin, c->Fprev, c->d_step,
-                  c->d_reps, c->d_flat, c->d_tiles, c->d_sys, c->d_sflat, c->d_stiles, c->d_cnt, (void*)c->d_cpart,
+                  c->d_reps, c->d_flat, c->d_tiles, c->d_sys, c->d_sflat, c->d_stiles, c->d_ftiles, c->d_cnt, (void*)c->d_cpart,
                   c->d_bad, c->d_theta, (void*)c->d_pack, (void*)c->d_gelu, c->before,
                   c->item_cnt, c->item_off};
   for (void* p : bufs)
@@ -1842,6 +1875,7 @@ extern "C" hca_status hca_default_params(hca_params* out) {
   out->b_int3 = 1;
   out->x0_extrapolate = 2;
   out->precision = 64;
+  out->mg_fuse = 1;
   return HCA_OK;
 }
 #endif

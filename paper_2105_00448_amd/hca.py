@@ -49,6 +49,7 @@ class Params(C.Structure):
         ("G_ref3", C.c_double), ("b_int3", C.c_int32),
         ("x0_extrapolate", C.c_int32),
         ("precision", C.c_int32),
+        ("mg_fuse", C.c_int32),
     ]
 
 
