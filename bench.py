@@ -555,6 +555,22 @@ def train_surrogate(stream, train_steps, n_pairs=1_000_000):
             "batch": batch, "seconds": t_train, "samples_per_s": train_steps * batch / t_train,
             "tflops": train_steps * batch * flop_per_sample / t_train / 1e12,
             "loss_first": float(losses[:10].mean()), "loss_last": float(losses[-50:].mean())}
+    # throughput against the batch (workgroups per step = batch / 64), on a
+    # second trainer so that the network above is untouched
+    sweep = []
+    tr2 = hca.Trainer(X, Y, seed=2, stream=stream)
+    for b in (4096, 16384, 65536):
+        n = 50
+        tr2.train(2, batch=b, lr=1e-4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr2.train(n, batch=b, lr=1e-4)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sweep.append({"batch": b, "workgroups": b // 64, "us_per_step": dt / n * 1e6,
+                      "samples_per_s": n * b / dt, "tflops": n * b * flop_per_sample / dt / 1e12})
+    tr2.close()
+    info["batch_sweep"] = sweep
     return tr, tr.export(), info
 
 
