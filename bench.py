@@ -707,6 +707,32 @@ def roofline_of(kt_dom, dom, workload, elem=8):
     return r
 
 
+def stream_ceiling():
+    """Device-to-device streaming rates of plain torch kernels on 3.2 GB FP64
+    arrays (a copy: 1 read + 1 write; an add: 2 reads + 1 write): what a
+    simple streaming kernel attains on this GPU, beside the 8 TB/s peak."""
+    import torch
+    n = 400_000_000
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    c = torch.empty_like(a)
+    out = {}
+    for name, fn, nbytes in (("copy", lambda: b.copy_(a), 16 * n),
+                             ("add", lambda: torch.add(a, b, out=c), 24 * n)):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_gbs"] = nbytes * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
 def config5_headline(args, stream):
     """The metric's configuration: plain vs surrogate+batched on 4 x 384^3."""
     import torch
@@ -722,6 +748,8 @@ def config5_headline(args, stream):
     cell0, w0, seed0, sched0 = reps[0]
     crop = (np.ascontiguousarray(cell0[:32, :32, :32]), np.ascontiguousarray(w0[:32, :32, :32]),
             seed0, sched0)
+    ceiling = stream_ceiling()
+    print(f"[bench] streaming ceiling {ceiling}", file=sys.stderr, flush=True)
     tr, net, train_info = train_surrogate(stream, args.train_steps)
     kw = {"graphs": args.graphs}
 
@@ -806,7 +834,8 @@ def config5_headline(args, stream):
         "dtype": "f64",
         "data": "synthetic",
         "config": dict(cfg, mode="surrogate ODE + batched ensemble (4 replicates in one context)"),
-        "roofline": sur_rec["roofline"],
+        "roofline": dict(sur_rec["roofline"], stream_ceiling=ceiling,
+                         frac_of_stream_copy=sur_rec["roofline"]["achieved"] / ceiling["copy_gbs"]),
         "plain": {k: plain_rec[k] for k in ("value", "ms_per_step", "init_s", "cg_iters_last_step",
                                              "roofline", "hbm_whole_step", "ode_phase_ms")
                   if k in plain_rec},
