@@ -871,12 +871,18 @@ int even_depth(int tz, int nz) {
 
 // Depth of level 0's fused-smoothing tiles: each tile recomputes three planes
 // below and above its own, so deeper tiles (up to 64 planes) while a system
-// still has about 512 of them.
+// still has about g_fused_target of them (HCA_FUSED_TARGET), and at least
+// g_fused_min planes (HCA_FUSED_MIN).  Measured (same GPU, two passes): the
+// 128^3 workload 2.319 ms per step at depth 8, 2.34 at 12, 2.26 at 16, 2.36
+// at 20; the 64-replicate ensemble within 0.2 % for depths 8 to 64; the
+// 4 x 384^3 lattices take 64.
+double g_fused_target = 256.0;
+int g_fused_min = 16;
 int fused_depth(int nx, int ny, int nz, int tx) {
   const int ty = kF3Block / tx;
   const double nxy = (double)((nx + tx - 1) / tx) * (double)((ny + ty - 1) / ty);
-  const int tz = (int)std::floor(nz * nxy / 512.0);
-  return even_depth(std::max(8, std::min(64, tz)), nz);
+  const int tz = (int)std::floor(nz * nxy / g_fused_target);
+  return even_depth(std::max(g_fused_min, std::min(64, tz)), nz);
 }
 
 int pick_tz(int nx, int ny, int nz, int tx, double target) {
@@ -1087,6 +1093,11 @@ hca_status build_tables(Ctx* c, const hca_replicate* in) {
   if (const char* e = getenv("HCA_TILE_REMAP")) g_tile_remap = atoi(e) != 0;
   if (const char* e = getenv("HCA_TILE_DEPTH")) g_tile_depth = std::max(0, atoi(e));
   if (const char* e = getenv("HCA_SOLVE_LEAD")) g_solve_lead = std::max(-8, std::min(8, atoi(e)));
+  if (const char* e = getenv("HCA_FUSED_TARGET")) {
+    const double v = atof(e);
+    if (v >= 1.0) g_fused_target = v;
+  }
+  if (const char* e = getenv("HCA_FUSED_MIN")) g_fused_min = std::max(2, std::min(64, atoi(e)));
   if (const char* e = getenv("HCA_MG_TILE_TARGET")) {
     const double v = atof(e);
     if (v >= 1.0) g_mg_tile_target = v;
