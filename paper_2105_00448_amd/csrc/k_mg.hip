@@ -676,8 +676,10 @@ __global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float omega, co
 // the stages work on the planes z+3, z+2, z+1 and z.
 //
 // Each thread owns one tile column (lane layout of the other stencil
-// kernels) and at most one ring column (dealt round robin over the
-// wavefronts).  A column's values of the planes around the current ones (its
+// kernels) and at most one ring column: ring columns go to the threads in
+// order, ring 1 first, so that a wavefront's ring columns mostly share a ring
+// and the wavefront skips the stages its ring does not need (dealt round
+// robin over the wavefronts instead, every wavefront ran all three).  A column's values of the planes around the current ones (its
 // own z-neighbours, and r and D^-1 of the four planes in flight) stay in the
 // owner's registers; only the x/y neighbours go through LDS, one plane per
 // stage, double buffered: stage s in step z reads the plane stage s-1 wrote in
@@ -742,8 +744,7 @@ __device__ inline F3Own f3_own(const Tile& t, const MgRep& m) {
   f.EX = tx + 6;
   const int q = (int)threadIdx.x;
   f.p[0] = (q / tx + 3) * f.EX + q % tx + 3;
-  constexpr int nw = kF3Block / 64;
-  f3_ring_cell((q & 63) * nw + (q >> 6), tx, ty, f.EX, f.p[1], f.ring1);
+  f3_ring_cell(q, tx, ty, f.EX, f.p[1], f.ring1);
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     f.col[j] = -1;
