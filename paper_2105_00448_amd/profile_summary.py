@@ -26,7 +26,10 @@ SOURCES = ["paper_2105_00448_amd/csrc/k_solver.hip", "paper_2105_00448_amd/csrc/
 COPY_KIB = 256 * 1024
 # the counter passes collect only these dispatches (--kernel-include-regex)
 PMC_REGEX = ("k_cg_update|k_cg_apply|k_mg_pre|k_mg_sweep|k_mg_restrict|k_mg_post1|k_mg_post2|"
-             "k_mg_post3|k_init_cells|copyBuffer")
+             "k_mg_post3|k_mg_coarse|k_init_cells|copyBuffer")
+# kernels priced per launch (levels below level 0, the one-workgroup coarse solve)
+PER_LAUNCH = ["k_mg_pre<false, float>", "k_mg_restrict<false, float>", "k_mg_post1<false, float>",
+              "k_mg_post2<false, float, double>", "k_mg_post2<false, float, float>", "k_mg_coarse"]
 # voxels (of one system) of each workload, and its systems per solve
 WORKLOADS = {"config5": (384 ** 3, 4), "plain128": (128 ** 3, 1)}
 
@@ -137,6 +140,17 @@ def main(workload, precision, kt_dir, f_dir, w_dir, command):
         json.dump(rec, open(os.path.join(ROOT, "profiles", f"{short}_{tag}_traffic.json"), "w"), indent=1)
         table.append(f"| {full} | {len(full_disp)} | {fetch / vox:.2f} | {write / vox:.2f} | {mb:.2f} | "
                      f"{bpv:.1f} | {mb / bpv:.3f} |")
+    small = ["| kernel | dispatches | mean us | FETCH KiB/dispatch | WRITE KiB/dispatch | GB/s |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for full in PER_LAUNCH:
+        fd = [float(r["Counter_Value"]) for r in F if name(r) == full]
+        wd = [float(r["Counter_Value"]) for r in W if name(r) == full]
+        du = dur.get(full, [])
+        if not fd or not wd or not du:
+            continue
+        fk, wk, us = sum(fd) / len(fd) * ffac, sum(wd) / len(wd) * wfac, sum(du) / len(du)
+        small.append(f"| {full} | {len(fd)} | {us:.1f} | {fk:.0f} | {wk:.0f} | "
+                     f"{(fk + wk) * 1024 / (us * 1e-6) / 1e9:.0f} |")
     md = [f"# HBM traffic of the solver's streaming kernels: {tag}", "",
           "Commands (repository root, one MI355X), one counter per run:", "",
           "    " + pmc_command(command, "FETCH_SIZE"),
@@ -148,6 +162,8 @@ def main(workload, precision, kt_dir, f_dir, w_dir, command):
           f"Per voxel of all {3 * nrep} systems ({3 * nvox * nrep} voxels), on the dispatches where every",
           "system still iterates (counter within 10 % of the kernel's largest; later",
           "dispatches skip finished systems):", ""] + table + [
+          "", "Kernels below level 0 (latency-bound: bytes per dispatch over all systems, mean",
+          "duration from the kernel trace, effective rate):", ""] + small + [
           "", "`profiles/<kernel>_" + tag + "_traffic.json` hold these numbers with the SHA-256 of the",
           "solver's sources; `bench.py` reports them as `roofline.traffic` only while those",
           "sources are unchanged."]
