@@ -442,8 +442,9 @@ struct PWin {
 };
 
 template <bool L0, typename RT>
-__global__ void __launch_bounds__(kBlock) k_mg_post1(MgLevel Lk, MgLevel Lc, float omega,
-                                                     const RT* __restrict__ r, const SolveScal* ss) {
+__global__ void __launch_bounds__(kBlock) k_mg_post1(MgLevel Lk, MgLevel Lc, const float* __restrict__ e,
+                                                     float omega, const RT* __restrict__ r,
+                                                     const SolveScal* ss) {
   __shared__ float lds[2][kPlaneMaxF];
   float* __restrict__ out = Lk.ualt;
   const float* __restrict__ u = Lk.u;
@@ -485,7 +486,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_post1(MgLevel Lk, MgLevel Lc, flo
     const long long iidx = x + (long long)G.nx * y;
     const PCol ci = pcol(valid ? x : 0, valid ? y : 0, G.nx, G.ny, mc);
     const PCol cf = pcol(fin ? fx : 0, fin ? fy : 0, G.nx, G.ny, mc);
-    const float* __restrict__ eb = Lc.u + mc.off;
+    const float* __restrict__ eb = e + mc.off;
     const long long csz = (long long)mc.nx * mc.ny;
     auto gather = [&](const PCol& c, bool on, int Z, float (&g)[4]) {
       if (on && Z >= 0 && Z < mc.nz) {
@@ -700,20 +701,26 @@ __global__ void __launch_bounds__(kBlock) k_mg_post2(MgLevel Lk, float omega, co
 // eight tile rows (ftile_of), so neighbouring tiles' halo reads meet in L2.
 constexpr int kF3Max = 848;   // extended plane: (32 + 6)(16 + 6) = (16 + 6)(32 + 6) = 836
 
+// Weights of a fused pass's sweeps, in stage order.
+struct F3W {
+  float w[3];
+};
+
 struct F3Own {
   int EX;
   int p[2];      // LDS index of the owned columns: tile column, ring column (-1: none)
-  int ring1;     // ring of the ring column (1..3; 4: none)
+  int ring1;     // ring of the ring column (1..R; R + 1: none)
   int col[2];    // column within a plane (-1: outside the lattice)
 };
 
-// Ring column k (rings 1, 2, 3 in turn; each ring top row, bottom row, left
-// and right column) of a tx x ty tile: LDS index and ring, or ring 4 if none.
-__device__ inline void f3_ring_cell(int k, int tx, int ty, int EX, int& p, int& ring) {
-  for (int rho = 1; rho <= 3; ++rho) {
+// Ring column k (rings 1..R in turn; each ring top row, bottom row, left and
+// right column) of a tx x ty tile extended by R rings: LDS index and ring,
+// or ring R + 1 if none.
+__device__ inline void f3_ring_cell(int k, int tx, int ty, int R, int EX, int& p, int& ring) {
+  for (int rho = 1; rho <= R; ++rho) {
     const int w = tx + 2 * rho, h = ty + 2 * rho - 2, n = 2 * w + 2 * h;
     if (k < n) {
-      const int o = 3 - rho;   // the ring's first row and column in the extended tile
+      const int o = R - rho;   // the ring's first row and column in the extended tile
       int hx, hy;
       if (k < w) {
         hx = o + k;
@@ -735,31 +742,30 @@ __device__ inline void f3_ring_cell(int k, int tx, int ty, int EX, int& p, int& 
     k -= n;
   }
   p = -1;
-  ring = 4;
+  ring = R + 1;
 }
 
-__device__ inline F3Own f3_own(const Tile& t, const MgRep& m) {
+__device__ inline F3Own f3_own(const Tile& t, const MgRep& m, int R) {
   F3Own f;
   const int tx = m.tx, ty = kF3Block / tx;
-  f.EX = tx + 6;
+  f.EX = tx + 2 * R;
   const int q = (int)threadIdx.x;
-  f.p[0] = (q / tx + 3) * f.EX + q % tx + 3;
-  f3_ring_cell(q, tx, ty, f.EX, f.p[1], f.ring1);
+  f.p[0] = (q / tx + R) * f.EX + q % tx + R;
+  f3_ring_cell(q, tx, ty, R, f.EX, f.p[1], f.ring1);
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     f.col[j] = -1;
     if (f.p[j] >= 0) {
-      const int x = t.x0 + f.p[j] % f.EX - 3, y = t.y0 + f.p[j] / f.EX - 3;
+      const int x = t.x0 + f.p[j] % f.EX - R, y = t.y0 + f.p[j] / f.EX - R;
       if (x >= 0 && x < m.nx && y >= 0 && y < m.ny) f.col[j] = x + m.nx * y;
     }
   }
   return f;
 }
 
-// Shift a plane history (index 0 the newest).  (Unrolling the steps by four
-// so that the history slots become compile-time indices removes these moves
-// but holds more registers, and measured slower; so did compile-time tile
-// widths.)
+// Shift a plane history (index 0 the newest).  (Unrolling the steps so that
+// the history slots become compile-time indices removes these moves but holds
+// more registers, and measured slower; so did compile-time tile widths.)
 template <int N>
 __device__ inline void f3_push(float (&h)[N], float v) {
 #pragma unroll
@@ -775,33 +781,40 @@ __device__ inline float f3_xy(const float* b, int p, int EX) {
 // ring of slot j's column (slot 0: the tile column)
 #define F3_RING(j) ((j) == 0 ? 0 : f.ring1)
 
-template <typename RT>
-__global__ void __launch_bounds__(kF3Block) k_mg_pre3(MgLevel Lk, MgLevel Lc, float w0, float w1, float w2,
-                                                      const float* __restrict__ r, const SolveScal* ss) {
-  __shared__ float sV0[2][kF3Max], sV1[2][kF3Max], sV2[2][kF3Max];
+// Pre-smoothing and restriction of a uniform level (level 0, or a coarser
+// level whose cells are all full 2^k-cubes: coupling a 2^k) in one pass: S
+// stages (S = 3 at level 0, 2 below): u1 = w[0] D^-1 r, then sweeps w[1..S-1]
+// (the last one's tile cells written to u), then the residual r - A u summed
+// over the 2 x 2 x 2 children into the next level's r.
+template <int S>
+__global__ void __launch_bounds__(kF3Block) k_mg_prefused(MgLevel Lk, MgLevel Lc, F3W w, float ascale,
+                                                          const float* __restrict__ r, const SolveScal* ss) {
+  __shared__ float sV[S][2][kF3Max];
   const int ti = ftile_of(Lk.nftiles, Lk.fchunk);
   if (ti < 0) return;
   const Tile t = Lk.ftiles[ti];
   if (ss[t.rep].done) return;
   const MgRep m = Lk.reps[t.rep];
   const MgRep mc = Lc.reps[t.rep];
-  const F3Own f = f3_own(t, m);
+  const F3Own f = f3_own(t, m, S);
   const int EX = f.EX, nz = m.nz, tx = m.tx;
-  const float a = m.a;
-  const int plane = m.nx * m.ny;   // a system's level 0 holds < 2^31 cells
+  const float a = m.a * ascale;
+  const int plane = m.nx * m.ny;   // a system's level holds < 2^31 cells
   const float* __restrict__ rS = r + m.off;
   const float* __restrict__ dS = Lk.dinv + m.off;
   float* __restrict__ uS = Lk.u + m.off;
   const int z0 = t.z0, z1 = t.z1;
-  float rh[2][4], dh[2][4];             // r, D^-1 of planes z+3, z+2, z+1, z
-  float h0[2][3], h1[2][3], h2[2][3];   // stage outputs, newest first
+  float rh[2][S + 1], dh[2][S + 1];   // r, D^-1 of planes z+S .. z (newest first)
+  float hs[S][2][3];                  // stage outputs, newest first
 #pragma unroll
-  for (int j = 0; j < 2; ++j)
+  for (int j = 0; j < 2; ++j) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      rh[j][k] = dh[j][k] = 0.f;
-      if (k < 3) h0[j][k] = h1[j][k] = h2[j][k] = 0.f;
-    }
+    for (int k = 0; k <= S; ++k) rh[j][k] = dh[j][k] = 0.f;
+#pragma unroll
+    for (int st = 0; st < S; ++st)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) hs[st][j][k] = 0.f;
+  }
   float nr[2], nd[2];   // stage-0 operands of the next plane
   auto fetch = [&](int z) {
 #pragma unroll
@@ -819,63 +832,47 @@ __global__ void __launch_bounds__(kF3Block) k_mg_pre3(MgLevel Lk, MgLevel Lc, fl
   const int x = t.x0 + lx, y = t.y0 + ly;
   const bool lead = ((lx | ly) & 1) == 0 && f.col[0] >= 0;
   float acc = 0.f;
-  fetch(z0 - 3);
-  for (int zz = z0 - 6; zz < z1; ++zz) {
-    const int wb = (zz + 6) & 1, rb = wb ^ 1;   // write this step's planes, read the last step's
-    {   // stage 0 at plane zz + 3: u1 = w0 D^-1 r
-      const int z = zz + 3;
+  fetch(z0 - S);
+  for (int zz = z0 - 2 * S; zz < z1; ++zz) {
+    const int wb = (zz + 2 * S) & 1, rb = wb ^ 1;   // write this step's planes, read the last step's
+    {   // stage 0 at plane zz + S
+      const int z = zz + S;
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        if (F3_RING(j) > 3) continue;
+        if (F3_RING(j) > S) continue;
         f3_push(rh[j], nr[j]);
         f3_push(dh[j], nd[j]);
-        const float v = w0 * nd[j] * nr[j];
-        f3_push(h0[j], v);
-        sV0[wb][f.p[j]] = v;
+        const float v = w.w[0] * nd[j] * nr[j];
+        f3_push(hs[0][j], v);
+        sV[0][wb][f.p[j]] = v;
       }
-      if (z + 1 <= z1 + 2) fetch(z + 1);
+      if (z + 1 <= z1 + S - 1) fetch(z + 1);
     }
-    {   // stage 1 at plane zz + 2: u2 (rings 0..2)
-      const int z = zz + 2;
-      if (z >= z0 - 2 && z <= z1 + 1) {
+#pragma unroll
+    for (int st = 1; st < S; ++st) {   // sweep st at plane zz + S - st (rings 0 .. S - st)
+      const int z = zz + S - st;
+      if (z >= z0 - (S - st) && z <= z1 - 1 + (S - st)) {
         const bool in = z >= 0 && z < nz;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          if (F3_RING(j) > 2) continue;
+          if (F3_RING(j) > S - st) continue;
           float v = 0.f;
           if (in && f.col[j] >= 0) {
-            const float nb = f3_xy(sV0[rb], f.p[j], EX) + (h0[j][2] + h0[j][0]);
-            v = (1.f - w1) * h0[j][1] + w1 * dh[j][1] * (rh[j][1] + a * nb);
+            const float nb = f3_xy(sV[st - 1][rb], f.p[j], EX) + (hs[st - 1][j][2] + hs[st - 1][j][0]);
+            v = (1.f - w.w[st]) * hs[st - 1][j][1] + w.w[st] * dh[j][st] * (rh[j][st] + a * nb);
+            if (st == S - 1 && j == 0 && z >= z0 && z < z1) uS[plane * z + f.col[0]] = v;
           }
-          f3_push(h1[j], v);
-          sV1[wb][f.p[j]] = v;
+          f3_push(hs[st][j], v);
+          sV[st][wb][f.p[j]] = v;
         }
       }
     }
-    {   // stage 2 at plane zz + 1: u3 (rings 0..1), the tile's columns to u
-      const int z = zz + 1;
-      if (z >= z0 - 1 && z <= z1) {
-        const bool in = z >= 0 && z < nz;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          if (F3_RING(j) > 1) continue;
-          float v = 0.f;
-          if (in && f.col[j] >= 0) {
-            const float nb = f3_xy(sV1[rb], f.p[j], EX) + (h1[j][2] + h1[j][0]);
-            v = (1.f - w2) * h1[j][1] + w2 * dh[j][2] * (rh[j][2] + a * nb);
-            if (j == 0 && z >= z0 && z < z1) uS[plane * z + f.col[0]] = v;
-          }
-          f3_push(h2[j], v);
-          sV2[wb][f.p[j]] = v;
-        }
-      }
-    }
-    if (zz >= z0) {   // stage 3 at plane zz: r - A u3, summed into level 1's r
+    if (zz >= z0) {   // stage S at plane zz: r - A u, summed into the next level's r
       const int z = zz;
       float res = 0.f;
       if (f.col[0] >= 0) {
-        const float nb = f3_xy(sV2[rb], f.p[0], EX) + (h2[0][2] + h2[0][0]);
-        res = rh[0][3] - h2[0][1] * __builtin_amdgcn_rcpf(dh[0][3]) + a * nb;
+        const float nb = f3_xy(sV[S - 1][rb], f.p[0], EX) + (hs[S - 1][0][2] + hs[S - 1][0][0]);
+        res = rh[0][S] - hs[S - 1][0][1] * __builtin_amdgcn_rcpf(dh[0][S]) + a * nb;
       }
       float q = res + __shfl_xor(res, 1, 64);
       q = q + __shfl_xor(q, tx, 64);
@@ -890,12 +887,17 @@ __global__ void __launch_bounds__(kF3Block) k_mg_pre3(MgLevel Lk, MgLevel Lc, fl
   }
 }
 
-template <typename RT, typename ST>
-__global__ void __launch_bounds__(kF3Block) k_mg_post3(MgLevel Lk, MgLevel Lc, float w2, float w1, float w0,
-                                                       const float* __restrict__ r, const RT* __restrict__ r64,
-                                                       SolverBufsT<ST> sb) {
+// Prolongation and post-smoothing of a uniform level in one pass: stage 0
+// u + P e (e the next level's correction), then S sweeps w[0..S-1].  ZOUT
+// (level 0): the last sweep is the CG's z (FP32, scaled) and feeds the tile's
+// r.z partial; otherwise it is written to out.
+template <int S, bool ZOUT, typename RT, typename ST>
+__global__ void __launch_bounds__(kF3Block) k_mg_postfused(MgLevel Lk, MgLevel Lc, const float* __restrict__ e,
+                                                           F3W w, float ascale, const float* __restrict__ r,
+                                                           const RT* __restrict__ r64, float* __restrict__ out,
+                                                           SolverBufsT<ST> sb) {
   __shared__ double lds8[kF3Block / 64];
-  __shared__ float sV0[2][kF3Max], sV1[2][kF3Max], sV2[2][kF3Max];
+  __shared__ float sV[S][2][kF3Max];
   __shared__ float sE[4][kF3Max];   // coarse plane Z interpolated in x, y (slot Z & 3); owner-private
   const int ti = ftile_of(Lk.nftiles, Lk.fchunk);
   if (ti < 0) return;
@@ -903,18 +905,16 @@ __global__ void __launch_bounds__(kF3Block) k_mg_post3(MgLevel Lk, MgLevel Lc, f
   if (sb.ss[t.rep].done) return;
   const MgRep m = Lk.reps[t.rep];
   const MgRep mc = Lc.reps[t.rep];
-  const F3Own f = f3_own(t, m);
+  const F3Own f = f3_own(t, m, S);
   const int EX = f.EX, nz = m.nz;
-  const float a = m.a;
+  const float a = m.a * ascale;
   const int plane = m.nx * m.ny;
   const float* __restrict__ rS = r + m.off;
   const float* __restrict__ dS = Lk.dinv + m.off;
   const float* __restrict__ uS = Lk.u + m.off;
-  const RT* __restrict__ r64S = r64 + m.off;
-  float* __restrict__ zS = sb.z32 + m.off;
   const int z0 = t.z0, z1 = t.z1;
-  const double isc = sb.ss[t.rep].isc;
-  const float* __restrict__ eb = Lc.u + mc.off;
+  const double isc = ZOUT ? sb.ss[t.rep].isc : 1.0;
+  const float* __restrict__ eb = e + mc.off;
   const int csz = mc.nx * mc.ny;
   // E of coarse plane Z at the owned columns
   auto make_e = [&](int Z) {
@@ -924,8 +924,8 @@ __global__ void __launch_bounds__(kF3Block) k_mg_post3(MgLevel Lk, MgLevel Lc, f
       if (f.col[j] < 0) continue;
       int Ix, Jx, Iy, Jy;
       float wx, wy;
-      lin_axis(t.x0 + f.p[j] % EX - 3, m.nx, mc.nx, Ix, Jx, wx);
-      lin_axis(t.y0 + f.p[j] / EX - 3, m.ny, mc.ny, Iy, Jy, wy);
+      lin_axis(t.x0 + f.p[j] % EX - S, m.nx, mc.nx, Ix, Jx, wx);
+      lin_axis(t.y0 + f.p[j] / EX - S, m.ny, mc.ny, Iy, Jy, wy);
       const float g0 = b[Iy * mc.nx + Ix], g1 = b[Iy * mc.nx + Jx];
       const float g2 = b[Jy * mc.nx + Ix], g3 = b[Jy * mc.nx + Jx];
       const float e0 = (1.f - wx) * g0 + wx * g1;
@@ -934,15 +934,17 @@ __global__ void __launch_bounds__(kF3Block) k_mg_post3(MgLevel Lk, MgLevel Lc, f
     }
   };
   int ehi = -(1 << 20);   // highest coarse plane in sE
-  float rh[2][4], dh[2][4];
-  float h0[2][3], h1[2][3], h2[2][3];
+  float rh[2][S + 1], dh[2][S + 1];
+  float hs[S][2][3];
 #pragma unroll
-  for (int j = 0; j < 2; ++j)
+  for (int j = 0; j < 2; ++j) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      rh[j][k] = dh[j][k] = 0.f;
-      if (k < 3) h0[j][k] = h1[j][k] = h2[j][k] = 0.f;
-    }
+    for (int k = 0; k <= S; ++k) rh[j][k] = dh[j][k] = 0.f;
+#pragma unroll
+    for (int st = 0; st < S; ++st)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) hs[st][j][k] = 0.f;
+  }
   float nu[2], nr[2], nd[2];
   auto fetch = [&](int z) {
 #pragma unroll
@@ -958,18 +960,18 @@ __global__ void __launch_bounds__(kF3Block) k_mg_post3(MgLevel Lk, MgLevel Lc, f
       }
     }
   };
-  RT r64n = (RT)0;   // the stored r of the tile column, next stage-3 plane
+  RT r64n = (RT)0;   // the stored r of the tile column, next output plane
   auto fetch64 = [&](int z) {
-    if (f.col[0] >= 0 && z >= z0 && z < z1) r64n = r64S[plane * z + f.col[0]];
+    if (ZOUT && f.col[0] >= 0 && z >= z0 && z < z1) r64n = r64[m.off + plane * z + f.col[0]];
   };
   double rz = 0.0;
-  fetch(z0 - 3);
-  for (int zz = z0 - 6; zz < z1; ++zz) {
-    const int wb = (zz + 6) & 1, rb = wb ^ 1;
+  fetch(z0 - S);
+  for (int zz = z0 - 2 * S; zz < z1; ++zz) {
+    const int wb = (zz + 2 * S) & 1, rb = wb ^ 1;
     const RT r64c = r64n;
     fetch64(zz + 1);
-    {   // stage 0 at plane zz + 3: u3 + P e
-      const int z = zz + 3;
+    {   // stage 0 at plane zz + S: u + P e
+      const int z = zz + S;
       int Iz = 0, Jz = 0;
       float wz = 0.f;
       const bool in = z >= 0 && z < nz;
@@ -980,7 +982,7 @@ __global__ void __launch_bounds__(kF3Block) k_mg_post3(MgLevel Lk, MgLevel Lc, f
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        if (F3_RING(j) > 3) continue;
+        if (F3_RING(j) > S) continue;
         f3_push(rh[j], nr[j]);
         f3_push(dh[j], nd[j]);
         float v = 0.f;
@@ -988,61 +990,50 @@ __global__ void __launch_bounds__(kF3Block) k_mg_post3(MgLevel Lk, MgLevel Lc, f
           const float eI = sE[Iz & 3][f.p[j]];
           v = nu[j] + (Jz == Iz ? eI : (1.f - wz) * eI + wz * sE[Jz & 3][f.p[j]]);
         }
-        f3_push(h0[j], v);
-        sV0[wb][f.p[j]] = v;
+        f3_push(hs[0][j], v);
+        sV[0][wb][f.p[j]] = v;
       }
-      if (z + 1 <= z1 + 2) fetch(z + 1);
+      if (z + 1 <= z1 + S - 1) fetch(z + 1);
     }
-    {   // stage 1 at plane zz + 2 (rings 0..2)
-      const int z = zz + 2;
-      if (z >= z0 - 2 && z <= z1 + 1) {
+#pragma unroll
+    for (int st = 1; st < S; ++st) {   // sweep st at plane zz + S - st (rings 0 .. S - st)
+      const int z = zz + S - st;
+      if (z >= z0 - (S - st) && z <= z1 - 1 + (S - st)) {
         const bool in = z >= 0 && z < nz;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          if (F3_RING(j) > 2) continue;
+          if (F3_RING(j) > S - st) continue;
           float v = 0.f;
           if (in && f.col[j] >= 0) {
-            const float nb = f3_xy(sV0[rb], f.p[j], EX) + (h0[j][2] + h0[j][0]);
-            v = (1.f - w2) * h0[j][1] + w2 * dh[j][1] * (rh[j][1] + a * nb);
+            const float nb = f3_xy(sV[st - 1][rb], f.p[j], EX) + (hs[st - 1][j][2] + hs[st - 1][j][0]);
+            v = (1.f - w.w[st - 1]) * hs[st - 1][j][1] + w.w[st - 1] * dh[j][st] * (rh[j][st] + a * nb);
           }
-          f3_push(h1[j], v);
-          sV1[wb][f.p[j]] = v;
+          f3_push(hs[st][j], v);
+          sV[st][wb][f.p[j]] = v;
         }
       }
     }
-    {   // stage 2 at plane zz + 1 (rings 0..1)
-      const int z = zz + 1;
-      if (z >= z0 - 1 && z <= z1) {
-        const bool in = z >= 0 && z < nz;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          if (F3_RING(j) > 1) continue;
-          float v = 0.f;
-          if (in && f.col[j] >= 0) {
-            const float nb = f3_xy(sV1[rb], f.p[j], EX) + (h1[j][2] + h1[j][0]);
-            v = (1.f - w1) * h1[j][1] + w1 * dh[j][2] * (rh[j][2] + a * nb);
-          }
-          f3_push(h2[j], v);
-          sV2[wb][f.p[j]] = v;
-        }
+    if (zz >= z0 && f.col[0] >= 0) {   // the last sweep at plane zz
+      const float nb = f3_xy(sV[S - 1][rb], f.p[0], EX) + (hs[S - 1][0][2] + hs[S - 1][0][0]);
+      const float v = (1.f - w.w[S - 1]) * hs[S - 1][0][1] + w.w[S - 1] * dh[0][S] * (rh[0][S] + a * nb);
+      if constexpr (ZOUT) {
+        sb.z32[m.off + plane * zz + f.col[0]] = v;
+        rz += (double)r64c * ((double)v * isc);
+      } else {
+        out[m.off + plane * zz + f.col[0]] = v;
       }
-    }
-    if (zz >= z0 && f.col[0] >= 0) {   // stage 3 at plane zz: z of the CG and r.z
-      const float nb = f3_xy(sV2[rb], f.p[0], EX) + (h2[0][2] + h2[0][0]);
-      const float v = (1.f - w0) * h2[0][1] + w0 * dh[0][3] * (rh[0][3] + a * nb);
-      zS[plane * zz + f.col[0]] = v;
-      rz += (double)r64c * ((double)v * isc);
     }
     __syncthreads();
   }
-  // the tile's r.z partial (fixed order)
-  for (int o = 32; o > 0; o >>= 1) rz += __shfl_xor(rz, o, 64);
-  if ((threadIdx.x & 63) == 0) lds8[threadIdx.x >> 6] = rz;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double tsum = 0.0;
-    for (int k = 0; k < kF3Block / 64; ++k) tsum += lds8[k];
-    store_partials(sb.partial + (size_t)ti * 3, tsum, 0.0, 0.0);
+  if constexpr (ZOUT) {   // the tile's r.z partial (fixed order)
+    for (int o = 32; o > 0; o >>= 1) rz += __shfl_xor(rz, o, 64);
+    if ((threadIdx.x & 63) == 0) lds8[threadIdx.x >> 6] = rz;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double tsum = 0.0;
+      for (int k = 0; k < kF3Block / 64; ++k) tsum += lds8[k];
+      store_partials(sb.partial + (size_t)ti * 3, tsum, 0.0, 0.0);
+    }
   }
 }
 
@@ -1433,12 +1424,16 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
   auto H = [&](int seg, int begin) {
     if (hook) hook(hctx, seg, begin);
   };
+  // a level's correction: its u, or its ualt where its post-smoothing ran fused
+  auto corr = [&](int k) -> const float* {
+    return (mg.fused && k < mg.nlev_glob && mg.lev[k].nftiles) ? mg.lev[k].ualt : mg.lev[k].u;
+  };
   if (mg.fused) {
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_PRE3_0, 1);
-    hca_launch(k_mg_pre3<float>, dim3(grid_ftiles(L.nftiles, L.fchunk)), dim3(kF3Block), 0, s, L, C, w0[0],
-               w0[1], w0[2], (const float*)sb.r32, ss);
+    hca_launch(k_mg_prefused<3>, dim3(grid_ftiles(L.nftiles, L.fchunk)), dim3(kF3Block), 0, s, L, C,
+               F3W{{w0[0], w0[1], w0[2]}}, 1.f, (const float*)sb.r32, ss);
     H(MG_PRE3_0, 0);
   } else {
     const MgLevel& L = mg.lev[0];
@@ -1462,6 +1457,11 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
       const MgLevel& L = mg.lev[k];
       const MgLevel& C = mg.lev[k + 1];
       if (!L.ntiles) continue;
+      if (mg.fused && L.nftiles) {
+        hca_launch(k_mg_prefused<2>, dim3(grid_ftiles(L.nftiles, L.fchunk)), dim3(kF3Block), 0, s, L, C,
+                   F3W{{wa, wb, 0.f}}, (float)(1 << k), (const float*)L.r, ss);
+        continue;
+      }
       hca_launch((k_mg_pre<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, wa, wb,
                  (const float*)L.r, L.u, ss);
       hca_launch((k_mg_restrict<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
@@ -1479,8 +1479,14 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
       const MgLevel& L = mg.lev[k];
       const MgLevel& C = mg.lev[k + 1];
       if (!L.ntiles) continue;
-      hca_launch((k_mg_post1<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C, wb,
-                 (const float*)L.r, ss);
+      if (mg.fused && L.nftiles) {
+        hca_launch((k_mg_postfused<2, false, T, T>), dim3(grid_ftiles(L.nftiles, L.fchunk)), dim3(kF3Block), 0, s,
+                   L, C, corr(k + 1), F3W{{wb, wa, 0.f}}, (float)(1 << k), (const float*)L.r, (const T*)nullptr,
+                   L.ualt, sb);
+        continue;
+      }
+      hca_launch((k_mg_post1<false, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
+                 corr(k + 1), wb, (const float*)L.r, ss);
       hca_launch((k_mg_post2<false, float, T>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, wa,
                  (const float*)L.ualt, (const float*)L.r, sb);
     }
@@ -1490,8 +1496,9 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
     const MgLevel& L = mg.lev[0];
     const MgLevel& C = mg.lev[1];
     H(MG_POST3_0, 1);
-    hca_launch((k_mg_post3<T, T>), dim3(grid_ftiles(L.nftiles, L.fchunk)), dim3(kF3Block), 0, s, L, C, w0[2],
-               w0[1], w0[0], (const float*)sb.r32, (const T*)sb.r, sb);
+    hca_launch((k_mg_postfused<3, true, T, T>), dim3(grid_ftiles(L.nftiles, L.fchunk)), dim3(kF3Block), 0, s, L,
+               C, corr(1), F3W{{w0[2], w0[1], w0[0]}}, 1.f, (const float*)sb.r32, (const T*)sb.r,
+               (float*)nullptr, sb);
     H(MG_POST3_0, 0);
     launch_cg_reduce(s, w, sb, RED_RZF, 0.0, 0);
   } else {
@@ -1499,7 +1506,7 @@ void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const Solv
     const MgLevel& C = mg.lev[1];
     H(MG_POST1_0, 1);
     hca_launch((k_mg_post1<true, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, C,
-               w0[2], (const float*)sb.r32, ss);
+               corr(1), w0[2], (const float*)sb.r32, ss);
     H(MG_POST1_0, 0);
     H(MG_SWEEP0, 1);
     hca_launch((k_mg_sweep<true, float>), dim3(grid_tiles(L.ntiles, w.max_blocks)), dim3(kBlock), 0, s, L, w0[1],

@@ -74,7 +74,7 @@ enum KernelClass {
     "k_ode", "k_ca_propose", "k_ca_resolve", "k_ca_finalize", "k_stats",
     "k_mg_prep0+k_mg_coarsen", "k_mg_pre<L0>", "k_mg_restrict<L0>", "mg levels >= 1 (global)",
     "k_mg_coarse", "k_mg_post1<L0>", "k_mg_post2<L0>", "k_mlp_apply", "k_vessel", "k_mg_sweep<L0>",
-    "k_mg_pre3<L0>", "k_mg_post3<L0>"};
+    "k_mg_prefused<L0>", "k_mg_postfused<L0>"};
 
 // Compulsory (algorithmic) HBM bytes per voxel of each kernel class; solver
 // classes per voxel of each active system (0: not priced, latency-bound).
@@ -878,6 +878,12 @@ int even_depth(int tz, int nz) {
 // 4 x 384^3 lattices take 64.
 double g_fused_target = 256.0;
 int g_fused_min = 16;
+// Coarser levels smooth in fused passes from this many cells over all systems
+// (HCA_FUSE_MIN_CELLS).  Measured per V-cycle segment: one 384^3 lattice's
+// levels >= 1 take 214 us unfused, 184 us with level 1 (21 M cells) fused,
+// 178 us with level 2 (2.7 M) too; the 128^3 lattice's level 1 (0.8 M) runs
+// at 25 us unfused and 33 us fused.
+long long g_fuse_min_cells = 2LL << 20;
 int fused_depth(int nx, int ny, int nz, int tx) {
   const int ty = kF3Block / tx;
   const double nxy = (double)((nx + tx - 1) / tx) * (double)((ny + ty - 1) / ty);
@@ -1098,6 +1104,10 @@ hca_status build_tables(Ctx* c, const hca_replicate* in) {
     if (v >= 1.0) g_fused_target = v;
   }
   if (const char* e = getenv("HCA_FUSED_MIN")) g_fused_min = std::max(2, std::min(64, atoi(e)));
+  {
+    const char* e = getenv("HCA_FUSE_MIN_CELLS");
+    g_fuse_min_cells = e ? std::max(1LL, atoll(e)) : (2LL << 20);
+  }
   if (const char* e = getenv("HCA_MG_TILE_TARGET")) {
     const double v = atof(e);
     if (v >= 1.0) g_mg_tile_target = v;
@@ -1340,9 +1350,21 @@ hca_status build_mg(Ctx* c) {
   for (int k = 0; k <= nglob; ++k) {
     std::vector<MgRep>& mr = mreps[k];
     mr.resize(S);
-    std::vector<Tile> tiles, rtiles;
-    int ntiles1 = 0, nrtiles1 = 0;
+    std::vector<Tile> tiles, rtiles, ftiles;
+    int ntiles1 = 0, nrtiles1 = 0, nftiles1 = 0, fchunk = 16;
     long long off = 0;
+    // a coarser level smooths in fused passes when every system iterates on
+    // it, all its cells are full 2^k-cubes (uniform couplings a 2^k) and the
+    // level holds at least g_fuse_min_cells cells over all systems (smaller
+    // levels run faster as one kernel per sweep)
+    bool fuse_k = k >= 1 && c->prm.mg_fuse;
+    long long cells_k = 0;
+    for (int r = 0; fuse_k && r < R; ++r) {
+      for (int i = 0; i < 3; ++i)
+        fuse_k = fuse_k && k < kcr[r] && dims[r][0][i] % (1 << k) == 0;
+      if (fuse_k) cells_k += (long long)dims[r][k][0] * dims[r][k][1] * dims[r][k][2];
+    }
+    fuse_k = fuse_k && cells_k * (S / R) >= g_fuse_min_cells;
     for (int s = 0; s < S; ++s) {
       const int r = s % R;
       MgRep& m = mr[s];
@@ -1375,11 +1397,16 @@ hca_status build_mg(Ctx* c) {
           m.rtile_b0 = (int)rtiles.size();
           add_tiles(rtiles, s, m.nx, m.ny, m.nz, m.tx, tz);
           m.rtile_nb = (int)rtiles.size() - m.rtile_b0;
+          if (fuse_k) {
+            add_tiles(ftiles, s, m.nx, m.ny, m.nz, m.tx, fused_depth(m.nx, m.ny, m.nz, m.tx), kF3Block / m.tx);
+            fchunk = std::max(fchunk, std::min(8 * ((m.nx + m.tx - 1) / m.tx), 256));
+          }
         }
       }
       if (s == R - 1) {
         ntiles1 = (int)tiles.size();
         nrtiles1 = (int)rtiles.size();
+        nftiles1 = (int)ftiles.size();
       }
     }
     MgLevel& L = mg.lev[k];
@@ -1401,12 +1428,17 @@ hca_status build_mg(Ctx* c) {
     } else {
       Tile* dt = nullptr;
       Tile* drt = nullptr;
-      if ((st = mg_upload(c, &dt, tiles)) != HCA_OK || (st = mg_upload(c, &drt, rtiles)) != HCA_OK)
+      Tile* dft = nullptr;
+      if ((st = mg_upload(c, &dt, tiles)) != HCA_OK || (st = mg_upload(c, &drt, rtiles)) != HCA_OK ||
+          (!ftiles.empty() && (st = mg_upload(c, &dft, ftiles)) != HCA_OK))
         return st;
       L.tiles = dt;
       L.ntiles = (int)tiles.size();
       L.rtiles = drt;
       L.nrtiles = (int)rtiles.size();
+      L.ftiles = dft;
+      L.nftiles = (int)ftiles.size();
+      L.fchunk = fchunk;
       const size_t n = (size_t)std::max<long long>(off, 1);
       if ((st = mg_alloc(c, &L.c, n)) != HCA_OK || (st = mg_alloc(c, &L.dinv, n)) != HCA_OK ||
           (st = mg_alloc(c, &L.r, n)) != HCA_OK || (st = mg_alloc(c, &L.u, n)) != HCA_OK ||
@@ -1418,7 +1450,7 @@ hca_status build_mg(Ctx* c) {
     }
     c->mg1.lev[k] = L;
     c->mg1.lev[k].ntiles = ntiles1;
-    if (k == 0) c->mg1.lev[k].nftiles = c->nftiles1;
+    c->mg1.lev[k].nftiles = k == 0 ? c->nftiles1 : nftiles1;
     c->mg1.lev[k].nrtiles = k == 0 ? 0 : nrtiles1;
   }
   int nglob1 = 1;

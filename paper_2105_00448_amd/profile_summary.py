@@ -26,9 +26,11 @@ SOURCES = ["paper_2105_00448_amd/csrc/k_solver.hip", "paper_2105_00448_amd/csrc/
 COPY_KIB = 256 * 1024
 # the counter passes collect only these dispatches (--kernel-include-regex)
 PMC_REGEX = ("k_cg_update|k_cg_apply|k_mg_pre|k_mg_sweep|k_mg_restrict|k_mg_post1|k_mg_post2|"
-             "k_mg_post3|k_mg_coarse|k_init_cells|copyBuffer")
+             "k_mg_postfused|k_mg_coarse|k_init_cells|copyBuffer")
 # kernels priced per launch (levels below level 0, the one-workgroup coarse solve)
-PER_LAUNCH = ["k_mg_pre<false, float>", "k_mg_restrict<false, float>", "k_mg_post1<false, float>",
+PER_LAUNCH = ["k_mg_prefused<2>", "k_mg_postfused<2, false, double, double>",
+              "k_mg_postfused<2, false, float, float>", "k_mg_pre<false, float>",
+              "k_mg_restrict<false, float>", "k_mg_post1<false, float>",
               "k_mg_post2<false, float, double>", "k_mg_post2<false, float, float>", "k_mg_coarse"]
 # voxels (of one system) of each workload, and its systems per solve
 WORKLOADS = {"config5": (384 ** 3, 4), "plain128": (128 ** 3, 1)}
@@ -38,7 +40,7 @@ def kernels(e):
     """Streaming kernels of the solve (demangled-name prefix -> (short name,
     algorithmic bytes per active voxel)); e = bytes of a stored field value.
     Level 0 of the multigrid is the <true, ...> instance, or the fused
-    three-stage passes k_mg_pre3 / k_mg_post3 (the default)."""
+    three-stage passes k_mg_prefused<3> / k_mg_postfused<3, ...> (the default)."""
     fp = "double" if e == 8 else "float"
     return {
         f"k_cg_update<false, {fp}>": ("k_cg_update", 6 * e),
@@ -48,8 +50,8 @@ def kernels(e):
         "k_mg_restrict<true, float>": ("k_mg_restrict_L0", 12.5),
         "k_mg_post1<true, float>": ("k_mg_post1_L0", 16.5),
         f"k_mg_post2<true, {fp}, {fp}>": ("k_mg_post2_L0", 12 + e),
-        "k_mg_pre3<float>": ("k_mg_pre3_L0", 12.5),
-        f"k_mg_post3<{fp}, {fp}>": ("k_mg_post3_L0", 16.5 + e),
+        "k_mg_prefused<3>": ("k_mg_prefused_L0", 12.5),
+        f"k_mg_postfused<3, true, {fp}, {fp}>": ("k_mg_postfused_L0", 16.5 + e),
     }
 
 

@@ -51,6 +51,34 @@ def test_fused_level0_smoothing_matches_per_sweep_kernels(shape, ng, seed, preci
     assert np.array_equal(f1["L"], f0["L"])
 
 
+@pytest.mark.parametrize("precision", [64, 32])
+@pytest.mark.parametrize("shape", [(48, 40, 36), (64, 64, 32), (32, 96, 16)], ids=str)
+def test_fused_coarser_levels_match_per_sweep_kernels(shape, precision, monkeypatch):
+    """Coarser levels whose cells are all full 2^k-cubes also smooth in fused
+    passes (two stages before and after; by default only on levels of at
+    least 2 M cells over all systems, here forced on every eligible level):
+    the same iteration counts and fields as one kernel per sweep."""
+    print(f"\n[mg fuse levels] {shape} precision {precision}", flush=True)
+    tis = synth.make_tissue(shape, 8, seed=sum(shape))
+    sched = synth.bolus_schedule([0, 2])
+    reps = [(tis.cell, tis.w, tis.seed, (sched.times, sched.amts))]
+    out = {}
+    for fuse in (0, 1):
+        monkeypatch.setenv("HCA_FUSE_MIN_CELLS", "1")
+        with hca.Simulation(reps, hca.default_params(precision=precision, mg_fuse=fuse)) as sim:
+            iters = []
+            for _ in range(4):
+                sim.step(1)
+                iters.append(list(sim.stats()["cg_iters"]))
+            out[fuse] = ({k: sim.field(k) for k in ("K", "G1", "G2")}, iters)
+    monkeypatch.delenv("HCA_FUSE_MIN_CELLS")
+    (f0, i0), (f1, i1) = out[0], out[1]
+    assert i0 == i1
+    tol = 1e-12 if precision == 64 else 1e-6
+    for k in ("K", "G1", "G2"):
+        assert relerr(f1[k], f0[k]) <= tol, k
+
+
 def test_fused_path_in_a_batch_with_uneven_replicates():
     """A batch of replicates of different shapes (tile widths 16 and 32, one
     2-D) solved together with the fused passes: each replicate equals its own
