@@ -248,6 +248,9 @@ __global__ void __launch_bounds__(kBlock) k_mg_prep0(MgLevel L0, const T* __rest
 }
 
 // Level k+1 from level k: c_{k+1} = sum of the children's c, Dinv_{k+1}.
+// From level 0 (FROM0) the same pass also writes level 0's Dinv = 1 / (c +
+// a deg) of every child (each level-0 cell is the child of exactly one
+// level-1 cell), so level 0's c is read once.
 template <bool FROM0, typename T>
 __global__ void __launch_bounds__(kBlock) k_mg_coarsen(MgLevel Lf, MgLevel Lc,
                                                        const T* __restrict__ c0) {
@@ -257,6 +260,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarsen(MgLevel Lf, MgLevel Lc,
     const MgRep mc = Lc.reps[t.rep];
     const MgRep mf = Lf.reps[t.rep];
     const Geo<false> G = geo_of<false>(mc);
+    const Geo<true> Gf = geo_of<true>(mf);
     for (int Z = t.z0; Z < t.z1; ++Z) {
       float s = 0.f;
       for (int dz = 0; dz < 2; ++dz) {
@@ -269,7 +273,13 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarsen(MgLevel Lf, MgLevel Lc,
             const int x = 2 * t.x + dx;
             if (x >= mf.nx) break;
             const long long j = mf.off + x + (long long)mf.nx * (y + (long long)mf.ny * z);
-            s += FROM0 ? (float)c0[j] : Lf.c[j];
+            if (FROM0) {
+              const double cj = (double)c0[j];
+              Lf.dinv[j] = (float)(1.0 / (cj + (double)Gf.gsum(x, y, z)));
+              s += (float)cj;
+            } else {
+              s += Lf.c[j];
+            }
           }
         }
       }
@@ -1399,7 +1409,9 @@ hipError_t mg_set_coarse_lds(int bytes) {
 
 template <typename T>
 void launch_mg_prepare(hipStream_t s, const Work& w, const MgBufs& mg, const T* c) {
-  if (mg.lev[0].ntiles)
+  // level 0's D^-1 comes with level 1's c (k_mg_coarsen<true>); a level 1 with
+  // no restriction tiles would leave it to k_mg_prep0
+  if (mg.lev[0].ntiles && !mg.lev[1].nrtiles)
     hca_launch(k_mg_prep0<T>, dim3(grid_tiles(mg.lev[0].ntiles, w.max_blocks)), dim3(kBlock), 0, s, mg.lev[0], c);
   for (int k = 0; k < mg.nlev_glob; ++k) {
     const MgLevel& Lc = mg.lev[k + 1];

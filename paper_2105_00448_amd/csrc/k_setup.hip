@@ -168,15 +168,29 @@ __global__ void __launch_bounds__(kBlock) k_setup_o2(Work w, DevParams p, const 
 //           V_c of the coupled step's start at both ends of every substep.
 // With one backward-Euler substep these are the coupled step's systems
 // c = 1/dt + R, b = u/dt + S.
-template <typename T>
+template <bool X, typename T>
 __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long long ntot,
                                                        const uint8_t* __restrict__ L,
                                                        const double* __restrict__ vw,
-                                                       const T* __restrict__ F,
+                                                       T* __restrict__ F,
                                                        const double* __restrict__ Vc,
                                                        const double* __restrict__ g0,
-                                                       T* __restrict__ c, T* __restrict__ b) {
+                                                       T* __restrict__ c, T* __restrict__ b,
+                                                       T* __restrict__ Fprev, unsigned xmask, int xmode) {
   const double th = p.theta, th1 = 1.0 - p.theta;
+  // X: the solves' initial guess as k_extrapolate forms it, from the value u
+  // just read for b (fields of xmask)
+  auto guess = [&](int f, long long j, double u) {
+    if (X && ((xmask >> f) & 1u)) {
+      const double up = Fprev[j];
+      Fprev[j] = (T)u;
+      if (xmode == 1) {
+        F[j] = (T)(u + (u - up));
+      } else if (up > 0.0 && u > 0.0 && u < up) {   // geometric, decaying values only
+        F[j] = (T)(u * (u / up));
+      }
+    }
+  };
   for_each_voxel(w, [&](int rep, const RepDev&, long long g) {
     const double wv = vw[g];
     const double k = F[g];
@@ -185,19 +199,24 @@ __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long
     const double up = p.phi_K * chi / (p.K1 + fmax(k, 0.0));
     c[g] = (T)(p.inv_tau + th * rw + th * up);
     b[g] = (T)(k * (p.inv_tau - th1 * (rw + up)) + rw * p.K0);
+    guess(0, g, k);
     const double kw = p.kappa_G * wv;
     const double cg = p.inv_tau + th * p.psi_G + th * kw;
     const double rg = p.psi_G + kw;
     for (int i = 0; i < 2 + p.drug3; ++i) {   // drug i in field i + 1
       const long long j = g + (i + 1) * ntot;
+      const double u = F[j];
       c[j] = (T)cg;
-      b[j] = (T)((double)F[j] * (p.inv_tau - th1 * rg) +
+      b[j] = (T)(u * (p.inv_tau - th1 * rg) +
                  kw * (th * g0[3 * rep + i] + th1 * g0[3 * w.nreps + 3 * rep + i]));
+      guess(i + 1, j, u);
     }
     if (p.vegf) {
       const long long j = g + (long long)p.fV * ntot;
+      const double u = F[j];
       c[j] = (T)(p.inv_tau + th * p.psi_V);
-      b[j] = (T)((double)F[j] * (p.inv_tau - th1 * p.psi_V) + p.sec_V * Vc[g] * chi);
+      b[j] = (T)(u * (p.inv_tau - th1 * p.psi_V) + p.sec_V * Vc[g] * chi);
+      guess(p.fV, j, u);
     }
   });
 }
@@ -327,10 +346,14 @@ void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uin
 
 template <typename T>
 void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
-                       const uint8_t* L, const double* vw, const T* F, const double* Vc,
-                       const double* g0, T* c, T* b) {
-  hca_launch(k_setup_step<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot, L,
-             vw, F, Vc, g0, c, b);
+                       const uint8_t* L, const double* vw, T* F, const double* Vc,
+                       const double* g0, T* c, T* b, T* Fprev, unsigned xmask, int xmode) {
+  if (Fprev)
+    hca_launch(k_setup_step<true, T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot,
+               L, vw, F, Vc, g0, c, b, Fprev, xmask, xmode);
+  else
+    hca_launch(k_setup_step<false, T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot,
+               L, vw, F, Vc, g0, c, b, Fprev, xmask, xmode);
 }
 
 template <typename T>
@@ -383,8 +406,8 @@ void launch_convert(hipStream_t s, const double* src, float* dst, long long n) {
   template void launch_setup_o2<T>(hipStream_t, const Work&, const DevParams&, const uint8_t*,     \
                                    const double*, const T*, T*, T*, int);                          \
   template void launch_setup_step<T>(hipStream_t, const Work&, const DevParams&, long long,        \
-                                     const uint8_t*, const double*, const T*, const double*,       \
-                                     const double*, T*, T*);                                       \
+                                     const uint8_t*, const double*, T*, const double*,             \
+                                     const double*, T*, T*, T*, unsigned, int);                    \
   template void launch_setup_o2_newton<T>(hipStream_t, const Work&, const DevParams&,              \
                                           const uint8_t*, const double*, const T*, const T*, T*,   \
                                           T*);                                                     \

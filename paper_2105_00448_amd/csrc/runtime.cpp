@@ -649,12 +649,15 @@ hca_status run_phases(Ctx* c, unsigned mask) {
       ProfScope ps(c, KC_PLASMA, kTagState);
       launch_plasma(s, wk, c->dp, c->d_step, j, c->dose_t, c->dose_a, c->g0);
     }
+    // the initial guess in the setup pass where nothing reads F after it
+    const bool guess_in_setup = c->Fprev && c->dp.theta >= 1.0;
     {
       ProfScope ps(c, KC_SETUP, kTagState);
-      launch_setup_step(s, wk, c->dp, c->ntot, c->L, c->w, c->F, c->Vc, c->g0, c->c, c->b);
+      launch_setup_step(s, wk, c->dp, c->ntot, c->L, c->w, c->F, c->Vc, c->g0, c->c, c->b,
+                        guess_in_setup ? c->Fprev : nullptr, fmask, c->prm.x0_extrapolate);
       if (c->dp.theta < 1.0) launch_rhs_lap(s, wk, c->dp, c->ntot, c->F, c->b);
     }
-    if (c->Fprev) {
+    if (c->Fprev && !guess_in_setup) {
       ProfScope ps(c, KC_SETUP, kTagState);
       launch_extrapolate(s, wk, c->ntot, c->dp.nf, fmask, c->prm.x0_extrapolate, c->F, c->Fprev);
     }
