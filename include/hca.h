@@ -190,11 +190,14 @@ typedef struct hca_params {
      phi, the vessel map and the cellular automaton are FP64 either way;
      hca_fields, hca_set_field and the state blobs stay FP64 (converted). */
   int32_t precision;
-  /* multigrid level 0 (precond = 1): 1 (default) runs its three sweeps before
-     the coarse-grid correction and the restriction as one pass over the
-     lattice, and its three sweeps after it as another (the intermediate
-     iterates stay on chip); 0 one kernel per sweep.  The two compute the same
-     V-cycle up to the rounding order of the neighbour sums. */
+  /* multigrid smoothing (precond = 1): 1 (default) runs level 0's three
+     sweeps before the coarse-grid correction and the restriction as one pass
+     over the lattice, and its three sweeps after it as another (the
+     intermediate iterates stay on chip); a coarser level whose cells are all
+     full 2^k-cubes and which holds at least 2 M cells over all systems does
+     the same with its two sweeps per side; 0 one kernel per sweep.  The two
+     compute the same V-cycle up to the rounding order of the neighbour
+     sums. */
   int32_t mg_fuse;
 } hca_params;
 
