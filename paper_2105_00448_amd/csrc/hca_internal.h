@@ -336,7 +336,8 @@ struct MgBufs {
   int coarse_lds_bytes;
   float w_a, w_b;            // Jacobi weights: pre-sweeps (w_a, w_b), post-sweeps (w_b, w_a)
   float w0[3];              // level 0: pre-sweeps (w0[0], w0[1], w0[2]), post-sweeps reversed
-  int fused;                // level 0: the fused pre and post passes (k_mg_pre3, k_mg_post3)
+  int fused;                // fused smoothing passes (k_mg_prefused, k_mg_postfused): level 0, and
+                            // the coarser levels with ftiles
   float** lev_c;            // device arrays of the per-level pointers
   float** lev_r;
   float** lev_u;

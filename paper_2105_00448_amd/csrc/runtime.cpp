@@ -103,8 +103,8 @@ const double kBytesPerVoxel[KC_COUNT] = {
     49.0 + 3 * kE,  // mlp apply: read L, K, G1, G2, P, Vc, phi; write P, Vc, phi
     9.0 + kE,       // vessel: read L, w, V (writes only where a vessel changes)
     16.0,           // mg sweep L0: read u (4), r (4), dinv (4); write u' (4)
-    12.5,           // mg pre3 L0 (fused): read r (4), dinv (4); write u3 (4), r1 (1/8 of 4)
-    16.5 + kE};     // mg post3 L0 (fused): read u3 (4), e (1/8), r (4), dinv (4), r (stored); write z (4)
+    12.5,           // mg prefused L0: read r (4), dinv (4); write u3 (4), r1 (1/8 of 4)
+    16.5 + kE};     // mg postfused L0: read u3 (4), e (1/8), r (4), dinv (4), r (stored); write z (4)
 constexpr double kBytesSetupVegf = 8.0 + 3 * kE;   // setup_step with vegf: + read V, Vc; write c, b
 constexpr double kBytesSetupDrug3 = 3 * kE;        // setup_step with drug3: + read G3; write c, b
 constexpr double kBytesStatsField = kE;            // stats: per extra field scanned (V, G3)
