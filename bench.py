@@ -950,12 +950,12 @@ def single_workload(args, stream, workload, repeats):
         d = kt[dom]
         mean_s = d["ms"] / d["launches"] * 1e-3
         achieved = d["bytes_per_launch"] / mean_s / 1e9
-        kname = dom.split("<")[0]
+        kname = dom.replace("<L0>", "_L0").split("<")[0]
         wname = workload
         rec["profiled_repeat_ms_per_step"] = el_prof / steps * 1e3
         rec["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                           "traffic": measured_traffic(kname, wname),
+                           "traffic": measured_traffic(kname, wname, d["bytes_per_launch"]),
                            "traffic_source": f"profiles/{kname}_{wname}_traffic.json",
                            "mean_launch_us": mean_s * 1e6,
                            "launches": d["launches"],
