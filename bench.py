@@ -586,36 +586,46 @@ def kernel_window(sim, names, steps, profile):
 
 
 def run_context(reps, params, warmup, steps, stream, net=None, margin=1e-3, prof_steps=3,
-                label=""):
-    """Init a context, `warmup` untimed steps, `steps` timed steps (no events,
-    graphs replayed), then two short profiled windows on the same context:
-    every kernel class (time shares, algorithmic bytes of a step) and the
-    dominant class alone (its launch durations)."""
+                label="", repeats=1):
+    """`repeats` times: init a fresh context, `warmup` untimed steps, `steps`
+    timed steps (no events, graphs replayed); `el` is the median of the timed
+    runs (`els` all of them).  Then two short profiled windows on the last
+    context: every kernel class (time shares, algorithmic bytes of a step) and
+    the dominant class alone (its launch durations)."""
+    import statistics
+
     import torch
 
     from paper_2105_00448_amd import hca
     names = [hca.lib().hca_kernel_name(k).decode() for k in range(hca.lib().hca_num_kernels())]
-    t0 = time.perf_counter()
-    sim = hca.Simulation(reps, params, stream=stream)
-    t_init = time.perf_counter() - t0
-    if net is not None:
-        sim.set_surrogate(net, margin)
-    print(f"[bench:{label}] init {t_init:.1f}s; {warmup} warm-up steps", file=sys.stderr, flush=True)
-    sim.step(warmup)
-    torch.cuda.synchronize()
-    sim.synchronize()
-    print(f"[bench:{label}] timing {steps} steps", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    sim.step(steps)
-    sim.synchronize()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    els = []
+    sim = None
+    for rep_i in range(repeats):
+        if sim is not None:
+            sim.close()
+            torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        sim = hca.Simulation(reps, params, stream=stream)
+        t_init = time.perf_counter() - t0
+        if net is not None:
+            sim.set_surrogate(net, margin)
+        print(f"[bench:{label}] run {rep_i + 1}/{repeats}: init {t_init:.1f}s; {warmup} warm-up steps",
+              file=sys.stderr, flush=True)
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        sim.synchronize()
+        print(f"[bench:{label}] timing {steps} steps", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.synchronize()
+        torch.cuda.synchronize()
+        els.append(time.perf_counter() - t0)
+        print(f"[bench:{label}] {steps} steps in {els[-1]:.3f}s", file=sys.stderr, flush=True)
+    el = statistics.median(els)
     st = [sim.stats(r) for r in range(len(reps))]
     if prof_steps == 0:
-        print(f"[bench:{label}] {steps} steps in {el:.2f}s", file=sys.stderr, flush=True)
-        return {"el": el, "init_s": t_init, "stats": st, "sim": sim, "dom": None}
-    print(f"[bench:{label}] {steps} steps in {el:.2f}s; profiling {prof_steps} + {prof_steps} "
-          f"steps", file=sys.stderr, flush=True)
+        return {"el": el, "els": els, "init_s": t_init, "stats": st, "sim": sim, "dom": None}
+    print(f"[bench:{label}] profiling {prof_steps} + {prof_steps} steps", file=sys.stderr, flush=True)
     kt_all = kernel_window(sim, names, prof_steps, 1)
     real = {k: v for k, v in kt_all.items() if v["launches"] > 0 and v["bytes_per_launch"] > 0}
     dom = max(real, key=lambda k: real[k]["ms"])
@@ -623,7 +633,7 @@ def run_context(reps, params, warmup, steps, stream, net=None, margin=1e-3, prof
     kt_mlp = None
     if net is not None:
         kt_mlp = kernel_window(sim, names, prof_steps, names.index("k_mlp_apply") + 2)["k_mlp_apply"]
-    out = {"el": el, "init_s": t_init, "stats": st, "kt_all": kt_all, "dom": dom,
+    out = {"el": el, "els": els, "init_s": t_init, "stats": st, "kt_all": kt_all, "dom": dom,
            "kt_dom": kt_dom[dom], "kt_mlp": kt_mlp, "sim": sim}
     return out
 
@@ -759,7 +769,10 @@ def config5_headline(args, stream):
         b_step, kms = step_bytes(kt, 3)
         ms = run["el"] / steps * 1e3
         tot = sum(v["ms"] for v in kt.values())
-        out = {"value": nvox * steps / run["el"], "ms_per_step": ms, "init_s": run["init_s"],
+        out = {"value": nvox * steps / run["el"], "ms_per_step": ms, "repeats": len(run["els"]),
+               "value_min_time": nvox * steps / min(run["els"]),
+               "ms_per_step_runs": [round(e / steps * 1e3, 3) for e in run["els"]],
+               "init_s": run["init_s"],
                "cg_iters_last_step": st[0]["cg_iters"],
                "roofline": roofline_of(run["kt_dom"], run["dom"],
                                        "config5" if elem == 8 else "config5_fp32", elem),
@@ -776,13 +789,17 @@ def config5_headline(args, stream):
             out["ode_phase_ms"] = ode["ms"] / ode["launches"]
         return out
 
-    plain = run_context(reps, hca.default_params(**kw), args.warmup, steps, stream, label="plain")
+    # fresh-context repeats (value = their median; value_min_time = the
+    # fastest, the paper's convention), about 100 timed steps per context at most
+    repeats = max(1, min(args.repeats, 100 // max(1, steps)))
+    plain = run_context(reps, hca.default_params(**kw), args.warmup, steps, stream, label="plain",
+                        repeats=repeats)
     plain_rec = summary(plain, "plain")
     plain["sim"].close()
     del plain
     torch.cuda.empty_cache()
     sur = run_context(reps, hca.default_params(**kw), args.warmup, steps, stream, net=net,
-                      label="surrogate")
+                      label="surrogate", repeats=repeats)
     sur_rec = summary(sur, "surrogate")
     st = sur["stats"]
     m = sur["kt_mlp"]
@@ -836,7 +853,11 @@ def config5_headline(args, stream):
         "config": dict(cfg, mode="surrogate ODE + batched ensemble (4 replicates in one context)"),
         "roofline": dict(sur_rec["roofline"], stream_ceiling=ceiling,
                          frac_of_stream_copy=sur_rec["roofline"]["achieved"] / ceiling["copy_gbs"]),
-        "plain": {k: plain_rec[k] for k in ("value", "ms_per_step", "init_s", "cg_iters_last_step",
+        "repeats": sur_rec["repeats"],
+        "value_min_time": sur_rec["value_min_time"],
+        "ms_per_step_runs": sur_rec["ms_per_step_runs"],
+        "plain": {k: plain_rec[k] for k in ("value", "ms_per_step", "repeats", "value_min_time",
+                                             "ms_per_step_runs", "init_s", "cg_iters_last_step",
                                              "roofline", "hbm_whole_step", "ode_phase_ms")
                   if k in plain_rec},
         "speedup_vs_plain": sur_rec["value"] / plain_rec["value"],
