@@ -711,9 +711,10 @@ def roofline_of(kt_dom, dom, workload, elem=8):
          "mean_launch_us": mean_s * 1e6, "launches": kt_dom["launches"],
          "bytes_per_launch": kt_dom["bytes_per_launch"]}
     if kname == "k_cg_update":
-        # the kernel moves 8 B per voxel more than the CG's compulsory 6 stored
-        # values (the multigrid's FP32 z read and r copy written)
-        r["frac_incl_fp32_copies"] = r["frac"] * (6 * elem + 8.0) / (6 * elem)
+        # the kernel moves 8 B per voxel more than the CG's compulsory 3 stored
+        # values r, q read and r written (the multigrid's FP32 z read and r copy
+        # written; x += alpha p is made by the next apply)
+        r["frac_incl_fp32_copies"] = r["frac"] * (3 * elem + 8.0) / (3 * elem)
     return r
 
 

@@ -265,17 +265,20 @@ enum ReduceKind { RED_START = 0, RED_APPLY = 1, RED_UPDATE = 2, RED_RZ = 3, RED_
 template <typename T>
 void launch_cg_reduce(hipStream_t s, const Work& w, const SolverBufsT<T>& sb, int kind, double rtol,
                       int maxit, unsigned field_mask = 7u, int nrep = 1);
-// One iteration is launch_cg_apply then launch_cg_update with the same
-// parity (the direction p alternates between p0 and p1).
+// One iteration is launch_cg_apply (with the iteration's parity: the
+// direction p alternates between p0 and p1) then launch_cg_update.  The apply
+// also makes the previous iteration's x += alpha p (x: the solved field), so
+// a solve ends with launch_cg_finish for the last one.
 template <typename T>
-void launch_cg_apply(hipStream_t s, const Work& w, const T* c, const SolverBufsT<T>& sb, int parity);
+void launch_cg_apply(hipStream_t s, const Work& w, const T* c, T* x, const SolverBufsT<T>& sb, int parity);
 // The apply kernel alone (no reduce), for the tile autotuner.
 template <typename T>
-void launch_cg_apply_kernel(hipStream_t s, const Work& w, const T* c, const SolverBufsT<T>& sb,
+void launch_cg_apply_kernel(hipStream_t s, const Work& w, const T* c, T* x, const SolverBufsT<T>& sb,
                             int parity);
 template <typename T>
-void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, T* x,
-                      const SolverBufsT<T>& sb, int parity);
+void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, const SolverBufsT<T>& sb);
+template <typename T>
+void launch_cg_finish(hipStream_t s, const Work& w, T* x, const SolverBufsT<T>& sb);
 
 // ---- geometric multigrid (k_mg.hip) ---------------------------------------
 constexpr int kMaxLevels = 16;

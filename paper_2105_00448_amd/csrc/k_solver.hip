@@ -20,7 +20,10 @@
 // The direction update p = z + beta p is fused into the next A p: each
 // workgroup forms p at its voxels and their neighbours from z and the
 // previous p (double-buffered p, so no workgroup overwrites a value another
-// still reads).
+// still reads).  Nothing in the iteration reads x, so x += alpha p is made
+// one iteration late, by the next apply, which reads the previous p anyway
+// (x moves once per iteration instead of x and p in the update); the last
+// iteration's update is made by a finishing pass after the solve.
 #include "dev_util.h"
 
 namespace hca {
@@ -72,7 +75,10 @@ constexpr int kStencilPrefetch = 1;
 // Marches the tile over [z0, z1) and calls f(i, deg, u_i, (A u)_i) for every
 // voxel of the tile inside the lattice, where u = op.value(op.load(j)) is the
 // operand (possibly formed on the fly from several arrays) and
-// (A u)_i = (c_i + a deg) u_i - a sum_nb u_j.  Each plane of u, with its x/y
+// (A u)_i = (c_i + a deg) u_i - a sum_nb u_j.  Values the op needs at the
+// voxel itself only (op.load_ctr, prefetched with the plane like c) are
+// handed, with the voxel's raw operand, to op.at_center(i, raw_i, extra_i)
+// when the voxel's plane enters LDS.  Each plane of u, with its x/y
 // frame, is formed once into LDS (double buffered); outside the lattice the
 // frame holds 0, which adds nothing to the neighbour sum.  Software
 // pipelined: the global loads (operand and c) of planes z+2 .. z+1+PD are in
@@ -88,9 +94,11 @@ template <int PD, typename T, typename OP, typename F>
 __device__ inline void plane_stencil(const TileCoord& tc, const T* __restrict__ c,
                                      T (*lds)[kPlaneMax], const OP& op, F f) {
   using Raw = typename OP::Raw;
+  using Ctr = typename OP::Ctr;
   struct Slot {
     Raw ri, rf;   // operand of the thread's cell and of its frame cell
     double c;     // c of the thread's cell
+    Ctr e;        // the op's extra values at the thread's cell
   };
   const double a = tc.a;
   const int W = tc.tx + 2;
@@ -125,7 +133,10 @@ __device__ inline void plane_stencil(const TileCoord& tc, const T* __restrict__ 
   auto load_slot = [&](Slot& sl, int zp) {
     const long long pz = tc.off + plane * zp;
     if (tc.valid) sl.ri = op.load(pz + iidx);
-    if (tc.valid && zp < z1) sl.c = c[pz + iidx];
+    if (tc.valid && zp < z1) {
+      sl.c = c[pz + iidx];
+      sl.e = op.load_ctr(pz + iidx);
+    }
     if (fin) sl.rf = op.load(pz + fidx);
   };
   auto store_slot = [&](const Slot& sl, T* buf) {
@@ -140,12 +151,13 @@ __device__ inline void plane_stencil(const TileCoord& tc, const T* __restrict__ 
   // ring: plane zp (z0 < zp <= min(z1, nz - 1)) in slot (zp - z0 - 1) % PD
   Slot ring[PD];
 #pragma unroll
-  for (int d = 0; d < PD; ++d) ring[d] = Slot{op.zero(), op.zero(), 0.0};
+  for (int d = 0; d < PD; ++d) ring[d] = Slot{op.zero(), op.zero(), 0.0, op.ctr_zero()};
   __syncthreads();   // the previous tile's readers are done with both buffers
   double um, cc;
   {
-    Slot s0{op.zero(), op.zero(), 0.0};
+    Slot s0{op.zero(), op.zero(), 0.0, op.ctr_zero()};
     load_slot(s0, z0);
+    if (tc.valid) op.at_center(i, s0.ri, s0.e);
     um = (tc.valid && z0 > 0) ? (double)(T)op.value(op.load(i - plane)) : 0.0;
 #pragma unroll
     for (int d = 0; d < PD; ++d)
@@ -165,6 +177,7 @@ __device__ inline void plane_stencil(const TileCoord& tc, const T* __restrict__ 
         if (zr) {   // plane z+1 into LDS; its slot then takes plane z+1+PD
           store_slot(ring[d], nxt);
           cn = ring[d].c;
+          if (tc.valid && z + 1 < z1) op.at_center(i + plane, ring[d].ri, ring[d].e);
           const int zq = z + 1 + PD;
           if (zq <= z1 && zq < tc.nz) load_slot(ring[d], zq);
         }
@@ -201,24 +214,41 @@ struct OpX {
   struct Raw {
     double x;
   };
+  struct Ctr {};
   const T* __restrict__ x;
   __device__ inline Raw zero() const { return Raw{0.0}; }
   __device__ inline Raw load(long long j) const { return Raw{x[j]}; }
   __device__ inline double value(const Raw& r) const { return r.x; }
+  __device__ inline Ctr ctr_zero() const { return Ctr{}; }
+  __device__ inline Ctr load_ctr(long long) const { return Ctr{}; }
+  __device__ inline void at_center(long long, const Raw&, const Ctr&) const {}
 };
 
+// The voxel's own x comes with it (extra) when the previous iteration's
+// x += alpha p_old is due (every iteration but a solve's first; alpha the
+// previous iteration's), made as the voxel's plane enters LDS.
 template <bool JAC, typename T>
 struct OpP {
   struct Raw {
     double z, p;
   };
+  struct Ctr {
+    double x;
+  };
   const T* __restrict__ z;
   const float* __restrict__ z32;
   const T* __restrict__ pold;
+  T* __restrict__ x;
   double beta;
   double isc;   // multigrid: z = z32 / sc
+  double alpha;
   bool first;
   __device__ inline Raw zero() const { return Raw{0.0, 0.0}; }
+  __device__ inline Ctr ctr_zero() const { return Ctr{0.0}; }
+  __device__ inline Ctr load_ctr(long long j) const { return Ctr{first ? 0.0 : (double)x[j]}; }
+  __device__ inline void at_center(long long i, const Raw& r, const Ctr& e) const {
+    if (!first) x[i] = (T)(e.x + alpha * r.p);
+  }
   __device__ inline Raw load(long long j) const {
     Raw r;
     if constexpr (JAC)
@@ -269,13 +299,15 @@ __global__ void __launch_bounds__(kBlock) k_cg_start(Work w, const T* __restrict
   }
 }
 
-// p_new = z + beta p_old (p_new = z on the first iteration), q = A p_new.
+// p_new = z + beta p_old (p_new = z on the first iteration), q = A p_new;
+// and the previous iteration's x += alpha p_old (not on the first).
 template <bool JAC, typename T>
 __global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, const T* __restrict__ c,
                                                      const T* __restrict__ z,
                                                      const T* __restrict__ pold,
                                                      T* __restrict__ pnew,
-                                                     T* __restrict__ q, SolverBufsT<T> sb) {
+                                                     T* __restrict__ q, T* __restrict__ x,
+                                                     SolverBufsT<T> sb) {
   __shared__ double lds4[4];
   __shared__ T lds[2][kPlaneMax];
   int t0, t1;
@@ -288,7 +320,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, const T* __restrict
     const bool first = ssr->first != 0;
     double pq = 0.0;
     {
-      const OpP<JAC, T> op{z, sb.z32, pold, beta, ssr->isc, first};
+      // ss.alpha is still the previous iteration's (this apply's reduce sets the next)
+      const OpP<JAC, T> op{z, sb.z32, pold, x, beta, ssr->isc, ssr->alpha, first};
       plane_stencil<kStencilPrefetch>(tc, c, lds, op, [&](long long i, int, double pc, double Ap) {
         const T qi = (T)Ap;
         pnew[i] = (T)pc;
@@ -301,12 +334,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_apply(Work w, const T* __restrict
   }
 }
 
-// x += alpha p, r -= alpha q; partials of r.r, r.z_old and (Jacobi) r.z'.
+// r -= alpha q; partials of r.r, r.z_old and (Jacobi) r.z'.  (x += alpha p
+// is made by the next apply, or by k_cg_finish after the last iteration.)
 template <bool JAC, typename T>
-__global__ void __launch_bounds__(kBlock) k_cg_update(Work w, T* __restrict__ x,
-                                                      const T* __restrict__ p,
-                                                      const T* __restrict__ q,
-                                                      SolverBufsT<T> sb) {
+__global__ void __launch_bounds__(kBlock) k_cg_update(Work w, const T* __restrict__ q, SolverBufsT<T> sb) {
   __shared__ double lds4[4];
   constexpr bool jac = JAC;
   int b0, b1;
@@ -324,13 +355,11 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(Work w, T* __restrict__ x,
     constexpr int kUpd = 4;
     const long long end = off + fb.end;
     for (long long i0 = off + fb.begin + threadIdx.x; i0 < end; i0 += kUpd * kBlock) {
-      double xv[kUpd], pv[kUpd], rv[kUpd], qv[kUpd], zo[kUpd], dv[kUpd];
+      double rv[kUpd], qv[kUpd], zo[kUpd], dv[kUpd];
 #pragma unroll
       for (int u = 0; u < kUpd; ++u) {
         const long long i = i0 + (long long)u * kBlock;
         if (i < end) {
-          xv[u] = x[i];
-          pv[u] = p[i];
           rv[u] = sb.r[i];
           qv[u] = q[i];
           zo[u] = jac ? (double)sb.z[i] : (double)sb.z32[i] * isc_prev;
@@ -341,7 +370,6 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(Work w, T* __restrict__ x,
       for (int u = 0; u < kUpd; ++u) {
         const long long i = i0 + (long long)u * kBlock;
         if (i >= end) continue;
-        x[i] = (T)(xv[u] + alpha * pv[u]);
         const double r = (double)(T)(rv[u] - alpha * qv[u]);
         sb.r[i] = (T)r;
         if (!jac) sb.r32[i] = (float)(r * sc);   // the multigrid's scaled copy
@@ -358,6 +386,25 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(Work w, T* __restrict__ x,
     rzo = block_sum(rzo, lds4);
     rzn = block_sum(rzn, lds4);
     store_partials(sb.partial + (size_t)it * 3, rr, rzo, rzn);
+  }
+}
+
+// The last iteration's x += alpha p of every system that iterated (the
+// earlier iterations' were made by the applies that followed them).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cg_finish(Work w, T* __restrict__ x, SolverBufsT<T> sb) {
+  int b0, b1;
+  work_range(w.nflat, b0, b1);
+  for (int it = b0; it < b1; ++it) {
+    const FlatBlk fb = w.flat[it];
+    const SolveScal* ssr = sb.ss + fb.rep;
+    const int n = ssr->it;
+    if (n == 0) continue;
+    const T* __restrict__ p = ((n - 1) & 1) ? sb.p0 : sb.p1;   // the direction of iteration n - 1
+    const double alpha = ssr->alpha;
+    const long long off = w.reps[fb.rep].off;
+    for (long long i = off + fb.begin + threadIdx.x; i < off + fb.end; i += kBlock)
+      x[i] = (T)((double)x[i] + alpha * (double)p[i]);
   }
 }
 
@@ -509,35 +556,38 @@ void launch_cg_start(hipStream_t s, const Work& w, double rtol, int maxit, const
 }
 
 template <typename T>
-void launch_cg_apply_kernel(hipStream_t s, const Work& w, const T* c, const SolverBufsT<T>& sb,
+void launch_cg_apply_kernel(hipStream_t s, const Work& w, const T* c, T* x, const SolverBufsT<T>& sb,
                             int parity) {
   const T* pold = parity ? sb.p1 : sb.p0;
   T* pnew = parity ? sb.p0 : sb.p1;
   if (sb.jacobi)
     hca_launch(k_cg_apply<true, T>, dim3(grid_tiles(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c,
-               (const T*)sb.z, pold, pnew, sb.q, sb);
+               (const T*)sb.z, pold, pnew, sb.q, x, sb);
   else
     hca_launch(k_cg_apply<false, T>, dim3(grid_tiles(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c,
-               (const T*)sb.z, pold, pnew, sb.q, sb);
+               (const T*)sb.z, pold, pnew, sb.q, x, sb);
 }
 
 template <typename T>
-void launch_cg_apply(hipStream_t s, const Work& w, const T* c, const SolverBufsT<T>& sb, int parity) {
-  launch_cg_apply_kernel(s, w, c, sb, parity);
+void launch_cg_apply(hipStream_t s, const Work& w, const T* c, T* x, const SolverBufsT<T>& sb, int parity) {
+  launch_cg_apply_kernel(s, w, c, x, sb, parity);
   launch_cg_reduce(s, w, sb, RED_APPLY, 0.0, 0);
 }
 
 template <typename T>
-void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, T* x,
-                      const SolverBufsT<T>& sb, int parity) {
-  const T* pnew = parity ? sb.p0 : sb.p1;
+void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, const SolverBufsT<T>& sb) {
   if (sb.jacobi)
-    hca_launch(k_cg_update<true, T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, x,
-               pnew, (const T*)sb.q, sb);
+    hca_launch(k_cg_update<true, T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w,
+               (const T*)sb.q, sb);
   else
-    hca_launch(k_cg_update<false, T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, x,
-               pnew, (const T*)sb.q, sb);
+    hca_launch(k_cg_update<false, T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w,
+               (const T*)sb.q, sb);
   launch_cg_reduce(s, w, sb, RED_UPDATE, rtol, maxit);
+}
+
+template <typename T>
+void launch_cg_finish(hipStream_t s, const Work& w, T* x, const SolverBufsT<T>& sb) {
+  hca_launch(k_cg_finish<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, x, sb);
 }
 
 #define HCA_SOLVER_INST(T)                                                                         \
@@ -545,11 +595,12 @@ void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, T* x
                                     int, unsigned, int);                                           \
   template void launch_cg_start<T>(hipStream_t, const Work&, double, int, const T*, const T*,      \
                                    const T*, const SolverBufsT<T>&, unsigned, int);                \
-  template void launch_cg_apply_kernel<T>(hipStream_t, const Work&, const T*,                      \
+  template void launch_cg_apply_kernel<T>(hipStream_t, const Work&, const T*, T*,                  \
                                           const SolverBufsT<T>&, int);                             \
-  template void launch_cg_apply<T>(hipStream_t, const Work&, const T*, const SolverBufsT<T>&, int); \
-  template void launch_cg_update<T>(hipStream_t, const Work&, double, int, T*,                     \
-                                    const SolverBufsT<T>&, int);
+  template void launch_cg_apply<T>(hipStream_t, const Work&, const T*, T*, const SolverBufsT<T>&,   \
+                                   int);                                                           \
+  template void launch_cg_update<T>(hipStream_t, const Work&, double, int, const SolverBufsT<T>&);  \
+  template void launch_cg_finish<T>(hipStream_t, const Work&, T*, const SolverBufsT<T>&);
 HCA_SOLVER_INST(double)
 HCA_SOLVER_INST(float)
 

@@ -66,7 +66,8 @@ enum KernelClass {
   KC_PLASMA = 0, KC_SETUP, KC_CG_START, KC_CG_APPLY, KC_CG_UPDATE, KC_ODE,
   KC_CA_PROPOSE, KC_CA_RESOLVE, KC_CA_FINALIZE, KC_STATS,
   KC_MG_PREP, KC_MG_PRE0, KC_MG_RESTRICT0, KC_MG_LEVELS, KC_MG_COARSE, KC_MG_POST1_0,
-  KC_MG_POST2_0, KC_MLP_APPLY, KC_VESSEL, KC_MG_SWEEP0, KC_MG_PRE3_0, KC_MG_POST3_0, KC_COUNT
+  KC_MG_POST2_0, KC_MLP_APPLY, KC_VESSEL, KC_MG_SWEEP0, KC_MG_PRE3_0, KC_MG_POST3_0, KC_CG_FINISH,
+  KC_COUNT
 };
 
 [[maybe_unused]] const char* kKernelNames[KC_COUNT] = {
@@ -74,7 +75,7 @@ enum KernelClass {
     "k_ode", "k_ca_propose", "k_ca_resolve", "k_ca_finalize", "k_stats",
     "k_mg_prep0+k_mg_coarsen", "k_mg_pre<L0>", "k_mg_restrict<L0>", "mg levels >= 1 (global)",
     "k_mg_coarse", "k_mg_post1<L0>", "k_mg_post2<L0>", "k_mlp_apply", "k_vessel", "k_mg_sweep<L0>",
-    "k_mg_prefused<L0>", "k_mg_postfused<L0>"};
+    "k_mg_prefused<L0>", "k_mg_postfused<L0>", "k_cg_finish"};
 
 // Compulsory (algorithmic) HBM bytes per voxel of each kernel class; solver
 // classes per voxel of each active system (0: not priced, latency-bound).
@@ -85,8 +86,9 @@ const double kBytesPerVoxel[KC_COUNT] = {
     0.0,            // plasma: per replicate only
     9.0 + 9 * kE,   // setup_step: read L, w, K, G1, G2; write c, b of three systems
     5 * kE,         // cg_start: read x, c, b; write r, (Jacobi: dinv, z)
-    4.0 + 4 * kE,   // cg_apply, multigrid: read z (4), p_old, c; write p_new, q
-    9 * kE,         // cg_update, Jacobi: read x, p, r, q, z, dinv; write x, r, z
+    4.0 + 6 * kE,   // cg_apply, multigrid: read z (4), p_old, c, x; write p_new, q, x (the
+                    // previous iteration's x += alpha p; a solve's first apply: 4 + 4 e)
+    6 * kE,         // cg_update, Jacobi: read r, q, z, dinv; write r, z
     49.0 + kE,      // ode: read L, K, P, Vc, phi; write P, Vc, phi
     11.0,           // ca_propose: scan (read L, phi; write code, win); the list's decisions
                     // gather per committed cell, not per voxel
@@ -104,15 +106,18 @@ const double kBytesPerVoxel[KC_COUNT] = {
     9.0 + kE,       // vessel: read L, w, V (writes only where a vessel changes)
     16.0,           // mg sweep L0: read u (4), r (4), dinv (4); write u' (4)
     12.5,           // mg prefused L0: read r (4), dinv (4); write u3 (4), r1 (1/8 of 4)
-    16.5 + kE};     // mg postfused L0: read u3 (4), e (1/8), r (4), dinv (4), r (stored); write z (4)
+    16.5 + kE,      // mg postfused L0: read u3 (4), e (1/8), r (4), dinv (4), r (stored); write z (4)
+    3 * kE};        // cg_finish: read x, p; write x (once per solve)
 constexpr double kBytesSetupVegf = 8.0 + 3 * kE;   // setup_step with vegf: + read V, Vc; write c, b
 constexpr double kBytesSetupDrug3 = 3 * kE;        // setup_step with drug3: + read G3; write c, b
 constexpr double kBytesStatsField = kE;            // stats: per extra field scanned (V, G3)
-// cg_update, multigrid: the compulsory x, p, r, q read and x, r written (the
-// CG's own traffic); the kernel also reads the FP32 z and writes the FP32
-// copy of r for the multigrid (8 B more per voxel, not counted here)
-constexpr double kBytesUpdateMg = 6 * kE;
-constexpr double kBytesApplyJacobi = 5 * kE;       // cg_apply, Jacobi: z is a stored field value
+// cg_update, multigrid: the compulsory r, q read and r written (the CG's own
+// traffic; x += alpha p moved to the next apply); the kernel also reads the
+// FP32 z and writes the FP32 copy of r for the multigrid (8 B more per voxel,
+// not counted here)
+constexpr double kBytesUpdateMg = 3 * kE;
+constexpr double kBytesApplyJacobi = 7 * kE;       // cg_apply, Jacobi: z is a stored field value
+constexpr double kBytesApplyX = 2 * kE;            // cg_apply's x read and write (not on a solve's first)
 
 constexpr int kTagState = -2;   // launches over every voxel of every replicate
 constexpr int kTagAll = -1;     // solver launches over every system
@@ -268,9 +273,10 @@ struct ProfScope {
   int kc;
   int tag;
   bool single;
+  double dbpv;   // added to the class's bytes per voxel for this launch
   hipEvent_t a = nullptr, b = nullptr;
-  ProfScope(Ctx* c_, int kc_, int tag_, bool single_ = true)
-      : c(c_), kc(kc_), tag(tag_), single(single_) {
+  ProfScope(Ctx* c_, int kc_, int tag_, bool single_ = true, double dbpv_ = 0.0)
+      : c(c_), kc(kc_), tag(tag_), single(single_), dbpv(dbpv_) {
     if (!prof_on(c, kc)) return;
     a = take_event(c);
     b = take_event(c);
@@ -297,7 +303,7 @@ struct ProfScope {
     } else {
       (void)hipEventRecord(b, c->stream);
     }
-    c->pending.push_back(ProfEntry{kc, a, b, tag, bpv_of(c, kc)});
+    c->pending.push_back(ProfEntry{kc, a, b, tag, bpv_of(c, kc) + dbpv});
   }
 };
 
@@ -515,8 +521,8 @@ bool capture_iterations(Ctx* c, const Work& W, const MgBufs& mg, double rtol, in
     return false;
   }
   for (int par = 0; par < 2; ++par) {
-    launch_cg_apply(cs, W, c->c, c->sb, par);
-    launch_cg_update(cs, W, rtol, maxit, c->F, c->sb, par);
+    launch_cg_apply(cs, W, c->c, c->F, c->sb, par);
+    launch_cg_update(cs, W, rtol, maxit, c->sb);
     if (c->use_mg) launch_mg_vcycle(cs, W, mg, c->sb, nullptr, nullptr);
   }
   hipGraph_t g = nullptr;
@@ -570,12 +576,13 @@ hca_status solve(Ctx* c, const Work& W_all, const MgBufs& mg_all, unsigned fmask
   int real = 0;
   auto iteration = [&](int it) {
     {
-      ProfScope ps(c, KC_CG_APPLY, it);
-      launch_cg_apply(c->stream, *Wp, c->c, c->sb, it & 1);
+      // a solve's first apply has no earlier x += alpha p to make
+      ProfScope ps(c, KC_CG_APPLY, it, true, it == 0 ? -kBytesApplyX : 0.0);
+      launch_cg_apply(c->stream, *Wp, c->c, c->F, c->sb, it & 1);
     }
     {
       ProfScope ps(c, KC_CG_UPDATE, it);
-      launch_cg_update(c->stream, *Wp, rtol, maxit, c->F, c->sb, it & 1);
+      launch_cg_update(c->stream, *Wp, rtol, maxit, c->sb);
     }
     // z = M r for the next direction (work only where this iteration did not converge)
     if (c->use_mg) run_vcycle(c, *Wp, *mgp, it + 1);
@@ -618,6 +625,10 @@ hca_status solve(Ctx* c, const Work& W_all, const MgBufs& mg_all, unsigned fmask
         graphs = graphs && (c->iter_graph[1] || capture_iterations(c, c->sys1, c->mg1, rtol, maxit, 1));
       }
     }
+  }
+  {   // the last iteration's x += alpha p (systems that iterated)
+    ProfScope ps(c, KC_CG_FINISH, 0);
+    launch_cg_finish(c->stream, W_all, c->F, c->sb);
   }
   prof_flush(c, c->h_ss, nsys);
   c->last_it[kind] = real;
@@ -1004,6 +1015,7 @@ hca_status plan_tiles(Ctx* c) {
     maxtiles = std::max(maxtiles, t);
   }
   Real* cb = (Real*)scratch(sizeof(Real) * n);
+  Real* tx = (Real*)scratch(sizeof(Real) * n);   // the apply's x (a zero alpha leaves it as it is)
   SolverBufs tsb{};
   tsb.z32 = (float*)scratch(4 * n);   // multigrid layout (jacobi = 0)
   tsb.p0 = (Real*)scratch(sizeof(Real) * n);
@@ -1014,7 +1026,7 @@ hca_status plan_tiles(Ctx* c) {
   RepDev* drep = (RepDev*)scratch(sizeof(RepDev) * R);
   Tile* dtiles = (Tile*)scratch(sizeof(Tile) * maxtiles);
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (!cb || !tsb.z32 || !tsb.p0 || !tsb.p1 || !tsb.q || !tsb.partial || !tsb.ss || !drep || !dtiles ||
+  if (!cb || !tx || !tsb.z32 || !tsb.p0 || !tsb.p1 || !tsb.q || !tsb.partial || !tsb.ss || !drep || !dtiles ||
       hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     release();
     if (e0) (void)hipEventDestroy(e0);
@@ -1025,7 +1037,7 @@ hca_status plan_tiles(Ctx* c) {
     if (e != hipSuccess && st == HCA_OK)
       st = fail(c, HCA_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
   };
-  for (void* p : {(void*)cb, (void*)tsb.p0, (void*)tsb.p1})
+  for (void* p : {(void*)cb, (void*)tx, (void*)tsb.p0, (void*)tsb.p1})
     check(hipMemsetAsync(p, 0, sizeof(Real) * n, c->stream));
   check(hipMemsetAsync(tsb.z32, 0, 4 * n, c->stream));
   check(hipMemsetAsync(tsb.ss, 0, sizeof(SolveScal) * R, c->stream));
@@ -1062,11 +1074,11 @@ hca_status plan_tiles(Ctx* c) {
       w.tiles = dtiles;
       w.ntiles = (int)tiles.size();
       w.max_blocks = c->work.max_blocks;
-      launch_cg_apply_kernel(c->stream, w, cb, tsb, 0);
+      launch_cg_apply_kernel(c->stream, w, cb, tx, tsb, 0);
       float tmin = 1e30f;
       for (int k = 0; k < 3; ++k) {
         check(hipEventRecord(e0, c->stream));
-        launch_cg_apply_kernel(c->stream, w, cb, tsb, 0);
+        launch_cg_apply_kernel(c->stream, w, cb, tx, tsb, 0);
         check(hipEventRecord(e1, c->stream));
         check(hipEventSynchronize(e1));
         float ms = 0.f;

@@ -25,7 +25,7 @@ SOURCES = ["paper_2105_00448_amd/csrc/k_solver.hip", "paper_2105_00448_amd/csrc/
            "paper_2105_00448_amd/csrc/dev_util.h", "paper_2105_00448_amd/csrc/hca_internal.h"]
 COPY_KIB = 256 * 1024
 # the counter passes collect only these dispatches (--kernel-include-regex)
-PMC_REGEX = ("k_cg_update|k_cg_apply|k_mg_pre|k_mg_sweep|k_mg_restrict|k_mg_post1|k_mg_post2|"
+PMC_REGEX = ("k_cg_update|k_cg_apply|k_cg_finish|k_mg_pre|k_mg_sweep|k_mg_restrict|k_mg_post1|k_mg_post2|"
              "k_mg_postfused|k_mg_coarse|k_init_cells|copyBuffer")
 # kernels priced per launch (levels below level 0, the one-workgroup coarse solve)
 PER_LAUNCH = ["k_mg_prefused<2>", "k_mg_postfused<2, false, double, double>",
@@ -43,8 +43,9 @@ def kernels(e):
     three-stage passes k_mg_prefused<3> / k_mg_postfused<3, ...> (the default)."""
     fp = "double" if e == 8 else "float"
     return {
-        f"k_cg_update<false, {fp}>": ("k_cg_update", 6 * e),
-        f"k_cg_apply<false, {fp}>": ("k_cg_apply", 4 + 4 * e),
+        f"k_cg_update<false, {fp}>": ("k_cg_update", 3 * e),
+        f"k_cg_apply<false, {fp}>": ("k_cg_apply", 4 + 6 * e),
+        f"k_cg_finish<{fp}>": ("k_cg_finish", 3 * e),
         "k_mg_pre<true, float>": ("k_mg_pre_L0", 12.0),
         "k_mg_sweep<true, float>": ("k_mg_sweep_L0", 16.0),
         "k_mg_restrict<true, float>": ("k_mg_restrict_L0", 12.5),
