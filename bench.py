@@ -878,10 +878,11 @@ def config5_headline(args, stream):
     return rec
 
 
-def single_workload(args, stream, workload, repeats):
+def single_workload(args, stream, workload, repeats, config_steps=False):
     """One workload (plain128, batched64) stepped from fresh contexts: the
     median of `repeats` timed runs, the dominant kernel's roofline from one
-    further event-timed run."""
+    further event-timed run.  `config_steps`: the workload's own step count
+    (a leg beside the headline), not --steps."""
     import torch
 
     from paper_2105_00448_amd import hca
@@ -890,7 +891,7 @@ def single_workload(args, stream, workload, repeats):
     solver_kw = {"precond": args.precond, "graphs": args.graphs, "autotune": args.autotune}
     if args.mg_coarse_max is not None:
         solver_kw["mg_coarse_max"] = args.mg_coarse_max
-    steps = args.steps if args.steps is not None else cfg_steps
+    steps = cfg_steps if config_steps or args.steps is None else args.steps
     nvox = sum(r[0].size for r in reps)
 
     # warm-up on a throwaway context (code loading, clocks), every kernel
@@ -1068,7 +1069,7 @@ def main():
     legs = [] if args.no_legs else [x for x in args.legs.split(",") if x]
     crop = rec.pop("_cpu_sample", None)
     if "plain128" in legs and args.workload != "plain128":
-        rec["plain128"] = single_workload(args, stream, "plain128", 3)
+        rec["plain128"] = single_workload(args, stream, "plain128", 3, config_steps=True)
     if "surrogate" in legs:
         rec["surrogate"] = surrogate_leg(stream, args.sur_steps, args.train_steps)
     if "batched" in legs:
