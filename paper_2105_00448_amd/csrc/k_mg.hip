@@ -866,12 +866,11 @@ __global__ void __launch_bounds__(kF3Block) k_mg_prefused(MgLevel Lk, MgLevel Lc
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           if (F3_RING(j) > S - st) continue;
-          float v = 0.f;
-          if (in && f.col[j] >= 0) {
-            const float nb = f3_xy(sV[st - 1][rb], f.p[j], EX) + (hs[st - 1][j][2] + hs[st - 1][j][0]);
-            v = (1.f - w.w[st]) * hs[st - 1][j][1] + w.w[st] * dh[j][st] * (rh[j][st] + a * nb);
-            if (st == S - 1 && j == 0 && z >= z0 && z < z1) uS[plane * z + f.col[0]] = v;
-          }
+          const float nb = f3_xy(sV[st - 1][rb], f.p[j], EX) + (hs[st - 1][j][2] + hs[st - 1][j][0]);
+          float v = (1.f - w.w[st]) * hs[st - 1][j][1] + w.w[st] * dh[j][st] * (rh[j][st] + a * nb);
+          const bool ok = in && f.col[j] >= 0;
+          v = ok ? v : 0.f;
+          if (st == S - 1 && j == 0 && ok && z >= z0 && z < z1) uS[plane * z + f.col[0]] = v;
           f3_push(hs[st][j], v);
           sV[st][wb][f.p[j]] = v;
         }
@@ -995,11 +994,10 @@ __global__ void __launch_bounds__(kF3Block) k_mg_postfused(MgLevel Lk, MgLevel L
         if (F3_RING(j) > S) continue;
         f3_push(rh[j], nr[j]);
         f3_push(dh[j], nd[j]);
-        float v = 0.f;
-        if (in && f.col[j] >= 0) {
-          const float eI = sE[Iz & 3][f.p[j]];
-          v = nu[j] + (Jz == Iz ? eI : (1.f - wz) * eI + wz * sE[Jz & 3][f.p[j]]);
-        }
+        // branch-free: with Jz == Iz, wz is 0 and the sum is eI exactly
+        const float eI = sE[Iz & 3][f.p[j]], eJ = sE[Jz & 3][f.p[j]];
+        float v = nu[j] + ((1.f - wz) * eI + wz * eJ);
+        v = (in && f.col[j] >= 0) ? v : 0.f;
         f3_push(hs[0][j], v);
         sV[0][wb][f.p[j]] = v;
       }
@@ -1013,11 +1011,9 @@ __global__ void __launch_bounds__(kF3Block) k_mg_postfused(MgLevel Lk, MgLevel L
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           if (F3_RING(j) > S - st) continue;
-          float v = 0.f;
-          if (in && f.col[j] >= 0) {
-            const float nb = f3_xy(sV[st - 1][rb], f.p[j], EX) + (hs[st - 1][j][2] + hs[st - 1][j][0]);
-            v = (1.f - w.w[st - 1]) * hs[st - 1][j][1] + w.w[st - 1] * dh[j][st] * (rh[j][st] + a * nb);
-          }
+          const float nb = f3_xy(sV[st - 1][rb], f.p[j], EX) + (hs[st - 1][j][2] + hs[st - 1][j][0]);
+          float v = (1.f - w.w[st - 1]) * hs[st - 1][j][1] + w.w[st - 1] * dh[j][st] * (rh[j][st] + a * nb);
+          v = (in && f.col[j] >= 0) ? v : 0.f;
           f3_push(hs[st][j], v);
           sV[st][wb][f.p[j]] = v;
         }
