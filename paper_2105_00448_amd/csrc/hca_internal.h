@@ -279,6 +279,15 @@ template <typename T>
 void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, const SolverBufsT<T>& sb);
 template <typename T>
 void launch_cg_finish(hipStream_t s, const Work& w, T* x, const SolverBufsT<T>& sb);
+// The solves' initial guess (x0_extrapolate = 3) for the systems of the
+// fields in fmask: F <- the least-squares fit of b in span(A F, A (F - Fprev))
+// or the geometric extrapolation, whichever leaves the smaller residual, and
+// Fprev <- F.  q, sg: scratch of the fields' size; part: kGuessPartsPerTile
+// doubles per tile of w; alpha: 3 per system.
+constexpr int kGuessPartsPerTile = 8;
+template <typename T>
+void launch_guess_projection(hipStream_t s, const Work& w, const T* c, const T* b, T* F, T* Fprev, T* q, T* sg,
+                             double* part, double* alpha, unsigned fmask, int nrep);
 
 // ---- geometric multigrid (k_mg.hip) ---------------------------------------
 constexpr int kMaxLevels = 16;

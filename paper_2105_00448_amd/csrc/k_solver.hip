@@ -408,6 +408,154 @@ __global__ void __launch_bounds__(kBlock) k_cg_finish(Work w, T* __restrict__ x,
   }
 }
 
+// ---- the solves' initial guess from their two previous solutions -----------
+//
+// x1 is the field's value (its last solve's solution), x2 the solution
+// before.  Two candidates: the least-squares fit x_f = b1 x1 + b2 (x1 - x2),
+// (b1, b2) minimising ||b - A x_f|| for this solve's system (the 2 x 2 normal
+// equations in u = A x1, w = A (x1 - x2)), and the geometric extrapolation
+// x_g (the per-voxel rule of k_extrapolate).  The one with the smaller
+// residual norm (from the same products: ||b||^2 - 2 b.y + y.y) is taken.  A
+// drug field's operator is the same from step to step and its solutions
+// follow a smooth course in time, so b lies close to the span of u and w;
+// once a field decays geometrically voxel by voxel, x_g does better.  The
+// difference x1 - x2 is formed per voxel before the operator is applied
+// (no cancellation between A x1 and A x2 when the two are close).
+__device__ inline double geo_guess(double u, double up) {
+  return (up > 0.0 && u > 0.0 && u < up) ? u * (u / up) : u;
+}
+
+template <typename T>
+struct OpPair {   // operand f(x1, x2) per voxel: x1 - x2 (GEO false) or x_g
+  struct Raw {
+    double a, b;
+  };
+  struct Ctr {};
+  const T* __restrict__ x1;
+  const T* __restrict__ x2;
+  bool geo;
+  __device__ inline Raw zero() const { return Raw{0.0, 0.0}; }
+  __device__ inline Raw load(long long j) const { return Raw{x1[j], x2[j]}; }
+  __device__ inline double value(const Raw& r) const { return geo ? geo_guess(r.a, r.b) : r.a - r.b; }
+  __device__ inline Ctr ctr_zero() const { return Ctr{}; }
+  __device__ inline Ctr load_ctr(long long) const { return Ctr{}; }
+  __device__ inline void at_center(long long, const Raw&, const Ctr&) const {}
+};
+
+// Per tile: w = A (x1 - x2) into q, g = A x_g into s (both free before the
+// solve), then u = A x1 and the products u.u, u.w, w.w, b.u, b.w, b.b, b.g,
+// g.g (w and g read back at the same voxel).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_guess_dots(Work w, const T* __restrict__ c, const T* __restrict__ b,
+                                                       const T* __restrict__ x1, const T* __restrict__ x2,
+                                                       T* __restrict__ q, T* __restrict__ sg,
+                                                       double* __restrict__ part, unsigned fmask, int nrep) {
+  __shared__ double lds4[4];
+  __shared__ T lds[2][kPlaneMax];
+  int t0, t1;
+  tile_range(w.ntiles, t0, t1);
+  for (int ti = t0; ti < t1; ++ti) {
+    const TileCoord tc = tile_coord(w, ti);
+    if (!((fmask >> (tc.rep / nrep)) & 1u)) continue;
+    plane_stencil<kStencilPrefetch>(tc, c, lds, OpPair<T>{x1, x2, false},
+                                    [&](long long i, int, double, double Aw) { q[i] = (T)Aw; });
+    plane_stencil<kStencilPrefetch>(tc, c, lds, OpPair<T>{x1, x2, true},
+                                    [&](long long i, int, double, double Ag) { sg[i] = (T)Ag; });
+    double d[kGuessPartsPerTile] = {};
+    plane_stencil<kStencilPrefetch>(tc, c, lds, OpX<T>{x1}, [&](long long i, int, double, double u) {
+      const double wv = q[i], g = sg[i], bi = b[i];
+      d[0] += u * u;
+      d[1] += u * wv;
+      d[2] += wv * wv;
+      d[3] += bi * u;
+      d[4] += bi * wv;
+      d[5] += bi * bi;
+      d[6] += bi * g;
+      d[7] += g * g;
+    });
+#pragma unroll
+    for (int k = 0; k < kGuessPartsPerTile; ++k) d[k] = block_sum(d[k], lds4);
+    if (threadIdx.x == 0) {
+      double* o = part + (size_t)ti * kGuessPartsPerTile;
+#pragma unroll
+      for (int k = 0; k < kGuessPartsPerTile; ++k) o[k] = d[k];
+    }
+  }
+}
+
+// One workgroup per system: the tiles' products summed in a fixed order; the
+// fit's coefficients (u and w nearly parallel, as when x2 = x1 after the
+// first solve: x1 alone, scaled), and which candidate is taken:
+// alpha[3 s] = 1 for x_g, else 0; alpha[3 s + 1], alpha[3 s + 2] = (b1, b2).
+__global__ void __launch_bounds__(kBlock) k_guess_reduce(Work w, const double* __restrict__ part,
+                                                         double* __restrict__ alpha, unsigned fmask,
+                                                         int nrep) {
+  __shared__ double lds4[4];
+  const int rep = blockIdx.x;
+  if (!((fmask >> (rep / nrep)) & 1u)) return;
+  const RepDev rp = w.reps[rep];
+  double t[kGuessPartsPerTile];
+#pragma unroll
+  for (int k = 0; k < kGuessPartsPerTile; ++k) {
+    double s = 0.0;
+    for (int j = threadIdx.x; j < rp.tile_nb; j += kBlock)
+      s += part[(size_t)(rp.tile_b0 + j) * kGuessPartsPerTile + k];
+    t[k] = block_sum(s, lds4);
+  }
+  if (threadIdx.x != 0) return;
+  const double uu = t[0], uw = t[1], ww = t[2], bu = t[3], bw = t[4], bb = t[5], bg = t[6], gg = t[7];
+  double b1 = 1.0, b2 = 0.0;
+  if (uu > 0.0) {
+    const double det = uu * ww - uw * uw;
+    if (ww > 0.0 && det > 1e-14 * uu * ww) {
+      b1 = (bu * ww - bw * uw) / det;
+      b2 = (bw * uu - bu * uw) / det;
+    } else {
+      b1 = bu / uu;
+    }
+  }
+  if (!isfinite(b1) || !isfinite(b2)) {
+    b1 = 1.0;
+    b2 = 0.0;
+  }
+  const double rf = bb - 2.0 * (b1 * bu + b2 * bw) + b1 * b1 * uu + 2.0 * b1 * b2 * uw + b2 * b2 * ww;
+  const double rg = bb - 2.0 * bg + gg;
+  alpha[3 * rep] = (isfinite(rg) && rg < rf) ? 1.0 : 0.0;
+  alpha[3 * rep + 1] = b1;
+  alpha[3 * rep + 2] = b2;
+}
+
+// F <- the chosen candidate, Fprev <- F (the systems of the fields in fmask).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_guess_apply(Work w, T* __restrict__ F, T* __restrict__ Fprev,
+                                                        const double* __restrict__ alpha, unsigned fmask,
+                                                        int nrep) {
+  int b0, b1;
+  work_range(w.nflat, b0, b1);
+  for (int it = b0; it < b1; ++it) {
+    const FlatBlk fb = w.flat[it];
+    if (!((fmask >> (fb.rep / nrep)) & 1u)) continue;
+    const bool geo = alpha[3 * fb.rep] != 0.0;
+    const double c1 = alpha[3 * fb.rep + 1], c2 = alpha[3 * fb.rep + 2];
+    const long long off = w.reps[fb.rep].off;
+    for (long long i = off + fb.begin + threadIdx.x; i < off + fb.end; i += kBlock) {
+      const double u = F[i], up = Fprev[i];
+      F[i] = (T)(geo ? geo_guess(u, up) : c1 * u + c2 * (double)(T)(u - up));
+      Fprev[i] = (T)u;
+    }
+  }
+}
+
+template <typename T>
+void launch_guess_projection(hipStream_t s, const Work& w, const T* c, const T* b, T* F, T* Fprev, T* q, T* sg,
+                             double* part, double* alpha, unsigned fmask, int nrep) {
+  hca_launch(k_guess_dots<T>, dim3(grid_tiles(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c, b,
+             (const T*)F, (const T*)Fprev, q, sg, part, fmask, nrep);
+  hca_launch(k_guess_reduce, dim3(w.nreps), dim3(kBlock), 0, s, w, (const double*)part, alpha, fmask, nrep);
+  hca_launch(k_guess_apply<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, F, Fprev,
+             (const double*)alpha, fmask, nrep);
+}
+
 // Power of two near 1/rms(r) for a system of n unknowns with ||r||^2 = rr
 // (1 when rr is 0 or not finite).
 __device__ inline double residual_scale(double rr, long long n) {
@@ -600,7 +748,9 @@ void launch_cg_finish(hipStream_t s, const Work& w, T* x, const SolverBufsT<T>& 
   template void launch_cg_apply<T>(hipStream_t, const Work&, const T*, T*, const SolverBufsT<T>&,   \
                                    int);                                                           \
   template void launch_cg_update<T>(hipStream_t, const Work&, double, int, const SolverBufsT<T>&);  \
-  template void launch_cg_finish<T>(hipStream_t, const Work&, T*, const SolverBufsT<T>&);
+  template void launch_cg_finish<T>(hipStream_t, const Work&, T*, const SolverBufsT<T>&);        \
+  template void launch_guess_projection<T>(hipStream_t, const Work&, const T*, const T*, T*, T*, T*, \
+                                           T*, double*, double*, unsigned, int);
 HCA_SOLVER_INST(double)
 HCA_SOLVER_INST(float)
 

@@ -67,7 +67,7 @@ enum KernelClass {
   KC_CA_PROPOSE, KC_CA_RESOLVE, KC_CA_FINALIZE, KC_STATS,
   KC_MG_PREP, KC_MG_PRE0, KC_MG_RESTRICT0, KC_MG_LEVELS, KC_MG_COARSE, KC_MG_POST1_0,
   KC_MG_POST2_0, KC_MLP_APPLY, KC_VESSEL, KC_MG_SWEEP0, KC_MG_PRE3_0, KC_MG_POST3_0, KC_CG_FINISH,
-  KC_COUNT
+  KC_GUESS, KC_COUNT
 };
 
 [[maybe_unused]] const char* kKernelNames[KC_COUNT] = {
@@ -75,7 +75,7 @@ enum KernelClass {
     "k_ode", "k_ca_propose", "k_ca_resolve", "k_ca_finalize", "k_stats",
     "k_mg_prep0+k_mg_coarsen", "k_mg_pre<L0>", "k_mg_restrict<L0>", "mg levels >= 1 (global)",
     "k_mg_coarse", "k_mg_post1<L0>", "k_mg_post2<L0>", "k_mlp_apply", "k_vessel", "k_mg_sweep<L0>",
-    "k_mg_prefused<L0>", "k_mg_postfused<L0>", "k_cg_finish"};
+    "k_mg_prefused<L0>", "k_mg_postfused<L0>", "k_cg_finish", "k_guess (fit)"};
 
 // Compulsory (algorithmic) HBM bytes per voxel of each kernel class; solver
 // classes per voxel of each active system (0: not priced, latency-bound).
@@ -107,7 +107,9 @@ const double kBytesPerVoxel[KC_COUNT] = {
     16.0,           // mg sweep L0: read u (4), r (4), dinv (4); write u' (4)
     12.5,           // mg prefused L0: read r (4), dinv (4); write u3 (4), r1 (1/8 of 4)
     16.5 + kE,      // mg postfused L0: read u3 (4), e (1/8), r (4), dinv (4), r (stored); write z (4)
-    3 * kE};        // cg_finish: read x, p; write x (once per solve)
+    3 * kE,         // cg_finish: read x, p; write x (once per solve)
+    17 * kE};       // guess fit, per voxel of one fitted field: read x1, x2, c; write A (x1 - x2);
+                    // the same for A x_g; read x1, c, b and the two; read x1, x2; write x0, x2
 constexpr double kBytesSetupVegf = 8.0 + 3 * kE;   // setup_step with vegf: + read V, Vc; write c, b
 constexpr double kBytesSetupDrug3 = 3 * kE;        // setup_step with drug3: + read G3; write c, b
 constexpr double kBytesStatsField = kE;            // stats: per extra field scanned (V, G3)
@@ -167,6 +169,8 @@ struct Ctx : ::hca_ctx {
   double *dose_t = nullptr, *dose_a = nullptr, *g0 = nullptr;
   Real* b_o2lin = nullptr;                       // o2_newton: the linearised O2 right-hand side
   Real* Fprev = nullptr;                         // x0_extrapolate: fields of the previous solve
+  double* d_gpart = nullptr;                     // x0_extrapolate = 3: products per solver tile
+  double* d_galpha = nullptr;                    // and the choice and fit coefficients per system
   long long* d_step = nullptr;
   // replicate tables (state kernels)
   RepDev* d_reps = nullptr;
@@ -661,16 +665,27 @@ hca_status run_phases(Ctx* c, unsigned mask) {
       launch_plasma(s, wk, c->dp, c->d_step, j, c->dose_t, c->dose_a, c->g0);
     }
     // the initial guess in the setup pass where nothing reads F after it
+    // (extrapolations), or fitted to this solve's system after the setup
+    // (x0_extrapolate 3: the fields but oxygen fitted after the setup, from
+    // this solve's system; oxygen, whose operator follows the cells, keeps the
+    // geometric extrapolation)
+    const unsigned fitmask = (c->Fprev && c->prm.x0_extrapolate == 3) ? (fmask & ~1u) : 0u;
+    const unsigned xmask = fmask & ~fitmask;
     const bool guess_in_setup = c->Fprev && c->dp.theta >= 1.0;
     {
       ProfScope ps(c, KC_SETUP, kTagState);
       launch_setup_step(s, wk, c->dp, c->ntot, c->L, c->w, c->F, c->Vc, c->g0, c->c, c->b,
-                        guess_in_setup ? c->Fprev : nullptr, fmask, c->prm.x0_extrapolate);
+                        guess_in_setup ? c->Fprev : nullptr, xmask, c->prm.x0_extrapolate);
       if (c->dp.theta < 1.0) launch_rhs_lap(s, wk, c->dp, c->ntot, c->F, c->b);
     }
-    if (c->Fprev && !guess_in_setup) {
+    if (c->Fprev && !guess_in_setup && xmask) {
       ProfScope ps(c, KC_SETUP, kTagState);
-      launch_extrapolate(s, wk, c->ntot, c->dp.nf, fmask, c->prm.x0_extrapolate, c->F, c->Fprev);
+      launch_extrapolate(s, wk, c->ntot, c->dp.nf, xmask, c->prm.x0_extrapolate, c->F, c->Fprev);
+    }
+    if (fitmask) {   // priced per voxel of each fitted field (three launches)
+      ProfScope ps(c, KC_GUESS, kTagState, false, (__builtin_popcount(fitmask) - 1) * kBytesPerVoxel[KC_GUESS]);
+      launch_guess_projection(s, c->sys_all, c->c, c->b, c->F, c->Fprev, c->sb.q, c->sb.p0, c->d_gpart,
+                              c->d_galpha, fitmask, c->nreps);
     }
     const bool newton = c->prm.o2_newton > 0 && (fmask & 1u);
     if (newton)
@@ -862,8 +877,8 @@ hca_status validate_params(const hca_params* p, std::string& msg) {
       return HCA_E_INVALID;
     }
   }
-  if (p->x0_extrapolate < 0 || p->x0_extrapolate > 2) {
-    msg = "x0_extrapolate in {0, 1, 2}";
+  if (p->x0_extrapolate < 0 || p->x0_extrapolate > 3) {
+    msg = "x0_extrapolate in {0, 1, 2, 3}";
     return HCA_E_INVALID;
   }
   if (p->mg_smooth != 2) {
@@ -1267,6 +1282,10 @@ hca_status alloc_all(Ctx* c) {
   HIPCHK(c, dalloc(&c->g0, (size_t)c->nreps * 6));   // levels at both ends of a field substep
   if (c->prm.o2_newton > 0 && (st = big(&c->b_o2lin, (size_t)c->ntot)) != HCA_OK) return st;
   if (c->prm.x0_extrapolate && (st = big(&c->Fprev, n3)) != HCA_OK) return st;
+  if (c->prm.x0_extrapolate == 3) {
+    HIPCHK(c, dalloc(&c->d_gpart, (size_t)kGuessPartsPerTile * std::max(1, c->sys_all.ntiles)));
+    HIPCHK(c, dalloc(&c->d_galpha, 3 * (size_t)nsys));
+  }
   HIPCHK(c, dalloc(&c->d_step, 1));
   HIPCHK(c, dalloc(&c->d_cnt, c->nreps));
   HIPCHK(c, dalloc(&c->d_cpart, (size_t)c->work.nflat * kCounterSlots));
@@ -1549,7 +1568,7 @@ hca_status steady_oxygen(Ctx* c) {
 void free_all(Ctx* c) {
   void* bufs[] = {c->L, c->code, c->win, (void*)c->ca_list.cells, (void*)c->ca_list.item_n, c->w, c->P, c->Vc, c->phi, c->F, c->c, c->b,
                   c->sb.r, c->sb.z, (void*)c->sb.z32, (void*)c->sb.r32, c->sb.p0, c->sb.p1, c->sb.q, c->sb.dinv, c->sb.partial,
-                  c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->b_o2lin, c->Fprev, c->d_step,
+                  c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->b_o2lin, c->Fprev, c->d_gpart, c->d_galpha, c->d_step,
                   c->d_reps, c->d_flat, c->d_tiles, c->d_sys, c->d_sflat, c->d_stiles, c->d_ftiles, c->d_cnt, (void*)c->d_cpart,
                   c->d_bad, c->d_theta, (void*)c->d_pack, (void*)c->d_gelu, c->before,
                   c->item_cnt, c->item_off};
@@ -1939,7 +1958,7 @@ extern "C" hca_status hca_default_params(hca_params* out) {
   out->epi_cl = 0.983e3;
   out->G_ref3 = 1.0;
   out->b_int3 = 1;
-  out->x0_extrapolate = 2;
+  out->x0_extrapolate = 3;
   out->precision = 64;
   out->mg_fuse = 1;
   return HCA_OK;

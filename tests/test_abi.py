@@ -140,7 +140,7 @@ def test_rejects_bad_params_and_arguments():
                dict(dv_min=45.0), dict(dv_min=15.0), dict(V_low=2e-4), dict(p_death=1.5),
                dict(birth_per_V=2.0e4), dict(w_new=0.0), dict(sec_V=float("nan")), dict(drug3=2),
                dict(epi_w1=0.0), dict(epi_q2=-1.0), dict(epi_cl=float("inf")), dict(G_ref3=0.0),
-               dict(b_int3=0), dict(b_int3=65), dict(x0_extrapolate=3), dict(x0_extrapolate=-1)):
+               dict(b_int3=0), dict(b_int3=65), dict(x0_extrapolate=4), dict(x0_extrapolate=-1)):
         assert init_status([(cell, w, NODOSE)], hca.default_params(**kw)) == hca.E_INVALID, kw
     lib = hca.lib()
     assert lib.hca_init(None, None, None, 0, None) == hca.E_INVALID

@@ -393,14 +393,16 @@ def test_error_paths_on_device(case32):
 
 
 def test_initial_guess_modes_agree(case32):
-    """The solves' initial guess (plain, linear, geometric extrapolation)
-    changes the iteration counts, not the converged fields: five full steps
-    from the same state with boluses agree to the field tolerance, and the
-    geometric guess needs fewer drug iterations once the plasma decays."""
+    """The solves' initial guess (plain, linear, geometric extrapolation, the
+    least-squares fit over the two previous solutions) changes the iteration
+    counts, not the converged fields: five full steps from the same state
+    with boluses agree to the field tolerance, and once the plasma decays the
+    geometric guess needs fewer drug iterations than the plain one and the
+    fit no more than the geometric one."""
     tis, _, _ = case32
     sched = synth.DoseSchedule(times=((0.0,), (0.0, 60.0)), amts=((1.0,), (1.0, 0.5)))
     out, iters = {}, {}
-    for mode in (0, 1, 2):
+    for mode in (0, 1, 2, 3):
         with make_sim([(tis, sched)], x0_extrapolate=mode) as sim:
             its = []
             for _ in range(5):
@@ -408,14 +410,14 @@ def test_initial_guess_modes_agree(case32):
                 its.append(sim.stats()["cg_iters"])
             out[mode] = {n: sim.field(n) for n in ("K", "G1", "G2", "P", "Vc", "L")}
             iters[mode] = np.array(its)
-    for mode in (1, 2):
+    for mode in (1, 2, 3):
         for name in ("K", "G1", "G2", "P", "Vc"):
             assert relerr(out[mode][name], out[0][name]) <= FIELD_TOL, (mode, name)
         assert np.array_equal(out[mode]["L"], out[0]["L"]), mode
     # at the working tolerance, once the plasma decays (steps 6..12 after a
     # single bolus) the geometric guess saves drug iterations
     one = synth.bolus_schedule([0])
-    for mode in (0, 2):
+    for mode in (0, 2, 3):
         with make_sim([(tis, one)], x0_extrapolate=mode, cg_rtol=1e-10, init_rtol=1e-10) as sim:
             its = []
             for _ in range(12):
@@ -423,6 +425,7 @@ def test_initial_guess_modes_agree(case32):
                 its.append(sim.stats()["cg_iters"])
             iters[mode] = np.array(its)
     assert iters[2][6:, 1:].sum() < iters[0][6:, 1:].sum(), (iters[0], iters[2])
+    assert iters[3][6:, 1:].sum() <= iters[2][6:, 1:].sum(), (iters[2], iters[3])
 
 
 @pytest.mark.parametrize("theta", [1.0, 0.5], ids=["be", "cn"])
