@@ -176,12 +176,12 @@ typedef struct hca_params {
      with hca_set_field restarts it): 0 u; 1 the linear extrapolation
      2u - u_prev; 2 the geometric one u (u / u_prev) where the voxel's value
      is positive and decaying (0 < u < u_prev), else u; 3 (default) for the
-     fields other than oxygen, per system, the better (smaller residual
-     ||b - A x0||) of the geometric guess and x0 = b1 u + b2 (u - u_prev) with
-     (b1, b2) minimising ||b - A x0|| for this solve's system, oxygen as 2.
-     The stopping rule, hence the solve's accuracy, is the same for all four;
-     the guess changes the iteration counts (3: about a third fewer drug
-     iterations than 2 on a 384^3 lattice after a bolus). */
+     fields other than oxygen, per system, the best (smallest residual
+     ||b - A x0|| for this solve's system) of the geometric guess and the
+     least-squares fits x0 = c1 u + c2 (u - u_prev) + c3 (u_prev - u_prev2)
+     (c3 = 0 too), u_prev2 the value at the solve before u_prev's; oxygen as
+     2.  The stopping rule, hence the solve's accuracy, is the same for all
+     four; the guess changes the iteration counts. */
   int32_t x0_extrapolate;
   /* storage precision of the solved fields (K, G1, G2, G3, V), their solver
      arrays and their guess history: 64 (default) FP64; 32 FP32, half the
@@ -311,7 +311,8 @@ hca_status hca_set_step(hca_ctx* c, int64_t step);
  * reproducibility the paper asks of its random numbers, here of the whole
  * state): the cell map, the vessel map, every solved field (K, G1, G2, and G3
  * / V with their options), P, V_c, phi, the solves' initial-guess history
- * (each field at its previous solve), the step index, the seed and the
+ * (each field at its previous solve, and with x0_extrapolate = 3 at the solve
+ * before that), the step index, the seed and the
  * cumulative event counts.  Layout: a 96-byte header (magic "HCASTATE",
  * version 1, option flags, nx, ny, nz, field count, step, seed, cumulative
  * counts), then the uint8 cell map padded to 8 bytes and FP64 arrays, all

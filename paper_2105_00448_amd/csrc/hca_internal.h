@@ -280,13 +280,13 @@ void launch_cg_update(hipStream_t s, const Work& w, double rtol, int maxit, cons
 template <typename T>
 void launch_cg_finish(hipStream_t s, const Work& w, T* x, const SolverBufsT<T>& sb);
 // The solves' initial guess (x0_extrapolate = 3) for the systems of the
-// fields in fmask: F <- the least-squares fit of b in span(A F, A (F - Fprev))
-// or the geometric extrapolation, whichever leaves the smaller residual, and
-// Fprev <- F.  q, sg: scratch of the fields' size; part: kGuessPartsPerTile
-// doubles per tile of w; alpha: 3 per system.
-constexpr int kGuessPartsPerTile = 8;
+// fields in fmask: F <- the best (smallest residual for this solve's system)
+// of the least-squares fits in span(A F, A (F - Fprev), A (Fprev - Fprev2))
+// and the geometric extrapolation; Fprev2 <- Fprev, Fprev <- F.  part:
+// kGuessPartsPerTile doubles per tile of w; alpha: 4 per system.
+constexpr int kGuessPartsPerTile = 12;
 template <typename T>
-void launch_guess_projection(hipStream_t s, const Work& w, const T* c, const T* b, T* F, T* Fprev, T* q, T* sg,
+void launch_guess_projection(hipStream_t s, const Work& w, const T* c, const T* b, T* F, T* Fprev, T* Fprev2,
                              double* part, double* alpha, unsigned fmask, int nrep);
 
 // ---- geometric multigrid (k_mg.hip) ---------------------------------------

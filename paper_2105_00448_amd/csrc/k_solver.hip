@@ -408,85 +408,236 @@ __global__ void __launch_bounds__(kBlock) k_cg_finish(Work w, T* __restrict__ x,
   }
 }
 
-// ---- the solves' initial guess from their two previous solutions -----------
+// ---- the solves' initial guess from their previous solutions ---------------
 //
-// x1 is the field's value (its last solve's solution), x2 the solution
-// before.  Two candidates: the least-squares fit x_f = b1 x1 + b2 (x1 - x2),
-// (b1, b2) minimising ||b - A x_f|| for this solve's system (the 2 x 2 normal
-// equations in u = A x1, w = A (x1 - x2)), and the geometric extrapolation
-// x_g (the per-voxel rule of k_extrapolate).  The one with the smaller
-// residual norm (from the same products: ||b||^2 - 2 b.y + y.y) is taken.  A
-// drug field's operator is the same from step to step and its solutions
-// follow a smooth course in time, so b lies close to the span of u and w;
-// once a field decays geometrically voxel by voxel, x_g does better.  The
-// difference x1 - x2 is formed per voxel before the operator is applied
-// (no cancellation between A x1 and A x2 when the two are close).
+// x1 is the field's value (its last solve's solution), x2 and x3 the two
+// solutions before.  Candidates: the least-squares fits
+//     x_f3 = c1 x1 + c2 (x1 - x2) + c3 (x2 - x3),   x_f2 = c1 x1 + c2 (x1 - x2),
+// the coefficients minimising ||b - A x|| for this solve's system (normal
+// equations in u = A x1, w1 = A (x1 - x2), w2 = A (x2 - x3)), and the
+// geometric extrapolation x_g (the per-voxel rule of k_extrapolate).  The
+// candidate with the smallest residual norm, ||b||^2 - 2 b.y + y.y from the
+// same products, is taken.  A drug field's operator is the same from step to
+// step and its solutions follow a smooth course in time, so b lies close to
+// the span of A x1 and the differences; once a field decays geometrically
+// voxel by voxel, x_g can do better.  The differences are formed per voxel
+// before the operator is applied, so nearly equal solutions do not cancel
+// in A x1 - A x2.
 __device__ inline double geo_guess(double u, double up) {
   return (up > 0.0 && u > 0.0 && u < up) ? u * (u / up) : u;
 }
 
-template <typename T>
-struct OpPair {   // operand f(x1, x2) per voxel: x1 - x2 (GEO false) or x_g
-  struct Raw {
-    double a, b;
+// plane_stencil for NC operands at once: f(i, Au) with Au[k] = (A v_k)_i,
+// v the operand values op.values(op.load(j), v) (rounded to T once, as in
+// plane_stencil); the same marching, frame and one-plane prefetch.
+template <int NC, typename T, typename OP, typename F>
+__device__ inline void plane_stencil_n(const TileCoord& tc, const T* __restrict__ c,
+                                       T (*lds)[NC][kPlaneMax], const OP& op, F f) {
+  using Raw = typename OP::Raw;
+  struct Slot {
+    Raw ri, rf;
+    double c;
   };
-  struct Ctr {};
-  const T* __restrict__ x1;
-  const T* __restrict__ x2;
-  bool geo;
-  __device__ inline Raw zero() const { return Raw{0.0, 0.0}; }
-  __device__ inline Raw load(long long j) const { return Raw{x1[j], x2[j]}; }
-  __device__ inline double value(const Raw& r) const { return geo ? geo_guess(r.a, r.b) : r.a - r.b; }
-  __device__ inline Ctr ctr_zero() const { return Ctr{}; }
-  __device__ inline Ctr load_ctr(long long) const { return Ctr{}; }
-  __device__ inline void at_center(long long, const Raw&, const Ctr&) const {}
+  const double a = tc.a;
+  const int W = tc.tx + 2;
+  const int o = (tc.ly + 1) * W + tc.lx + 1;
+  const int nframe = 2 * W + 2 * tc.ty;
+  const long long plane = (long long)tc.nx * tc.ny;
+  const int k = threadIdx.x;
+  const bool has_frame = k < nframe;
+  int hx = 0, hy = 0;
+  if (k < W) {
+    hx = k;
+  } else if (k < 2 * W) {
+    hx = k - W;
+    hy = tc.ty + 1;
+  } else if (k < 2 * W + tc.ty) {
+    hy = 1 + k - 2 * W;
+  } else {
+    hx = W - 1;
+    hy = 1 + k - 2 * W - tc.ty;
+  }
+  const int gx = tc.x0 + hx - 1, gy = tc.y0 + hy - 1;
+  const bool fin = has_frame && gx >= 0 && gx < tc.nx && gy >= 0 && gy < tc.ny;
+  const int fo = hy * W + hx;
+  const long long fidx = fin ? gx + (long long)tc.nx * gy : 0;
+  const long long iidx = tc.x + (long long)tc.nx * tc.y;
+  const int z0 = tc.z0, z1 = tc.z1;
+  auto load_slot = [&](Slot& sl, int zp) {
+    const long long pz = tc.off + plane * zp;
+    if (tc.valid) sl.ri = op.load(pz + iidx);
+    if (tc.valid && zp < z1) sl.c = c[pz + iidx];
+    if (fin) sl.rf = op.load(pz + fidx);
+  };
+  auto store_slot = [&](const Slot& sl, T (*buf)[kPlaneMax]) {
+    double v[NC], vf[NC];
+    op.values(sl.ri, v);
+    op.values(sl.rf, vf);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      buf[q][o] = tc.valid ? (T)v[q] : (T)0;
+      if (has_frame) buf[q][fo] = fin ? (T)vf[q] : (T)0;
+    }
+  };
+  const bool xl = tc.x > 0, xr = tc.x + 1 < tc.nx, yl = tc.y > 0, yr = tc.y + 1 < tc.ny;
+  const int deg_xy = (int)xl + (int)xr + (int)yl + (int)yr;
+  long long i = tc.off + iidx + plane * z0;
+  int cur = 0;
+  Slot ring{op.zero(), op.zero(), 0.0};
+  __syncthreads();   // the previous tile's readers are done with both buffers
+  double um[NC], uc[NC], cc;
+  {
+    Slot s0{op.zero(), op.zero(), 0.0};
+    load_slot(s0, z0);
+    double v[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) v[q] = 0.0;
+    if (tc.valid && z0 > 0) op.values(op.load(i - plane), v);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) um[q] = (double)(T)v[q];
+    if (z0 + 1 <= z1 && z0 + 1 < tc.nz) load_slot(ring, z0 + 1);
+    cc = s0.c;
+    store_slot(s0, lds[0]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NC; ++q) uc[q] = lds[0][q][o];
+  for (int z = z0; z < z1; ++z) {
+    const bool zl = z > 0, zr = z + 1 < tc.nz;
+    const int nx = cur ^ 1;
+    double cn = 0.0;
+    if (zr) {   // plane z+1 into LDS; the slot then takes plane z+2
+      store_slot(ring, lds[nx]);
+      cn = ring.c;
+      if (z + 2 <= z1 && z + 2 < tc.nz) load_slot(ring, z + 2);
+    }
+    double s[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+      s[q] = (((double)lds[cur][q][o - 1] + (double)lds[cur][q][o + 1]) + (double)lds[cur][q][o - W]) +
+             (double)lds[cur][q][o + W];
+    __syncthreads();
+    double up[NC], Au[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) up[q] = zr ? (double)lds[nx][q][o] : 0.0;
+    if (tc.valid) {
+      const int deg = deg_xy + (int)zl + (int)zr;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) Au[q] = (cc + a * deg) * uc[q] - a * ((s[q] + um[q]) + up[q]);
+      f(i, Au);
+    }
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      um[q] = uc[q];
+      uc[q] = up[q];
+    }
+    cc = cn;
+    cur = nx;
+    i += plane;
+  }
+}
+
+template <typename T>
+struct OpHist {   // x1, x1 - x2, x2 - x3, x_g per voxel
+  struct Raw {
+    double x1, x2, x3;
+  };
+  const T* __restrict__ p1;
+  const T* __restrict__ p2;
+  const T* __restrict__ p3;
+  __device__ inline Raw zero() const { return Raw{0.0, 0.0, 0.0}; }
+  __device__ inline Raw load(long long j) const { return Raw{p1[j], p2[j], p3[j]}; }
+  __device__ inline void values(const Raw& r, double (&v)[4]) const {
+    v[0] = r.x1;
+    v[1] = r.x1 - r.x2;
+    v[2] = r.x2 - r.x3;
+    v[3] = geo_guess(r.x1, r.x2);
+  }
 };
 
-// Per tile: w = A (x1 - x2) into q, g = A x_g into s (both free before the
-// solve), then u = A x1 and the products u.u, u.w, w.w, b.u, b.w, b.b, b.g,
-// g.g (w and g read back at the same voxel).
+// Products per tile, in the order of kGuessPartsPerTile: u.u, u.w1, u.w2,
+// w1.w1, w1.w2, w2.w2, b.u, b.w1, b.w2, b.b, b.g, g.g.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_guess_dots(Work w, const T* __restrict__ c, const T* __restrict__ b,
                                                        const T* __restrict__ x1, const T* __restrict__ x2,
-                                                       T* __restrict__ q, T* __restrict__ sg,
-                                                       double* __restrict__ part, unsigned fmask, int nrep) {
+                                                       const T* __restrict__ x3, double* __restrict__ part,
+                                                       unsigned fmask, int nrep) {
   __shared__ double lds4[4];
-  __shared__ T lds[2][kPlaneMax];
+  __shared__ T lds[2][4][kPlaneMax];
   int t0, t1;
   tile_range(w.ntiles, t0, t1);
   for (int ti = t0; ti < t1; ++ti) {
     const TileCoord tc = tile_coord(w, ti);
     if (!((fmask >> (tc.rep / nrep)) & 1u)) continue;
-    plane_stencil<kStencilPrefetch>(tc, c, lds, OpPair<T>{x1, x2, false},
-                                    [&](long long i, int, double, double Aw) { q[i] = (T)Aw; });
-    plane_stencil<kStencilPrefetch>(tc, c, lds, OpPair<T>{x1, x2, true},
-                                    [&](long long i, int, double, double Ag) { sg[i] = (T)Ag; });
     double d[kGuessPartsPerTile] = {};
-    plane_stencil<kStencilPrefetch>(tc, c, lds, OpX<T>{x1}, [&](long long i, int, double, double u) {
-      const double wv = q[i], g = sg[i], bi = b[i];
+    plane_stencil_n<4>(tc, c, lds, OpHist<T>{x1, x2, x3}, [&](long long i, const double (&A)[4]) {
+      const double u = A[0], w1 = A[1], w2 = A[2], g = A[3], bi = b[i];
       d[0] += u * u;
-      d[1] += u * wv;
-      d[2] += wv * wv;
-      d[3] += bi * u;
-      d[4] += bi * wv;
-      d[5] += bi * bi;
-      d[6] += bi * g;
-      d[7] += g * g;
+      d[1] += u * w1;
+      d[2] += u * w2;
+      d[3] += w1 * w1;
+      d[4] += w1 * w2;
+      d[5] += w2 * w2;
+      d[6] += bi * u;
+      d[7] += bi * w1;
+      d[8] += bi * w2;
+      d[9] += bi * bi;
+      d[10] += bi * g;
+      d[11] += g * g;
     });
 #pragma unroll
-    for (int k = 0; k < kGuessPartsPerTile; ++k) d[k] = block_sum(d[k], lds4);
+    for (int q = 0; q < kGuessPartsPerTile; ++q) d[q] = block_sum(d[q], lds4);
     if (threadIdx.x == 0) {
       double* o = part + (size_t)ti * kGuessPartsPerTile;
 #pragma unroll
-      for (int k = 0; k < kGuessPartsPerTile; ++k) o[k] = d[k];
+      for (int q = 0; q < kGuessPartsPerTile; ++q) o[q] = d[q];
     }
   }
 }
 
-// One workgroup per system: the tiles' products summed in a fixed order; the
-// fit's coefficients (u and w nearly parallel, as when x2 = x1 after the
-// first solve: x1 alone, scaled), and which candidate is taken:
-// alpha[3 s] = 1 for x_g, else 0; alpha[3 s + 1], alpha[3 s + 2] = (b1, b2).
+// Least squares in the first n of the basis images (n = 1, 2, 3): the normal
+// equations G c = r scaled to a unit diagonal and solved by Cholesky; false
+// if a pivot is not well above 0 (the vectors nearly dependent).
+__device__ inline bool ls_fit(const double (&G)[3][3], const double (&r)[3], int n, double (&cf)[3]) {
+  double D[3], S[3][3], y[3];
+  for (int p = 0; p < n; ++p) {
+    if (!(G[p][p] > 0.0)) return false;
+    D[p] = 1.0 / sqrt(G[p][p]);
+  }
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q) S[p][q] = G[p][q] * D[p] * D[q];
+  double Lm[3][3] = {};
+  for (int p = 0; p < n; ++p) {   // S = L L^T
+    double dd = S[p][p];
+    for (int k = 0; k < p; ++k) dd -= Lm[p][k] * Lm[p][k];
+    if (!(dd > 1e-12)) return false;
+    Lm[p][p] = sqrt(dd);
+    for (int q = p + 1; q < n; ++q) {
+      double v = S[q][p];
+      for (int k = 0; k < p; ++k) v -= Lm[q][k] * Lm[p][k];
+      Lm[q][p] = v / Lm[p][p];
+    }
+  }
+  for (int p = 0; p < n; ++p) {   // L y = D r
+    double v = r[p] * D[p];
+    for (int k = 0; k < p; ++k) v -= Lm[p][k] * y[k];
+    y[p] = v / Lm[p][p];
+  }
+  for (int p = n - 1; p >= 0; --p) {   // L^T z = y, c = D z
+    double v = y[p];
+    for (int k = p + 1; k < n; ++k) v -= Lm[k][p] * cf[k];
+    cf[p] = v / Lm[p][p];
+  }
+  for (int p = 0; p < n; ++p) cf[p] *= D[p];
+  for (int p = n; p < 3; ++p) cf[p] = 0.0;
+  for (int p = 0; p < n; ++p)
+    if (!isfinite(cf[p])) return false;
+  return true;
+}
+
+// One workgroup per system: the tiles' products summed in a fixed order, the
+// candidates' coefficients and residual norms, and the choice:
+// alpha[4 s] = 1 for x_g, else 0; alpha[4 s + 1 .. 3] = (c1, c2, c3).
 __global__ void __launch_bounds__(kBlock) k_guess_reduce(Work w, const double* __restrict__ part,
                                                          double* __restrict__ alpha, unsigned fmask,
                                                          int nrep) {
@@ -503,56 +654,67 @@ __global__ void __launch_bounds__(kBlock) k_guess_reduce(Work w, const double* _
     t[k] = block_sum(s, lds4);
   }
   if (threadIdx.x != 0) return;
-  const double uu = t[0], uw = t[1], ww = t[2], bu = t[3], bw = t[4], bb = t[5], bg = t[6], gg = t[7];
-  double b1 = 1.0, b2 = 0.0;
-  if (uu > 0.0) {
-    const double det = uu * ww - uw * uw;
-    if (ww > 0.0 && det > 1e-14 * uu * ww) {
-      b1 = (bu * ww - bw * uw) / det;
-      b2 = (bw * uu - bu * uw) / det;
-    } else {
-      b1 = bu / uu;
+  const double G[3][3] = {{t[0], t[1], t[2]}, {t[1], t[3], t[4]}, {t[2], t[4], t[5]}};
+  const double r[3] = {t[6], t[7], t[8]};
+  const double bb = t[9], bg = t[10], gg = t[11];
+  auto resid = [&](const double (&cf)[3]) {
+    double q = bb;
+    for (int p = 0; p < 3; ++p) {
+      q -= 2.0 * cf[p] * r[p];
+      for (int k = 0; k < 3; ++k) q += cf[p] * G[p][k] * cf[k];
+    }
+    return q;
+  };
+  double best[3] = {1.0, 0.0, 0.0};   // x1 alone (also when x1 = 0)
+  double rbest = resid(best);
+  for (int n = 1; n <= 3; ++n) {
+    double cf[3];
+    if (ls_fit(G, r, n, cf)) {
+      const double q = resid(cf);
+      if (isfinite(q) && q < rbest) {
+        rbest = q;
+        for (int p = 0; p < 3; ++p) best[p] = cf[p];
+      }
     }
   }
-  if (!isfinite(b1) || !isfinite(b2)) {
-    b1 = 1.0;
-    b2 = 0.0;
-  }
-  const double rf = bb - 2.0 * (b1 * bu + b2 * bw) + b1 * b1 * uu + 2.0 * b1 * b2 * uw + b2 * b2 * ww;
   const double rg = bb - 2.0 * bg + gg;
-  alpha[3 * rep] = (isfinite(rg) && rg < rf) ? 1.0 : 0.0;
-  alpha[3 * rep + 1] = b1;
-  alpha[3 * rep + 2] = b2;
+  alpha[4 * rep] = (isfinite(rg) && rg < rbest) ? 1.0 : 0.0;
+  alpha[4 * rep + 1] = best[0];
+  alpha[4 * rep + 2] = best[1];
+  alpha[4 * rep + 3] = best[2];
 }
 
-// F <- the chosen candidate, Fprev <- F (the systems of the fields in fmask).
+// F <- the chosen candidate, Fprev2 <- Fprev, Fprev <- F (the systems of the
+// fields in fmask).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_guess_apply(Work w, T* __restrict__ F, T* __restrict__ Fprev,
-                                                        const double* __restrict__ alpha, unsigned fmask,
-                                                        int nrep) {
+                                                        T* __restrict__ Fprev2, const double* __restrict__ alpha,
+                                                        unsigned fmask, int nrep) {
   int b0, b1;
   work_range(w.nflat, b0, b1);
   for (int it = b0; it < b1; ++it) {
     const FlatBlk fb = w.flat[it];
     if (!((fmask >> (fb.rep / nrep)) & 1u)) continue;
-    const bool geo = alpha[3 * fb.rep] != 0.0;
-    const double c1 = alpha[3 * fb.rep + 1], c2 = alpha[3 * fb.rep + 2];
+    const bool geo = alpha[4 * fb.rep] != 0.0;
+    const double c1 = alpha[4 * fb.rep + 1], c2 = alpha[4 * fb.rep + 2], c3 = alpha[4 * fb.rep + 3];
     const long long off = w.reps[fb.rep].off;
     for (long long i = off + fb.begin + threadIdx.x; i < off + fb.end; i += kBlock) {
-      const double u = F[i], up = Fprev[i];
-      F[i] = (T)(geo ? geo_guess(u, up) : c1 * u + c2 * (double)(T)(u - up));
-      Fprev[i] = (T)u;
+      const double u1 = F[i], u2 = Fprev[i], u3 = Fprev2[i];
+      F[i] = (T)(geo ? geo_guess(u1, u2)
+                     : c1 * u1 + c2 * (double)(T)(u1 - u2) + c3 * (double)(T)(u2 - u3));
+      Fprev2[i] = (T)u2;
+      Fprev[i] = (T)u1;
     }
   }
 }
 
 template <typename T>
-void launch_guess_projection(hipStream_t s, const Work& w, const T* c, const T* b, T* F, T* Fprev, T* q, T* sg,
+void launch_guess_projection(hipStream_t s, const Work& w, const T* c, const T* b, T* F, T* Fprev, T* Fprev2,
                              double* part, double* alpha, unsigned fmask, int nrep) {
   hca_launch(k_guess_dots<T>, dim3(grid_tiles(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c, b,
-             (const T*)F, (const T*)Fprev, q, sg, part, fmask, nrep);
+             (const T*)F, (const T*)Fprev, (const T*)Fprev2, part, fmask, nrep);
   hca_launch(k_guess_reduce, dim3(w.nreps), dim3(kBlock), 0, s, w, (const double*)part, alpha, fmask, nrep);
-  hca_launch(k_guess_apply<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, F, Fprev,
+  hca_launch(k_guess_apply<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, F, Fprev, Fprev2,
              (const double*)alpha, fmask, nrep);
 }
 
@@ -750,7 +912,7 @@ void launch_cg_finish(hipStream_t s, const Work& w, T* x, const SolverBufsT<T>& 
   template void launch_cg_update<T>(hipStream_t, const Work&, double, int, const SolverBufsT<T>&);  \
   template void launch_cg_finish<T>(hipStream_t, const Work&, T*, const SolverBufsT<T>&);        \
   template void launch_guess_projection<T>(hipStream_t, const Work&, const T*, const T*, T*, T*, T*, \
-                                           T*, double*, double*, unsigned, int);
+                                           double*, double*, unsigned, int);
 HCA_SOLVER_INST(double)
 HCA_SOLVER_INST(float)
 

@@ -108,8 +108,8 @@ const double kBytesPerVoxel[KC_COUNT] = {
     12.5,           // mg prefused L0: read r (4), dinv (4); write u3 (4), r1 (1/8 of 4)
     16.5 + kE,      // mg postfused L0: read u3 (4), e (1/8), r (4), dinv (4), r (stored); write z (4)
     3 * kE,         // cg_finish: read x, p; write x (once per solve)
-    17 * kE};       // guess fit, per voxel of one fitted field: read x1, x2, c; write A (x1 - x2);
-                    // the same for A x_g; read x1, c, b and the two; read x1, x2; write x0, x2
+    11 * kE};       // guess fit, per voxel of one fitted field: read x1, x2, x3, c, b (the products);
+                    // read x1, x2, x3; write x0, x1, x2 (the shifted history)
 constexpr double kBytesSetupVegf = 8.0 + 3 * kE;   // setup_step with vegf: + read V, Vc; write c, b
 constexpr double kBytesSetupDrug3 = 3 * kE;        // setup_step with drug3: + read G3; write c, b
 constexpr double kBytesStatsField = kE;            // stats: per extra field scanned (V, G3)
@@ -169,8 +169,9 @@ struct Ctx : ::hca_ctx {
   double *dose_t = nullptr, *dose_a = nullptr, *g0 = nullptr;
   Real* b_o2lin = nullptr;                       // o2_newton: the linearised O2 right-hand side
   Real* Fprev = nullptr;                         // x0_extrapolate: fields of the previous solve
+  Real* Fprev2 = nullptr;                        // x0_extrapolate = 3: and of the solve before
   double* d_gpart = nullptr;                     // x0_extrapolate = 3: products per solver tile
-  double* d_galpha = nullptr;                    // and the choice and fit coefficients per system
+  double* d_galpha = nullptr;                    // and the choice and fit coefficients per system (4)
   long long* d_step = nullptr;
   // replicate tables (state kernels)
   RepDev* d_reps = nullptr;
@@ -684,8 +685,8 @@ hca_status run_phases(Ctx* c, unsigned mask) {
     }
     if (fitmask) {   // priced per voxel of each fitted field (three launches)
       ProfScope ps(c, KC_GUESS, kTagState, false, (__builtin_popcount(fitmask) - 1) * kBytesPerVoxel[KC_GUESS]);
-      launch_guess_projection(s, c->sys_all, c->c, c->b, c->F, c->Fprev, c->sb.q, c->sb.p0, c->d_gpart,
-                              c->d_galpha, fitmask, c->nreps);
+      launch_guess_projection(s, c->sys_all, c->c, c->b, c->F, c->Fprev, c->Fprev2, c->d_gpart, c->d_galpha,
+                              fitmask, c->nreps);
     }
     const bool newton = c->prm.o2_newton > 0 && (fmask & 1u);
     if (newton)
@@ -1283,8 +1284,9 @@ hca_status alloc_all(Ctx* c) {
   if (c->prm.o2_newton > 0 && (st = big(&c->b_o2lin, (size_t)c->ntot)) != HCA_OK) return st;
   if (c->prm.x0_extrapolate && (st = big(&c->Fprev, n3)) != HCA_OK) return st;
   if (c->prm.x0_extrapolate == 3) {
+    if ((st = big(&c->Fprev2, n3)) != HCA_OK) return st;
     HIPCHK(c, dalloc(&c->d_gpart, (size_t)kGuessPartsPerTile * std::max(1, c->sys_all.ntiles)));
-    HIPCHK(c, dalloc(&c->d_galpha, 3 * (size_t)nsys));
+    HIPCHK(c, dalloc(&c->d_galpha, 4 * (size_t)nsys));
   }
   HIPCHK(c, dalloc(&c->d_step, 1));
   HIPCHK(c, dalloc(&c->d_cnt, c->nreps));
@@ -1568,7 +1570,7 @@ hca_status steady_oxygen(Ctx* c) {
 void free_all(Ctx* c) {
   void* bufs[] = {c->L, c->code, c->win, (void*)c->ca_list.cells, (void*)c->ca_list.item_n, c->w, c->P, c->Vc, c->phi, c->F, c->c, c->b,
                   c->sb.r, c->sb.z, (void*)c->sb.z32, (void*)c->sb.r32, c->sb.p0, c->sb.p1, c->sb.q, c->sb.dinv, c->sb.partial,
-                  c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->b_o2lin, c->Fprev, c->d_gpart, c->d_galpha, c->d_step,
+                  c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->b_o2lin, c->Fprev, c->Fprev2, c->d_gpart, c->d_galpha, c->d_step,
                   c->d_reps, c->d_flat, c->d_tiles, c->d_sys, c->d_sflat, c->d_stiles, c->d_ftiles, c->d_cnt, (void*)c->d_cpart,
                   c->d_bad, c->d_theta, (void*)c->d_pack, (void*)c->d_gelu, c->before,
                   c->item_cnt, c->item_off};
@@ -1669,11 +1671,13 @@ void* field_ptr(Ctx* c, hca_field f, size_t& elem) {
 //   cells FP64 P, Vc, phi, 3 x n
 //   Fprev FP64 each solved field at its previous solve (the initial-guess
 //         history), nf x n, present with flag bit 2
+//   Fprev2 FP64 each solved field at the solve before that, nf x n, present
+//         with flag bit 3
 // n = nx ny nz, arrays x-fastest as everywhere.
 
 constexpr uint64_t kStateMagic = 0x4554415453414348ull;   // "HCASTATE"
 constexpr uint32_t kStateVersion = 1;
-constexpr uint32_t kStateVegf = 1u, kStateDrug3 = 2u, kStatePrev = 4u;
+constexpr uint32_t kStateVegf = 1u, kStateDrug3 = 2u, kStatePrev = 4u, kStatePrev2 = 8u;
 
 struct StateHeader {
   uint64_t magic;
@@ -1688,7 +1692,7 @@ static_assert(sizeof(StateHeader) == 96, "state header layout");
 
 struct StateLayout {
   StateHeader hdr;
-  size_t n, off_L, off_w, off_F, off_cell, off_prev, bytes;
+  size_t n, off_L, off_w, off_F, off_cell, off_prev, off_prev2, bytes;
 };
 
 StateLayout state_layout(const StateHeader& h) {
@@ -1700,7 +1704,8 @@ StateLayout state_layout(const StateHeader& h) {
   l.off_F = l.off_w + 8 * l.n;
   l.off_cell = l.off_F + 8 * (size_t)h.nf * l.n;
   l.off_prev = l.off_cell + 24 * l.n;
-  l.bytes = l.off_prev + ((h.flags & kStatePrev) ? 8 * (size_t)h.nf * l.n : 0);
+  l.off_prev2 = l.off_prev + ((h.flags & kStatePrev) ? 8 * (size_t)h.nf * l.n : 0);
+  l.bytes = l.off_prev2 + ((h.flags & kStatePrev2) ? 8 * (size_t)h.nf * l.n : 0);
   return l;
 }
 
@@ -1710,7 +1715,7 @@ StateHeader context_header(const Ctx* c, int rep) {
   h.magic = kStateMagic;
   h.version = kStateVersion;
   h.flags = (c->dp.vegf ? kStateVegf : 0u) | (c->dp.drug3 ? kStateDrug3 : 0u) |
-            (c->Fprev ? kStatePrev : 0u);
+            (c->Fprev ? kStatePrev : 0u) | (c->Fprev2 ? kStatePrev2 : 0u);
   h.nx = R.nx;
   h.ny = R.ny;
   h.nz = R.nz;
@@ -1794,6 +1799,11 @@ hca_status export_state(Ctx* c, int rep, void* dst, size_t dst_bytes, int dst_is
       if ((st = field_out(c, c->Fprev + (size_t)f * c->ntot + R.off, n, d + lay.off_prev + 8 * n * f,
                           dst_is_device)) != HCA_OK)
         return st;
+  if (c->Fprev2)
+    for (int f = 0; f < c->dp.nf; ++f)
+      if ((st = field_out(c, c->Fprev2 + (size_t)f * c->ntot + R.off, n, d + lay.off_prev2 + 8 * n * f,
+                          dst_is_device)) != HCA_OK)
+        return st;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return HCA_OK;
 }
@@ -1858,6 +1868,16 @@ hca_status import_state(Ctx* c, int rep, const void* src, size_t src_bytes, int 
         if ((st = field_in(c, s + lay.off_prev + 8 * n * f, n, src_is_device, dstp)) != HCA_OK) return st;
       } else {   // no history saved: the extrapolation restarts from the state
         HIPCHK(c, hipMemcpyAsync(dstp, c->F + (size_t)f * c->ntot + R.off, sizeof(Real) * n,
+                                 hipMemcpyDeviceToDevice, c->stream));
+      }
+    }
+  if (c->Fprev2)   // after Fprev: without its own section the history restarts from Fprev
+    for (int f = 0; f < c->dp.nf; ++f) {
+      Real* dstp = c->Fprev2 + (size_t)f * c->ntot + R.off;
+      if (h.flags & kStatePrev2) {
+        if ((st = field_in(c, s + lay.off_prev2 + 8 * n * f, n, src_is_device, dstp)) != HCA_OK) return st;
+      } else {
+        HIPCHK(c, hipMemcpyAsync(dstp, c->Fprev + (size_t)f * c->ntot + R.off, sizeof(Real) * n,
                                  hipMemcpyDeviceToDevice, c->stream));
       }
     }
@@ -2145,6 +2165,9 @@ hca_status init_impl(::hca_ctx** out, const hca_params* p, const hca_replicate* 
   if (c->Fprev && hipMemcpyAsync(c->Fprev, c->F, (size_t)c->dp.nf * c->ntot * sizeof(Real), hipMemcpyDeviceToDevice,
                                  c->stream) != hipSuccess)
     return bail(HCA_E_DEVICE);
+  if (c->Fprev2 && hipMemcpyAsync(c->Fprev2, c->F, (size_t)c->dp.nf * c->ntot * sizeof(Real),
+                                  hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return bail(HCA_E_DEVICE);
   launch_zero_counters(c->stream, c->d_cnt, n_reps, 1);
   launch_zero_counters(c->stream, c->d_cnt, n_reps, 0);
   launch_stats(c->stream, c->work, c->L, c->w, c->F, c->dp.nf, c->ntot, c->P, c->Vc, c->phi,
@@ -2254,6 +2277,9 @@ hca_status api_set_field(::hca_ctx* c_, int rep, hca_field f, const void* src, s
       const size_t off = (size_t)(rf - c->F) + (size_t)R.off;
       HIPCHK(c, hipMemcpyAsync(c->Fprev + off, c->F + off, sizeof(Real) * (size_t)R.n,
                                hipMemcpyDeviceToDevice, c->stream));
+      if (c->Fprev2)
+        HIPCHK(c, hipMemcpyAsync(c->Fprev2 + off, c->F + off, sizeof(Real) * (size_t)R.n,
+                                 hipMemcpyDeviceToDevice, c->stream));
     }
   } else {
     HIPCHK(c, hipMemcpyAsync(dst + (size_t)R.off * elem, src, bytes, kind, c->stream));
