@@ -558,7 +558,7 @@ struct OpHist {   // x1, x1 - x2, x2 - x3, x_g per voxel
 // Products per tile, in the order of kGuessPartsPerTile: u.u, u.w1, u.w2,
 // w1.w1, w1.w2, w2.w2, b.u, b.w1, b.w2, b.b, b.g, g.g.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_guess_dots(Work w, const T* __restrict__ c, const T* __restrict__ b,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_guess_dots(Work w, const T* __restrict__ c, const T* __restrict__ b,
                                                        const T* __restrict__ x1, const T* __restrict__ x2,
                                                        const T* __restrict__ x3, double* __restrict__ part,
                                                        unsigned fmask, int nrep) {
