@@ -137,3 +137,27 @@ def test_bad_states_are_rejected_and_change_nothing():
     with pytest.raises(hca.HcaError) as e:
         hca.Simulation(resume, states=[b1[0], b2[1]])
     assert e.value.status == hca.E_INVALID
+
+
+def test_state_without_the_second_guess_level_restarts_it():
+    """A state exported with the geometric guess (x0_extrapolate = 2: one
+    history level) imports into a context with the fitted guess (two levels):
+    the missing level restarts from the first, and the run continues to the
+    same fields (solves to 1e-15: the guess changes iteration counts, not the
+    converged fields) and cell map."""
+    reps = cases(False)
+    tight = dict(cg_rtol=1e-15, init_rtol=1e-15, cg_maxit=20000, init_maxit=400)
+    with hca.Simulation(reps, hca.default_params(x0_extrapolate=2, **tight)) as src:
+        src.step(6)
+        blobs = [src.export_state(r) for r in range(len(reps))]
+    resume_reps = [(None, None, seed, sched) for (_, _, seed, sched) in reps]
+    with hca.Simulation(resume_reps, hca.default_params(x0_extrapolate=3, **tight), states=blobs) as fit, \
+            hca.Simulation(resume_reps, hca.default_params(x0_extrapolate=2, **tight), states=blobs) as geo:
+        fit.step(6)
+        geo.step(6)
+        for r in range(len(reps)):
+            assert np.array_equal(fit.field("L", r), geo.field("L", r)), r
+            for k in ("K", "G1", "G2"):
+                a, b = fit.field(k, r), geo.field(k, r)
+                scale = np.abs(b).max()
+                assert np.abs(a - b).max() <= 1e-10 * (scale if scale > 0 else 1.0), (r, k)
