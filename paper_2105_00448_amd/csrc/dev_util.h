@@ -94,6 +94,39 @@ __device__ inline void store_partials(double* slot, double a, double b, double c
   }
 }
 
+// A deferred solve end (CgFinish: x += alpha p of each field's last CG
+// iteration) on the voxels [off, off + len) of replicate rep, len at most
+// kFlatChunk.  Thread t takes the voxels t + k kBlock, every load issued
+// before the stores; the caller's next barrier publishes the values to the
+// rest of the workgroup.
+template <typename T>
+__device__ inline void cg_finish_run(const CgFinish<T>* __restrict__ finp, int rep, long long off, int len) {
+  if (!finp) return;
+  const CgFinish<T> fin = *finp;
+  constexpr int kPer = kFlatChunk / kBlock;
+  for (int f = 0; f < fin.nf; ++f) {
+    const SolveScal* ssr = fin.ss + f * fin.nrep + rep;
+    const int n = ssr->it;
+    if (n == 0) continue;
+    const long long base = (long long)f * fin.ntot + off;
+    const T* p = (((n - 1) & 1) ? fin.p0 : fin.p1) + base;   // the direction of iteration n - 1
+    T* x = fin.x + base;
+    const double alpha = ssr->alpha;
+    double xv[kPer], pv[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int li = (int)threadIdx.x + k * kBlock;
+      xv[k] = li < len ? (double)x[li] : 0.0;
+      pv[k] = li < len ? (double)p[li] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int li = (int)threadIdx.x + k * kBlock;
+      if (li < len) x[li] = (T)fma(alpha, pv[k], xv[k]);
+    }
+  }
+}
+
 // ---- Philox4x64-10 (Salmon et al., SC'11) ----------------------------------
 struct U64x4 {
   uint64_t v[4];

@@ -370,10 +370,27 @@ template <typename T>
 void launch_mg_vcycle(hipStream_t s, const Work& w, const MgBufs& mg, const SolverBufsT<T>& sb,
                       MgHook hook, void* hook_ctx);
 
-// ODE (k_ode.hip)
+// The last CG iteration's x += alpha p of a solve of every field (the systems
+// f * nrep + r of SolverBufsT, f < nf), left to the first kernel that reads
+// the fields after the solve: the ODE phase, which streams every voxel once
+// anyway and is bound by its arithmetic.  Kernels take it by a pointer to
+// device memory (null: nothing left to make), read per run of voxels, so its
+// fields hold no registers over the kernel.
+template <typename T>
+struct CgFinish {
+  T* x;                 // the field array: nf fields of ntot voxels
+  const T* p0;          // the double-buffered directions (same layout)
+  const T* p1;
+  const SolveScal* ss;  // per system: it (0: no iteration to finish), alpha
+  long long ntot;
+  int nf, nrep;
+};
+
+// ODE (k_ode.hip); fin (device memory, or null): a deferred solve end, made
+// for each run of voxels before the run's fields are read.
 template <typename T>
 void launch_ode(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L, const T* K,
-                double* P, double* Vc, double* phi);
+                double* P, double* Vc, double* phi, const CgFinish<T>* fin);
 
 // CA and stats (k_ca.hip)
 // The committed cancer cells (phi >= 1) of a step, listed by the propose

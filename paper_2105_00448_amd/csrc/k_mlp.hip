@@ -260,6 +260,8 @@ __device__ inline void forward32(const NET& net, const float (&x)[kMlpIn], int l
 // ---- surrogate in the coupled step ---------------------------------------------
 
 // Per flat work item, in runs of at most kFlatChunk voxels:
+//  0. a deferred solve end (fin) is made on the run's voxels (K, G1 and G2
+//     alias fin.x and are not restrict-qualified);
 //  1. the item's occupied voxels are listed in LDS, in voxel order;
 //  2. each wavefront evaluates the network on 32 listed voxels at a time
 //     (one 32-sample MFMA tile; every lane takes part in the GELUs); a voxel
@@ -276,14 +278,13 @@ __device__ inline void forward32(const NET& net, const float (&x)[kMlpIn], int l
 template <typename T>
 __global__ void __launch_bounds__(kBlock, 4) k_mlp_apply(Work w, MlpDev net,
                                                          const uint8_t* __restrict__ L,
-                                                         const T* __restrict__ K,
-                                                         const T* __restrict__ G1,
-                                                         const T* __restrict__ G2,
+                                                         const T* K, const T* G1, const T* G2,
                                                          double* __restrict__ P,
                                                          double* __restrict__ Vc,
                                                          double* __restrict__ phi,
                                                          unsigned long long* __restrict__ part,
-                                                         CaList fbl) {
+                                                         CaList fbl,
+                                                         const CgFinish<T>* __restrict__ fin) {
   __shared__ unsigned long long lds4[4];
   __shared__ int list[kFlatChunk];
   __shared__ int wcnt[4];
@@ -318,6 +319,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_mlp_apply(Work w, MlpDev net,
     for (long long c0 = fb.begin; c0 < fb.end; c0 += kFlatChunk) {
       const long long off = roff + c0;
       const int len = (int)min((long long)kFlatChunk, fb.end - c0);
+      cg_finish_run(fin, fb.rep, off, len);   // 0. published by the listing's barriers
       // 1. list the occupied voxels (index within the run), in order
       int n = 0;
       for (int base = 0; base < len; base += kBlock) {
@@ -847,9 +849,10 @@ void launch_mlp_pack(hipStream_t s, const float* theta, bf16x8* packed) {
 template <typename T>
 void launch_mlp_apply(hipStream_t s, const Work& w, const DevParams& p, const MlpDev& net,
                       const uint8_t* L, const T* K, const T* G1, const T* G2, double* P,
-                      double* Vc, double* phi, unsigned long long* part, Counters* cnt, CaList fb) {
+                      double* Vc, double* phi, unsigned long long* part, Counters* cnt, CaList fb,
+                      const CgFinish<T>* fin) {
   hca_launch(k_mlp_apply<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, net, L,
-             K, G1, G2, P, Vc, phi, part, fb);
+             K, G1, G2, P, Vc, phi, part, fb, fin);
   launch_ode_list(s, w, p, L, K, P, Vc, phi, fb);
   launch_counters_reduce(s, w, part, cnt, CNT_SUR);
 }
@@ -922,7 +925,8 @@ void launch_mlp_eval(hipStream_t s, const bf16x8* pk, const float* th, const flo
 #define HCA_MLP_INST(T)                                                                            \
   template void launch_mlp_apply<T>(hipStream_t, const Work&, const DevParams&, const MlpDev&,     \
                                     const uint8_t*, const T*, const T*, const T*, double*,         \
-                                    double*, double*, unsigned long long*, Counters*, CaList);     \
+                                    double*, double*, unsigned long long*, Counters*, CaList,      \
+                                    const CgFinish<T>*);                                           \
   template void launch_mlp_harvest<T>(hipStream_t, const Work&, const DevParams&, const uint8_t*,  \
                                       const T*, const T*, const T*, const double*, const double*,  \
                                       const double*, const long long*, float*, float*);

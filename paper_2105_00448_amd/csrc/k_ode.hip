@@ -9,12 +9,15 @@
 
 namespace hca {
 
+// fin: a deferred solve end, made per run before its listing (K aliases
+// fin.x, so K is not restrict-qualified).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_ode(Work w, DevParams p, const uint8_t* __restrict__ L,
-                                                const T* __restrict__ K,
+                                                const T* K,
                                                 double* __restrict__ P,
                                                 double* __restrict__ Vc,
-                                                double* __restrict__ phi) {
+                                                double* __restrict__ phi,
+                                                const CgFinish<T>* __restrict__ fin) {
   __shared__ int list[kFlatChunk];
   __shared__ int wcnt[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -25,6 +28,7 @@ __global__ void __launch_bounds__(kBlock) k_ode(Work w, DevParams p, const uint8
     for (long long c0 = fb.begin; c0 < fb.end; c0 += kFlatChunk) {
       const long long off = w.reps[fb.rep].off + c0;
       const int len = (int)min((long long)kFlatChunk, fb.end - c0);
+      cg_finish_run(fin, fb.rep, off, len);   // published by the listing's barriers
       int n = 0;
       for (int base = 0; base < len; base += kBlock) {
         const int li = base + (int)threadIdx.x;
@@ -55,8 +59,9 @@ __global__ void __launch_bounds__(kBlock) k_ode(Work w, DevParams p, const uint8
 
 template <typename T>
 void launch_ode(hipStream_t s, const Work& w, const DevParams& p, const uint8_t* L, const T* K,
-                double* P, double* Vc, double* phi) {
-  hca_launch(k_ode<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, K, P, Vc, phi);
+                double* P, double* Vc, double* phi, const CgFinish<T>* fin) {
+  hca_launch(k_ode<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, L, K, P, Vc, phi,
+             fin);
 }
 
 // The plain integrator on listed voxels only: flat work item it's voxels
@@ -99,8 +104,8 @@ template void launch_ode_list<double>(hipStream_t, const Work&, const DevParams&
 template void launch_ode_list<float>(hipStream_t, const Work&, const DevParams&, const uint8_t*,
                                      const float*, double*, double*, double*, CaList);
 template void launch_ode<double>(hipStream_t, const Work&, const DevParams&, const uint8_t*,
-                                 const double*, double*, double*, double*);
+                                 const double*, double*, double*, double*, const CgFinish<double>*);
 template void launch_ode<float>(hipStream_t, const Work&, const DevParams&, const uint8_t*,
-                                const float*, double*, double*, double*);
+                                const float*, double*, double*, double*, const CgFinish<float>*);
 
 }  // namespace hca

@@ -404,7 +404,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_finish(Work w, T* __restrict__ x,
     const double alpha = ssr->alpha;
     const long long off = w.reps[fb.rep].off;
     for (long long i = off + fb.begin + threadIdx.x; i < off + fb.end; i += kBlock)
-      x[i] = (T)((double)x[i] + alpha * (double)p[i]);
+      x[i] = (T)fma(alpha, (double)p[i], (double)x[i]);
   }
 }
 

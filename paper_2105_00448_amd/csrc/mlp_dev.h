@@ -72,11 +72,14 @@ void launch_mlp_pack(hipStream_t s, const float* theta, bf16x8* packed);
 void launch_mlp_gelu_table(hipStream_t s, float2* tab);
 // The network's update for every occupied voxel; the voxels that fall back
 // are listed in `fb` (per flat work item, as CaList lists cells) and then
-// advanced by the plain integrator (launch_ode_list).
+// advanced by the plain integrator (launch_ode_list).  fin (device memory, or
+// null): a deferred solve end, made per run of voxels before the run's fields
+// are read.
 template <typename T>
 void launch_mlp_apply(hipStream_t s, const Work& w, const DevParams& p, const MlpDev& net,
                       const uint8_t* L, const T* K, const T* G1, const T* G2, double* P,
-                      double* Vc, double* phi, unsigned long long* part, Counters* cnt, CaList fb);
+                      double* Vc, double* phi, unsigned long long* part, Counters* cnt, CaList fb,
+                      const CgFinish<T>* fin);
 // Training pairs of one coupled step: before the plain ODE phase,
 // save_state keeps (P, Vc, phi); after it, harvest writes one row per
 // occupied voxel, in voxel order, at row item_off[item] + rank in the item.

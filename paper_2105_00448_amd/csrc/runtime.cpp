@@ -172,6 +172,7 @@ struct Ctx : ::hca_ctx {
   Real* Fprev2 = nullptr;                        // x0_extrapolate = 3: and of the solve before
   double* d_gpart = nullptr;                     // x0_extrapolate = 3: products per solver tile
   double* d_galpha = nullptr;                    // and the choice and fit coefficients per system (4)
+  CgFinish<Real>* d_fin = nullptr;               // the solve end that the ODE phase can make
   long long* d_step = nullptr;
   // replicate tables (state kernels)
   RepDev* d_reps = nullptr;
@@ -204,6 +205,7 @@ struct Ctx : ::hca_ctx {
   Counters* h_cnt = nullptr;     // pinned
   long long step = 0;
   int last_it[2] = {0, 0};       // iterations of the last step solve / init solve
+  bool fin_pending = false;      // the last solve's x += alpha p left to the ODE phase
   std::vector<SolveScal> last_ss;
   int picard_iters = 0;
 
@@ -559,8 +561,11 @@ int g_solve_lead = 0;
 // system but the oxygen ones has converged (the drugs often need only a few
 // iterations), the remaining iterations run on the oxygen prefix's tables
 // (sys1, mg1: the same arrays, fewer workgroups) and its captured graph.
+// defer_finish (a solve of every field that the ODE phase follows): when every
+// system converged, the last iteration's x += alpha p is left to the ODE
+// kernel (c->fin_pending), which reads every voxel of the fields anyway.
 hca_status solve(Ctx* c, const Work& W_all, const MgBufs& mg_all, unsigned fmask, double rtol,
-                 int maxit, int kind) {
+                 int maxit, int kind, bool defer_finish = false) {
   const int nsys = W_all.nreps;
   const Work* Wp = &W_all;
   const MgBufs* mgp = &mg_all;
@@ -631,7 +636,11 @@ hca_status solve(Ctx* c, const Work& W_all, const MgBufs& mg_all, unsigned fmask
       }
     }
   }
-  {   // the last iteration's x += alpha p (systems that iterated)
+  bool allconv = true;
+  for (int s = 0; s < nsys; ++s) allconv = allconv && c->h_ss[s].conv;
+  if (defer_finish && allconv) {
+    c->fin_pending = true;
+  } else {   // the last iteration's x += alpha p (systems that iterated)
     ProfScope ps(c, KC_CG_FINISH, 0);
     launch_cg_finish(c->stream, W_all, c->F, c->sb);
   }
@@ -647,6 +656,19 @@ hca_status solve(Ctx* c, const Work& W_all, const MgBufs& mg_all, unsigned fmask
       return fail(c, HCA_E_NOCONV, buf);
     }
   return HCA_OK;
+}
+
+// The deferred solve end for the ODE phase (null: none) and its bytes per
+// voxel (x, p read and x written for each system that iterated).
+const CgFinish<Real>* take_finish(Ctx* c, double& bpv) {
+  bpv = 0.0;
+  if (!c->fin_pending) return nullptr;
+  c->fin_pending = false;
+  double vox = 0.0;
+  for (int s = 0; s < c->dp.nf * c->nreps; ++s)
+    if (c->h_ss[s].it > 0) vox += (double)c->sys_n[s];
+  bpv = kBytesPerVoxel[KC_CG_FINISH] * vox / (double)c->ntot;
+  return c->d_fin;
 }
 
 // The solves' stopping tolerance: cg_rtol, and no less than FP32 storage can
@@ -691,7 +713,9 @@ hca_status run_phases(Ctx* c, unsigned mask) {
     const bool newton = c->prm.o2_newton > 0 && (fmask & 1u);
     if (newton)
       HIPCHK(c, hipMemcpyAsync(c->b_o2lin, c->b, sizeof(Real) * (size_t)c->ntot, hipMemcpyDeviceToDevice, s));
-    hca_status st = solve(c, c->sys_all, c->mg_all, fmask, solve_rtol(c), c->prm.cg_maxit, 0);
+    // the last substep's solve ends in the ODE phase when one follows
+    const bool defer = (mask & HCA_PH_ODE) && j + 1 == c->dp.nsub_pde && !newton;
+    hca_status st = solve(c, c->sys_all, c->mg_all, fmask, solve_rtol(c), c->prm.cg_maxit, 0, defer);
     if (st != HCA_OK) return st;
     // Newton steps on the oxygen uptake at the new value, from the linearised solution
     for (int k = 0; newton && k < c->prm.o2_newton; ++k) {
@@ -704,13 +728,15 @@ hca_status run_phases(Ctx* c, unsigned mask) {
     }
   }
   if (mask & HCA_PH_ODE) {
+    double fin_bpv;
+    const CgFinish<Real>* fin = take_finish(c, fin_bpv);
     if (c->sur_on) {
-      ProfScope ps(c, KC_MLP_APPLY, kTagState);
+      ProfScope ps(c, KC_MLP_APPLY, kTagState, true, fin_bpv);
       launch_mlp_apply(s, wk, c->dp, c->net, c->L, c->K, c->G1, c->G2, c->P, c->Vc, c->phi,
-                       c->d_cpart, c->d_cnt, c->ca_list);
+                       c->d_cpart, c->d_cnt, c->ca_list, fin);
     } else {
-      ProfScope ps(c, KC_ODE, kTagState);
-      launch_ode(s, wk, c->dp, c->L, c->K, c->P, c->Vc, c->phi);
+      ProfScope ps(c, KC_ODE, kTagState, true, fin_bpv);
+      launch_ode(s, wk, c->dp, c->L, c->K, c->P, c->Vc, c->phi, fin);
     }
   }
   if (mask & HCA_PH_CA) {
@@ -1288,6 +1314,11 @@ hca_status alloc_all(Ctx* c) {
     HIPCHK(c, dalloc(&c->d_gpart, (size_t)kGuessPartsPerTile * std::max(1, c->sys_all.ntiles)));
     HIPCHK(c, dalloc(&c->d_galpha, 4 * (size_t)nsys));
   }
+  {
+    const CgFinish<Real> fin{c->F, c->sb.p0, c->sb.p1, c->sb.ss, c->ntot, c->dp.nf, c->nreps};
+    HIPCHK(c, dalloc(&c->d_fin, 1));
+    HIPCHK(c, hipMemcpy(c->d_fin, &fin, sizeof fin, hipMemcpyHostToDevice));
+  }
   HIPCHK(c, dalloc(&c->d_step, 1));
   HIPCHK(c, dalloc(&c->d_cnt, c->nreps));
   HIPCHK(c, dalloc(&c->d_cpart, (size_t)c->work.nflat * kCounterSlots));
@@ -1570,7 +1601,7 @@ hca_status steady_oxygen(Ctx* c) {
 void free_all(Ctx* c) {
   void* bufs[] = {c->L, c->code, c->win, (void*)c->ca_list.cells, (void*)c->ca_list.item_n, c->w, c->P, c->Vc, c->phi, c->F, c->c, c->b,
                   c->sb.r, c->sb.z, (void*)c->sb.z32, (void*)c->sb.r32, c->sb.p0, c->sb.p1, c->sb.q, c->sb.dinv, c->sb.partial,
-                  c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->b_o2lin, c->Fprev, c->Fprev2, c->d_gpart, c->d_galpha, c->d_step,
+                  c->sb.counter, c->sb.ss, c->sb.ndone, c->dose_t, c->dose_a, c->g0, c->b_o2lin, c->Fprev, c->Fprev2, c->d_gpart, c->d_galpha, (void*)c->d_fin, c->d_step,
                   c->d_reps, c->d_flat, c->d_tiles, c->d_sys, c->d_sflat, c->d_stiles, c->d_ftiles, c->d_cnt, (void*)c->d_cpart,
                   c->d_bad, c->d_theta, (void*)c->d_pack, (void*)c->d_gelu, c->before,
                   c->item_cnt, c->item_off};
@@ -2490,8 +2521,10 @@ hca_status api_harvest_step(::hca_ctx* c_, float* X, float* Y, int64_t cap_rows,
   if (st != HCA_OK) return st;
   launch_mlp_save_state(s, wk, c->P, c->Vc, c->phi, c->before);
   {
-    ProfScope ps(c, KC_ODE, kTagState);
-    launch_ode(s, wk, c->dp, c->L, c->K, c->P, c->Vc, c->phi);
+    double fin_bpv;   // none: the solves above ran without the ODE phase
+    const CgFinish<Real>* fin = take_finish(c, fin_bpv);
+    ProfScope ps(c, KC_ODE, kTagState, true, fin_bpv);
+    launch_ode(s, wk, c->dp, c->L, c->K, c->P, c->Vc, c->phi, fin);
   }
   launch_mlp_harvest(s, wk, c->dp, c->L, c->K, c->G1, c->G2, c->P, c->Vc, c->before, c->item_off,
                      X, Y);

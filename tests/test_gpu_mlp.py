@@ -686,3 +686,35 @@ def case_sur():
                  out_scale=np.array([3e-5, 4e-5, 2e-3], np.float32),
                  in_lo=raw.min(0).astype(np.float32), in_hi=raw.max(0).astype(np.float32))
     return tis, sched, s, theta, stats
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_surrogate_solve_end_in_the_ode_phase_is_the_separate_one(trained, precision):
+    """In a full step the surrogate's kernel makes the solves' last
+    x += alpha p on each run of voxels before it reads them (the plain
+    kernel's case is in test_gpu_solve_end.py); run as separate phases, the
+    solve makes it.  Two uneven replicates, three steps, a wide fallback
+    margin (the fallback integrator reads the finished fields too): the
+    same state and counts bit for bit."""
+    tr, _ = trained
+    net = tr.export()
+    reps = []
+    for shape, seed in (((12, 14, 10), 51), ((1, 20, 18), 52)):
+        t = synth.make_tissue(shape, 4, seed=seed)
+        sched = synth.bolus_schedule([0])
+        reps.append((t.cell, t.w, t.seed, (sched.times, sched.amts)))
+    params = hca.default_params(precision=precision)
+    print(f"\n[surrogate solve end] precision {precision}", flush=True)
+    with hca.Simulation(reps, params) as a, hca.Simulation(reps, params) as b:
+        for sim in (a, b):
+            sim.set_surrogate(net, 0.02)
+        for n in range(3):
+            a.step()
+            b.run_phases(hca.PH_O2 | hca.PH_DRUGS)
+            b.run_phases(hca.PH_ODE | hca.PH_CA | hca.PH_STATS | hca.PH_ADVANCE)
+            for r in range(len(reps)):
+                for k in ("L", "K", "G1", "G2", "P", "Vc", "phi"):
+                    np.testing.assert_array_equal(a.field(k, r), b.field(k, r),
+                                                  err_msg=f"step {n} replicate {r} {k}")
+                np.testing.assert_equal(a.stats(r), b.stats(r), err_msg=f"step {n} replicate {r}")
+        assert a.stats(0)["sur_voxels"] > 0
