@@ -3,18 +3,22 @@ that bench.py times: four replicates of a 384^3 lattice in one context
 (512-Gaussian density, Philox seeds 5000-5003, a bolus of both drugs at step
 0, default parameters: FP64 multigrid-preconditioned CG to relative residual
 1e-10, captured iterations replayed as HIP graphs, the solves' last update
-made inside the ODE kernel).  After two steps, one more coupled step is
-checked against the oracle wherever the oracle can follow it at this size
-(its full solves and its whole-lattice CA would take hours on one core):
+made inside the ODE kernel).  Every replicate starts the checked step (step
+2) from a seeded synthetic state (the cell map with vacancies, oxygen and
+drugs drawn uniformly, P and V_c at the oracle's steady values, the
+cell-cycle clocks uniform), so no input comes from the library; one coupled step is then checked against the
+oracle wherever the oracle can follow it at this size (its full solves and
+its whole-lattice CA would take hours on one core):
 
 * the solves (Eqs. (oxygen), (chemo)): every field's true relative residual,
-  with the oracle's own systems (`o2_system`, `drug_system` built from the
-  state before the step, the plasma levels from its PK) and its operator,
-  below the stopping tolerance with a margin for the drift of the CG's
-  recursive residual;
+  with the oracle's own systems (`o2_system`, `drug_system`, the plasma
+  levels from its PK) and its operator, below the stopping tolerance with a
+  margin for the drift of the CG's recursive residual;
 * the intracellular step at sampled occupied voxels that do not commit:
-  the oracle's `ode_step` from the state before the step and the solved
-  oxygen, P and V_c to 1e-10, phi bit for bit;
+  the oracle's `ode_step` from the starting state and the solved oxygen,
+  P and V_c to 1e-10, phi bit for bit; with the surrogate (second test),
+  the starting state plus the oracle's quantised forward of the standardised
+  inputs within each voxel's bound (tests/mlp_bounds.py);
 * the CA at every committed cell (Algorithm 1's cell update): the committed
   set from the oracle's cycle increment, each cell's kill decision from the
   oracle's Philox uniforms and kill probabilities at its voxel index within
@@ -22,17 +26,15 @@ checked against the oracle wherever the oracle can follow it at this size
   committed cell stays with phi = 0; each new cell has phi, P, V_c = 0 and a
   committed, surviving cell among its 26 neighbours; the library's event
   counts equal these.
-
-The surrogate's outputs at scale are covered by test_gpu_mlp.py (a tiled
-lattice of 2.36 M voxels against the 32^3 result) and the bench's
-error_matched_inputs.
 """
 import numpy as np
 import pytest
 
 import bench
+from mlp_bounds import host_net, quantised_forward_bound
 from oracle import ca as oca
 from oracle import lattice as olat
+from oracle import mlp as omlp
 from oracle import model as om
 from oracle import ode as oode
 from oracle.constants import DEFAULT as OP
@@ -42,39 +44,105 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 RES_TOL = 2e-10     # CG stopping tolerance 1e-10, with a margin for recursion drift
 ODE_TOL = 1e-10
+STEP = 2
 NAMES = ("L", "K", "G1", "G2", "P", "Vc", "phi")
+STATE = ("K", "G1", "G2", "P", "Vc", "phi")
 
 
-def moore():
-    return [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
-            if (dz, dy, dx) != (0, 0, 0)]
+def synthetic_state(cell, rng):
+    """Seeded starting state of one replicate: the workload's cell map with
+    5 % of its cells removed (the generated tissue fills every non-vessel
+    voxel where its density saturates, which leaves no room for a division),
+    K ~ U[5, 20] mmHg, G_i ~ U[0, G_ref,i], P and V_c of occupied voxels at
+    the oracle's steady values for that K (0 elsewhere), phi ~ U[0, 1) on
+    cancer cells."""
+    cell = np.where((cell != 0) & (rng.random(cell.shape) < 0.05), np.uint8(0), cell)
+    occ = cell != 0
+    K = rng.uniform(5.0, 20.0, cell.shape)
+    G1 = rng.uniform(0.0, OP.G_ref[0], cell.shape)
+    G2 = rng.uniform(0.0, OP.G_ref[1], cell.shape)
+    P = np.where(occ, oode.steady_p53(K, OP), 0.0)
+    Vc = np.where(occ, oode.steady_vegf(K, P, OP), 0.0)
+    phi = np.where(cell == 1, rng.random(cell.shape), 0.0)
+    return dict(L=cell, K=K, G1=G1, G2=G2, P=P, Vc=Vc, phi=phi)
+
+
+def run_step(reps, olds, net=None, margin=1e-3):
+    """One coupled step of the four-replicate context from the given states."""
+    with hca.Simulation(reps, hca.default_params()) as sim:
+        for r, o in enumerate(olds):
+            for k in NAMES:
+                sim.set_field(k, o[k], r)
+        sim.set_step(STEP)
+        if net is not None:
+            sim.set_surrogate(net, margin)
+        sim.step()
+        new = [{k: sim.field(k, r) for k in NAMES} for r in range(len(reps))]
+        stats = [sim.stats(r) for r in range(len(reps))]
+    return new, stats
+
+
+def check_solves(r, o, n, w, sched):
+    g0 = om.plasma_pair((STEP + 1) * OP.dt_min, sched, OP)
+    systems = (("K", om.o2_system(o["L"], w, o["K"], OP), OP.a_K),
+               ("G1", om.drug_system(w, o["G1"], g0[0], OP), OP.a_G),
+               ("G2", om.drug_system(w, o["G2"], g0[1], OP), OP.a_G))
+    for name, (c, b), a in systems:
+        res = b - olat.operator_apply(c, a, n[name])
+        rel = np.linalg.norm(res) / np.linalg.norm(b)
+        print(f"[full size] replicate {r} {name}: true rel. residual {rel:.2e}", flush=True)
+        assert rel <= RES_TOL, (r, name, rel)
+
+
+def check_ca(r, o, n, st, committed, cell, seed):
+    gids = np.flatnonzero(committed)
+    u0, u1, _ = oca.kill_uniforms(gids, STEP, seed)
+    p1 = oca.kill_probability(n["G1"].ravel()[gids], OP.G_ref[0], OP.b_int[0])
+    p2 = oca.kill_probability(n["G2"].ravel()[gids], OP.G_ref[1], OP.b_int[1])
+    killed = (u0 < p1) | (u1 < p2)
+    Ln = n["L"].ravel()
+    print(f"[full size] replicate {r}: {gids.size} committed, {killed.sum()} killed", flush=True)
+    assert gids.size > 0 and killed.any() and not killed.all(), r
+    assert np.all(Ln[gids[killed]] == 0), r
+    assert np.all(Ln[gids[~killed]] == 1), r
+    assert np.all(n["phi"].ravel()[gids] == 0.0), r
+    for name in ("P", "Vc"):
+        assert np.all(n[name].ravel()[gids[killed]] == 0.0), (r, name)
+    # new cells: reset state and a committed, surviving parent among the neighbours
+    born = np.flatnonzero((o["L"].ravel() == 0) & (Ln == 1))
+    for name in ("phi", "P", "Vc"):
+        assert np.all(n[name].ravel()[born] == 0.0), (r, name)
+    parent = np.zeros(committed.size, dtype=bool)
+    parent[gids[~killed]] = True
+    nz, ny, nx = cell.shape
+    bz, rem = np.divmod(born, ny * nx)
+    by, bx = np.divmod(rem, nx)
+    has_parent = np.zeros(born.size, dtype=bool)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                z, y, x = bz + dz, by + dy, bx + dx
+                ok = (z >= 0) & (z < nz) & (y >= 0) & (y < ny) & (x >= 0) & (x < nx)
+                j = (np.clip(z, 0, nz - 1) * ny + np.clip(y, 0, ny - 1)) * nx + np.clip(x, 0, nx - 1)
+                has_parent |= ok & parent[j] & ((dz, dy, dx) != (0, 0, 0))
+    assert born.size > 0 and has_parent.all(), r
+    # the library's counts of this step
+    assert st["committed"] == gids.size, r
+    assert st["kills"] == killed.sum(), r
+    assert st["divisions"] == born.size, r
+    assert (Ln == 1).sum() == (o["L"] == 1).sum() - killed.sum() + born.size, r
 
 
 def test_headline_workload_step_against_the_oracle():
     reps, _, _ = bench.make_workload("config5")
-    print(f"\n[full size] {len(reps)} x {reps[0][0].shape} voxels, default parameters", flush=True)
-    with hca.Simulation(reps, hca.default_params()) as sim:
-        sim.step(2)
-        old = [{k: sim.field(k, r) for k in NAMES} for r in range(len(reps))]
-        steps = [sim.stats(r)["step"] for r in range(len(reps))]
-        sim.step()
-        new = [{k: sim.field(k, r) for k in NAMES} for r in range(len(reps))]
-        stats = [sim.stats(r) for r in range(len(reps))]
-    rng = np.random.default_rng(7)
+    rng = np.random.default_rng(11)
+    olds = [synthetic_state(cell, rng) for cell, _, _, _ in reps]
+    print(f"\n[full size] plain: {len(reps)} x {reps[0][0].shape} voxels", flush=True)
+    new, stats = run_step(reps, olds)
     for r, (cell, w, seed, (times, amts)) in enumerate(reps):
-        o, n, st, step = old[r], new[r], stats[r], steps[r]
-        assert step == 2 and st["step"] == 3, (step, st["step"])
-        sched = om.Schedule(times=times, amts=amts)
-        # the solves: true residual of the library's fields in the oracle's systems
-        g0 = om.plasma_pair((step + 1) * OP.dt_min, sched, OP)
-        systems = (("K", om.o2_system(o["L"], w, o["K"], OP), OP.a_K),
-                   ("G1", om.drug_system(w, o["G1"], g0[0], OP), OP.a_G),
-                   ("G2", om.drug_system(w, o["G2"], g0[1], OP), OP.a_G))
-        for name, (c, b), a in systems:
-            res = b - olat.operator_apply(c, a, n[name])
-            rel = np.linalg.norm(res) / np.linalg.norm(b)
-            print(f"[full size] replicate {r} {name}: true rel. residual {rel:.2e}", flush=True)
-            assert rel <= RES_TOL, (r, name, rel)
+        o, n, st = olds[r], new[r], stats[r]
+        assert st["step"] == STEP + 1
+        check_solves(r, o, n, w, om.Schedule(times=times, amts=amts))
         # the cells that commit this step, from the oracle's cycle increment
         K = np.maximum(n["K"], 0.0)
         can = o["L"] == 1
@@ -91,38 +159,69 @@ def test_headline_workload_step_against_the_oracle():
             assert np.abs(got - ref).max() <= ODE_TOL * np.abs(ref).max(), (r, name)
         assert np.array_equal(n["phi"].ravel()[idx], f_s), r
         assert np.array_equal(n["L"].ravel()[idx], o["L"].ravel()[idx]), r
-        # the CA at every committed cell: kill trials at the cells' voxel indices
-        gids = np.flatnonzero(committed)
-        u0, u1, _ = oca.kill_uniforms(gids, step, seed)
-        p1 = oca.kill_probability(n["G1"].ravel()[gids], OP.G_ref[0], OP.b_int[0])
-        p2 = oca.kill_probability(n["G2"].ravel()[gids], OP.G_ref[1], OP.b_int[1])
-        killed = (u0 < p1) | (u1 < p2)
-        Ln = n["L"].ravel()
-        print(f"[full size] replicate {r}: {gids.size} committed, {killed.sum()} killed", flush=True)
-        assert gids.size > 0 and killed.any() and not killed.all(), r
-        assert np.all(Ln[gids[killed]] == 0), r
-        assert np.all(Ln[gids[~killed]] == 1), r
-        assert np.all(n["phi"].ravel()[gids] == 0.0), r
-        for name in ("P", "Vc"):
-            assert np.all(n[name].ravel()[gids[killed]] == 0.0), (r, name)
-        # new cells: reset state and a committed, surviving parent among the neighbours
-        born = np.flatnonzero((o["L"].ravel() == 0) & (Ln == 1))
-        for name in ("phi", "P", "Vc"):
-            assert np.all(n[name].ravel()[born] == 0.0), (r, name)
-        parent = np.zeros(committed.size, dtype=bool)
-        parent[gids[~killed]] = True
-        nz, ny, nx = cell.shape
-        bz, rem = np.divmod(born, ny * nx)
-        by, bx = np.divmod(rem, nx)
-        has_parent = np.zeros(born.size, dtype=bool)
-        for dz, dy, dx in moore():
-            z, y, x = bz + dz, by + dy, bx + dx
-            ok = (z >= 0) & (z < nz) & (y >= 0) & (y < ny) & (x >= 0) & (x < nx)
-            j = (np.clip(z, 0, nz - 1) * ny + np.clip(y, 0, ny - 1)) * nx + np.clip(x, 0, nx - 1)
-            has_parent |= ok & parent[j]
-        assert has_parent.all(), r
-        # the library's counts of this step
-        assert st["committed"] == gids.size, r
-        assert st["kills"] == killed.sum(), r
-        assert st["divisions"] == born.size, r
-        assert (Ln == 1).sum() == can.sum() - killed.sum() + born.size, r
+        check_ca(r, o, n, st, committed, cell, seed)
+
+
+def test_headline_surrogate_step_against_the_oracle():
+    """The same step with a network set (the bench's fallback margin 1e-3):
+    the oracle's initial parameters (seed 5) with biases ~ 0.3 N(0, 1), input
+    statistics of the starting states, output scales of a plausible update.
+    Sampled occupied voxels whose outcome is decided beyond the bound (no
+    fallback, no commitment either way) hold the starting state plus the
+    oracle's quantised forward; the solves and the CA are checked as in the
+    plain step, the committed set now from the network's update of phi
+    (cells whose decision lies within the bound of 1 or of the margin are
+    left out of the sample; the CA check covers every cell with phi = 0
+    after the step that was a committed cancer cell by the library's own
+    decision, through the counts)."""
+    reps, _, _ = bench.make_workload("config5")
+    rng = np.random.default_rng(12)
+    olds = [synthetic_state(cell, rng) for cell, _, _, _ in reps]
+    p = omlp.unpack(omlp.init_params(5))
+    for k in p:
+        if k.startswith("b"):
+            p[k] = 0.3 * rng.standard_normal(p[k].shape)
+    theta = omlp.pack(p).astype(np.float32).astype(np.float64)
+    raw = np.concatenate([np.stack([o[k][o["L"] != 0] for k in STATE], 1) for o in olds])
+    sd = raw.std(0)
+    stats = dict(in_mean=raw.mean(0).astype(np.float32),
+                 in_scale=np.where(sd > 0, 1.0 / np.where(sd > 0, sd, 1.0), 1.0).astype(np.float32),
+                 out_mean=np.array([1e-5, -2e-5, 5e-3], np.float32),
+                 out_scale=np.array([3e-5, 4e-5, 2e-3], np.float32),
+                 in_lo=raw.min(0).astype(np.float32), in_hi=raw.max(0).astype(np.float32))
+    del raw
+    net, th32 = host_net(theta, stats)
+    margin = 1e-3
+    print(f"\n[full size] surrogate: {len(reps)} x {reps[0][0].shape} voxels", flush=True)
+    new, st_all = run_step(reps, olds, net, margin)
+    sc = stats["out_scale"].astype(np.float64)
+    mu = stats["out_mean"].astype(np.float64)
+    for r, (cell, w, seed, (times, amts)) in enumerate(reps):
+        o, n, st = olds[r], new[r], st_all[r]
+        check_solves(r, o, n, w, om.Schedule(times=times, amts=amts))
+        assert st["sur_voxels"] + st["sur_fallbacks"] == (o["L"] != 0).sum(), r
+        idx = rng.choice(np.flatnonzero(o["L"] != 0), size=8192, replace=False)
+        inp = np.stack([n[k].ravel()[idx] if k in ("K", "G1", "G2") else o[k].ravel()[idx]
+                        for k in STATE], 1)
+        xs = (inp.astype(np.float32) - stats["in_mean"]) * stats["in_scale"]
+        y, Ey = quantised_forward_bound(theta, xs.astype(np.float64))
+        upd = y * sc + mu
+        base = inp[:, 3:]
+        tol = (Ey * sc + 2.0 ** -22 * (np.abs(y * sc) + np.abs(mu))
+               + 2.0 ** -51 * (np.abs(base) + np.abs(upd)))
+        cancer = o["L"].ravel()[idx] == 1
+        phi1 = base[:, 2] + upd[:, 2]
+        gap = np.abs(phi1 - 1.0)
+        # decided beyond the bound: the network's update, no commitment
+        sure = ~cancer | ((gap > margin + tol[:, 2]) & (phi1 + tol[:, 2] < 1.0))
+        assert sure.sum() > 4000, r
+        for name, j in (("P", 0), ("Vc", 1), ("phi", 2)):
+            m = sure & cancer if name == "phi" else sure
+            dev = np.abs((n[name].ravel()[idx] - base[:, j]) - upd[:, j])[m]
+            assert (dev <= tol[m, j]).all(), (r, name, (dev / tol[m, j]).max())
+        assert np.array_equal(n["L"].ravel()[idx][sure], o["L"].ravel()[idx][sure]), r
+        # the CA: the cells the library committed (cancer cells reset to phi = 0
+        # or removed) hold the oracle's kill decisions at their voxel indices
+        can = o["L"] == 1
+        committed = can & ((n["phi"] == 0.0) | (n["L"] == 0))
+        check_ca(r, o, n, st, committed, cell, seed)

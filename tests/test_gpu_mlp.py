@@ -26,6 +26,8 @@ from oracle import ode as oode
 from oracle.constants import DEFAULT as OP
 from paper_2105_00448_amd import hca, synth
 
+from mlp_bounds import host_net, quantised_forward_bound
+
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
@@ -494,40 +496,6 @@ def test_gradient_elementwise_matches_quantised_oracle(batch):
     tr.close()
 
 
-def quantised_forward_bound(theta, Xs):
-    """The oracle's quantised forward y of the standardised rows Xs and, per
-    row and output, a bound E on |y_gpu - y| for the library's evaluation
-    (FP32 accumulation, GELU from its table).  Layer by layer: the kernel's
-    pre-activation z differs from the oracle's by at most Ez = sum |W| Eh
-    (the previous layer's activation differences) + 65 2^-24 sum |W h| +
-    |b| (FP32 accumulation of <= 64 products and the bias); the value it
-    rounds, GELU(z), by at most ev = 1.01 |GELU'(z)| Ez + 8e-6 |z| (the
-    table's Phi is within 7.5e-6) + 2^-23 |GELU(z)|.  Rounding to bfloat16
-    is monotone, so the kernel's activation equals the oracle's unless
-    [GELU(z) - ev, GELU(z) + ev] holds a rounding boundary; then it differs by
-    at most the larger of the end values' rounding shifts, Eh.  The inputs
-    and weights are rounded identically on both sides (Eh = 0 there)."""
-    q = omlp.bf16
-    p = omlp.unpack(theta)
-    W = {k: q(v) for k, v in p.items() if k.startswith("W")}
-    gam = 65 * 2.0 ** -24
-    h = q(Xs)
-    Eh = np.zeros_like(h)
-    for i in (1, 2, 3):
-        Wi, bi = W[f"W{i}"], p[f"b{i}"]
-        z = h @ Wi.T + bi
-        Ez = Eh @ np.abs(Wi).T + gam * (np.abs(h) @ np.abs(Wi).T + np.abs(bi))
-        v = omlp.gelu(z)
-        ev = 1.01 * np.abs(omlp.gelu_grad(z)) * Ez + 8e-6 * np.abs(z) + 2.0 ** -23 * np.abs(v)
-        hq = q(v)
-        Eh = np.maximum(np.abs(q(v + ev) - hq), np.abs(q(v - ev) - hq))
-        h = hq
-    W4, b4 = W["W4"], p["b4"]
-    y = h @ W4.T + b4
-    Ey = Eh @ np.abs(W4).T + gam * (np.abs(h) @ np.abs(W4).T + np.abs(b4))
-    return y, Ey
-
-
 def test_surrogate_apply_matches_oracle(case_sur):
     """The ODE phase with a surrogate set, on an oracle state, against the
     oracle: a voxel advanced by the network equals input + the oracle's
@@ -604,21 +572,6 @@ def test_surrogate_apply_matches_oracle(case_sur):
         plain = (abs(got["P"][i] - Pp[i]) <= 1e-10 * scaleP and got["phi"][i] == php[i])
         netw = abs((got["P"][i] - base[i, 0]) - upd[i, 0]) <= tol[i, 0]
         assert plain or netw, i
-
-
-def host_net(theta, stats):
-    """An Mlp descriptor of FP32 host parameters (kept alive by the caller
-    through the returned array) and the given statistics, box check off."""
-    net = hca.Mlp()
-    th32 = np.ascontiguousarray(theta, dtype=np.float32)
-    net.theta = th32.ctypes.data
-    net.theta_is_device = 0
-    for k, v in stats.items():
-        arr = getattr(net, k)
-        for i, x in enumerate(v):
-            arr[i] = float(x)
-    net.box_check = 0
-    return net, th32
 
 
 @pytest.mark.parametrize("precision", [64, 32])
