@@ -211,11 +211,13 @@ void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uin
 // G3 (drug3) and V (vegf, its source from Vc); c and b of the same layout.
 // With Fprev, the same pass also forms the solves' initial guess of the
 // fields in xmask as launch_extrapolate does (mode xmode; theta = 1 only:
-// a theta < 1 right-hand side still reads F afterwards).
+// a theta < 1 right-hand side still reads F afterwards).  keep_c: the c of
+// the fields but oxygen (a function of the vessel map and the constants) is
+// already stored and is not written again.
 template <typename T>
 void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
                        const uint8_t* L, const double* vw, T* F, const double* Vc,
-                       const double* g0, T* c, T* b, T* Fprev, unsigned xmask, int xmode);
+                       const double* g0, T* c, T* b, T* Fprev, unsigned xmask, int xmode, int keep_c);
 // Newton step on the oxygen uptake at the new value: c, b of the oxygen
 // systems (the first ntot entries) from the iterate K and the linearised
 // substep's right-hand side b_lin.

@@ -167,7 +167,9 @@ __global__ void __launch_bounds__(kBlock) k_setup_o2(Work w, DevParams p, const 
 //   VEGF (vegf): R = psi_V, S = sec_V V_c chi, Eq. (vac_v) with no Avastin,
 //           V_c of the coupled step's start at both ends of every substep.
 // With one backward-Euler substep these are the coupled step's systems
-// c = 1/dt + R, b = u/dt + S.
+// c = 1/dt + R, b = u/dt + S.  The fields but oxygen have a c that depends on
+// the vessel map and the constants only: keep_c leaves the c already stored
+// for them.
 template <bool X, typename T>
 __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long long ntot,
                                                        const uint8_t* __restrict__ L,
@@ -176,7 +178,8 @@ __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long
                                                        const double* __restrict__ Vc,
                                                        const double* __restrict__ g0,
                                                        T* __restrict__ c, T* __restrict__ b,
-                                                       T* __restrict__ Fprev, unsigned xmask, int xmode) {
+                                                       T* __restrict__ Fprev, unsigned xmask, int xmode,
+                                                       int keep_c) {
   const double th = p.theta, th1 = 1.0 - p.theta;
   // X: the solves' initial guess as k_extrapolate forms it, from the value u
   // just read for b (fields of xmask)
@@ -206,7 +209,7 @@ __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long
     for (int i = 0; i < 2 + p.drug3; ++i) {   // drug i in field i + 1
       const long long j = g + (i + 1) * ntot;
       const double u = F[j];
-      c[j] = (T)cg;
+      if (!keep_c) c[j] = (T)cg;
       b[j] = (T)(u * (p.inv_tau - th1 * rg) +
                  kw * (th * g0[3 * rep + i] + th1 * g0[3 * w.nreps + 3 * rep + i]));
       guess(i + 1, j, u);
@@ -214,7 +217,7 @@ __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long
     if (p.vegf) {
       const long long j = g + (long long)p.fV * ntot;
       const double u = F[j];
-      c[j] = (T)(p.inv_tau + th * p.psi_V);
+      if (!keep_c) c[j] = (T)(p.inv_tau + th * p.psi_V);
       b[j] = (T)(u * (p.inv_tau - th1 * p.psi_V) + p.sec_V * Vc[g] * chi);
       guess(p.fV, j, u);
     }
@@ -347,13 +350,13 @@ void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uin
 template <typename T>
 void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
                        const uint8_t* L, const double* vw, T* F, const double* Vc,
-                       const double* g0, T* c, T* b, T* Fprev, unsigned xmask, int xmode) {
+                       const double* g0, T* c, T* b, T* Fprev, unsigned xmask, int xmode, int keep_c) {
   if (Fprev)
     hca_launch(k_setup_step<true, T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot,
-               L, vw, F, Vc, g0, c, b, Fprev, xmask, xmode);
+               L, vw, F, Vc, g0, c, b, Fprev, xmask, xmode, keep_c);
   else
     hca_launch(k_setup_step<false, T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot,
-               L, vw, F, Vc, g0, c, b, Fprev, xmask, xmode);
+               L, vw, F, Vc, g0, c, b, Fprev, xmask, xmode, keep_c);
 }
 
 template <typename T>
@@ -407,7 +410,7 @@ void launch_convert(hipStream_t s, const double* src, float* dst, long long n) {
                                    const double*, const T*, T*, T*, int);                          \
   template void launch_setup_step<T>(hipStream_t, const Work&, const DevParams&, long long,        \
                                      const uint8_t*, const double*, T*, const double*,             \
-                                     const double*, T*, T*, T*, unsigned, int);                    \
+                                     const double*, T*, T*, T*, unsigned, int, int);               \
   template void launch_setup_o2_newton<T>(hipStream_t, const Work&, const DevParams&,              \
                                           const uint8_t*, const double*, const T*, const T*, T*,   \
                                           T*);                                                     \

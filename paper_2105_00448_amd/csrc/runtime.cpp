@@ -206,6 +206,11 @@ struct Ctx : ::hca_ctx {
   long long step = 0;
   int last_it[2] = {0, 0};       // iterations of the last step solve / init solve
   bool fin_pending = false;      // the last solve's x += alpha p left to the ODE phase
+  // The fields but oxygen have a c (and so multigrid data) that follows the
+  // vessel map and the constants only: true while the stored ones are current
+  // (cleared by anything that writes a state field; never set with the
+  // vessel update, which changes the map between steps).
+  bool fixed_ops = false;
   std::vector<SolveScal> last_ss;
   int picard_iters = 0;
 
@@ -564,8 +569,10 @@ int g_solve_lead = 0;
 // defer_finish (a solve of every field that the ODE phase follows): when every
 // system converged, the last iteration's x += alpha p is left to the ODE
 // kernel (c->fin_pending), which reads every voxel of the fields anyway.
+// prep_o2_only: the other fields' multigrid data are current (c->fixed_ops);
+// only the oxygen systems' are rebuilt from this step's c.
 hca_status solve(Ctx* c, const Work& W_all, const MgBufs& mg_all, unsigned fmask, double rtol,
-                 int maxit, int kind, bool defer_finish = false) {
+                 int maxit, int kind, bool defer_finish = false, bool prep_o2_only = false) {
   const int nsys = W_all.nreps;
   const Work* Wp = &W_all;
   const MgBufs* mgp = &mg_all;
@@ -573,8 +580,9 @@ hca_status solve(Ctx* c, const Work& W_all, const MgBufs& mg_all, unsigned fmask
   const Work& W = W_all;
   const MgBufs& mg = mg_all;
   if (c->use_mg) {
-    ProfScope ps(c, KC_MG_PREP, kTagAll, false);
-    launch_mg_prepare(c->stream, W, mg, c->c);
+    const double nf = c->dp.nf;   // oxygen alone: 1/nf of the priced voxels
+    ProfScope ps(c, KC_MG_PREP, kTagAll, false, prep_o2_only ? -bpv_of(c, KC_MG_PREP) * (nf - 1.0) / nf : 0.0);
+    launch_mg_prepare(c->stream, prep_o2_only ? c->sys1 : W, prep_o2_only ? c->mg1 : mg, c->c);
   }
   {
     ProfScope ps(c, KC_CG_START, kTagAll);
@@ -695,10 +703,13 @@ hca_status run_phases(Ctx* c, unsigned mask) {
     const unsigned fitmask = (c->Fprev && c->prm.x0_extrapolate == 3) ? (fmask & ~1u) : 0u;
     const unsigned xmask = fmask & ~fitmask;
     const bool guess_in_setup = c->Fprev && c->dp.theta >= 1.0;
+    // the fields but oxygen keep their c and multigrid data while the vessel
+    // map is unchanged (2 or 3 stored values per voxel fewer in the setup)
+    const bool keep = c->fixed_ops && !c->dp.vegf;
     {
-      ProfScope ps(c, KC_SETUP, kTagState);
+      ProfScope ps(c, KC_SETUP, kTagState, true, keep ? -(2.0 + c->dp.drug3) * kE : 0.0);
       launch_setup_step(s, wk, c->dp, c->ntot, c->L, c->w, c->F, c->Vc, c->g0, c->c, c->b,
-                        guess_in_setup ? c->Fprev : nullptr, xmask, c->prm.x0_extrapolate);
+                        guess_in_setup ? c->Fprev : nullptr, xmask, c->prm.x0_extrapolate, keep ? 1 : 0);
       if (c->dp.theta < 1.0) launch_rhs_lap(s, wk, c->dp, c->ntot, c->F, c->b);
     }
     if (c->Fprev && !guess_in_setup && xmask) {
@@ -715,8 +726,10 @@ hca_status run_phases(Ctx* c, unsigned mask) {
       HIPCHK(c, hipMemcpyAsync(c->b_o2lin, c->b, sizeof(Real) * (size_t)c->ntot, hipMemcpyDeviceToDevice, s));
     // the last substep's solve ends in the ODE phase when one follows
     const bool defer = (mask & HCA_PH_ODE) && j + 1 == c->dp.nsub_pde && !newton;
-    hca_status st = solve(c, c->sys_all, c->mg_all, fmask, solve_rtol(c), c->prm.cg_maxit, 0, defer);
+    hca_status st = solve(c, c->sys_all, c->mg_all, fmask, solve_rtol(c), c->prm.cg_maxit, 0, defer,
+                          keep);
     if (st != HCA_OK) return st;
+    c->fixed_ops = !c->dp.vegf;
     // Newton steps on the oxygen uptake at the new value, from the linearised solution
     for (int k = 0; newton && k < c->prm.o2_newton; ++k) {
       {
@@ -1869,6 +1882,7 @@ hca_status import_state(Ctx* c, int rep, const void* src, size_t src_bytes, int 
   const char* s = static_cast<const char*>(src);
   const hipMemcpyKind in = src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   const size_t n = lay.n;
+  c->fixed_ops = false;   // the vessel map may change: rebuild every field's c and multigrid data
   // the maps staged in the proposal buffer and the right-hand side (both
   // rewritten before their next use) and validated together
   double* wstage = reinterpret_cast<double*>(c->b);   // nf x ntot Real values: room for ntot doubles
@@ -2269,6 +2283,7 @@ hca_status api_set_field(::hca_ctx* c_, int rep, hca_field f, const void* src, s
   const RepHost& R = c->reps[rep];
   const size_t bytes = (size_t)R.n * elem;
   if (src_bytes < bytes) return fail(c, HCA_E_RANGE, "source buffer too small");
+  c->fixed_ops = false;   // the next solve rebuilds every field's c and multigrid data
   const hipMemcpyKind kind = src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   if (f == HCA_F_CELL) {
     // stage in the proposal buffer (rewritten by every CA pass) and validate
