@@ -211,13 +211,16 @@ void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uin
 // G3 (drug3) and V (vegf, its source from Vc); c and b of the same layout.
 // With Fprev, the same pass also forms the solves' initial guess of the
 // fields in xmask as launch_extrapolate does (mode xmode; theta = 1 only:
-// a theta < 1 right-hand side still reads F afterwards).  keep_c: the c of
-// the fields but oxygen (a function of the vessel map and the constants) is
-// already stored and is not written again.
+// a theta < 1 right-hand side still reads F afterwards), the value it
+// extrapolates from going to Fprev_out (Fprev, or the buffer that takes its
+// role when the history rotates).  keep_c: the c of the fields but oxygen (a
+// function of the vessel map and the constants) is already stored and is
+// not written again.
 template <typename T>
 void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
                        const uint8_t* L, const double* vw, T* F, const double* Vc,
-                       const double* g0, T* c, T* b, T* Fprev, unsigned xmask, int xmode, int keep_c);
+                       const double* g0, T* c, T* b, const T* Fprev, T* Fprev_out, unsigned xmask,
+                       int xmode, int keep_c);
 // Newton step on the oxygen uptake at the new value: c, b of the oxygen
 // systems (the first ntot entries) from the iterate K and the linearised
 // substep's right-hand side b_lin.
@@ -284,12 +287,14 @@ void launch_cg_finish(hipStream_t s, const Work& w, T* x, const SolverBufsT<T>& 
 // The solves' initial guess (x0_extrapolate = 3) for the systems of the
 // fields in fmask: F <- the best (smallest residual for this solve's system)
 // of the least-squares fits in span(A F, A (F - Fprev), A (Fprev - Fprev2))
-// and the geometric extrapolation; Fprev2 <- Fprev, Fprev <- F.  part:
-// kGuessPartsPerTile doubles per tile of w; alpha: 4 per system.
+// and the geometric extrapolation; Fprev2 <- Fprev, Fprev <- F, or with
+// rotate Fprev2 <- F alone (the caller then swaps the two buffers' roles: one
+// stored value per voxel fewer).  part: kGuessPartsPerTile doubles per tile
+// of w; alpha: 4 per system.
 constexpr int kGuessPartsPerTile = 12;
 template <typename T>
 void launch_guess_projection(hipStream_t s, const Work& w, const T* c, const T* b, T* F, T* Fprev, T* Fprev2,
-                             double* part, double* alpha, unsigned fmask, int nrep);
+                             double* part, double* alpha, unsigned fmask, int nrep, int rotate);
 
 // ---- geometric multigrid (k_mg.hip) ---------------------------------------
 constexpr int kMaxLevels = 16;

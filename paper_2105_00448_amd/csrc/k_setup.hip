@@ -178,15 +178,16 @@ __global__ void __launch_bounds__(kBlock) k_setup_step(Work w, DevParams p, long
                                                        const double* __restrict__ Vc,
                                                        const double* __restrict__ g0,
                                                        T* __restrict__ c, T* __restrict__ b,
-                                                       T* __restrict__ Fprev, unsigned xmask, int xmode,
-                                                       int keep_c) {
+                                                       const T* Fprev, T* Fprev_out, unsigned xmask,
+                                                       int xmode, int keep_c) {
   const double th = p.theta, th1 = 1.0 - p.theta;
   // X: the solves' initial guess as k_extrapolate forms it, from the value u
-  // just read for b (fields of xmask)
+  // just read for b (fields of xmask); u goes to Fprev_out (Fprev itself, or
+  // the buffer that takes Fprev's role after the step's history rotation)
   auto guess = [&](int f, long long j, double u) {
     if (X && ((xmask >> f) & 1u)) {
       const double up = Fprev[j];
-      Fprev[j] = (T)u;
+      Fprev_out[j] = (T)u;
       if (xmode == 1) {
         F[j] = (T)(u + (u - up));
       } else if (up > 0.0 && u > 0.0 && u < up) {   // geometric, decaying values only
@@ -350,13 +351,14 @@ void launch_setup_o2(hipStream_t s, const Work& w, const DevParams& p, const uin
 template <typename T>
 void launch_setup_step(hipStream_t s, const Work& w, const DevParams& p, long long ntot,
                        const uint8_t* L, const double* vw, T* F, const double* Vc,
-                       const double* g0, T* c, T* b, T* Fprev, unsigned xmask, int xmode, int keep_c) {
+                       const double* g0, T* c, T* b, const T* Fprev, T* Fprev_out, unsigned xmask,
+                       int xmode, int keep_c) {
   if (Fprev)
     hca_launch(k_setup_step<true, T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot,
-               L, vw, F, Vc, g0, c, b, Fprev, xmask, xmode, keep_c);
+               L, vw, F, Vc, g0, c, b, Fprev, Fprev_out, xmask, xmode, keep_c);
   else
     hca_launch(k_setup_step<false, T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, p, ntot,
-               L, vw, F, Vc, g0, c, b, Fprev, xmask, xmode, keep_c);
+               L, vw, F, Vc, g0, c, b, Fprev, Fprev_out, xmask, xmode, keep_c);
 }
 
 template <typename T>
@@ -410,7 +412,7 @@ void launch_convert(hipStream_t s, const double* src, float* dst, long long n) {
                                    const double*, const T*, T*, T*, int);                          \
   template void launch_setup_step<T>(hipStream_t, const Work&, const DevParams&, long long,        \
                                      const uint8_t*, const double*, T*, const double*,             \
-                                     const double*, T*, T*, T*, unsigned, int, int);               \
+                                     const double*, T*, T*, const T*, T*, unsigned, int, int);     \
   template void launch_setup_o2_newton<T>(hipStream_t, const Work&, const DevParams&,              \
                                           const uint8_t*, const double*, const T*, const T*, T*,   \
                                           T*);                                                     \

@@ -689,7 +689,7 @@ __global__ void __launch_bounds__(kBlock) k_guess_reduce(Work w, const double* _
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_guess_apply(Work w, T* __restrict__ F, T* __restrict__ Fprev,
                                                         T* __restrict__ Fprev2, const double* __restrict__ alpha,
-                                                        unsigned fmask, int nrep) {
+                                                        unsigned fmask, int nrep, int rotate) {
   int b0, b1;
   work_range(w.nflat, b0, b1);
   for (int it = b0; it < b1; ++it) {
@@ -702,20 +702,24 @@ __global__ void __launch_bounds__(kBlock) k_guess_apply(Work w, T* __restrict__ 
       const double u1 = F[i], u2 = Fprev[i], u3 = Fprev2[i];
       F[i] = (T)(geo ? geo_guess(u1, u2)
                      : c1 * u1 + c2 * (double)(T)(u1 - u2) + c3 * (double)(T)(u2 - u3));
-      Fprev2[i] = (T)u2;
-      Fprev[i] = (T)u1;
+      if (rotate) {   // u3 is not needed again: its buffer takes u1 and the roles swap
+        Fprev2[i] = (T)u1;
+      } else {
+        Fprev2[i] = (T)u2;
+        Fprev[i] = (T)u1;
+      }
     }
   }
 }
 
 template <typename T>
 void launch_guess_projection(hipStream_t s, const Work& w, const T* c, const T* b, T* F, T* Fprev, T* Fprev2,
-                             double* part, double* alpha, unsigned fmask, int nrep) {
+                             double* part, double* alpha, unsigned fmask, int nrep, int rotate) {
   hca_launch(k_guess_dots<T>, dim3(grid_tiles(w.ntiles, w.max_blocks)), dim3(kBlock), 0, s, w, c, b,
              (const T*)F, (const T*)Fprev, (const T*)Fprev2, part, fmask, nrep);
   hca_launch(k_guess_reduce, dim3(w.nreps), dim3(kBlock), 0, s, w, (const double*)part, alpha, fmask, nrep);
   hca_launch(k_guess_apply<T>, dim3(grid_for(w.nflat, w.max_blocks)), dim3(kBlock), 0, s, w, F, Fprev, Fprev2,
-             (const double*)alpha, fmask, nrep);
+             (const double*)alpha, fmask, nrep, rotate);
 }
 
 // Power of two near 1/rms(r) for a system of n unknowns with ||r||^2 = rr
@@ -912,7 +916,7 @@ void launch_cg_finish(hipStream_t s, const Work& w, T* x, const SolverBufsT<T>& 
   template void launch_cg_update<T>(hipStream_t, const Work&, double, int, const SolverBufsT<T>&);  \
   template void launch_cg_finish<T>(hipStream_t, const Work&, T*, const SolverBufsT<T>&);        \
   template void launch_guess_projection<T>(hipStream_t, const Work&, const T*, const T*, T*, T*, T*, \
-                                           double*, double*, unsigned, int);
+                                           double*, double*, unsigned, int, int);
 HCA_SOLVER_INST(double)
 HCA_SOLVER_INST(float)
 

@@ -109,7 +109,8 @@ const double kBytesPerVoxel[KC_COUNT] = {
     16.5 + kE,      // mg postfused L0: read u3 (4), e (1/8), r (4), dinv (4), r (stored); write z (4)
     3 * kE,         // cg_finish: read x, p; write x (once per solve)
     11 * kE};       // guess fit, per voxel of one fitted field: read x1, x2, x3, c, b (the products);
-                    // read x1, x2, x3; write x0, x1, x2 (the shifted history)
+                    // read x1, x2, x3; write x0, x1, x2 (the shifted history; x0 and x1 alone
+                    // when the history buffers rotate)
 constexpr double kBytesSetupVegf = 8.0 + 3 * kE;   // setup_step with vegf: + read V, Vc; write c, b
 constexpr double kBytesSetupDrug3 = 3 * kE;        // setup_step with drug3: + read G3; write c, b
 constexpr double kBytesStatsField = kE;            // stats: per extra field scanned (V, G3)
@@ -706,21 +707,29 @@ hca_status run_phases(Ctx* c, unsigned mask) {
     // the fields but oxygen keep their c and multigrid data while the vessel
     // map is unchanged (2 or 3 stored values per voxel fewer in the setup)
     const bool keep = c->fixed_ops && !c->dp.vegf;
+    // with every field solved and every guess formed here, the history
+    // rotates: this solve's starting values go to Fprev2's buffer (whose
+    // values are read for the last time), then Fprev and Fprev2 swap roles
+    const bool rotate = fitmask && guess_in_setup && fmask == (1u << c->dp.nf) - 1u;
     {
       ProfScope ps(c, KC_SETUP, kTagState, true, keep ? -(2.0 + c->dp.drug3) * kE : 0.0);
       launch_setup_step(s, wk, c->dp, c->ntot, c->L, c->w, c->F, c->Vc, c->g0, c->c, c->b,
-                        guess_in_setup ? c->Fprev : nullptr, xmask, c->prm.x0_extrapolate, keep ? 1 : 0);
+                        guess_in_setup ? c->Fprev : nullptr, rotate ? c->Fprev2 : c->Fprev, xmask,
+                        c->prm.x0_extrapolate, keep ? 1 : 0);
       if (c->dp.theta < 1.0) launch_rhs_lap(s, wk, c->dp, c->ntot, c->F, c->b);
     }
     if (c->Fprev && !guess_in_setup && xmask) {
       ProfScope ps(c, KC_SETUP, kTagState);
       launch_extrapolate(s, wk, c->ntot, c->dp.nf, xmask, c->prm.x0_extrapolate, c->F, c->Fprev);
     }
-    if (fitmask) {   // priced per voxel of each fitted field (three launches)
-      ProfScope ps(c, KC_GUESS, kTagState, false, (__builtin_popcount(fitmask) - 1) * kBytesPerVoxel[KC_GUESS]);
+    if (fitmask) {   // priced per voxel of each fitted field (three launches; one stored value less rotating)
+      const double per_field = kBytesPerVoxel[KC_GUESS] - (rotate ? kE : 0.0);
+      ProfScope ps(c, KC_GUESS, kTagState, false,
+                   __builtin_popcount(fitmask) * per_field - kBytesPerVoxel[KC_GUESS]);
       launch_guess_projection(s, c->sys_all, c->c, c->b, c->F, c->Fprev, c->Fprev2, c->d_gpart, c->d_galpha,
-                              fitmask, c->nreps);
+                              fitmask, c->nreps, rotate ? 1 : 0);
     }
+    if (rotate) std::swap(c->Fprev, c->Fprev2);
     const bool newton = c->prm.o2_newton > 0 && (fmask & 1u);
     if (newton)
       HIPCHK(c, hipMemcpyAsync(c->b_o2lin, c->b, sizeof(Real) * (size_t)c->ntot, hipMemcpyDeviceToDevice, s));
